@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Throughput of the DA-FMM hot path on one MI355X.
+
+Workload: N = 1,000,000 points uniform in [0,1)^3 (seed 1), charges U(-1,1),
+uniform octree of depth 5 on the root cube [0,1]^3, truncation order p = 8,
+potentials and fields.  One step is one pass of the whole path over this input
+with the positions and charges already in HBM: fmm_plan (root, Morton keys,
+radix sort, boxes, U/V/W/X lists, sorted particles, M2L slot tables) followed
+by fmm_evaluate (P2M, M2M, M2L, P2L, L2L, L2P/M2P, P2P, output).  The step is
+timed for the plain FP64 path (reported as `value`) and for the mixed path
+(FP32 P2P with FP64 accumulation, FP32-MFMA M2L), reported beside it.
+
+The roofline entry is for the dominant kernel, M2L: its algorithmic work is
+2 (p+1)^4 flops per V-list pair (the harmonic contraction), measured with HIP
+events on the evaluation stream over the timed steps.  The CPU baseline times
+the plain oracle on a bounded sample: the points of one octant of the cube
+([0,0.5)^3, 1/8 of the input) with the same box width (uniform depth 4 on the
+half-size root), p = 8.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particles/s at 1e-7 rel. err (plain FP64 vs mixed); p50/p99 solve latency"
+N_DEFAULT, DEPTH, ORDER, SEED = 1_000_000, 5, 8, 1
+FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS = 78.6, 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_mode(x, q, precision, steps, warmup, n):
+    import torch
+    from paper_2508_02626_amd import fmm
+    phi = torch.empty(n, dtype=torch.float64, device=x.device)
+    fld = torch.empty(n, 3, dtype=torch.float64, device=x.device)
+
+    def step():
+        pl = fmm.Plan(x, ORDER, uniform_depth=DEPTH, root=[0, 0, 0, 1], precision=precision)
+        pl.evaluate(q, phi, fld)
+        return pl
+
+    for _ in range(warmup):
+        step().close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step().close()
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / steps
+    # stage breakdown and evaluate-only rate on one plan, HIP events per stage
+    pl = fmm.Plan(x, ORDER, uniform_depth=DEPTH, root=[0, 0, 0, 1], precision=precision)
+    pl.evaluate(q, phi, fld)
+    torch.cuda.synchronize()
+    pl.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pl.evaluate(q, phi, fld)
+    torch.cuda.synchronize()
+    eval_s = (time.perf_counter() - t0) / steps
+    stages = pl.read_timing()
+    sizes = pl.sizes()
+    pl.close()
+    return dict(step_s=step_s, eval_s=eval_s, stages=stages, sizes=sizes,
+                phi=phi.cpu().numpy(), fld=fld.cpu().numpy())
+
+
+def cpu_baseline(xh, qh):
+    """The oracle DA-FMM on the octant [0,0.5)^3 of the same input."""
+    import oracle
+    sel = np.all(xh < 0.5, axis=1)
+    xs, qs = xh[sel], qh[sel]
+    t0 = time.perf_counter()
+    tree = oracle.Tree(xs, root=[0, 0, 0, 0.5], uniform_depth=DEPTH - 1)
+    tree.fmm(ORDER, qs)
+    dt = time.perf_counter() - t0
+    return {"value": len(qs) / dt, "unit": "particles/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "seconds": dt,
+            "sample": "oracle DA-FMM (TPSA operators, memoised translations) on the %d points of "
+                      "the octant [0,0.5)^3 of the same input, uniform depth 4 on the root [0,0.5]^3 "
+                      "(same box width), p=8, potential+field" % len(qs)}
+
+
+def sampled_sigma(xh, qh, phi, fld, count=2000, seed=7):
+    import oracle
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(len(qh), size=min(count, len(qh)), replace=False))
+    dp, df = oracle.direct(xh, qh, idx)
+    s_phi = float(np.linalg.norm(phi[idx] - dp) / np.linalg.norm(dp))
+    s_fld = float(np.linalg.norm(fld[idx] - df) / np.linalg.norm(df))
+    return s_phi, s_fld, len(idx)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=N_DEFAULT)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the solve would shard)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2508_02626_amd import inputs
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    n = args.n
+    xh, qh = inputs.uniform(n, SEED)
+    x = torch.tensor(xh, device="cuda:0")
+    q = torch.tensor(qh, device="cuda:0")
+    log("bench: n=%d depth=%d p=%d steps=%d warmup=%d" % (n, DEPTH, ORDER, args.steps, args.warmup))
+    res = {}
+    for mode in (["fp64"] if args.no_mixed else ["fp64", "mixed"]):
+        r = run_mode(x, q, mode, args.steps, args.warmup, n)
+        r["sigma_phi"], r["sigma_field"], r["sigma_targets"] = sampled_sigma(xh, qh, r["phi"], r["fld"])
+        log("bench: %s step %.3f ms eval %.3f ms sigma %.3e" % (mode, 1e3 * r["step_s"], 1e3 * r["eval_s"],
+                                                                r["sigma_phi"]))
+        res[mode] = r
+    f = res["fp64"]
+    nv = f["sizes"]["V"]
+    m2l_ms = f["stages"]["m2l"][0] / max(f["stages"]["m2l"][1], 1)
+    flops = 2.0 * (ORDER + 1) ** 4 * nv
+    achieved = flops / (m2l_ms * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": n / f["step_s"],
+        "unit": "particles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * f["step_s"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "uniform cube: N=%d uniform in [0,1)^3 (seed %d), q~U(-1,1), uniform octree "
+                               "depth 5 on [0,1]^3, order p=8, potential+field" % (n, SEED),
+                   "n": n, "order": ORDER, "tree": "uniform depth 5", "step": "fmm_plan + fmm_evaluate"},
+        "accuracy": {"sigma_phi_vs_direct": f["sigma_phi"], "sigma_field_vs_direct": f["sigma_field"],
+                     "targets_sampled": f["sigma_targets"]},
+        "eval_only": {"value": n / f["eval_s"], "ms": 1e3 * f["eval_s"]},
+        "stage_ms": {k: v[0] / max(v[1], 1) for k, v in f["stages"].items()},
+        "roofline": {"kernel": "k_m2l<8,double>", "bound": "mfma", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None, "flops_per_launch": flops, "ms_per_launch": m2l_ms},
+    }
+    if "mixed" in res:
+        m = res["mixed"]
+        mm = m["stages"]["m2l"][0] / max(m["stages"]["m2l"][1], 1)
+        out["mixed"] = {"value": n / m["step_s"], "ms_per_step": 1e3 * m["step_s"],
+                        "eval_only_value": n / m["eval_s"], "eval_ms": 1e3 * m["eval_s"],
+                        "sigma_phi_vs_direct": m["sigma_phi"], "sigma_field_vs_direct": m["sigma_field"],
+                        "dtype": "f64 with f32 P2P terms and f32 MFMA M2L",
+                        "stage_ms": {k: v[0] / max(v[1], 1) for k, v in m["stages"].items()},
+                        "m2l_tflops": flops / (mm * 1e-3) / 1e12, "m2l_peak_fp32": FP32_PEAK_TFLOPS}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(xh, qh)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,183 @@
+/*
+ * fmm.h - C ABI of the MI355X (gfx950) DA-FMM library, libfmm_mi355x.so.
+ *
+ * The library computes, for N point charges q_i at positions r_i, the Coulomb
+ * potential phi_i = sum_{j != i} q_j / |r_i - r_j| (left-hand side of the
+ * paper's Eq. P2M_phi, no physical constant) and, on request, the field
+ * E_i = -grad phi_i = sum_{j != i} q_j (r_i - r_j) / |r_i - r_j|^3, with the
+ * differential-algebra fast multipole method of Zhang, arXiv 2508.02626:
+ * Taylor (DA) multipole expansions in d = r / r^2 (Sec. 2.1), translated by
+ * M2M (Sec. 2.2), converted by M2L (Sec. 2.3), P2L (Sec. 2.4), shifted by
+ * L2L (Sec. 2.5), evaluated by L2P / M2P (Sec. 3.2), with the near field
+ * summed pairwise (Sec. 1).  Pairs at distance zero contribute nothing.
+ *
+ * Conventions for every entry point
+ *  - Pointers named *_dev are device pointers of the current HIP device;
+ *    pointers named *_host are host pointers.  Arrays are contiguous, FP64,
+ *    in the caller's (original) particle order; positions are [n][3].
+ *  - All device work is enqueued on the stream argument (0 = null stream) and
+ *    is asynchronous unless stated; the caller keeps inputs alive and outputs
+ *    untouched until the stream has passed the call.
+ *  - The plan copies what it needs from xyz_dev and never keeps the caller's
+ *    pointers.  It owns its workspace (tree, lists, sorted particles,
+ *    expansions), allocated through the caller's allocator or, when none is
+ *    given, with stream-ordered hipMallocAsync, and released by
+ *    fmm_plan_destroy.
+ *  - Every function returns FMM_OK or a negative status; arguments are
+ *    validated before anything is enqueued.  No function aborts or prints;
+ *    fmm_last_error() gives the calling thread's last message.
+ *  - Calls on different plans may run concurrently on different streams.
+ *    Concurrent calls on one plan must be ordered by the caller.
+ */
+#ifndef FMM_MI355X_H
+#define FMM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    FMM_OK = 0,
+    FMM_EINVAL = -1,        /* invalid argument (also non-finite coordinates) */
+    FMM_ENOMEM = -2,        /* device or host allocation failed              */
+    FMM_EDEVICE = -3,       /* a HIP call failed; see fmm_last_error()        */
+    FMM_EUNSUPPORTED = -4   /* valid but not supported by this build          */
+};
+
+enum { FMM_FP64 = 0, FMM_MIXED = 1 };
+
+typedef struct fmm_plan_s *fmm_plan_t;
+
+/* Optional stream-ordered allocator (e.g. a framework's caching allocator).
+ * alloc returns NULL on failure; free must accept what alloc returned. */
+typedef struct {
+    void *(*alloc)(size_t bytes, hipStream_t stream, void *ctx);
+    void (*free)(void *ptr, hipStream_t stream, void *ctx);
+    void *ctx;
+} fmm_allocator_t;
+
+typedef struct {
+    int32_t uniform_depth; /* >= 0: full octree of this depth (leaf_size unused);
+                              -1: adaptive octree, a box with more than
+                              leaf_size particles is subdivided (Sec. 3.5)    */
+    int32_t max_depth;     /* adaptive depth cap, 1..21 (default 21)          */
+    int32_t precision;     /* FMM_FP64, or FMM_MIXED: FP32 P2P with a
+                              compensated sum and, for order <= 8, FP32 MFMA
+                              M2L; everything else stays FP64                 */
+    int32_t want_field;    /* nonzero: fmm_evaluate may be given a field array */
+    const double *root;    /* host {lo_x, lo_y, lo_z, W} of the root cube, or
+                              NULL for the bounding cube of the points        */
+} fmm_options_t;
+
+/* Default options: adaptive, max_depth 21, FP64, field on, bounding cube. */
+void fmm_default_options(fmm_options_t *opt);
+
+/*
+ * fmm_plan - build the octree and interaction lists for n points.
+ *   xyz_dev    [n][3] FP64 device positions (read during the call only)
+ *   n          number of points, 1 <= n < 2^31
+ *   order      truncation order p of the DA vectors, 0..12 (Sec. 3, "order")
+ *   leaf_size  s >= 1 for adaptive trees (Sec. 3.5); ignored for uniform trees
+ *   opt        options, or NULL for fmm_default_options
+ *   alloc      allocator, or NULL for hipMallocAsync on `stream`
+ *   stream     HIP stream for all device work
+ *   out        receives the plan handle on success (untouched on failure)
+ * Synchronises `stream` to learn tree and list sizes; returns FMM_EINVAL for
+ * invalid arguments or non-finite coordinates.
+ */
+int fmm_plan(const double *xyz_dev, int64_t n, int32_t order, int32_t leaf_size,
+             const fmm_options_t *opt, const fmm_allocator_t *alloc, hipStream_t stream,
+             fmm_plan_t *out);
+
+/*
+ * fmm_evaluate - potentials (and fields) for charges q.
+ *   q_dev      [n] FP64 device charges, original order
+ *   phi_dev    [n] FP64 device output potentials
+ *   field_dev  [n][3] FP64 device output fields E = -grad phi, or NULL
+ * Asynchronous on `stream`.  Deterministic: the same plan and charges give
+ * bitwise identical results on every call.
+ */
+int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_dev, double *field_dev,
+                 hipStream_t stream);
+
+/*
+ * fmm_evaluate_batch - evaluate `count` independent plans, packing the work
+ * of all of them into shared launches (one launch per pipeline stage instead
+ * of one per stage and plan).  Arrays of length count; field[i] may be NULL.
+ * Plans may differ in n, order and precision.  Each result is bitwise equal to
+ * fmm_evaluate on the same plan alone.
+ */
+int fmm_evaluate_batch(fmm_plan_t const *plans, const double *const *q_dev,
+                       double *const *phi_dev, double *const *field_dev, int32_t count,
+                       hipStream_t stream);
+
+/* Device bytes held by the plan (its workspace), for admission control. */
+int fmm_plan_footprint(fmm_plan_t plan, size_t *bytes);
+
+/* Predicted device bytes of a plan before building it (upper bound used for
+ * admission: tree, lists and expansions for n points at this order). */
+int fmm_plan_estimate(int64_t n, int32_t order, int32_t leaf_size,
+                      const fmm_options_t *opt, size_t *bytes);
+
+/* Sizes of the plan: out[0]=boxes, [1]=|U|, [2]=|V|, [3]=|W|, [4]=|X|,
+ * [5]=deepest level, [6]=key depth D, [7]=n, [8]=order, [9]=coefficients per
+ * expansion (p+1)(p+2)(p+3)/6. */
+int fmm_plan_sizes(fmm_plan_t plan, int64_t out[10]);
+
+/*
+ * fmm_plan_export_tree - copy the tree to host buffers (any may be NULL).
+ *   root_host[4]  {lo_x, lo_y, lo_z, W}
+ *   perm_host[n]  sorted position -> original index (particles sorted by
+ *                 (Morton key, original index))
+ *   per box (boxes in (level, Morton code) order): level, morton, first
+ *   particle (sorted position), count, parent (-1 for the root), first child
+ *   (-1 if none), number of children
+ *   lists as CSR over boxes: *_off[boxes+1] (int64), *_src[|list|] (int32),
+ *   sources of each box ascending; U (P2P), V (M2L), W (M2P), X (P2L).
+ * Synchronous (waits for `stream`).
+ */
+int fmm_plan_export_tree(fmm_plan_t plan, hipStream_t stream, double *root_host,
+                         int64_t *perm_host, int32_t *level_host, uint64_t *morton_host,
+                         int64_t *first_host, int64_t *count_host, int32_t *parent_host,
+                         int32_t *child_begin_host, int32_t *nchild_host,
+                         int64_t *U_off_host, int32_t *U_src_host, int64_t *V_off_host,
+                         int32_t *V_src_host, int64_t *W_off_host, int32_t *W_src_host,
+                         int64_t *X_off_host, int32_t *X_src_host);
+
+/*
+ * fmm_plan_export_expansions - copy the multipole (M) and local (L) expansions
+ * of the last fmm_evaluate to host buffers [boxes][(p+1)(p+2)(p+3)/6], in the
+ * paper's DA convention: M holds the Taylor coefficients of phi_M in
+ * d = r/r^2 about the box centre (Eq. P2M), L those of phi_L in d' = r - c
+ * (Eq. P2L); monomials ordered by degree, then descending exponents of d1, d2
+ * (Table 1).  Either pointer may be NULL.  Synchronous.
+ */
+int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, double *M_host,
+                               double *L_host);
+
+/*
+ * Stage timing of fmm_evaluate.  With timing on, every fmm_evaluate on the
+ * plan brackets each stage with HIP events on its stream.  fmm_plan_read_timing
+ * waits for the recorded events, adds their durations (milliseconds) per stage
+ * into ms[0..15] and the number of timed evaluations into calls[0..15], and
+ * clears the records.  Stages: 0 permute charges, 1 P2M, 2 M2M, 3 fold,
+ * 4 M2L, 5 P2L, 6 unfold, 7 L2L, 8 L2P+M2P, 9 P2P+output.
+ */
+int fmm_plan_set_timing(fmm_plan_t plan, int on);
+int fmm_plan_read_timing(fmm_plan_t plan, double ms[16], int64_t calls[16]);
+
+/* Release the plan.  Stream-ordered on the plan's build stream: memory is
+ * returned after work already enqueued there has finished. */
+int fmm_plan_destroy(fmm_plan_t plan);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *fmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

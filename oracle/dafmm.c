@@ -40,21 +40,27 @@ void oracle_tree_coords(const oracle_tree *t, int32_t b, int64_t g[3]);
 
 static double *da_new(const da_ctx *c) { return calloc((size_t)c->n, sizeof(double)); }
 
+/* a[i] += val for the monomial x^e, dropped when its degree exceeds the order */
+static void da_add_mono(const da_ctx *c, double *a, int i, int j, int k, double val)
+{
+    if (i + j + k <= c->p) a[da_index(i, j, k)] += val;
+}
+
 /* the DA vector c0 + d_v */
 static void da_var(const da_ctx *c, double *a, int v, double c0)
 {
     da_zero(c, a);
     a[0] = c0;
-    a[da_index(v == 0, v == 1, v == 2)] = 1.0;
+    da_add_mono(c, a, v == 0, v == 1, v == 2, 1.0);
 }
 
 /* |d|^2 = d1^2 + d2^2 + d3^2 as a DA vector */
 static void da_norm2_vars(const da_ctx *c, double *out)
 {
     da_zero(c, out);
-    out[da_index(2, 0, 0)] = 1.0;
-    out[da_index(0, 2, 0)] = 1.0;
-    out[da_index(0, 0, 2)] = 1.0;
+    da_add_mono(c, out, 2, 0, 0, 1.0);
+    da_add_mono(c, out, 0, 2, 0, 1.0);
+    da_add_mono(c, out, 0, 0, 2, 1.0);
 }
 
 /* ---- P2M (Sec. 2.1, Eq. P2M; Sec. 3.1: a square root and an inverse) ---- */
@@ -66,7 +72,7 @@ static void p2m_add(const da_ctx *c, const double y[3], double q, double *M)
     for (int i = 0; i < c->n; ++i) v[i] *= y2;       /* r_i^2 d^2 */
     v[0] += 1.0;                                      /* 1 + ...   */
     for (int k = 0; k < 3; ++k)                       /* - 2 r_i.d */
-        v[da_index(k == 0, k == 1, k == 2)] += -2.0 * y[k];
+        da_add_mono(c, v, k == 0, k == 1, k == 2, -2.0 * y[k]);
     da_sqrt(c, v, s);
     da_inv(c, s, t);
     for (int i = 0; i < c->n; ++i) M[i] += q * t[i];
@@ -100,7 +106,7 @@ static void m2m_map(const da_ctx *c, const double r0[3], double *args[3], double
     da_norm2_vars(c, dd);
     for (int i = 0; i < c->n; ++i) den[i] = r02 * dd[i];
     den[0] += 1.0;
-    for (int k = 0; k < 3; ++k) den[da_index(k == 0, k == 1, k == 2)] += 2.0 * r0[k];
+    for (int k = 0; k < 3; ++k) da_add_mono(c, den, k == 0, k == 1, k == 2, 2.0 * r0[k]);
     da_inv(c, den, R);
     for (int k = 0; k < 3; ++k) {
         da_var(c, t, k, 0.0);

@@ -212,7 +212,7 @@ int oracle_da_inv_r(int p, const double x0[3], double *out)
     for (int k = 0; k < 3; ++k) {
         da_zero(&c, t);
         t[0] = x0[k];
-        t[da_index(k == 0, k == 1, k == 2)] = 1.0;
+        if (p >= 1) t[da_index(k == 0, k == 1, k == 2)] = 1.0;
         da_mul(&c, t, t, t);
         for (int i = 0; i < c.n; ++i) v[i] += t[i];
     }

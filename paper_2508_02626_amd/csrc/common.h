@@ -1,0 +1,159 @@
+// Internal declarations of the MI355X DA-FMM library (not part of the ABI).
+//
+// Expansion storage.  The paper's DA vectors (Sec. 2) hold Taylor
+// coefficients M_a of phi_M in d = r/r^2 (multipole, Eq. P2M) and L_b of phi_L
+// in d' = r - c (local, Eq. P2L), monomials ordered by degree and descending
+// exponents (Table 1).  On the device every box keeps them in scaled units
+// that make the translation operators independent of the level:
+//     Mhat_a = w_|a| M_a / h^|a|,   w_n = (-1)^n / (2n-1)!!,
+//     Lhat_b = b! L_b h^(|b|+1),
+// h being the box width.  With these, the DA M2L of Sec. 2.3 becomes
+//     Lhat_b += sum_a D_(a+b)(k) Mhat_a,   D_g(k) = d^g (1/|x|) at x = k,
+// k the integer offset of the two boxes (the harmonic degrees of phi_M turn the
+// composition into a derivative-tensor contraction), and M2M, L2L are fixed
+// matrices per child octant.  The export path converts back to the DA
+// convention.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace fmm {
+
+constexpr int kMaxOrder = 12;
+constexpr int kMaxDepth = 21;
+constexpr int kVSlots = 189;   // M2L sources per box, one slot per offset (Sec. 3.4)
+constexpr int kMaxBatch = 256; // plans per batched launch
+
+__host__ __device__ inline int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+__host__ __device__ inline int nharm(int p) { return (p + 1) * (p + 1); }
+__host__ __device__ inline int below(int n) { return n * (n + 1) * (n + 2) / 6; }
+// position of d1^i d2^j d3^k in the DA order of Table 1
+__host__ __device__ inline int mono_index(int i, int j, int k)
+{
+    int n = i + j + k, a = j + k;
+    return below(n) + a * (a + 1) / 2 + k;
+}
+// Harmonic (compressed) order used by M2L: exponents (i, j, kz) with kz in {0,1};
+// degree n holds (i, n-i, 0) for i = n..0, then (i, n-1-i, 1) for i = n-1..0.
+__host__ __device__ inline int harm_index(int i, int j, int kz)
+{
+    int n = i + j + kz;
+    return n * n + (kz == 0 ? (n - i) : (n + 1) + (n - 1 - i));
+}
+inline int pad16(int n) { return (n + 15) & ~15; }
+inline int pad4(int n) { return (n + 3) & ~3; }
+
+// Morton codes: bit b of the x, y, z cell index sits at code bits 3b+2, 3b+1, 3b.
+__host__ __device__ inline void deinterleave(uint64_t code, int l, int c[3])
+{
+    c[0] = c[1] = c[2] = 0;
+    for (int b = 0; b < l; ++b) {
+        c[0] |= (int)((code >> (3 * b + 2)) & 1) << b;
+        c[1] |= (int)((code >> (3 * b + 1)) & 1) << b;
+        c[2] |= (int)((code >> (3 * b)) & 1) << b;
+    }
+}
+__host__ __device__ inline uint64_t interleave(const int c[3], int l)
+{
+    uint64_t k = 0;
+    for (int b = 0; b < l; ++b) {
+        k |= (uint64_t)((c[0] >> b) & 1) << (3 * b + 2);
+        k |= (uint64_t)((c[1] >> b) & 1) << (3 * b + 1);
+        k |= (uint64_t)((c[2] >> b) & 1) << (3 * b);
+    }
+    return k;
+}
+
+// V-list slots.  A box whose octant within its parent is o (bits ox, oy, oz)
+// sees sources at offsets k = target - source with k_x in [-3,2] if ox = 0 and
+// [-2,3] if ox = 1 (likewise y, z), excluding the 27 near offsets: 189 slots,
+// numbered in lexicographic order of (k_x, k_y, k_z).
+__host__ __device__ inline int vslot_of(int oct, int kx, int ky, int kz)
+{
+    int s[3] = {((oct >> 2) & 1) ? -2 : -3, ((oct >> 1) & 1) ? -2 : -3, (oct & 1) ? -2 : -3};
+    int a[3] = {kx - s[0], ky - s[1], kz - s[2]};
+    for (int t = 0; t < 3; ++t)
+        if (a[t] < 0 || a[t] > 5) return -1;
+    int nx = -1 - s[0], ny = -1 - s[1], nz = -1 - s[2]; // start of the near cube
+    bool inx = a[0] >= nx && a[0] < nx + 3, iny = a[1] >= ny && a[1] < ny + 3,
+         inz = a[2] >= nz && a[2] < nz + 3;
+    if (inx && iny && inz) return -1;
+    int clx = a[0] - nx < 0 ? 0 : (a[0] - nx > 3 ? 3 : a[0] - nx);
+    int cly = a[1] - ny < 0 ? 0 : (a[1] - ny > 3 ? 3 : a[1] - ny);
+    int clz = a[2] - nz < 0 ? 0 : (a[2] - nz > 3 ? 3 : a[2] - nz);
+    int skipped = clx * 9 + (inx ? (cly * 3 + (iny ? clz : 0)) : 0);
+    return a[0] * 36 + a[1] * 6 + a[2] - skipped;
+}
+
+// Per-order constant tables (device pointers), built once per order and device.
+struct OrderTables {
+    int p, nc, nh, ldm, ldh, ldd;   // ldd: stride of one offset's derivative table
+    int d3;                         // 2p+1 (stride of the additive D layout)
+    const double *D;    // [343][ldd] derivative tensors d^g(1/|x|) at integer x, additive layout
+    const float *Df;    // same in FP32
+    const int *offs;    // [8][189] packed offsets (kx+3)*49 + (ky+3)*7 + (kz+3)
+    const int *hoff;    // [ldh] additive D address of each harmonic index (-1 padding)
+    const double *S;    // [8][nc][nc] M2M, S[o][a][b] = d Mhat'_b / d Mhat_a
+    const double *G;    // [8][nc][nc] L2L, G[o][g][b] = d Lhat'_b / d Lhat_g
+    const double *P2M;  // [nc][nc] moments -> Mhat, P2M[g][a] = d Mhat_a / d Q_g
+    const int *fold_off; const int *fold_idx; const double *fold_c;     // Mhat -> folded
+    const int *unfold_off; const int *unfold_idx; const double *unfold_c; // Lh -> Lhat
+    const double *inv_fact;     // [nc] 1/b!
+    const double *inv_w;        // [p+1] 1/w_n = (-1)^n (2n-1)!!
+    const int *exps;            // [nc] packed exponents i | j<<8 | k<<16
+};
+
+// Everything a kernel needs to know about one plan (lives in device memory).
+struct PlanView {
+    int p, nc, nh, ldm, ldh;
+    int precision;          // FMM_FP64 / FMM_MIXED
+    int mixed_m2l;          // FP32 MFMA M2L
+    int depth, D;
+    int32_t n, nboxes, nleaves, nxtgt, nslots;
+    double lo[3], W;
+    const int32_t *level, *parent, *child_begin, *nchild, *first, *count;
+    const uint64_t *morton;
+    const int32_t *perm;                // sorted position -> original index
+    const double *xs, *ys, *zs;         // sorted positions (SoA)
+    const float *ux, *uy, *uz;          // mixed: leaf-local offsets, hi parts
+    const float *vx, *vy, *vz;          // mixed: leaf-local offsets, lo parts
+    const int32_t *leaf_of;             // sorted position -> leaf box
+    const int64_t *U_off, *V_off, *W_off, *X_off;
+    const int32_t *U_src, *W_src, *X_src;
+    const int32_t *m2l_tgt;             // M2L targets, octant-grouped, padded to 16
+    const int32_t *vslot;               // [m2l targets][189] source box or -1
+    const int32_t *leaves;              // leaf boxes
+    const int32_t *xtgt;                // boxes with a non-empty X list
+    const int32_t *lvl_nonleaf;         // non-leaf boxes grouped by level
+    const int32_t *lvl_nonleaf_off;     // [depth+2] ranges into lvl_nonleaf
+    const OrderTables *tab;             // device copy of the order tables
+    // evaluation buffers
+    double *qs;                         // sorted charges
+    double *M, *Mh, *Lh, *L;            // [boxes][ldm] / [boxes][ldh]
+    float *Mhf;                         // FP32 folded multipoles (mixed M2L)
+    double *phi_far, *fld_far;          // far-field part, sorted order
+    // caller's arrays for this evaluation
+    const double *q_in;
+    double *phi_out, *fld_out;
+};
+
+// Work split of a batched launch: plan k owns items [b[k], b[k+1]).
+struct Bases {
+    int n;
+    int b[kMaxBatch + 1];
+};
+
+__device__ inline int find_plan(const Bases &B, int item)
+{
+    int lo = 0, hi = B.n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (B.b[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+inline unsigned ceil_div(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
+
+} // namespace fmm

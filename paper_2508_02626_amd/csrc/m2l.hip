@@ -1,0 +1,155 @@
+// M2L (Sec. 2.3) on the matrix cores.
+//
+// In scaled units the DA M2L is the contraction
+//     Lhat_b(B) = sum_{C in V(B)} sum_a D_(a+b)(k_BC) Mhat_a(C),
+// D_g(k) the derivative tensor of 1/|x| at the integer box offset k.  Because
+// 1/|x| is harmonic, D_(g+2e_z) = -D_(g+2e_x) - D_(g+2e_y): the contraction is
+// carried out on the (p+1)^2 components with a_z, b_z <= 1 after folding Mhat
+// onto them, and the other components of Lhat are recovered afterwards (unfold).
+//
+// Work decomposition.  A block holds 64 targets (4 wavefronts x 16) of one
+// octant, so they share the same 189 source offsets (Sec. 3.4: at most 189
+// boxes per interaction list).  For every offset slot the block stages the
+// offset's derivative table and the 16 source vectors of each wavefront in
+// LDS, then each wavefront runs a (p+1)^2 x (p+1)^2 by 16 product with
+// 16x16x4 MFMAs: A[b][a] = D(addr(b) + addr(a)) is gathered from LDS with the
+// additive address addr(i,j,k) = k (2p+1)^2 + i (2p+1) + j, which turns the
+// Hankel structure of the matrix into a single add per operand; B holds the
+// gathered sources.  Accumulators stay in registers across all 189 slots, so
+// every target is written once; the FP32 variant adds each slot's FP32 partial
+// into FP64 accumulators, so only the per-slot products carry FP32 rounding.  Operand layouts (verified on gfx950):
+// A: lane l holds A[l%16][l/16]; B: lane l holds B[l/16][l%16];
+// D: f64 lane l reg r -> D[4r + l/16][l%16], f32 lane l reg r -> D[4(l/16)+r][l%16].
+#include "ops.h"
+
+namespace fmm {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef double4_t acc_t;
+    __device__ static acc_t run(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lane, int r) { return 4 * r + (lane >> 4); }
+    __device__ static const double *D(const OrderTables &t) { return t.D; }
+    __device__ static const double *M(const PlanView &v) { return v.Mh; }
+};
+template <> struct Mfma<float> {
+    typedef float4_t acc_t;
+    __device__ static acc_t run(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+    __device__ static const float *D(const OrderTables &t) { return t.Df; }
+    __device__ static const float *M(const PlanView &v) { return v.Mhf; }
+};
+
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
+{
+    constexpr int NH = (P + 1) * (P + 1);
+    constexpr int LDH = (NH + 15) & ~15;
+    constexpr int MT = LDH / 16;
+    constexpr int NK = (NH + 3) & ~3;
+    constexpr int KS = NK / 4;
+    constexpr int D3 = 2 * P + 1;
+    constexpr int LDD = (3 * D3 * D3 + 1) & ~1;
+    constexpr int BST = NK + 1;
+    typedef typename Mfma<T>::acc_t acc_t;
+    __shared__ T sD[LDD];
+    __shared__ T sB[4][16][BST];
+    __shared__ int sHo[NK];
+    __shared__ int soct;
+
+    const int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int tile = blockIdx.x - B.b[k];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
+    const int slot = tile * kM2LSlots + wave * 16 + col;
+    const int tgt = v.m2l_tgt[slot];
+    if (!__syncthreads_or(tgt >= 0)) return;
+    if (tgt >= 0) soct = (int)(v.morton[tgt] & 7); // every target of the block has this octant
+    const OrderTables &tb = *v.tab;
+    for (int a = tid; a < NK; a += 256) sHo[a] = a < NH ? tb.hoff[a] : 0;
+    int hb[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        int b = mt * 16 + col;
+        hb[mt] = b < NH ? tb.hoff[b] : 0;
+    }
+    acc_t acc[MT];
+    double4_t acc64[MT]; // FP32 path: per-offset partials are summed in FP64
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) { acc[mt] = acc_t{0, 0, 0, 0}; acc64[mt] = double4_t{0, 0, 0, 0}; }
+    __syncthreads();
+    const int oct = soct;
+    const T *Dt = Mfma<T>::D(tb);
+    const T *Mh = Mfma<T>::M(v);
+    const int ldh = v.ldh;
+    const int32_t *vsl = v.vslot + (int64_t)slot * kVSlots;
+    for (int j = 0; j < kVSlots; ++j) {
+        const int src = tgt >= 0 ? vsl[j] : -1;
+        if (!__syncthreads_or(src >= 0)) continue;
+        const T *Dk = Dt + (int64_t)tb.offs[oct * kVSlots + j] * LDD;
+        for (int e = tid; e < LDD; e += 256) sD[e] = Dk[e];
+#pragma unroll 4
+        for (int t = 0; t < 16; ++t) {
+            const int sb = __shfl(src, t);
+            for (int e = lane; e < NK; e += 64)
+                sB[wave][t][e] = sb >= 0 ? Mh[(int64_t)sb * ldh + e] : (T)0;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int ks = 0; ks < KS; ++ks) {
+            const int a = ks * 4 + kq;
+            const T bv = sB[wave][col][a];
+            const int ha = sHo[a];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = Mfma<T>::run(sD[hb[mt] + ha], bv, acc[mt]);
+        }
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc64[mt][r] += (double)acc[mt][r];
+                acc[mt] = acc_t{0, 0, 0, 0};
+            }
+        }
+        __syncthreads();
+    }
+    if (tgt < 0) return;
+    double *Lh = v.Lh + (int64_t)tgt * ldh;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            int b = mt * 16 + Mfma<T>::row(lane, r);
+            if (b < NH) Lh[b] = sizeof(T) == 4 ? acc64[mt][r] : (double)acc[mt][r];
+        }
+}
+
+#define M2L_CASE(PP)                                                               \
+    case PP:                                                                       \
+        if (f32) k_m2l<PP, float><<<nb, 256, 0, s>>>(V, B);                        \
+        else k_m2l<PP, double><<<nb, 256, 0, s>>>(V, B);                           \
+        break;
+
+void launch_m2l(int p, int f32, const PlanView *V, const Bases &B, hipStream_t s)
+{
+    unsigned nb = (unsigned)B.b[B.n];
+    if (!nb) return;
+    switch (p) {
+        M2L_CASE(0) M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5) M2L_CASE(6)
+        M2L_CASE(7) M2L_CASE(8) M2L_CASE(9) M2L_CASE(10) M2L_CASE(11)
+    default:
+        if (f32) k_m2l<12, float><<<nb, 256, 0, s>>>(V, B);
+        else k_m2l<12, double><<<nb, 256, 0, s>>>(V, B);
+    }
+}
+
+} // namespace fmm

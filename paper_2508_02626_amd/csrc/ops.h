@@ -1,0 +1,19 @@
+// Launchers of the evaluation kernels (see ops.hip and m2l.hip).  Every
+// launcher takes the device array of plan views and the block split.
+#pragma once
+#include "common.h"
+
+namespace fmm {
+void launch_permute_q(const PlanView *V, const Bases &B, hipStream_t s);   // 256 particles/block
+void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block
+void launch_fold(const PlanView *V, const Bases &B, hipStream_t s);        // 4 boxes/block
+void launch_m2m(int ldm, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents/block
+void launch_l2l(int ldm, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents/block
+void launch_unfold(const PlanView *V, const Bases &B, hipStream_t s);      // 4 boxes/block
+void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 X target/block
+void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block
+void launch_p2p(int mixed, const PlanView *V, const Bases &B, hipStream_t s); // 4 leaves/block
+void launch_zero(double *p, int64_t n, hipStream_t s);
+void launch_m2l(int p, int f32, const PlanView *V, const Bases &B, hipStream_t s); // 64 slots/block
+constexpr int kM2LSlots = 64;
+} // namespace fmm

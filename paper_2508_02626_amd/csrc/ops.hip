@@ -1,0 +1,565 @@
+// Evaluation kernels other than M2L.  Every kernel serves a batch of plans:
+// block b belongs to the plan k with Bases.b[k] <= b < Bases.b[k+1].
+//
+// Scaled units (h = box width): Mhat_a = w_|a| M_a / h^|a|, Lhat_b = b! L_b h^(|b|+1).
+//   P2M  (Sec. 2.1) Mhat_a = sum_g P[g][a] Q_g with raw moments Q_g = sum q u^g,
+//        u = (x - c)/h; one wavefront per leaf, one lane per moment, so the
+//        per-box reduction is an in-lane sequential sum (deterministic).
+//   M2M  (Sec. 2.2) parent Mhat = sum over children of S_octant * child Mhat.
+//   L2L  (Sec. 2.5) child Lhat += G_octant * parent Lhat.
+//   L2P / M2P (Sec. 3.2) share one evaluation routine (nested Horner with the
+//        gradient); M2P evaluates phi = |d| phi_M(d), d = y/|y|^2 (Eq. P2M_phi).
+//   P2L  (Sec. 2.4) Lhat_b += q d^b(1/|x|) at x = (c - x_i)/h.
+//   P2P  (Sec. 1) pairwise sum over the U list, skipping j == i and r == 0.
+#include "ops.h"
+
+namespace fmm {
+
+// LDS exchange between the lanes of one wavefront (no workgroup barrier: the
+// four wavefronts of a P2P block run independent loops)
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline void box_geom(const PlanView &v, int b, double cen[3], double &h)
+{
+    int l = v.level[b], c[3];
+    deinterleave(v.morton[b], l, c);
+    h = v.W / (double)(1ll << l);
+    for (int k = 0; k < 3; ++k) cen[k] = v.lo[k] + ((double)c[k] + 0.5) * h;
+}
+
+// ---------------- charges in sorted order ----------------
+__global__ __launch_bounds__(256) void k_permute_q(const PlanView *V, Bases B)
+{
+    int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    int i = (blockIdx.x - B.b[k]) * 256 + threadIdx.x;
+    if (i < v.n) v.qs[i] = v.q_in[v.perm[i]];
+}
+
+// ---------------- P2M ----------------
+template <int P>
+__global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
+{
+    constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
+    constexpr int R = (NC + 63) / 64;
+    __shared__ double pw[3][P + 1][65];
+    __shared__ double Q[NC];
+    int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int box = v.leaves[blockIdx.x - B.b[k]];
+    const int lane = threadIdx.x;
+    double cen[3], h;
+    box_geom(v, box, cen, h);
+    const double ih = 1.0 / h;
+    int ex[R], ey[R], ez[R];
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int g = lane + 64 * r;
+        int e = g < NC ? v.tab->exps[g] : 0;
+        ex[r] = e & 255; ey[r] = (e >> 8) & 255; ez[r] = (e >> 16) & 255;
+        acc[r] = 0.0;
+    }
+    const int f = v.first[box], cnt = v.count[box];
+    for (int s = 0; s < cnt; s += 64) {
+        int i = f + s + lane;
+        double u0 = 0, u1 = 0, u2 = 0, q = 0;
+        if (s + lane < cnt) {
+            u0 = (v.xs[i] - cen[0]) * ih;
+            u1 = (v.ys[i] - cen[1]) * ih;
+            u2 = (v.zs[i] - cen[2]) * ih;
+            q = v.qs[i];
+        }
+        double a = q, b = 1.0, c = 1.0;
+#pragma unroll
+        for (int e = 0; e <= P; ++e) {
+            pw[0][e][lane] = a; pw[1][e][lane] = b; pw[2][e][lane] = c;
+            a *= u0; b *= u1; c *= u2;
+        }
+        __syncthreads();
+        int m = cnt - s < 64 ? cnt - s : 64;
+        for (int t = 0; t < m; ++t)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] += pw[0][ex[r]][t] * pw[1][ey[r]][t] * pw[2][ez[r]][t];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (lane + 64 * r < NC) Q[lane + 64 * r] = acc[r];
+    __syncthreads();
+    double *M = v.M + (int64_t)box * v.ldm;
+    const double *T = v.tab->P2M;
+    for (int a = lane; a < v.ldm; a += 64) {
+        double s = 0.0;
+        if (a < NC) {
+            int e = v.tab->exps[a];
+            int d = (e & 255) + ((e >> 8) & 255) + ((e >> 16) & 255);
+            for (int g = below(d); g < below(d + 1); ++g) s += T[(int64_t)g * NC + a] * Q[g];
+        }
+        M[a] = s;
+    }
+}
+
+// ---------------- fold Mhat onto the harmonic components used by M2L ----------------
+__global__ __launch_bounds__(256) void k_fold(const PlanView *V, Bases B)
+{
+    int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    int box = (blockIdx.x - B.b[k]) * 4 + (threadIdx.x >> 6);
+    if (box >= v.nboxes) return;
+    const OrderTables &t = *v.tab;
+    const double *M = v.M + (int64_t)box * v.ldm;
+    for (int c = threadIdx.x & 63; c < v.ldh; c += 64) {
+        double s = 0.0;
+        for (int e = t.fold_off[c]; e < t.fold_off[c + 1]; ++e) s += t.fold_c[e] * M[t.fold_idx[e]];
+        v.Mh[(int64_t)box * v.ldh + c] = s;
+        if (v.mixed_m2l) v.Mhf[(int64_t)box * v.ldh + c] = (float)s;
+    }
+}
+
+// ---------------- M2M / L2L: 16 parents per block ----------------
+constexpr int kPG = 16;
+
+// child of parent b in octant o, or -1
+__device__ inline int child_in_octant(const PlanView &v, int b, int o)
+{
+    int cb = v.child_begin[b], nc = v.nchild[b];
+    for (int i = 0; i < nc; ++i)
+        if ((int)(v.morton[cb + i] & 7) == o) return cb + i;
+    return -1;
+}
+
+// up: 1 = M2M (children -> parent), 0 = L2L (parent -> children)
+template <int UP>
+__global__ __launch_bounds__(256) void k_translate(const PlanView *V, Bases B, int level)
+{
+    extern __shared__ double sh[]; // [kPG][ldm]
+    __shared__ int sbox[kPG], schild[kPG];
+    __shared__ int sany;
+    int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int g = blockIdx.x - B.b[k];
+    const int lb = v.lvl_nonleaf_off[level], le = v.lvl_nonleaf_off[level + 1];
+    const int nc = v.nc, ldm = v.ldm, tid = threadIdx.x;
+    if (tid < kPG) {
+        int idx = lb + g * kPG + tid;
+        sbox[tid] = idx < le ? v.lvl_nonleaf[idx] : -1;
+    }
+    __syncthreads();
+    const double *Mat = UP ? v.tab->S : v.tab->G;
+    double acc[kPG][2];
+    if (!UP) { // parent local expansions, loaded once
+        for (int e = tid; e < kPG * ldm; e += 256) {
+            int q = e / ldm, a = e - q * ldm;
+            sh[e] = sbox[q] >= 0 ? v.L[(int64_t)sbox[q] * ldm + a] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kPG; ++q) acc[q][0] = acc[q][1] = 0.0;
+    for (int o = 0; o < 8; ++o) {
+        __syncthreads(); // the previous octant is done with sh, schild and sany
+        if (tid == 0) sany = 0;
+        __syncthreads();
+        if (tid < kPG) {
+            int c = sbox[tid] >= 0 ? child_in_octant(v, sbox[tid], o) : -1;
+            schild[tid] = c;
+            if (c >= 0) atomicOr(&sany, 1);
+        }
+        __syncthreads();
+        if (!sany) continue;
+        if (UP) {
+            for (int e = tid; e < kPG * ldm; e += 256) {
+                int q = e / ldm, a = e - q * ldm;
+                sh[e] = schild[q] >= 0 ? v.M[(int64_t)schild[q] * ldm + a] : 0.0;
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int q = 0; q < kPG; ++q) acc[q][0] = acc[q][1] = 0.0;
+        }
+        const double *T = Mat + (int64_t)o * nc * nc;
+        for (int a = 0; a < nc; ++a) {
+            double s0 = tid < nc ? T[(int64_t)a * nc + tid] : 0.0;
+            double s1 = tid + 256 < nc ? T[(int64_t)a * nc + tid + 256] : 0.0;
+#pragma unroll
+            for (int q = 0; q < kPG; ++q) {
+                double m = sh[q * ldm + a];
+                acc[q][0] += s0 * m;
+                acc[q][1] += s1 * m;
+            }
+        }
+        if (!UP) { // add into each existing child of this octant
+#pragma unroll
+            for (int q = 0; q < kPG; ++q) {
+                int c = schild[q];
+                if (c < 0) continue;
+                if (tid < nc) v.L[(int64_t)c * ldm + tid] += acc[q][0];
+                if (tid + 256 < nc) v.L[(int64_t)c * ldm + tid + 256] += acc[q][1];
+            }
+        }
+    }
+    if (UP) {
+#pragma unroll
+        for (int q = 0; q < kPG; ++q) {
+            int b = sbox[q];
+            if (b < 0) continue;
+            for (int r = 0; r < 2; ++r) {
+                int a = tid + 256 * r;
+                if (a < ldm) v.M[(int64_t)b * ldm + a] = a < nc ? acc[q][r] : 0.0;
+            }
+        }
+    }
+}
+
+// ---------------- unfold the M2L result to full local expansions ----------------
+__global__ __launch_bounds__(256) void k_unfold(const PlanView *V, Bases B)
+{
+    int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    int box = (blockIdx.x - B.b[k]) * 4 + (threadIdx.x >> 6);
+    if (box >= v.nboxes) return;
+    const OrderTables &t = *v.tab;
+    const double *Lh = v.Lh + (int64_t)box * v.ldh;
+    // rows of Lh exist only for boxes that received M2L or P2L contributions
+    bool on = v.level[box] >= 2 &&
+              (v.V_off[box + 1] > v.V_off[box] || v.X_off[box + 1] > v.X_off[box]);
+    for (int b = threadIdx.x & 63; b < v.ldm; b += 64) {
+        double s = 0.0;
+        if (on && b < v.nc)
+            for (int e = t.unfold_off[b]; e < t.unfold_off[b + 1]; ++e) s += t.unfold_c[e] * Lh[t.unfold_idx[e]];
+        v.L[(int64_t)box * v.ldm + b] = s;
+    }
+}
+
+// ---------------- P2L (X list) ----------------
+// One wavefront per target box; lane = source particle; the harmonic
+// components (b_z <= 1) of d^b(1/|x|) follow from the Taylor recurrence of 1/|x|,
+// which stays within b_z <= 1; the sum over particles is done per coefficient.
+template <int P>
+__global__ __launch_bounds__(64) void k_p2l(const PlanView *V, Bases B)
+{
+    constexpr int NH = (P + 1) * (P + 1);
+    constexpr int R = (NH + 63) / 64;
+    __shared__ double a[NH][65];
+    int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int box = v.xtgt[blockIdx.x - B.b[k]];
+    const int lane = threadIdx.x;
+    double cen[3], h;
+    box_geom(v, box, cen, h);
+    const double ih = 1.0 / h;
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int64_t e = v.X_off[box]; e < v.X_off[box + 1]; ++e) {
+        int src = v.X_src[e];
+        int f = v.first[src], cnt = v.count[src];
+        for (int s = 0; s < cnt; s += 64) {
+            double x = 1, y = 0, z = 0, q = 0;
+            if (s + lane < cnt) {
+                int i = f + s + lane;
+                x = (cen[0] - v.xs[i]) * ih; y = (cen[1] - v.ys[i]) * ih; z = (cen[2] - v.zs[i]) * ih;
+                q = v.qs[i];
+            }
+            double r2 = x * x + y * y + z * z, ir2 = 1.0 / r2;
+            // Taylor coefficients a_g, then D_g = g! a_g; a[0] = q / r
+            a[0][lane] = q * sqrt(ir2);
+#pragma unroll
+            for (int n = 1; n <= P; ++n) {
+#pragma unroll
+                for (int kz = 0; kz <= 1; ++kz)
+#pragma unroll
+                    for (int i = n - kz; i >= 0; --i) {
+                        int j = n - kz - i;
+                        double s1 = 0.0, s2 = 0.0;
+                        if (i >= 1) s1 += x * a[harm_index(i - 1, j, kz)][lane];
+                        if (j >= 1) s1 += y * a[harm_index(i, j - 1, kz)][lane];
+                        if (kz >= 1) s1 += z * a[harm_index(i, j, kz - 1)][lane];
+                        if (i >= 2) s2 += a[harm_index(i - 2, j, kz)][lane];
+                        if (j >= 2) s2 += a[harm_index(i, j - 2, kz)][lane];
+                        a[harm_index(i, j, kz)][lane] =
+                            -((2 * n - 1) * s1 + (n - 1) * s2) * ir2 / (double)n;
+                    }
+            }
+            __syncthreads();
+            int m = cnt - s < 64 ? cnt - s : 64;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                int c = lane + 64 * r;
+                if (c < NH)
+                    for (int t = 0; t < m; ++t) acc[r] += a[c][t];
+            }
+            __syncthreads();
+        }
+    }
+    // D_c = c! a_c; c = (i, j, kz)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        int c = lane + 64 * r;
+        if (c < NH) {
+            int n = 0;
+            while ((n + 1) * (n + 1) <= c) ++n;
+            int w = c - n * n, i, j, kz;
+            if (w <= n) { kz = 0; i = n - w; j = n - i; }
+            else { kz = 1; i = n - 1 - (w - n - 1); j = n - 1 - i; }
+            double fct = 1.0;
+            for (int t = 2; t <= i; ++t) fct *= t;
+            for (int t = 2; t <= j; ++t) fct *= t;
+            double *dst = v.Lh + (int64_t)box * v.ldh + c;
+            double base = v.V_off[box + 1] > v.V_off[box] ? *dst : 0.0; // M2L wrote this row?
+            *dst = base + acc[r] * fct;
+        }
+    }
+}
+
+// ---------------- far field at the targets: L2P + M2P ----------------
+template <int P>
+__device__ inline int cmono(int i, int j, int k)
+{
+    int n = i + j + k, a = j + k;
+    return n * (n + 1) * (n + 2) / 6 + a * (a + 1) / 2 + k;
+}
+
+// f = sum_a c_a x^a y^b z^c and its gradient, nested Horner in z, y, x
+template <int P>
+__device__ inline void eval_poly(const double *c, double x, double y, double z, double &f,
+                                 double &fx, double &fy, double &fz)
+{
+    f = fx = fy = fz = 0.0;
+#pragma unroll
+    for (int i = P; i >= 0; --i) {
+        double S = 0.0, Sy = 0.0, Sz = 0.0;
+#pragma unroll
+        for (int j = P - i; j >= 0; --j) {
+            double T = 0.0, Tz = 0.0;
+#pragma unroll
+            for (int kk = P - i - j; kk >= 0; --kk) {
+                Tz = Tz * z + T;
+                T = T * z + c[cmono<P>(i, j, kk)];
+            }
+            Sy = Sy * y + S;
+            S = S * y + T;
+            Sz = Sz * y + Tz;
+        }
+        fx = fx * x + f;
+        f = f * x + S;
+        fy = fy * x + Sy;
+        fz = fz * x + Sz;
+    }
+}
+
+template <int P>
+__global__ __launch_bounds__(64) void k_far(const PlanView *V, Bases B)
+{
+    constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
+    __shared__ double cl[NC], cm[NC];
+    int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int box = v.leaves[blockIdx.x - B.b[k]];
+    const int lane = threadIdx.x;
+    const OrderTables &t = *v.tab;
+    double cen[3], h;
+    box_geom(v, box, cen, h);
+    const bool loc = v.level[box] >= 2;
+    if (loc)
+        for (int a = lane; a < NC; a += 64) cl[a] = v.L[(int64_t)box * v.ldm + a] * t.inv_fact[a];
+    __syncthreads();
+    const int f = v.first[box], cnt = v.count[box];
+    const int64_t w0 = v.W_off[box], w1 = v.W_off[box + 1];
+    for (int s = 0; s < cnt; s += 64) {
+        int i = f + s + lane;
+        bool act = s + lane < cnt;
+        double x = act ? v.xs[i] : cen[0], y = act ? v.ys[i] : cen[1], z = act ? v.zs[i] : cen[2];
+        double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        if (loc) {
+            double ih = 1.0 / h, f0, fx, fy, fz;
+            eval_poly<P>(cl, (x - cen[0]) * ih, (y - cen[1]) * ih, (z - cen[2]) * ih, f0, fx, fy, fz);
+            phi = f0 * ih;
+            double ih2 = ih * ih;
+            gx = fx * ih2; gy = fy * ih2; gz = fz * ih2;
+        }
+        for (int64_t e = w0; e < w1; ++e) {
+            int src = v.W_src[e];
+            double sc[3], hs;
+            __syncthreads();
+            box_geom(v, src, sc, hs);
+            for (int a = lane; a < NC; a += 64) {
+                int ea = t.exps[a];
+                cm[a] = v.M[(int64_t)src * v.ldm + a] * t.inv_w[(ea & 255) + ((ea >> 8) & 255) + ((ea >> 16) & 255)];
+            }
+            __syncthreads();
+            double y0 = x - sc[0], y1 = y - sc[1], y2 = z - sc[2];
+            double s2 = 1.0 / (y0 * y0 + y1 * y1 + y2 * y2), sr = sqrt(s2);
+            double f0, fx, fy, fz;
+            eval_poly<P>(cm, y0 * s2 * hs, y1 * s2 * hs, y2 * s2 * hs, f0, fx, fy, fz);
+            double yf = y0 * fx + y1 * fy + y2 * fz;
+            phi += sr * f0;
+            gx += sr * (-y0 * s2 * f0 + hs * s2 * fx - 2.0 * hs * s2 * s2 * y0 * yf);
+            gy += sr * (-y1 * s2 * f0 + hs * s2 * fy - 2.0 * hs * s2 * s2 * y1 * yf);
+            gz += sr * (-y2 * s2 * f0 + hs * s2 * fz - 2.0 * hs * s2 * s2 * y2 * yf);
+        }
+        if (act) {
+            v.phi_far[i] = phi;
+            v.fld_far[3 * i] = -gx; v.fld_far[3 * i + 1] = -gy; v.fld_far[3 * i + 2] = -gz;
+        }
+    }
+}
+
+// ---------------- P2P and output ----------------
+// Four wavefronts per block, one target leaf each.  Leaves with <= 32 (16)
+// targets split the sources over 2 (4) lane groups whose partial sums are
+// combined in a fixed order at the end.  FP64: plain sums.  Mixed: pair
+// offsets are formed in FP64 and rounded to FP32, the pair terms are FP32, each
+// source box is summed in FP32 and the box partials are accumulated in FP64.
+template <int MIXED>
+__global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B)
+{
+    __shared__ double sx[4][64], sy[4][64], sz[4][64], sq[4][64];
+    int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = (blockIdx.x - B.b[k]) * 4 + wave;
+    if (li >= v.nleaves) return;
+    const int box = v.leaves[li];
+    const int f = v.first[box], cnt = v.count[box];
+    int G = cnt > 32 ? 1 : (cnt > 16 ? 2 : 4);
+    const int TPG = 64 / G, grp = lane / TPG, tl = lane % TPG;
+    const int64_t u0 = v.U_off[box], u1 = v.U_off[box + 1];
+    for (int ts = 0; ts < cnt; ts += TPG) {
+        const int ti = ts + tl;
+        const bool act = ti < cnt;
+        const int i = f + (act ? ti : 0);
+        const double xi = v.xs[i], yi = v.ys[i], zi = v.zs[i];
+        double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+        for (int64_t e = u0; e < u1; ++e) {
+            const int src = v.U_src[e];
+            const int sf = v.first[src], sc = v.count[src];
+            for (int s = 0; s < sc; s += 64) {
+                if (s + lane < sc) {
+                    int j = sf + s + lane;
+                    sx[wave][lane] = v.xs[j]; sy[wave][lane] = v.ys[j]; sz[wave][lane] = v.zs[j];
+                    sq[wave][lane] = v.qs[j];
+                }
+                wave_sync();
+                const int m = sc - s < 64 ? sc - s : 64;
+                const int jbase = sf + s;
+                if (MIXED) {
+                    float p = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+                    for (int jj = grp; jj < m; jj += G) {
+                        float dx = (float)(xi - sx[wave][jj]);
+                        float dy = (float)(yi - sy[wave][jj]);
+                        float dz = (float)(zi - sz[wave][jj]);
+                        float r2 = dx * dx + dy * dy + dz * dz;
+                        bool ok = (jbase + jj != i) && r2 > 0.f;
+                        float ri = ok ? __builtin_amdgcn_rsqf(r2) : 0.f;
+                        float qr = (float)sq[wave][jj] * ri;
+                        float qr3 = qr * ri * ri;
+                        p += qr;
+                        fx += qr3 * dx; fy += qr3 * dy; fz += qr3 * dz;
+                    }
+                    phi += (double)p; ex += (double)fx; ey += (double)fy; ez += (double)fz;
+                } else {
+                    for (int jj = grp; jj < m; jj += G) {
+                        double dx = xi - sx[wave][jj], dy = yi - sy[wave][jj], dz = zi - sz[wave][jj];
+                        double r2 = dx * dx + dy * dy + dz * dz;
+                        bool ok = (jbase + jj != i) && r2 > 0.0;
+                        double ri = ok ? rsqrt(r2) : 0.0;
+                        double qr = sq[wave][jj] * ri;
+                        double qr3 = qr * ri * ri;
+                        phi += qr;
+                        ex += qr3 * dx; ey += qr3 * dy; ez += qr3 * dz;
+                    }
+                }
+                wave_sync();
+            }
+        }
+        // combine lane groups in a fixed order
+        if (G >= 4) {
+            phi += __shfl_down(phi, 16); ex += __shfl_down(ex, 16);
+            ey += __shfl_down(ey, 16); ez += __shfl_down(ez, 16);
+        }
+        if (G >= 2) {
+            phi += __shfl_down(phi, 32); ex += __shfl_down(ex, 32);
+            ey += __shfl_down(ey, 32); ez += __shfl_down(ez, 32);
+        }
+        if (act && grp == 0) {
+            int o = v.perm[i];
+            v.phi_out[o] = v.phi_far[i] + phi;
+            if (v.fld_out) {
+                v.fld_out[3 * o] = v.fld_far[3 * i] + ex;
+                v.fld_out[3 * o + 1] = v.fld_far[3 * i + 1] + ey;
+                v.fld_out[3 * o + 2] = v.fld_far[3 * i + 2] + ez;
+            }
+        }
+    }
+}
+
+__global__ void k_zero(double *p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// ---------------- launchers ----------------
+#define DISPATCH_P(p, KERNEL, ...)                                                     \
+    switch (p) {                                                                       \
+    case 0: KERNEL<0> __VA_ARGS__; break;  case 1: KERNEL<1> __VA_ARGS__; break;     \
+    case 2: KERNEL<2> __VA_ARGS__; break;  case 3: KERNEL<3> __VA_ARGS__; break;     \
+    case 4: KERNEL<4> __VA_ARGS__; break;  case 5: KERNEL<5> __VA_ARGS__; break;     \
+    case 6: KERNEL<6> __VA_ARGS__; break;  case 7: KERNEL<7> __VA_ARGS__; break;     \
+    case 8: KERNEL<8> __VA_ARGS__; break;  case 9: KERNEL<9> __VA_ARGS__; break;     \
+    case 10: KERNEL<10> __VA_ARGS__; break; case 11: KERNEL<11> __VA_ARGS__; break;  \
+    default: KERNEL<12> __VA_ARGS__; break;                                            \
+    }
+
+static inline unsigned nblk(const Bases &B) { return (unsigned)B.b[B.n]; }
+
+void launch_permute_q(const PlanView *V, const Bases &B, hipStream_t s)
+{
+    if (nblk(B)) k_permute_q<<<nblk(B), 256, 0, s>>>(V, B);
+}
+void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s)
+{
+    if (nblk(B)) DISPATCH_P(p, k_p2m, <<<nblk(B), 64, 0, s>>>(V, B));
+}
+void launch_fold(const PlanView *V, const Bases &B, hipStream_t s)
+{
+    if (nblk(B)) k_fold<<<nblk(B), 256, 0, s>>>(V, B);
+}
+void launch_m2m(int ldm, const PlanView *V, const Bases &B, int level, hipStream_t s)
+{
+    if (nblk(B)) k_translate<1><<<nblk(B), 256, sizeof(double) * kPG * ldm, s>>>(V, B, level);
+}
+void launch_l2l(int ldm, const PlanView *V, const Bases &B, int level, hipStream_t s)
+{
+    if (nblk(B)) k_translate<0><<<nblk(B), 256, sizeof(double) * kPG * ldm, s>>>(V, B, level);
+}
+void launch_unfold(const PlanView *V, const Bases &B, hipStream_t s)
+{
+    if (nblk(B)) k_unfold<<<nblk(B), 256, 0, s>>>(V, B);
+}
+void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s)
+{
+    if (nblk(B)) DISPATCH_P(p, k_p2l, <<<nblk(B), 64, 0, s>>>(V, B));
+}
+void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s)
+{
+    if (nblk(B)) DISPATCH_P(p, k_far, <<<nblk(B), 64, 0, s>>>(V, B));
+}
+void launch_p2p(int mixed, const PlanView *V, const Bases &B, hipStream_t s)
+{
+    if (!nblk(B)) return;
+    if (mixed) k_p2p<1><<<nblk(B), 256, 0, s>>>(V, B);
+    else k_p2p<0><<<nblk(B), 256, 0, s>>>(V, B);
+}
+void launch_zero(double *p, int64_t n, hipStream_t s)
+{
+    if (n > 0) k_zero<<<ceil_div(n, 256), 256, 0, s>>>(p, n);
+}
+
+} // namespace fmm

@@ -1,0 +1,378 @@
+// Per-order constant tables, derived on the host in long double from closed
+// forms (not from a DA composition), then rounded to FP64 / FP32 and uploaded
+// once per (device, order).
+//
+//  P2M     The multipole of one charge at offset y is (1 - 2 y.d + y^2 d^2)^-1/2
+//          (Eq. P2M, sign reading), the Legendre generating function; its
+//          degree-n coefficients c_a(y) obey
+//              n c_a = (2n-1) sum_k y_k c_(a-e_k) - (n-1) |y|^2 sum_k c_(a-2e_k).
+//          Each c_a is a homogeneous polynomial in y, so the expansion of a box
+//          is a fixed linear map of its raw moments Q_g = sum q u^g (u = y/h).
+//  M2L     With harmonic degrees, phi = sum_a w_|a| M_a d^a(1/|x|), so the
+//          local coefficients are derivatives of 1/|x| at the offset:
+//          Lhat_b = sum_a D_(a+b)(k) Mhat_a (see common.h).  D_g(k) = g! a_g(k)
+//          from the recurrence of the Taylor coefficients a_g of 1/|x|:
+//              n |x|^2 a_g + (2n-1) sum_k x_k a_(g-e_k) + (n-1) sum_k a_(g-2e_k) = 0.
+//          Since d^2/dz^2 (1/r) = -(d^2/dx^2 + d^2/dy^2)(1/r), only components
+//          with a_z, b_z <= 1 are contracted: Mhat is first folded onto them,
+//          and the result unfolded by the same identity.
+//  M2M     The child's field sum_a W_a d^a(1/|x - c|) (W = w M) re-expanded at
+//          the parent centre by Taylor in the source position, then projected
+//          onto harmonic polynomials per degree (which leaves the field
+//          unchanged and gives the DA representative):
+//              pi_n(P) = sum_k (-1)^k (2n-2k-1)!! / ((2n-1)!! (2k)!!) r^(2k) Lap^k P.
+//  L2L     Taylor shift of a polynomial (map M3 of Sec. 2.5).
+#include "tables.h"
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <vector>
+
+namespace fmm {
+
+typedef long double ld;
+
+namespace {
+
+struct Mono {
+    int p, n;
+    std::vector<int> e; // 3 per monomial
+    Mono(int p_) : p(p_), n(ncoef(p_)), e(3 * ncoef(p_))
+    {
+        for (int d = 0; d <= p; ++d)
+            for (int i = d; i >= 0; --i)
+                for (int j = d - i; j >= 0; --j) {
+                    int k = d - i - j, id = mono_index(i, j, k);
+                    e[3 * id] = i; e[3 * id + 1] = j; e[3 * id + 2] = k;
+                }
+    }
+    int deg(int id) const { return e[3 * id] + e[3 * id + 1] + e[3 * id + 2]; }
+};
+
+ld fact(int n) { ld r = 1; for (int i = 2; i <= n; ++i) r *= i; return r; }
+ld dfact(int n) { ld r = 1; for (int i = n; i > 1; i -= 2) r *= i; return r; } // n!!, (-1)!! = 1
+ld binom(int m, int a) { return fact(m) / (fact(a) * fact(m - a)); }
+ld ipow(ld x, int k) { ld r = 1; for (int i = 0; i < k; ++i) r *= x; return r; }
+
+// Taylor coefficients a_g(x) of 1/|x| for |g| <= maxdeg and g_z <= maxz,
+// stored by mono_index (order maxdeg); entries with g_z > maxz left 0.
+void inv_r_taylor(const ld x[3], int maxdeg, int maxz, std::vector<ld> &a)
+{
+    Mono m(maxdeg);
+    a.assign(m.n, 0.0L);
+    ld r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    a[0] = 1.0L / std::sqrt(r2);
+    for (int id = 1; id < m.n; ++id) {
+        int g[3] = {m.e[3 * id], m.e[3 * id + 1], m.e[3 * id + 2]};
+        if (g[2] > maxz) continue;
+        int n = g[0] + g[1] + g[2];
+        ld s1 = 0, s2 = 0;
+        for (int k = 0; k < 3; ++k) {
+            if (g[k] >= 1) {
+                int h[3] = {g[0], g[1], g[2]}; h[k] -= 1;
+                s1 += x[k] * a[mono_index(h[0], h[1], h[2])];
+            }
+            if (g[k] >= 2) {
+                int h[3] = {g[0], g[1], g[2]}; h[k] -= 2;
+                s2 += a[mono_index(h[0], h[1], h[2])];
+            }
+        }
+        a[id] = -((2 * n - 1) * s1 + (n - 1) * s2) / (n * r2);
+    }
+}
+
+// P2M: coefficients of the polynomials c_a(u) (degree |a|) over monomials u^g.
+// Returns C[a][g] (n x n, block diagonal by degree).
+std::vector<ld> p2m_polys(const Mono &m)
+{
+    int n = m.n;
+    std::vector<ld> C((size_t)n * n, 0.0L);
+    C[0] = 1.0L;
+    for (int id = 1; id < n; ++id) {
+        int a[3] = {m.e[3 * id], m.e[3 * id + 1], m.e[3 * id + 2]};
+        int d = a[0] + a[1] + a[2];
+        std::vector<ld> out(n, 0.0L);
+        for (int k = 0; k < 3; ++k) {
+            if (a[k] >= 1) { // (2d-1) u_k c_(a-e_k)
+                int h[3] = {a[0], a[1], a[2]}; h[k] -= 1;
+                const ld *src = &C[(size_t)mono_index(h[0], h[1], h[2]) * n];
+                for (int g = 0; g < n; ++g)
+                    if (src[g] != 0) {
+                        int t[3] = {m.e[3 * g], m.e[3 * g + 1], m.e[3 * g + 2]}; t[k] += 1;
+                        out[mono_index(t[0], t[1], t[2])] += (2 * d - 1) * src[g];
+                    }
+            }
+            if (a[k] >= 2) { // -(d-1) |u|^2 c_(a-2e_k)
+                int h[3] = {a[0], a[1], a[2]}; h[k] -= 2;
+                const ld *src = &C[(size_t)mono_index(h[0], h[1], h[2]) * n];
+                for (int g = 0; g < n; ++g)
+                    if (src[g] != 0)
+                        for (int j = 0; j < 3; ++j) {
+                            int t[3] = {m.e[3 * g], m.e[3 * g + 1], m.e[3 * g + 2]}; t[j] += 2;
+                            out[mono_index(t[0], t[1], t[2])] -= (d - 1) * src[g];
+                        }
+            }
+        }
+        for (int g = 0; g < n; ++g) C[(size_t)id * n + g] = out[g] / d;
+    }
+    return C;
+}
+
+// harmonic projection of the homogeneous polynomial with coefficient vector v
+// (over all monomials of order p; only degree `deg` entries nonzero)
+std::vector<ld> harmonic_projection(const Mono &m, const std::vector<ld> &v, int deg)
+{
+    int n = m.n;
+    std::vector<ld> out(n, 0.0L), lap = v;
+    for (int k = 0; 2 * k <= deg; ++k) {
+        ld c = ((k & 1) ? -1.0L : 1.0L) * dfact(2 * deg - 2 * k - 1) /
+               (dfact(2 * deg - 1) * dfact(2 * k));
+        // r^(2k) * lap
+        std::vector<ld> t = lap;
+        for (int s = 0; s < k; ++s) {
+            std::vector<ld> u(n, 0.0L);
+            for (int g = 0; g < n; ++g)
+                if (t[g] != 0)
+                    for (int j = 0; j < 3; ++j) {
+                        int e[3] = {m.e[3 * g], m.e[3 * g + 1], m.e[3 * g + 2]}; e[j] += 2;
+                        int d = e[0] + e[1] + e[2];
+                        if (d <= m.p) u[mono_index(e[0], e[1], e[2])] += t[g];
+                    }
+            t.swap(u);
+        }
+        for (int g = 0; g < n; ++g) out[g] += c * t[g];
+        // next Laplacian
+        std::vector<ld> u(n, 0.0L);
+        for (int g = 0; g < n; ++g)
+            if (lap[g] != 0)
+                for (int j = 0; j < 3; ++j) {
+                    int e[3] = {m.e[3 * g], m.e[3 * g + 1], m.e[3 * g + 2]};
+                    if (e[j] < 2) continue;
+                    ld f = (ld)e[j] * (e[j] - 1);
+                    e[j] -= 2;
+                    u[mono_index(e[0], e[1], e[2])] += f * lap[g];
+                }
+        lap.swap(u);
+    }
+    return out;
+}
+
+struct Built {
+    std::vector<double> D, S, G, P2M, fold_c, unfold_c, inv_fact, inv_w;
+    std::vector<float> Df;
+    std::vector<int> offs, hoff, fold_off, fold_idx, unfold_off, unfold_idx, exps;
+    int ldd = 0;
+};
+
+void build_tables(int p, Built &B)
+{
+    Mono m(p);
+    const int nc = m.n, nh = nharm(p), ldh = pad16(nh), d3 = 2 * p + 1;
+    // exponent packing, factorial tables
+    B.exps.resize(nc);
+    B.inv_fact.resize(nc);
+    for (int id = 0; id < nc; ++id) {
+        int i = m.e[3 * id], j = m.e[3 * id + 1], k = m.e[3 * id + 2];
+        B.exps[id] = i | (j << 8) | (k << 16);
+        B.inv_fact[id] = (double)(1.0L / (fact(i) * fact(j) * fact(k)));
+    }
+    B.inv_w.resize(p + 1);
+    for (int n = 0; n <= p; ++n) B.inv_w[n] = (double)(((n & 1) ? -1.0L : 1.0L) * dfact(2 * n - 1));
+
+    // harmonic index -> exponents, additive D addresses
+    std::vector<int> hx(nh), hy(nh), hz(nh);
+    for (int n = 0; n <= p; ++n) {
+        for (int i = n; i >= 0; --i) { int c = harm_index(i, n - i, 0); hx[c] = i; hy[c] = n - i; hz[c] = 0; }
+        for (int i = n - 1; i >= 0; --i) { int c = harm_index(i, n - 1 - i, 1); hx[c] = i; hy[c] = n - 1 - i; hz[c] = 1; }
+    }
+    B.hoff.assign(ldh, 0);
+    for (int c = 0; c < nh; ++c) B.hoff[c] = hz[c] * d3 * d3 + hx[c] * d3 + hy[c];
+
+    // derivative tensors at the 343 integer offsets (near ones left zero)
+    B.ldd = (3 * d3 * d3 + 1) & ~1;
+    B.D.assign((size_t)343 * B.ldd, 0.0);
+    B.Df.assign((size_t)343 * B.ldd, 0.0f);
+    std::vector<ld> a;
+    for (int kx = -3; kx <= 3; ++kx)
+        for (int ky = -3; ky <= 3; ++ky)
+            for (int kz = -3; kz <= 3; ++kz) {
+                if (std::abs(kx) <= 1 && std::abs(ky) <= 1 && std::abs(kz) <= 1) continue;
+                ld x[3] = {(ld)kx, (ld)ky, (ld)kz};
+                inv_r_taylor(x, 2 * p, 2, a);
+                size_t base = (size_t)((kx + 3) * 49 + (ky + 3) * 7 + (kz + 3)) * B.ldd;
+                for (int z = 0; z <= 2; ++z)
+                    for (int i = 0; i + z <= 2 * p; ++i)
+                        for (int j = 0; i + j + z <= 2 * p; ++j) {
+                            ld v = a[mono_index(i, j, z)] * fact(i) * fact(j) * fact(z);
+                            B.D[base + z * d3 * d3 + i * d3 + j] = (double)v;
+                            B.Df[base + z * d3 * d3 + i * d3 + j] = (float)v;
+                        }
+            }
+    // V-list slot -> offset
+    B.offs.assign(8 * kVSlots, 0);
+    for (int o = 0; o < 8; ++o)
+        for (int kx = -3; kx <= 3; ++kx)
+            for (int ky = -3; ky <= 3; ++ky)
+                for (int kz = -3; kz <= 3; ++kz) {
+                    int s = vslot_of(o, kx, ky, kz);
+                    if (s >= 0) B.offs[o * kVSlots + s] = (kx + 3) * 49 + (ky + 3) * 7 + (kz + 3);
+                }
+
+    // P2M: moments -> Mhat, table[g][a] = w_|a| C[a][g]
+    std::vector<ld> C = p2m_polys(m);
+    B.P2M.assign((size_t)nc * nc, 0.0);
+    for (int id = 0; id < nc; ++id) {
+        int d = m.deg(id);
+        ld w = ((d & 1) ? -1.0L : 1.0L) / dfact(2 * d - 1);
+        for (int g = 0; g < nc; ++g) B.P2M[(size_t)g * nc + id] = (double)(w * C[(size_t)id * nc + g]);
+    }
+
+    // M2M: S[o][a][b] = d Mhat'_b / d Mhat_a.  tau = (child - parent) / h_child.
+    // The harmonic projection is linear: tabulate it on the monomial basis.
+    std::vector<ld> Pi((size_t)nc * nc, 0.0L); // Pi[g][b]: projection of u^g, coefficient b
+    for (int g = 0; g < nc; ++g) {
+        std::vector<ld> unit(nc, 0.0L);
+        unit[g] = 1.0L;
+        std::vector<ld> h = harmonic_projection(m, unit, m.deg(g));
+        for (int be = 0; be < nc; ++be) Pi[(size_t)g * nc + be] = h[be];
+    }
+    B.S.assign((size_t)8 * nc * nc, 0.0);
+    for (int o = 0; o < 8; ++o) {
+        ld tau[3] = {((o >> 2) & 1) ? 0.5L : -0.5L, ((o >> 1) & 1) ? 0.5L : -0.5L,
+                     (o & 1) ? 0.5L : -0.5L};
+        for (int al = 0; al < nc; ++al) {
+            int ea[3] = {m.e[3 * al], m.e[3 * al + 1], m.e[3 * al + 2]};
+            // shifted (non-harmonic) coefficients N_g = 2^-|g| (-tau)^(g-a)/(g-a)!
+            std::vector<ld> out(nc, 0.0L);
+            for (int g = 0; g < nc; ++g) {
+                int eg[3] = {m.e[3 * g], m.e[3 * g + 1], m.e[3 * g + 2]};
+                if (eg[0] < ea[0] || eg[1] < ea[1] || eg[2] < ea[2]) continue;
+                ld v = std::ldexp(1.0L, -(eg[0] + eg[1] + eg[2]));
+                for (int k = 0; k < 3; ++k) v *= ipow(-tau[k], eg[k] - ea[k]) / fact(eg[k] - ea[k]);
+                for (int be = 0; be < nc; ++be) out[be] += Pi[(size_t)g * nc + be] * v;
+            }
+            for (int be = 0; be < nc; ++be) B.S[((size_t)o * nc + al) * nc + be] = (double)out[be];
+        }
+    }
+    // L2L: G[o][g][b] = tau^(g-b)/(g-b)! 2^-(|g|+1) for g >= b
+    B.G.assign((size_t)8 * nc * nc, 0.0);
+    for (int o = 0; o < 8; ++o) {
+        ld tau[3] = {((o >> 2) & 1) ? 0.5L : -0.5L, ((o >> 1) & 1) ? 0.5L : -0.5L,
+                     (o & 1) ? 0.5L : -0.5L};
+        for (int g = 0; g < nc; ++g) {
+            int eg[3] = {m.e[3 * g], m.e[3 * g + 1], m.e[3 * g + 2]};
+            for (int be = 0; be < nc; ++be) {
+                int eb[3] = {m.e[3 * be], m.e[3 * be + 1], m.e[3 * be + 2]};
+                if (eg[0] < eb[0] || eg[1] < eb[1] || eg[2] < eb[2]) continue;
+                ld v = std::ldexp(1.0L, -(eg[0] + eg[1] + eg[2] + 1));
+                for (int k = 0; k < 3; ++k) v *= ipow(tau[k], eg[k] - eb[k]) / fact(eg[k] - eb[k]);
+                B.G[((size_t)o * nc + g) * nc + be] = (double)v;
+            }
+        }
+    }
+    // fold: harmonic c = (I,J,kz) <- full (I-2a, J-2(m-a), kz+2m), coefficient (-1)^m C(m,a)
+    B.fold_off.assign(ldh + 1, 0);
+    for (int c = 0; c < ldh; ++c) {
+        B.fold_off[c] = (int)B.fold_idx.size();
+        if (c >= nh) continue;
+        for (int mm = 0; hz[c] + 2 * mm <= p; ++mm)
+            for (int aa = 0; aa <= mm; ++aa) {
+                int i = hx[c] - 2 * aa, j = hy[c] - 2 * (mm - aa), k = hz[c] + 2 * mm;
+                if (i < 0 || j < 0) continue;
+                B.fold_idx.push_back(mono_index(i, j, k));
+                B.fold_c.push_back((double)(((mm & 1) ? -1.0L : 1.0L) * binom(mm, aa)));
+            }
+    }
+    B.fold_off[ldh] = (int)B.fold_idx.size();
+    // unfold: full b = (i,j,k) <- harmonic (i+2a, j+2(m-a), k mod 2), m = k/2
+    B.unfold_off.assign(nc + 1, 0);
+    for (int be = 0; be < nc; ++be) {
+        B.unfold_off[be] = (int)B.unfold_idx.size();
+        int i = m.e[3 * be], j = m.e[3 * be + 1], k = m.e[3 * be + 2], mm = k / 2;
+        for (int aa = 0; aa <= mm; ++aa) {
+            B.unfold_idx.push_back(harm_index(i + 2 * aa, j + 2 * (mm - aa), k & 1));
+            B.unfold_c.push_back((double)(((mm & 1) ? -1.0L : 1.0L) * binom(mm, aa)));
+        }
+    }
+    B.unfold_off[nc] = (int)B.unfold_idx.size();
+}
+
+struct Entry {
+    OrderTables host;       // device pointers
+    OrderTables *dev = nullptr;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, int>, Entry> g_cache;
+
+template <typename T>
+int upload(const std::vector<T> &v, const T **out, std::string &err)
+{
+    void *d = nullptr;
+    size_t bytes = sizeof(T) * (v.empty() ? 1 : v.size());
+    if (hipMalloc(&d, bytes) != hipSuccess) { err = "hipMalloc failed for order tables"; return -1; }
+    if (!v.empty() && hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        err = "hipMemcpy failed for order tables";
+        return -1;
+    }
+    *out = (const T *)d;
+    return 0;
+}
+
+} // namespace
+
+const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::string &err)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { err = "hipGetDevice failed"; return nullptr; }
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, p);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) {
+        if (host_copy) *host_copy = &it->second.host;
+        return it->second.dev;
+    }
+    Built B;
+    build_tables(p, B);
+    Entry e;
+    OrderTables &t = e.host;
+    t.p = p; t.nc = ncoef(p); t.nh = nharm(p); t.ldm = pad16(t.nc); t.ldh = pad16(t.nh);
+    t.ldd = B.ldd; t.d3 = 2 * p + 1;
+    if (upload(B.D, &t.D, err) || upload(B.Df, &t.Df, err) || upload(B.offs, &t.offs, err) ||
+        upload(B.hoff, &t.hoff, err) || upload(B.S, &t.S, err) || upload(B.G, &t.G, err) ||
+        upload(B.P2M, &t.P2M, err) || upload(B.fold_off, &t.fold_off, err) ||
+        upload(B.fold_idx, &t.fold_idx, err) || upload(B.fold_c, &t.fold_c, err) ||
+        upload(B.unfold_off, &t.unfold_off, err) || upload(B.unfold_idx, &t.unfold_idx, err) ||
+        upload(B.unfold_c, &t.unfold_c, err) || upload(B.inv_fact, &t.inv_fact, err) ||
+        upload(B.inv_w, &t.inv_w, err) || upload(B.exps, &t.exps, err))
+        return nullptr;
+    void *d = nullptr;
+    if (hipMalloc(&d, sizeof(OrderTables)) != hipSuccess ||
+        hipMemcpy(d, &t, sizeof(OrderTables), hipMemcpyHostToDevice) != hipSuccess) {
+        err = "hipMalloc/hipMemcpy failed for order tables";
+        return nullptr;
+    }
+    e.dev = (OrderTables *)d;
+    auto &slot = g_cache[key];
+    slot = e;
+    if (host_copy) *host_copy = &slot.host;
+    return slot.dev;
+}
+
+// Host-side copies for tests of the closed forms (same construction).
+int host_order_tables(int p, int which, std::vector<double> &out)
+{
+    Built B;
+    build_tables(p, B);
+    switch (which) {
+    case 0: out = B.D; return B.ldd;
+    case 1: out = B.S; return ncoef(p);
+    case 2: out = B.G; return ncoef(p);
+    case 3: out = B.P2M; return ncoef(p);
+    default: return -1;
+    }
+}
+
+} // namespace fmm

@@ -1,0 +1,229 @@
+"""Python binding of libfmm_mi355x.so (include/fmm.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  PyTorch tensors supply device memory and the current HIP stream.
+There is no fallback: if the library is missing or no GPU is present the calls
+raise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmm_mi355x.so")
+
+FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_EUNSUPPORTED = 0, -1, -2, -3, -4
+FMM_FP64, FMM_MIXED = 0, 1
+
+SYMBOLS = ["fmm_default_options", "fmm_plan", "fmm_evaluate", "fmm_evaluate_batch",
+           "fmm_plan_footprint", "fmm_plan_estimate", "fmm_plan_sizes", "fmm_plan_export_tree",
+           "fmm_plan_export_expansions", "fmm_plan_set_timing", "fmm_plan_read_timing",
+           "fmm_plan_destroy", "fmm_last_error"]
+STAGES = ["permute", "p2m", "m2m", "fold", "m2l", "p2l", "unfold", "l2l", "l2p_m2p", "p2p"]
+
+
+class FmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (status %d)" % (msg, code))
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("uniform_depth", ctypes.c_int32), ("max_depth", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("want_field", ctypes.c_int32),
+                ("root", ctypes.POINTER(ctypes.c_double))]
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", ctypes.c_void_p), ("free", ctypes.c_void_p), ("ctx", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise FmmError(FMM_EUNSUPPORTED, "libfmm_mi355x.so is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, P = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER
+        L.fmm_default_options.argtypes = [P(Options)]
+        L.fmm_default_options.restype = None
+        L.fmm_plan.argtypes = [vp, i64, i32, i32, P(Options), P(Allocator), vp, P(vp)]
+        L.fmm_evaluate.argtypes = [vp, vp, vp, vp, vp]
+        L.fmm_evaluate_batch.argtypes = [P(vp), P(vp), P(vp), P(vp), i32, vp]
+        L.fmm_plan_footprint.argtypes = [vp, P(ctypes.c_size_t)]
+        L.fmm_plan_estimate.argtypes = [i64, i32, i32, P(Options), P(ctypes.c_size_t)]
+        L.fmm_plan_sizes.argtypes = [vp, P(i64)]
+        L.fmm_plan_export_tree.argtypes = [vp, vp] + [vp] * 17
+        L.fmm_plan_export_expansions.argtypes = [vp, vp, vp, vp]
+        L.fmm_plan_set_timing.argtypes = [vp, ctypes.c_int]
+        L.fmm_plan_read_timing.argtypes = [vp, P(ctypes.c_double), P(i64)]
+        L.fmm_plan_destroy.argtypes = [vp]
+        L.fmm_last_error.restype = ctypes.c_char_p
+        L.fmm_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != FMM_OK:
+        raise FmmError(rc, lib().fmm_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _options(uniform_depth, max_depth, precision, want_field, root):
+    o = Options()
+    lib().fmm_default_options(ctypes.byref(o))
+    o.uniform_depth = uniform_depth
+    o.max_depth = max_depth
+    o.precision = {"fp64": FMM_FP64, "mixed": FMM_MIXED}[precision] if isinstance(precision, str) else precision
+    o.want_field = 1 if want_field else 0
+    keep = None
+    if root is not None:
+        keep = (ctypes.c_double * 4)(*[float(v) for v in root])
+        o.root = ctypes.cast(keep, ctypes.POINTER(ctypes.c_double))
+    return o, keep
+
+
+class Plan:
+    """Octree, interaction lists and workspace for one point set (fmm_plan)."""
+
+    def __init__(self, xyz, order, leaf_size=64, uniform_depth=-1, max_depth=21,
+                 precision="fp64", want_field=True, root=None, stream=None):
+        import torch
+        if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda):
+            raise FmmError(FMM_EINVAL, "xyz must be a CUDA/HIP tensor")
+        xyz = xyz.to(torch.float64).contiguous()
+        if xyz.dim() != 2 or xyz.shape[1] != 3:
+            raise FmmError(FMM_EINVAL, "xyz must have shape [n, 3]")
+        self.n = int(xyz.shape[0])
+        self.order = int(order)
+        self.device = xyz.device
+        o, keep = _options(uniform_depth, max_depth, precision, want_field, root)
+        h = ctypes.c_void_p()
+        _check(lib().fmm_plan(_ptr(xyz), self.n, self.order, int(leaf_size), ctypes.byref(o), None,
+                              _stream(stream), ctypes.byref(h)))
+        self._h = h
+        del keep
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().fmm_plan_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def evaluate(self, q, phi=None, field=None, want_field=True, stream=None):
+        import torch
+        q = q.to(torch.float64).contiguous()
+        if q.shape != (self.n,) or not q.is_cuda:
+            raise FmmError(FMM_EINVAL, "q must be a device tensor of shape [n]")
+        if phi is None:
+            phi = torch.empty(self.n, dtype=torch.float64, device=q.device)
+        if field is None and want_field:
+            field = torch.empty(self.n, 3, dtype=torch.float64, device=q.device)
+        _check(lib().fmm_evaluate(self._h, _ptr(q), _ptr(phi), _ptr(field), _stream(stream)))
+        return phi, field
+
+    def sizes(self):
+        out = (ctypes.c_int64 * 10)()
+        _check(lib().fmm_plan_sizes(self._h, out))
+        keys = ["boxes", "U", "V", "W", "X", "depth", "key_depth", "n", "order", "ncoef"]
+        return dict(zip(keys, [int(v) for v in out]))
+
+    def footprint(self):
+        b = ctypes.c_size_t()
+        _check(lib().fmm_plan_footprint(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def export_tree(self, stream=None):
+        s = self.sizes()
+        nb = s["boxes"]
+        d = dict(root=np.zeros(4), perm=np.zeros(self.n, np.int64), level=np.zeros(nb, np.int32),
+                 morton=np.zeros(nb, np.uint64), first=np.zeros(nb, np.int64), count=np.zeros(nb, np.int64),
+                 parent=np.zeros(nb, np.int32), child_begin=np.zeros(nb, np.int32), nchild=np.zeros(nb, np.int32))
+        for k in "UVWX":
+            d[k + "_off"] = np.zeros(nb + 1, np.int64)
+            d[k + "_src"] = np.zeros(max(s[k], 1), np.int32)
+        keys = ["root", "perm", "level", "morton", "first", "count", "parent", "child_begin", "nchild",
+                "U_off", "U_src", "V_off", "V_src", "W_off", "W_src", "X_off", "X_src"]
+        _check(lib().fmm_plan_export_tree(self._h, _stream(stream),
+                                          *[ctypes.c_void_p(d[k].ctypes.data) for k in keys]))
+        for k in "UVWX":
+            d[k + "_src"] = d[k + "_src"][:s[k]]
+        return d
+
+    def set_timing(self, on=True):
+        _check(lib().fmm_plan_set_timing(self._h, 1 if on else 0))
+
+    def read_timing(self):
+        """{stage: (total ms, timed evaluations)} since the previous read."""
+        ms = (ctypes.c_double * 16)()
+        calls = (ctypes.c_int64 * 16)()
+        _check(lib().fmm_plan_read_timing(self._h, ms, calls))
+        return {name: (ms[i], int(calls[i])) for i, name in enumerate(STAGES)}
+
+    def export_expansions(self, stream=None):
+        s = self.sizes()
+        M = np.zeros((s["boxes"], s["ncoef"]))
+        L = np.zeros((s["boxes"], s["ncoef"]))
+        _check(lib().fmm_plan_export_expansions(self._h, _stream(stream), ctypes.c_void_p(M.ctypes.data),
+                                                ctypes.c_void_p(L.ctypes.data)))
+        return M, L
+
+
+def plan(xyz, order, leaf_size=64, **kw):
+    return Plan(xyz, order, leaf_size, **kw)
+
+
+def evaluate_batch(plans, qs, want_field=True, stream=None):
+    """One fmm_evaluate_batch call over several plans; returns [(phi, field)]."""
+    import torch
+    n = len(plans)
+    outs = []
+    qv = (ctypes.c_void_p * n)()
+    pv = (ctypes.c_void_p * n)()
+    fv = (ctypes.c_void_p * n)()
+    hv = (ctypes.c_void_p * n)()
+    keep = []
+    for i, (p, q) in enumerate(zip(plans, qs)):
+        q = q.to(torch.float64).contiguous()
+        phi = torch.empty(p.n, dtype=torch.float64, device=q.device)
+        fld = torch.empty(p.n, 3, dtype=torch.float64, device=q.device) if want_field else None
+        keep.append(q)
+        outs.append((phi, fld))
+        qv[i] = q.data_ptr()
+        pv[i] = phi.data_ptr()
+        fv[i] = fld.data_ptr() if fld is not None else None
+        hv[i] = p.handle.value
+    _check(lib().fmm_evaluate_batch(hv, qv, pv, fv if want_field else None, n, _stream(stream)))
+    return outs
+
+
+def estimate(n, order, leaf_size=64, uniform_depth=-1, max_depth=21, precision="fp64"):
+    o, keep = _options(uniform_depth, max_depth, precision, True, None)
+    b = ctypes.c_size_t()
+    _check(lib().fmm_plan_estimate(int(n), int(order), int(leaf_size), ctypes.byref(o), ctypes.byref(b)))
+    return int(b.value)

@@ -1,0 +1,186 @@
+"""GPU DA-FMM against the oracle (Sec. 2 operators, Sec. 1 recipe).
+
+FP64 path: potentials and fields equal the oracle FMM to relative L2 1e-12,
+multipole and local expansions coefficient by coefficient.  Mixed path: its
+error against the oracle is bounded and stated.  Evaluation is deterministic
+and a batched evaluation equals the single ones bit for bit.  At full size
+(1e6 uniform points, depth 5, p = 8) potentials are checked against the
+direct sum on sampled targets."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2508_02626_amd import inputs
+from gpu_util import gpu_solve, oracle_tree, rel_l2, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+CFG1 = dict(uniform_depth=3, root=[0, 0, 0, 1])
+
+
+def _check_fp64(x, q, p, kw, tol=1e-12):
+    pl, phi, fld = gpu_solve(x, q, p, **kw)
+    t = oracle_tree(x, **kw)
+    ophi, ofld = t.fmm(p, q)
+    e_phi, e_fld = rel_l2(phi, ophi), rel_l2(fld, ofld)
+    say("  p=%d rel L2 vs oracle: phi %.3e field %.3e" % (p, e_phi, e_fld))
+    assert e_phi <= tol and e_fld <= tol
+    pl.close()
+    return phi, fld
+
+
+@pytest.mark.parametrize("p", [0, 1, 2, 3, 4, 6, 8, 10])
+def test_config1_potentials_match_oracle(p):
+    x, q = inputs.uniform(2000, 0)
+    say("config1 p", p)
+    _check_fp64(x, q, p, CFG1)
+
+
+def test_order12_small_tree():
+    x, q = inputs.uniform(600, 12)
+    say("uniform depth 2, p=12")
+    _check_fp64(x, q, 12, dict(uniform_depth=2, root=[0, 0, 0, 1]))
+
+
+@pytest.mark.parametrize("name,gen,p,kw", [
+    ("plummer_6000_s32_p3", lambda: inputs.plummer(6000, 2), 3, dict(leaf_size=32)),
+    ("plummer_6000_s32_p7", lambda: inputs.plummer(6000, 2), 7, dict(leaf_size=32)),
+    ("clusters_4000_s16_p5", lambda: inputs.clusters(4000, 3), 5, dict(leaf_size=16)),
+    ("gaussian_5000_s50_p6", lambda: inputs.gaussian(5000, 4), 6, dict(leaf_size=50)),
+    ("ragged_777_s5_p4", lambda: inputs.uniform(777, 5), 4, dict(leaf_size=5)),
+    ("bbox_uniform_d3_p5", lambda: inputs.plummer(3000, 6), 5, dict(uniform_depth=3)),
+])
+def test_adaptive_potentials_match_oracle(name, gen, p, kw):
+    x, q = gen()
+    say("case", name)
+    _check_fp64(x, q, p, kw)
+
+
+def test_degenerate_inputs():
+    one = (np.array([[0.3, 0.2, 0.1]]), np.array([2.0]))
+    pl, phi, fld = gpu_solve(*one, 4, leaf_size=4)
+    assert phi[0] == 0.0 and np.all(fld == 0.0)
+    two = (np.array([[0.5, 0.5, 0.5], [0.5, 0.5, 0.5]]), np.array([1.0, -2.0]))
+    pl, phi, fld = gpu_solve(*two, 4, leaf_size=1)
+    assert np.all(phi == 0.0) and np.all(fld == 0.0)       # coincident pair contributes nothing
+    x = np.concatenate([np.tile([[0.1, 0.7, 0.3]], (100, 1)), inputs.uniform(300, 1)[0]])
+    q = np.random.default_rng(0).uniform(-1, 1, 400)
+    _check_fp64(x, q, 5, dict(leaf_size=8, max_depth=5))
+
+
+@pytest.mark.parametrize("name,gen,p,kw", [
+    ("config1_p6", lambda: inputs.uniform(2000, 0), 6, CFG1),
+    ("plummer_5000_s32_p5", lambda: inputs.plummer(5000, 2), 5, dict(leaf_size=32)),
+])
+def test_expansions_match_oracle(name, gen, p, kw):
+    """Coefficient-by-coefficient parity of M (Eq. P2M) and L (Eq. P2L form)."""
+    x, q = gen()
+    say("expansions", name)
+    pl, phi, fld = gpu_solve(x, q, p, **kw)
+    M, L = pl.export_expansions()
+    t = oracle_tree(x, **kw)
+    _, _, oM, oL = t.fmm(p, q, want_expansions=True)
+    deg = oracle.exponents(p).sum(axis=1)
+    for d in range(p + 1):
+        s = deg == d
+        sm = np.abs(oM[:, s]).max()
+        sl = np.abs(oL[:, s]).max()
+        assert np.abs(M[:, s] - oM[:, s]).max() <= 1e-12 * sm + 1e-300, ("M", d)
+        assert np.abs(L[:, s] - oL[:, s]).max() <= 1e-12 * sl + 1e-300, ("L", d)
+    pl.close()
+
+
+def test_error_against_direct_decays_with_order():
+    x, q = inputs.uniform(2000, 0)
+    d, fd = oracle.direct(x, q)
+    errs = []
+    for p in (2, 4, 6, 8, 10):
+        pl, phi, fld = gpu_solve(x, q, p, **CFG1)
+        errs.append(rel_l2(phi, d))
+        pl.close()
+    say("  sigma vs direct by order", errs)
+    assert all(b < 0.5 * a for a, b in zip(errs, errs[1:]))
+
+
+def test_deterministic_repeat():
+    x, q = inputs.plummer(8000, 3)
+    from paper_2508_02626_amd import fmm
+    pl = fmm.Plan(to_dev(x), 6, leaf_size=32)
+    qt = to_dev(q)
+    a, fa = pl.evaluate(qt)
+    a, fa = a.cpu().numpy(), fa.cpu().numpy()
+    for _ in range(3):
+        b, fb = pl.evaluate(qt)
+        assert np.array_equal(a, b.cpu().numpy()) and np.array_equal(fa, fb.cpu().numpy())
+    pl2 = fmm.Plan(to_dev(x), 6, leaf_size=32)
+    c, fc = pl2.evaluate(qt)
+    assert np.array_equal(a, c.cpu().numpy())
+
+
+@pytest.mark.parametrize("p", [4, 6, 8])
+def test_mixed_precision_error_is_bounded(p):
+    """Mixed path (FP32 P2P terms with FP64 accumulation, FP32-MFMA M2L for
+    p <= 8): stated error against the FP64 oracle FMM."""
+    x, q = inputs.uniform(2000, 0)
+    pl, phi, fld = gpu_solve(x, q, p, precision="mixed", **CFG1)
+    t = oracle_tree(x, **CFG1)
+    ophi, ofld = t.fmm(p, q)
+    e_phi, e_fld = rel_l2(phi, ophi), rel_l2(fld, ofld)
+    say("  mixed p=%d rel L2 vs oracle: phi %.3e field %.3e" % (p, e_phi, e_fld))
+    assert e_phi < 3e-7 and e_fld < 3e-7
+
+
+def test_mixed_adaptive_error_is_bounded():
+    x, q = inputs.plummer(8000, 4)
+    pl, phi, fld = gpu_solve(x, q, 6, precision="mixed", leaf_size=32)
+    ophi, ofld = oracle_tree(x, leaf_size=32).fmm(6, q)
+    e_phi, e_fld = rel_l2(phi, ophi), rel_l2(fld, ofld)
+    say("  mixed plummer p=6 rel L2 vs oracle: phi %.3e field %.3e" % (e_phi, e_fld))
+    assert e_phi < 3e-7 and e_fld < 3e-7
+
+
+def test_batch_equals_single():
+    from paper_2508_02626_amd import fmm
+    probs = [
+        (inputs.uniform(3000, 20), 4, dict(uniform_depth=3, root=[0, 0, 0, 1])),
+        (inputs.plummer(5000, 21), 6, dict(leaf_size=32, precision="mixed")),
+        (inputs.clusters(2000, 22), 8, dict(leaf_size=20)),
+        (inputs.uniform(1000, 23), 6, dict(leaf_size=16)),
+        (inputs.uniform(1500, 24), 4, dict(leaf_size=12, precision="mixed")),
+        ((np.array([[0.2, 0.2, 0.2]]), np.array([1.0])), 5, dict(leaf_size=4)),
+    ]
+    plans, qs, singles = [], [], []
+    for (x, q), p, kw in probs:
+        pl = fmm.Plan(to_dev(x), p, **kw)
+        qt = to_dev(q)
+        a, fa = pl.evaluate(qt)
+        singles.append((a.cpu().numpy(), fa.cpu().numpy()))
+        plans.append(pl)
+        qs.append(qt)
+    outs = fmm.evaluate_batch(plans, qs)
+    for (a, fa), (b, fb) in zip(singles, outs):
+        assert np.array_equal(a, b.cpu().numpy())
+        assert np.array_equal(fa, fb.cpu().numpy())
+
+
+def test_full_size_uniform_sampled_against_direct():
+    """1e6 points, depth 5, p = 8 (the benchmark workload), in the launch
+    configuration the benchmark times: sampled targets against the direct sum,
+    and the tree bit-exact against the oracle."""
+    from paper_2508_02626_amd import fmm
+    x, q = inputs.uniform(1_000_000, 1)
+    kw = dict(uniform_depth=5, root=[0, 0, 0, 1])
+    for prec in ("fp64", "mixed"):
+        pl, phi, fld = gpu_solve(x, q, 8, precision=prec, **kw)
+        idx = np.random.default_rng(7).choice(len(q), 300, replace=False)
+        d, fd = oracle.direct(x, q, idx)
+        e = rel_l2(phi[idx], d)
+        ef = rel_l2(fld[idx], fd)
+        say("  %s 1e6 p=8 sampled sigma phi %.3e field %.3e" % (prec, e, ef))
+        assert e < 5e-5 and ef < 2e-4
+        if prec == "fp64":
+            g = pl.export_tree()
+            o = oracle_tree(x, **kw).export()
+            for k in ("perm", "first", "count", "V_off", "V_src", "U_off", "U_src"):
+                assert np.array_equal(g[k].astype(np.int64), o[k].astype(np.int64)), k
+        pl.close()
