@@ -267,8 +267,11 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     for (int w = 0; w < 4; ++w) P->off[w] = P->own<int64_t>(nb + 1);
     NOMEM(coll); NOMEM(cntV); NOMEM(cntU); NOMEM(cntW); NOMEM(cntX); NOMEM(scr);
     NOMEM(P->off[0]); NOMEM(P->off[1]); NOMEM(P->off[2]); NOMEM(P->off[3]);
+    int32_t *vslot = P->own<int32_t>((size_t)nb * kVSlots);
+    NOMEM(vslot);
+    fill_i32(vslot, (int64_t)nb * kVSlots, -1, s);
     colleagues(ta, coll, s);
-    vlist(ta, coll, 0, cntV, nullptr, nullptr, s);
+    vlist(ta, coll, 0, cntV, nullptr, nullptr, nullptr, s);
     uwlist(ta, coll, 0, cntU, nullptr, nullptr, cntW, nullptr, nullptr, s);
     scan_exclusive(cntU, P->off[0], nb, scr, s);
     scan_exclusive(cntV, P->off[1], nb, scr, s);
@@ -283,10 +286,9 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     if (badh) return fail(FMM_EINVAL, "non-finite coordinates");
     P->nlist[0] = tot[0]; P->nlist[1] = tot[1]; P->nlist[2] = tot[2]; P->nlist[3] = tot[2];
     for (int w = 0; w < 4; ++w) { P->src[w] = P->own<int32_t>(P->nlist[w] ? P->nlist[w] : 1); NOMEM(P->src[w]); }
-    vlist(ta, coll, 1, nullptr, P->off[1], P->src[1], s);
+    vlist(ta, coll, 1, nullptr, P->off[1], P->src[1], vslot, s); // ascending by construction
     uwlist(ta, coll, 1, nullptr, P->off[0], P->src[0], nullptr, P->off[2], P->src[2], s);
     sort_segments(P->off[0], nb, P->src[0], s);
-    sort_segments(P->off[1], nb, P->src[1], s);
     sort_segments(P->off[2], nb, P->src[2], s);
     // X = transpose of W
     HIPCHK(hipMemsetAsync(cntX, 0, sizeof(int64_t) * nb, s));
@@ -345,11 +347,13 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     // M2L target slots
     int64_t slot_cap = ((int64_t)nt + 8 * (kM2LSlots - 1) + kM2LSlots - 1) / kM2LSlots * kM2LSlots;
     if (slot_cap < kM2LSlots) slot_cap = kM2LSlots;
-    int32_t *slots = P->own<int32_t>(slot_cap), *pos_of = P->temp<int32_t>(nb);
-    int32_t *vslot = P->own<int32_t>(slot_cap * kVSlots);
-    int *octcnt = P->temp<int>(16), *octoff = P->temp<int>(16);
-    NOMEM(slots); NOMEM(pos_of); NOMEM(vslot); NOMEM(octcnt); NOMEM(octoff);
-    m2l_tiles(ta, mtg, nt, octcnt, octoff, slots, pos_of, P->off[1], P->src[1], vslot, slot_cap, s);
+    int32_t *slots = P->own<int32_t>(slot_cap);
+    int *octoff = P->temp<int>(32);
+    uint64_t *okey = P->temp<uint64_t>(nt + 1), *otk = P->temp<uint64_t>(nt + 1);
+    int32_t *oval = P->temp<int32_t>(nt + 1), *otv = P->temp<int32_t>(nt + 1);
+    int32_t *oscr = P->temp<int32_t>(sort_scratch_bytes(nt + 1) / 4 + 1);
+    NOMEM(slots); NOMEM(octoff); NOMEM(okey); NOMEM(otk); NOMEM(oval); NOMEM(otv); NOMEM(oscr);
+    m2l_tiles(P->bx, mtg, nt, okey, oval, otk, otv, oscr, octoff, slots, slot_cap, s);
     P->nslots = (int)slot_cap;
     // evaluation buffers
     double *qs = P->own<double>(n), *pf = P->own<double>(n), *ff = P->own<double>(3ull * n);
@@ -414,6 +418,18 @@ extern "C" int fmm_plan(const double *xyz_dev, int64_t n, int32_t order, int32_t
     int rc = check_options(o, order, leaf_size);
     if (rc) return rc;
     if (alloc && (!alloc->alloc || !alloc->free)) return fail(FMM_EINVAL, "allocator without functions");
+    static thread_local int pool_dev = -1;
+    {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess && dev != pool_dev) {
+            hipMemPool_t pool;
+            if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+                uint64_t thr = UINT64_MAX; // keep freed memory for reuse by later plans
+                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+            }
+            pool_dev = dev;
+        }
+    }
     std::string err;
     const OrderTables *host_tab = nullptr;
     const OrderTables *tab = get_order_tables(order, &host_tab, err);
@@ -549,8 +565,8 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     T.begin(2);
     for (auto &r : runs)
         for (int l = maxdepth - 1; l >= 0; --l)
-            launch_m2m(P[r.first]->ldm, V + r.first,
-                       sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l); }), l, s);
+            launch_m2m(V + r.first,
+                       sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldm / 16); }), l, s);
     T.end();
     T.begin(3);
     launch_fold(V, make([](const fmm_plan_s *p) { return stage_blocks(p).fold; }, all), s);
@@ -571,8 +587,8 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     T.begin(7);
     for (auto &r : runs)
         for (int l = 2; l < maxdepth; ++l)
-            launch_l2l(P[r.first]->ldm, V + r.first,
-                       sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l); }), l, s);
+            launch_l2l(V + r.first,
+                       sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldm / 16); }), l, s);
     T.end();
     T.begin(8);
     for (auto &r : runs)

@@ -121,8 +121,8 @@ struct PlanView {
     const int32_t *leaf_of;             // sorted position -> leaf box
     const int64_t *U_off, *V_off, *W_off, *X_off;
     const int32_t *U_src, *W_src, *X_src;
-    const int32_t *m2l_tgt;             // M2L targets, octant-grouped, padded to 16
-    const int32_t *vslot;               // [m2l targets][189] source box or -1
+    const int32_t *m2l_tgt;             // M2L targets, octant-grouped, groups padded to 64
+    const int32_t *vslot;               // [boxes][189] M2L source per offset slot, or -1
     const int32_t *leaves;              // leaf boxes
     const int32_t *xtgt;                // boxes with a non-empty X list
     const int32_t *lvl_nonleaf;         // non-leaf boxes grouped by level

@@ -9,9 +9,11 @@
 //
 // Work decomposition.  A block holds 64 targets (4 wavefronts x 16) of one
 // octant, so they share the same 189 source offsets (Sec. 3.4: at most 189
-// boxes per interaction list).  For every offset slot the block stages the
-// offset's derivative table and the 16 source vectors of each wavefront in
-// LDS, then each wavefront runs a (p+1)^2 x (p+1)^2 by 16 product with
+// boxes per interaction list); slots that no target of the block uses are
+// skipped.  For every offset slot the block stages the offset's derivative
+// table and the 16 source vectors of each wavefront in LDS (loaded into
+// registers while the previous slot is being multiplied), then each wavefront
+// runs a (p+1)^2 x (p+1)^2 by 16 product with
 // 16x16x4 MFMAs: A[b][a] = D(addr(b) + addr(a)) is gathered from LDS with the
 // additive address addr(i,j,k) = k (2p+1)^2 + i (2p+1) + j, which turns the
 // Hankel structure of the matrix into a single add per operand; B holds the
@@ -60,11 +62,15 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     constexpr int D3 = 2 * P + 1;
     constexpr int LDD = (3 * D3 * D3 + 1) & ~1;
     constexpr int BST = NK + 1;
+    constexpr int DR = (LDD + 255) / 256; // derivative-table words per thread
+    constexpr int BR = (16 * NK) / 64;    // source-tile words per lane (16 rows of NK)
     typedef typename Mfma<T>::acc_t acc_t;
     __shared__ T sD[LDD];
     __shared__ T sB[4][16][BST];
     __shared__ int sHo[NK];
-    __shared__ int soct;
+    __shared__ int sTg[64];
+    __shared__ int sList[kVSlots];
+    __shared__ int sN, soct;
 
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
@@ -74,6 +80,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     const int tgt = v.m2l_tgt[slot];
     if (!__syncthreads_or(tgt >= 0)) return;
     if (tgt >= 0) soct = (int)(v.morton[tgt] & 7); // every target of the block has this octant
+    if (tid < 64) sTg[tid] = v.m2l_tgt[tile * kM2LSlots + tid];
     const OrderTables &tb = *v.tab;
     for (int a = tid; a < NK; a += 256) sHo[a] = a < NH ? tb.hoff[a] : 0;
     int hb[MT];
@@ -82,28 +89,66 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         int b = mt * 16 + col;
         hb[mt] = b < NH ? tb.hoff[b] : 0;
     }
+    __syncthreads();
+    // slots used by at least one target of the block, in increasing order
+    const int32_t *vs = v.vslot;
+    if (tid < kVSlots) {
+        bool any = false;
+        for (int t = 0; t < 64 && !any; ++t) {
+            int g = sTg[t];
+            any = g >= 0 && vs[(int64_t)g * kVSlots + tid] >= 0;
+        }
+        sList[tid] = any ? 1 : 0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int n = 0;
+        for (int j = 0; j < kVSlots; ++j)
+            if (sList[j]) sList[n++] = j;
+        sN = n;
+    }
+    __syncthreads();
+    const int nvalid = sN, oct = soct, ldh = v.ldh;
+    const T *Dt = Mfma<T>::D(tb);
+    const T *Mh = Mfma<T>::M(v);
+    const int32_t *vsl = vs + (int64_t)(tgt >= 0 ? tgt : 0) * kVSlots;
+
     acc_t acc[MT];
     double4_t acc64[MT]; // FP32 path: per-offset partials are summed in FP64
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) { acc[mt] = acc_t{0, 0, 0, 0}; acc64[mt] = double4_t{0, 0, 0, 0}; }
-    __syncthreads();
-    const int oct = soct;
-    const T *Dt = Mfma<T>::D(tb);
-    const T *Mh = Mfma<T>::M(v);
-    const int ldh = v.ldh;
-    const int32_t *vsl = v.vslot + (int64_t)slot * kVSlots;
-    for (int j = 0; j < kVSlots; ++j) {
-        const int src = tgt >= 0 ? vsl[j] : -1;
-        if (!__syncthreads_or(src >= 0)) continue;
+
+    T pD[DR], pB[BR];
+    auto prefetch = [&](int j) {
         const T *Dk = Dt + (int64_t)tb.offs[oct * kVSlots + j] * LDD;
-        for (int e = tid; e < LDD; e += 256) sD[e] = Dk[e];
-#pragma unroll 4
-        for (int t = 0; t < 16; ++t) {
-            const int sb = __shfl(src, t);
-            for (int e = lane; e < NK; e += 64)
-                sB[wave][t][e] = sb >= 0 ? Mh[(int64_t)sb * ldh + e] : (T)0;
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            int e = tid + 256 * r;
+            pD[r] = e < LDD ? Dk[e] : (T)0;
+        }
+        const int src = tgt >= 0 ? vsl[j] : -1;
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            const int f = lane + 64 * r, t = f / NK, e = f - t * NK;
+            const int st = __shfl(src, t);
+            pB[r] = st >= 0 ? Mh[(int64_t)st * ldh + e] : (T)0;
+        }
+    };
+    if (nvalid > 0) prefetch(sList[0]);
+    for (int q = 0; q < nvalid; ++q) {
+        __syncthreads(); // the previous slot's products are done with sD / sB
+#pragma unroll
+        for (int r = 0; r < DR; ++r) {
+            int e = tid + 256 * r;
+            if (e < LDD) sD[e] = pD[r];
+        }
+#pragma unroll
+        for (int r = 0; r < BR; ++r) {
+            const int f = lane + 64 * r, t = f / NK, e = f - t * NK;
+            sB[wave][t][e] = pB[r];
         }
         __syncthreads();
+        if (q + 1 < nvalid) prefetch(sList[q + 1]); // in flight during the products
 #pragma unroll 2
         for (int ks = 0; ks < KS; ++ks) {
             const int a = ks * 4 + kq;
@@ -120,7 +165,6 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
                 acc[mt] = acc_t{0, 0, 0, 0};
             }
         }
-        __syncthreads();
     }
     if (tgt < 0) return;
     double *Lh = v.Lh + (int64_t)tgt * ldh;

@@ -7,8 +7,8 @@ namespace fmm {
 void launch_permute_q(const PlanView *V, const Bases &B, hipStream_t s);   // 256 particles/block
 void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block
 void launch_fold(const PlanView *V, const Bases &B, hipStream_t s);        // 4 boxes/block
-void launch_m2m(int ldm, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents/block
-void launch_l2l(int ldm, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents/block
+void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block
+void launch_l2l(const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block
 void launch_unfold(const PlanView *V, const Bases &B, hipStream_t s);      // 4 boxes/block
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 X target/block
 void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block

@@ -122,7 +122,14 @@ __global__ __launch_bounds__(256) void k_fold(const PlanView *V, Bases B)
     }
 }
 
-// ---------------- M2M / L2L: 16 parents per block ----------------
+// ---------------- M2M / L2L on the matrix cores ----------------
+// One wavefront computes a 16 x 16 tile: 16 output coefficients (rows) of 16
+// parents (columns) of one level, as sum over octants of T_o^t * X_o with the
+// 16x16x4 FP64 MFMA.  M2M: X_o holds the octant-o children's Mhat and the
+// tile is written to the parents.  L2L: X holds the parents' Lhat, and the
+// product of octant o is added to the octant-o children.  S is zero unless
+// |a| <= |b| and G unless g >= b, so only the contributing degree range of
+// the inner index is visited.
 constexpr int kPG = 16;
 
 // child of parent b in octant o, or -1
@@ -134,84 +141,61 @@ __device__ inline int child_in_octant(const PlanView &v, int b, int o)
     return -1;
 }
 
-// up: 1 = M2M (children -> parent), 0 = L2L (parent -> children)
-template <int UP>
-__global__ __launch_bounds__(256) void k_translate(const PlanView *V, Bases B, int level)
+__device__ inline int degree_of(int idx)
 {
-    extern __shared__ double sh[]; // [kPG][ldm]
-    __shared__ int sbox[kPG], schild[kPG];
-    __shared__ int sany;
-    int k = find_plan(B, blockIdx.x);
+    int d = 0;
+    while (below(d + 1) <= idx) ++d;
+    return d;
+}
+
+template <int UP>
+__global__ __launch_bounds__(64) void k_translate(const PlanView *V, Bases B, int level)
+{
+    typedef double double4_t __attribute__((ext_vector_type(4)));
+    const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
-    const int g = blockIdx.x - B.b[k];
+    const int item = blockIdx.x - B.b[k];
+    const int MT = v.ldm / 16, g = item / MT, mt = item - g * MT;
+    const int lane = threadIdx.x, col = lane & 15, kq = lane >> 4;
     const int lb = v.lvl_nonleaf_off[level], le = v.lvl_nonleaf_off[level + 1];
-    const int nc = v.nc, ldm = v.ldm, tid = threadIdx.x;
-    if (tid < kPG) {
-        int idx = lb + g * kPG + tid;
-        sbox[tid] = idx < le ? v.lvl_nonleaf[idx] : -1;
-    }
-    __syncthreads();
+    const int pidx = lb + g * kPG + col;
+    const int parent = pidx < le ? v.lvl_nonleaf[pidx] : -1;
+    const int nc = v.nc, ldm = v.ldm;
+    const int bA = mt * 16 + col; // row of the A operand held by this lane
     const double *Mat = UP ? v.tab->S : v.tab->G;
-    double acc[kPG][2];
-    if (!UP) { // parent local expansions, loaded once
-        for (int e = tid; e < kPG * ldm; e += 256) {
-            int q = e / ldm, a = e - q * ldm;
-            sh[e] = sbox[q] >= 0 ? v.L[(int64_t)sbox[q] * ldm + a] : 0.0;
-        }
-    }
-#pragma unroll
-    for (int q = 0; q < kPG; ++q) acc[q][0] = acc[q][1] = 0.0;
+    const int dlo = degree_of(mt * 16 < nc ? mt * 16 : nc - 1);
+    const int dhi = degree_of(mt * 16 + 15 < nc ? mt * 16 + 15 : nc - 1);
+    // inner index range [k0, k1) that can contribute to this row tile
+    const int k0 = UP ? 0 : (below(dlo) & ~3);
+    const int k1 = UP ? below(dhi + 1) : nc;
+    double4_t acc = {0, 0, 0, 0};
     for (int o = 0; o < 8; ++o) {
-        __syncthreads(); // the previous octant is done with sh, schild and sany
-        if (tid == 0) sany = 0;
-        __syncthreads();
-        if (tid < kPG) {
-            int c = sbox[tid] >= 0 ? child_in_octant(v, sbox[tid], o) : -1;
-            schild[tid] = c;
-            if (c >= 0) atomicOr(&sany, 1);
-        }
-        __syncthreads();
-        if (!sany) continue;
-        if (UP) {
-            for (int e = tid; e < kPG * ldm; e += 256) {
-                int q = e / ldm, a = e - q * ldm;
-                sh[e] = schild[q] >= 0 ? v.M[(int64_t)schild[q] * ldm + a] : 0.0;
-            }
-            __syncthreads();
-        } else {
-#pragma unroll
-            for (int q = 0; q < kPG; ++q) acc[q][0] = acc[q][1] = 0.0;
-        }
+        const int ch = parent >= 0 ? child_in_octant(v, parent, o) : -1;
+        if (!__any(ch >= 0)) continue;
         const double *T = Mat + (int64_t)o * nc * nc;
-        for (int a = 0; a < nc; ++a) {
-            double s0 = tid < nc ? T[(int64_t)a * nc + tid] : 0.0;
-            double s1 = tid + 256 < nc ? T[(int64_t)a * nc + tid + 256] : 0.0;
-#pragma unroll
-            for (int q = 0; q < kPG; ++q) {
-                double m = sh[q * ldm + a];
-                acc[q][0] += s0 * m;
-                acc[q][1] += s1 * m;
-            }
+        const double *X = UP ? (ch >= 0 ? v.M + (int64_t)ch * ldm : nullptr)
+                             : (parent >= 0 ? v.L + (int64_t)parent * ldm : nullptr);
+        if (!UP) acc = double4_t{0, 0, 0, 0};
+#pragma unroll 8
+        for (int kk = k0; kk < k1; kk += 4) {
+            const int a = kk + kq;
+            const double av = (bA < nc && a < nc) ? T[(int64_t)a * nc + bA] : 0.0;
+            const double bv = (X && a < nc) ? X[a] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
         }
-        if (!UP) { // add into each existing child of this octant
+        if (!UP && ch >= 0) {
 #pragma unroll
-            for (int q = 0; q < kPG; ++q) {
-                int c = schild[q];
-                if (c < 0) continue;
-                if (tid < nc) v.L[(int64_t)c * ldm + tid] += acc[q][0];
-                if (tid + 256 < nc) v.L[(int64_t)c * ldm + tid + 256] += acc[q][1];
+            for (int r = 0; r < 4; ++r) {
+                const int b = mt * 16 + 4 * r + kq; // f64 layout: lane l reg r -> row 4r + l/16
+                if (b < nc) v.L[(int64_t)ch * ldm + b] += acc[r];
             }
         }
     }
-    if (UP) {
+    if (UP && parent >= 0) {
 #pragma unroll
-        for (int q = 0; q < kPG; ++q) {
-            int b = sbox[q];
-            if (b < 0) continue;
-            for (int r = 0; r < 2; ++r) {
-                int a = tid + 256 * r;
-                if (a < ldm) v.M[(int64_t)b * ldm + a] = a < nc ? acc[q][r] : 0.0;
-            }
+        for (int r = 0; r < 4; ++r) {
+            const int b = mt * 16 + 4 * r + kq;
+            v.M[(int64_t)parent * ldm + b] = acc[r]; // rows >= nc are zero
         }
     }
 }
@@ -531,13 +515,13 @@ void launch_fold(const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (nblk(B)) k_fold<<<nblk(B), 256, 0, s>>>(V, B);
 }
-void launch_m2m(int ldm, const PlanView *V, const Bases &B, int level, hipStream_t s)
+void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s)
 {
-    if (nblk(B)) k_translate<1><<<nblk(B), 256, sizeof(double) * kPG * ldm, s>>>(V, B, level);
+    if (nblk(B)) k_translate<1><<<nblk(B), 64, 0, s>>>(V, B, level);
 }
-void launch_l2l(int ldm, const PlanView *V, const Bases &B, int level, hipStream_t s)
+void launch_l2l(const PlanView *V, const Bases &B, int level, hipStream_t s)
 {
-    if (nblk(B)) k_translate<0><<<nblk(B), 256, sizeof(double) * kPG * ldm, s>>>(V, B, level);
+    if (nblk(B)) k_translate<0><<<nblk(B), 64, 0, s>>>(V, B, level);
 }
 void launch_unfold(const PlanView *V, const Bases &B, hipStream_t s)
 {

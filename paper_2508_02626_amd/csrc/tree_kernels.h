@@ -31,7 +31,7 @@ void fill_children(const uint64_t *keys, int D, int l, int lb, int le, const int
                    BoxArrays bx, hipStream_t s);
 void colleagues(const TreeArgs &a, int32_t *coll, hipStream_t s);
 void vlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *cnt, const int64_t *off,
-           int32_t *src, hipStream_t s);
+           int32_t *src, int32_t *vslot, hipStream_t s);
 void uwlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *ucnt, const int64_t *uoff,
             int32_t *usrc, int64_t *wcnt, const int64_t *woff, int32_t *wsrc, hipStream_t s);
 void sort_segments(const int64_t *off, int nseg, int32_t *v, hipStream_t s);
@@ -42,9 +42,9 @@ void flags(const BoxArrays &bx, int nboxes, int what, const int64_t *off, int64_
 void compact(const int64_t *flag, const int64_t *pos, int nboxes, int32_t *out, hipStream_t s);
 void leaf_of(const BoxArrays &bx, const int32_t *leaves, int nleaves, int32_t *lo, hipStream_t s);
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
-void m2l_tiles(const TreeArgs &a, const int32_t *tg, int nt, int *octcnt, int *octoff,
-               int32_t *slots, int32_t *pos_of, const int64_t *voff, const int32_t *vsrc,
-               int32_t *vslot, int64_t slot_cap, hipStream_t s);
+void m2l_tiles(const BoxArrays &bx, const int32_t *tg, int nt, uint64_t *key, int32_t *val,
+               uint64_t *tk, int32_t *tv, int32_t *sort_scratch, int *octoff, int32_t *slots,
+               int64_t slot_cap, hipStream_t s);
 void local_split(const double *xs, const double *ys, const double *zs, const int32_t *leaf_of,
                  const BoxArrays &bx, int n, const double root[4], float *ux, float *uy, float *uz,
                  float *vx, float *vy, float *vz, hipStream_t s);

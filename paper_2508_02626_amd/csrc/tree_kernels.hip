@@ -15,6 +15,7 @@
 //   lists  Carrier-Greengard-Rokhlin U, V, W, X with "adjacent" = closed cubes
 //          touch (integer finest-grid test), each list ascending in box number.
 #include "tree_kernels.h"
+#include "sort.h"
 
 namespace fmm {
 
@@ -271,30 +272,51 @@ __global__ __launch_bounds__(256) void k_colleagues(TreeView t, int32_t *coll)
                 int f = -1;
                 if (nb[0] >= 0 && nb[1] >= 0 && nb[2] >= 0 && nb[0] < side && nb[1] < side && nb[2] < side)
                     f = find_box(t, l, interleave(nb, l));
-                if (f >= 0) coll[27 * b + m++] = f;
+                if (f >= 0) { // insert keeping ascending box numbers
+                    int j = m++;
+                    while (j > 0 && coll[27 * b + j - 1] > f) { coll[27 * b + j] = coll[27 * b + j - 1]; --j; }
+                    coll[27 * b + j] = f;
+                }
             }
     for (; m < 27; ++m) coll[27 * b + m] = -1;
 }
 
-// which: 0 count, 1 fill.  V for boxes of level >= 2.
+// which: 0 count, 1 fill.  V for boxes of level >= 2: children of the
+// parent's colleagues that are not adjacent (same level, so adjacency is
+// max |delta| <= 1 in cell coordinates).  Colleagues are sorted and children
+// are consecutive, so the list comes out ascending.  The fill pass also
+// records each source in the box's M2L slot row (offset slot, Sec. 3.4).
 __global__ __launch_bounds__(256) void k_vlist(TreeView t, const int32_t *coll, int which,
-                                               int64_t *cnt, const int64_t *off, int32_t *src)
+                                               int64_t *cnt, const int64_t *off, int32_t *src,
+                                               int32_t *vslot)
 {
     int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= t.nboxes) return;
     int n = 0;
     int64_t o = which ? off[b] : 0;
-    if (t.bx.level[b] >= 2) {
-        int pb = t.bx.parent[b];
+    const int l = t.bx.level[b];
+    if (l >= 2) {
+        int cb[3], cc[3];
+        deinterleave(t.bx.morton[b], l, cb);
+        const int oct = (int)(t.bx.morton[b] & 7);
+        const int pb = t.bx.parent[b];
         for (int i = 0; i < 27; ++i) {
             int c = coll[27 * pb + i];
             if (c < 0) break;
+            deinterleave(t.bx.morton[c], l - 1, cc);
             for (int k = 0; k < t.bx.nchild[c]; ++k) {
                 int d = t.bx.child_begin[c] + k;
-                if (!adjacent(t, d, b)) {
-                    if (which) src[o + n] = d;
-                    ++n;
+                int od = (int)(t.bx.morton[d] & 7);
+                int dx = 2 * cc[0] + ((od >> 2) & 1) - cb[0];
+                int dy = 2 * cc[1] + ((od >> 1) & 1) - cb[1];
+                int dz = 2 * cc[2] + (od & 1) - cb[2];
+                if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
+                if (which) {
+                    src[o + n] = d;
+                    int sl = vslot_of(oct, -dx, -dy, -dz); // offset = target - source
+                    if (sl >= 0) vslot[(int64_t)b * kVSlots + sl] = d;
                 }
+                ++n;
             }
         }
     }
@@ -384,10 +406,10 @@ void colleagues(const TreeArgs &a, int32_t *coll, hipStream_t s)
 }
 
 void vlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *cnt, const int64_t *off,
-           int32_t *src, hipStream_t s)
+           int32_t *src, int32_t *vslot, hipStream_t s)
 {
     TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes};
-    k_vlist<<<ceil_div(a.nboxes, 256), 256, 0, s>>>(t, coll, which, cnt, off, src);
+    k_vlist<<<ceil_div(a.nboxes, 256), 256, 0, s>>>(t, coll, which, cnt, off, src, vslot);
 }
 
 void uwlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *ucnt, const int64_t *uoff,
@@ -470,60 +492,51 @@ void leaf_of(const BoxArrays &bx, const int32_t *leaves, int nleaves, int32_t *l
 }
 
 // ---------------- M2L target tiles ----------------
-// Targets (boxes with a V list) grouped by octant, each group padded to a
-// multiple of 64 so that the 64 targets of one M2L block share one set of 189
-// offsets.
-__global__ __launch_bounds__(256) void k_oct_count(const BoxArrays bx, const int32_t *tg, int nt,
-                                                   int *octcnt)
+// Targets (boxes with a V list, ascending) are stably sorted by octant, then
+// each octant group is placed at a multiple of 64 so that the 64 targets of
+// one M2L block share one set of 189 offsets.
+__global__ __launch_bounds__(256) void k_oct_keys(const BoxArrays bx, const int32_t *tg, int nt,
+                                                  uint64_t *key, int32_t *val)
 {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= nt) return;
-    atomicAdd(&octcnt[bx.morton[tg[i]] & 7], 1);
+    key[i] = bx.morton[tg[i]] & 7;
+    val[i] = tg[i];
 }
 
-__global__ void k_oct_offsets(int *octcnt, int *octoff)
+// start of every octant in the sorted keys, and the padded output offsets
+__global__ void k_oct_offsets(const uint64_t *key, int nt, int *octoff)
 {
-    if (threadIdx.x != 0) return;
-    int s = 0;
-    for (int o = 0; o < 8; ++o) { octoff[o] = s; s += (octcnt[o] + 63) & ~63; }
-    octoff[8] = s;
-}
-
-// stable placement: targets are scanned in box order by one wavefront per octant
-__global__ __launch_bounds__(64) void k_oct_place(const BoxArrays bx, const int32_t *tg, int nt,
-                                                  const int *octoff, int32_t *slots, int32_t *pos_of)
-{
-    int o = blockIdx.x, lane = threadIdx.x;
-    int base = octoff[o];
-    for (int s = 0; s < nt; s += 64) {
-        int i = s + lane;
-        bool mine = i < nt && (int)(bx.morton[tg[i]] & 7) == o;
-        uint64_t m = __ballot(mine);
-        if (mine) {
-            int p = base + __popcll(m & ((1ull << lane) - 1ull));
-            slots[p] = tg[i];
-            pos_of[tg[i]] = p;
+    __shared__ int st[9];
+    int o = threadIdx.x;
+    if (o <= 8) {
+        int lo = 0, hi = nt;
+        while (lo < hi) {
+            int mid = (lo + hi) >> 1;
+            if (key[mid] < (uint64_t)o) lo = mid + 1; else hi = mid;
         }
-        base += __popcll(m);
+        st[o] = o == 8 ? nt : lo;
+    }
+    __syncthreads();
+    if (o == 0) {
+        int s = 0;
+        for (int k = 0; k < 8; ++k) {
+            octoff[k] = s;              // padded start
+            octoff[9 + k] = st[k];      // unpadded start
+            s += (st[k + 1] - st[k] + 63) & ~63;
+        }
+        octoff[8] = s;
+        octoff[17] = nt;
     }
 }
 
-__global__ __launch_bounds__(256) void k_vslot_fill(TreeView t, const int64_t *voff, const int32_t *vsrc,
-                                                    const int32_t *pos_of, int32_t *vslot)
+__global__ __launch_bounds__(256) void k_oct_place(const uint64_t *key, const int32_t *val, int nt,
+                                                   const int *octoff, int32_t *slots)
 {
-    int b = blockIdx.x * 256 + threadIdx.x;
-    if (b >= t.nboxes) return;
-    if (voff[b + 1] == voff[b]) return;
-    int l = t.bx.level[b], cb[3], cs[3];
-    deinterleave(t.bx.morton[b], l, cb);
-    int oct = (int)(t.bx.morton[b] & 7);
-    int32_t *row = vslot + (int64_t)pos_of[b] * kVSlots;
-    for (int64_t e = voff[b]; e < voff[b + 1]; ++e) {
-        int c = vsrc[e];
-        deinterleave(t.bx.morton[c], l, cs);
-        int sl = vslot_of(oct, cb[0] - cs[0], cb[1] - cs[1], cb[2] - cs[2]);
-        if (sl >= 0) row[sl] = c;
-    }
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= nt) return;
+    int o = (int)key[i];
+    slots[octoff[o] + (i - octoff[9 + o])] = val[i];
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
@@ -537,18 +550,16 @@ void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
     if (n > 0) k_fill_i32<<<ceil_div(n, 256), 256, 0, s>>>(p, n, v);
 }
 
-void m2l_tiles(const TreeArgs &a, const int32_t *tg, int nt, int *octcnt, int *octoff,
-               int32_t *slots, int32_t *pos_of, const int64_t *voff, const int32_t *vsrc,
-               int32_t *vslot, int64_t slot_cap, hipStream_t s)
+void m2l_tiles(const BoxArrays &bx, const int32_t *tg, int nt, uint64_t *key, int32_t *val,
+               uint64_t *tk, int32_t *tv, int32_t *sort_scratch, int *octoff, int32_t *slots,
+               int64_t slot_cap, hipStream_t s)
 {
-    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes};
-    fill_i32(octcnt, 9, 0, s);
     fill_i32(slots, slot_cap, -1, s);
-    fill_i32(vslot, slot_cap * kVSlots, -1, s);
-    if (nt > 0) k_oct_count<<<ceil_div(nt, 256), 256, 0, s>>>(a.bx, tg, nt, octcnt);
-    k_oct_offsets<<<1, 64, 0, s>>>(octcnt, octoff);
-    if (nt > 0) k_oct_place<<<8, 64, 0, s>>>(a.bx, tg, nt, octoff, slots, pos_of);
-    k_vslot_fill<<<ceil_div(a.nboxes, 256), 256, 0, s>>>(t, voff, vsrc, pos_of, vslot);
+    if (nt == 0) return;
+    k_oct_keys<<<ceil_div(nt, 256), 256, 0, s>>>(bx, tg, nt, key, val);
+    radix_sort_pairs(key, val, tk, tv, nt, 3, sort_scratch, s);
+    k_oct_offsets<<<1, 64, 0, s>>>(key, nt, octoff);
+    k_oct_place<<<ceil_div(nt, 256), 256, 0, s>>>(key, val, nt, octoff, slots);
 }
 
 // ---------------- mixed precision particle data ----------------
