@@ -42,6 +42,11 @@ __host__ __device__ inline int harm_index(int i, int j, int kz)
     return n * n + (kz == 0 ? (n - i) : (n + 1) + (n - 1 - i));
 }
 inline int pad16(int n) { return (n + 15) & ~15; }
+// Additive layout of one offset's derivative table: addr(i,j,k) = k*s2 + i*s1 + j
+// for x, y exponents up to 2p and z exponent up to 2.
+__host__ __device__ constexpr int dlayout_s1(int p) { return 2 * p + 2; }
+__host__ __device__ constexpr int dlayout_s2(int p) { return (2 * p + 1) * (2 * p + 2); }
+__host__ __device__ constexpr int dlayout_ldd(int p) { return (3 * dlayout_s2(p) + 1) & ~1; }
 inline int pad4(int n) { return (n + 3) & ~3; }
 
 // Morton codes: bit b of the x, y, z cell index sits at code bits 3b+2, 3b+1, 3b.
@@ -89,7 +94,7 @@ __host__ __device__ inline int vslot_of(int oct, int kx, int ky, int kz)
 // Per-order constant tables (device pointers), built once per order and device.
 struct OrderTables {
     int p, nc, nh, ldm, ldh, ldd;   // ldd: stride of one offset's derivative table
-    int d3;                         // 2p+1 (stride of the additive D layout)
+    int d3;                         // x stride of the additive D layout
     const double *D;    // [343][ldd] derivative tensors d^g(1/|x|) at integer x, additive layout
     const float *Df;    // same in FP32
     const int *offs;    // [8][189] packed offsets (kx+3)*49 + (ky+3)*7 + (kz+3)

@@ -15,8 +15,9 @@
 // registers while the previous slot is being multiplied), then each wavefront
 // runs a (p+1)^2 x (p+1)^2 by 16 product with
 // 16x16x4 MFMAs: A[b][a] = D(addr(b) + addr(a)) is gathered from LDS with the
-// additive address addr(i,j,k) = k (2p+1)^2 + i (2p+1) + j, which turns the
-// Hankel structure of the matrix into a single add per operand; B holds the
+// additive address addr(i,j,k) = k s2 + i (2p+2) + j, which turns the
+// Hankel structure of the matrix into a single add per operand (the x stride
+// 2p+2 keeps the 16 rows of one operand load in different LDS banks); B holds the
 // gathered sources.  Accumulators stay in registers across all 189 slots, so
 // every target is written once; the FP32 variant adds each slot's FP32 partial
 // into FP64 accumulators, so only the per-slot products carry FP32 rounding.  Operand layouts (verified on gfx950):
@@ -59,8 +60,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     constexpr int MT = LDH / 16;
     constexpr int NK = (NH + 3) & ~3;
     constexpr int KS = NK / 4;
-    constexpr int D3 = 2 * P + 1;
-    constexpr int LDD = (3 * D3 * D3 + 1) & ~1;
+    constexpr int LDD = dlayout_ldd(P);
     constexpr int BST = NK + 1;
     constexpr int DR = (LDD + 255) / 256; // derivative-table words per thread
     constexpr int BR = (16 * NK) / 64;    // source-tile words per lane (16 rows of NK)
@@ -149,13 +149,28 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         }
         __syncthreads();
         if (q + 1 < nvalid) prefetch(sList[q + 1]); // in flight during the products
-#pragma unroll 2
-        for (int ks = 0; ks < KS; ++ks) {
-            const int a = ks * 4 + kq;
-            const T bv = sB[wave][col][a];
-            const int ha = sHo[a];
+        // operands of step ks+1 are read from LDS while the MFMAs of step ks run
+        T ac[MT], an[MT], bc, bn = (T)0;
+        {
+            const int ha = sHo[kq];
+            bc = sB[wave][col][kq];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt] = Mfma<T>::run(sD[hb[mt] + ha], bv, acc[mt]);
+            for (int mt = 0; mt < MT; ++mt) ac[mt] = sD[hb[mt] + ha];
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            if (ks + 1 < KS) {
+                const int a = (ks + 1) * 4 + kq;
+                const int ha = sHo[a];
+                bn = sB[wave][col][a];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) an[mt] = sD[hb[mt] + ha];
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) acc[mt] = Mfma<T>::run(ac[mt], bc, acc[mt]);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) ac[mt] = an[mt];
+            bc = bn;
         }
         if constexpr (sizeof(T) == 4) {
 #pragma unroll

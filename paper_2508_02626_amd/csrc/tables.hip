@@ -169,7 +169,11 @@ struct Built {
 void build_tables(int p, Built &B)
 {
     Mono m(p);
-    const int nc = m.n, nh = nharm(p), ldh = pad16(nh), d3 = 2 * p + 1;
+    const int nc = m.n, nh = nharm(p), ldh = pad16(nh);
+    // additive layout addr(i,j,k) = k*s2 + i*s1 + j of the derivative tables;
+    // s1 = 2p+2 makes consecutive harmonic indices (x down, y up) step by the
+    // odd amount 2p+1, so 16 MFMA rows read 16 different LDS banks
+    const int s1 = dlayout_s1(p), s2 = dlayout_s2(p);
     // exponent packing, factorial tables
     B.exps.resize(nc);
     B.inv_fact.resize(nc);
@@ -188,10 +192,10 @@ void build_tables(int p, Built &B)
         for (int i = n - 1; i >= 0; --i) { int c = harm_index(i, n - 1 - i, 1); hx[c] = i; hy[c] = n - 1 - i; hz[c] = 1; }
     }
     B.hoff.assign(ldh, 0);
-    for (int c = 0; c < nh; ++c) B.hoff[c] = hz[c] * d3 * d3 + hx[c] * d3 + hy[c];
+    for (int c = 0; c < nh; ++c) B.hoff[c] = hz[c] * s2 + hx[c] * s1 + hy[c];
 
     // derivative tensors at the 343 integer offsets (near ones left zero)
-    B.ldd = (3 * d3 * d3 + 1) & ~1;
+    B.ldd = dlayout_ldd(p);
     B.D.assign((size_t)343 * B.ldd, 0.0);
     B.Df.assign((size_t)343 * B.ldd, 0.0f);
     std::vector<ld> a;
@@ -206,8 +210,8 @@ void build_tables(int p, Built &B)
                     for (int i = 0; i + z <= 2 * p; ++i)
                         for (int j = 0; i + j + z <= 2 * p; ++j) {
                             ld v = a[mono_index(i, j, z)] * fact(i) * fact(j) * fact(z);
-                            B.D[base + z * d3 * d3 + i * d3 + j] = (double)v;
-                            B.Df[base + z * d3 * d3 + i * d3 + j] = (float)v;
+                            B.D[base + z * s2 + i * s1 + j] = (double)v;
+                            B.Df[base + z * s2 + i * s1 + j] = (float)v;
                         }
             }
     // V-list slot -> offset
@@ -339,7 +343,7 @@ const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::s
     Entry e;
     OrderTables &t = e.host;
     t.p = p; t.nc = ncoef(p); t.nh = nharm(p); t.ldm = pad16(t.nc); t.ldh = pad16(t.nh);
-    t.ldd = B.ldd; t.d3 = 2 * p + 1;
+    t.ldd = B.ldd; t.d3 = dlayout_s1(p);
     if (upload(B.D, &t.D, err) || upload(B.Df, &t.Df, err) || upload(B.offs, &t.offs, err) ||
         upload(B.hoff, &t.hoff, err) || upload(B.S, &t.S, err) || upload(B.G, &t.G, err) ||
         upload(B.P2M, &t.P2M, err) || upload(B.fold_off, &t.fold_off, err) ||
