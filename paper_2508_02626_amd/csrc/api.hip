@@ -559,12 +559,18 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     for (auto &r : runs)
         launch_p2m(P[r.first]->p, V + r.first,
                    sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).p2m; }), s);
+    for (auto &r : runs)
+        launch_p2m_transform(V + r.first, sub(r.first, r.second, [](const fmm_plan_s *p) {
+            return (int)ceil_div(p->nleaves, 16) * (p->ldm / 16); }), s);
     T.end();
     int maxdepth = 0;
     for (int i = 0; i < count; ++i) maxdepth = std::max(maxdepth, P[i]->depth);
     T.begin(2);
+    // Multipoles of levels 0 and 1 are never read by M2L (V lists start at
+    // level 2) nor by M2P (W lists hold boxes of level >= 2), so the upward
+    // pass stops at level 2; fmm_plan_export_expansions completes it on demand.
     for (auto &r : runs)
-        for (int l = maxdepth - 1; l >= 0; --l)
+        for (int l = maxdepth - 1; l >= 2; --l)
             launch_m2m(V + r.first,
                        sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldm / 16); }), l, s);
     T.end();
@@ -776,6 +782,15 @@ extern "C" int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, d
     }
     std::vector<double> buf((size_t)nb * ldm);
     if (M_host) {
+        // finish the upward pass into levels 1 and 0 (not needed by the evaluation)
+        Bases B{};
+        B.n = 1;
+        B.b[0] = 0;
+        for (int l = std::min(1, P->depth - 1); l >= 0; --l) {
+            B.b[1] = nonleaf_groups(P, l) * (P->ldm / 16);
+            launch_m2m(P->view_dev, B, l, stream);
+        }
+        HIPCHK(hipStreamSynchronize(stream));
         HIPCHK(hipMemcpy(buf.data(), P->view.M, 8ull * nb * ldm, hipMemcpyDeviceToHost));
         for (int b = 0; b < nb; ++b) {
             double h = P->root[3] / std::ldexp(1.0, lev[b]);

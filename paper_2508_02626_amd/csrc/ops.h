@@ -6,6 +6,7 @@
 namespace fmm {
 void launch_permute_q(const PlanView *V, const Bases &B, hipStream_t s);   // 256 particles/block
 void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block
+void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 leaves x 16 rows/block
 void launch_fold(const PlanView *V, const Bases &B, hipStream_t s);        // 4 boxes/block
 void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block
 void launch_l2l(const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block

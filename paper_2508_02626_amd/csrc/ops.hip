@@ -4,7 +4,8 @@
 // Scaled units (h = box width): Mhat_a = w_|a| M_a / h^|a|, Lhat_b = b! L_b h^(|b|+1).
 //   P2M  (Sec. 2.1) Mhat_a = sum_g P[g][a] Q_g with raw moments Q_g = sum q u^g,
 //        u = (x - c)/h; one wavefront per leaf, one lane per moment, so the
-//        per-box reduction is an in-lane sequential sum (deterministic).
+//        per-box reduction is an in-lane sequential sum (deterministic); the
+//        fixed matrix P is then applied to 16 leaves at a time on MFMA.
 //   M2M  (Sec. 2.2) parent Mhat = sum over children of S_octant * child Mhat.
 //   L2L  (Sec. 2.5) child Lhat += G_octant * parent Lhat.
 //   L2P / M2P (Sec. 3.2) share one evaluation routine (nested Horner with the
@@ -32,6 +33,13 @@ __device__ inline void box_geom(const PlanView &v, int b, double cen[3], double 
     for (int k = 0; k < 3; ++k) cen[k] = v.lo[k] + ((double)c[k] + 0.5) * h;
 }
 
+__device__ inline int degree_of(int idx)
+{
+    int d = 0;
+    while (below(d + 1) <= idx) ++d;
+    return d;
+}
+
 // ---------------- charges in sorted order ----------------
 __global__ __launch_bounds__(256) void k_permute_q(const PlanView *V, Bases B)
 {
@@ -48,7 +56,6 @@ __global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
     constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
     constexpr int R = (NC + 63) / 64;
     __shared__ double pw[3][P + 1][65];
-    __shared__ double Q[NC];
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int box = v.leaves[blockIdx.x - B.b[k]];
@@ -88,20 +95,47 @@ __global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
             for (int r = 0; r < R; ++r) acc[r] += pw[0][ex[r]][t] * pw[1][ey[r]][t] * pw[2][ez[r]][t];
         __syncthreads();
     }
+    // raw moments go to the (not yet used) local-expansion row of the leaf;
+    // k_p2m_transform turns them into Mhat
+    double *Qg = v.L + (int64_t)box * v.ldm;
 #pragma unroll
     for (int r = 0; r < R; ++r)
-        if (lane + 64 * r < NC) Q[lane + 64 * r] = acc[r];
-    __syncthreads();
-    double *M = v.M + (int64_t)box * v.ldm;
+        if (lane + 64 * r < NC) Qg[lane + 64 * r] = acc[r];
+}
+
+// Mhat = P2M^t Q for 16 leaves x 16 coefficients per wavefront (FP64 MFMA);
+// the matrix is block diagonal by degree, so only the tile's degree range of
+// moments is visited.
+__global__ __launch_bounds__(64) void k_p2m_transform(const PlanView *V, Bases B)
+{
+    typedef double double4_t __attribute__((ext_vector_type(4)));
+    const int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int item = blockIdx.x - B.b[k];
+    const int MT = v.ldm / 16, g = item / MT, mt = item - g * MT;
+    const int lane = threadIdx.x, col = lane & 15, kq = lane >> 4;
+    const int li = g * 16 + col;
+    const int leaf = li < v.nleaves ? v.leaves[li] : -1;
+    const int nc = v.nc, ldm = v.ldm;
+    const int bA = mt * 16 + col;
     const double *T = v.tab->P2M;
-    for (int a = lane; a < v.ldm; a += 64) {
-        double s = 0.0;
-        if (a < NC) {
-            int e = v.tab->exps[a];
-            int d = (e & 255) + ((e >> 8) & 255) + ((e >> 16) & 255);
-            for (int g = below(d); g < below(d + 1); ++g) s += T[(int64_t)g * NC + a] * Q[g];
-        }
-        M[a] = s;
+    const int dlo = degree_of(mt * 16 < nc ? mt * 16 : nc - 1);
+    const int dhi = degree_of(mt * 16 + 15 < nc ? mt * 16 + 15 : nc - 1);
+    const int k0 = below(dlo) & ~3, k1 = below(dhi + 1);
+    const double *Q = leaf >= 0 ? v.L + (int64_t)leaf * ldm : nullptr;
+    double4_t acc = {0, 0, 0, 0};
+#pragma unroll 4
+    for (int kk = k0; kk < k1; kk += 4) {
+        const int a = kk + kq;
+        const double av = (bA < nc && a < nc) ? T[(int64_t)a * nc + bA] : 0.0;
+        const double bv = (Q && a < nc) ? Q[a] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    if (leaf < 0) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int b = mt * 16 + 4 * r + kq;
+        v.M[(int64_t)leaf * ldm + b] = b < nc ? acc[r] : 0.0;
     }
 }
 
@@ -132,22 +166,6 @@ __global__ __launch_bounds__(256) void k_fold(const PlanView *V, Bases B)
 // the inner index is visited.
 constexpr int kPG = 16;
 
-// child of parent b in octant o, or -1
-__device__ inline int child_in_octant(const PlanView &v, int b, int o)
-{
-    int cb = v.child_begin[b], nc = v.nchild[b];
-    for (int i = 0; i < nc; ++i)
-        if ((int)(v.morton[cb + i] & 7) == o) return cb + i;
-    return -1;
-}
-
-__device__ inline int degree_of(int idx)
-{
-    int d = 0;
-    while (below(d + 1) <= idx) ++d;
-    return d;
-}
-
 template <int UP>
 __global__ __launch_bounds__(64) void k_translate(const PlanView *V, Bases B, int level)
 {
@@ -168,9 +186,23 @@ __global__ __launch_bounds__(64) void k_translate(const PlanView *V, Bases B, in
     // inner index range [k0, k1) that can contribute to this row tile
     const int k0 = UP ? 0 : (below(dlo) & ~3);
     const int k1 = UP ? below(dhi + 1) : nc;
+    // children of this lane's parent by octant (-1 if absent)
+    int chs[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) chs[o] = -1;
+    if (parent >= 0) {
+        const int cb = v.child_begin[parent], ncd = v.nchild[parent];
+        for (int i = 0; i < ncd; ++i) {
+            const int c = cb + i, oc = (int)(v.morton[c] & 7);
+#pragma unroll
+            for (int o = 0; o < 8; ++o)
+                if (o == oc) chs[o] = c;
+        }
+    }
     double4_t acc = {0, 0, 0, 0};
+#pragma unroll
     for (int o = 0; o < 8; ++o) {
-        const int ch = parent >= 0 ? child_in_octant(v, parent, o) : -1;
+        const int ch = chs[o];
         if (!__any(ch >= 0)) continue;
         const double *T = Mat + (int64_t)o * nc * nc;
         const double *X = UP ? (ch >= 0 ? v.M + (int64_t)ch * ldm : nullptr)
@@ -396,14 +428,63 @@ __global__ __launch_bounds__(64) void k_far(const PlanView *V, Bases B)
 
 // ---------------- P2P and output ----------------
 // Four wavefronts per block, one target leaf each.  Leaves with <= 32 (16)
-// targets split the sources over 2 (4) lane groups whose partial sums are
-// combined in a fixed order at the end.  FP64: plain sums.  Mixed: pair
-// offsets are formed in FP64 and rounded to FP32, the pair terms are FP32, each
-// source box is summed in FP32 and the box partials are accumulated in FP64.
+// targets split every source chunk into 2 (4) contiguous ranges handled by
+// separate lane groups, whose partial sums are combined in a fixed order at
+// the end.  Source chunks (<= 64 particles of one U-list box) are staged in
+// LDS as 32-byte records; the next chunk is loaded into registers while the
+// current one is summed.  FP64: plain sums.  Mixed: pair offsets are formed in
+// FP64 and rounded to FP32, the pair terms are FP32 (hardware rsq), each chunk
+// is summed in FP32 and the chunk partials are accumulated in FP64.
+struct SrcRec {
+    double x, y, z, q;
+};
+
+template <int MIXED>
+__device__ inline void p2p_range(const SrcRec *S, int lo, int hi, int jbase, int i, double xi,
+                                 double yi, double zi, double &phi, double &ex, double &ey,
+                                 double &ez)
+{
+    if (MIXED) {
+        float p = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
+        auto pair = [&](int jj) {
+            const SrcRec s = S[jj];
+            const float dx = (float)(xi - s.x), dy = (float)(yi - s.y), dz = (float)(zi - s.z);
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            const bool ok = (jbase + jj != i) && r2 > 0.f;
+            float ri = __builtin_amdgcn_rsqf(r2);
+            ri = ok ? ri : 0.f;
+            const float qr = (float)s.q * ri;
+            const float qr3 = qr * ri * ri;
+            p += qr;
+            fx += qr3 * dx; fy += qr3 * dy; fz += qr3 * dz;
+        };
+        int jj = lo;
+        for (; jj + 4 <= hi; jj += 4) { pair(jj); pair(jj + 1); pair(jj + 2); pair(jj + 3); }
+        for (; jj < hi; ++jj) pair(jj);
+        phi += (double)p; ex += (double)fx; ey += (double)fy; ez += (double)fz;
+    } else {
+        auto pair = [&](int jj) {
+            const SrcRec s = S[jj];
+            const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const bool ok = (jbase + jj != i) && r2 > 0.0;
+            double ri = rsqrt(r2);
+            ri = ok ? ri : 0.0;
+            const double qr = s.q * ri;
+            const double qr3 = qr * ri * ri;
+            phi += qr;
+            ex += qr3 * dx; ey += qr3 * dy; ez += qr3 * dz;
+        };
+        int jj = lo;
+        for (; jj + 4 <= hi; jj += 4) { pair(jj); pair(jj + 1); pair(jj + 2); pair(jj + 3); }
+        for (; jj < hi; ++jj) pair(jj);
+    }
+}
+
 template <int MIXED>
 __global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B)
 {
-    __shared__ double sx[4][64], sy[4][64], sz[4][64], sq[4][64];
+    __shared__ SrcRec sS[4][64];
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -411,56 +492,48 @@ __global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B)
     if (li >= v.nleaves) return;
     const int box = v.leaves[li];
     const int f = v.first[box], cnt = v.count[box];
-    int G = cnt > 32 ? 1 : (cnt > 16 ? 2 : 4);
+    const int G = cnt > 32 ? 1 : (cnt > 16 ? 2 : 4);
     const int TPG = 64 / G, grp = lane / TPG, tl = lane % TPG;
     const int64_t u0 = v.U_off[box], u1 = v.U_off[box + 1];
+    SrcRec *S = sS[wave];
     for (int ts = 0; ts < cnt; ts += TPG) {
         const int ti = ts + tl;
         const bool act = ti < cnt;
         const int i = f + (act ? ti : 0);
         const double xi = v.xs[i], yi = v.ys[i], zi = v.zs[i];
         double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
-        for (int64_t e = u0; e < u1; ++e) {
-            const int src = v.U_src[e];
-            const int sf = v.first[src], sc = v.count[src];
-            for (int s = 0; s < sc; s += 64) {
-                if (s + lane < sc) {
-                    int j = sf + s + lane;
-                    sx[wave][lane] = v.xs[j]; sy[wave][lane] = v.ys[j]; sz[wave][lane] = v.zs[j];
-                    sq[wave][lane] = v.qs[j];
-                }
-                wave_sync();
-                const int m = sc - s < 64 ? sc - s : 64;
-                const int jbase = sf + s;
-                if (MIXED) {
-                    float p = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
-                    for (int jj = grp; jj < m; jj += G) {
-                        float dx = (float)(xi - sx[wave][jj]);
-                        float dy = (float)(yi - sy[wave][jj]);
-                        float dz = (float)(zi - sz[wave][jj]);
-                        float r2 = dx * dx + dy * dy + dz * dz;
-                        bool ok = (jbase + jj != i) && r2 > 0.f;
-                        float ri = ok ? __builtin_amdgcn_rsqf(r2) : 0.f;
-                        float qr = (float)sq[wave][jj] * ri;
-                        float qr3 = qr * ri * ri;
-                        p += qr;
-                        fx += qr3 * dx; fy += qr3 * dy; fz += qr3 * dz;
-                    }
-                    phi += (double)p; ex += (double)fx; ey += (double)fy; ez += (double)fz;
-                } else {
-                    for (int jj = grp; jj < m; jj += G) {
-                        double dx = xi - sx[wave][jj], dy = yi - sy[wave][jj], dz = zi - sz[wave][jj];
-                        double r2 = dx * dx + dy * dy + dz * dz;
-                        bool ok = (jbase + jj != i) && r2 > 0.0;
-                        double ri = ok ? rsqrt(r2) : 0.0;
-                        double qr = sq[wave][jj] * ri;
-                        double qr3 = qr * ri * ri;
-                        phi += qr;
-                        ex += qr3 * dx; ey += qr3 * dy; ez += qr3 * dz;
-                    }
-                }
-                wave_sync();
+        // walk (U entry, 64-particle chunk) pairs with one chunk prefetched
+        int64_t e = u0;
+        int s = 0, sf = 0, sc = 0;
+        if (e < u1) { int src = v.U_src[e]; sf = v.first[src]; sc = v.count[src]; }
+        SrcRec nx{0, 0, 0, 0};
+        auto fetch = [&](int base, int m) {
+            if (lane < m) {
+                const int j = base + lane;
+                nx.x = v.xs[j]; nx.y = v.ys[j]; nx.z = v.zs[j]; nx.q = v.qs[j];
             }
+        };
+        // advance to the first non-empty chunk
+        while (e < u1 && sc == 0) {
+            if (++e < u1) { int src = v.U_src[e]; sf = v.first[src]; sc = v.count[src]; }
+        }
+        if (e < u1) fetch(sf, sc < 64 ? sc : 64);
+        while (e < u1) {
+            const int jbase = sf + s, m = sc - s < 64 ? sc - s : 64;
+            wave_sync();
+            S[lane] = nx;
+            wave_sync();
+            // next chunk
+            s += 64;
+            if (s >= sc) {
+                s = 0;
+                do {
+                    if (++e < u1) { int src = v.U_src[e]; sf = v.first[src]; sc = v.count[src]; }
+                } while (e < u1 && sc == 0);
+            }
+            if (e < u1) fetch(sf + s, sc - s < 64 ? sc - s : 64);
+            const int per = (m + G - 1) / G, lo = grp * per, hi = lo + per < m ? lo + per : m;
+            p2p_range<MIXED>(S, lo, hi, jbase, i, xi, yi, zi, phi, ex, ey, ez);
         }
         // combine lane groups in a fixed order
         if (G >= 4) {
@@ -510,6 +583,10 @@ void launch_permute_q(const PlanView *V, const Bases &B, hipStream_t s)
 void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (nblk(B)) DISPATCH_P(p, k_p2m, <<<nblk(B), 64, 0, s>>>(V, B));
+}
+void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s)
+{
+    if (nblk(B)) k_p2m_transform<<<nblk(B), 64, 0, s>>>(V, B);
 }
 void launch_fold(const PlanView *V, const Bases &B, hipStream_t s)
 {
