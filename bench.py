@@ -17,6 +17,11 @@ the plain oracle on a bounded sample: the points of one octant of the cube
 ([0,0.5)^3, 1/8 of the input) with the same box width (uniform depth 4 on the
 half-size root), p = 8.
 
+Other workloads (--workload): plummer4m (4e6 Plummer points, adaptive s=64,
+p=10), batch256 (256 independent problems, one fmm_evaluate_batch), serve
+(Poisson request stream through the continuous-batching server, p50/p99).
+Each prints one JSON line of the same form.
+
 Prints one JSON line.
 """
 import argparse
@@ -101,12 +106,205 @@ def sampled_sigma(xh, qh, phi, fld, count=2000, seed=7):
     return s_phi, s_fld, len(idx)
 
 
+def base_record(args):
+    return {"metric": METRIC, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "data": "synthetic"}
+
+
+def stage_avg(stages):
+    return {k: v[0] / max(v[1], 1) for k, v in stages.items()}
+
+
+def bench_plummer(args):
+    """4e6 Plummer points (a=0.05, r<=1, seed 2), adaptive s=64, p=10."""
+    import torch
+    from paper_2508_02626_amd import fmm, inputs
+    n = args.n if args.n != N_DEFAULT else 4_000_000
+    xh, qh = inputs.plummer(n, 2)
+    x = torch.tensor(xh, device="cuda:0")
+    q = torch.tensor(qh, device="cuda:0")
+    p = 10
+    res = {}
+    for mode in ("fp64", "mixed"):
+        def step():
+            pl = fmm.Plan(x, p, leaf_size=64, precision=mode)
+            pl.evaluate(q)
+            return pl
+        for _ in range(args.warmup):
+            step().close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step().close()
+        torch.cuda.synchronize()
+        step_s = (time.perf_counter() - t0) / args.steps
+        pl = fmm.Plan(x, p, leaf_size=64, precision=mode)
+        phi, fld = pl.evaluate(q)
+        torch.cuda.synchronize()
+        pl.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pl.evaluate(q, phi, fld)
+        torch.cuda.synchronize()
+        eval_s = (time.perf_counter() - t0) / args.steps
+        st, sizes = pl.read_timing(), pl.sizes()
+        pl.close()
+        sp, sf, nt = sampled_sigma(xh, qh, phi.cpu().numpy(), fld.cpu().numpy(), count=1000)
+        log("bench plummer: %s step %.2f ms eval %.2f ms sigma %.3e" % (mode, 1e3 * step_s, 1e3 * eval_s, sp))
+        res[mode] = dict(step_s=step_s, eval_s=eval_s, stages=stage_avg(st), sizes=sizes, sigma=sp, sigma_f=sf)
+    f, m = res["fp64"], res["mixed"]
+    flops = 2.0 * (p + 1) ** 4 * f["sizes"]["V"]
+    m2l_ms = f["stages"]["m2l"]
+    out = base_record(args)
+    out.update({
+        "value": n / f["step_s"], "ms_per_step": 1e3 * f["step_s"], "dtype": "f64",
+        "config": {"workload": "Plummer sphere: N=%d, scale 0.05, truncated at r=1 (seed 2), q~U(-1,1), "
+                               "adaptive octree s=64, p=10, potential+field" % n, "n": n, "order": p,
+                   "tree": "adaptive s=64", "step": "fmm_plan + fmm_evaluate", "sizes": f["sizes"]},
+        "accuracy": {"sigma_phi_vs_direct": f["sigma"], "sigma_field_vs_direct": f["sigma_f"],
+                     "targets_sampled": 1000},
+        "eval_only": {"value": n / f["eval_s"], "ms": 1e3 * f["eval_s"]},
+        "stage_ms": f["stages"],
+        "roofline": {"kernel": "k_m2l<10,double>", "bound": "mfma", "achieved": flops / (m2l_ms * 1e-3) / 1e12,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": flops / (m2l_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
+                     "flops_per_launch": flops, "ms_per_launch": m2l_ms},
+        "mixed": {"value": n / m["step_s"], "ms_per_step": 1e3 * m["step_s"], "eval_ms": 1e3 * m["eval_s"],
+                  "sigma_phi_vs_direct": m["sigma"], "sigma_field_vs_direct": m["sigma_f"],
+                  "dtype": "f64 with f32 P2P terms (M2L stays FP64 at p=10)", "stage_ms": m["stages"]},
+    })
+    return out
+
+
+def bench_batch(args):
+    """256 problems (N log-uniform in [1e3, 2e5], half uniform, half 8-cluster
+    mixtures, p in {4,6,8}), adaptive s=64, mixed precision: plans + one
+    fmm_evaluate_batch per step, against evaluating the plans one by one."""
+    import torch
+    from paper_2508_02626_amd import fmm, inputs
+    probs = [inputs.batch_problem(i) for i in range(256)]
+    xs = [torch.tensor(x, device="cuda:0") for x, _, _ in probs]
+    qs = [torch.tensor(q, device="cuda:0") for _, q, _ in probs]
+    ntot = sum(len(q) for _, q, _ in probs)
+
+    def plans():
+        return [fmm.Plan(x, p, leaf_size=64, precision="mixed") for x, (_, _, p) in zip(xs, probs)]
+
+    def run(batched):
+        ps = plans()
+        if batched:
+            fmm.evaluate_batch(ps, qs)
+        else:
+            for pl, q in zip(ps, qs):
+                pl.evaluate(q)
+        return ps
+
+    times = {}
+    for batched in (True, False):
+        for _ in range(args.warmup):
+            for pl in run(batched):
+                pl.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for pl in run(batched):
+                pl.close()
+        torch.cuda.synchronize()
+        times[batched] = (time.perf_counter() - t0) / args.steps
+    # evaluate-only, plans built once
+    ps = plans()
+    torch.cuda.synchronize()
+    ev = {}
+    for batched in (True, False):
+        fmm.evaluate_batch(ps, qs) if batched else [pl.evaluate(q) for pl, q in zip(ps, qs)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            if batched:
+                fmm.evaluate_batch(ps, qs)
+            else:
+                for pl, q in zip(ps, qs):
+                    pl.evaluate(q)
+        torch.cuda.synchronize()
+        ev[batched] = (time.perf_counter() - t0) / args.steps
+    for pl in ps:
+        pl.close()
+    log("bench batch: step %.1f ms (one by one %.1f ms), evaluate %.1f ms (one by one %.1f ms)" %
+        (1e3 * times[True], 1e3 * times[False], 1e3 * ev[True], 1e3 * ev[False]))
+    out = base_record(args)
+    out.update({
+        "value": ntot / times[True], "ms_per_step": 1e3 * times[True], "dtype": "f64 with f32 P2P and f32 MFMA M2L",
+        "config": {"workload": "256 independent problems, N log-uniform in [1e3,2e5] (seeds 1000+i), half "
+                               "uniform cube, half 8-cluster mixtures (sigma 0.02), p in {4,6,8}, adaptive s=64, "
+                               "mixed precision; step = 256 fmm_plan + one fmm_evaluate_batch", "n_total": ntot},
+        "one_by_one": {"value": ntot / times[False], "ms_per_step": 1e3 * times[False]},
+        "eval_only": {"batched_ms": 1e3 * ev[True], "one_by_one_ms": 1e3 * ev[False],
+                      "batched_value": ntot / ev[True]},
+        "roofline": None,
+    })
+    return out
+
+
+def bench_serve(args):
+    """Poisson stream through the continuous-batching server: N log-uniform in
+    [1e3, 1e6], uniform or Plummer, rel. error in {1e-4, 1e-7, 1e-9} -> p in
+    {4, 8, 12}; saturated throughput first, then arrival rates 0.25/0.5/0.75/0.9
+    of it; p50/p99 latency per rate."""
+    import torch
+    from paper_2508_02626_amd import inputs, serve
+    nreq, warm = args.requests, max(args.requests // 10, 5)
+    reqs = [inputs.served_request(i) for i in range(nreq + warm)]
+    ntot = sum(len(q) for _, q, _ in reqs[warm:])
+    srv = serve.Server(hbm_budget_bytes=64 << 30, slots=4)
+    # saturated: everything submitted at once
+    futs = [srv.submit(x, q, e) for x, q, e in reqs[:warm]]
+    [f.result() for f in futs]
+    t0 = time.perf_counter()
+    futs = [srv.submit(x, q, e) for x, q, e in reqs[warm:]]
+    lat_sat = [f.result()[2] for f in futs]
+    sat_s = time.perf_counter() - t0
+    rate_sat = nreq / sat_s
+    log("bench serve: saturated %.1f req/s, %.3e particles/s" % (rate_sat, ntot / sat_s))
+    rates = {}
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        lam = frac * rate_sat
+        arr = inputs.poisson_arrivals(nreq, lam, seed=5)
+        futs = []
+        t0 = time.perf_counter()
+        for (x, q, e), ta in zip(reqs[warm:], arr):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            futs.append(srv.submit(x, q, e))
+        lat = [f.result()[2] for f in futs]
+        span = time.perf_counter() - t0
+        st = serve.latency_stats(lat)
+        st.update({"arrival_rate_req_s": lam, "throughput_particles_s": ntot / span})
+        rates["%.2f" % frac] = st
+        log("bench serve: rate %.2f x sat: p50 %.1f ms p99 %.1f ms" % (frac, st["p50_ms"], st["p99_ms"]))
+    srv.close()
+    out = base_record(args)
+    out.update({
+        "value": ntot / sat_s, "ms_per_step": 1e3 * sat_s / nreq, "dtype": "f64 (p=12) / mixed (p<=8)",
+        "config": {"workload": "served Poisson stream: %d requests (+%d warm-up), N log-uniform in [1e3,1e6], "
+                               "uniform or Plummer, rel. error {1e-4,1e-7,1e-9} -> p {4,8,12}, adaptive s=64, "
+                               "4 slots, 64 GiB admission budget" % (nreq, warm), "requests": nreq},
+        "saturated": dict(serve.latency_stats(lat_sat), requests_per_s=rate_sat),
+        "latency_by_load": rates,
+        "roofline": None,
+    })
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_DEFAULT)
+    ap.add_argument("--workload", default="uniform1m", choices=["uniform1m", "plummer4m", "batch256", "serve"])
+    ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
@@ -119,6 +317,10 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.workload != "uniform1m":
+        fn = {"plummer4m": bench_plummer, "batch256": bench_batch, "serve": bench_serve}[args.workload]
+        print(json.dumps(fn(args)), flush=True)
+        return
     n = args.n
     xh, qh = inputs.uniform(n, SEED)
     x = torch.tensor(xh, device="cuda:0")

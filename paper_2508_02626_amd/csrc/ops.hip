@@ -157,9 +157,10 @@ __global__ __launch_bounds__(256) void k_fold(const PlanView *V, Bases B)
 }
 
 // ---------------- M2M / L2L on the matrix cores ----------------
-// One wavefront computes a 16 x 16 tile: 16 output coefficients (rows) of 16
+// A block computes a 16 x 16 tile: 16 output coefficients (rows) of 16
 // parents (columns) of one level, as sum over octants of T_o^t * X_o with the
-// 16x16x4 FP64 MFMA.  M2M: X_o holds the octant-o children's Mhat and the
+// 16x16x4 FP64 MFMA, one wavefront per octant (M2M sums the eight partial
+// tiles in octant order).  M2M: X_o holds the octant-o children's Mhat and the
 // tile is written to the parents.  L2L: X holds the parents' Lhat, and the
 // product of octant o is added to the octant-o children.  S is zero unless
 // |a| <= |b| and G unless g >= b, so only the contributing degree range of
@@ -167,14 +168,16 @@ __global__ __launch_bounds__(256) void k_fold(const PlanView *V, Bases B)
 constexpr int kPG = 16;
 
 template <int UP>
-__global__ __launch_bounds__(64) void k_translate(const PlanView *V, Bases B, int level)
+__global__ __launch_bounds__(512) void k_translate(const PlanView *V, Bases B, int level)
 {
     typedef double double4_t __attribute__((ext_vector_type(4)));
+    __shared__ double4_t red[8][64]; // M2M: per-octant partial tiles
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int item = blockIdx.x - B.b[k];
     const int MT = v.ldm / 16, g = item / MT, mt = item - g * MT;
-    const int lane = threadIdx.x, col = lane & 15, kq = lane >> 4;
+    const int o = threadIdx.x >> 6; // one wavefront per child octant
+    const int lane = threadIdx.x & 63, col = lane & 15, kq = lane >> 4;
     const int lb = v.lvl_nonleaf_off[level], le = v.lvl_nonleaf_off[level + 1];
     const int pidx = lb + g * kPG + col;
     const int parent = pidx < le ? v.lvl_nonleaf[pidx] : -1;
@@ -186,28 +189,17 @@ __global__ __launch_bounds__(64) void k_translate(const PlanView *V, Bases B, in
     // inner index range [k0, k1) that can contribute to this row tile
     const int k0 = UP ? 0 : (below(dlo) & ~3);
     const int k1 = UP ? below(dhi + 1) : nc;
-    // children of this lane's parent by octant (-1 if absent)
-    int chs[8];
-#pragma unroll
-    for (int o = 0; o < 8; ++o) chs[o] = -1;
+    int ch = -1; // child of this lane's parent in octant o
     if (parent >= 0) {
         const int cb = v.child_begin[parent], ncd = v.nchild[parent];
-        for (int i = 0; i < ncd; ++i) {
-            const int c = cb + i, oc = (int)(v.morton[c] & 7);
-#pragma unroll
-            for (int o = 0; o < 8; ++o)
-                if (o == oc) chs[o] = c;
-        }
+        for (int i = 0; i < ncd; ++i)
+            if ((int)(v.morton[cb + i] & 7) == o) ch = cb + i;
     }
     double4_t acc = {0, 0, 0, 0};
-#pragma unroll
-    for (int o = 0; o < 8; ++o) {
-        const int ch = chs[o];
-        if (!__any(ch >= 0)) continue;
+    if (__any(ch >= 0)) {
         const double *T = Mat + (int64_t)o * nc * nc;
         const double *X = UP ? (ch >= 0 ? v.M + (int64_t)ch * ldm : nullptr)
                              : (parent >= 0 ? v.L + (int64_t)parent * ldm : nullptr);
-        if (!UP) acc = double4_t{0, 0, 0, 0};
 #pragma unroll 8
         for (int kk = k0; kk < k1; kk += 4) {
             const int a = kk + kq;
@@ -223,12 +215,17 @@ __global__ __launch_bounds__(64) void k_translate(const PlanView *V, Bases B, in
             }
         }
     }
-    if (UP && parent >= 0) {
+    if (!UP) return;
+    red[o][lane] = acc;
+    __syncthreads();
+    if (o != 0 || parent < 0) return;
+    double4_t sum = red[0][lane];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int b = mt * 16 + 4 * r + kq;
-            v.M[(int64_t)parent * ldm + b] = acc[r]; // rows >= nc are zero
-        }
+    for (int w = 1; w < 8; ++w) sum += red[w][lane]; // fixed order
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int b = mt * 16 + 4 * r + kq;
+        v.M[(int64_t)parent * ldm + b] = sum[r]; // rows >= nc are zero
     }
 }
 
@@ -594,11 +591,11 @@ void launch_fold(const PlanView *V, const Bases &B, hipStream_t s)
 }
 void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s)
 {
-    if (nblk(B)) k_translate<1><<<nblk(B), 64, 0, s>>>(V, B, level);
+    if (nblk(B)) k_translate<1><<<nblk(B), 512, 0, s>>>(V, B, level);
 }
 void launch_l2l(const PlanView *V, const Bases &B, int level, hipStream_t s)
 {
-    if (nblk(B)) k_translate<0><<<nblk(B), 64, 0, s>>>(V, B, level);
+    if (nblk(B)) k_translate<0><<<nblk(B), 512, 0, s>>>(V, B, level);
 }
 void launch_unfold(const PlanView *V, const Bases &B, hipStream_t s)
 {

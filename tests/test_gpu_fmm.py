@@ -184,3 +184,22 @@ def test_full_size_uniform_sampled_against_direct():
             for k in ("perm", "first", "count", "V_off", "V_src", "U_off", "U_src"):
                 assert np.array_equal(g[k].astype(np.int64), o[k].astype(np.int64)), k
         pl.close()
+
+
+def test_full_size_plummer_sampled_against_direct():
+    """4e6 Plummer points, adaptive s = 64, p = 10 (FP64 M2L), mixed P2P:
+    sampled targets against the direct sum; sizes and lists against the oracle."""
+    from paper_2508_02626_amd import fmm
+    x, q = inputs.plummer(4_000_000, 2)
+    pl, phi, fld = gpu_solve(x, q, 10, leaf_size=64, precision="mixed")
+    idx = np.random.default_rng(9).choice(len(q), 200, replace=False)
+    d, fd = oracle.direct(x, q, idx)
+    e, ef = rel_l2(phi[idx], d), rel_l2(fld[idx], fd)
+    say("  plummer 4e6 p=10 sampled sigma phi %.3e field %.3e" % (e, ef), pl.sizes())
+    assert e < 2e-5 and ef < 1e-4
+    g = pl.export_tree()
+    t = oracle_tree(x, leaf_size=64)
+    o = t.export()
+    for k in ("perm", "level", "morton", "first", "count", "V_off", "V_src", "W_src", "X_src", "U_src"):
+        assert np.array_equal(g[k].astype(np.int64), o[k].astype(np.int64)), k
+    pl.close()
