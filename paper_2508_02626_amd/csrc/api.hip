@@ -586,6 +586,9 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     for (auto &r : runs)
         launch_p2l(P[r.first]->p, V + r.first,
                    sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).p2l; }), s);
+    for (auto &r : runs)
+        launch_p2l_transform(V + r.first, sub(r.first, r.second, [](const fmm_plan_s *p) {
+            return (int)ceil_div(p->nxtgt, 16) * (p->ldh / 16); }), s);
     T.end();
     T.begin(6);
     launch_unfold(V, make([](const fmm_plan_s *p) { return stage_blocks(p).unfold; }, all), s);

@@ -102,6 +102,7 @@ struct OrderTables {
     const double *S;    // [8][nc][nc] M2M, S[o][a][b] = d Mhat'_b / d Mhat_a
     const double *G;    // [8][nc][nc] L2L, G[o][g][b] = d Lhat'_b / d Lhat_g
     const double *P2M;  // [nc][nc] moments -> Mhat, P2M[g][a] = d Mhat_a / d Q_g
+    const double *P2L;  // [nc][ldh] inverse moments -> harmonic Lhat
     const int *fold_off; const int *fold_idx; const double *fold_c;     // Mhat -> folded
     const int *unfold_off; const int *unfold_idx; const double *unfold_c; // Lh -> Lhat
     const double *inv_fact;     // [nc] 1/b!

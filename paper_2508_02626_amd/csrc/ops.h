@@ -12,6 +12,7 @@ void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s); //
 void launch_l2l(const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block
 void launch_unfold(const PlanView *V, const Bases &B, hipStream_t s);      // 4 boxes/block
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 X target/block
+void launch_p2l_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 X targets x 16 rows/block
 void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block
 void launch_p2p(int mixed, const PlanView *V, const Bases &B, hipStream_t s); // 4 leaves/block
 void launch_zero(double *p, int64_t n, hipStream_t s);

@@ -10,7 +10,8 @@
 //   L2L  (Sec. 2.5) child Lhat += G_octant * parent Lhat.
 //   L2P / M2P (Sec. 3.2) share one evaluation routine (nested Horner with the
 //        gradient); M2P evaluates phi = |d| phi_M(d), d = y/|y|^2 (Eq. P2M_phi).
-//   P2L  (Sec. 2.4) Lhat_b += q d^b(1/|x|) at x = (c - x_i)/h.
+//   P2L  (Sec. 2.4) Lhat_b += q d^b(1/|x|) at x = (c - x_i)/h, through inverse
+//        moments and a fixed harmonic map.
 //   P2P  (Sec. 1) pairwise sum over the U list, skipping j == i and r == 0.
 #include "ops.h"
 
@@ -250,15 +251,19 @@ __global__ __launch_bounds__(256) void k_unfold(const PlanView *V, Bases B)
 }
 
 // ---------------- P2L (X list) ----------------
-// One wavefront per target box; lane = source particle; the harmonic
-// components (b_z <= 1) of d^b(1/|x|) follow from the Taylor recurrence of 1/|x|,
-// which stays within b_z <= 1; the sum over particles is done per coefficient.
+// Lhat_b(B) += sum_i q_i d^b(1/|x|) at x_i' = (c_B - x_i)/h_B (Sec. 2.4 in
+// scaled units).  With d^b(1/|x|) = (-1)^n (2n-1)!! pi(x^b)/|x|^(2n+1), the
+// harmonic components are a fixed map (table P2L) of the inverse moments
+// W_g = sum_i q_i x'^g / |x'|^(2|g|+1).  One wavefront per target box
+// accumulates W over the particles of its X list, one lane per moment (as in
+// P2M); k_p2l_transform then applies the map on MFMA for 16 boxes at a time.
 template <int P>
 __global__ __launch_bounds__(64) void k_p2l(const PlanView *V, Bases B)
 {
-    constexpr int NH = (P + 1) * (P + 1);
-    constexpr int R = (NH + 63) / 64;
-    __shared__ double a[NH][65];
+    constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
+    constexpr int R = (NC + 63) / 64;
+    __shared__ double pw[3][P + 1][65];
+    __shared__ double sr[P + 1][65];
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int box = v.xtgt[blockIdx.x - B.b[k]];
@@ -266,66 +271,88 @@ __global__ __launch_bounds__(64) void k_p2l(const PlanView *V, Bases B)
     double cen[3], h;
     box_geom(v, box, cen, h);
     const double ih = 1.0 / h;
+    int ex[R], ey[R], ez[R], en[R];
     double acc[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int r = 0; r < R; ++r) {
+        int g = lane + 64 * r;
+        int e = g < NC ? v.tab->exps[g] : 0;
+        ex[r] = e & 255; ey[r] = (e >> 8) & 255; ez[r] = (e >> 16) & 255;
+        en[r] = ex[r] + ey[r] + ez[r];
+        acc[r] = 0.0;
+    }
     for (int64_t e = v.X_off[box]; e < v.X_off[box + 1]; ++e) {
-        int src = v.X_src[e];
-        int f = v.first[src], cnt = v.count[src];
+        const int src = v.X_src[e];
+        const int f = v.first[src], cnt = v.count[src];
         for (int s = 0; s < cnt; s += 64) {
-            double x = 1, y = 0, z = 0, q = 0;
+            double x = 1.0, y = 0.0, z = 0.0, q = 0.0;
             if (s + lane < cnt) {
-                int i = f + s + lane;
+                const int i = f + s + lane;
                 x = (cen[0] - v.xs[i]) * ih; y = (cen[1] - v.ys[i]) * ih; z = (cen[2] - v.zs[i]) * ih;
                 q = v.qs[i];
             }
-            double r2 = x * x + y * y + z * z, ir2 = 1.0 / r2;
-            // Taylor coefficients a_g, then D_g = g! a_g; a[0] = q / r
-            a[0][lane] = q * sqrt(ir2);
+            const double ir2 = 1.0 / (x * x + y * y + z * z);
+            double a = 1.0, b = 1.0, c = 1.0, w = q * sqrt(ir2);
 #pragma unroll
-            for (int n = 1; n <= P; ++n) {
-#pragma unroll
-                for (int kz = 0; kz <= 1; ++kz)
-#pragma unroll
-                    for (int i = n - kz; i >= 0; --i) {
-                        int j = n - kz - i;
-                        double s1 = 0.0, s2 = 0.0;
-                        if (i >= 1) s1 += x * a[harm_index(i - 1, j, kz)][lane];
-                        if (j >= 1) s1 += y * a[harm_index(i, j - 1, kz)][lane];
-                        if (kz >= 1) s1 += z * a[harm_index(i, j, kz - 1)][lane];
-                        if (i >= 2) s2 += a[harm_index(i - 2, j, kz)][lane];
-                        if (j >= 2) s2 += a[harm_index(i, j - 2, kz)][lane];
-                        a[harm_index(i, j, kz)][lane] =
-                            -((2 * n - 1) * s1 + (n - 1) * s2) * ir2 / (double)n;
-                    }
+            for (int t = 0; t <= P; ++t) {
+                pw[0][t][lane] = a; pw[1][t][lane] = b; pw[2][t][lane] = c; sr[t][lane] = w;
+                a *= x; b *= y; c *= z; w *= ir2;
             }
             __syncthreads();
-            int m = cnt - s < 64 ? cnt - s : 64;
+            const int m = cnt - s < 64 ? cnt - s : 64;
+            for (int t = 0; t < m; ++t)
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                int c = lane + 64 * r;
-                if (c < NH)
-                    for (int t = 0; t < m; ++t) acc[r] += a[c][t];
-            }
+                for (int r = 0; r < R; ++r)
+                    acc[r] += pw[0][ex[r]][t] * pw[1][ey[r]][t] * pw[2][ez[r]][t] * sr[en[r]][t];
             __syncthreads();
         }
     }
-    // D_c = c! a_c; c = (i, j, kz)
+    double *W = v.L + (int64_t)box * v.ldm; // free until the unfold stage
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        int c = lane + 64 * r;
-        if (c < NH) {
-            int n = 0;
-            while ((n + 1) * (n + 1) <= c) ++n;
-            int w = c - n * n, i, j, kz;
-            if (w <= n) { kz = 0; i = n - w; j = n - i; }
-            else { kz = 1; i = n - 1 - (w - n - 1); j = n - 1 - i; }
-            double fct = 1.0;
-            for (int t = 2; t <= i; ++t) fct *= t;
-            for (int t = 2; t <= j; ++t) fct *= t;
-            double *dst = v.Lh + (int64_t)box * v.ldh + c;
-            double base = v.V_off[box + 1] > v.V_off[box] ? *dst : 0.0; // M2L wrote this row?
-            *dst = base + acc[r] * fct;
+    for (int r = 0; r < R; ++r)
+        if (lane + 64 * r < NC) W[lane + 64 * r] = acc[r];
+}
+
+__device__ inline int harm_degree(int c)
+{
+    int n = 0;
+    while ((n + 1) * (n + 1) <= c) ++n;
+    return n;
+}
+
+__global__ __launch_bounds__(64) void k_p2l_transform(const PlanView *V, Bases B)
+{
+    typedef double double4_t __attribute__((ext_vector_type(4)));
+    const int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int item = blockIdx.x - B.b[k];
+    const int MT = v.ldh / 16, g = item / MT, mt = item - g * MT;
+    const int lane = threadIdx.x, col = lane & 15, kq = lane >> 4;
+    const int bi = g * 16 + col;
+    const int box = bi < v.nxtgt ? v.xtgt[bi] : -1;
+    const int nc = v.nc, nh = v.nh, ldh = v.ldh;
+    const int cA = mt * 16 + col;
+    const double *T = v.tab->P2L;
+    const int dlo = harm_degree(mt * 16 < nh ? mt * 16 : nh - 1);
+    const int dhi = harm_degree(mt * 16 + 15 < nh ? mt * 16 + 15 : nh - 1);
+    const int k0 = below(dlo) & ~3, k1 = below(dhi + 1);
+    const double *W = box >= 0 ? v.L + (int64_t)box * v.ldm : nullptr;
+    double4_t acc = {0, 0, 0, 0};
+#pragma unroll 4
+    for (int kk = k0; kk < k1; kk += 4) {
+        const int a = kk + kq;
+        const double av = (cA < nh && a < nc) ? T[(int64_t)a * ldh + cA] : 0.0;
+        const double bv = (W && a < nc) ? W[a] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    if (box < 0) return;
+    const bool has_v = v.V_off[box + 1] > v.V_off[box]; // M2L wrote this row?
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int c = mt * 16 + 4 * r + kq;
+        if (c < nh) {
+            double *dst = v.Lh + (int64_t)box * ldh + c;
+            *dst = (has_v ? *dst : 0.0) + acc[r];
         }
     }
 }
@@ -604,6 +631,10 @@ void launch_unfold(const PlanView *V, const Bases &B, hipStream_t s)
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (nblk(B)) DISPATCH_P(p, k_p2l, <<<nblk(B), 64, 0, s>>>(V, B));
+}
+void launch_p2l_transform(const PlanView *V, const Bases &B, hipStream_t s)
+{
+    if (nblk(B)) k_p2l_transform<<<nblk(B), 64, 0, s>>>(V, B);
 }
 void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {

@@ -160,7 +160,7 @@ std::vector<ld> harmonic_projection(const Mono &m, const std::vector<ld> &v, int
 }
 
 struct Built {
-    std::vector<double> D, S, G, P2M, fold_c, unfold_c, inv_fact, inv_w;
+    std::vector<double> D, S, G, P2M, P2L, fold_c, unfold_c, inv_fact, inv_w;
     std::vector<float> Df;
     std::vector<int> offs, hoff, fold_off, fold_idx, unfold_off, unfold_idx, exps;
     int ldd = 0;
@@ -241,6 +241,21 @@ void build_tables(int p, Built &B)
         unit[g] = 1.0L;
         std::vector<ld> h = harmonic_projection(m, unit, m.deg(g));
         for (int be = 0; be < nc; ++be) Pi[(size_t)g * nc + be] = h[be];
+    }
+    // P2L: d^b(1/|x|) = (-1)^n (2n-1)!! pi(x^b)(x) / |x|^(2n+1) (n = |b|), since
+    // the non-harmonic part of x^b, a multiple of |x|^2, turns into a Laplacian
+    // of 1/|x|.  So the harmonic components of Lhat are a fixed map of the
+    // inverse moments W_g = sum q x^g / |x|^(2|g|+1):
+    // P2L[g][c] = (-1)^n (2n-1)!! * (coefficient of x^g in pi(x^b(c))).
+    B.P2L.assign((size_t)nc * ldh, 0.0);
+    for (int g = 0; g < nc; ++g) {
+        int n = m.deg(g);
+        ld f = ((n & 1) ? -1.0L : 1.0L) * dfact(2 * n - 1);
+        for (int c = 0; c < nh; ++c) {
+            int be = mono_index(hx[c], hy[c], hz[c]);
+            if (m.deg(be) != n) continue;
+            B.P2L[(size_t)g * ldh + c] = (double)(f * Pi[(size_t)be * nc + g]);
+        }
     }
     B.S.assign((size_t)8 * nc * nc, 0.0);
     for (int o = 0; o < 8; ++o) {
@@ -346,7 +361,7 @@ const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::s
     t.ldd = B.ldd; t.d3 = dlayout_s1(p);
     if (upload(B.D, &t.D, err) || upload(B.Df, &t.Df, err) || upload(B.offs, &t.offs, err) ||
         upload(B.hoff, &t.hoff, err) || upload(B.S, &t.S, err) || upload(B.G, &t.G, err) ||
-        upload(B.P2M, &t.P2M, err) || upload(B.fold_off, &t.fold_off, err) ||
+        upload(B.P2M, &t.P2M, err) || upload(B.P2L, &t.P2L, err) || upload(B.fold_off, &t.fold_off, err) ||
         upload(B.fold_idx, &t.fold_idx, err) || upload(B.fold_c, &t.fold_c, err) ||
         upload(B.unfold_off, &t.unfold_off, err) || upload(B.unfold_idx, &t.unfold_idx, err) ||
         upload(B.unfold_c, &t.unfold_c, err) || upload(B.inv_fact, &t.inv_fact, err) ||
