@@ -162,4 +162,15 @@ __device__ inline int find_plan(const Bases &B, int item)
 
 inline unsigned ceil_div(long long a, long long b) { return (unsigned)((a + b - 1) / b); }
 
+// Work groups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Maps the i-th block (of n) so that every XCD receives one contiguous range of
+// items: neighbouring items (Morton-adjacent boxes sharing interaction-list
+// sources) then share an L2.  Bijective on [0, n).
+constexpr int kXCDs = 8;
+__device__ inline int xcd_remap(int i, int n)
+{
+    const int x = i % kXCDs, y = i / kXCDs, q = n / kXCDs, r = n % kXCDs;
+    return x * q + (x < r ? x : r) + y;
+}
+
 } // namespace fmm

@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
 
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
-    const int tile = blockIdx.x - B.b[k];
+    const int tile = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
     const int slot = tile * kM2LSlots + wave * 16 + col;
     const int tgt = v.m2l_tgt[slot];

@@ -512,7 +512,7 @@ __global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B)
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int li = (blockIdx.x - B.b[k]) * 4 + wave;
+    const int li = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]) * 4 + wave;
     if (li >= v.nleaves) return;
     const int box = v.leaves[li];
     const int f = v.first[box], cnt = v.count[box];
