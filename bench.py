@@ -39,6 +39,22 @@ METRIC = "particles/s at 1e-7 rel. err (plain FP64 vs mixed); p50/p99 solve late
 N_DEFAULT, DEPTH, ORDER, SEED = 1_000_000, 5, 8, 1
 FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS = 78.6, 157.3
 
+# HBM bytes per launch of k_m2l<8,double> on this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration (read x2.0,
+# write x1.0; profiles/uniform1m_hbm_traffic.txt).  Valid only for the kernel
+# sources it was measured on: a different fingerprint reports null.
+M2L_TRAFFIC = {"fingerprint": "f3cb2fbfda46102a", "bytes": (3663.92 + 25.16) * 1e6}
+M2L_SOURCES = ("paper_2508_02626_amd/csrc/m2l.hip", "paper_2508_02626_amd/csrc/common.h")
+
+
+def m2l_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in M2L_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return M2L_TRAFFIC["bytes"] if h.hexdigest()[:16] == M2L_TRAFFIC["fingerprint"] else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -309,8 +325,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solve would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs a solve on a single GPU "
+              "and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2508_02626_amd import inputs
@@ -360,7 +376,8 @@ def main():
         "stage_ms": {k: v[0] / max(v[1], 1) for k, v in f["stages"].items()},
         "roofline": {"kernel": "k_m2l<8,double>", "bound": "mfma", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": None, "flops_per_launch": flops, "ms_per_launch": m2l_ms},
+                     "traffic": m2l_traffic(), "traffic_unit": "bytes per launch",
+                     "flops_per_launch": flops, "ms_per_launch": m2l_ms},
     }
     if "mixed" in res:
         m = res["mixed"]
