@@ -36,6 +36,36 @@ constexpr int kMaxUniformDepth = 8;
 
 } // namespace
 
+// Everything the host needs to know about a tree before it sizes the list
+// arrays, gathered on the device and fetched with one copy.
+struct PlanSizes {
+    int64_t tot[4];                  // U, V, W, X list lengths
+    int64_t nleaves, nnonleaf, nxtgt, nmtg;
+    int64_t lnl[kMaxDepth + 2];      // non-leaf boxes before each level
+    int32_t lvl_begin[kMaxDepth + 2];
+    double root[4];
+    int32_t bad;
+};
+
+__global__ void k_collect_sizes(const int64_t *uoff, const int64_t *voff, const int64_t *woff,
+                                const int64_t *xoff, const int64_t *pleaf, const int64_t *pnon,
+                                const int64_t *px, const int64_t *pv, const int32_t *lvl_begin,
+                                const double *root, const int *bad, int nb, PlanSizes *out)
+{
+    const int t = threadIdx.x;
+    if (t == 0) {
+        out->tot[0] = uoff[nb]; out->tot[1] = voff[nb]; out->tot[2] = woff[nb]; out->tot[3] = xoff[nb];
+        out->nleaves = pleaf[nb]; out->nnonleaf = pnon[nb]; out->nxtgt = px[nb]; out->nmtg = pv[nb];
+        out->bad = *bad;
+    }
+    if (t < 4) out->root[t] = root[t];
+    if (t < kMaxDepth + 2) {
+        int b = lvl_begin[t];
+        out->lvl_begin[t] = b;
+        out->lnl[t] = pnon[b < nb ? b : nb];
+    }
+}
+
 struct fmm_plan_s {
     int device = 0;
     hipStream_t stream = 0;
@@ -64,10 +94,14 @@ struct fmm_plan_s {
     std::vector<Rec> recs;      // recorded, not yet read
     std::vector<Rec> pool;      // reusable event pairs
 
+    // host copies kept for the lifetime of the plan (sources of async copies)
+    std::vector<int32_t> lvl_host;
+    PlanSizes sizes{};
+
+    static size_t rounded(size_t bytes) { return ((bytes ? bytes : 8) + 255) & ~(size_t)255; }
     void *raw_alloc(size_t bytes)
     {
-        if (bytes == 0) bytes = 8;
-        bytes = (bytes + 255) & ~(size_t)255;
+        bytes = rounded(bytes);
         void *p = nullptr;
         if (user_alloc) p = alloc.alloc(bytes, stream, alloc.ctx);
         else if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
@@ -79,28 +113,59 @@ struct fmm_plan_s {
         if (user_alloc) alloc.free(p, stream, alloc.ctx);
         else (void)hipFreeAsync(p, stream);
     }
+    // Buffers are carved from a few large chunks (reserve_*), one per build
+    // phase; a request that does not fit the current chunk gets its own
+    // allocation.  Owned buffers live until destroy, temporaries until the end
+    // of the build.
+    struct Chunk { char *base = nullptr; size_t cap = 0, used = 0; };
+    Chunk own_chunk, temp_chunk;
+    void *carve(Chunk &c, size_t bytes)
+    {
+        bytes = rounded(bytes);
+        if (!c.base || c.used + bytes > c.cap) return nullptr;
+        void *p = c.base + c.used;
+        c.used += bytes;
+        return p;
+    }
+    bool reserve(bool owned, size_t bytes)
+    {
+        bytes = rounded(bytes);
+        void *p = raw_alloc(bytes);
+        if (!p) return false;
+        if (owned) { bufs.push_back({p, bytes}); footprint += bytes; own_chunk = {(char *)p, bytes, 0}; }
+        else { temps.push_back({p, bytes}); temp_chunk = {(char *)p, bytes, 0}; }
+        return true;
+    }
     template <typename T> T *own(size_t count)
     {
-        void *p = raw_alloc(sizeof(T) * count);
-        if (p) { bufs.push_back({p, sizeof(T) * count}); footprint += sizeof(T) * count; }
+        size_t b = sizeof(T) * count;
+        void *p = carve(own_chunk, b);
+        if (p) return (T *)p;
+        p = raw_alloc(b);
+        if (p) { bufs.push_back({p, b}); footprint += rounded(b); }
         return (T *)p;
     }
     template <typename T> T *temp(size_t count)
     {
-        void *p = raw_alloc(sizeof(T) * count);
-        if (p) temps.push_back({p, sizeof(T) * count});
+        size_t b = sizeof(T) * count;
+        void *p = carve(temp_chunk, b);
+        if (p) return (T *)p;
+        p = raw_alloc(b);
+        if (p) temps.push_back({p, b});
         return (T *)p;
     }
     void release_temps()
     {
         for (auto &t : temps) raw_free(t.first);
         temps.clear();
+        temp_chunk = Chunk{};
     }
     void release_all()
     {
         release_temps();
         for (auto &b : bufs) raw_free(b.first);
         bufs.clear();
+        own_chunk = Chunk{};
         footprint = 0;
     }
 };
@@ -131,239 +196,205 @@ template <typename T> int copy_to_host(T *dst, const T *src, size_t n, hipStream
         if (!(ptr)) return fail(FMM_ENOMEM, "device allocation failed (" #ptr ")");       \
     } while (0)
 
-// Adaptive boxes, level by level (one host synchronisation per level to learn
-// how many children the level produced).
-int build_adaptive(fmm_plan_s *P, const uint64_t *keys)
-{
-    hipStream_t s = P->stream;
-    int cap = std::max(64, (int)std::min<int64_t>(2 + 16LL * P->n / (P->leaf_size + 1), 1LL << 30));
-    auto alloc_boxes = [&](int c, BoxArrays &b) {
-        b.level = P->temp<int32_t>(c); b.first = P->temp<int32_t>(c); b.count = P->temp<int32_t>(c);
-        b.parent = P->temp<int32_t>(c); b.child_begin = P->temp<int32_t>(c); b.nchild = P->temp<int32_t>(c);
-        b.morton = P->temp<uint64_t>(c);
-        return b.level && b.first && b.count && b.parent && b.child_begin && b.nchild && b.morton;
-    };
-    BoxArrays bx{};
-    if (!alloc_boxes(cap, bx)) return fail(FMM_ENOMEM, "device allocation failed (boxes)");
-    root_box(P->n, bx, s);
-    P->lvl_begin = {0, 1};
-    int64_t *nch = P->temp<int64_t>(cap + 1), *off = P->temp<int64_t>(cap + 2);
-    int64_t *scr = P->temp<int64_t>(scan_scratch_bytes(cap) / 8 + 1);
-    NOMEM(nch); NOMEM(off); NOMEM(scr);
-    int ncap_scan = cap;
-    for (int l = 0; l < P->D; ++l) {
-        int lb = P->lvl_begin[l], le = P->lvl_begin[l + 1], m = le - lb;
-        if (m > ncap_scan) {
-            ncap_scan = 2 * m;
-            nch = P->temp<int64_t>(ncap_scan + 1); off = P->temp<int64_t>(ncap_scan + 2);
-            scr = P->temp<int64_t>(scan_scratch_bytes(ncap_scan) / 8 + 1);
-            NOMEM(nch); NOMEM(off); NOMEM(scr);
-        }
-        count_children(keys, P->D, l, lb, le, P->leaf_size, bx, nch, s);
-        scan_exclusive(nch, off, m, scr, s);
-        int64_t total = 0;
-        if (copy_to_host(&total, off + m, 1, s)) return FMM_EDEVICE;
-        HIPCHK(hipStreamSynchronize(s));
-        if (total == 0) break;
-        if (le + total > cap) { // grow, keep contents
-            int ncap = (int)std::max<int64_t>(2LL * cap, le + total + 1);
-            BoxArrays nb{};
-            if (!alloc_boxes(ncap, nb)) return fail(FMM_ENOMEM, "device allocation failed (boxes)");
-            HIPCHK(hipMemcpyAsync(nb.level, bx.level, 4ull * le, hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(nb.first, bx.first, 4ull * le, hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(nb.count, bx.count, 4ull * le, hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(nb.parent, bx.parent, 4ull * le, hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(nb.child_begin, bx.child_begin, 4ull * le, hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(nb.nchild, bx.nchild, 4ull * le, hipMemcpyDeviceToDevice, s));
-            HIPCHK(hipMemcpyAsync(nb.morton, bx.morton, 8ull * le, hipMemcpyDeviceToDevice, s));
-            bx = nb;
-            cap = ncap;
-        }
-        fill_children(keys, P->D, l, lb, le, off, bx, s);
-        P->lvl_begin.push_back(le + (int)total);
-    }
-    P->nboxes = P->lvl_begin.back();
-    // move into owned arrays of the exact size
-    int nb = P->nboxes;
-    BoxArrays o{};
-    o.level = P->own<int32_t>(nb); o.first = P->own<int32_t>(nb); o.count = P->own<int32_t>(nb);
-    o.parent = P->own<int32_t>(nb); o.child_begin = P->own<int32_t>(nb); o.nchild = P->own<int32_t>(nb);
-    o.morton = P->own<uint64_t>(nb);
-    if (!(o.level && o.first && o.count && o.parent && o.child_begin && o.nchild && o.morton))
-        return fail(FMM_ENOMEM, "device allocation failed (boxes)");
-    HIPCHK(hipMemcpyAsync(o.level, bx.level, 4ull * nb, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(o.first, bx.first, 4ull * nb, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(o.count, bx.count, 4ull * nb, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(o.parent, bx.parent, 4ull * nb, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(o.child_begin, bx.child_begin, 4ull * nb, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(o.nchild, bx.nchild, 4ull * nb, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(o.morton, bx.morton, 8ull * nb, hipMemcpyDeviceToDevice, s));
-    P->bx = o;
-    return 0;
-}
+// Byte total of a list of buffers carved from one chunk.
+struct Sizer {
+    size_t total = 0;
+    template <typename T> Sizer &add(size_t count) { total += fmm_plan_s::rounded(sizeof(T) * count); return *this; }
+};
 
+// Plan construction, stream-ordered on the plan's stream with three host
+// synchronisations (two for a uniform tree): the box count of an adaptive
+// tree, the list and work-list sizes, and the end of the build.
 int build_plan(fmm_plan_s *P, const double *xyz)
 {
     hipStream_t s = P->stream;
     const int n = P->n;
-    // root cube
+    const bool adaptive = !P->uniform;
+    // ---- phase A: particles (sizes known from n)
+    {
+        Sizer o;
+        o.add<int32_t>(n).add<double>(n).add<double>(n).add<double>(n).add<double>(n).add<double>(n).add<double>(3ull * n);
+        if (!P->reserve(true, o.total)) return fail(FMM_ENOMEM, "device allocation failed (particles)");
+        Sizer t;
+        t.add<double>(4).add<double>(6 * kBBoxBlocks).add<int>(1).add<uint64_t>(n).add<uint64_t>(n).add<int32_t>(n)
+         .add<int32_t>(sort_scratch_bytes(n) / 4 + 1);
+        if (adaptive) t.add<int64_t>(n + 1).add<int64_t>(n + 2).add<int64_t>(scan_scratch_bytes(n + 1) / 8 + 1);
+        if (!P->reserve(false, t.total)) return fail(FMM_ENOMEM, "device allocation failed (keys)");
+    }
+    P->perm = P->own<int32_t>(n);
+    double *xs = P->own<double>(n), *ys = P->own<double>(n), *zs = P->own<double>(n);
+    double *qs = P->own<double>(n), *pf = P->own<double>(n), *ff = P->own<double>(3ull * n);
     double *root_dev = P->temp<double>(4), *part = P->temp<double>(6 * kBBoxBlocks);
     int *bad = P->temp<int>(1);
-    NOMEM(root_dev); NOMEM(part); NOMEM(bad);
-    HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
-    if (P->root[3] <= 0) { // bounding cube
-        bbox(xyz, n, part, root_dev, s);
-        if (copy_to_host(P->root, root_dev, 4, s)) return FMM_EDEVICE;
-        HIPCHK(hipStreamSynchronize(s));
-        if (!std::isfinite(P->root[0]) || !std::isfinite(P->root[1]) || !std::isfinite(P->root[2]) ||
-            !std::isfinite(P->root[3]))
-            return fail(FMM_EINVAL, "non-finite coordinates");
-    }
-    // keys and sorted order
     uint64_t *keys = P->temp<uint64_t>(n), *tk = P->temp<uint64_t>(n);
     int32_t *tv = P->temp<int32_t>(n), *sscr = P->temp<int32_t>(sort_scratch_bytes(n) / 4 + 1);
-    P->perm = P->own<int32_t>(n);
-    NOMEM(keys); NOMEM(tk); NOMEM(tv); NOMEM(sscr); NOMEM(P->perm);
-    morton_keys(xyz, n, P->root, P->D, keys, P->perm, bad, s);
+    NOMEM(P->perm); NOMEM(xs); NOMEM(ys); NOMEM(zs); NOMEM(qs); NOMEM(pf); NOMEM(ff);
+    NOMEM(root_dev); NOMEM(part); NOMEM(bad); NOMEM(keys); NOMEM(tk); NOMEM(tv); NOMEM(sscr);
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
+    if (P->root[3] <= 0) bbox(xyz, n, part, root_dev, s); // bounding cube, stays on the device
+    else HIPCHK(hipMemcpyAsync(root_dev, P->root, sizeof(P->root), hipMemcpyHostToDevice, s));
+    morton_keys(xyz, n, root_dev, P->D, keys, P->perm, bad, s);
     radix_sort_pairs(keys, P->perm, tk, tv, n, 3 * P->D, sscr, s);
-    double *xs = P->own<double>(n), *ys = P->own<double>(n), *zs = P->own<double>(n);
-    NOMEM(xs); NOMEM(ys); NOMEM(zs);
     gather_sorted(xyz, P->perm, n, xs, ys, zs, s);
-    // boxes
-    if (P->uniform) {
-        P->lvl_begin.assign(1, 0);
-        long long tot = 0, sz = 1;
-        for (int l = 0; l <= P->D; ++l) { tot += sz; sz *= 8; P->lvl_begin.push_back((int)tot); }
-        P->nboxes = (int)tot;
-        int nb = P->nboxes;
-        BoxArrays o{};
-        o.level = P->own<int32_t>(nb); o.first = P->own<int32_t>(nb); o.count = P->own<int32_t>(nb);
-        o.parent = P->own<int32_t>(nb); o.child_begin = P->own<int32_t>(nb); o.nchild = P->own<int32_t>(nb);
-        o.morton = P->own<uint64_t>(nb);
-        if (!(o.level && o.first && o.count && o.parent && o.child_begin && o.nchild && o.morton))
-            return fail(FMM_ENOMEM, "device allocation failed (boxes)");
-        uniform_boxes(keys, n, P->D, nb, o, s);
-        P->bx = o;
+    // ---- box count
+    int64_t *ecnt = nullptr, *eoff = nullptr;
+    if (adaptive) {
+        ecnt = P->temp<int64_t>(n + 1);
+        eoff = P->temp<int64_t>(n + 2);
+        int64_t *escr = P->temp<int64_t>(scan_scratch_bytes(n + 1) / 8 + 1);
+        NOMEM(ecnt); NOMEM(eoff); NOMEM(escr);
+        emit_count(keys, n, P->D, P->leaf_size, ecnt, s);
+        scan_exclusive(ecnt, eoff, n, escr, s);
+        int64_t total = 0;
+        if (copy_to_host(&total, eoff + n, 1, s)) return FMM_EDEVICE;
+        HIPCHK(hipStreamSynchronize(s));
+        if (total < 1 || total >= (1LL << 31)) return fail(FMM_EDEVICE, "bad box count");
+        P->nboxes = (int)total;
     } else {
-        int rc = build_adaptive(P, keys);
-        if (rc) return rc;
+        long long tot = 0, sz = 1;
+        for (int l = 0; l <= P->D; ++l) { tot += sz; sz *= 8; }
+        P->nboxes = (int)tot;
     }
-    P->depth = (int)P->lvl_begin.size() - 2;
     const int nb = P->nboxes;
-    int32_t *lvl_dev = P->own<int32_t>(kMaxDepth + 2);
-    NOMEM(lvl_dev);
+    // ---- phase B: boxes, list counts, work lists (sizes known from nb)
     {
-        std::vector<int32_t> lb(kMaxDepth + 2, nb);
-        for (size_t i = 0; i < P->lvl_begin.size() && i < lb.size(); ++i) lb[i] = P->lvl_begin[i];
-        HIPCHK(hipMemcpyAsync(lvl_dev, lb.data(), sizeof(int32_t) * lb.size(), hipMemcpyHostToDevice, s));
-        HIPCHK(hipStreamSynchronize(s)); // lb is a host temporary
+        Sizer o;
+        o.add<int32_t>(nb).add<int32_t>(nb).add<int32_t>(nb).add<int32_t>(nb).add<int32_t>(nb).add<int32_t>(nb)
+         .add<uint64_t>(nb).add<int32_t>(kMaxDepth + 2);
+        for (int w = 0; w < 4; ++w) o.add<int64_t>(nb + 1);
+        o.add<int32_t>((size_t)nb * kVSlots).add<int32_t>(nb).add<int32_t>(nb).add<int32_t>(nb)
+         .add<int32_t>(kMaxDepth + 2).add<PlanView>(1)
+         .add<double>((size_t)nb * P->ldm).add<double>((size_t)nb * P->ldm)
+         .add<double>((size_t)nb * P->ldh).add<double>((size_t)nb * P->ldh);
+        if (P->mixed_m2l) o.add<float>((size_t)nb * P->ldh);
+        if (!P->reserve(true, o.total)) return fail(FMM_ENOMEM, "device allocation failed (boxes)");
+        Sizer t;
+        if (adaptive)
+            t.add<uint64_t>(nb).add<int32_t>(nb).add<uint64_t>(nb).add<int32_t>(nb).add<int32_t>(nb).add<int32_t>(nb)
+             .add<uint64_t>(nb).add<int32_t>(sort_scratch_bytes(nb) / 4 + 1);
+        t.add<int32_t>(27ull * nb);
+        for (int w = 0; w < 8; ++w) t.add<int64_t>(nb + 1);
+        for (int w = 0; w < 4; ++w) t.add<int64_t>(nb + 1);
+        t.add<int64_t>(scan_multi_scratch_bytes(nb, 8) / 8 + 1).add<int32_t>(nb).add<PlanSizes>(1);
+        if (!P->reserve(false, t.total)) return fail(FMM_ENOMEM, "device allocation failed (lists)");
     }
-    TreeArgs ta{P->bx, lvl_dev, P->D, nb};
-    // lists: count, scan, sizes
-    int32_t *coll = P->temp<int32_t>(27ull * nb);
-    int64_t *cntV = P->temp<int64_t>(nb), *cntU = P->temp<int64_t>(nb), *cntW = P->temp<int64_t>(nb);
-    int64_t *cntX = P->temp<int64_t>(nb);
-    int64_t *scr = P->temp<int64_t>(scan_scratch_bytes(nb) / 8 + 1);
-    for (int w = 0; w < 4; ++w) P->off[w] = P->own<int64_t>(nb + 1);
-    NOMEM(coll); NOMEM(cntV); NOMEM(cntU); NOMEM(cntW); NOMEM(cntX); NOMEM(scr);
-    NOMEM(P->off[0]); NOMEM(P->off[1]); NOMEM(P->off[2]); NOMEM(P->off[3]);
+    BoxArrays bx{};
+    bx.level = P->own<int32_t>(nb); bx.first = P->own<int32_t>(nb); bx.count = P->own<int32_t>(nb);
+    bx.parent = P->own<int32_t>(nb); bx.child_begin = P->own<int32_t>(nb); bx.nchild = P->own<int32_t>(nb);
+    bx.morton = P->own<uint64_t>(nb);
+    int32_t *lvl_dev = P->own<int32_t>(kMaxDepth + 2);
+    if (!(bx.level && bx.first && bx.count && bx.parent && bx.child_begin && bx.nchild && bx.morton && lvl_dev))
+        return fail(FMM_ENOMEM, "device allocation failed (boxes)");
+    P->bx = bx;
+    for (int w = 0; w < 4; ++w) { P->off[w] = P->own<int64_t>(nb + 1); NOMEM(P->off[w]); }
     int32_t *vslot = P->own<int32_t>((size_t)nb * kVSlots);
-    NOMEM(vslot);
+    int32_t *leaves = P->own<int32_t>(nb), *nonleaf = P->own<int32_t>(nb), *xtgt = P->own<int32_t>(nb);
+    int32_t *lnl_off = P->own<int32_t>(kMaxDepth + 2);
+    P->view_dev = P->own<PlanView>(1);
+    double *M = P->own<double>((size_t)nb * P->ldm), *L = P->own<double>((size_t)nb * P->ldm);
+    double *Mh = P->own<double>((size_t)nb * P->ldh), *Lh = P->own<double>((size_t)nb * P->ldh);
+    float *Mhf = P->mixed_m2l ? P->own<float>((size_t)nb * P->ldh) : nullptr;
+    NOMEM(vslot); NOMEM(leaves); NOMEM(nonleaf); NOMEM(xtgt); NOMEM(lnl_off); NOMEM(P->view_dev);
+    NOMEM(M); NOMEM(L); NOMEM(Mh); NOMEM(Lh);
+    if (P->mixed_m2l) NOMEM(Mhf);
+    if (adaptive) {
+        uint64_t *elevel = P->temp<uint64_t>(nb), *etk = P->temp<uint64_t>(nb), *emorton = P->temp<uint64_t>(nb);
+        int32_t *eidx = P->temp<int32_t>(nb), *etv = P->temp<int32_t>(nb);
+        int32_t *efirst = P->temp<int32_t>(nb), *ecount = P->temp<int32_t>(nb);
+        int32_t *escr = P->temp<int32_t>(sort_scratch_bytes(nb) / 4 + 1);
+        NOMEM(elevel); NOMEM(etk); NOMEM(emorton); NOMEM(eidx); NOMEM(etv); NOMEM(efirst); NOMEM(ecount); NOMEM(escr);
+        adaptive_boxes(keys, n, P->D, P->leaf_size, eoff, nb, elevel, eidx, etk, etv, efirst, ecount, emorton,
+                       escr, bx, lvl_dev, s);
+    } else {
+        uniform_boxes(keys, n, P->D, nb, bx, s);
+        P->lvl_host.assign(kMaxDepth + 2, nb);
+        long long tot = 0, sz = 1;
+        P->lvl_host[0] = 0;
+        for (int l = 0; l <= P->D; ++l) { tot += sz; sz *= 8; P->lvl_host[l + 1] = (int)tot; }
+        HIPCHK(hipMemcpyAsync(lvl_dev, P->lvl_host.data(), sizeof(int32_t) * (kMaxDepth + 2),
+                              hipMemcpyHostToDevice, s));
+    }
+    TreeArgs ta{bx, lvl_dev, P->D, nb};
+    int32_t *coll = P->temp<int32_t>(27ull * nb);
+    int64_t *cnt[4], *flg[4], *pos[4];
+    for (int w = 0; w < 4; ++w) { cnt[w] = P->temp<int64_t>(nb + 1); NOMEM(cnt[w]); }
+    for (int w = 0; w < 4; ++w) { flg[w] = P->temp<int64_t>(nb + 1); pos[w] = P->temp<int64_t>(nb + 1); NOMEM(flg[w]); NOMEM(pos[w]); }
+    int64_t *mscr = P->temp<int64_t>(scan_multi_scratch_bytes(nb, 8) / 8 + 1);
+    int32_t *mtg = P->temp<int32_t>(nb);
+    PlanSizes *sizes_dev = P->temp<PlanSizes>(1);
+    NOMEM(coll); NOMEM(mscr); NOMEM(mtg); NOMEM(sizes_dev);
     fill_i32(vslot, (int64_t)nb * kVSlots, -1, s);
     colleagues(ta, coll, s);
-    vlist(ta, coll, 0, cntV, nullptr, nullptr, nullptr, s);
-    uwlist(ta, coll, 0, cntU, nullptr, nullptr, cntW, nullptr, nullptr, s);
-    scan_exclusive(cntU, P->off[0], nb, scr, s);
-    scan_exclusive(cntV, P->off[1], nb, scr, s);
-    scan_exclusive(cntW, P->off[2], nb, scr, s);
-    int64_t tot[3];
-    if (copy_to_host(&tot[0], P->off[0] + nb, 1, s) || copy_to_host(&tot[1], P->off[1] + nb, 1, s) ||
-        copy_to_host(&tot[2], P->off[2] + nb, 1, s))
-        return FMM_EDEVICE;
-    int badh = 0;
-    if (copy_to_host(&badh, bad, 1, s)) return FMM_EDEVICE;
-    HIPCHK(hipStreamSynchronize(s));
-    if (badh) return fail(FMM_EINVAL, "non-finite coordinates");
-    P->nlist[0] = tot[0]; P->nlist[1] = tot[1]; P->nlist[2] = tot[2]; P->nlist[3] = tot[2];
-    for (int w = 0; w < 4; ++w) { P->src[w] = P->own<int32_t>(P->nlist[w] ? P->nlist[w] : 1); NOMEM(P->src[w]); }
-    vlist(ta, coll, 1, nullptr, P->off[1], P->src[1], vslot, s); // ascending by construction
-    uwlist(ta, coll, 1, nullptr, P->off[0], P->src[0], nullptr, P->off[2], P->src[2], s);
-    sort_segments(P->off[0], nb, P->src[0], s);
-    sort_segments(P->off[2], nb, P->src[2], s);
-    // X = transpose of W
-    HIPCHK(hipMemsetAsync(cntX, 0, sizeof(int64_t) * nb, s));
-    if (P->nlist[2] > 0) {
-        int64_t m = P->nlist[2];
-        uint64_t *wk = P->temp<uint64_t>(m), *wk2 = P->temp<uint64_t>(m);
-        int32_t *wv2 = P->temp<int32_t>(m), *wscr = P->temp<int32_t>(sort_scratch_bytes((int)m) / 4 + 1);
-        NOMEM(wk); NOMEM(wk2); NOMEM(wv2); NOMEM(wscr);
-        w_pairs(P->off[2], P->src[2], nb, wk, P->src[3], cntX, s);
-        int bits = 1;
-        while ((1LL << bits) < nb) ++bits;
-        radix_sort_pairs(wk, P->src[3], wk2, wv2, (int)m, bits, wscr, s);
+    vlist(ta, coll, 0, cnt[1], nullptr, nullptr, nullptr, s);
+    HIPCHK(hipMemsetAsync(cnt[3], 0, sizeof(int64_t) * nb, s));
+    uwlist(ta, coll, 0, cnt[0], nullptr, nullptr, cnt[2], nullptr, nullptr, cnt[3], s);
+    flags(bx, nb, cnt[3], cnt[1], flg[0], flg[1], flg[2], flg[3], s);
+    {
+        const int64_t *in[8] = {cnt[0], cnt[1], cnt[2], cnt[3], flg[0], flg[1], flg[2], flg[3]};
+        int64_t *out[8] = {P->off[0], P->off[1], P->off[2], P->off[3], pos[0], pos[1], pos[2], pos[3]};
+        scan_exclusive_multi(in, out, 8, nb, mscr, s);
     }
-    scan_exclusive(cntX, P->off[3], nb, scr, s);
-    // work lists: leaves, non-leaves, X targets, M2L targets
-    int64_t *flag = P->temp<int64_t>(nb), *pos = P->temp<int64_t>(nb + 1);
-    int64_t *flag2 = P->temp<int64_t>(nb), *pos2 = P->temp<int64_t>(nb + 1);
-    int64_t *flag3 = P->temp<int64_t>(nb), *pos3 = P->temp<int64_t>(nb + 1);
-    int64_t *flag4 = P->temp<int64_t>(nb), *pos4 = P->temp<int64_t>(nb + 1);
-    int32_t *leaves = P->own<int32_t>(nb), *nonleaf = P->own<int32_t>(nb), *xtgt = P->own<int32_t>(nb);
-    int32_t *mtg = P->temp<int32_t>(nb);
-    NOMEM(flag); NOMEM(pos); NOMEM(flag2); NOMEM(pos2); NOMEM(flag3); NOMEM(pos3); NOMEM(flag4); NOMEM(pos4);
-    NOMEM(leaves); NOMEM(nonleaf); NOMEM(xtgt); NOMEM(mtg);
-    flags(P->bx, nb, 0, nullptr, flag, s);
-    scan_exclusive(flag, pos, nb, scr, s);
-    compact(flag, pos, nb, leaves, s);
-    flags(P->bx, nb, 1, nullptr, flag2, s);
-    scan_exclusive(flag2, pos2, nb, scr, s);
-    compact(flag2, pos2, nb, nonleaf, s);
-    flags(P->bx, nb, 2, P->off[3], flag3, s);
-    scan_exclusive(flag3, pos3, nb, scr, s);
-    compact(flag3, pos3, nb, xtgt, s);
-    flags(P->bx, nb, 2, P->off[1], flag4, s);
-    scan_exclusive(flag4, pos4, nb, scr, s);
-    compact(flag4, pos4, nb, mtg, s);
-    std::vector<int64_t> posh(nb + 1);
-    int64_t cnts[3], xt = 0;
-    if (copy_to_host(posh.data(), pos2, nb + 1, s) || copy_to_host(&cnts[0], pos + nb, 1, s) ||
-        copy_to_host(&cnts[1], pos3 + nb, 1, s) || copy_to_host(&cnts[2], pos4 + nb, 1, s) ||
-        copy_to_host(&xt, P->off[3] + nb, 1, s))
-        return FMM_EDEVICE;
+    compact(flg[0], pos[0], nb, leaves, s);
+    compact(flg[1], pos[1], nb, nonleaf, s);
+    compact(flg[2], pos[2], nb, xtgt, s);
+    compact(flg[3], pos[3], nb, mtg, s);
+    k_collect_sizes<<<1, 64, 0, s>>>(P->off[0], P->off[1], P->off[2], P->off[3], pos[0], pos[1], pos[2], pos[3],
+                                     lvl_dev, root_dev, bad, nb, sizes_dev);
+    HIPCHK(hipGetLastError());
+    if (copy_to_host(&P->sizes, sizes_dev, 1, s)) return FMM_EDEVICE;
     HIPCHK(hipStreamSynchronize(s));
-    P->nleaves = (int)cnts[0];
-    P->nxtgt = (int)cnts[1];
-    const int nt = (int)cnts[2];
-    if (xt != P->nlist[3]) return fail(FMM_EDEVICE, "X list size mismatch");
-    P->lvl_nonleaf_off.assign(P->depth + 2, 0);
-    for (int l = 0; l <= P->depth + 1; ++l) {
-        int b = l < (int)P->lvl_begin.size() ? P->lvl_begin[l] : nb;
-        P->lvl_nonleaf_off[l] = (int)posh[std::min(b, nb)];
-    }
-    int32_t *lnl_off = P->own<int32_t>(P->depth + 2);
-    NOMEM(lnl_off);
-    HIPCHK(hipMemcpyAsync(lnl_off, P->lvl_nonleaf_off.data(), sizeof(int32_t) * (P->depth + 2),
-                          hipMemcpyHostToDevice, s));
-    // M2L target slots
+    const PlanSizes &Z = P->sizes;
+    if (Z.bad) return fail(FMM_EINVAL, "non-finite coordinates");
+    for (int k = 0; k < 4; ++k) P->root[k] = Z.root[k];
+    int depth = 0;
+    while (depth + 1 <= kMaxDepth && Z.lvl_begin[depth + 1] < nb) ++depth;
+    P->depth = depth;
+    P->lvl_begin.assign(Z.lvl_begin, Z.lvl_begin + depth + 2);
+    P->lvl_nonleaf_off.assign(depth + 2, 0);
+    for (int l = 0; l <= depth + 1; ++l) P->lvl_nonleaf_off[l] = (int)Z.lnl[l];
+    for (int w = 0; w < 4; ++w) P->nlist[w] = Z.tot[w];
+    if (Z.tot[2] != Z.tot[3]) return fail(FMM_EDEVICE, "X list size mismatch");
+    P->nleaves = (int)Z.nleaves;
+    P->nxtgt = (int)Z.nxtgt;
+    const int nt = (int)Z.nmtg;
+    // ---- phase C: list contents and M2L tiles (sizes known)
     int64_t slot_cap = ((int64_t)nt + 8 * (kM2LSlots - 1) + kM2LSlots - 1) / kM2LSlots * kM2LSlots;
     if (slot_cap < kM2LSlots) slot_cap = kM2LSlots;
+    const int64_t mw = P->nlist[2];
+    {
+        Sizer o;
+        for (int w = 0; w < 4; ++w) o.add<int32_t>(P->nlist[w] ? P->nlist[w] : 1);
+        o.add<int32_t>(slot_cap);
+        if (!P->reserve(true, o.total)) return fail(FMM_ENOMEM, "device allocation failed (list arrays)");
+        Sizer t;
+        if (mw > 0) t.add<uint64_t>(mw).add<uint64_t>(mw).add<int32_t>(mw).add<int32_t>(sort_scratch_bytes((int)mw) / 4 + 1);
+        t.add<int>(32).add<uint64_t>(nt + 1).add<uint64_t>(nt + 1).add<int32_t>(nt + 1).add<int32_t>(nt + 1)
+         .add<int32_t>(sort_scratch_bytes(nt + 1) / 4 + 1);
+        if (!P->reserve(false, t.total)) return fail(FMM_ENOMEM, "device allocation failed (list temporaries)");
+    }
+    for (int w = 0; w < 4; ++w) { P->src[w] = P->own<int32_t>(P->nlist[w] ? P->nlist[w] : 1); NOMEM(P->src[w]); }
     int32_t *slots = P->own<int32_t>(slot_cap);
+    NOMEM(slots);
+    vlist(ta, coll, 1, nullptr, P->off[1], P->src[1], vslot, s); // ascending by construction
+    uwlist(ta, coll, 1, nullptr, P->off[0], P->src[0], nullptr, P->off[2], P->src[2], nullptr, s);
+    if (mw > 0) { // X = transpose of W
+        uint64_t *wk = P->temp<uint64_t>(mw), *wk2 = P->temp<uint64_t>(mw);
+        int32_t *wv2 = P->temp<int32_t>(mw), *wscr = P->temp<int32_t>(sort_scratch_bytes((int)mw) / 4 + 1);
+        NOMEM(wk); NOMEM(wk2); NOMEM(wv2); NOMEM(wscr);
+        w_pairs(P->off[2], P->src[2], nb, wk, P->src[3], s);
+        int bits = 1;
+        while ((1LL << bits) < nb) ++bits;
+        radix_sort_pairs(wk, P->src[3], wk2, wv2, (int)mw, bits, wscr, s);
+    }
+    P->lvl_host.assign(P->lvl_nonleaf_off.begin(), P->lvl_nonleaf_off.end());
+    HIPCHK(hipMemcpyAsync(lnl_off, P->lvl_host.data(), sizeof(int32_t) * (depth + 2), hipMemcpyHostToDevice, s));
     int *octoff = P->temp<int>(32);
     uint64_t *okey = P->temp<uint64_t>(nt + 1), *otk = P->temp<uint64_t>(nt + 1);
     int32_t *oval = P->temp<int32_t>(nt + 1), *otv = P->temp<int32_t>(nt + 1);
     int32_t *oscr = P->temp<int32_t>(sort_scratch_bytes(nt + 1) / 4 + 1);
-    NOMEM(slots); NOMEM(octoff); NOMEM(okey); NOMEM(otk); NOMEM(oval); NOMEM(otv); NOMEM(oscr);
-    m2l_tiles(P->bx, mtg, nt, okey, oval, otk, otv, oscr, octoff, slots, slot_cap, s);
+    NOMEM(octoff); NOMEM(okey); NOMEM(otk); NOMEM(oval); NOMEM(otv); NOMEM(oscr);
+    m2l_tiles(bx, mtg, nt, okey, oval, otk, otv, oscr, octoff, slots, slot_cap, s);
     P->nslots = (int)slot_cap;
-    // evaluation buffers
-    double *qs = P->own<double>(n), *pf = P->own<double>(n), *ff = P->own<double>(3ull * n);
-    double *M = P->own<double>((size_t)nb * P->ldm), *L = P->own<double>((size_t)nb * P->ldm);
-    double *Mh = P->own<double>((size_t)nb * P->ldh), *Lh = P->own<double>((size_t)nb * P->ldh);
-    float *Mhf = P->mixed_m2l ? P->own<float>((size_t)nb * P->ldh) : nullptr;
-    NOMEM(qs); NOMEM(pf); NOMEM(ff); NOMEM(M); NOMEM(L); NOMEM(Mh); NOMEM(Lh);
-    if (P->mixed_m2l) NOMEM(Mhf);
-    P->view_dev = P->own<PlanView>(1);
-    NOMEM(P->view_dev);
 
     PlanView &v = P->view;
     v.p = P->p; v.nc = P->nc; v.nh = P->nh; v.ldm = P->ldm; v.ldh = P->ldh;
@@ -371,8 +402,8 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     v.n = n; v.nboxes = nb; v.nleaves = P->nleaves; v.nxtgt = P->nxtgt; v.nslots = P->nslots;
     for (int k = 0; k < 3; ++k) v.lo[k] = P->root[k];
     v.W = P->root[3];
-    v.level = P->bx.level; v.parent = P->bx.parent; v.child_begin = P->bx.child_begin;
-    v.nchild = P->bx.nchild; v.first = P->bx.first; v.count = P->bx.count; v.morton = P->bx.morton;
+    v.level = bx.level; v.parent = bx.parent; v.child_begin = bx.child_begin;
+    v.nchild = bx.nchild; v.first = bx.first; v.count = bx.count; v.morton = bx.morton;
     v.perm = P->perm; v.xs = xs; v.ys = ys; v.zs = zs;
     v.U_off = P->off[0]; v.V_off = P->off[1]; v.W_off = P->off[2]; v.X_off = P->off[3];
     v.U_src = P->src[0]; v.W_src = P->src[2]; v.X_src = P->src[3];
@@ -380,7 +411,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     v.lvl_nonleaf = nonleaf; v.lvl_nonleaf_off = lnl_off; v.tab = P->tab;
     v.qs = qs; v.M = M; v.Mh = Mh; v.Lh = Lh; v.L = L; v.Mhf = Mhf; v.phi_far = pf; v.fld_far = ff;
     HIPCHK(hipMemcpyAsync(P->view_dev, &v, sizeof(PlanView), hipMemcpyHostToDevice, s));
-    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
     P->release_temps();
     HIPCHK(hipStreamSynchronize(s));
     return 0;

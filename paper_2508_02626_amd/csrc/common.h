@@ -49,6 +49,16 @@ __host__ __device__ constexpr int dlayout_s2(int p) { return (2 * p + 1) * (2 * 
 __host__ __device__ constexpr int dlayout_ldd(int p) { return (3 * dlayout_s2(p) + 1) & ~1; }
 inline int pad4(int n) { return (n + 3) & ~3; }
 
+// LDS exchange between the lanes of one wavefront (no workgroup barrier: the
+// wavefronts of a block run independent loops)
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ inline uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
+
 // Morton codes: bit b of the x, y, z cell index sits at code bits 3b+2, 3b+1, 3b.
 __host__ __device__ inline void deinterleave(uint64_t code, int l, int c[3])
 {

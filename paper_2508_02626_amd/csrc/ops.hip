@@ -17,15 +17,6 @@
 
 namespace fmm {
 
-// LDS exchange between the lanes of one wavefront (no workgroup barrier: the
-// four wavefronts of a P2P block run independent loops)
-__device__ inline void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ inline void box_geom(const PlanView &v, int b, double cen[3], double &h)
 {
     int l = v.level[b], c[3];

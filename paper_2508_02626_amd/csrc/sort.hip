@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_block_sums(const T *in, int64
 
 // one block scans the block sums in place (exclusive), total at sums[nb]
 template <typename T>
-__global__ __launch_bounds__(1024) void k_scan_sums(T *sums, int nb)
+__device__ inline void k_scan_sums_body(T *sums, int nb)
 {
     __shared__ T sh[1024];
     __shared__ T carry;
@@ -66,8 +66,7 @@ __global__ __launch_bounds__(1024) void k_scan_sums(T *sums, int nb)
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scan_apply(const T *in, int64_t n, const T *sums,
-                                                         T *out, int write_total)
+__device__ inline void k_scan_apply_body(const T *in, int64_t n, const T *sums, T *out, int write_total)
 {
     __shared__ T sh[kThreads];
     int64_t base = (int64_t)blockIdx.x * kTile;
@@ -94,6 +93,74 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const T *in, int64_t n,
     }
     if (write_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == kThreads - 1)
         out[n] = sums[gridDim.x];
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan_sums(T *sums, int nb)
+{
+    k_scan_sums_body(sums, nb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scan_apply(const T *in, int64_t n, const T *sums,
+                                                         T *out, int write_total)
+{
+    k_scan_apply_body(in, n, sums, out, write_total);
+}
+
+// Several scans of equal length in one set of launches (blockIdx.y = scan).
+struct ScanBatch {
+    const int64_t *in[kMaxScanBatch];
+    int64_t *out[kMaxScanBatch];
+};
+
+__global__ __launch_bounds__(kThreads) void k_scan_block_sums_m(ScanBatch sb, int64_t n, int64_t *sums,
+                                                                 int64_t stride)
+{
+    __shared__ int64_t sh[kWaves];
+    const int64_t *in = sb.in[blockIdx.y];
+    int64_t base = (int64_t)blockIdx.x * kTile;
+    int64_t s = 0;
+    for (int r = 0; r < kItems; ++r) {
+        int64_t i = base + r * kThreads + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < kWaves; ++w) t += sh[w];
+        sums[blockIdx.y * stride + blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums_m(int64_t *sums, int nb, int64_t stride)
+{
+    k_scan_sums_body(sums + blockIdx.x * stride, nb);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_apply_m(ScanBatch sb, int64_t n, const int64_t *sums,
+                                                           int64_t stride)
+{
+    k_scan_apply_body(sb.in[blockIdx.y], n, sums + blockIdx.y * stride, sb.out[blockIdx.y], 1);
+}
+
+size_t scan_multi_scratch_bytes(int64_t n, int count)
+{
+    return sizeof(int64_t) * (ceil_div(n > 0 ? n : 1, kTile) + 2) * (size_t)count;
+}
+
+void scan_exclusive_multi(const int64_t *const *in, int64_t *const *out, int count, int64_t n,
+                          int64_t *scratch, hipStream_t s)
+{
+    ScanBatch sb{};
+    for (int i = 0; i < count; ++i) { sb.in[i] = in[i]; sb.out[i] = out[i]; }
+    unsigned nb = ceil_div(n > 0 ? n : 1, kTile);
+    int64_t stride = nb + 2;
+    k_scan_block_sums_m<<<dim3(nb, count), kThreads, 0, s>>>(sb, n, scratch, stride);
+    k_scan_sums_m<<<count, 1024, 0, s>>>(scratch, (int)nb, stride);
+    k_scan_apply_m<<<dim3(nb, count), kThreads, 0, s>>>(sb, n, scratch, stride);
 }
 
 size_t scan_scratch_bytes(int64_t n) { return sizeof(int64_t) * (ceil_div(n > 0 ? n : 1, kTile) + 2); }

@@ -19,34 +19,29 @@ struct TreeArgs {
 };
 
 void bbox(const double *xyz, int n, double *part, double *root, hipStream_t s);
-void morton_keys(const double *xyz, int n, const double root[4], int D, uint64_t *keys,
+void morton_keys(const double *xyz, int n, const double *root_dev, int D, uint64_t *keys,
                  int32_t *idx, int *bad, hipStream_t s);
 void gather_sorted(const double *xyz, const int32_t *perm, int n, double *xs, double *ys,
                    double *zs, hipStream_t s);
 void uniform_boxes(const uint64_t *keys, int n, int D, int nboxes, BoxArrays bx, hipStream_t s);
-void root_box(int n, BoxArrays bx, hipStream_t s);
-void count_children(const uint64_t *keys, int D, int l, int lb, int le, int leaf_size,
-                    BoxArrays bx, int64_t *nch, hipStream_t s);
-void fill_children(const uint64_t *keys, int D, int l, int lb, int le, const int64_t *off,
-                   BoxArrays bx, hipStream_t s);
+// adaptive tree: boxes emitted per particle (count, then fill after a scan)
+void emit_count(const uint64_t *keys, int n, int D, int leaf_size, int64_t *cnt, hipStream_t s);
+void adaptive_boxes(const uint64_t *keys, int n, int D, int leaf_size, const int64_t *off, int nb,
+                    uint64_t *elevel, int32_t *eidx, uint64_t *tk, int32_t *tv, int32_t *efirst,
+                    int32_t *ecount, uint64_t *emorton, int32_t *sort_scratch, BoxArrays bx,
+                    int32_t *lvl_begin, hipStream_t s);
 void colleagues(const TreeArgs &a, int32_t *coll, hipStream_t s);
 void vlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *cnt, const int64_t *off,
            int32_t *src, int32_t *vslot, hipStream_t s);
 void uwlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *ucnt, const int64_t *uoff,
-            int32_t *usrc, int64_t *wcnt, const int64_t *woff, int32_t *wsrc, hipStream_t s);
-void sort_segments(const int64_t *off, int nseg, int32_t *v, hipStream_t s);
-void w_pairs(const int64_t *woff, const int32_t *wsrc, int nboxes, uint64_t *key, int32_t *val,
-             int64_t *xcnt, hipStream_t s);
-void flags(const BoxArrays &bx, int nboxes, int what, const int64_t *off, int64_t *flag,
-           hipStream_t s);
+            int32_t *usrc, int64_t *wcnt, const int64_t *woff, int32_t *wsrc, int64_t *xcnt, hipStream_t s);
+void w_pairs(const int64_t *woff, const int32_t *wsrc, int nboxes, uint64_t *key, int32_t *val, hipStream_t s);
+void flags(const BoxArrays &bx, int nboxes, const int64_t *xcnt, const int64_t *vcnt, int64_t *fleaf,
+           int64_t *fnon, int64_t *fx, int64_t *fv, hipStream_t s);
 void compact(const int64_t *flag, const int64_t *pos, int nboxes, int32_t *out, hipStream_t s);
-void leaf_of(const BoxArrays &bx, const int32_t *leaves, int nleaves, int32_t *lo, hipStream_t s);
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 void m2l_tiles(const BoxArrays &bx, const int32_t *tg, int nt, uint64_t *key, int32_t *val,
                uint64_t *tk, int32_t *tv, int32_t *sort_scratch, int *octoff, int32_t *slots,
                int64_t slot_cap, hipStream_t s);
-void local_split(const double *xs, const double *ys, const double *zs, const int32_t *leaf_of,
-                 const BoxArrays &bx, int n, const double root[4], float *ux, float *uy, float *uz,
-                 float *vx, float *vy, float *vz, hipStream_t s);
 
 } // namespace fmm

@@ -43,15 +43,20 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const double *xyz, int n, 
     if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-__global__ void k_bbox_final(const double *part, int nb, double *root)
+__global__ __launch_bounds__(64) void k_bbox_final(const double *part, int nb, double *root)
 {
-    if (threadIdx.x != 0) return;
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = 0; b < nb; ++b)
+    for (int b = threadIdx.x; b < nb; b += 64)
         for (int k = 0; k < 3; ++k) {
             mn[k] = fmin(mn[k], part[6 * b + k]);
             mx[k] = fmax(mx[k], part[6 * b + 3 + k]);
         }
+    for (int o = 32; o > 0; o >>= 1)
+        for (int k = 0; k < 3; ++k) {
+            mn[k] = fmin(mn[k], __shfl_xor(mn[k], o));
+            mx[k] = fmax(mx[k], __shfl_xor(mx[k], o));
+        }
+    if (threadIdx.x != 0) return;
     double W = 0.0;
     for (int k = 0; k < 3; ++k) {
         root[k] = mn[k];
@@ -69,13 +74,13 @@ void bbox(const double *xyz, int n, double *part, double *root, hipStream_t s)
     k_bbox_final<<<1, 64, 0, s>>>(part, nb, root);
 }
 
-__global__ __launch_bounds__(256) void k_keys(const double *xyz, int n, double lo0, double lo1,
-                                              double lo2, double scale, int D, uint64_t *keys,
-                                              int32_t *idx, int *bad)
+__global__ __launch_bounds__(256) void k_keys(const double *xyz, int n, const double *root, int D,
+                                              uint64_t *keys, int32_t *idx, int *bad)
 {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    double lo[3] = {lo0, lo1, lo2};
+    const double lo[3] = {root[0], root[1], root[2]};
+    const double scale = (double)(1ll << D) / root[3]; // correctly rounded, as on the host
     double gmax = (double)((1ll << D) - 1);
     int g[3];
     bool finite = true;
@@ -93,11 +98,10 @@ __global__ __launch_bounds__(256) void k_keys(const double *xyz, int n, double l
     idx[i] = i;
 }
 
-void morton_keys(const double *xyz, int n, const double root[4], int D, uint64_t *keys,
+void morton_keys(const double *xyz, int n, const double *root_dev, int D, uint64_t *keys,
                  int32_t *idx, int *bad, hipStream_t s)
 {
-    double scale = std::ldexp(1.0, D) / root[3];
-    k_keys<<<ceil_div(n, 256), 256, 0, s>>>(xyz, n, root[0], root[1], root[2], scale, D, keys, idx, bad);
+    k_keys<<<ceil_div(n, 256), 256, 0, s>>>(xyz, n, root_dev, D, keys, idx, bad);
 }
 
 __global__ __launch_bounds__(256) void k_gather_sorted(const double *xyz, const int32_t *perm, int n,
@@ -159,73 +163,154 @@ void uniform_boxes(const uint64_t *keys, int n, int D, int nboxes, BoxArrays bx,
     k_uniform_boxes<<<ceil_div(nboxes, 256), 256, 0, s>>>(keys, n, D, nboxes, bx);
 }
 
-__global__ void k_root_box(int n, BoxArrays bx)
+// Adaptive tree straight from the sorted keys, with no host round trip per
+// level.  The boxes of level l are the runs of equal level-l key prefixes
+// inside boxes of level l-1 that split; a box of level l exists iff the run
+// of level l-1 around it holds more than s particles (counts only shrink
+// down the tree, so this also covers every older ancestor).  Particle i
+// starts a run at every level from first_new_level(i) down, so it emits the
+// boxes of those levels whose parent run exceeds s, down to the first run
+// that holds at most s particles (or level D).
+__device__ inline int first_new_level(uint64_t prev, uint64_t cur, int D)
 {
-    bx.level[0] = 0; bx.morton[0] = 0; bx.first[0] = 0; bx.count[0] = n;
-    bx.parent[0] = -1; bx.child_begin[0] = -1; bx.nchild[0] = 0;
+    uint64_t x = prev ^ cur;
+    if (x == 0) return D + 1;
+    return D - (63 - __clzll((long long)x)) / 3;
 }
 
-// adaptive: number of non-empty children of each box of [lb, le) that splits
-__global__ __launch_bounds__(256) void k_count_children(const uint64_t *keys, int D, int l, int lb,
-                                                        int le, int leaf_size, BoxArrays bx,
-                                                        int64_t *nch)
+// true iff the level-l run containing particle i holds more than s particles
+// (both searches are clamped to s elements on either side of i)
+__device__ inline bool run_exceeds(const uint64_t *keys, int n, int i, int l, int D, int s)
 {
-    int b = lb + blockIdx.x * 256 + threadIdx.x;
-    if (b >= le) return;
-    int c = 0;
-    if (bx.count[b] > leaf_size && l < D) {
-        int f = bx.first[b], e = f + bx.count[b];
-        int sh = 3 * (D - l - 1);
-        uint64_t m = bx.morton[b];
-        int s = f;
-        for (int o = 0; o < 8; ++o) {
-            uint64_t code = m * 8 + (uint64_t)o;
-            int t = lower_bound_key(keys, s, e, (code + 1) << sh);
-            if (t > s) ++c;
-            s = t;
+    const int sh = 3 * (D - l);
+    const uint64_t pre = keys[i] >> sh;
+    int a = lower_bound_key(keys, i - s > 0 ? i - s : 0, i, pre << sh);
+    int b = lower_bound_key(keys, i + 1, i + s + 1 < n ? i + s + 1 : n, (pre + 1) << sh);
+    return b - a > s;
+}
+
+template <bool FILL>
+__device__ int emit_boxes(const uint64_t *keys, int n, int D, int s, int i, int64_t pos,
+                          uint64_t *elevel, int32_t *eidx, int32_t *efirst, int32_t *ecount,
+                          uint64_t *emorton)
+{
+    int l = i == 0 ? 0 : first_new_level(keys[i - 1], keys[i], D);
+    if (l > D) return 0;
+    if (l > 0 && !run_exceeds(keys, n, i, l - 1, D, s)) return 0;
+    int cnt = 0, hi = n;
+    for (;; ++l) {
+        const int sh = 3 * (D - l);
+        const uint64_t pre = keys[i] >> sh, lim = (pre + 1) << sh;
+        const int w = i + s + 1 < hi ? i + s + 1 : hi;
+        int e = lower_bound_key(keys, i + 1, w, lim);
+        if (e == w && w < hi) e = lower_bound_key(keys, w, hi, lim);
+        if (FILL) {
+            int64_t k = pos + cnt;
+            elevel[k] = (uint64_t)l;
+            eidx[k] = (int32_t)k;
+            efirst[k] = i;
+            ecount[k] = e - i;
+            emorton[k] = pre;
         }
+        ++cnt;
+        if (e - i <= s || l == D) break;
+        hi = e;
     }
-    nch[b - lb] = c;
+    return cnt;
 }
 
-__global__ __launch_bounds__(256) void k_fill_children(const uint64_t *keys, int D, int l, int lb,
-                                                       int le, const int64_t *off, BoxArrays bx)
+__global__ __launch_bounds__(256) void k_emit_count(const uint64_t *keys, int n, int D, int s, int64_t *cnt)
 {
-    int b = lb + blockIdx.x * 256 + threadIdx.x;
-    if (b >= le) return;
-    int cnt = (int)(off[b - lb + 1] - off[b - lb]);
-    if (cnt == 0) { bx.child_begin[b] = -1; bx.nchild[b] = 0; return; }
-    int cb = le + (int)off[b - lb];
-    bx.child_begin[b] = cb;
-    bx.nchild[b] = cnt;
-    int f = bx.first[b], e = f + bx.count[b];
-    int sh = 3 * (D - l - 1);
-    uint64_t m = bx.morton[b];
-    int s = f, k = 0;
-    for (int o = 0; o < 8; ++o) {
-        uint64_t code = m * 8 + (uint64_t)o;
-        int t = lower_bound_key(keys, s, e, (code + 1) << sh);
-        if (t > s) {
-            int c = cb + k++;
-            bx.level[c] = l + 1; bx.morton[c] = code; bx.first[c] = s; bx.count[c] = t - s;
-            bx.parent[c] = b; bx.child_begin[c] = -1; bx.nchild[c] = 0;
-        }
-        s = t;
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    cnt[i] = emit_boxes<false>(keys, n, D, s, i, 0, nullptr, nullptr, nullptr, nullptr, nullptr);
+}
+
+__global__ __launch_bounds__(256) void k_emit_fill(const uint64_t *keys, int n, int D, int s,
+                                                   const int64_t *off, uint64_t *elevel, int32_t *eidx,
+                                                   int32_t *efirst, int32_t *ecount, uint64_t *emorton)
+{
+    int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    emit_boxes<true>(keys, n, D, s, i, off[i], elevel, eidx, efirst, ecount, emorton);
+}
+
+// boxes in (level, Morton) order: the emitted boxes stably sorted by level
+// (within a level they were emitted in particle order, i.e. Morton order)
+__global__ __launch_bounds__(256) void k_box_place(const uint64_t *elevel, const int32_t *eidx, int nb,
+                                                   const int32_t *efirst, const int32_t *ecount,
+                                                   const uint64_t *emorton, BoxArrays bx)
+{
+    int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nb) return;
+    int e = eidx[b];
+    bx.level[b] = (int32_t)elevel[b];
+    bx.first[b] = efirst[e];
+    bx.count[b] = ecount[e];
+    bx.morton[b] = emorton[e];
+}
+
+// lvl_begin[l] = first box of level l (nb for levels below the deepest)
+__global__ __launch_bounds__(256) void k_level_bounds(const int32_t *level, int nb, int32_t *lvl_begin)
+{
+    int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nb) return;
+    int l = level[b];
+    int from = b == 0 ? 0 : level[b - 1] + 1;
+    for (int k = from; k <= l; ++k) lvl_begin[k] = b;
+    if (b == nb - 1)
+        for (int k = l + 1; k <= kMaxDepth + 1; ++k) lvl_begin[k] = nb;
+}
+
+__device__ inline int lower_bound_first(const int32_t *first, int lo, int hi, int v)
+{
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (first[mid] < v) lo = mid + 1; else hi = mid;
     }
+    return lo;
 }
 
-void root_box(int n, BoxArrays bx, hipStream_t s) { k_root_box<<<1, 1, 0, s>>>(n, bx); }
-
-void count_children(const uint64_t *keys, int D, int l, int lb, int le, int leaf_size,
-                    BoxArrays bx, int64_t *nch, hipStream_t s)
+// parent: the box of the level above whose particle range contains this
+// box's first particle; children: the boxes of the level below that start
+// inside this box's range (contiguous)
+__global__ __launch_bounds__(256) void k_box_links(BoxArrays bx, int nb, const int32_t *lvl_begin)
 {
-    k_count_children<<<ceil_div(le - lb, 256), 256, 0, s>>>(keys, D, l, lb, le, leaf_size, bx, nch);
+    int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= nb) return;
+    const int l = bx.level[b], f = bx.first[b], c = bx.count[b];
+    if (l == 0) {
+        bx.parent[b] = -1;
+    } else {
+        int lo = lvl_begin[l - 1], hi = lvl_begin[l];
+        bx.parent[b] = lower_bound_first(bx.first, lo, hi, f + 1) - 1;
+    }
+    int c0 = 0, c1 = 0;
+    if (l < kMaxDepth) {
+        int lo = lvl_begin[l + 1], hi = lvl_begin[l + 2];
+        c0 = lower_bound_first(bx.first, lo, hi, f);
+        c1 = lower_bound_first(bx.first, c0, hi, f + c);
+    }
+    bx.child_begin[b] = c1 > c0 ? c0 : -1;
+    bx.nchild[b] = c1 - c0;
 }
 
-void fill_children(const uint64_t *keys, int D, int l, int lb, int le, const int64_t *off,
-                   BoxArrays bx, hipStream_t s)
+void emit_count(const uint64_t *keys, int n, int D, int leaf_size, int64_t *cnt, hipStream_t s)
 {
-    k_fill_children<<<ceil_div(le - lb, 256), 256, 0, s>>>(keys, D, l, lb, le, off, bx);
+    k_emit_count<<<ceil_div(n, 256), 256, 0, s>>>(keys, n, D, leaf_size, cnt);
+}
+
+void adaptive_boxes(const uint64_t *keys, int n, int D, int leaf_size, const int64_t *off, int nb,
+                    uint64_t *elevel, int32_t *eidx, uint64_t *tk, int32_t *tv, int32_t *efirst,
+                    int32_t *ecount, uint64_t *emorton, int32_t *sort_scratch, BoxArrays bx,
+                    int32_t *lvl_begin, hipStream_t s)
+{
+    k_emit_fill<<<ceil_div(n, 256), 256, 0, s>>>(keys, n, D, leaf_size, off, elevel, eidx, efirst, ecount,
+                                                 emorton);
+    radix_sort_pairs(elevel, eidx, tk, tv, nb, 5, sort_scratch, s);
+    k_box_place<<<ceil_div(nb, 256), 256, 0, s>>>(elevel, eidx, nb, efirst, ecount, emorton, bx);
+    k_level_bounds<<<ceil_div(nb, 256), 256, 0, s>>>(bx.level, nb, lvl_begin);
+    k_box_links<<<ceil_div(nb, 256), 256, 0, s>>>(bx, nb, lvl_begin);
 }
 
 // ---------------- lists ----------------
@@ -259,203 +344,318 @@ __device__ inline bool adjacent(const TreeView &t, int a, int b)
     return true;
 }
 
+// The list kernels give one wavefront to each box (four boxes per block).
+
+// Colleagues: the up to 27 same-level boxes adjacent to b (b included),
+// ascending, padded with -1.  Lane j < 27 looks up neighbour cell j.
 __global__ __launch_bounds__(256) void k_colleagues(TreeView t, int32_t *coll)
 {
-    int b = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= t.nboxes) return;
-    int l = t.bx.level[b], c[3], nb[3], side = 1 << l, m = 0;
+    const int l = t.bx.level[b], side = 1 << l;
+    int c[3];
     deinterleave(t.bx.morton[b], l, c);
-    for (int dx = -1; dx <= 1; ++dx)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dz = -1; dz <= 1; ++dz) {
-                nb[0] = c[0] + dx; nb[1] = c[1] + dy; nb[2] = c[2] + dz;
-                int f = -1;
-                if (nb[0] >= 0 && nb[1] >= 0 && nb[2] >= 0 && nb[0] < side && nb[1] < side && nb[2] < side)
-                    f = find_box(t, l, interleave(nb, l));
-                if (f >= 0) { // insert keeping ascending box numbers
-                    int j = m++;
-                    while (j > 0 && coll[27 * b + j - 1] > f) { coll[27 * b + j] = coll[27 * b + j - 1]; --j; }
-                    coll[27 * b + j] = f;
-                }
-            }
-    for (; m < 27; ++m) coll[27 * b + m] = -1;
+    int f = INT_MAX;
+    if (lane < 27) {
+        int nb[3] = {c[0] + lane / 9 - 1, c[1] + (lane / 3) % 3 - 1, c[2] + lane % 3 - 1};
+        if (nb[0] >= 0 && nb[1] >= 0 && nb[2] >= 0 && nb[0] < side && nb[1] < side && nb[2] < side) {
+            int g = find_box(t, l, interleave(nb, l));
+            if (g >= 0) f = g;
+        }
+    }
+    int rank = 0;
+    for (int k = 0; k < 27; ++k) rank += __shfl(f, k) < f;
+    const int found = __popcll(__ballot(f != INT_MAX));
+    if (f != INT_MAX) coll[27 * b + rank] = f;    // ranks fill [0, found)
+    if (lane >= found && lane < 27) coll[27 * b + lane] = -1;
 }
 
 // which: 0 count, 1 fill.  V for boxes of level >= 2: children of the
 // parent's colleagues that are not adjacent (same level, so adjacency is
-// max |delta| <= 1 in cell coordinates).  Colleagues are sorted and children
-// are consecutive, so the list comes out ascending.  The fill pass also
-// records each source in the box's M2L slot row (offset slot, Sec. 3.4).
+// max |delta| <= 1 in cell coordinates).  Lane j of a round looks at child
+// j % 8 of colleague j / 8; colleagues are ascending and children
+// consecutive, so compaction in lane order gives an ascending list.  The fill
+// pass also records each source in the box's M2L slot row (Sec. 3.4).
 __global__ __launch_bounds__(256) void k_vlist(TreeView t, const int32_t *coll, int which,
                                                int64_t *cnt, const int64_t *off, int32_t *src,
                                                int32_t *vslot)
 {
-    int b = blockIdx.x * 256 + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= t.nboxes) return;
     int n = 0;
-    int64_t o = which ? off[b] : 0;
     const int l = t.bx.level[b];
     if (l >= 2) {
-        int cb[3], cc[3];
+        const int64_t o = which ? off[b] : 0;
+        int cb[3];
         deinterleave(t.bx.morton[b], l, cb);
         const int oct = (int)(t.bx.morton[b] & 7);
         const int pb = t.bx.parent[b];
-        for (int i = 0; i < 27; ++i) {
-            int c = coll[27 * pb + i];
-            if (c < 0) break;
-            deinterleave(t.bx.morton[c], l - 1, cc);
-            for (int k = 0; k < t.bx.nchild[c]; ++k) {
-                int d = t.bx.child_begin[c] + k;
-                int od = (int)(t.bx.morton[d] & 7);
-                int dx = 2 * cc[0] + ((od >> 2) & 1) - cb[0];
-                int dy = 2 * cc[1] + ((od >> 1) & 1) - cb[1];
-                int dz = 2 * cc[2] + (od & 1) - cb[2];
-                if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
-                if (which) {
-                    src[o + n] = d;
-                    int sl = vslot_of(oct, -dx, -dy, -dz); // offset = target - source
-                    if (sl >= 0) vslot[(int64_t)b * kVSlots + sl] = d;
+        for (int base = 0; base < 27 * 8; base += 64) {
+            const int j = base + lane, i = j >> 3, k = j & 7;
+            bool sel = false;
+            int d = -1, dx = 0, dy = 0, dz = 0;
+            if (i < 27) {
+                int c = coll[27 * pb + i];
+                if (c >= 0 && k < t.bx.nchild[c]) {
+                    d = t.bx.child_begin[c] + k;
+                    int cd[3];
+                    deinterleave(t.bx.morton[d], l, cd);
+                    dx = cd[0] - cb[0]; dy = cd[1] - cb[1]; dz = cd[2] - cb[2];
+                    sel = dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1;
                 }
-                ++n;
             }
+            const uint64_t m = __ballot(sel);
+            if (sel && which) {
+                src[o + n + __popcll(m & lanes_below(lane))] = d;
+                int sl = vslot_of(oct, -dx, -dy, -dz); // offset = target - source
+                if (sl >= 0) vslot[(int64_t)b * kVSlots + sl] = d;
+            }
+            n += __popcll(m);
         }
     }
-    if (!which) cnt[b] = n;
+    if (!which && lane == 0) cnt[b] = n;
 }
 
-// U (P2P) and W (M2P) for leaves, by walking colleagues and their descendants.
-constexpr int kStack = 8 * (kMaxDepth + 1) + 8;
+// U (P2P) and W (M2P) for leaves.  U(b): the leaves adjacent to b (b
+// included); W(b): boxes not adjacent to b whose parent is adjacent to b and
+// that descend from a colleague of b.  A wavefront walks the adjacent
+// descendants of b's colleagues breadth-first through an LDS stack (64
+// entries per step), then adds the coarser adjacent leaves (colleagues of
+// b's ancestors); both lists are collected in LDS and written ascending.  A
+// walk that would overflow the LDS buffers is redone by one lane with a
+// private depth-first stack.  The count pass also counts the X lists
+// (X = transpose of W).
+constexpr int kUWStack = 512, kUWBuf = 512;
+constexpr int kSerialStack = 8 * (kMaxDepth + 1) + 8;
 
-__global__ __launch_bounds__(128) void k_uwlist(TreeView t, const int32_t *coll, int which,
-                                                int64_t *ucnt, const int64_t *uoff, int32_t *usrc,
-                                                int64_t *wcnt, const int64_t *woff, int32_t *wsrc)
+struct Cell { long long x[3], side; };
+
+__device__ inline Cell cell_of(const TreeView &t, int a)
 {
-    int b = blockIdx.x * 128 + threadIdx.x;
-    if (b >= t.nboxes) return;
-    int nu = 0, nw = 0;
-    if (t.bx.nchild[b] == 0) {
-        int64_t uo = which ? uoff[b] : 0, wo = which ? woff[b] : 0;
-        int stack[kStack];
-        for (int i = 0; i < 27; ++i) {
-            int c = coll[27 * b + i];
-            if (c < 0) break;
-            // U: descend through adjacent boxes down to leaves
-            int sp = 0;
-            stack[sp++] = c;
-            while (sp > 0) {
-                int x = stack[--sp];
-                if (t.bx.nchild[x] == 0) {
-                    if (which) usrc[uo + nu] = x;
-                    ++nu;
-                    continue;
-                }
-                for (int k = t.bx.nchild[x] - 1; k >= 0; --k) {
-                    int d = t.bx.child_begin[x] + k;
-                    if (adjacent(t, d, b)) stack[sp++] = d;
-                }
-            }
-            // W: descendants not adjacent whose parent is adjacent
-            if (c == b) continue;
-            sp = 0;
-            if (t.bx.nchild[c] > 0) stack[sp++] = c;
-            while (sp > 0) {
-                int x = stack[--sp];
-                for (int k = t.bx.nchild[x] - 1; k >= 0; --k) {
-                    int d = t.bx.child_begin[x] + k;
-                    if (!adjacent(t, d, b)) {
-                        if (which) wsrc[wo + nw] = d;
-                        ++nw;
-                    } else if (t.bx.nchild[d] > 0) {
-                        stack[sp++] = d;
-                    }
-                }
-            }
-        }
-        // U, coarser leaves: colleagues of ancestors that are leaves and adjacent
-        for (int a = t.bx.parent[b]; a >= 0; a = t.bx.parent[a])
-            for (int i = 0; i < 27; ++i) {
-                int c = coll[27 * a + i];
-                if (c < 0) break;
-                if (c != a && t.bx.nchild[c] == 0 && adjacent(t, c, b)) {
-                    if (which) usrc[uo + nu] = c;
-                    ++nu;
-                }
-            }
-    }
-    if (!which) { ucnt[b] = nu; wcnt[b] = nw; }
+    Cell c;
+    int ca[3], la = t.bx.level[a];
+    deinterleave(t.bx.morton[a], la, ca);
+    c.side = 1ll << (t.D - la);
+    for (int k = 0; k < 3; ++k) c.x[k] = ca[k] * c.side;
+    return c;
 }
 
-// ascending order inside every CSR segment (insertion sort, segments are short)
-__global__ __launch_bounds__(256) void k_sort_segments(const int64_t *off, int nseg, int32_t *v)
+__device__ inline bool touches(const Cell &a, const Cell &b)
 {
-    int b = blockIdx.x * 256 + threadIdx.x;
-    if (b >= nseg) return;
-    int64_t s = off[b], e = off[b + 1];
-    for (int64_t i = s + 1; i < e; ++i) {
+    for (int k = 0; k < 3; ++k)
+        if (a.x[k] > b.x[k] + b.side || b.x[k] > a.x[k] + a.side) return false;
+    return true;
+}
+
+__device__ inline void sort_serial(int32_t *v, int64_t m)
+{
+    for (int64_t i = 1; i < m; ++i) {
         int32_t x = v[i];
         int64_t j = i - 1;
-        while (j >= s && v[j] > x) { v[j + 1] = v[j]; --j; }
+        while (j >= 0 && v[j] > x) { v[j + 1] = v[j]; --j; }
         v[j + 1] = x;
     }
+}
+
+// one lane: depth-first walk writing straight to the lists, then sorting them
+__device__ void uw_serial(const TreeView &t, const int32_t *coll, int b, int which, int32_t *usrc,
+                          int32_t *wsrc, int64_t *xcnt, int &nu_out, int &nw_out)
+{
+    const Cell cb = cell_of(t, b);
+    int stack[kSerialStack];
+    int nu = 0, nw = 0;
+    for (int i = 0; i < 27; ++i) {
+        int c = coll[27 * b + i];
+        if (c < 0) break;
+        int sp = 0;
+        stack[sp++] = c;
+        while (sp > 0) {
+            int x = stack[--sp];
+            const int nch = t.bx.nchild[x];
+            if (nch == 0) {
+                if (which) usrc[nu] = x;
+                ++nu;
+                continue;
+            }
+            for (int k = nch - 1; k >= 0; --k) {
+                int d = t.bx.child_begin[x] + k;
+                if (touches(cell_of(t, d), cb)) {
+                    stack[sp++] = d;
+                } else {
+                    if (which) wsrc[nw] = d;
+                    else atomicAdd((unsigned long long *)&xcnt[d], 1ull);
+                    ++nw;
+                }
+            }
+        }
+    }
+    for (int a = t.bx.parent[b]; a >= 0; a = t.bx.parent[a])
+        for (int i = 0; i < 27; ++i) {
+            int c = coll[27 * a + i];
+            if (c < 0) break;
+            if (c != a && t.bx.nchild[c] == 0 && touches(cell_of(t, c), cb)) {
+                if (which) usrc[nu] = c;
+                ++nu;
+            }
+        }
+    if (which) { sort_serial(usrc, nu); sort_serial(wsrc, nw); }
+    nu_out = nu;
+    nw_out = nw;
+}
+
+// ascending copy of buf[0..m) (distinct values) to out, by ranks
+__device__ inline void write_ranked(const int32_t *buf, int m, int32_t *out, int lane)
+{
+    for (int j = lane; j < m; j += 64) {
+        int v = buf[j], r = 0;
+        for (int k = 0; k < m; ++k) r += buf[k] < v;
+        out[r] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_uwlist(TreeView t, const int32_t *coll, int which,
+                                                int64_t *ucnt, const int64_t *uoff, int32_t *usrc,
+                                                int64_t *wcnt, const int64_t *woff, int32_t *wsrc,
+                                                int64_t *xcnt)
+{
+    __shared__ int32_t sstk[4][kUWStack];
+    __shared__ int32_t sbu[4][kUWBuf];
+    __shared__ int32_t sbw[4][kUWBuf];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int b = blockIdx.x * 4 + wv;
+    if (b >= t.nboxes) return;
+    if (t.bx.nchild[b] != 0) {
+        if (!which && lane == 0) { ucnt[b] = 0; wcnt[b] = 0; }
+        return;
+    }
+    int32_t *stk = sstk[wv], *bu = sbu[wv], *bw = sbw[wv];
+    const uint64_t below = lanes_below(lane);
+    const Cell cb = cell_of(t, b);
+    int nu = 0, nw = 0;
+    bool ok = true;
+    {
+        int c = lane < 27 ? coll[27 * b + lane] : -1;
+        uint64_t m = __ballot(c >= 0);
+        if (c >= 0) stk[__popcll(m & below)] = c;
+        int sp = __popcll(m);
+        wave_sync();
+        while (sp > 0) {
+            const int take = sp < 64 ? sp : 64;
+            if (sp - take + 8 * take > kUWStack || nu + take > kUWBuf || nw + 8 * take > kUWBuf) {
+                ok = false;
+                break;
+            }
+            const int x = lane < take ? stk[sp - take + lane] : -1;
+            sp -= take;
+            wave_sync();
+            const int nch = x >= 0 ? t.bx.nchild[x] : 0;
+            const bool isu = x >= 0 && nch == 0;
+            uint64_t mu = __ballot(isu);
+            if (isu) bu[nu + __popcll(mu & below)] = x;
+            nu += __popcll(mu);
+            const int cfirst = nch > 0 ? t.bx.child_begin[x] : 0;
+            for (int k = 0; k < 8; ++k) {
+                const bool has = k < nch;
+                const int d = cfirst + k;
+                const bool adj = has && touches(cell_of(t, d), cb);
+                const bool isw = has && !adj;
+                const uint64_t mp = __ballot(adj), mw = __ballot(isw);
+                if (adj) stk[sp + __popcll(mp & below)] = d;
+                if (isw) bw[nw + __popcll(mw & below)] = d;
+                sp += __popcll(mp);
+                nw += __popcll(mw);
+            }
+            wave_sync();
+        }
+    }
+    if (ok) {
+        for (int a = t.bx.parent[b]; a >= 0; a = t.bx.parent[a]) {
+            const int c = lane < 27 ? coll[27 * a + lane] : -1;
+            const bool hit = c >= 0 && c != a && t.bx.nchild[c] == 0 && touches(cell_of(t, c), cb);
+            const uint64_t m = __ballot(hit);
+            if (nu + __popcll(m) > kUWBuf) { ok = false; break; }
+            if (hit) bu[nu + __popcll(m & below)] = c;
+            nu += __popcll(m);
+        }
+    }
+    wave_sync();
+    if (!ok) {
+        int su = 0, sw = 0;
+        if (lane == 0)
+            uw_serial(t, coll, b, which, which ? usrc + uoff[b] : nullptr, which ? wsrc + woff[b] : nullptr,
+                      xcnt, su, sw);
+        if (!which && lane == 0) { ucnt[b] = su; wcnt[b] = sw; }
+        return;
+    }
+    if (!which) {
+        for (int j = lane; j < nw; j += 64) atomicAdd((unsigned long long *)&xcnt[bw[j]], 1ull);
+        if (lane == 0) { ucnt[b] = nu; wcnt[b] = nw; }
+        return;
+    }
+    write_ranked(bu, nu, usrc + uoff[b], lane);
+    write_ranked(bw, nw, wsrc + woff[b], lane);
 }
 
 void colleagues(const TreeArgs &a, int32_t *coll, hipStream_t s)
 {
     TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes};
-    k_colleagues<<<ceil_div(a.nboxes, 256), 256, 0, s>>>(t, coll);
+    k_colleagues<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll);
 }
 
 void vlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *cnt, const int64_t *off,
            int32_t *src, int32_t *vslot, hipStream_t s)
 {
     TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes};
-    k_vlist<<<ceil_div(a.nboxes, 256), 256, 0, s>>>(t, coll, which, cnt, off, src, vslot);
+    k_vlist<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, which, cnt, off, src, vslot);
 }
 
 void uwlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *ucnt, const int64_t *uoff,
-            int32_t *usrc, int64_t *wcnt, const int64_t *woff, int32_t *wsrc, hipStream_t s)
+            int32_t *usrc, int64_t *wcnt, const int64_t *woff, int32_t *wsrc, int64_t *xcnt, hipStream_t s)
 {
     TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes};
-    k_uwlist<<<ceil_div(a.nboxes, 128), 128, 0, s>>>(t, coll, which, ucnt, uoff, usrc, wcnt, woff, wsrc);
-}
-
-void sort_segments(const int64_t *off, int nseg, int32_t *v, hipStream_t s)
-{
-    k_sort_segments<<<ceil_div(nseg, 256), 256, 0, s>>>(off, nseg, v);
+    k_uwlist<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, which, ucnt, uoff, usrc, wcnt, woff, wsrc, xcnt);
 }
 
 // X = transpose of W: pairs (key = source box, value = target box), stably
 // sorted by source; targets arrive in ascending order.
 __global__ __launch_bounds__(256) void k_w_pairs(const int64_t *woff, const int32_t *wsrc, int nboxes,
-                                                 uint64_t *key, int32_t *val, int64_t *xcnt)
+                                                 uint64_t *key, int32_t *val)
 {
     int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= nboxes) return;
     for (int64_t e = woff[b]; e < woff[b + 1]; ++e) {
         key[e] = (uint64_t)wsrc[e];
         val[e] = b;
-        atomicAdd((unsigned long long *)&xcnt[wsrc[e]], 1ull);
     }
 }
 
-void w_pairs(const int64_t *woff, const int32_t *wsrc, int nboxes, uint64_t *key, int32_t *val,
-             int64_t *xcnt, hipStream_t s)
+void w_pairs(const int64_t *woff, const int32_t *wsrc, int nboxes, uint64_t *key, int32_t *val, hipStream_t s)
 {
-    k_w_pairs<<<ceil_div(nboxes, 256), 256, 0, s>>>(woff, wsrc, nboxes, key, val, xcnt);
+    k_w_pairs<<<ceil_div(nboxes, 256), 256, 0, s>>>(woff, wsrc, nboxes, key, val);
 }
 
 // ---------------- work lists ----------------
-// flag[b] = predicate; compaction via exclusive scan of the flags
-__global__ __launch_bounds__(256) void k_flags(const BoxArrays bx, int nboxes, int what,
-                                               const int64_t *off, int64_t *flag)
+// Work-list membership of every box: leaves, non-leaves, boxes with an X
+// list, boxes with a V list; compaction via exclusive scans of the flags.
+__global__ __launch_bounds__(256) void k_flags(const BoxArrays bx, int nboxes, const int64_t *xcnt,
+                                               const int64_t *vcnt, int64_t *fleaf, int64_t *fnon,
+                                               int64_t *fx, int64_t *fv)
 {
     int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= nboxes) return;
-    int64_t f = 0;
-    if (what == 0) f = bx.nchild[b] == 0;               // leaves
-    else if (what == 1) f = bx.nchild[b] > 0;           // non-leaves
-    else f = off[b + 1] > off[b];                       // non-empty list
-    flag[b] = f;
+    const bool leaf = bx.nchild[b] == 0;
+    fleaf[b] = leaf;
+    fnon[b] = !leaf;
+    fx[b] = xcnt[b] > 0;
+    fv[b] = vcnt[b] > 0;
+}
+
+void flags(const BoxArrays &bx, int nboxes, const int64_t *xcnt, const int64_t *vcnt, int64_t *fleaf,
+           int64_t *fnon, int64_t *fx, int64_t *fv, hipStream_t s)
+{
+    k_flags<<<ceil_div(nboxes, 256), 256, 0, s>>>(bx, nboxes, xcnt, vcnt, fleaf, fnon, fx, fv);
 }
 
 __global__ __launch_bounds__(256) void k_compact(const int64_t *flag, const int64_t *pos, int nboxes,
@@ -466,29 +666,9 @@ __global__ __launch_bounds__(256) void k_compact(const int64_t *flag, const int6
     if (flag[b]) out[pos[b]] = b;
 }
 
-void flags(const BoxArrays &bx, int nboxes, int what, const int64_t *off, int64_t *flag, hipStream_t s)
-{
-    k_flags<<<ceil_div(nboxes, 256), 256, 0, s>>>(bx, nboxes, what, off, flag);
-}
-
 void compact(const int64_t *flag, const int64_t *pos, int nboxes, int32_t *out, hipStream_t s)
 {
     k_compact<<<ceil_div(nboxes, 256), 256, 0, s>>>(flag, pos, nboxes, out);
-}
-
-// leaf of every sorted particle
-__global__ __launch_bounds__(256) void k_leaf_of(const BoxArrays bx, const int32_t *leaves, int nleaves,
-                                                 int32_t *leaf_of)
-{
-    int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= nleaves) return;
-    int b = leaves[i];
-    for (int k = bx.first[b]; k < bx.first[b] + bx.count[b]; ++k) leaf_of[k] = b;
-}
-
-void leaf_of(const BoxArrays &bx, const int32_t *leaves, int nleaves, int32_t *lo, hipStream_t s)
-{
-    k_leaf_of<<<ceil_div(nleaves, 256), 256, 0, s>>>(bx, leaves, nleaves, lo);
 }
 
 // ---------------- M2L target tiles ----------------
@@ -560,40 +740,6 @@ void m2l_tiles(const BoxArrays &bx, const int32_t *tg, int nt, uint64_t *key, in
     radix_sort_pairs(key, val, tk, tv, nt, 3, sort_scratch, s);
     k_oct_offsets<<<1, 64, 0, s>>>(key, nt, octoff);
     k_oct_place<<<ceil_div(nt, 256), 256, 0, s>>>(key, val, nt, octoff, slots);
-}
-
-// ---------------- mixed precision particle data ----------------
-// leaf-local offsets x - c_leaf split into an FP32 head and an FP32 tail
-__global__ __launch_bounds__(256) void k_local_split(const double *xs, const double *ys, const double *zs,
-                                                     const int32_t *leaf_of, const BoxArrays bx, int n,
-                                                     double lo0, double lo1, double lo2, double W,
-                                                     float *ux, float *uy, float *uz, float *vx,
-                                                     float *vy, float *vz)
-{
-    int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    int b = leaf_of[i];
-    int l = bx.level[b], c[3];
-    deinterleave(bx.morton[b], l, c);
-    double h = W / (double)(1ll << l);
-    double lo[3] = {lo0, lo1, lo2}, x[3] = {xs[i], ys[i], zs[i]};
-    float hi[3], lw[3];
-    for (int k = 0; k < 3; ++k) {
-        double cen = lo[k] + ((double)c[k] + 0.5) * h;
-        double d = x[k] - cen;
-        hi[k] = (float)d;
-        lw[k] = (float)(d - (double)hi[k]);
-    }
-    ux[i] = hi[0]; uy[i] = hi[1]; uz[i] = hi[2];
-    vx[i] = lw[0]; vy[i] = lw[1]; vz[i] = lw[2];
-}
-
-void local_split(const double *xs, const double *ys, const double *zs, const int32_t *leaf_of,
-                 const BoxArrays &bx, int n, const double root[4], float *ux, float *uy, float *uz,
-                 float *vx, float *vy, float *vz, hipStream_t s)
-{
-    k_local_split<<<ceil_div(n, 256), 256, 0, s>>>(xs, ys, zs, leaf_of, bx, n, root[0], root[1], root[2],
-                                                  root[3], ux, uy, uz, vx, vy, vz);
 }
 
 } // namespace fmm
