@@ -94,6 +94,24 @@ int fmm_plan(const double *xyz_dev, int64_t n, int32_t order, int32_t leaf_size,
              fmm_plan_t *out);
 
 /*
+ * fmm_plan_batch - build `count` independent plans (the many-small-problems
+ * case of Sec. 1's recipe applied to each problem).  Arrays of length count:
+ * xyz_dev[i] [n[i]][3] device coordinates, order[i], leaf_size[i]; opts is
+ * NULL (defaults for all) or an array of count options.  With no allocator
+ * the plans are built concurrently by up to `threads` host threads, each on a
+ * stream of its own that first waits for the work already enqueued on
+ * `stream`; with an allocator they are built one after the other on `stream`.
+ * On return every plan is complete and behaves as one built by fmm_plan on
+ * `stream` (destroy is ordered on `stream`).  On failure no plan is returned
+ * (out[] is all NULL) and the status and message of the first failing plan
+ * are reported.
+ */
+int fmm_plan_batch(int32_t count, const double *const *xyz_dev, const int64_t *n,
+                   const int32_t *order, const int32_t *leaf_size, const fmm_options_t *opts,
+                   const fmm_allocator_t *alloc, hipStream_t stream, int32_t threads,
+                   fmm_plan_t *out);
+
+/*
  * fmm_evaluate - potentials (and fields) for charges q.
  *   q_dev      [n] FP64 device charges, original order
  *   phi_dev    [n] FP64 device output potentials
@@ -171,7 +189,8 @@ int fmm_plan_set_timing(fmm_plan_t plan, int on);
 int fmm_plan_read_timing(fmm_plan_t plan, double ms[16], int64_t calls[16]);
 
 /* Release the plan.  Stream-ordered on the plan's build stream: memory is
- * returned after work already enqueued there has finished. */
+ * returned after work already enqueued there, and the latest evaluation on
+ * every other stream that evaluated the plan, have finished. */
 int fmm_plan_destroy(fmm_plan_t plan);
 
 /* Message of the calling thread's last failed call ("" if none). */

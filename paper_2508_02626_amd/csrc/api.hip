@@ -3,9 +3,11 @@
 #include "fmm.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "common.h"
@@ -94,6 +96,21 @@ struct fmm_plan_s {
     std::vector<Rec> recs;      // recorded, not yet read
     std::vector<Rec> pool;      // reusable event pairs
 
+    // streams other than the build stream that evaluated this plan, each with
+    // an event after its latest evaluation; destroy waits for them
+    std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
+    int note_use(hipStream_t s)
+    {
+        if (s == stream) return 0;
+        hipEvent_t ev = nullptr;
+        for (auto &u : uses)
+            if (u.first == s) ev = u.second;
+        if (!ev) {
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return -1;
+            uses.push_back({s, ev});
+        }
+        return hipEventRecord(ev, s) == hipSuccess ? 0 : -1;
+    }
     // host copies kept for the lifetime of the plan (sources of async copies)
     std::vector<int32_t> lvl_host;
     PlanSizes sizes{};
@@ -495,6 +512,74 @@ extern "C" int fmm_plan(const double *xyz_dev, int64_t n, int32_t order, int32_t
     return FMM_OK;
 }
 
+extern "C" int fmm_plan_batch(int32_t count, const double *const *xyz_dev, const int64_t *n,
+                              const int32_t *order, const int32_t *leaf_size, const fmm_options_t *opts,
+                              const fmm_allocator_t *alloc, hipStream_t stream, int32_t threads,
+                              fmm_plan_t *out)
+{
+    g_err.clear();
+    if (count < 0 || (count > 0 && (!xyz_dev || !n || !order || !leaf_size || !out)))
+        return fail(FMM_EINVAL, "bad batch arguments");
+    if (count == 0) return FMM_OK;
+    for (int i = 0; i < count; ++i) out[i] = nullptr;
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(FMM_EINVAL, "allocator without functions");
+    for (int i = 0; i < count; ++i) { // everything checkable on the host, before any device call
+        fmm_options_t o;
+        fmm_default_options(&o);
+        if (opts) o = opts[i];
+        if (!xyz_dev[i]) return fail(FMM_EINVAL, "plan " + std::to_string(i) + ": null pointer argument");
+        if (n[i] < 1 || n[i] >= (1LL << 31)) return fail(FMM_EINVAL, "plan " + std::to_string(i) + ": bad n");
+        if (int rc = check_options(o, order[i], leaf_size[i])) {
+            g_err = "plan " + std::to_string(i) + ": " + g_err;
+            return rc;
+        }
+    }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    // work enqueued on the caller's stream before this call precedes the builds
+    hipEvent_t ready = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ready, stream));
+    int nthr = alloc ? 1 : std::max(1, std::min<int>(threads, count));
+    std::atomic<int> next{0}, first_bad{count};
+    std::vector<int> rcs(count, FMM_OK);
+    std::vector<std::string> msgs(count);
+    auto worker = [&](bool own_stream) {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        hipStream_t ws = stream;
+        if (own_stream && hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) ws = stream;
+        if (ws != stream) (void)hipStreamWaitEvent(ws, ready, 0);
+        for (int i; (i = next.fetch_add(1)) < count;) {
+            if (first_bad.load() < count) break;
+            int rc = fmm_plan(xyz_dev[i], n[i], order[i], leaf_size[i], opts ? &opts[i] : nullptr, alloc, ws, &out[i]);
+            if (rc) {
+                rcs[i] = rc;
+                msgs[i] = g_err;
+                int cur = first_bad.load();
+                while (i < cur && !first_bad.compare_exchange_weak(cur, i)) {}
+                break;
+            }
+            out[i]->stream = stream; // built and synchronised: later frees are ordered on the caller's stream
+        }
+        if (ws != stream) (void)hipStreamDestroy(ws);
+    };
+    if (nthr == 1) {
+        worker(false);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nthr; ++t) pool.emplace_back(worker, true);
+        for (auto &t : pool) t.join();
+    }
+    (void)hipEventDestroy(ready);
+    int bad = first_bad.load();
+    if (bad < count) {
+        for (int i = 0; i < count; ++i)
+            if (out[i]) { fmm_plan_destroy(out[i]); out[i] = nullptr; }
+        return fail(rcs[bad] ? rcs[bad] : FMM_EDEVICE, "plan " + std::to_string(bad) + ": " + msgs[bad]);
+    }
+    return FMM_OK;
+}
+
 namespace {
 
 struct StagePlan {
@@ -665,7 +750,10 @@ extern "C" int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_de
     v.fld_out = field_dev;
     HIPCHK(hipMemcpyAsync(P->view_dev, &v, sizeof(PlanView), hipMemcpyHostToDevice, stream));
     fmm_plan_s *arr[1] = {P};
-    return run_pipeline(arr, 1, P->view_dev, stream);
+    int rc = run_pipeline(arr, 1, P->view_dev, stream);
+    if (rc) return rc;
+    if (P->note_use(stream)) return fail(FMM_EDEVICE, "event record failed");
+    return FMM_OK;
 }
 
 extern "C" int fmm_evaluate_batch(fmm_plan_t const *plans, const double *const *q_dev,
@@ -705,6 +793,8 @@ extern "C" int fmm_evaluate_batch(fmm_plan_t const *plans, const double *const *
         (void)hipFreeAsync(Vd, stream);
         if (rc) return rc;
     }
+    for (int i = 0; i < count; ++i)
+        if (plans[i]->note_use(stream)) return fail(FMM_EDEVICE, "event record failed");
     return FMM_OK;
 }
 
@@ -876,6 +966,11 @@ extern "C" int fmm_plan_destroy(fmm_plan_t plan)
     int dev = 0;
     (void)hipGetDevice(&dev);
     if (dev != plan->device) (void)hipSetDevice(plan->device);
+    for (auto &u : plan->uses) {
+        (void)hipStreamWaitEvent(plan->stream, u.second, 0);
+        (void)hipEventDestroy(u.second);
+    }
+    plan->uses.clear();
     plan->release_all();
     if (dev != plan->device) (void)hipSetDevice(dev);
     delete plan;

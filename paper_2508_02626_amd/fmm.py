@@ -19,7 +19,7 @@ FMM_FP64, FMM_MIXED = 0, 1
 SYMBOLS = ["fmm_default_options", "fmm_plan", "fmm_evaluate", "fmm_evaluate_batch",
            "fmm_plan_footprint", "fmm_plan_estimate", "fmm_plan_sizes", "fmm_plan_export_tree",
            "fmm_plan_export_expansions", "fmm_plan_set_timing", "fmm_plan_read_timing",
-           "fmm_plan_destroy", "fmm_last_error"]
+           "fmm_plan_destroy", "fmm_last_error", "fmm_plan_batch"]
 STAGES = ["permute", "p2m", "m2m", "fold", "m2l", "p2l", "unfold", "l2l", "l2p_m2p", "p2p"]
 
 
@@ -63,6 +63,8 @@ def lib():
         L.fmm_plan_set_timing.argtypes = [vp, ctypes.c_int]
         L.fmm_plan_read_timing.argtypes = [vp, P(ctypes.c_double), P(i64)]
         L.fmm_plan_destroy.argtypes = [vp]
+        L.fmm_plan_batch.argtypes = [i32, P(vp), P(i64), P(i32), P(i32), P(Options), P(Allocator), vp, i32,
+                                     P(vp)]
         L.fmm_last_error.restype = ctypes.c_char_p
         L.fmm_last_error.argtypes = []
         _lib = L
@@ -118,6 +120,12 @@ class Plan:
                               _stream(stream), ctypes.byref(h)))
         self._h = h
         del keep
+
+    @classmethod
+    def _adopt(cls, h, n, order, device):
+        self = cls.__new__(cls)
+        self._h, self.n, self.order, self.device = h, int(n), int(order), device
+        return self
 
     def close(self):
         h = getattr(self, "_h", None)
@@ -196,6 +204,32 @@ class Plan:
 
 def plan(xyz, order, leaf_size=64, **kw):
     return Plan(xyz, order, leaf_size, **kw)
+
+
+def plan_batch(xyzs, orders, leaf_size=64, precision="fp64", uniform_depth=-1, max_depth=21,
+               want_field=True, threads=8, stream=None):
+    """fmm_plan_batch: build one plan per point set, concurrently on up to
+    `threads` host threads; orders, leaf_size and precision may be scalars or
+    per-problem sequences."""
+    import torch
+    m = len(xyzs)
+    seq = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * m
+    orders, leafs, precs = seq(orders), seq(leaf_size), seq(precision)
+    xs = []
+    for x in xyzs:
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dim() == 2 and x.shape[1] == 3):
+            raise FmmError(FMM_EINVAL, "every xyz must be a CUDA/HIP tensor of shape [n, 3]")
+        xs.append(x.to(torch.float64).contiguous())
+    xv = (ctypes.c_void_p * m)(*[x.data_ptr() for x in xs])
+    nv = (ctypes.c_int64 * m)(*[x.shape[0] for x in xs])
+    ov = (ctypes.c_int32 * m)(*[int(o) for o in orders])
+    lv = (ctypes.c_int32 * m)(*[int(l) for l in leafs])
+    opts = (Options * m)()
+    for i in range(m):
+        opts[i], _ = _options(uniform_depth, max_depth, precs[i], want_field, None)
+    hv = (ctypes.c_void_p * m)()
+    _check(lib().fmm_plan_batch(m, xv, nv, ov, lv, opts, None, _stream(stream), int(threads), hv))
+    return [Plan._adopt(ctypes.c_void_p(hv[i]), xs[i].shape[0], orders[i], xs[i].device) for i in range(m)]
 
 
 def evaluate_batch(plans, qs, want_field=True, stream=None):

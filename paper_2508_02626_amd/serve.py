@@ -6,8 +6,9 @@ dispatcher admits them in arrival order while (a) a worker slot is free and
 HBM budget (fmm_plan_estimate plus inputs and outputs).  Each slot owns a HIP
 stream (default priority) and a worker thread; when it takes a request it
 also takes the other waiting small requests that fit, builds their plans on
-its stream and evaluates them together with one fmm_evaluate_batch call (one
-launch per pipeline stage for all of them).  Slots run concurrently, so
+its stream (concurrently, with fmm_plan_batch) and evaluates them together
+with one fmm_evaluate_batch call (one launch per pipeline stage for all of
+them).  Slots run concurrently, so
 requests that arrive while others are on the GPU overlap with them.  Every
 kernel is deterministic and a batched evaluation equals the single one bit
 for bit, so a result does not depend on what it was served with.
@@ -80,7 +81,7 @@ class Server:
     """Continuous-batching FMM server for one GPU."""
 
     def __init__(self, hbm_budget_bytes=32 << 30, slots=4, pack_threshold=200_000, max_pack=32,
-                 leaf_size=64, precision=None, device="cuda:0"):
+                 leaf_size=64, precision=None, device="cuda:0", build_threads=4):
         import torch
         from . import fmm
         self.torch, self.fmm = torch, fmm
@@ -88,6 +89,7 @@ class Server:
         self.adm = Admission(hbm_budget_bytes)
         self.pack_threshold = pack_threshold
         self.max_pack = max_pack
+        self.build_threads = build_threads
         self.leaf_size = leaf_size
         self.precision = precision
         self.pending = deque()
@@ -164,13 +166,17 @@ class Server:
     def _run_group(self, group, stream):
         torch, fmm = self.torch, self.fmm
         with torch.cuda.stream(stream):
-            plans, qs, outs = [], [], []
+            xs, qs, outs = [], [], []
             for r in group:
-                x = torch.from_numpy(r.x).pin_memory().to(self.device, non_blocking=True)
-                q = torch.from_numpy(r.q).pin_memory().to(self.device, non_blocking=True)
-                plans.append(fmm.Plan(x, r.order, leaf_size=r.leaf_size, precision=r.precision,
-                                      stream=stream))
-                qs.append(q)
+                xs.append(torch.from_numpy(r.x).pin_memory().to(self.device, non_blocking=True))
+                qs.append(torch.from_numpy(r.q).pin_memory().to(self.device, non_blocking=True))
+            if len(group) == 1:
+                r = group[0]
+                plans = [fmm.Plan(xs[0], r.order, leaf_size=r.leaf_size, precision=r.precision, stream=stream)]
+            else:
+                plans = fmm.plan_batch(xs, [r.order for r in group], leaf_size=[r.leaf_size for r in group],
+                                       precision=[r.precision for r in group], threads=self.build_threads,
+                                       stream=stream)
             if len(group) == 1:
                 outs.append(plans[0].evaluate(qs[0], stream=stream))
             else:

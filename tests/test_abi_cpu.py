@@ -60,6 +60,17 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.fmm_evaluate_batch(None, None, None, None, 0, None) == fmm.FMM_OK
     alloc = fmm.Allocator()
     assert lib.fmm_plan(fake, 10, 4, 8, None, ctypes.byref(alloc), None, ctypes.byref(h)) == fmm.FMM_EINVAL
+    # batched plan construction validates every entry before any device call
+    hv = (ctypes.c_void_p * 2)()
+    xv = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    nv = (ctypes.c_int64 * 2)(10, 10)
+    ov = (ctypes.c_int32 * 2)(4, 13)
+    lv = (ctypes.c_int32 * 2)(8, 8)
+    assert lib.fmm_plan_batch(-1, None, None, None, None, None, None, None, 4, hv) == fmm.FMM_EINVAL
+    assert lib.fmm_plan_batch(0, None, None, None, None, None, None, None, 4, hv) == fmm.FMM_OK
+    assert lib.fmm_plan_batch(2, xv, nv, ov, lv, None, None, None, 4, hv) == fmm.FMM_EINVAL
+    assert b"plan 1" in lib.fmm_last_error()
+    assert hv[0] is None and hv[1] is None
 
 
 def test_estimate_grows_with_n_and_order():
