@@ -10,15 +10,20 @@
 // Work decomposition.  A block holds 64 targets (4 wavefronts x 16) of one
 // octant, so they share the same 189 source offsets (Sec. 3.4: at most 189
 // boxes per interaction list); slots that no target of the block uses are
-// skipped.  For every offset slot the block stages the offset's derivative
-// table and the 16 source vectors of each wavefront in LDS (loaded into
-// registers while the previous slot is being multiplied), then each wavefront
-// runs a (p+1)^2 x (p+1)^2 by 16 product with
-// 16x16x4 MFMAs: A[b][a] = D(addr(b) + addr(a)) is gathered from LDS with the
-// additive address addr(i,j,k) = k s2 + i (2p+2) + j, which turns the
-// Hankel structure of the matrix into a single add per operand (the x stride
-// 2p+2 keeps the 16 rows of one operand load in different LDS banks); B holds the
-// gathered sources.  Accumulators stay in registers across all 189 slots, so
+// skipped, and so are the products of a wavefront none of whose targets uses
+// the slot.  For every offset slot each wavefront runs a (p+1)^2 x (p+1)^2 by
+// 16 product with 16x16x4 MFMAs: A[b][a] = D(addr(b) + addr(a)) is gathered
+// from the slot's derivative table in LDS with the additive address
+// addr(i,j,k) = k s2 + i (2p+2) + j, which turns the Hankel structure of the
+// matrix into a single add per operand (the x stride 2p+2 keeps the 16 rows of
+// one operand load in different LDS banks); B, the 16 source vectors, is
+// loaded from memory straight into the lanes that feed it to the MFMA, one
+// slot ahead (each k-step's operand register is refilled for the next slot
+// once its MFMAs are issued).  The derivative tables are double-buffered in
+// LDS, so a slot costs one workgroup barrier.  When (p+1)^2 exceeds a
+// multiple of 16 by one or two rows (p = 6, 8), those rows are computed with
+// FMAs on the vector unit from the same operands instead of a mostly empty
+// MFMA row tile.  Accumulators stay in registers across all 189 slots, so
 // every target is written once; the FP32 variant adds each slot's FP32 partial
 // into FP64 accumulators, so only the per-slot products carry FP32 rounding.  Operand layouts (verified on gfx950):
 // A: lane l holds A[l%16][l/16]; B: lane l holds B[l/16][l%16];
@@ -52,21 +57,27 @@ template <> struct Mfma<float> {
     __device__ static const float *M(const PlanView &v) { return v.Mhf; }
 };
 
+// Loads through global address-space pointers: generic (flat) loads would also
+// count against the LDS wait counter and stall the operand reads behind them.
+template <typename T> __device__ inline T gload(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+
 template <int P, typename T>
 __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
 {
     constexpr int NH = (P + 1) * (P + 1);
-    constexpr int LDH = (NH + 15) & ~15;
-    constexpr int MT = LDH / 16;
+    constexpr int MF = NH / 16, XR0 = NH - 16 * MF;
+    constexpr bool XV = MF >= 1 && XR0 <= 2;     // leftover rows go to the VALU
+    constexpr int MT = XV ? MF : (NH + 15) / 16; // MFMA row tiles
+    constexpr int XR = XV ? XR0 : 0;             // VALU rows
     constexpr int NK = (NH + 3) & ~3;
     constexpr int KS = NK / 4;
     constexpr int LDD = dlayout_ldd(P);
-    constexpr int BST = NK + 1;
     constexpr int DR = (LDD + 255) / 256; // derivative-table words per thread
-    constexpr int BR = (16 * NK) / 64;    // source-tile words per lane (16 rows of NK)
     typedef typename Mfma<T>::acc_t acc_t;
-    __shared__ T sD[LDD];
-    __shared__ T sB[4][16][BST];
+    __shared__ T sD[2][LDD];
     __shared__ int sHo[NK];
     __shared__ int sTg[64];
     __shared__ int sList[kVSlots];
@@ -76,19 +87,21 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     const PlanView &v = V[k];
     const int tile = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
-    const int slot = tile * kM2LSlots + wave * 16 + col;
-    const int tgt = v.m2l_tgt[slot];
+    // lanes col, col+16, col+32, col+48 serve target wave*16+col (one B column)
+    const int tgt = v.m2l_tgt[tile * kM2LSlots + wave * 16 + col];
     if (!__syncthreads_or(tgt >= 0)) return;
     if (tgt >= 0) soct = (int)(v.morton[tgt] & 7); // every target of the block has this octant
     if (tid < 64) sTg[tid] = v.m2l_tgt[tile * kM2LSlots + tid];
     const OrderTables &tb = *v.tab;
     for (int a = tid; a < NK; a += 256) sHo[a] = a < NH ? tb.hoff[a] : 0;
-    int hb[MT];
+    int hb[MT], hx[XR > 0 ? XR : 1];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         int b = mt * 16 + col;
         hb[mt] = b < NH ? tb.hoff[b] : 0;
     }
+#pragma unroll
+    for (int x = 0; x < XR; ++x) hx[x] = tb.hoff[16 * MT + x];
     __syncthreads();
     // slots used by at least one target of the block, in increasing order
     const int32_t *vs = v.vslot;
@@ -115,71 +128,123 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
 
     acc_t acc[MT];
     double4_t acc64[MT]; // FP32 path: per-offset partials are summed in FP64
+    T xacc[XR > 0 ? XR : 1];
+    double xacc64[XR > 0 ? XR : 1];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) { acc[mt] = acc_t{0, 0, 0, 0}; acc64[mt] = double4_t{0, 0, 0, 0}; }
+#pragma unroll
+    for (int x = 0; x < XR; ++x) { xacc[x] = (T)0; xacc64[x] = 0.0; }
 
-    T pD[DR], pB[BR];
-    auto prefetch = [&](int j) {
+    // B operand of k-step ks: component 4 ks + kq of this lane's source
+    T pb[KS], pd[DR];
+    auto load_d = [&](int j) {
         const T *Dk = Dt + (int64_t)tb.offs[oct * kVSlots + j] * LDD;
 #pragma unroll
         for (int r = 0; r < DR; ++r) {
             int e = tid + 256 * r;
-            pD[r] = e < LDD ? Dk[e] : (T)0;
-        }
-        const int src = tgt >= 0 ? vsl[j] : -1;
-#pragma unroll
-        for (int r = 0; r < BR; ++r) {
-            const int f = lane + 64 * r, t = f / NK, e = f - t * NK;
-            const int st = __shfl(src, t);
-            pB[r] = st >= 0 ? Mh[(int64_t)st * ldh + e] : (T)0;
+            pd[r] = e < LDD ? gload(Dk + e) : (T)0;
         }
     };
-    if (nvalid > 0) prefetch(sList[0]);
-    for (int q = 0; q < nvalid; ++q) {
-        __syncthreads(); // the previous slot's products are done with sD / sB
+    // always issued (clamped address), so that the waits can count the loads;
+    // operands of absent sources and padding components are zeroed at use.
+    // FP64: each k-step's register is refilled for the next slot right after
+    // its MFMAs (no second register set); FP32: the next slot's operands go to
+    // a second set loaded at the top of the slot.
+    constexpr bool DB = sizeof(T) == 4;
+    T pbn[DB ? KS : 1];
+    auto load_b = [&](int ks, int src) {
+        const int a = 4 * ks + kq;
+        const T val = gload(Mh + (int64_t)(src >= 0 ? src : 0) * ldh + (a < NH ? a : NH - 1));
+        if constexpr (DB) pbn[ks] = val;
+        else pb[ks] = val;
+    };
+    int src = -1;
+    if (nvalid > 0) {
+        load_d(sList[0]);
 #pragma unroll
         for (int r = 0; r < DR; ++r) {
             int e = tid + 256 * r;
-            if (e < LDD) sD[e] = pD[r];
+            if (e < LDD) sD[0][e] = pd[r];
         }
+        src = tgt >= 0 ? gload(vsl + sList[0]) : -1;
 #pragma unroll
-        for (int r = 0; r < BR; ++r) {
-            const int f = lane + 64 * r, t = f / NK, e = f - t * NK;
-            sB[wave][t][e] = pB[r];
+        for (int ks = 0; ks < KS; ++ks) load_b(ks, src);
+        if constexpr (DB) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) pb[ks] = pbn[ks];
         }
         __syncthreads();
-        if (q + 1 < nvalid) prefetch(sList[q + 1]); // in flight during the products
-        // operands of step ks+1 are read from LDS while the MFMAs of step ks run
-        T ac[MT], an[MT], bc, bn = (T)0;
+    }
+    for (int q = 0; q < nvalid; ++q) {
+        const int cur = q & 1;
+        const bool more = q + 1 < nvalid;
+        const int jn = more ? sList[q + 1] : 0;
+        if (more) load_d(jn); // in flight during the products
+        const int nsrc = (more && tgt >= 0) ? gload(vsl + jn) : -1;
+        const T *D = sD[cur];
+        if constexpr (DB) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) load_b(ks, nsrc);
+            __builtin_amdgcn_sched_barrier(0); // keep the loads ahead of the products
+        }
         {
-            const int ha = sHo[kq];
-            bc = sB[wave][col][kq];
+            // A operands of step ks+1 are read from LDS while the MFMAs of step ks run
+            T ac[MT], an[MT];
+            {
+                const int ha = sHo[kq];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) ac[mt] = sD[hb[mt] + ha];
-        }
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-            if (ks + 1 < KS) {
-                const int a = (ks + 1) * 4 + kq;
-                const int ha = sHo[a];
-                bn = sB[wave][col][a];
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) an[mt] = sD[hb[mt] + ha];
+                for (int mt = 0; mt < MT; ++mt) ac[mt] = D[hb[mt] + ha];
             }
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) acc[mt] = Mfma<T>::run(ac[mt], bc, acc[mt]);
+            for (int ks = 0; ks < KS; ++ks) {
+                const int ha = sHo[4 * ks + kq];
+                if (ks + 1 < KS) {
+                    const int hn = sHo[4 * (ks + 1) + kq];
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) ac[mt] = an[mt];
-            bc = bn;
-        }
-        if constexpr (sizeof(T) == 4) {
+                    for (int mt = 0; mt < MT; ++mt) an[mt] = D[hb[mt] + hn];
+                }
+                const T bv = (src >= 0 && 4 * ks + kq < NH) ? pb[ks] : (T)0;
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
+                for (int mt = 0; mt < MT; ++mt) acc[mt] = Mfma<T>::run(ac[mt], bv, acc[mt]);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc64[mt][r] += (double)acc[mt][r];
-                acc[mt] = acc_t{0, 0, 0, 0};
+                for (int x = 0; x < XR; ++x) xacc[x] += D[hx[x] + ha] * bv;
+                if constexpr (!DB) load_b(ks, nsrc); // next slot's operand, consumed one slot later
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) ac[mt] = an[mt];
+            }
+            if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc64[mt][r] += (double)acc[mt][r];
+                    acc[mt] = acc_t{0, 0, 0, 0};
+                }
+#pragma unroll
+                for (int x = 0; x < XR; ++x) { xacc64[x] += (double)xacc[x]; xacc[x] = (T)0; }
             }
         }
+        if constexpr (DB) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) pb[ks] = pbn[ks];
+        }
+        if (more) {
+#pragma unroll
+            for (int r = 0; r < DR; ++r) {
+                int e = tid + 256 * r;
+                if (e < LDD) sD[cur ^ 1][e] = pd[r];
+            }
+        }
+        src = nsrc;
+        __syncthreads(); // next table written; everyone is done with this one
+    }
+    // VALU rows: each lane holds the terms a = kq (mod 4); sum the four lanes
+    double xs[XR > 0 ? XR : 1];
+#pragma unroll
+    for (int x = 0; x < XR; ++x) {
+        double t = sizeof(T) == 4 ? xacc64[x] : (double)xacc[x];
+        t += __shfl_xor(t, 16);
+        t += __shfl_xor(t, 32);
+        xs[x] = t;
     }
     if (tgt < 0) return;
     double *Lh = v.Lh + (int64_t)tgt * ldh;
@@ -190,6 +255,10 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
             int b = mt * 16 + Mfma<T>::row(lane, r);
             if (b < NH) Lh[b] = sizeof(T) == 4 ? acc64[mt][r] : (double)acc[mt][r];
         }
+    if (kq == 0) {
+#pragma unroll
+        for (int x = 0; x < XR; ++x) Lh[16 * MT + x] = xs[x];
+    }
 }
 
 #define M2L_CASE(PP)                                                               \
