@@ -59,6 +59,14 @@ __device__ inline void wave_sync()
 }
 __device__ inline uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
+// Global address-space views of device pointers.  Loads and stores through
+// them compile to global_* instructions, counted by the vector-memory counter
+// only; the generic (flat_*) form also counts against the LDS counter, so an
+// LDS read that waits would wait for every memory load in flight as well.
+template <typename T> using gp = __attribute__((address_space(1))) T *;
+template <typename T> __device__ inline gp<const T> gptr(const T *p) { return (gp<const T>)p; }
+template <typename T> __device__ inline gp<T> gptr(T *p) { return (gp<T>)p; }
+
 // Morton codes: bit b of the x, y, z cell index sits at code bits 3b+2, 3b+1, 3b.
 __host__ __device__ inline void deinterleave(uint64_t code, int l, int c[3])
 {

@@ -442,30 +442,36 @@ __global__ __launch_bounds__(64) void k_far(const PlanView *V, Bases B)
 }
 
 // ---------------- P2P and output ----------------
-// Four wavefronts per block, one target leaf each.  Leaves with <= 32 (16)
-// targets split every source chunk into 2 (4) contiguous ranges handled by
-// separate lane groups, whose partial sums are combined in a fixed order at
-// the end.  Source chunks (<= 64 particles of one U-list box) are staged in
-// LDS as 32-byte records; the next chunk is loaded into registers while the
-// current one is summed.  FP64: plain sums.  Mixed: pair offsets are formed in
-// FP64 and rounded to FP32, the pair terms are FP32 (hardware rsq), each chunk
-// is summed in FP32 and the chunk partials are accumulated in FP64.
+// Four wavefronts per block, one target leaf each.  A pass takes up to 64
+// targets of the leaf; every lane holds two of them (targets t and t + TPG,
+// TPG = ceil(c/2) for the c targets of the pass), and the 64 / TPG lane groups
+// split every source chunk into contiguous ranges, so that each source read
+// from LDS serves two pairs and few lanes idle.  The group partial sums are
+// combined in a fixed order at the end.  Source chunks (<= 64 particles of one
+// U-list box) are staged in LDS as 32-byte records; the next chunk is loaded
+// into registers while the current one is summed.  FP64: plain sums.  Mixed:
+// pair offsets are formed in FP64 and rounded to FP32, the pair terms are FP32
+// (hardware rsq), each lane sums a chunk in FP32 and the chunk partials are
+// accumulated in FP64.
 struct SrcRec {
     double x, y, z, q;
 };
 
+struct Tgt {
+    double x, y, z;
+    int i;
+    double phi, ex, ey, ez;
+};
+
 template <int MIXED>
-__device__ inline void p2p_range(const SrcRec *S, int lo, int hi, int jbase, int i, double xi,
-                                 double yi, double zi, double &phi, double &ex, double &ey,
-                                 double &ez)
+__device__ inline void p2p_range(const SrcRec *S, int lo, int hi, int jbase, Tgt &a, Tgt &b)
 {
     if (MIXED) {
-        float p = 0.f, fx = 0.f, fy = 0.f, fz = 0.f;
-        auto pair = [&](int jj) {
-            const SrcRec s = S[jj];
-            const float dx = (float)(xi - s.x), dy = (float)(yi - s.y), dz = (float)(zi - s.z);
+        float pa = 0.f, ax = 0.f, ay = 0.f, az = 0.f, pb = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
+        auto term = [](const SrcRec &s, const Tgt &t, int j, float &p, float &fx, float &fy, float &fz) {
+            const float dx = (float)(t.x - s.x), dy = (float)(t.y - s.y), dz = (float)(t.z - s.z);
             const float r2 = dx * dx + dy * dy + dz * dz;
-            const bool ok = (jbase + jj != i) && r2 > 0.f;
+            const bool ok = j != t.i && r2 > 0.f;
             float ri = __builtin_amdgcn_rsqf(r2);
             ri = ok ? ri : 0.f;
             const float qr = (float)s.q * ri;
@@ -474,25 +480,45 @@ __device__ inline void p2p_range(const SrcRec *S, int lo, int hi, int jbase, int
             fx += qr3 * dx; fy += qr3 * dy; fz += qr3 * dz;
         };
         int jj = lo;
-        for (; jj + 4 <= hi; jj += 4) { pair(jj); pair(jj + 1); pair(jj + 2); pair(jj + 3); }
-        for (; jj < hi; ++jj) pair(jj);
-        phi += (double)p; ex += (double)fx; ey += (double)fy; ez += (double)fz;
+        for (; jj + 2 <= hi; jj += 2) {
+            const SrcRec s0 = S[jj], s1 = S[jj + 1];
+            term(s0, a, jbase + jj, pa, ax, ay, az);
+            term(s0, b, jbase + jj, pb, bx, by, bz);
+            term(s1, a, jbase + jj + 1, pa, ax, ay, az);
+            term(s1, b, jbase + jj + 1, pb, bx, by, bz);
+        }
+        if (jj < hi) {
+            const SrcRec s0 = S[jj];
+            term(s0, a, jbase + jj, pa, ax, ay, az);
+            term(s0, b, jbase + jj, pb, bx, by, bz);
+        }
+        a.phi += (double)pa; a.ex += (double)ax; a.ey += (double)ay; a.ez += (double)az;
+        b.phi += (double)pb; b.ex += (double)bx; b.ey += (double)by; b.ez += (double)bz;
     } else {
-        auto pair = [&](int jj) {
-            const SrcRec s = S[jj];
-            const double dx = xi - s.x, dy = yi - s.y, dz = zi - s.z;
+        auto term = [](const SrcRec &s, Tgt &t, int j) {
+            const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const bool ok = (jbase + jj != i) && r2 > 0.0;
+            const bool ok = j != t.i && r2 > 0.0;
             double ri = rsqrt(r2);
             ri = ok ? ri : 0.0;
             const double qr = s.q * ri;
             const double qr3 = qr * ri * ri;
-            phi += qr;
-            ex += qr3 * dx; ey += qr3 * dy; ez += qr3 * dz;
+            t.phi += qr;
+            t.ex += qr3 * dx; t.ey += qr3 * dy; t.ez += qr3 * dz;
         };
         int jj = lo;
-        for (; jj + 4 <= hi; jj += 4) { pair(jj); pair(jj + 1); pair(jj + 2); pair(jj + 3); }
-        for (; jj < hi; ++jj) pair(jj);
+        for (; jj + 2 <= hi; jj += 2) {
+            const SrcRec s0 = S[jj], s1 = S[jj + 1];
+            term(s0, a, jbase + jj);
+            term(s0, b, jbase + jj);
+            term(s1, a, jbase + jj + 1);
+            term(s1, b, jbase + jj + 1);
+        }
+        if (jj < hi) {
+            const SrcRec s0 = S[jj];
+            term(s0, a, jbase + jj);
+            term(s0, b, jbase + jj);
+        }
     }
 }
 
@@ -500,37 +526,49 @@ template <int MIXED>
 __global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B)
 {
     __shared__ SrcRec sS[4][64];
+    __shared__ double sR[4][8][64]; // group partials for the final combination
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]) * 4 + wave;
     if (li >= v.nleaves) return;
+    const auto first = gptr(v.first), count = gptr(v.count), usrc = gptr(v.U_src);
+    const auto xs = gptr(v.xs), ys = gptr(v.ys), zs = gptr(v.zs);
+    const auto qs = gptr(v.qs);
     const int box = v.leaves[li];
-    const int f = v.first[box], cnt = v.count[box];
-    const int G = cnt > 32 ? 1 : (cnt > 16 ? 2 : 4);
-    const int TPG = 64 / G, grp = lane / TPG, tl = lane % TPG;
+    const int f = first[box], cnt = count[box];
     const int64_t u0 = v.U_off[box], u1 = v.U_off[box + 1];
     SrcRec *S = sS[wave];
-    for (int ts = 0; ts < cnt; ts += TPG) {
-        const int ti = ts + tl;
-        const bool act = ti < cnt;
-        const int i = f + (act ? ti : 0);
-        const double xi = v.xs[i], yi = v.ys[i], zi = v.zs[i];
-        double phi = 0.0, ex = 0.0, ey = 0.0, ez = 0.0;
+    double(*R)[64] = sR[wave];
+    for (int ts = 0; ts < cnt; ts += 64) {
+        const int c = cnt - ts < 64 ? cnt - ts : 64;
+        const int TPG = (c + 1) >> 1, G = 64 / TPG, grp = lane / TPG, tl = lane - grp * TPG;
+        const bool inG = grp < G;
+        const bool acta = inG && tl < c, actb = inG && tl + TPG < c;
+        Tgt ta, tb;
+        ta.i = f + ts + (acta ? tl : 0);
+        tb.i = actb ? f + ts + tl + TPG : -1;
+        {
+            const int ib = actb ? tb.i : ta.i;
+            ta.x = xs[ta.i]; ta.y = ys[ta.i]; ta.z = zs[ta.i];
+            tb.x = xs[ib]; tb.y = ys[ib]; tb.z = zs[ib];
+        }
+        ta.phi = ta.ex = ta.ey = ta.ez = 0.0;
+        tb.phi = tb.ex = tb.ey = tb.ez = 0.0;
         // walk (U entry, 64-particle chunk) pairs with one chunk prefetched
         int64_t e = u0;
         int s = 0, sf = 0, sc = 0;
-        if (e < u1) { int src = v.U_src[e]; sf = v.first[src]; sc = v.count[src]; }
+        if (e < u1) { int src = usrc[e]; sf = first[src]; sc = count[src]; }
         SrcRec nx{0, 0, 0, 0};
         auto fetch = [&](int base, int m) {
             if (lane < m) {
                 const int j = base + lane;
-                nx.x = v.xs[j]; nx.y = v.ys[j]; nx.z = v.zs[j]; nx.q = v.qs[j];
+                nx.x = xs[j]; nx.y = ys[j]; nx.z = zs[j]; nx.q = qs[j];
             }
         };
         // advance to the first non-empty chunk
         while (e < u1 && sc == 0) {
-            if (++e < u1) { int src = v.U_src[e]; sf = v.first[src]; sc = v.count[src]; }
+            if (++e < u1) { int src = usrc[e]; sf = first[src]; sc = count[src]; }
         }
         if (e < u1) fetch(sf, sc < 64 ? sc : 64);
         while (e < u1) {
@@ -543,29 +581,38 @@ __global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B)
             if (s >= sc) {
                 s = 0;
                 do {
-                    if (++e < u1) { int src = v.U_src[e]; sf = v.first[src]; sc = v.count[src]; }
+                    if (++e < u1) { int src = usrc[e]; sf = first[src]; sc = count[src]; }
                 } while (e < u1 && sc == 0);
             }
             if (e < u1) fetch(sf + s, sc - s < 64 ? sc - s : 64);
-            const int per = (m + G - 1) / G, lo = grp * per, hi = lo + per < m ? lo + per : m;
-            p2p_range<MIXED>(S, lo, hi, jbase, i, xi, yi, zi, phi, ex, ey, ez);
+            const int per = (m + G - 1) / G;
+            const int lo = inG ? grp * per : m, hi = lo + per < m ? lo + per : m;
+            p2p_range<MIXED>(S, lo, hi, jbase, ta, tb);
         }
-        // combine lane groups in a fixed order
-        if (G >= 4) {
-            phi += __shfl_down(phi, 16); ex += __shfl_down(ex, 16);
-            ey += __shfl_down(ey, 16); ez += __shfl_down(ez, 16);
-        }
-        if (G >= 2) {
-            phi += __shfl_down(phi, 32); ex += __shfl_down(ex, 32);
-            ey += __shfl_down(ey, 32); ez += __shfl_down(ez, 32);
-        }
-        if (act && grp == 0) {
-            int o = v.perm[i];
-            v.phi_out[o] = v.phi_far[i] + phi;
-            if (v.fld_out) {
-                v.fld_out[3 * o] = v.fld_far[3 * i] + ex;
-                v.fld_out[3 * o + 1] = v.fld_far[3 * i + 1] + ey;
-                v.fld_out[3 * o + 2] = v.fld_far[3 * i + 2] + ez;
+        // combine the lane groups in a fixed order
+        wave_sync();
+        R[0][lane] = ta.phi; R[1][lane] = ta.ex; R[2][lane] = ta.ey; R[3][lane] = ta.ez;
+        R[4][lane] = tb.phi; R[5][lane] = tb.ex; R[6][lane] = tb.ey; R[7][lane] = tb.ez;
+        wave_sync();
+        if (lane < TPG) {
+            double acc[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) acc[r] = R[r][lane];
+            for (int g = 1; g < G; ++g)
+#pragma unroll
+                for (int r = 0; r < 8; ++r) acc[r] += R[r][g * TPG + lane];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int t = lane + h * TPG;
+                if (t >= c) continue;
+                const int i = f + ts + t;
+                const int o = v.perm[i];
+                v.phi_out[o] = v.phi_far[i] + acc[4 * h];
+                if (v.fld_out) {
+                    v.fld_out[3 * o] = v.fld_far[3 * i] + acc[4 * h + 1];
+                    v.fld_out[3 * o + 1] = v.fld_far[3 * i + 1] + acc[4 * h + 2];
+                    v.fld_out[3 * o + 2] = v.fld_far[3 * i + 2] + acc[4 * h + 3];
+                }
             }
         }
     }
