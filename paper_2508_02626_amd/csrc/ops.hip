@@ -463,17 +463,29 @@ struct Tgt {
     double phi, ex, ey, ez;
 };
 
+// 1/sqrt(x) for finite x > 0: the hardware estimate (relative error about
+// 2^-24) refined by one third-order Householder step,
+// y' = y (1 + e/2 + 3e^2/8) with e = 1 - x y^2, which leaves an error at the
+// level of the final rounding.  x = 0 gives NaN (callers select it away).
+__device__ inline double rsqrt_refined(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-(x * y), y, 1.0);
+    return fma(y, e * fma(e, 0.375, 0.5), y);
+}
+
+// A pair contributes iff r^2 > 0: this skips j == i (same coordinates) and
+// coincident points alike.
 template <int MIXED>
-__device__ inline void p2p_range(const SrcRec *S, int lo, int hi, int jbase, Tgt &a, Tgt &b)
+__device__ inline void p2p_range(const SrcRec *S, int lo, int hi, Tgt &a, Tgt &b)
 {
     if (MIXED) {
         float pa = 0.f, ax = 0.f, ay = 0.f, az = 0.f, pb = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
-        auto term = [](const SrcRec &s, const Tgt &t, int j, float &p, float &fx, float &fy, float &fz) {
+        auto term = [](const SrcRec &s, const Tgt &t, float &p, float &fx, float &fy, float &fz) {
             const float dx = (float)(t.x - s.x), dy = (float)(t.y - s.y), dz = (float)(t.z - s.z);
             const float r2 = dx * dx + dy * dy + dz * dz;
-            const bool ok = j != t.i && r2 > 0.f;
             float ri = __builtin_amdgcn_rsqf(r2);
-            ri = ok ? ri : 0.f;
+            ri = r2 > 0.f ? ri : 0.f;
             const float qr = (float)s.q * ri;
             const float qr3 = qr * ri * ri;
             p += qr;
@@ -482,25 +494,23 @@ __device__ inline void p2p_range(const SrcRec *S, int lo, int hi, int jbase, Tgt
         int jj = lo;
         for (; jj + 2 <= hi; jj += 2) {
             const SrcRec s0 = S[jj], s1 = S[jj + 1];
-            term(s0, a, jbase + jj, pa, ax, ay, az);
-            term(s0, b, jbase + jj, pb, bx, by, bz);
-            term(s1, a, jbase + jj + 1, pa, ax, ay, az);
-            term(s1, b, jbase + jj + 1, pb, bx, by, bz);
+            term(s0, a, pa, ax, ay, az);
+            term(s0, b, pb, bx, by, bz);
+            term(s1, a, pa, ax, ay, az);
+            term(s1, b, pb, bx, by, bz);
         }
         if (jj < hi) {
             const SrcRec s0 = S[jj];
-            term(s0, a, jbase + jj, pa, ax, ay, az);
-            term(s0, b, jbase + jj, pb, bx, by, bz);
+            term(s0, a, pa, ax, ay, az);
+            term(s0, b, pb, bx, by, bz);
         }
         a.phi += (double)pa; a.ex += (double)ax; a.ey += (double)ay; a.ez += (double)az;
         b.phi += (double)pb; b.ex += (double)bx; b.ey += (double)by; b.ez += (double)bz;
     } else {
-        auto term = [](const SrcRec &s, Tgt &t, int j) {
+        auto term = [](const SrcRec &s, Tgt &t) {
             const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
             const double r2 = dx * dx + dy * dy + dz * dz;
-            const bool ok = j != t.i && r2 > 0.0;
-            double ri = rsqrt(r2);
-            ri = ok ? ri : 0.0;
+            const double ri = r2 > 0.0 ? rsqrt_refined(r2) : 0.0;
             const double qr = s.q * ri;
             const double qr3 = qr * ri * ri;
             t.phi += qr;
@@ -509,15 +519,15 @@ __device__ inline void p2p_range(const SrcRec *S, int lo, int hi, int jbase, Tgt
         int jj = lo;
         for (; jj + 2 <= hi; jj += 2) {
             const SrcRec s0 = S[jj], s1 = S[jj + 1];
-            term(s0, a, jbase + jj);
-            term(s0, b, jbase + jj);
-            term(s1, a, jbase + jj + 1);
-            term(s1, b, jbase + jj + 1);
+            term(s0, a);
+            term(s0, b);
+            term(s1, a);
+            term(s1, b);
         }
         if (jj < hi) {
             const SrcRec s0 = S[jj];
-            term(s0, a, jbase + jj);
-            term(s0, b, jbase + jj);
+            term(s0, a);
+            term(s0, b);
         }
     }
 }
@@ -572,7 +582,7 @@ __global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B)
         }
         if (e < u1) fetch(sf, sc < 64 ? sc : 64);
         while (e < u1) {
-            const int jbase = sf + s, m = sc - s < 64 ? sc - s : 64;
+            const int m = sc - s < 64 ? sc - s : 64;
             wave_sync();
             S[lane] = nx;
             wave_sync();
@@ -587,7 +597,7 @@ __global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B)
             if (e < u1) fetch(sf + s, sc - s < 64 ? sc - s : 64);
             const int per = (m + G - 1) / G;
             const int lo = inG ? grp * per : m, hi = lo + per < m ? lo + per : m;
-            p2p_range<MIXED>(S, lo, hi, jbase, ta, tb);
+            p2p_range<MIXED>(S, lo, hi, ta, tb);
         }
         // combine the lane groups in a fixed order
         wave_sync();
