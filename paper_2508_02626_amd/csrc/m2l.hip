@@ -14,9 +14,9 @@
 // the slot.  For every offset slot each wavefront runs a (p+1)^2 x (p+1)^2 by
 // 16 product with 16x16x4 MFMAs: A[b][a] = D(addr(b) + addr(a)) is gathered
 // from the slot's derivative table in LDS with the additive address
-// addr(i,j,k) = k s2 + i (2p+2) + j, which turns the Hankel structure of the
-// matrix into a single add per operand (the x stride 2p+2 keeps the 16 rows of
-// one operand load in different LDS banks); B, the 16 source vectors, is
+// addr(i,j,k) = k s2 + i s1 + j, which turns the Hankel structure of the
+// matrix into a single add per operand (the strides s1, s2 are chosen per
+// order to spread one operand load over the LDS banks); B, the 16 source vectors, is
 // loaded from memory straight into the lanes that feed it to the MFMA, one
 // slot ahead (each k-step's operand register is refilled for the next slot
 // once its MFMAs are issued).  The derivative tables are double-buffered in
@@ -81,6 +81,8 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     __shared__ int sHo[NK];
     __shared__ int sTg[64];
     __shared__ int sList[kVSlots];
+    __shared__ int sSrc[64][kVSlots]; // slot rows of the block's targets
+    __shared__ int sDoff[kVSlots];     // derivative table of each slot of this octant
     __shared__ int sN, soct;
 
     const int k = find_plan(B, blockIdx.x);
@@ -103,15 +105,21 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
 #pragma unroll
     for (int x = 0; x < XR; ++x) hx[x] = tb.hoff[16 * MT + x];
     __syncthreads();
-    // slots used by at least one target of the block, in increasing order
-    const int32_t *vs = v.vslot;
+    // the targets' slot rows, then the slots used by at least one target of
+    // the block, in increasing order
+    {
+        const auto vs = gptr(v.vslot);
+        for (int e = tid; e < 64 * kVSlots; e += 256) {
+            const int t = e / kVSlots, j = e - t * kVSlots, g = sTg[t];
+            sSrc[t][j] = g >= 0 ? vs[(int64_t)g * kVSlots + j] : -1;
+        }
+    }
+    __syncthreads();
     if (tid < kVSlots) {
         bool any = false;
-        for (int t = 0; t < 64 && !any; ++t) {
-            int g = sTg[t];
-            any = g >= 0 && vs[(int64_t)g * kVSlots + tid] >= 0;
-        }
+        for (int t = 0; t < 64; ++t) any = any || sSrc[t][tid] >= 0;
         sList[tid] = any ? 1 : 0;
+        sDoff[tid] = gptr(tb.offs)[soct * kVSlots + tid] * LDD;
     }
     __syncthreads();
     if (tid == 0) {
@@ -121,10 +129,10 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         sN = n;
     }
     __syncthreads();
-    const int nvalid = sN, oct = soct, ldh = v.ldh;
+    const int nvalid = sN, ldh = v.ldh;
     const T *Dt = Mfma<T>::D(tb);
     const T *Mh = Mfma<T>::M(v);
-    const int32_t *vsl = vs + (int64_t)(tgt >= 0 ? tgt : 0) * kVSlots;
+    const int *vsl = sSrc[wave * 16 + col];
 
     acc_t acc[MT];
     double4_t acc64[MT]; // FP32 path: per-offset partials are summed in FP64
@@ -138,7 +146,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     // B operand of k-step ks: component 4 ks + kq of this lane's source
     T pb[KS], pd[DR];
     auto load_d = [&](int j) {
-        const T *Dk = Dt + (int64_t)tb.offs[oct * kVSlots + j] * LDD;
+        const T *Dk = Dt + sDoff[j];
 #pragma unroll
         for (int r = 0; r < DR; ++r) {
             int e = tid + 256 * r;
@@ -166,7 +174,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
             int e = tid + 256 * r;
             if (e < LDD) sD[0][e] = pd[r];
         }
-        src = tgt >= 0 ? gload(vsl + sList[0]) : -1;
+        src = vsl[sList[0]];
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) load_b(ks, src);
         if constexpr (DB) {
@@ -180,7 +188,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         const bool more = q + 1 < nvalid;
         const int jn = more ? sList[q + 1] : 0;
         if (more) load_d(jn); // in flight during the products
-        const int nsrc = (more && tgt >= 0) ? gload(vsl + jn) : -1;
+        const int nsrc = more ? vsl[jn] : -1;
         const T *D = sD[cur];
         if constexpr (DB) {
 #pragma unroll

@@ -170,9 +170,8 @@ void build_tables(int p, Built &B)
 {
     Mono m(p);
     const int nc = m.n, nh = nharm(p), ldh = pad16(nh);
-    // additive layout addr(i,j,k) = k*s2 + i*s1 + j of the derivative tables;
-    // s1 = 2p+2 makes consecutive harmonic indices (x down, y up) step by the
-    // odd amount 2p+1, so 16 MFMA rows read 16 different LDS banks
+    // additive layout addr(i,j,k) = k*s2 + i*s1 + j of the derivative tables
+    // (strides per order, chosen for the M2L operand gather)
     const int s1 = dlayout_s1(p), s2 = dlayout_s2(p);
     // exponent packing, factorial tables
     B.exps.resize(nc);
