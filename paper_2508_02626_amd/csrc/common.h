@@ -58,7 +58,7 @@ __host__ __device__ constexpr int dlayout_s2(int p)
     constexpr int t[13] = {1, 11, 30, 49, 91, 125, 184, 252, 328, 392, 516, 580, 719};
     return t[p];
 }
-__host__ __device__ constexpr int dlayout_ldd(int p) { return (3 * dlayout_s2(p) + 1) & ~1; }
+__host__ __device__ constexpr int dlayout_ldd(int p) { return (3 * dlayout_s2(p) + 3) & ~3; } // 16-byte rows
 inline int pad4(int n) { return (n + 3) & ~3; }
 
 // LDS exchange between the lanes of one wavefront (no workgroup barrier: the

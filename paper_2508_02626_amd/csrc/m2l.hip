@@ -72,13 +72,25 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     constexpr bool XV = MF >= 1 && XR0 <= 2;     // leftover rows go to the VALU
     constexpr int MT = XV ? MF : (NH + 15) / 16; // MFMA row tiles
     constexpr int XR = XV ? XR0 : 0;             // VALU rows
-    constexpr int NK = (NH + 3) & ~3;
-    constexpr int KS = NK / 4;
+    // K order: k-step ks gives lane group kq the index
+    // a = 8 (ks / 2) + 2 kq + ks % 2, so that the two steps of a pair read two
+    // consecutive components of the lane's source: B operands come as aligned
+    // pairs.  (p+1)^2 = 1 (mod 8) for even p, so a lone last step covers what
+    // is left; odd p with an odd number of 4-index steps takes one more step.
+    constexpr int KS0 = (NH + 3) / 4;
+    constexpr int KS = (KS0 % 2 == 0 || NH - 8 * (KS0 / 2) <= 1) ? KS0 : KS0 + 1;
+    constexpr int VW = 2;
+    constexpr int NV = (KS + 1) / 2; // pair loads per lane and slot
+    static_assert(8 * NV <= ((NH + 15) & ~15), "pairs must stay inside a padded row");
     constexpr int LDD = dlayout_ldd(P);
-    constexpr int DR = (LDD + 255) / 256; // derivative-table words per thread
+    constexpr int DW = 16 / (int)sizeof(T); // derivative tables move in 16-byte vectors
+    static_assert(LDD % DW == 0, "derivative rows must be whole vectors");
+    constexpr int DV = (LDD / DW + 255) / 256; // derivative-table vectors per thread
     typedef typename Mfma<T>::acc_t acc_t;
-    __shared__ T sD[2][LDD];
-    __shared__ int sHo[NK];
+    typedef T vec_t __attribute__((ext_vector_type(2)));
+    typedef T dvec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+    __shared__ dvec_t sD[2][LDD / DW];
+    __shared__ int sHo[4][KS]; // additive address of the K index of (ks, kq) (0 if padding)
     __shared__ int sTg[64];
     __shared__ int sList[kVSlots];
     __shared__ int sSrc[64][kVSlots]; // slot rows of the block's targets
@@ -95,7 +107,10 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     if (tgt >= 0) soct = (int)(v.morton[tgt] & 7); // every target of the block has this octant
     if (tid < 64) sTg[tid] = v.m2l_tgt[tile * kM2LSlots + tid];
     const OrderTables &tb = *v.tab;
-    for (int a = tid; a < NK; a += 256) sHo[a] = a < NH ? tb.hoff[a] : 0;
+    for (int e = tid; e < 4 * KS; e += 256) {
+        const int g = e / KS, ks = e - g * KS, a = 8 * (ks / 2) + 2 * g + ks % 2;
+        sHo[g][ks] = a < NH ? tb.hoff[a] : 0;
+    }
     int hb[MT], hx[XR > 0 ? XR : 1];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
@@ -143,43 +158,47 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
 #pragma unroll
     for (int x = 0; x < XR; ++x) { xacc[x] = (T)0; xacc64[x] = 0.0; }
 
-    // B operand of k-step ks: component 4 ks + kq of this lane's source
-    T pb[KS], pd[DR];
+    // B operands of k-steps 2 vi and 2 vi + 1: components 8 vi + 2 kq (+1)
+    vec_t pb[NV];
+    dvec_t pd[DV];
     auto load_d = [&](int j) {
-        const T *Dk = Dt + sDoff[j];
+        const dvec_t *Dk = (const dvec_t *)(Dt + sDoff[j]);
 #pragma unroll
-        for (int r = 0; r < DR; ++r) {
+        for (int r = 0; r < DV; ++r) {
             int e = tid + 256 * r;
-            pd[r] = e < LDD ? gload(Dk + e) : (T)0;
+            pd[r] = e < LDD / DW ? gload(Dk + e) : dvec_t{};
         }
     };
-    // always issued (clamped address), so that the waits can count the loads;
-    // operands of absent sources and padding components are zeroed at use.
-    // FP64: each k-step's register is refilled for the next slot right after
-    // its MFMAs (no second register set); FP32: the next slot's operands go to
-    // a second set loaded at the top of the slot.
+    auto store_d = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < DV; ++r) {
+            int e = tid + 256 * r;
+            if (e < LDD / DW) sD[buf][e] = pd[r];
+        }
+    };
+    // always issued (a clamped row for absent sources), so that the waits can
+    // count the loads; operands of absent sources and padding components are
+    // zeroed at use.  FP64: each vector register is refilled for the next slot
+    // right after its MFMAs (no second register set); FP32: the next slot's
+    // operands go to a second set loaded at the top of the slot.
     constexpr bool DB = sizeof(T) == 4;
-    T pbn[DB ? KS : 1];
-    auto load_b = [&](int ks, int src) {
-        const int a = 4 * ks + kq;
-        const T val = gload(Mh + (int64_t)(src >= 0 ? src : 0) * ldh + (a < NH ? a : NH - 1));
-        if constexpr (DB) pbn[ks] = val;
-        else pb[ks] = val;
+    vec_t pbn[DB ? NV : 1];
+    const int64_t kofs = 2 * kq;
+    auto load_b = [&](int vi, int src) {
+        const vec_t val = gload((const vec_t *)(Mh + (int64_t)(src >= 0 ? src : 0) * ldh + kofs) + 4 * vi);
+        if constexpr (DB) pbn[vi] = val;
+        else pb[vi] = val;
     };
     int src = -1;
     if (nvalid > 0) {
         load_d(sList[0]);
-#pragma unroll
-        for (int r = 0; r < DR; ++r) {
-            int e = tid + 256 * r;
-            if (e < LDD) sD[0][e] = pd[r];
-        }
+        store_d(0);
         src = vsl[sList[0]];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) load_b(ks, src);
+        for (int vi = 0; vi < NV; ++vi) load_b(vi, src);
         if constexpr (DB) {
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) pb[ks] = pbn[ks];
+            for (int vi = 0; vi < NV; ++vi) pb[vi] = pbn[vi];
         }
         __syncthreads();
     }
@@ -189,34 +208,36 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         const int jn = more ? sList[q + 1] : 0;
         if (more) load_d(jn); // in flight during the products
         const int nsrc = more ? vsl[jn] : -1;
-        const T *D = sD[cur];
+        const T *D = (const T *)sD[cur];
+        const int *Ho = sHo[kq];
         if constexpr (DB) {
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) load_b(ks, nsrc);
+            for (int vi = 0; vi < NV; ++vi) load_b(vi, nsrc);
             __builtin_amdgcn_sched_barrier(0); // keep the loads ahead of the products
         }
         {
             // A operands of step ks+1 are read from LDS while the MFMAs of step ks run
             T ac[MT], an[MT];
             {
-                const int ha = sHo[kq];
+                const int ha = Ho[0];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) ac[mt] = D[hb[mt] + ha];
             }
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                const int ha = sHo[4 * ks + kq];
+                const int ha = Ho[ks];
                 if (ks + 1 < KS) {
-                    const int hn = sHo[4 * (ks + 1) + kq];
+                    const int hn = Ho[ks + 1];
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) an[mt] = D[hb[mt] + hn];
                 }
-                const T bv = (src >= 0 && 4 * ks + kq < NH) ? pb[ks] : (T)0;
+                const T bv = (src >= 0 && 8 * (ks / 2) + 2 * kq + ks % 2 < NH) ? pb[ks / VW][ks % VW] : (T)0;
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) acc[mt] = Mfma<T>::run(ac[mt], bv, acc[mt]);
 #pragma unroll
                 for (int x = 0; x < XR; ++x) xacc[x] += D[hx[x] + ha] * bv;
-                if constexpr (!DB) load_b(ks, nsrc); // next slot's operand, consumed one slot later
+                if constexpr (!DB) // next slot's operands, once this vector is used up
+                    if (ks % VW == VW - 1 || ks == KS - 1) load_b(ks / VW, nsrc);
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) ac[mt] = an[mt];
             }
@@ -233,15 +254,9 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         }
         if constexpr (DB) {
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) pb[ks] = pbn[ks];
+            for (int vi = 0; vi < NV; ++vi) pb[vi] = pbn[vi];
         }
-        if (more) {
-#pragma unroll
-            for (int r = 0; r < DR; ++r) {
-                int e = tid + 256 * r;
-                if (e < LDD) sD[cur ^ 1][e] = pd[r];
-            }
-        }
+        if (more) store_d(cur ^ 1);
         src = nsrc;
         __syncthreads(); // next table written; everyone is done with this one
     }
