@@ -410,7 +410,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     int32_t *oval = P->temp<int32_t>(nt + 1), *otv = P->temp<int32_t>(nt + 1);
     int32_t *oscr = P->temp<int32_t>(sort_scratch_bytes(nt + 1) / 4 + 1);
     NOMEM(octoff); NOMEM(okey); NOMEM(otk); NOMEM(oval); NOMEM(otv); NOMEM(oscr);
-    m2l_tiles(bx, mtg, nt, okey, oval, otk, otv, oscr, octoff, slots, slot_cap, s);
+    m2l_tiles(bx, mtg, nt, P->uniform, okey, oval, otk, otv, oscr, octoff, slots, slot_cap, s);
     P->nslots = (int)slot_cap;
 
     PlanView &v = P->view;

@@ -674,14 +674,31 @@ void compact(const int64_t *flag, const int64_t *pos, int nboxes, int32_t *out, 
 // ---------------- M2L target tiles ----------------
 // Targets (boxes with a V list, ascending) are stably sorted by octant, then
 // each octant group is placed at a multiple of 64 so that the 64 targets of
-// one M2L block share one set of 189 offsets.
-__global__ __launch_bounds__(256) void k_oct_keys(const BoxArrays bx, const int32_t *tg, int nt,
+// one M2L block share one set of 189 offsets.  In a uniform tree the offsets a
+// box actually has depend only on its octant and on its distance (0, 1, 2 or
+// more cells) to each face of the root, so there the targets are also grouped
+// by these distances (Morton order inside a group): the blocks near the faces
+// then skip the offsets none of their targets has.
+constexpr int kCatBits = 12;
+
+__global__ __launch_bounds__(256) void k_oct_keys(const BoxArrays bx, const int32_t *tg, int nt, int uniform,
                                                   uint64_t *key, int32_t *val)
 {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= nt) return;
-    key[i] = bx.morton[tg[i]] & 7;
-    val[i] = tg[i];
+    const int b = tg[i];
+    uint64_t cat = 0;
+    if (uniform) {
+        const int l = bx.level[b], side = 1 << l;
+        int c[3];
+        deinterleave(bx.morton[b], l, c);
+        for (int k = 0; k < 3; ++k) {
+            const int lo = c[k] < 3 ? c[k] : 3, hi = side - 1 - c[k] < 3 ? side - 1 - c[k] : 3;
+            cat |= (uint64_t)(lo * 4 + hi) << (4 * k);
+        }
+    }
+    key[i] = ((bx.morton[b] & 7) << kCatBits) | cat;
+    val[i] = b;
 }
 
 // start of every octant in the sorted keys, and the padded output offsets
@@ -693,7 +710,7 @@ __global__ void k_oct_offsets(const uint64_t *key, int nt, int *octoff)
         int lo = 0, hi = nt;
         while (lo < hi) {
             int mid = (lo + hi) >> 1;
-            if (key[mid] < (uint64_t)o) lo = mid + 1; else hi = mid;
+            if ((key[mid] >> kCatBits) < (uint64_t)o) lo = mid + 1; else hi = mid;
         }
         st[o] = o == 8 ? nt : lo;
     }
@@ -715,7 +732,7 @@ __global__ __launch_bounds__(256) void k_oct_place(const uint64_t *key, const in
 {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= nt) return;
-    int o = (int)key[i];
+    int o = (int)(key[i] >> kCatBits);
     slots[octoff[o] + (i - octoff[9 + o])] = val[i];
 }
 
@@ -730,14 +747,14 @@ void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
     if (n > 0) k_fill_i32<<<ceil_div(n, 256), 256, 0, s>>>(p, n, v);
 }
 
-void m2l_tiles(const BoxArrays &bx, const int32_t *tg, int nt, uint64_t *key, int32_t *val,
+void m2l_tiles(const BoxArrays &bx, const int32_t *tg, int nt, int uniform, uint64_t *key, int32_t *val,
                uint64_t *tk, int32_t *tv, int32_t *sort_scratch, int *octoff, int32_t *slots,
                int64_t slot_cap, hipStream_t s)
 {
     fill_i32(slots, slot_cap, -1, s);
     if (nt == 0) return;
-    k_oct_keys<<<ceil_div(nt, 256), 256, 0, s>>>(bx, tg, nt, key, val);
-    radix_sort_pairs(key, val, tk, tv, nt, 3, sort_scratch, s);
+    k_oct_keys<<<ceil_div(nt, 256), 256, 0, s>>>(bx, tg, nt, uniform, key, val);
+    radix_sort_pairs(key, val, tk, tv, nt, kCatBits + 3, sort_scratch, s);
     k_oct_offsets<<<1, 64, 0, s>>>(key, nt, octoff);
     k_oct_place<<<ceil_div(nt, 256), 256, 0, s>>>(key, val, nt, octoff, slots);
 }
