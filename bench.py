@@ -13,9 +13,7 @@ timed for the plain FP64 path (reported as `value`) and for the mixed path
 The roofline entry is for the dominant kernel, M2L: its algorithmic work is
 2 (p+1)^4 flops per V-list pair (the harmonic contraction), measured with HIP
 events on the evaluation stream over the timed steps.  The CPU baseline times
-the plain oracle on a bounded sample: the points of one octant of the cube
-([0,0.5)^3, 1/8 of the input) with the same box width (uniform depth 4 on the
-half-size root), p = 8.
+the plain oracle on the same workload once (a few seconds on the host cores).
 
 Other workloads (--workload): plummer4m (4e6 Plummer points, adaptive s=64,
 p=10), batch256 (256 independent problems, one fmm_evaluate_batch), serve
@@ -43,7 +41,7 @@ FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS = 78.6, 157.3
 # FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration (read x2.0,
 # write x1.0; profiles/uniform1m_hbm_traffic.txt).  Valid only for the kernel
 # sources it was measured on: a different fingerprint reports null.
-M2L_TRAFFIC = {"fingerprint": "f3cb2fbfda46102a", "bytes": (3663.92 + 25.16) * 1e6}
+M2L_TRAFFIC = {"fingerprint": "398da7ea6d3c6576", "bytes": (3643.99 + 25.16) * 1e6}
 M2L_SOURCES = ("paper_2508_02626_amd/csrc/m2l.hip", "paper_2508_02626_amd/csrc/common.h")
 
 
@@ -97,19 +95,16 @@ def run_mode(x, q, precision, steps, warmup, n):
 
 
 def cpu_baseline(xh, qh):
-    """The oracle DA-FMM on the octant [0,0.5)^3 of the same input."""
+    """The oracle DA-FMM on the whole workload (same points, tree and order)."""
     import oracle
-    sel = np.all(xh < 0.5, axis=1)
-    xs, qs = xh[sel], qh[sel]
     t0 = time.perf_counter()
-    tree = oracle.Tree(xs, root=[0, 0, 0, 0.5], uniform_depth=DEPTH - 1)
-    tree.fmm(ORDER, qs)
+    tree = oracle.Tree(xh, root=[0, 0, 0, 1], uniform_depth=DEPTH)
+    tree.fmm(ORDER, qh)
     dt = time.perf_counter() - t0
-    return {"value": len(qs) / dt, "unit": "particles/s", "cores": oracle.num_threads(),
+    return {"value": len(qh) / dt, "unit": "particles/s", "cores": oracle.num_threads(),
             "kind": "oracle", "seconds": dt,
-            "sample": "oracle DA-FMM (TPSA operators, memoised translations) on the %d points of "
-                      "the octant [0,0.5)^3 of the same input, uniform depth 4 on the root [0,0.5]^3 "
-                      "(same box width), p=8, potential+field" % len(qs)}
+            "sample": "oracle DA-FMM (TPSA operators, memoised translations) on the whole workload: "
+                      "%d points, uniform depth %d on [0,1]^3, p=%d, potential+field" % (len(qh), DEPTH, ORDER)}
 
 
 def sampled_sigma(xh, qh, phi, fld, count=2000, seed=7):
