@@ -42,6 +42,7 @@ __host__ __device__ inline int harm_index(int i, int j, int kz)
     return n * n + (kz == 0 ? (n - i) : (n + 1) + (n - 1 - i));
 }
 inline int pad16(int n) { return (n + 15) & ~15; }
+inline int pad4(int n) { return (n + 3) & ~3; }
 // Additive layout of one offset's derivative table: addr(i,j,k) = k*s2 + i*s1 + j
 // for x, y exponents up to 2p and z exponent up to 2 (any s1 > 2p and
 // s2 > 2p (s1 + 1) keep it one-to-one).  The strides are chosen per order to
@@ -59,7 +60,11 @@ __host__ __device__ constexpr int dlayout_s2(int p)
     return t[p];
 }
 __host__ __device__ constexpr int dlayout_ldd(int p) { return (3 * dlayout_s2(p) + 3) & ~3; } // 16-byte rows
-inline int pad4(int n) { return (n + 3) & ~3; }
+// entries d^g with g_z <= 2, |g| <= 2p (the ones M2L reads), rounded up to 4
+__host__ __device__ constexpr int dlayout_ldc(int p)
+{
+    return ((2 * p + 1) * (2 * p + 2) / 2 + (2 * p) * (2 * p + 1) / 2 + (2 * p - 1) * (2 * p) / 2 + 3) & ~3;
+}
 
 // LDS exchange between the lanes of one wavefront (no workgroup barrier: the
 // wavefronts of a block run independent loops)
@@ -123,10 +128,12 @@ __host__ __device__ inline int vslot_of(int oct, int kx, int ky, int kz)
 
 // Per-order constant tables (device pointers), built once per order and device.
 struct OrderTables {
-    int p, nc, nh, ldm, ldh, ldd;   // ldd: stride of one offset's derivative table
+    int p, nc, nh, ldm, ldh, ldd;   // ldd: size of one offset's table in the additive (LDS) layout
+    int ldc;                        // stride of one offset's compact table
     int d3;                         // x stride of the additive D layout
-    const double *D;    // [343][ldd] derivative tensors d^g(1/|x|) at integer x, additive layout
+    const double *D;    // [343][ldc] derivative tensors d^g(1/|x|) at integer x, compact
     const float *Df;    // same in FP32
+    const int *dmap;    // [ldc] additive-layout address of each compact entry
     const int *offs;    // [8][189] packed offsets (kx+3)*49 + (ky+3)*7 + (kz+3)
     const int *hoff;    // [ldh] additive D address of each harmonic index (-1 padding)
     const double *S;    // [8][nc][nc] M2M, S[o][a][b] = d Mhat'_b / d Mhat_a

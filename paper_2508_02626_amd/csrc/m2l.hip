@@ -82,14 +82,15 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     constexpr int VW = 2;
     constexpr int NV = (KS + 1) / 2; // pair loads per lane and slot
     static_assert(8 * NV <= ((NH + 15) & ~15), "pairs must stay inside a padded row");
-    constexpr int LDD = dlayout_ldd(P);
-    constexpr int DW = 16 / (int)sizeof(T); // derivative tables move in 16-byte vectors
-    static_assert(LDD % DW == 0, "derivative rows must be whole vectors");
-    constexpr int DV = (LDD / DW + 255) / 256; // derivative-table vectors per thread
+    constexpr int LDD = dlayout_ldd(P); // table size in the additive LDS layout
+    constexpr int LDC = dlayout_ldc(P); // compact table in memory (only the entries read)
+    constexpr int DW = 16 / (int)sizeof(T); // compact tables move in 16-byte vectors
+    static_assert(LDC % DW == 0, "compact rows must be whole vectors");
+    constexpr int DV = (LDC / DW + 255) / 256; // table vectors per thread
     typedef typename Mfma<T>::acc_t acc_t;
     typedef T vec_t __attribute__((ext_vector_type(2)));
     typedef T dvec_t __attribute__((ext_vector_type(16 / sizeof(T))));
-    __shared__ dvec_t sD[2][LDD / DW];
+    __shared__ T sD[2][LDD];
     __shared__ int sHo[4][KS]; // additive address of the K index of (ks, kq) (0 if padding)
     __shared__ int sTg[64];
     __shared__ int sList[kVSlots];
@@ -134,7 +135,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         bool any = false;
         for (int t = 0; t < 64; ++t) any = any || sSrc[t][tid] >= 0;
         sList[tid] = any ? 1 : 0;
-        sDoff[tid] = gptr(tb.offs)[soct * kVSlots + tid] * LDD;
+        sDoff[tid] = gptr(tb.offs)[soct * kVSlots + tid] * LDC;
     }
     __syncthreads();
     if (tid == 0) {
@@ -161,20 +162,28 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     // B operands of k-steps 2 vi and 2 vi + 1: components 8 vi + 2 kq (+1)
     vec_t pb[NV];
     dvec_t pd[DV];
+    int dm[DV][DW]; // LDS address of each compact table entry this thread moves
+#pragma unroll
+    for (int r = 0; r < DV; ++r)
+#pragma unroll
+        for (int w = 0; w < DW; ++w) {
+            const int e = (tid + 256 * r) * DW + w;
+            dm[r][w] = e < LDC ? gptr(tb.dmap)[e] : LDD - 1;
+        }
     auto load_d = [&](int j) {
         const dvec_t *Dk = (const dvec_t *)(Dt + sDoff[j]);
 #pragma unroll
         for (int r = 0; r < DV; ++r) {
             int e = tid + 256 * r;
-            pd[r] = e < LDD / DW ? gload(Dk + e) : dvec_t{};
+            pd[r] = e < LDC / DW ? gload(Dk + e) : dvec_t{};
         }
     };
-    auto store_d = [&](int buf) {
+    auto store_d = [&](int buf) { // scatter into the additive layout
 #pragma unroll
-        for (int r = 0; r < DV; ++r) {
-            int e = tid + 256 * r;
-            if (e < LDD / DW) sD[buf][e] = pd[r];
-        }
+        for (int r = 0; r < DV; ++r)
+            if (tid + 256 * r < LDC / DW)
+#pragma unroll
+                for (int w = 0; w < DW; ++w) sD[buf][dm[r][w]] = pd[r][w];
     };
     // always issued (a clamped row for absent sources), so that the waits can
     // count the loads; operands of absent sources and padding components are
@@ -208,7 +217,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         const int jn = more ? sList[q + 1] : 0;
         if (more) load_d(jn); // in flight during the products
         const int nsrc = more ? vsl[jn] : -1;
-        const T *D = (const T *)sD[cur];
+        const T *D = sD[cur];
         const int *Ho = sHo[kq];
         if constexpr (DB) {
 #pragma unroll

@@ -24,6 +24,8 @@
 //  L2L     Taylor shift of a polynomial (map M3 of Sec. 2.5).
 #include "tables.h"
 
+#include <stdexcept>
+
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -162,8 +164,8 @@ std::vector<ld> harmonic_projection(const Mono &m, const std::vector<ld> &v, int
 struct Built {
     std::vector<double> D, S, G, P2M, P2L, fold_c, unfold_c, inv_fact, inv_w;
     std::vector<float> Df;
-    std::vector<int> offs, hoff, fold_off, fold_idx, unfold_off, unfold_idx, exps;
-    int ldd = 0;
+    std::vector<int> offs, hoff, fold_off, fold_idx, unfold_off, unfold_idx, exps, dmap;
+    int ldd = 0, ldc = 0;
 };
 
 void build_tables(int p, Built &B)
@@ -193,10 +195,20 @@ void build_tables(int p, Built &B)
     B.hoff.assign(ldh, 0);
     for (int c = 0; c < nh; ++c) B.hoff[c] = hz[c] * s2 + hx[c] * s1 + hy[c];
 
-    // derivative tensors at the 343 integer offsets (near ones left zero)
+    // derivative tensors at the 343 integer offsets (near ones left zero),
+    // stored compactly: only the entries d^g with g_z <= 2, |g| <= 2p that the
+    // M2L reads, in (z, x, y) order; dmap[e] is the additive LDS address of
+    // entry e (row padding -> ldd - 1, an address the layout never uses)
     B.ldd = dlayout_ldd(p);
-    B.D.assign((size_t)343 * B.ldd, 0.0);
-    B.Df.assign((size_t)343 * B.ldd, 0.0f);
+    B.dmap.clear();
+    for (int z = 0; z <= 2; ++z)
+        for (int i = 0; i + z <= 2 * p; ++i)
+            for (int j = 0; i + j + z <= 2 * p; ++j) B.dmap.push_back(z * s2 + i * s1 + j);
+    B.ldc = pad4((int)B.dmap.size());
+    if (B.ldc != dlayout_ldc(p)) throw std::logic_error("compact derivative table size");
+    B.dmap.resize(B.ldc, B.ldd - 1);
+    B.D.assign((size_t)343 * B.ldc, 0.0);
+    B.Df.assign((size_t)343 * B.ldc, 0.0f);
     std::vector<ld> a;
     for (int kx = -3; kx <= 3; ++kx)
         for (int ky = -3; ky <= 3; ++ky)
@@ -204,13 +216,13 @@ void build_tables(int p, Built &B)
                 if (std::abs(kx) <= 1 && std::abs(ky) <= 1 && std::abs(kz) <= 1) continue;
                 ld x[3] = {(ld)kx, (ld)ky, (ld)kz};
                 inv_r_taylor(x, 2 * p, 2, a);
-                size_t base = (size_t)((kx + 3) * 49 + (ky + 3) * 7 + (kz + 3)) * B.ldd;
+                size_t e = (size_t)((kx + 3) * 49 + (ky + 3) * 7 + (kz + 3)) * B.ldc;
                 for (int z = 0; z <= 2; ++z)
                     for (int i = 0; i + z <= 2 * p; ++i)
-                        for (int j = 0; i + j + z <= 2 * p; ++j) {
+                        for (int j = 0; i + j + z <= 2 * p; ++j, ++e) {
                             ld v = a[mono_index(i, j, z)] * fact(i) * fact(j) * fact(z);
-                            B.D[base + z * s2 + i * s1 + j] = (double)v;
-                            B.Df[base + z * s2 + i * s1 + j] = (float)v;
+                            B.D[e] = (double)v;
+                            B.Df[e] = (float)v;
                         }
             }
     // V-list slot -> offset
@@ -357,8 +369,9 @@ const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::s
     Entry e;
     OrderTables &t = e.host;
     t.p = p; t.nc = ncoef(p); t.nh = nharm(p); t.ldm = pad16(t.nc); t.ldh = pad16(t.nh);
-    t.ldd = B.ldd; t.d3 = dlayout_s1(p);
-    if (upload(B.D, &t.D, err) || upload(B.Df, &t.Df, err) || upload(B.offs, &t.offs, err) ||
+    t.ldd = B.ldd; t.ldc = B.ldc; t.d3 = dlayout_s1(p);
+    if (upload(B.D, &t.D, err) || upload(B.Df, &t.Df, err) || upload(B.dmap, &t.dmap, err) ||
+        upload(B.offs, &t.offs, err) ||
         upload(B.hoff, &t.hoff, err) || upload(B.S, &t.S, err) || upload(B.G, &t.G, err) ||
         upload(B.P2M, &t.P2M, err) || upload(B.P2L, &t.P2L, err) || upload(B.fold_off, &t.fold_off, err) ||
         upload(B.fold_idx, &t.fold_idx, err) || upload(B.fold_c, &t.fold_c, err) ||
@@ -385,7 +398,7 @@ int host_order_tables(int p, int which, std::vector<double> &out)
     Built B;
     build_tables(p, B);
     switch (which) {
-    case 0: out = B.D; return B.ldd;
+    case 0: out = B.D; return B.ldc;
     case 1: out = B.S; return ncoef(p);
     case 2: out = B.G; return ncoef(p);
     case 3: out = B.P2M; return ncoef(p);
