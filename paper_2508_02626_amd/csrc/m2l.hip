@@ -57,6 +57,14 @@ template <> struct Mfma<float> {
     __device__ static const float *M(const PlanView &v) { return v.Mhf; }
 };
 
+// k-steps of 4 indices needed to cover nh indices with groups of vw steps
+// (index 4 vw (s / vw) + vw g + s % vw for step s and lane group g)
+__host__ __device__ constexpr int m2l_ksteps(int nh, int vw)
+{
+    const int q = nh / (4 * vw), r = nh - 4 * vw * q;
+    return vw * q + (r == 0 ? 0 : (r <= vw ? r : vw));
+}
+
 // Loads through global address-space pointers: generic (flat) loads would also
 // count against the LDS wait counter and stall the operand reads behind them.
 template <typename T> __device__ inline T gload(const T *p)
@@ -72,23 +80,24 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     constexpr bool XV = MF >= 1 && XR0 <= 2;     // leftover rows go to the VALU
     constexpr int MT = XV ? MF : (NH + 15) / 16; // MFMA row tiles
     constexpr int XR = XV ? XR0 : 0;             // VALU rows
-    // K order: k-step ks gives lane group kq the index
-    // a = 8 (ks / 2) + 2 kq + ks % 2, so that the two steps of a pair read two
-    // consecutive components of the lane's source: B operands come as aligned
-    // pairs.  (p+1)^2 = 1 (mod 8) for even p, so a lone last step covers what
-    // is left; odd p with an odd number of 4-index steps takes one more step.
+    // K order: with groups of VW k-steps, step ks gives lane group kq the index
+    // a = 4 VW (ks / VW) + VW kq + ks % VW, so that the VW steps of a group read
+    // VW consecutive components of the lane's source: B operands come as one
+    // aligned vector per group.  A last, partial group needs only as many
+    // steps as the components left over, up to VW.  VW = 4 (16-byte FP32
+    // loads) where that costs no step over (p+1)^2 / 4 rounded up, else 2.
     constexpr int KS0 = (NH + 3) / 4;
-    constexpr int KS = (KS0 % 2 == 0 || NH - 8 * (KS0 / 2) <= 1) ? KS0 : KS0 + 1;
-    constexpr int VW = 2;
-    constexpr int NV = (KS + 1) / 2; // pair loads per lane and slot
-    static_assert(8 * NV <= ((NH + 15) & ~15), "pairs must stay inside a padded row");
+    constexpr int VW = (sizeof(T) == 4 && m2l_ksteps(NH, 4) == KS0) ? 4 : 2;
+    constexpr int KS = m2l_ksteps(NH, VW);
+    constexpr int NV = (KS + VW - 1) / VW; // vector loads per lane and slot
+    static_assert(4 * VW * NV <= ((NH + 15) & ~15), "vectors must stay inside a padded row");
     constexpr int LDD = dlayout_ldd(P); // table size in the additive LDS layout
     constexpr int LDC = dlayout_ldc(P); // compact table in memory (only the entries read)
     constexpr int DW = 16 / (int)sizeof(T); // compact tables move in 16-byte vectors
     static_assert(LDC % DW == 0, "compact rows must be whole vectors");
     constexpr int DV = (LDC / DW + 255) / 256; // table vectors per thread
     typedef typename Mfma<T>::acc_t acc_t;
-    typedef T vec_t __attribute__((ext_vector_type(2)));
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
     typedef T dvec_t __attribute__((ext_vector_type(16 / sizeof(T))));
     __shared__ T sD[2][LDD];
     __shared__ int sHo[4][KS]; // additive address of the K index of (ks, kq) (0 if padding)
@@ -109,7 +118,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     if (tid < 64) sTg[tid] = v.m2l_tgt[tile * kM2LSlots + tid];
     const OrderTables &tb = *v.tab;
     for (int e = tid; e < 4 * KS; e += 256) {
-        const int g = e / KS, ks = e - g * KS, a = 8 * (ks / 2) + 2 * g + ks % 2;
+        const int g = e / KS, ks = e - g * KS, a = 4 * VW * (ks / VW) + VW * g + ks % VW;
         sHo[g][ks] = a < NH ? tb.hoff[a] : 0;
     }
     int hb[MT], hx[XR > 0 ? XR : 1];
@@ -159,7 +168,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
 #pragma unroll
     for (int x = 0; x < XR; ++x) { xacc[x] = (T)0; xacc64[x] = 0.0; }
 
-    // B operands of k-steps 2 vi and 2 vi + 1: components 8 vi + 2 kq (+1)
+    // B operands of k-steps VW vi .. VW vi + VW - 1: components 4 VW vi + VW kq (+0 .. VW-1)
     vec_t pb[NV];
     dvec_t pd[DV];
     int dm[DV][DW]; // LDS address of each compact table entry this thread moves
@@ -192,7 +201,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     // operands go to a second set loaded at the top of the slot.
     constexpr bool DB = sizeof(T) == 4;
     vec_t pbn[DB ? NV : 1];
-    const int64_t kofs = 2 * kq;
+    const int64_t kofs = VW * kq;
     auto load_b = [&](int vi, int src) {
         const vec_t val = gload((const vec_t *)(Mh + (int64_t)(src >= 0 ? src : 0) * ldh + kofs) + 4 * vi);
         if constexpr (DB) pbn[vi] = val;
@@ -240,7 +249,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt) an[mt] = D[hb[mt] + hn];
                 }
-                const T bv = (src >= 0 && 8 * (ks / 2) + 2 * kq + ks % 2 < NH) ? pb[ks / VW][ks % VW] : (T)0;
+                const T bv = (src >= 0 && 4 * VW * (ks / VW) + VW * kq + ks % VW < NH) ? pb[ks / VW][ks % VW] : (T)0;
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) acc[mt] = Mfma<T>::run(ac[mt], bv, acc[mt]);
 #pragma unroll
