@@ -52,7 +52,8 @@ struct PlanSizes {
 __global__ void k_collect_sizes(const int64_t *uoff, const int64_t *voff, const int64_t *woff,
                                 const int64_t *xoff, const int64_t *pleaf, const int64_t *pnon,
                                 const int64_t *px, const int64_t *pv, const int32_t *lvl_begin,
-                                const double *root, const int *bad, int nb, PlanSizes *out)
+                                const double *root, const int *bad, int nb, PlanSizes *out,
+                                int32_t *lnl_off)
 {
     const int t = threadIdx.x;
     if (t == 0) {
@@ -65,6 +66,7 @@ __global__ void k_collect_sizes(const int64_t *uoff, const int64_t *voff, const 
         int b = lvl_begin[t];
         out->lvl_begin[t] = b;
         out->lnl[t] = pnon[b < nb ? b : nb];
+        lnl_off[t] = (int32_t)pnon[b < nb ? b : nb]; // non-leaf boxes before level t
     }
 }
 
@@ -111,9 +113,8 @@ struct fmm_plan_s {
         }
         return hipEventRecord(ev, s) == hipSuccess ? 0 : -1;
     }
-    // host copies kept for the lifetime of the plan (sources of async copies)
-    std::vector<int32_t> lvl_host;
-    PlanSizes sizes{};
+    PlanSizes sizes{};         // host copy of the device size record
+    int32_t *lvl_dev = nullptr; // first box of every level (device)
 
     static size_t rounded(size_t bytes) { return ((bytes ? bytes : 8) + 255) & ~(size_t)255; }
     void *raw_alloc(size_t bytes)
@@ -247,9 +248,9 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     int32_t *tv = P->temp<int32_t>(n), *sscr = P->temp<int32_t>(sort_scratch_bytes(n) / 4 + 1);
     NOMEM(P->perm); NOMEM(xs); NOMEM(ys); NOMEM(zs); NOMEM(qs); NOMEM(pf); NOMEM(ff);
     NOMEM(root_dev); NOMEM(part); NOMEM(bad); NOMEM(keys); NOMEM(tk); NOMEM(tv); NOMEM(sscr);
-    HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), s));
-    if (P->root[3] <= 0) bbox(xyz, n, part, root_dev, s); // bounding cube, stays on the device
-    else HIPCHK(hipMemcpyAsync(root_dev, P->root, sizeof(P->root), hipMemcpyHostToDevice, s));
+    const bool given = P->root[3] > 0;
+    plan_init(given ? P->root : nullptr, root_dev, bad, s);
+    if (!given) bbox(xyz, n, part, root_dev, s); // bounding cube, stays on the device
     morton_keys(xyz, n, root_dev, P->D, keys, P->perm, bad, s);
     radix_sort_pairs(keys, P->perm, tk, tv, n, 3 * P->D, sscr, s);
     gather_sorted(xyz, P->perm, n, xs, ys, zs, s);
@@ -299,7 +300,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     bx.level = P->own<int32_t>(nb); bx.first = P->own<int32_t>(nb); bx.count = P->own<int32_t>(nb);
     bx.parent = P->own<int32_t>(nb); bx.child_begin = P->own<int32_t>(nb); bx.nchild = P->own<int32_t>(nb);
     bx.morton = P->own<uint64_t>(nb);
-    int32_t *lvl_dev = P->own<int32_t>(kMaxDepth + 2);
+    int32_t *lvl_dev = P->lvl_dev = P->own<int32_t>(kMaxDepth + 2);
     if (!(bx.level && bx.first && bx.count && bx.parent && bx.child_begin && bx.nchild && bx.morton && lvl_dev))
         return fail(FMM_ENOMEM, "device allocation failed (boxes)");
     P->bx = bx;
@@ -323,13 +324,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         adaptive_boxes(keys, n, P->D, P->leaf_size, eoff, nb, elevel, eidx, etk, etv, efirst, ecount, emorton,
                        escr, bx, lvl_dev, s);
     } else {
-        uniform_boxes(keys, n, P->D, nb, bx, s);
-        P->lvl_host.assign(kMaxDepth + 2, nb);
-        long long tot = 0, sz = 1;
-        P->lvl_host[0] = 0;
-        for (int l = 0; l <= P->D; ++l) { tot += sz; sz *= 8; P->lvl_host[l + 1] = (int)tot; }
-        HIPCHK(hipMemcpyAsync(lvl_dev, P->lvl_host.data(), sizeof(int32_t) * (kMaxDepth + 2),
-                              hipMemcpyHostToDevice, s));
+        uniform_boxes(keys, n, P->D, nb, bx, lvl_dev, s);
     }
     TreeArgs ta{bx, lvl_dev, P->D, nb};
     int32_t *coll = P->temp<int32_t>(27ull * nb);
@@ -341,9 +336,8 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     PlanSizes *sizes_dev = P->temp<PlanSizes>(1);
     NOMEM(coll); NOMEM(mscr); NOMEM(mtg); NOMEM(sizes_dev);
     fill_i32(vslot, (int64_t)nb * kVSlots, -1, s);
-    colleagues(ta, coll, s);
-    vlist(ta, coll, 0, cnt[1], nullptr, nullptr, nullptr, s);
-    HIPCHK(hipMemsetAsync(cnt[3], 0, sizeof(int64_t) * nb, s));
+    colleagues(ta, coll, cnt[3], s);                        // also clears the X counts
+    vlist(ta, coll, 0, cnt[1], nullptr, nullptr, vslot, s); // V counts and M2L slot rows
     uwlist(ta, coll, 0, cnt[0], nullptr, nullptr, cnt[2], nullptr, nullptr, cnt[3], s);
     flags(bx, nb, cnt[3], cnt[1], flg[0], flg[1], flg[2], flg[3], s);
     {
@@ -356,7 +350,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     compact(flg[2], pos[2], nb, xtgt, s);
     compact(flg[3], pos[3], nb, mtg, s);
     k_collect_sizes<<<1, 64, 0, s>>>(P->off[0], P->off[1], P->off[2], P->off[3], pos[0], pos[1], pos[2], pos[3],
-                                     lvl_dev, root_dev, bad, nb, sizes_dev);
+                                     lvl_dev, root_dev, bad, nb, sizes_dev, lnl_off);
     HIPCHK(hipGetLastError());
     if (copy_to_host(&P->sizes, sizes_dev, 1, s)) return FMM_EDEVICE;
     HIPCHK(hipStreamSynchronize(s));
@@ -380,7 +374,8 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     const int64_t mw = P->nlist[2];
     {
         Sizer o;
-        for (int w = 0; w < 4; ++w) o.add<int32_t>(P->nlist[w] ? P->nlist[w] : 1);
+        for (int w = 0; w < 4; ++w)
+            if (w != 1) o.add<int32_t>(P->nlist[w] ? P->nlist[w] : 1);
         o.add<int32_t>(slot_cap);
         if (!P->reserve(true, o.total)) return fail(FMM_ENOMEM, "device allocation failed (list arrays)");
         Sizer t;
@@ -389,10 +384,13 @@ int build_plan(fmm_plan_s *P, const double *xyz)
          .add<int32_t>(sort_scratch_bytes(nt + 1) / 4 + 1);
         if (!P->reserve(false, t.total)) return fail(FMM_ENOMEM, "device allocation failed (list temporaries)");
     }
-    for (int w = 0; w < 4; ++w) { P->src[w] = P->own<int32_t>(P->nlist[w] ? P->nlist[w] : 1); NOMEM(P->src[w]); }
+    for (int w = 0; w < 4; ++w) { // the V list itself is built on demand (export); M2L uses the slot rows
+        if (w == 1) continue;
+        P->src[w] = P->own<int32_t>(P->nlist[w] ? P->nlist[w] : 1);
+        NOMEM(P->src[w]);
+    }
     int32_t *slots = P->own<int32_t>(slot_cap);
     NOMEM(slots);
-    vlist(ta, coll, 1, nullptr, P->off[1], P->src[1], vslot, s); // ascending by construction
     uwlist(ta, coll, 1, nullptr, P->off[0], P->src[0], nullptr, P->off[2], P->src[2], nullptr, s);
     if (mw > 0) { // X = transpose of W
         uint64_t *wk = P->temp<uint64_t>(mw), *wk2 = P->temp<uint64_t>(mw);
@@ -403,8 +401,6 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         while ((1LL << bits) < nb) ++bits;
         radix_sort_pairs(wk, P->src[3], wk2, wv2, (int)mw, bits, wscr, s);
     }
-    P->lvl_host.assign(P->lvl_nonleaf_off.begin(), P->lvl_nonleaf_off.end());
-    HIPCHK(hipMemcpyAsync(lnl_off, P->lvl_host.data(), sizeof(int32_t) * (depth + 2), hipMemcpyHostToDevice, s));
     int *octoff = P->temp<int>(32);
     uint64_t *okey = P->temp<uint64_t>(nt + 1), *otk = P->temp<uint64_t>(nt + 1);
     int32_t *oval = P->temp<int32_t>(nt + 1), *otv = P->temp<int32_t>(nt + 1);
@@ -848,6 +844,19 @@ extern "C" int fmm_plan_export_tree(fmm_plan_t plan, hipStream_t stream, double 
     fmm_plan_s *P = plan;
     HIPCHK(hipStreamSynchronize(stream));
     const int nb = P->nboxes, n = P->n;
+    if (!P->src[1]) { // the V list proper is built on first request (evaluation reads the slot rows)
+        TreeArgs ta{P->bx, P->lvl_dev, P->D, nb};
+        int32_t *coll = nullptr;
+        HIPCHK(hipMalloc((void **)&coll, sizeof(int32_t) * 27 * (size_t)nb));
+        int32_t *v1 = P->own<int32_t>(P->nlist[1] ? P->nlist[1] : 1);
+        if (!v1) { (void)hipFree(coll); return fail(FMM_ENOMEM, "device allocation failed (V list)"); }
+        colleagues(ta, coll, nullptr, P->stream);
+        vlist(ta, coll, 1, nullptr, P->off[1], v1, nullptr, P->stream);
+        hipError_t e1 = hipStreamSynchronize(P->stream);
+        (void)hipFree(coll);
+        if (e1 != hipSuccess) return fail(FMM_EDEVICE, std::string("V list: ") + hipGetErrorString(e1));
+        P->src[1] = v1;
+    }
     if (root_host) std::memcpy(root_host, P->root, sizeof(P->root));
     std::vector<int32_t> t32;
     auto widen = [&](int64_t *dst, const int32_t *src, int cnt) -> int {

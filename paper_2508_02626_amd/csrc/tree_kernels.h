@@ -18,19 +18,21 @@ struct TreeArgs {
     int D, nboxes;
 };
 
+void plan_init(const double *given_root, double *root_dev, int *bad, hipStream_t s);
 void bbox(const double *xyz, int n, double *part, double *root, hipStream_t s);
 void morton_keys(const double *xyz, int n, const double *root_dev, int D, uint64_t *keys,
                  int32_t *idx, int *bad, hipStream_t s);
 void gather_sorted(const double *xyz, const int32_t *perm, int n, double *xs, double *ys,
                    double *zs, hipStream_t s);
-void uniform_boxes(const uint64_t *keys, int n, int D, int nboxes, BoxArrays bx, hipStream_t s);
+void uniform_boxes(const uint64_t *keys, int n, int D, int nboxes, BoxArrays bx, int32_t *lvl_begin,
+                   hipStream_t s);
 // adaptive tree: boxes emitted per particle (count, then fill after a scan)
 void emit_count(const uint64_t *keys, int n, int D, int leaf_size, int64_t *cnt, hipStream_t s);
 void adaptive_boxes(const uint64_t *keys, int n, int D, int leaf_size, const int64_t *off, int nb,
                     uint64_t *elevel, int32_t *eidx, uint64_t *tk, int32_t *tv, int32_t *efirst,
                     int32_t *ecount, uint64_t *emorton, int32_t *sort_scratch, BoxArrays bx,
                     int32_t *lvl_begin, hipStream_t s);
-void colleagues(const TreeArgs &a, int32_t *coll, hipStream_t s);
+void colleagues(const TreeArgs &a, int32_t *coll, int64_t *zero, hipStream_t s);
 void vlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *cnt, const int64_t *off,
            int32_t *src, int32_t *vslot, hipStream_t s);
 void uwlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *ucnt, const int64_t *uoff,

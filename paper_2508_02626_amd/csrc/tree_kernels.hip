@@ -66,6 +66,22 @@ __global__ __launch_bounds__(64) void k_bbox_final(const double *part, int nb, d
     root[3] = W == 0.0 ? 1.0 : W;
 }
 
+// clears the non-finite flag and, when the root cube is given, stores it
+__global__ void k_plan_init(int given, double r0, double r1, double r2, double r3, double *root, int *bad)
+{
+    if (threadIdx.x != 0) return;
+    *bad = 0;
+    if (given) { root[0] = r0; root[1] = r1; root[2] = r2; root[3] = r3; }
+}
+
+void plan_init(const double *given_root, double *root_dev, int *bad, hipStream_t s)
+{
+    if (given_root)
+        k_plan_init<<<1, 64, 0, s>>>(1, given_root[0], given_root[1], given_root[2], given_root[3], root_dev, bad);
+    else
+        k_plan_init<<<1, 64, 0, s>>>(0, 0, 0, 0, 0, root_dev, bad);
+}
+
 void bbox(const double *xyz, int n, double *part, double *root, hipStream_t s)
 {
     int nb = (int)ceil_div(n, 256);
@@ -133,9 +149,18 @@ __device__ inline int lower_bound_key(const uint64_t *keys, int lo, int hi, uint
 
 // Uniform tree: box b of level l has Morton code b - level_begin[l].
 __global__ __launch_bounds__(256) void k_uniform_boxes(const uint64_t *keys, int n, int D, int nboxes,
-                                                       BoxArrays bx)
+                                                       BoxArrays bx, int32_t *lvl_begin)
 {
     int b = blockIdx.x * 256 + threadIdx.x;
+    if (b == 0) { // level starts: 0, 1, 9, 73, ... then nboxes
+        long long beg = 0, size = 1;
+        for (int l = 0; l <= kMaxDepth + 1; ++l) {
+            lvl_begin[l] = l <= D ? (int)beg : nboxes;
+            beg += size;
+            size *= 8;
+            if (beg > nboxes) beg = nboxes;
+        }
+    }
     if (b >= nboxes) return;
     int l = 0;
     long long beg = 0, size = 1;
@@ -158,9 +183,10 @@ __global__ __launch_bounds__(256) void k_uniform_boxes(const uint64_t *keys, int
     }
 }
 
-void uniform_boxes(const uint64_t *keys, int n, int D, int nboxes, BoxArrays bx, hipStream_t s)
+void uniform_boxes(const uint64_t *keys, int n, int D, int nboxes, BoxArrays bx, int32_t *lvl_begin,
+                   hipStream_t s)
 {
-    k_uniform_boxes<<<ceil_div(nboxes, 256), 256, 0, s>>>(keys, n, D, nboxes, bx);
+    k_uniform_boxes<<<ceil_div(nboxes, 256), 256, 0, s>>>(keys, n, D, nboxes, bx, lvl_begin);
 }
 
 // Adaptive tree straight from the sorted keys, with no host round trip per
@@ -348,11 +374,12 @@ __device__ inline bool adjacent(const TreeView &t, int a, int b)
 
 // Colleagues: the up to 27 same-level boxes adjacent to b (b included),
 // ascending, padded with -1.  Lane j < 27 looks up neighbour cell j.
-__global__ __launch_bounds__(256) void k_colleagues(TreeView t, int32_t *coll)
+__global__ __launch_bounds__(256) void k_colleagues(TreeView t, int32_t *coll, int64_t *zero)
 {
     const int lane = threadIdx.x & 63;
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (b >= t.nboxes) return;
+    if (zero && lane == 0) zero[b] = 0; // counters the later list passes accumulate into
     const int l = t.bx.level[b], side = 1 << l;
     int c[3];
     deinterleave(t.bx.morton[b], l, c);
@@ -375,8 +402,8 @@ __global__ __launch_bounds__(256) void k_colleagues(TreeView t, int32_t *coll)
 // parent's colleagues that are not adjacent (same level, so adjacency is
 // max |delta| <= 1 in cell coordinates).  Lane j of a round looks at child
 // j % 8 of colleague j / 8; colleagues are ascending and children
-// consecutive, so compaction in lane order gives an ascending list.  The fill
-// pass also records each source in the box's M2L slot row (Sec. 3.4).
+// consecutive, so compaction in lane order gives an ascending list.  Either
+// pass records each source in the box's M2L slot row (Sec. 3.4) if given one.
 __global__ __launch_bounds__(256) void k_vlist(TreeView t, const int32_t *coll, int which,
                                                int64_t *cnt, const int64_t *off, int32_t *src,
                                                int32_t *vslot)
@@ -407,8 +434,8 @@ __global__ __launch_bounds__(256) void k_vlist(TreeView t, const int32_t *coll, 
                 }
             }
             const uint64_t m = __ballot(sel);
-            if (sel && which) {
-                src[o + n + __popcll(m & lanes_below(lane))] = d;
+            if (sel && which) src[o + n + __popcll(m & lanes_below(lane))] = d;
+            if (sel && vslot) {
                 int sl = vslot_of(oct, -dx, -dy, -dz); // offset = target - source
                 if (sl >= 0) vslot[(int64_t)b * kVSlots + sl] = d;
             }
@@ -598,10 +625,10 @@ __global__ __launch_bounds__(256) void k_uwlist(TreeView t, const int32_t *coll,
     write_ranked(bw, nw, wsrc + woff[b], lane);
 }
 
-void colleagues(const TreeArgs &a, int32_t *coll, hipStream_t s)
+void colleagues(const TreeArgs &a, int32_t *coll, int64_t *zero, hipStream_t s)
 {
     TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes};
-    k_colleagues<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll);
+    k_colleagues<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, zero);
 }
 
 void vlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *cnt, const int64_t *off,
