@@ -173,8 +173,38 @@ void scan_exclusive(const int64_t *in, int64_t *out, int64_t n, int64_t *scratch
     k_scan_apply<int64_t><<<nb, kThreads, 0, s>>>(in, n, scratch, out, 1);
 }
 
+// one block, in place, for short arrays (n <= kSmallScan, the digit counts of
+// sorts up to 64k elements): 1024 threads own
+// runs of n/1024 consecutive elements
+constexpr int kSmallScan = 1024 * 8;
+__global__ __launch_bounds__(1024) void k_scan_small(int32_t *data, int n)
+{
+    __shared__ int32_t sh[1024];
+    const int per = (n + 1023) / 1024, b = threadIdx.x * per, e = min(b + per, n);
+    int32_t tot = 0;
+    for (int i = b; i < e; ++i) tot += data[i];
+    sh[threadIdx.x] = tot;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        int32_t t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int32_t run = sh[threadIdx.x] - tot;
+    for (int i = b; i < e; ++i) {
+        int32_t v = data[i];
+        data[i] = run;
+        run += v;
+    }
+}
+
 static void scan_exclusive_i32(int32_t *data, int64_t n, int32_t *scratch, hipStream_t s)
 {
+    if (n <= kSmallScan) {
+        k_scan_small<<<1, 1024, 0, s>>>(data, (int)n);
+        return;
+    }
     unsigned nb = ceil_div(n > 0 ? n : 1, kTile);
     k_scan_block_sums<int32_t><<<nb, kThreads, 0, s>>>(data, n, scratch);
     k_scan_sums<int32_t><<<1, 1024, 0, s>>>(scratch, (int)nb);

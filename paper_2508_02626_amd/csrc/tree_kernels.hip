@@ -569,8 +569,13 @@ __global__ __launch_bounds__(256) void k_uwlist(TreeView t, const int32_t *coll,
         int sp = __popcll(m);
         wave_sync();
         while (sp > 0) {
-            const int take = sp < 64 ? sp : 64;
-            if (sp - take + 8 * take > kUWStack || nu + take > kUWBuf || nw + 8 * take > kUWBuf) {
+            // pop as many as fit: the stack grows by at most 7 per popped box,
+            // each popped box adds at most 1 U and 8 W entries
+            int take = sp < 64 ? sp : 64;
+            take = min(take, (kUWStack - sp) / 7);
+            take = min(take, kUWBuf - nu);
+            take = min(take, (kUWBuf - nw) / 8);
+            if (take <= 0) {
                 ok = false;
                 break;
             }
