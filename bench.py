@@ -89,9 +89,20 @@ def run_mode(x, q, precision, steps, warmup, n):
     eval_s = (time.perf_counter() - t0) / steps
     stages = pl.read_timing()
     sizes = pl.sizes()
+    sizes["p2p_pairs"] = p2p_pairs(pl.export_tree())
     pl.close()
     return dict(step_s=step_s, eval_s=eval_s, stages=stages, sizes=sizes,
                 phi=phi.cpu().numpy(), fld=fld.cpu().numpy())
+
+
+def p2p_pairs(t):
+    """Particle pairs summed by P2P: for every leaf, its count times the
+    particles of its U list (the pair of a particle with itself included)."""
+    cnt = t["count"].astype(np.int64)
+    uo, us = t["U_off"], t["U_src"]
+    per_box = np.add.reduceat(cnt[us], uo[:-1]) if len(us) else np.zeros(len(cnt), np.int64)
+    per_box = np.where(uo[1:] > uo[:-1], per_box, 0)
+    return int((cnt * per_box).sum())
 
 
 def cpu_baseline(xh, qh):
@@ -115,6 +126,22 @@ def sampled_sigma(xh, qh, phi, fld, count=2000, seed=7):
     s_phi = float(np.linalg.norm(phi[idx] - dp) / np.linalg.norm(dp))
     s_fld = float(np.linalg.norm(fld[idx] - df) / np.linalg.norm(df))
     return s_phi, s_fld, len(idx)
+
+
+# Algorithmic FP64 operations of one P2P pair (potential and field):
+# 3 differences, r^2 (3 mul + 2 add), 1/r (counted as 2: square root and
+# division), q/r, q/r^3 (3 mul), 4 accumulations (1 add + 3 fused
+# multiply-adds counted as 2) = 20.
+P2P_FLOPS_PER_PAIR = 20
+
+
+def p2p_roofline(r):
+    ms = r["stages"]["p2p"][0] / max(r["stages"]["p2p"][1], 1)
+    pairs = r["sizes"]["p2p_pairs"]
+    achieved = P2P_FLOPS_PER_PAIR * pairs / (ms * 1e-3) / 1e12
+    return {"kernel": "k_p2p<0>", "bound": "alu", "pairs_per_launch": pairs, "ms_per_launch": ms,
+            "pairs_per_s": pairs / (ms * 1e-3), "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s (FP64 vector)", "frac": achieved / FP64_PEAK_TFLOPS}
 
 
 def base_record(args):
@@ -160,10 +187,14 @@ def bench_plummer(args):
         torch.cuda.synchronize()
         eval_s = (time.perf_counter() - t0) / args.steps
         st, sizes = pl.read_timing(), pl.sizes()
+        if mode == "fp64":
+            sizes["p2p_pairs"] = p2p_pairs(pl.export_tree())
         pl.close()
-        sp, sf, nt = sampled_sigma(xh, qh, phi.cpu().numpy(), fld.cpu().numpy(), count=1000)
+        ph, fh = phi.cpu().numpy(), fld.cpu().numpy()
+        sp, sf, nt = sampled_sigma(xh, qh, ph, fh, count=1000)
         log("bench plummer: %s step %.2f ms eval %.2f ms sigma %.3e" % (mode, 1e3 * step_s, 1e3 * eval_s, sp))
-        res[mode] = dict(step_s=step_s, eval_s=eval_s, stages=stage_avg(st), sizes=sizes, sigma=sp, sigma_f=sf)
+        res[mode] = dict(step_s=step_s, eval_s=eval_s, stages=stage_avg(st), sizes=sizes, sigma=sp, sigma_f=sf,
+                         phi=ph, fld=fh)
     f, m = res["fp64"], res["mixed"]
     flops = 2.0 * (p + 1) ** 4 * f["sizes"]["V"]
     m2l_ms = f["stages"]["m2l"]
@@ -181,8 +212,14 @@ def bench_plummer(args):
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": flops / (m2l_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
                      "flops_per_launch": flops, "ms_per_launch": m2l_ms},
+        "p2p": {"kernel": "k_p2p<0>", "pairs_per_launch": f["sizes"]["p2p_pairs"],
+                "pairs_per_s": f["sizes"]["p2p_pairs"] / (1e-3 * f["stages"]["p2p"]),
+                "achieved": P2P_FLOPS_PER_PAIR * f["sizes"]["p2p_pairs"] / (1e-3 * f["stages"]["p2p"]) / 1e12,
+                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s (FP64 vector)"},
         "mixed": {"value": n / m["step_s"], "ms_per_step": 1e3 * m["step_s"], "eval_ms": 1e3 * m["eval_s"],
                   "sigma_phi_vs_direct": m["sigma"], "sigma_field_vs_direct": m["sigma_f"],
+                  "rel_l2_vs_fp64_path_phi": float(np.linalg.norm(m["phi"] - f["phi"]) / np.linalg.norm(f["phi"])),
+                  "rel_l2_vs_fp64_path_field": float(np.linalg.norm(m["fld"] - f["fld"]) / np.linalg.norm(f["fld"])),
                   "dtype": "f64 with f32 P2P terms (M2L stays FP64 at p=10)", "stage_ms": m["stages"]},
     })
     return out
@@ -374,16 +411,21 @@ def main():
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": m2l_traffic(), "traffic_unit": "bytes per launch",
                      "flops_per_launch": flops, "ms_per_launch": m2l_ms},
+        "p2p": p2p_roofline(f),
     }
     if "mixed" in res:
         m = res["mixed"]
         mm = m["stages"]["m2l"][0] / max(m["stages"]["m2l"][1], 1)
-        out["mixed"] = {"value": n / m["step_s"], "ms_per_step": 1e3 * m["step_s"],
+        out["mixed"] = {"rel_l2_vs_fp64_path_phi": float(np.linalg.norm(m["phi"] - f["phi"]) / np.linalg.norm(f["phi"])),
+                        "rel_l2_vs_fp64_path_field": float(np.linalg.norm(m["fld"] - f["fld"]) / np.linalg.norm(f["fld"])),
+                        "value": n / m["step_s"], "ms_per_step": 1e3 * m["step_s"],
                         "eval_only_value": n / m["eval_s"], "eval_ms": 1e3 * m["eval_s"],
                         "sigma_phi_vs_direct": m["sigma_phi"], "sigma_field_vs_direct": m["sigma_field"],
                         "dtype": "f64 with f32 P2P terms and f32 MFMA M2L",
                         "stage_ms": {k: v[0] / max(v[1], 1) for k, v in m["stages"].items()},
-                        "m2l_tflops": flops / (mm * 1e-3) / 1e12, "m2l_peak_fp32": FP32_PEAK_TFLOPS}
+                        "m2l_tflops": flops / (mm * 1e-3) / 1e12, "m2l_peak_fp32": FP32_PEAK_TFLOPS,
+                        "p2p_pairs_per_s": m["sizes"]["p2p_pairs"] / (1e-3 * m["stages"]["p2p"][0] /
+                                                                      max(m["stages"]["p2p"][1], 1))}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(xh, qh)
     print(json.dumps(out), flush=True)
