@@ -116,8 +116,10 @@ int fmm_plan_batch(int32_t count, const double *const *xyz_dev, const int64_t *n
  *   q_dev      [n] FP64 device charges, original order
  *   phi_dev    [n] FP64 device output potentials
  *   field_dev  [n][3] FP64 device output fields E = -grad phi, or NULL
- * Asynchronous on `stream`.  Deterministic: the same plan and charges give
- * bitwise identical results on every call.
+ * Asynchronous on `stream`: P2P runs on a stream of the plan's own, forked
+ * from `stream` after the charges are sorted and joined back before M2L, so
+ * it overlaps the upward pass.  Deterministic: the
+ * same plan and charges give bitwise identical results on every call.
  */
 int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_dev, double *field_dev,
                  hipStream_t stream);
@@ -179,11 +181,12 @@ int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, double *M_ho
 
 /*
  * Stage timing of fmm_evaluate.  With timing on, every fmm_evaluate on the
- * plan brackets each stage with HIP events on its stream.  fmm_plan_read_timing
- * waits for the recorded events, adds their durations (milliseconds) per stage
- * into ms[0..15] and the number of timed evaluations into calls[0..15], and
- * clears the records.  Stages: 0 permute charges, 1 P2M, 2 M2M, 3 fold,
- * 4 M2L, 5 P2L, 6 unfold, 7 L2L, 8 L2P+M2P, 9 P2P+output.
+ * plan brackets each stage with HIP events on the stream it runs on.
+ * fmm_plan_read_timing waits for the recorded events, adds their durations
+ * (milliseconds) per stage into ms[0..15] and the number of timed evaluations
+ * into calls[0..15], and clears the records.  Stages: 0 permute charges,
+ * 1 P2M, 2 M2M, 3 fold, 4 M2L, 5 P2L, 6 unfold, 7 L2L, 8 L2P+M2P+output,
+ * 9 P2P (on the plan's side stream, concurrent with stages 1-3).
  */
 int fmm_plan_set_timing(fmm_plan_t plan, int on);
 int fmm_plan_read_timing(fmm_plan_t plan, double ms[16], int64_t calls[16]);

@@ -4,6 +4,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
+#include <mutex>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -70,6 +72,44 @@ __global__ void k_collect_sizes(const int64_t *uoff, const int64_t *voff, const 
     }
 }
 
+// Side streams (with their fork and join events) are kept in a per-device
+// pool: creating a stream costs far more than an evaluation's launches, and a
+// plan built per solve would otherwise create one every time.  A released
+// stream may still be running its last P2P; work queued on it later simply
+// follows.
+namespace {
+struct SideSet { hipStream_t s; hipEvent_t fork, join; };
+std::mutex g_side_mu;
+std::map<int, std::vector<SideSet>> g_side_pool;
+} // namespace
+
+static int side_acquire(int dev, hipStream_t &s, hipEvent_t &fork, hipEvent_t &join)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_side_mu);
+        auto &v = g_side_pool[dev];
+        if (!v.empty()) {
+            s = v.back().s; fork = v.back().fork; join = v.back().join;
+            v.pop_back();
+            return 0;
+        }
+    }
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) { s = nullptr; return -1; }
+    if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        s = nullptr;
+        return -1;
+    }
+    return 0;
+}
+
+static void side_release(int dev, hipStream_t s, hipEvent_t fork, hipEvent_t join)
+{
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    g_side_pool[dev].push_back({s, fork, join});
+}
+
 struct fmm_plan_s {
     int device = 0;
     hipStream_t stream = 0;
@@ -112,6 +152,21 @@ struct fmm_plan_s {
             uses.push_back({s, ev});
         }
         return hipEventRecord(ev, s) == hipSuccess ? 0 : -1;
+    }
+    // P2P runs on a stream of the plan's own, concurrently with the far-field
+    // stages; two events fork it after the charge permutation and join it
+    // before the output
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int ensure_side()
+    {
+        if (side) return 0;
+        return side_acquire(device, side, ev_fork, ev_join);
+    }
+    void release_side()
+    {
+        if (side) side_release(device, side, ev_fork, ev_join);
+        side = nullptr; ev_fork = ev_join = nullptr;
     }
     PlanSizes sizes{};         // host copy of the device size record
     int32_t *lvl_dev = nullptr; // first box of every level (device)
@@ -422,7 +477,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     v.U_src = P->src[0]; v.W_src = P->src[2]; v.X_src = P->src[3];
     v.m2l_tgt = slots; v.vslot = vslot; v.leaves = leaves; v.xtgt = xtgt;
     v.lvl_nonleaf = nonleaf; v.lvl_nonleaf_off = lnl_off; v.tab = P->tab;
-    v.qs = qs; v.M = M; v.Mh = Mh; v.Lh = Lh; v.L = L; v.Mhf = Mhf; v.phi_far = pf; v.fld_far = ff;
+    v.qs = qs; v.M = M; v.Mh = Mh; v.Lh = Lh; v.L = L; v.Mhf = Mhf; v.phi_near = pf; v.fld_near = ff;
     HIPCHK(hipMemcpyAsync(P->view_dev, &v, sizeof(PlanView), hipMemcpyHostToDevice, s));
     HIPCHK(hipGetLastError());
     P->release_temps();
@@ -611,6 +666,11 @@ struct StageTimer {
     fmm_plan_s::Rec cur{};
     bool on = false;
     StageTimer(fmm_plan_s *p, hipStream_t st) : P(p), s(st) {}
+    void begin(int stage, hipStream_t on_stream)
+    {
+        s = on_stream;
+        begin(stage);
+    }
     void begin(int stage)
     {
         on = P && P->timing;
@@ -650,6 +710,31 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     T.begin(0);
     launch_permute_q(V, Bp, s);
     T.end();
+    // P2P needs only the sorted charges: fork it onto the side stream, where it
+    // runs next to P2M, M2M and fold
+    fmm_plan_s *F = P[0];
+    if (F->ensure_side()) return fail(FMM_EDEVICE, "side stream creation failed");
+    HIPCHK(hipEventRecord(F->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(F->side, F->ev_fork, 0));
+    {
+        StageTimer T2(count == 1 ? P[0] : nullptr, F->side);
+        T2.begin(9);
+        for (int mixed = 0; mixed <= 1; ++mixed) { // FP64 and mixed plans in separate launches
+            for (int i = 0; i < count;) {
+                if ((P[i]->precision == FMM_MIXED) != (mixed == 1)) { ++i; continue; }
+                int j = i;
+                while (j < count && (P[j]->precision == FMM_MIXED) == (mixed == 1)) ++j;
+                Bases Bq{};
+                Bq.n = j - i;
+                Bq.b[0] = 0;
+                for (int t = 0; t < j - i; ++t) Bq.b[t + 1] = Bq.b[t] + stage_blocks(P[i + t]).p2p;
+                launch_p2p(mixed, V + i, Bq, F->side);
+                i = j;
+            }
+        }
+        T2.end();
+    }
+    HIPCHK(hipEventRecord(F->ev_join, F->side));
     // runs of equal order (callers sort batches by order)
     std::vector<std::pair<int, int>> runs;
     for (int i = 0; i < count;) {
@@ -689,6 +774,10 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     T.begin(3);
     launch_fold(V, make([](const fmm_plan_s *p) { return stage_blocks(p).fold; }, all), s);
     T.end();
+    // P2P overlaps the latency-bound upward pass; M2L, which fills the GPU by
+    // itself, starts once P2P is done (running the two together slows M2L by
+    // about as much as it hides)
+    HIPCHK(hipStreamWaitEvent(s, F->ev_join, 0));
     T.begin(4);
     for (auto &r : runs)
         launch_m2l(P[r.first]->p, P[r.first]->mixed_m2l, V + r.first,
@@ -711,22 +800,11 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
             launch_l2l(V + r.first,
                        sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldm / 16); }), l, s);
     T.end();
+    // far field (L2P + M2P) plus the near field, written in the caller's order
     T.begin(8);
     for (auto &r : runs)
         launch_far(P[r.first]->p, V + r.first,
                    sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).far; }), s);
-    T.end();
-    T.begin(9);
-    // P2P: FP64 and mixed plans in separate launches
-    for (int mixed = 0; mixed <= 1; ++mixed) {
-        for (int i = 0; i < count;) {
-            if ((P[i]->precision == FMM_MIXED) != (mixed == 1)) { ++i; continue; }
-            int j = i;
-            while (j < count && (P[j]->precision == FMM_MIXED) == (mixed == 1)) ++j;
-            launch_p2p(mixed, V + i, sub(i, j, [](const fmm_plan_s *p) { return stage_blocks(p).p2p; }), s);
-            i = j;
-        }
-    }
     T.end();
     HIPCHK(hipGetLastError());
     return 0;
@@ -981,6 +1059,7 @@ extern "C" int fmm_plan_destroy(fmm_plan_t plan)
     }
     plan->uses.clear();
     plan->release_all();
+    plan->release_side();
     if (dev != plan->device) (void)hipSetDevice(dev);
     delete plan;
     return FMM_OK;

@@ -175,7 +175,7 @@ struct PlanView {
     double *qs;                         // sorted charges
     double *M, *Mh, *Lh, *L;            // [boxes][ldm] / [boxes][ldh]
     float *Mhf;                         // FP32 folded multipoles (mixed M2L)
-    double *phi_far, *fld_far;          // far-field part, sorted order
+    double *phi_near, *fld_near;        // near-field (P2P) part, sorted order
     // caller's arrays for this evaluation
     const double *q_in;
     double *phi_out, *fld_out;

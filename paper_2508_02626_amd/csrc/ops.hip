@@ -434,14 +434,21 @@ __global__ __launch_bounds__(64) void k_far(const PlanView *V, Bases B)
             gy += sr * (-y1 * s2 * f0 + hs * s2 * fy - 2.0 * hs * s2 * s2 * y1 * yf);
             gz += sr * (-y2 * s2 * f0 + hs * s2 * fz - 2.0 * hs * s2 * s2 * y2 * yf);
         }
-        if (act) {
-            v.phi_far[i] = phi;
-            v.fld_far[3 * i] = -gx; v.fld_far[3 * i + 1] = -gy; v.fld_far[3 * i + 2] = -gz;
+        if (act) { // far part plus the near part P2P left, in the caller's order
+            const int o = v.perm[i];
+            v.phi_out[o] = phi + v.phi_near[i];
+            if (v.fld_out) {
+                v.fld_out[3 * o] = -gx + v.fld_near[3 * i];
+                v.fld_out[3 * o + 1] = -gy + v.fld_near[3 * i + 1];
+                v.fld_out[3 * o + 2] = -gz + v.fld_near[3 * i + 2];
+            }
         }
     }
 }
 
-// ---------------- P2P and output ----------------
+// ---------------- P2P ----------------
+// The near-field part goes to phi_near / fld_near (sorted order); the far-field
+// kernel adds it and writes the caller's order.
 // Four wavefronts per block, one target leaf each.  A pass takes up to 64
 // targets of the leaf; every lane holds two of them (targets t and t + TPG,
 // TPG = ceil(c/2) for the c targets of the pass), and the 64 / TPG lane groups
@@ -616,13 +623,10 @@ __global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B)
                 const int t = lane + h * TPG;
                 if (t >= c) continue;
                 const int i = f + ts + t;
-                const int o = v.perm[i];
-                v.phi_out[o] = v.phi_far[i] + acc[4 * h];
-                if (v.fld_out) {
-                    v.fld_out[3 * o] = v.fld_far[3 * i] + acc[4 * h + 1];
-                    v.fld_out[3 * o + 1] = v.fld_far[3 * i + 1] + acc[4 * h + 2];
-                    v.fld_out[3 * o + 2] = v.fld_far[3 * i + 2] + acc[4 * h + 3];
-                }
+                v.phi_near[i] = acc[4 * h];
+                v.fld_near[3 * i] = acc[4 * h + 1];
+                v.fld_near[3 * i + 1] = acc[4 * h + 2];
+                v.fld_near[3 * i + 2] = acc[4 * h + 3];
             }
         }
     }
