@@ -635,7 +635,7 @@ namespace {
 
 struct StagePlan {
     // per-stage block counts of one plan
-    int permute, p2m, fold, m2l, p2l, unfold, far, p2p;
+    int permute, p2m, fold, m2l, p2l, unfold, far, p2p[2];
 };
 
 StagePlan stage_blocks(const fmm_plan_s *P)
@@ -648,7 +648,9 @@ StagePlan stage_blocks(const fmm_plan_s *P)
     sp.p2l = P->nxtgt;
     sp.unfold = sp.fold;
     sp.far = P->nleaves;
-    sp.p2p = (int)ceil_div(P->nleaves, 4);
+    const int split = p2p_split(P->nleaves);
+    sp.p2p[0] = (int)ceil_div(split, 4);
+    sp.p2p[1] = (int)ceil_div(P->nleaves - split, 4);
     return sp;
 }
 
@@ -710,15 +712,15 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     T.begin(0);
     launch_permute_q(V, Bp, s);
     T.end();
-    // P2P needs only the sorted charges: fork it onto the side stream, where it
-    // runs next to P2M, M2M and fold
+    // P2P needs only the sorted charges.  Its first part runs on the side
+    // stream next to P2M, M2M and fold; its second part next to the
+    // downward pass (unfold, L2L).  M2L, which fills the GPU by itself, runs
+    // alone: overlapping it with P2P slows it by about as much as it hides.
     fmm_plan_s *F = P[0];
     if (F->ensure_side()) return fail(FMM_EDEVICE, "side stream creation failed");
-    HIPCHK(hipEventRecord(F->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(F->side, F->ev_fork, 0));
-    {
-        StageTimer T2(count == 1 ? P[0] : nullptr, F->side);
-        T2.begin(9);
+    StageTimer T2(count == 1 ? P[0] : nullptr, F->side);
+    auto p2p_part = [&](int part) {
+        T2.begin(9 + part);
         for (int mixed = 0; mixed <= 1; ++mixed) { // FP64 and mixed plans in separate launches
             for (int i = 0; i < count;) {
                 if ((P[i]->precision == FMM_MIXED) != (mixed == 1)) { ++i; continue; }
@@ -727,13 +729,16 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
                 Bases Bq{};
                 Bq.n = j - i;
                 Bq.b[0] = 0;
-                for (int t = 0; t < j - i; ++t) Bq.b[t + 1] = Bq.b[t] + stage_blocks(P[i + t]).p2p;
-                launch_p2p(mixed, V + i, Bq, F->side);
+                for (int t = 0; t < j - i; ++t) Bq.b[t + 1] = Bq.b[t] + stage_blocks(P[i + t]).p2p[part];
+                launch_p2p(mixed, part, V + i, Bq, F->side);
                 i = j;
             }
         }
         T2.end();
-    }
+    };
+    HIPCHK(hipEventRecord(F->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(F->side, F->ev_fork, 0));
+    p2p_part(0);
     HIPCHK(hipEventRecord(F->ev_join, F->side));
     // runs of equal order (callers sort batches by order)
     std::vector<std::pair<int, int>> runs;
@@ -774,15 +779,16 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     T.begin(3);
     launch_fold(V, make([](const fmm_plan_s *p) { return stage_blocks(p).fold; }, all), s);
     T.end();
-    // P2P overlaps the latency-bound upward pass; M2L, which fills the GPU by
-    // itself, starts once P2P is done (running the two together slows M2L by
-    // about as much as it hides)
-    HIPCHK(hipStreamWaitEvent(s, F->ev_join, 0));
+    HIPCHK(hipStreamWaitEvent(s, F->ev_join, 0)); // first part of P2P done
     T.begin(4);
     for (auto &r : runs)
         launch_m2l(P[r.first]->p, P[r.first]->mixed_m2l, V + r.first,
                    sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).m2l; }), s);
     T.end();
+    HIPCHK(hipEventRecord(F->ev_fork, s)); // second part of P2P next to the downward pass
+    HIPCHK(hipStreamWaitEvent(F->side, F->ev_fork, 0));
+    p2p_part(1);
+    HIPCHK(hipEventRecord(F->ev_join, F->side));
     T.begin(5);
     for (auto &r : runs)
         launch_p2l(P[r.first]->p, V + r.first,
@@ -801,6 +807,7 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
                        sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldm / 16); }), l, s);
     T.end();
     // far field (L2P + M2P) plus the near field, written in the caller's order
+    HIPCHK(hipStreamWaitEvent(s, F->ev_join, 0));
     T.begin(8);
     for (auto &r : runs)
         launch_far(P[r.first]->p, V + r.first,

@@ -14,7 +14,10 @@ void launch_unfold(const PlanView *V, const Bases &B, hipStream_t s);      // 4 
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 X target/block
 void launch_p2l_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 X targets x 16 rows/block
 void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block
-void launch_p2p(int mixed, const PlanView *V, const Bases &B, hipStream_t s); // 4 leaves/block
+// P2P runs in two parts (leaves [0, split) and [split, nleaves)), each
+// overlapping a latency-bound phase of the far field
+__host__ __device__ inline int p2p_split(int nleaves) { return (int)((int64_t)nleaves * 5 / 8) & ~3; }
+void launch_p2p(int mixed, int part, const PlanView *V, const Bases &B, hipStream_t s); // 4 leaves/block
 void launch_zero(double *p, int64_t n, hipStream_t s);
 void launch_m2l(int p, int f32, const PlanView *V, const Bases &B, hipStream_t s); // 64 slots/block
 constexpr int kM2LSlots = 64;

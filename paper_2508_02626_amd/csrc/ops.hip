@@ -540,15 +540,18 @@ __device__ inline void p2p_range(const SrcRec *S, int lo, int hi, Tgt &a, Tgt &b
 }
 
 template <int MIXED>
-__global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B)
+__global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B, int part)
 {
     __shared__ SrcRec sS[4][64];
     __shared__ double sR[4][8][64]; // group partials for the final combination
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int li = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]) * 4 + wave;
-    if (li >= v.nleaves) return;
+    // part 0: leaves [0, split), part 1: leaves [split, nleaves)
+    const int split = p2p_split(v.nleaves);
+    const int lo = part ? split : 0, hi = part ? v.nleaves : split;
+    const int li = lo + xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]) * 4 + wave;
+    if (li >= hi) return;
     const auto first = gptr(v.first), count = gptr(v.count), usrc = gptr(v.U_src);
     const auto xs = gptr(v.xs), ys = gptr(v.ys), zs = gptr(v.zs);
     const auto qs = gptr(v.qs);
@@ -692,11 +695,11 @@ void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (nblk(B)) DISPATCH_P(p, k_far, <<<nblk(B), 64, 0, s>>>(V, B));
 }
-void launch_p2p(int mixed, const PlanView *V, const Bases &B, hipStream_t s)
+void launch_p2p(int mixed, int part, const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (!nblk(B)) return;
-    if (mixed) k_p2p<1><<<nblk(B), 256, 0, s>>>(V, B);
-    else k_p2p<0><<<nblk(B), 256, 0, s>>>(V, B);
+    if (mixed) k_p2p<1><<<nblk(B), 256, 0, s>>>(V, B, part);
+    else k_p2p<0><<<nblk(B), 256, 0, s>>>(V, B, part);
 }
 void launch_zero(double *p, int64_t n, hipStream_t s)
 {
