@@ -80,7 +80,7 @@ void fmm_default_options(fmm_options_t *opt);
  * fmm_plan - build the octree and interaction lists for n points.
  *   xyz_dev    [n][3] FP64 device positions (read during the call only)
  *   n          number of points, 1 <= n < 2^31
- *   order      truncation order p of the DA vectors, 0..12 (Sec. 3, "order")
+ *   order      truncation order p of the DA vectors, 0..16 (Sec. 3, "order")
  *   leaf_size  s >= 1 for adaptive trees (Sec. 3.5); ignored for uniform trees
  *   opt        options, or NULL for fmm_default_options
  *   alloc      allocator, or NULL for hipMallocAsync on `stream`

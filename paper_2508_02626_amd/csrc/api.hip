@@ -493,7 +493,7 @@ int check_options(const fmm_options_t &o, int order, int leaf_size)
         return fail(FMM_EINVAL, "max_depth must be 1..21");
     if (o.precision != FMM_FP64 && o.precision != FMM_MIXED) return fail(FMM_EINVAL, "bad precision");
     if (o.uniform_depth < 0 && leaf_size < 1) return fail(FMM_EINVAL, "leaf_size must be >= 1");
-    if (order < 0 || order > kMaxOrder) return fail(FMM_EINVAL, "order must be 0..12");
+    if (order < 0 || order > kMaxOrder) return fail(FMM_EINVAL, "order must be 0..16");
     if (o.root) {
         for (int k = 0; k < 4; ++k)
             if (!std::isfinite(o.root[k])) return fail(FMM_EINVAL, "non-finite root");

@@ -20,7 +20,7 @@
 
 namespace fmm {
 
-constexpr int kMaxOrder = 12;
+constexpr int kMaxOrder = 16;
 constexpr int kMaxDepth = 21;
 constexpr int kVSlots = 189;   // M2L sources per box, one slot per offset (Sec. 3.4)
 constexpr int kMaxBatch = 256; // plans per batched launch
@@ -51,12 +51,12 @@ inline int pad4(int n) { return (n + 3) & ~3; }
 // 10% of the smallest table.
 __host__ __device__ constexpr int dlayout_s1(int p)
 {
-    constexpr int t[13] = {1, 3, 6, 7, 10, 11, 13, 15, 19, 19, 24, 24, 28};
+    constexpr int t[17] = {1, 3, 6, 7, 10, 11, 13, 15, 19, 19, 24, 24, 28, 28, 30, 34, 38};
     return t[p];
 }
 __host__ __device__ constexpr int dlayout_s2(int p)
 {
-    constexpr int t[13] = {1, 11, 30, 49, 91, 125, 184, 252, 328, 392, 516, 580, 719};
+    constexpr int t[17] = {1, 11, 30, 49, 91, 125, 184, 252, 328, 392, 516, 580, 719, 773, 887, 1066, 1252};
     return t[p];
 }
 __host__ __device__ constexpr int dlayout_ldd(int p) { return (3 * dlayout_s2(p) + 3) & ~3; } // 16-byte rows

@@ -72,14 +72,21 @@ template <typename T> __device__ inline T gload(const T *p)
     return *(const __attribute__((address_space(1))) T *)p;
 }
 
+// From p = 12 on two wavefronts share each group of 16 targets, each taking
+// half of the row tiles (registers would not hold all of them).
+__host__ __device__ constexpr int m2l_row_split(int p) { return p >= 12 ? 2 : 1; }
+
 template <int P, typename T>
-__global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
+__global__ __launch_bounds__(256 * m2l_row_split(P)) void k_m2l(const PlanView *V, Bases B)
 {
+    constexpr int RS = m2l_row_split(P);
+    constexpr int NT = 256 * RS; // threads per block
     constexpr int NH = (P + 1) * (P + 1);
     constexpr int MF = NH / 16, XR0 = NH - 16 * MF;
     constexpr bool XV = MF >= 1 && XR0 <= 2;     // leftover rows go to the VALU
     constexpr int MT = XV ? MF : (NH + 15) / 16; // MFMA row tiles
     constexpr int XR = XV ? XR0 : 0;             // VALU rows
+    constexpr int MTW = (MT + RS - 1) / RS;      // row tiles per wavefront
     // K order: with groups of VW k-steps, step ks gives lane group kq the index
     // a = 4 VW (ks / VW) + VW kq + ks % VW, so that the VW steps of a group read
     // VW consecutive components of the lane's source: B operands come as one
@@ -95,7 +102,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     constexpr int LDC = dlayout_ldc(P); // compact table in memory (only the entries read)
     constexpr int DW = 16 / (int)sizeof(T); // compact tables move in 16-byte vectors
     static_assert(LDC % DW == 0, "compact rows must be whole vectors");
-    constexpr int DV = (LDC / DW + 255) / 256; // table vectors per thread
+    constexpr int DV = (LDC / DW + NT - 1) / NT; // table vectors per thread
     typedef typename Mfma<T>::acc_t acc_t;
     typedef T vec_t __attribute__((ext_vector_type(VW)));
     typedef T dvec_t __attribute__((ext_vector_type(16 / sizeof(T))));
@@ -111,20 +118,21 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     const PlanView &v = V[k];
     const int tile = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
-    // lanes col, col+16, col+32, col+48 serve target wave*16+col (one B column)
-    const int tgt = v.m2l_tgt[tile * kM2LSlots + wave * 16 + col];
+    const int tw = RS > 1 ? wave & 3 : wave, half = RS > 1 ? wave >> 2 : 0; // target group, row share
+    // lanes col, col+16, col+32, col+48 serve target tw*16+col (one B column)
+    const int tgt = v.m2l_tgt[tile * kM2LSlots + tw * 16 + col];
     if (!__syncthreads_or(tgt >= 0)) return;
     if (tgt >= 0) soct = (int)(v.morton[tgt] & 7); // every target of the block has this octant
     if (tid < 64) sTg[tid] = v.m2l_tgt[tile * kM2LSlots + tid];
     const OrderTables &tb = *v.tab;
-    for (int e = tid; e < 4 * KS; e += 256) {
+    for (int e = tid; e < 4 * KS; e += NT) {
         const int g = e / KS, ks = e - g * KS, a = 4 * VW * (ks / VW) + VW * g + ks % VW;
         sHo[g][ks] = a < NH ? tb.hoff[a] : 0;
     }
-    int hb[MT], hx[XR > 0 ? XR : 1];
+    int hb[MTW], hx[XR > 0 ? XR : 1];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        int b = mt * 16 + col;
+    for (int mt = 0; mt < MTW; ++mt) {
+        int b = (half * MTW + mt) * 16 + col;
         hb[mt] = b < NH ? tb.hoff[b] : 0;
     }
 #pragma unroll
@@ -134,7 +142,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     // the block, in increasing order
     {
         const auto vs = gptr(v.vslot);
-        for (int e = tid; e < 64 * kVSlots; e += 256) {
+        for (int e = tid; e < 64 * kVSlots; e += NT) {
             const int t = e / kVSlots, j = e - t * kVSlots, g = sTg[t];
             sSrc[t][j] = g >= 0 ? vs[(int64_t)g * kVSlots + j] : -1;
         }
@@ -157,55 +165,60 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     const int nvalid = sN, ldh = v.ldh;
     const T *Dt = Mfma<T>::D(tb);
     const T *Mh = Mfma<T>::M(v);
-    const int *vsl = sSrc[wave * 16 + col];
+    const int *vsl = sSrc[tw * 16 + col];
 
-    acc_t acc[MT];
-    double4_t acc64[MT]; // FP32 path: per-offset partials are summed in FP64
+    acc_t acc[MTW];
+    double4_t acc64[MTW]; // FP32 path: per-offset partials are summed in FP64
     T xacc[XR > 0 ? XR : 1];
     double xacc64[XR > 0 ? XR : 1];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) { acc[mt] = acc_t{0, 0, 0, 0}; acc64[mt] = double4_t{0, 0, 0, 0}; }
+    for (int mt = 0; mt < MTW; ++mt) { acc[mt] = acc_t{0, 0, 0, 0}; acc64[mt] = double4_t{0, 0, 0, 0}; }
 #pragma unroll
     for (int x = 0; x < XR; ++x) { xacc[x] = (T)0; xacc64[x] = 0.0; }
 
-    // B operands of k-steps VW vi .. VW vi + VW - 1: components 4 VW vi + VW kq (+0 .. VW-1)
-    vec_t pb[NV];
+    // B operands of k-steps VW t .. VW t + VW - 1 (vector t of a slot):
+    // components 4 VW t + VW kq (+0 .. VW-1).  FP64 keeps a window of NW
+    // vectors in flight: vector t of the current slot lives in pb[t % NW], and
+    // once it is used, vector t + NW is loaded into the same register (taken
+    // from the next slot when t + NW runs past the end of this one).  Up to
+    // p = 12 the window is the whole slot.
+    constexpr bool DB = sizeof(T) == 4;
+    constexpr int NW = (DB || P <= 12 || NV <= 8) ? NV : 8;
+    vec_t pb[NW];
     dvec_t pd[DV];
     int dm[DV][DW]; // LDS address of each compact table entry this thread moves
 #pragma unroll
     for (int r = 0; r < DV; ++r)
 #pragma unroll
         for (int w = 0; w < DW; ++w) {
-            const int e = (tid + 256 * r) * DW + w;
+            const int e = (tid + NT * r) * DW + w;
             dm[r][w] = e < LDC ? gptr(tb.dmap)[e] : LDD - 1;
         }
     auto load_d = [&](int j) {
         const dvec_t *Dk = (const dvec_t *)(Dt + sDoff[j]);
 #pragma unroll
         for (int r = 0; r < DV; ++r) {
-            int e = tid + 256 * r;
+            int e = tid + NT * r;
             pd[r] = e < LDC / DW ? gload(Dk + e) : dvec_t{};
         }
     };
     auto store_d = [&](int buf) { // scatter into the additive layout
 #pragma unroll
         for (int r = 0; r < DV; ++r)
-            if (tid + 256 * r < LDC / DW)
+            if (tid + NT * r < LDC / DW)
 #pragma unroll
                 for (int w = 0; w < DW; ++w) sD[buf][dm[r][w]] = pd[r][w];
     };
-    // always issued (a clamped row for absent sources), so that the waits can
-    // count the loads; operands of absent sources and padding components are
-    // zeroed at use.  FP64: each vector register is refilled for the next slot
-    // right after its MFMAs (no second register set); FP32: the next slot's
-    // operands go to a second set loaded at the top of the slot.
-    constexpr bool DB = sizeof(T) == 4;
+    // Loads are always issued (a clamped row for absent sources), so that the
+    // waits can count them; operands of absent sources and padding components
+    // are zeroed at use.  FP32: the next slot's operands go to a second
+    // register set loaded at the top of the slot.
     vec_t pbn[DB ? NV : 1];
     const int64_t kofs = VW * kq;
-    auto load_b = [&](int vi, int src) {
-        const vec_t val = gload((const vec_t *)(Mh + (int64_t)(src >= 0 ? src : 0) * ldh + kofs) + 4 * vi);
-        if constexpr (DB) pbn[vi] = val;
-        else pb[vi] = val;
+    auto load_b = [&](int buf, int t, int src) {
+        const vec_t val = gload((const vec_t *)(Mh + (int64_t)(src >= 0 ? src : 0) * ldh + kofs) + 4 * t);
+        if constexpr (DB) pbn[buf] = val;
+        else pb[buf] = val;
     };
     int src = -1;
     if (nvalid > 0) {
@@ -213,10 +226,10 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         store_d(0);
         src = vsl[sList[0]];
 #pragma unroll
-        for (int vi = 0; vi < NV; ++vi) load_b(vi, src);
+        for (int t = 0; t < NW; ++t) load_b(t, t, src);
         if constexpr (DB) {
 #pragma unroll
-            for (int vi = 0; vi < NV; ++vi) pb[vi] = pbn[vi];
+            for (int t = 0; t < NV; ++t) pb[t] = pbn[t];
         }
         __syncthreads();
     }
@@ -230,16 +243,16 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         const int *Ho = sHo[kq];
         if constexpr (DB) {
 #pragma unroll
-            for (int vi = 0; vi < NV; ++vi) load_b(vi, nsrc);
+            for (int t = 0; t < NV; ++t) load_b(t, t, nsrc);
             __builtin_amdgcn_sched_barrier(0); // keep the loads ahead of the products
         }
         {
             // A operands of step ks+1 are read from LDS while the MFMAs of step ks run
-            T ac[MT], an[MT];
+            T ac[MTW], an[MTW];
             {
                 const int ha = Ho[0];
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) ac[mt] = D[hb[mt] + ha];
+                for (int mt = 0; mt < MTW; ++mt) ac[mt] = D[hb[mt] + ha];
             }
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
@@ -247,21 +260,28 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
                 if (ks + 1 < KS) {
                     const int hn = Ho[ks + 1];
 #pragma unroll
-                    for (int mt = 0; mt < MT; ++mt) an[mt] = D[hb[mt] + hn];
+                    for (int mt = 0; mt < MTW; ++mt) an[mt] = D[hb[mt] + hn];
                 }
-                const T bv = (src >= 0 && 4 * VW * (ks / VW) + VW * kq + ks % VW < NH) ? pb[ks / VW][ks % VW] : (T)0;
+                const T bv = (src >= 0 && 4 * VW * (ks / VW) + VW * kq + ks % VW < NH)
+                                 ? pb[(ks / VW) % NW][ks % VW] : (T)0;
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) acc[mt] = Mfma<T>::run(ac[mt], bv, acc[mt]);
+                for (int mt = 0; mt < MTW; ++mt)
+                    if (RS == 1 || half * MTW + mt < MT) acc[mt] = Mfma<T>::run(ac[mt], bv, acc[mt]);
+                if (half == RS - 1)
 #pragma unroll
-                for (int x = 0; x < XR; ++x) xacc[x] += D[hx[x] + ha] * bv;
-                if constexpr (!DB) // next slot's operands, once this vector is used up
-                    if (ks % VW == VW - 1 || ks == KS - 1) load_b(ks / VW, nsrc);
+                    for (int x = 0; x < XR; ++x) xacc[x] += D[hx[x] + ha] * bv;
+                if constexpr (!DB) // refill once this vector is used up
+                    if (ks % VW == VW - 1 || ks == KS - 1) {
+                        const int t = ks / VW;
+                        if (t + NW < NV) load_b((t + NW) % NW, t + NW, src);
+                        else load_b(t % NW, t % NW, nsrc);
+                    }
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) ac[mt] = an[mt];
+                for (int mt = 0; mt < MTW; ++mt) ac[mt] = an[mt];
             }
             if constexpr (sizeof(T) == 4) {
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
+                for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) acc64[mt][r] += (double)acc[mt][r];
                     acc[mt] = acc_t{0, 0, 0, 0};
@@ -272,7 +292,7 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         }
         if constexpr (DB) {
 #pragma unroll
-            for (int vi = 0; vi < NV; ++vi) pb[vi] = pbn[vi];
+            for (int t = 0; t < NV; ++t) pb[t] = pbn[t];
         }
         if (more) store_d(cur ^ 1);
         src = nsrc;
@@ -290,13 +310,14 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
     if (tgt < 0) return;
     double *Lh = v.Lh + (int64_t)tgt * ldh;
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MTW; ++mt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            int b = mt * 16 + Mfma<T>::row(lane, r);
-            if (b < NH) Lh[b] = sizeof(T) == 4 ? acc64[mt][r] : (double)acc[mt][r];
+            int b = (half * MTW + mt) * 16 + Mfma<T>::row(lane, r);
+            if (b < NH && (RS == 1 || half * MTW + mt < MT))
+                Lh[b] = sizeof(T) == 4 ? acc64[mt][r] : (double)acc[mt][r];
         }
-    if (kq == 0) {
+    if (kq == 0 && half == RS - 1) {
 #pragma unroll
         for (int x = 0; x < XR; ++x) Lh[16 * MT + x] = xs[x];
     }
@@ -307,17 +328,19 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
         if (f32) k_m2l<PP, float><<<nb, 256, 0, s>>>(V, B);                        \
         else k_m2l<PP, double><<<nb, 256, 0, s>>>(V, B);                           \
         break;
+#define M2L_CASE64(PP)                                                             \
+    case PP: k_m2l<PP, double><<<nb, 256 * m2l_row_split(PP), 0, s>>>(V, B); break;
 
+// FP32 M2L exists for p <= 8 only (the mixed path keeps M2L in FP64 above)
 void launch_m2l(int p, int f32, const PlanView *V, const Bases &B, hipStream_t s)
 {
     unsigned nb = (unsigned)B.b[B.n];
     if (!nb) return;
     switch (p) {
         M2L_CASE(0) M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5) M2L_CASE(6)
-        M2L_CASE(7) M2L_CASE(8) M2L_CASE(9) M2L_CASE(10) M2L_CASE(11)
-    default:
-        if (f32) k_m2l<12, float><<<nb, 256, 0, s>>>(V, B);
-        else k_m2l<12, double><<<nb, 256, 0, s>>>(V, B);
+        M2L_CASE(7) M2L_CASE(8) M2L_CASE64(9) M2L_CASE64(10) M2L_CASE64(11) M2L_CASE64(12)
+        M2L_CASE64(13) M2L_CASE64(14) M2L_CASE64(15)
+    default: k_m2l<16, double><<<nb, 256 * m2l_row_split(16), 0, s>>>(V, B);
     }
 }
 

@@ -650,7 +650,9 @@ __global__ void k_zero(double *p, int64_t n)
     case 6: KERNEL<6> __VA_ARGS__; break;  case 7: KERNEL<7> __VA_ARGS__; break;     \
     case 8: KERNEL<8> __VA_ARGS__; break;  case 9: KERNEL<9> __VA_ARGS__; break;     \
     case 10: KERNEL<10> __VA_ARGS__; break; case 11: KERNEL<11> __VA_ARGS__; break;  \
-    default: KERNEL<12> __VA_ARGS__; break;                                            \
+    case 12: KERNEL<12> __VA_ARGS__; break; case 13: KERNEL<13> __VA_ARGS__; break;  \
+    case 14: KERNEL<14> __VA_ARGS__; break; case 15: KERNEL<15> __VA_ARGS__; break;  \
+    default: KERNEL<16> __VA_ARGS__; break;                                            \
     }
 
 static inline unsigned nblk(const Bases &B) { return (unsigned)B.b[B.n]; }

@@ -281,7 +281,9 @@ void build_tables(int p, Built &B)
                 if (eg[0] < ea[0] || eg[1] < ea[1] || eg[2] < ea[2]) continue;
                 ld v = std::ldexp(1.0L, -(eg[0] + eg[1] + eg[2]));
                 for (int k = 0; k < 3; ++k) v *= ipow(-tau[k], eg[k] - ea[k]) / fact(eg[k] - ea[k]);
-                for (int be = 0; be < nc; ++be) out[be] += Pi[(size_t)g * nc + be] * v;
+                // the projection keeps the degree: only that degree's block of Pi
+                const int n = m.deg(g);
+                for (int be = below(n); be < below(n + 1); ++be) out[be] += Pi[(size_t)g * nc + be] * v;
             }
             for (int be = 0; be < nc; ++be) B.S[((size_t)o * nc + al) * nc + be] = (double)out[be];
         }

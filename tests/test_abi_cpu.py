@@ -37,7 +37,7 @@ def test_invalid_arguments_rejected_on_host():
     assert b"null" in lib.fmm_last_error()
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
     assert lib.fmm_plan(fake, 0, 4, 8, ctypes.byref(o), None, None, ctypes.byref(h)) == fmm.FMM_EINVAL
-    assert lib.fmm_plan(fake, 10, 13, 8, ctypes.byref(o), None, None, ctypes.byref(h)) == fmm.FMM_EINVAL
+    assert lib.fmm_plan(fake, 10, 17, 8, ctypes.byref(o), None, None, ctypes.byref(h)) == fmm.FMM_EINVAL
     assert lib.fmm_plan(fake, 10, -1, 8, ctypes.byref(o), None, None, ctypes.byref(h)) == fmm.FMM_EINVAL
     assert lib.fmm_plan(fake, 10, 4, 0, ctypes.byref(o), None, None, ctypes.byref(h)) == fmm.FMM_EINVAL
     o.precision = 7
@@ -64,7 +64,7 @@ def test_invalid_arguments_rejected_on_host():
     hv = (ctypes.c_void_p * 2)()
     xv = (ctypes.c_void_p * 2)(0x1000, 0x2000)
     nv = (ctypes.c_int64 * 2)(10, 10)
-    ov = (ctypes.c_int32 * 2)(4, 13)
+    ov = (ctypes.c_int32 * 2)(4, 17)
     lv = (ctypes.c_int32 * 2)(8, 8)
     assert lib.fmm_plan_batch(-1, None, None, None, None, None, None, None, 4, hv) == fmm.FMM_EINVAL
     assert lib.fmm_plan_batch(0, None, None, None, None, None, None, None, 4, hv) == fmm.FMM_OK

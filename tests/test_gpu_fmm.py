@@ -36,6 +36,32 @@ def test_config1_potentials_match_oracle(p):
     _check_fp64(x, q, p, CFG1)
 
 
+@pytest.mark.parametrize("p", [13, 14, 15, 16])
+def test_high_orders_match_oracle(p):
+    """Orders above 12 (M2L with the row tiles split over two wavefronts and a
+    rolling operand window) on a small clustered tree whose few V offsets keep
+    the oracle's DA compositions affordable."""
+    x, q = inputs.clusters(60, 5)
+    say("clusters 60, s=6, p", p)
+    _check_fp64(x, q, p, dict(leaf_size=6))
+
+
+def test_high_order_error_against_direct():
+    """At 2e5 Plummer points the error against the direct sum keeps falling up
+    to p = 16 (sampled targets)."""
+    x, q = inputs.plummer(200_000, 8)
+    idx = np.sort(np.random.default_rng(3).choice(len(q), 400, replace=False))
+    d, _ = oracle.direct(x, q, idx)
+    errs = []
+    for p in (10, 12, 14, 16):
+        pl, phi, fld = gpu_solve(x, q, p, leaf_size=64)
+        errs.append(rel_l2(phi[idx], d))
+        pl.close()
+    say("  plummer 2e5 sigma by order 10/12/14/16", errs)
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert errs[-1] < 1e-7
+
+
 def test_order12_small_tree():
     x, q = inputs.uniform(600, 12)
     say("uniform depth 2, p=12")
