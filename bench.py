@@ -198,6 +198,25 @@ def bench_plummer(args):
         log("bench plummer: %s step %.2f ms eval %.2f ms sigma %.3e" % (mode, 1e3 * step_s, 1e3 * eval_s, sp))
         res[mode] = dict(step_s=step_s, eval_s=eval_s, stages=stage_avg(st), sizes=sizes, sigma=sp, sigma_f=sf,
                          phi=ph, fld=fh)
+    # the same problem at the order that reaches a relative error of 1e-7
+    hi = {}
+    ph = 14
+    for mode in ("fp64", "mixed"):
+        pl = fmm.Plan(x, ph, leaf_size=64, precision=mode)
+        phi, fld = pl.evaluate(q)
+        pl.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(1, args.steps // 2)):
+            pl = fmm.Plan(x, ph, leaf_size=64, precision=mode)
+            pl.evaluate(q, phi, fld)
+            pl.close()
+        torch.cuda.synchronize()
+        step_s = (time.perf_counter() - t0) / max(1, args.steps // 2)
+        sp, sf, nt = sampled_sigma(xh, qh, phi.cpu().numpy(), fld.cpu().numpy(), count=1000)
+        log("bench plummer: p=%d %s step %.2f ms sigma %.3e" % (ph, mode, 1e3 * step_s, sp))
+        hi[mode] = {"value": n / step_s, "ms_per_step": 1e3 * step_s, "sigma_phi_vs_direct": sp,
+                    "sigma_field_vs_direct": sf}
     f, m = res["fp64"], res["mixed"]
     flops = 2.0 * (p + 1) ** 4 * f["sizes"]["V"]
     m2l_ms = f["stages"]["m2l"]
@@ -224,6 +243,7 @@ def bench_plummer(args):
                   "rel_l2_vs_fp64_path_phi": float(np.linalg.norm(m["phi"] - f["phi"]) / np.linalg.norm(f["phi"])),
                   "rel_l2_vs_fp64_path_field": float(np.linalg.norm(m["fld"] - f["fld"]) / np.linalg.norm(f["fld"])),
                   "dtype": "f64 with f32 P2P terms (M2L stays FP64 at p=10)", "stage_ms": m["stages"]},
+        "order_for_1e-7": {"order": ph, "fp64": hi["fp64"], "mixed": hi["mixed"]},
     })
     return out
 
