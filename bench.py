@@ -17,7 +17,8 @@ the plain oracle on the same workload once (a few seconds on the host cores).
 
 Other workloads (--workload): plummer4m (4e6 Plummer points, adaptive s=64,
 p=10), batch256 (256 independent problems, one fmm_evaluate_batch), serve
-(Poisson request stream through the continuous-batching server, p50/p99).
+(Poisson request stream through the continuous-batching server, p50/p99),
+sweep (leaf size x order x N on Gaussian points, and the scaling with N).
 Each prints one JSON line of the same form.
 
 Prints one JSON line.
@@ -369,13 +370,99 @@ def bench_serve(args):
     return out
 
 
+def bench_sweep(args):
+    """Leaf-size and order sweep and the scaling with N, on the distribution
+    of the paper's sweeps (3-D Gaussian, unit standard deviation, adaptive
+    tree), plain FP64 path, one step = fmm_plan + fmm_evaluate.  For every N
+    and p the leaf size with the shortest step is reported (the experiment
+    behind the paper's optimal-s table); then the step time over N at
+    p in {2, 6, 10} with that leaf size, and the slope of its log-log fit."""
+    import torch
+    from paper_2508_02626_amd import fmm, inputs
+    sizes_n = [100_000, 1_000_000, 10_000_000]
+    orders = [2, 4, 6, 8, 10]
+    leaf = [16, 32, 64, 128, 256, 512]
+    reps = max(1, min(args.steps, 3))
+
+    def timed(x, q, p, s):
+        def step():
+            pl = fmm.Plan(x, p, leaf_size=s, precision="fp64")
+            pl.evaluate(q)
+            return pl
+        step().close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step().close()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    table, best = {}, {}
+    for n in sizes_n:
+        xh, qh = inputs.gaussian(n, 3)
+        x = torch.tensor(xh, device="cuda:0")
+        q = torch.tensor(qh, device="cuda:0")
+        table[n], best[n] = {}, {}
+        for p in orders:
+            row = {s: 1e3 * timed(x, q, p, s) for s in leaf}
+            table[n][p] = row
+            best[n][p] = min(row, key=row.get)
+            log("bench sweep: N=%d p=%d best s=%d (%.2f ms)" % (n, p, best[n][p], row[best[n][p]]))
+        del x, q
+    # accuracy of each order against the direct sum at N = 1e6, best leaf size
+    xh, qh = inputs.gaussian(1_000_000, 3)
+    x = torch.tensor(xh, device="cuda:0")
+    q = torch.tensor(qh, device="cuda:0")
+    sigma = {}
+    for p in orders:
+        pl = fmm.Plan(x, p, leaf_size=best[1_000_000][p], precision="fp64")
+        phi, fld = pl.evaluate(q)
+        pl.close()
+        sigma[p] = sampled_sigma(xh, qh, phi.cpu().numpy(), fld.cpu().numpy(), count=500)[0]
+    del x, q
+    # scaling with N at the best leaf size of the nearest swept N
+    scan = [10_000, 30_000, 100_000, 300_000, 1_000_000, 3_000_000, 10_000_000]
+    linear = {}
+    for p in (2, 6, 10):
+        ms = []
+        for n in scan:
+            near = min(sizes_n, key=lambda m: abs(np.log(m / n)))
+            xh, qh = inputs.gaussian(n, 4)
+            x = torch.tensor(xh, device="cuda:0")
+            q = torch.tensor(qh, device="cuda:0")
+            ms.append(1e3 * timed(x, q, p, best[near][p]))
+            del x, q
+        ln, lt = np.log(scan), np.log(ms)
+        big = np.array(scan) >= 100_000
+        linear[p] = {"n": scan, "ms": ms, "slope": float(np.polyfit(ln, lt, 1)[0]),
+                     "slope_n_ge_1e5": float(np.polyfit(ln[big], lt[big], 1)[0])}
+        log("bench sweep: p=%d slope %.3f (N>=1e5: %.3f)" % (p, linear[p]["slope"], linear[p]["slope_n_ge_1e5"]))
+    n_top, p_top = sizes_n[-1], orders[-1]
+    t_top = table[n_top][p_top][best[n_top][p_top]]
+    out = base_record(args)
+    out.update({
+        "steps": reps, "warmup": 1,
+        "value": n_top / (t_top * 1e-3), "ms_per_step": t_top, "dtype": "f64",
+        "config": {"workload": "3-D Gaussian (unit std, seeds 3 and 4), q~U(-1,1), adaptive octree, plain FP64, "
+                               "potential+field; value = N=1e7, p=10 at its best leaf size",
+                   "n": sizes_n, "orders": orders, "leaf_sizes": leaf},
+        "step_ms": {str(n): {str(p): {str(s): v for s, v in r.items()} for p, r in t.items()}
+                    for n, t in table.items()},
+        "best_leaf_size": {str(n): {str(p): s for p, s in b.items()} for n, b in best.items()},
+        "sigma_phi_vs_direct_n1e6": {str(p): v for p, v in sigma.items()},
+        "scaling_with_n": {str(p): v for p, v in linear.items()},
+        "roofline": None,
+    })
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N_DEFAULT)
-    ap.add_argument("--workload", default="uniform1m", choices=["uniform1m", "plummer4m", "batch256", "serve"])
+    ap.add_argument("--workload", default="uniform1m", choices=["uniform1m", "plummer4m", "batch256", "serve", "sweep"])
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
@@ -390,7 +477,8 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     if args.workload != "uniform1m":
-        fn = {"plummer4m": bench_plummer, "batch256": bench_batch, "serve": bench_serve}[args.workload]
+        fn = {"plummer4m": bench_plummer, "batch256": bench_batch, "serve": bench_serve,
+              "sweep": bench_sweep}[args.workload]
         print(json.dumps(fn(args)), flush=True)
         return
     n = args.n

@@ -87,7 +87,10 @@ void fmm_default_options(fmm_options_t *opt);
  *   stream     HIP stream for all device work
  *   out        receives the plan handle on success (untouched on failure)
  * Synchronises `stream` to learn tree and list sizes; returns FMM_EINVAL for
- * invalid arguments or non-finite coordinates.
+ * invalid arguments or non-finite coordinates, FMM_EUNSUPPORTED when the
+ * tree has so many boxes that its folded multipoles (order >= 6: boxes + 1
+ * rows of 16 ceil(k / 4) doubles, k the M2L k-steps, 24 at order 8) reach
+ * 4 GiB.
  */
 int fmm_plan(const double *xyz_dev, int64_t n, int32_t order, int32_t leaf_size,
              const fmm_options_t *opt, const fmm_allocator_t *alloc, hipStream_t stream,

@@ -72,6 +72,91 @@ __global__ void k_collect_sizes(const int64_t *uoff, const int64_t *voff, const 
     }
 }
 
+// Device memory cache.  Plans are built and destroyed per solve, and every
+// build takes a few large chunks (owned and temporary), so hipMallocAsync /
+// hipFreeAsync calls would dominate small solves.  A freed chunk is kept,
+// with an event recorded on the stream that freed it, in a per-device list
+// (up to kCacheBytes); an allocation of at most the chunk's size and at least
+// half of it takes it back after making its own stream wait for that event,
+// so the memory is reused in stream order without blocking the host.
+namespace {
+constexpr size_t kCacheBytes = (size_t)8 << 30;
+struct Cached { void *p; size_t bytes; hipEvent_t ready; };
+std::mutex g_cache_mu;
+std::map<int, std::multimap<size_t, Cached>> g_mem_cache;
+std::map<int, size_t> g_cache_total;
+std::map<int, std::vector<hipEvent_t>> g_event_pool;
+} // namespace
+
+// *got receives the size of the chunk handed out (>= bytes)
+static void *cache_alloc(int dev, size_t bytes, hipStream_t s, size_t *got)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto &m = g_mem_cache[dev];
+        auto it = m.lower_bound(bytes);
+        if (it != m.end() && it->first <= 2 * bytes) {
+            Cached c = it->second;
+            m.erase(it);
+            g_cache_total[dev] -= c.bytes;
+            if (hipStreamWaitEvent(s, c.ready, 0) == hipSuccess) {
+                g_event_pool[dev].push_back(c.ready);
+                *got = c.bytes;
+                return c.p;
+            }
+            (void)hipEventSynchronize(c.ready);
+            (void)hipEventDestroy(c.ready);
+            (void)hipFree(c.p);
+        }
+    }
+    void *p = nullptr;
+    if (hipMallocAsync(&p, bytes, s) != hipSuccess) {
+        // out of memory: hand the cached chunks back to the device and retry
+        (void)hipGetLastError();
+        std::multimap<size_t, Cached> all;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            all.swap(g_mem_cache[dev]);
+            g_cache_total[dev] = 0;
+        }
+        if (all.empty()) return nullptr;
+        for (auto &e : all) {
+            (void)hipEventSynchronize(e.second.ready);
+            (void)hipEventDestroy(e.second.ready);
+            (void)hipFree(e.second.p);
+        }
+        if (hipMallocAsync(&p, bytes, s) != hipSuccess) return nullptr;
+    }
+    *got = bytes;
+    return p;
+}
+
+static void cache_free(int dev, void *p, size_t bytes, hipStream_t s)
+{
+    hipEvent_t ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        if (g_cache_total[dev] + bytes > kCacheBytes) {
+            (void)hipFreeAsync(p, s);
+            return;
+        }
+        auto &ep = g_event_pool[dev];
+        if (!ep.empty()) { ev = ep.back(); ep.pop_back(); }
+    }
+    if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFreeAsync(p, s);
+        return;
+    }
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        (void)hipEventDestroy(ev);
+        (void)hipFreeAsync(p, s);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    g_mem_cache[dev].insert({bytes, Cached{p, bytes, ev}});
+    g_cache_total[dev] += bytes;
+}
+
 // Side streams (with their fork and join events) are kept in a per-device
 // pool: creating a stream costs far more than an evaluation's launches, and a
 // plan built per solve would otherwise create one every time.  A released
@@ -119,7 +204,7 @@ struct fmm_plan_s {
     std::vector<std::pair<void *, size_t>> temps; // freed at the end of the build
     size_t footprint = 0;
     double root[4] = {0, 0, 0, 1};
-    int p = 0, nc = 0, nh = 0, ldm = 0, ldh = 0, D = 0, depth = 0, leaf_size = 0;
+    int p = 0, nc = 0, nh = 0, ldm = 0, ldh = 0, ldmh = 0, D = 0, depth = 0, leaf_size = 0;
     int uniform = 0, precision = 0, mixed_m2l = 0;
     int n = 0, nboxes = 0, nleaves = 0, nxtgt = 0, nslots = 0;
     int64_t nlist[4] = {0, 0, 0, 0};
@@ -172,19 +257,19 @@ struct fmm_plan_s {
     int32_t *lvl_dev = nullptr; // first box of every level (device)
 
     static size_t rounded(size_t bytes) { return ((bytes ? bytes : 8) + 255) & ~(size_t)255; }
-    void *raw_alloc(size_t bytes)
+    // returns the chunk and, in *got, its size
+    void *raw_alloc(size_t bytes, size_t *got)
     {
         bytes = rounded(bytes);
-        void *p = nullptr;
-        if (user_alloc) p = alloc.alloc(bytes, stream, alloc.ctx);
-        else if (hipMallocAsync(&p, bytes, stream) != hipSuccess) p = nullptr;
-        return p;
+        *got = bytes;
+        if (user_alloc) return alloc.alloc(bytes, stream, alloc.ctx);
+        return cache_alloc(device, bytes, stream, got);
     }
-    void raw_free(void *p)
+    void raw_free(void *p, size_t bytes)
     {
         if (!p) return;
         if (user_alloc) alloc.free(p, stream, alloc.ctx);
-        else (void)hipFreeAsync(p, stream);
+        else cache_free(device, p, bytes, stream);
     }
     // Buffers are carved from a few large chunks (reserve_*), one per build
     // phase; a request that does not fit the current chunk gets its own
@@ -203,40 +288,41 @@ struct fmm_plan_s {
     bool reserve(bool owned, size_t bytes)
     {
         bytes = rounded(bytes);
-        void *p = raw_alloc(bytes);
+        size_t got = 0;
+        void *p = raw_alloc(bytes, &got);
         if (!p) return false;
-        if (owned) { bufs.push_back({p, bytes}); footprint += bytes; own_chunk = {(char *)p, bytes, 0}; }
-        else { temps.push_back({p, bytes}); temp_chunk = {(char *)p, bytes, 0}; }
+        if (owned) { bufs.push_back({p, got}); footprint += bytes; own_chunk = {(char *)p, bytes, 0}; }
+        else { temps.push_back({p, got}); temp_chunk = {(char *)p, bytes, 0}; }
         return true;
     }
     template <typename T> T *own(size_t count)
     {
-        size_t b = sizeof(T) * count;
+        size_t b = sizeof(T) * count, got = 0;
         void *p = carve(own_chunk, b);
         if (p) return (T *)p;
-        p = raw_alloc(b);
-        if (p) { bufs.push_back({p, b}); footprint += rounded(b); }
+        p = raw_alloc(b, &got);
+        if (p) { bufs.push_back({p, got}); footprint += rounded(b); }
         return (T *)p;
     }
     template <typename T> T *temp(size_t count)
     {
-        size_t b = sizeof(T) * count;
+        size_t b = sizeof(T) * count, got = 0;
         void *p = carve(temp_chunk, b);
         if (p) return (T *)p;
-        p = raw_alloc(b);
-        if (p) temps.push_back({p, b});
+        p = raw_alloc(b, &got);
+        if (p) temps.push_back({p, got});
         return (T *)p;
     }
     void release_temps()
     {
-        for (auto &t : temps) raw_free(t.first);
+        for (auto &t : temps) raw_free(t.first, t.second);
         temps.clear();
         temp_chunk = Chunk{};
     }
     void release_all()
     {
         release_temps();
-        for (auto &b : bufs) raw_free(b.first);
+        for (auto &b : bufs) raw_free(b.first, b.second);
         bufs.clear();
         own_chunk = Chunk{};
         footprint = 0;
@@ -329,6 +415,9 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         P->nboxes = (int)tot;
     }
     const int nb = P->nboxes;
+    // the sign-class M2L addresses the folded multipoles with 32-bit byte offsets
+    if (m2l_sym(P->p) && (unsigned long long)(nb + 1) * (unsigned long long)P->ldmh * 8ULL >= (1ULL << 32))
+        return fail(FMM_EUNSUPPORTED, "too many boxes for this order (folded multipoles reach 4 GiB)");
     // ---- phase B: boxes, list counts, work lists (sizes known from nb)
     {
         Sizer o;
@@ -338,8 +427,8 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         o.add<int32_t>((size_t)nb * kVSlots).add<int32_t>(nb).add<int32_t>(nb).add<int32_t>(nb)
          .add<int32_t>(kMaxDepth + 2).add<PlanView>(1)
          .add<double>((size_t)nb * P->ldm).add<double>((size_t)nb * P->ldm)
-         .add<double>((size_t)nb * P->ldh).add<double>((size_t)nb * P->ldh);
-        if (P->mixed_m2l) o.add<float>((size_t)nb * P->ldh);
+         .add<double>((size_t)(nb + 1) * P->ldmh).add<double>((size_t)nb * P->ldh);
+        if (P->mixed_m2l) o.add<float>((size_t)(nb + 1) * P->ldmh);
         if (!P->reserve(true, o.total)) return fail(FMM_ENOMEM, "device allocation failed (boxes)");
         Sizer t;
         if (adaptive)
@@ -365,8 +454,9 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     int32_t *lnl_off = P->own<int32_t>(kMaxDepth + 2);
     P->view_dev = P->own<PlanView>(1);
     double *M = P->own<double>((size_t)nb * P->ldm), *L = P->own<double>((size_t)nb * P->ldm);
-    double *Mh = P->own<double>((size_t)nb * P->ldh), *Lh = P->own<double>((size_t)nb * P->ldh);
-    float *Mhf = P->mixed_m2l ? P->own<float>((size_t)nb * P->ldh) : nullptr;
+    // folded multipoles: one row per box and an all-zero row after them
+    double *Mh = P->own<double>((size_t)(nb + 1) * P->ldmh), *Lh = P->own<double>((size_t)nb * P->ldh);
+    float *Mhf = P->mixed_m2l ? P->own<float>((size_t)(nb + 1) * P->ldmh) : nullptr;
     NOMEM(vslot); NOMEM(leaves); NOMEM(nonleaf); NOMEM(xtgt); NOMEM(lnl_off); NOMEM(P->view_dev);
     NOMEM(M); NOMEM(L); NOMEM(Mh); NOMEM(Lh);
     if (P->mixed_m2l) NOMEM(Mhf);
@@ -465,7 +555,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     P->nslots = (int)slot_cap;
 
     PlanView &v = P->view;
-    v.p = P->p; v.nc = P->nc; v.nh = P->nh; v.ldm = P->ldm; v.ldh = P->ldh;
+    v.p = P->p; v.nc = P->nc; v.nh = P->nh; v.ldm = P->ldm; v.ldh = P->ldh; v.ldmh = P->ldmh;
     v.precision = P->precision; v.mixed_m2l = P->mixed_m2l; v.depth = P->depth; v.D = P->D;
     v.n = n; v.nboxes = nb; v.nleaves = P->nleaves; v.nxtgt = P->nxtgt; v.nslots = P->nslots;
     for (int k = 0; k < 3; ++k) v.lo[k] = P->root[k];
@@ -539,7 +629,7 @@ extern "C" int fmm_plan(const double *xyz_dev, int64_t n, int32_t order, int32_t
     P->stream = stream;
     if (alloc) { P->alloc = *alloc; P->user_alloc = true; }
     P->p = order; P->nc = ncoef(order); P->nh = nharm(order);
-    P->ldm = pad16(P->nc); P->ldh = pad16(P->nh);
+    P->ldm = pad16(P->nc); P->ldh = pad16(P->nh); P->ldmh = folded_ld(order);
     P->uniform = o.uniform_depth >= 0;
     P->D = P->uniform ? o.uniform_depth : o.max_depth;
     P->leaf_size = leaf_size;
@@ -598,7 +688,8 @@ extern "C" int fmm_plan_batch(int32_t count, const double *const *xyz_dev, const
     auto worker = [&](bool own_stream) {
         if (hipSetDevice(dev) != hipSuccess) return;
         hipStream_t ws = stream;
-        if (own_stream && hipStreamCreateWithFlags(&ws, hipStreamNonBlocking) != hipSuccess) ws = stream;
+        hipEvent_t e1 = nullptr, e2 = nullptr; // (unused events of the pooled stream set)
+        if (own_stream && side_acquire(dev, ws, e1, e2)) ws = stream;
         if (ws != stream) (void)hipStreamWaitEvent(ws, ready, 0);
         for (int i; (i = next.fetch_add(1)) < count;) {
             if (first_bad.load() < count) break;
@@ -612,7 +703,7 @@ extern "C" int fmm_plan_batch(int32_t count, const double *const *xyz_dev, const
             }
             out[i]->stream = stream; // built and synchronised: later frees are ordered on the caller's stream
         }
-        if (ws != stream) (void)hipStreamDestroy(ws);
+        if (ws != stream) side_release(dev, ws, e1, e2);
     };
     if (nthr == 1) {
         worker(false);
@@ -643,10 +734,10 @@ StagePlan stage_blocks(const fmm_plan_s *P)
     StagePlan sp;
     sp.permute = (int)ceil_div(P->n, 256);
     sp.p2m = P->nleaves;
-    sp.fold = (int)ceil_div(P->nboxes, 4);
+    sp.fold = (int)ceil_div(P->nboxes + 1, 4); // and the zero row
     sp.m2l = P->nslots / kM2LSlots;
     sp.p2l = P->nxtgt;
-    sp.unfold = sp.fold;
+    sp.unfold = (int)ceil_div(P->nboxes, 4);
     sp.far = P->nleaves;
     const int split = p2p_split(P->nleaves);
     sp.p2p[0] = (int)ceil_div(split, 4);
@@ -900,8 +991,8 @@ extern "C" int fmm_plan_estimate(int64_t n, int32_t order, int32_t leaf_size, co
     } else {
         boxes = 1 + 8.0 * 2.0 * n / (leaf_size + 1);
     }
-    double ldm = pad16(ncoef(order)), ldh = pad16(nharm(order));
-    double per_box = 8 * (2 * ldm + 2 * ldh) + 4 * (ldh) + 4 * 200 + 64; // expansions, slots, lists
+    double ldm = pad16(ncoef(order)), ldh = pad16(nharm(order)), ldmh = folded_ld(order);
+    double per_box = 8 * (2 * ldm + ldh + ldmh) + 4 * ldmh + 4 * 200 + 64; // expansions, slots, lists
     double per_particle = 8 * 3 + 4 + 8 * 5 + 8 * 2;
     double total = boxes * per_box + n * per_particle + 8 * 27 * boxes;
     *bytes = (size_t)(total * 1.25);

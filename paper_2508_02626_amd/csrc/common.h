@@ -66,6 +66,51 @@ __host__ __device__ constexpr int dlayout_ldc(int p)
     return ((2 * p + 1) * (2 * p + 2) / 2 + (2 * p) * (2 * p + 1) / 2 + (2 * p - 1) * (2 * p) / 2 + 3) & ~3;
 }
 
+// Sign classes of M2L offsets.  1/|x| is even in every coordinate, so
+// D_g(s o k) = s^g D_g(k) for a sign vector s (s^g = prod s_i^g_i).  The V
+// list offsets of one octant fall into 56 classes of offsets that differ only
+// in sign (|k_x|, |k_y|, |k_z| fixed); with the multipoles of a class's members
+// combined by a Walsh-Hadamard transform over the signs, one contraction with
+// the derivative table of a single representative serves the whole class,
+// output rows taking the combination that matches their parity.  The M2L
+// operands are kept in parity-sorted order for this: the harmonic components
+// of each parity class c (x, y, z exponent parities as bits 2, 1, 0), in
+// increasing harmonic index, padded to 16 rows (output) or 4 columns (input).
+constexpr int kSymClasses = 56;
+__host__ __device__ constexpr int sym_class_count(int p, int c)
+{
+    int n = 0;
+    for (int i = (c >> 2) & 1; i + (c & 1) <= p; i += 2)
+        for (int j = (c >> 1) & 1; i + j + (c & 1) <= p; j += 2) ++n;
+    return n;
+}
+__host__ __device__ constexpr int sym_row_tiles(int p)
+{
+    int n = 0;
+    for (int c = 0; c < 8; ++c) n += (sym_class_count(p, c) + 15) / 16;
+    return n;
+}
+__host__ __device__ constexpr int sym_ksteps(int p)
+{
+    int n = 0;
+    for (int c = 0; c < 8; ++c) n += (sym_class_count(p, c) + 3) / 4;
+    return n;
+}
+// orders whose M2L runs on sign classes (fewer matrix-core products from p = 6
+// on; above p = 11 the accumulators of all row tiles no longer fit one
+// wavefront's registers and the slot-by-slot kernel is used)
+__host__ __device__ constexpr bool m2l_sym(int p) { return p >= 6 && p <= 11; }
+// Folded multipoles of sign-class orders are stored so that a lane's
+// operands of vw consecutive k-steps are adjacent (one 16-byte load): sorted
+// column 4 ks + g (k-step ks, lane group g) sits at 4 vw (ks / vw) + vw g +
+// ks % vw, vw = 2 for FP64 and 4 for FP32.
+__host__ __device__ constexpr int sym_pos(int ks, int g, int vw) { return 4 * vw * (ks / vw) + vw * g + ks % vw; }
+// row stride of the folded multipoles (both precisions' layouts fit)
+__host__ __device__ constexpr int folded_ld(int p)
+{
+    return m2l_sym(p) ? 16 * ((sym_ksteps(p) + 3) / 4) : (((p + 1) * (p + 1) + 15) & ~15);
+}
+
 // LDS exchange between the lanes of one wavefront (no workgroup barrier: the
 // wavefronts of a block run independent loops)
 __device__ inline void wave_sync()
@@ -131,6 +176,9 @@ struct OrderTables {
     int p, nc, nh, ldm, ldh, ldd;   // ldd: size of one offset's table in the additive (LDS) layout
     int ldc;                        // stride of one offset's compact table
     int d3;                         // x stride of the additive D layout
+    int ldmh;                       // row stride of the folded multipoles
+    const int *mpos;    // [ldmh] harmonic index of each folded position (-1 padding)
+    const int *mposf;   // same for the FP32 copy
     const double *D;    // [343][ldc] derivative tensors d^g(1/|x|) at integer x, compact
     const float *Df;    // same in FP32
     const int *dmap;    // [ldc] additive-layout address of each compact entry
@@ -142,6 +190,14 @@ struct OrderTables {
     const double *P2L;  // [nc][ldh] inverse moments -> harmonic Lhat
     const int *fold_off; const int *fold_idx; const double *fold_c;     // Mhat -> folded
     const int *unfold_off; const int *unfold_idx; const double *unfold_c; // Lh -> Lhat
+    // sign classes (orders with m2l_sym): rows and columns in parity order,
+    // and per octant the 56 classes: representative offset (packed as in offs)
+    // | zero-axis mask << 16, and the V slot of each member, indexed by the
+    // axes it negates (bits 2, 1, 0 = x, y, z; -1 where there is none)
+    const int *srow;    // [16 row tiles] harmonic index of each sorted row (-1 padding)
+    const int *scol;    // [4 k-steps] harmonic index of each sorted column (-1 padding)
+    const int *srep;    // [8][56]
+    const int *smem;    // [8][56][8]
     const double *inv_fact;     // [nc] 1/b!
     const double *inv_w;        // [p+1] 1/w_n = (-1)^n (2n-1)!!
     const int *exps;            // [nc] packed exponents i | j<<8 | k<<16
@@ -149,7 +205,7 @@ struct OrderTables {
 
 // Everything a kernel needs to know about one plan (lives in device memory).
 struct PlanView {
-    int p, nc, nh, ldm, ldh;
+    int p, nc, nh, ldm, ldh, ldmh;
     int precision;          // FMM_FP64 / FMM_MIXED
     int mixed_m2l;          // FP32 MFMA M2L
     int depth, D;
@@ -173,7 +229,7 @@ struct PlanView {
     const OrderTables *tab;             // device copy of the order tables
     // evaluation buffers
     double *qs;                         // sorted charges
-    double *M, *Mh, *Lh, *L;            // [boxes][ldm] / [boxes][ldh]
+    double *M, *Mh, *Lh, *L;            // [boxes][ldm] / [boxes][ldmh] / [boxes][ldh]
     float *Mhf;                         // FP32 folded multipoles (mixed M2L)
     double *phi_near, *fld_near;        // near-field (P2P) part, sorted order
     // caller's arrays for this evaluation

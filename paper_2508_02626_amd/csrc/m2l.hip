@@ -30,6 +30,8 @@
 // D: f64 lane l reg r -> D[4r + l/16][l%16], f32 lane l reg r -> D[4(l/16)+r][l%16].
 #include "ops.h"
 
+#include <type_traits>
+
 namespace fmm {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -149,9 +151,9 @@ __global__ __launch_bounds__(256 * m2l_row_split(P)) void k_m2l(const PlanView *
     }
     __syncthreads();
     if (tid < kVSlots) {
-        bool any = false;
-        for (int t = 0; t < 64; ++t) any = any || sSrc[t][tid] >= 0;
-        sList[tid] = any ? 1 : 0;
+        int any = 0;
+        for (int t = 0; t < 64; ++t) any |= sSrc[t][tid] >= 0;
+        sList[tid] = any;
         sDoff[tid] = gptr(tb.offs)[soct * kVSlots + tid] * LDC;
     }
     __syncthreads();
@@ -162,7 +164,7 @@ __global__ __launch_bounds__(256 * m2l_row_split(P)) void k_m2l(const PlanView *
         sN = n;
     }
     __syncthreads();
-    const int nvalid = sN, ldh = v.ldh;
+    const int nvalid = sN, ldh = v.ldmh;
     const T *Dt = Mfma<T>::D(tb);
     const T *Mh = Mfma<T>::M(v);
     const int *vsl = sSrc[tw * 16 + col];
@@ -323,6 +325,276 @@ __global__ __launch_bounds__(256 * m2l_row_split(P)) void k_m2l(const PlanView *
     }
 }
 
+// ---------------- M2L on sign classes (orders with m2l_sym) ----------------
+// Same block decomposition (64 targets of one octant, 4 wavefronts x 16), but
+// the loop runs over the octant's 56 sign classes instead of its 189 slots.
+// For class c with representative offset k (components >= 0 on the axes
+// where the class has a pair of members) and members s o k, s negating the
+// axes in the 3-bit mask m:
+//     sum_m sum_a D_(a+b)(s o k) Mhat_a(m) = sum_a D_(a+b)(k) H_a[par(a+b)],
+//     H[r] = sum_m (-1)^|m & r| Mhat(m),
+// a Walsh-Hadamard transform of the members' multipoles (absent members
+// count as zero).  Rows and columns are in parity-sorted order, so the
+// parity of a + b is the same for a whole 16-row tile and k-step: each MFMA
+// takes its B operand from one transform output fixed at compile time.  Where
+// k has a zero component, D_g(k) vanishes for odd g on that axis, and the
+// row-tile / k-step pairs of opposite parity on it are skipped.  Each k-step
+// loads the members' operands (one component per lane and member, 8 loads,
+// always issued so that the waits count them) W steps ahead, across class
+// boundaries.
+template <int P> struct SymShape {
+    static constexpr int RT = sym_row_tiles(P), KS = sym_ksteps(P);
+    int rc[RT], kc[KS]; // parity class of each row tile and k-step
+    constexpr SymShape() : rc(), kc()
+    {
+        int r = 0, k = 0;
+        for (int c = 0; c < 8; ++c) {
+            const int n = sym_class_count(P, c);
+            for (int t = 0; t < (n + 15) / 16; ++t) rc[r++] = c;
+            for (int t = 0; t < (n + 3) / 4; ++t) kc[k++] = c;
+        }
+    }
+};
+
+template <typename T> __device__ inline void wht8(T (&h)[8])
+{
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!(i & bit)) {
+                const T u = h[i], w = h[i | bit];
+                h[i] = u + w;
+                h[i | bit] = u - w;
+            }
+}
+
+template <int P, typename T>
+__global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
+{
+    static constexpr SymShape<P> S{};
+    constexpr int RT = SymShape<P>::RT, KS = SymShape<P>::KS;
+    constexpr int NT = 256, MTW = RT; // one wavefront holds all row tiles of its 16 targets
+    static_assert(RT <= 12, "accumulators of at most 12 row tiles per wavefront");
+    // operands move in vectors of VW k-steps (sym_pos layout); a class has KSV
+    // vectors, rounded up to an even count KSVW (a virtual last one)
+    constexpr int VW = 16 / (int)sizeof(T), KSV = (KS + VW - 1) / VW, KSVW = (KSV + 1) / 2 * 2;
+    static_assert(4 * VW * KSV <= folded_ld(P), "vectors inside the folded row");
+    constexpr int LDD = dlayout_ldd(P), LDC = dlayout_ldc(P);
+    constexpr int DW = 16 / (int)sizeof(T);
+    static_assert(LDC % DW == 0, "compact rows must be whole vectors");
+    constexpr int DV = (LDC / DW + NT - 1) / NT;
+    typedef typename Mfma<T>::acc_t acc_t;
+    typedef T dvec_t __attribute__((ext_vector_type(16 / sizeof(T))));
+    __shared__ T sD[2][LDD];
+    __shared__ int sHo[4][KS];              // D address of column (ks, kq) (0 for padding)
+    __shared__ int sTg[64];
+    __shared__ int sList[kSymClasses];      // classes the block uses
+    __shared__ int sRep[kSymClasses];       // representative | zero mask << 16
+    __shared__ int sMem[kSymClasses][8];    // member slots
+    __shared__ int sZend[8];                // end of each zero mask's classes in sList
+    __shared__ int sSrc[64][kVSlots];
+    __shared__ int sN, soct;
+
+    const int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int tile = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
+    const int tgt = v.m2l_tgt[tile * kM2LSlots + wave * 16 + col];
+    if (!__syncthreads_or(tgt >= 0)) return;
+    if (tgt >= 0) soct = (int)(v.morton[tgt] & 7);
+    if (tid < 64) sTg[tid] = v.m2l_tgt[tile * kM2LSlots + tid];
+    const OrderTables &tb = *v.tab;
+    for (int e = tid; e < 4 * KS; e += NT) {
+        const int g = e / KS, ks = e - g * KS, a = gptr(tb.scol)[4 * ks + g];
+        sHo[g][ks] = a >= 0 ? gptr(tb.hoff)[a] : 0;
+    }
+    int hb[MTW];
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) {
+        const int b = gptr(tb.srow)[16 * mt + col];
+        hb[mt] = b >= 0 ? gptr(tb.hoff)[b] : 0;
+    }
+    __syncthreads();
+    {
+        const auto vs = gptr(v.vslot);
+        for (int e = tid; e < 64 * kVSlots; e += NT) {
+            const int t = e / kVSlots, j = e - t * kVSlots, g = sTg[t];
+            sSrc[t][j] = g >= 0 ? vs[(int64_t)g * kVSlots + j] : -1;
+        }
+        for (int e = tid; e < kSymClasses * 8; e += NT)
+            sMem[e >> 3][e & 7] = gptr(tb.smem)[soct * kSymClasses * 8 + e];
+        if (tid < kSymClasses) sRep[tid] = gptr(tb.srep)[soct * kSymClasses + tid];
+    }
+    __syncthreads();
+    if (tid < kSymClasses) {
+        int any = 0;
+        for (int m = 0; m < 8; ++m) {
+            const int j = sMem[tid][m];
+            if (j >= 0)
+                for (int t = 0; t < 64; ++t) any |= sSrc[t][j] >= 0;
+        }
+        sList[tid] = any;
+    }
+    __syncthreads();
+    if (tid == 0) { // compact; the table lists classes by zero mask, keep where each mask ends
+        int n = 0;
+        for (int c = 0; c < kSymClasses; ++c) {
+            if (sList[c]) sList[n++] = c;
+            sZend[sRep[c] >> 16] = n;
+        }
+        sN = n;
+    }
+    __syncthreads();
+    const int nvalid = sN;
+    const int64_t ldmh = v.ldmh;
+    const T *Dt = Mfma<T>::D(tb);
+    const T *Mh = Mfma<T>::M(v);
+    const int *vsl = sSrc[wave * 16 + col];
+
+    acc_t acc[MTW];
+    double4_t acc64[MTW];
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) { acc[mt] = acc_t{0, 0, 0, 0}; acc64[mt] = double4_t{0, 0, 0, 0}; }
+
+    dvec_t pd[DV];
+    int dm[DV][DW];
+#pragma unroll
+    for (int r = 0; r < DV; ++r)
+#pragma unroll
+        for (int w = 0; w < DW; ++w) {
+            const int e = (tid + NT * r) * DW + w;
+            dm[r][w] = e < LDC ? gptr(tb.dmap)[e] : LDD - 1;
+        }
+    auto load_d = [&](int c) {
+        const dvec_t *Dk = (const dvec_t *)(Dt + (int64_t)(sRep[c] & 0xffff) * LDC);
+#pragma unroll
+        for (int r = 0; r < DV; ++r) {
+            const int e = tid + NT * r;
+            pd[r] = e < LDC / DW ? gload(Dk + e) : dvec_t{};
+        }
+    };
+    auto store_d = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < DV; ++r)
+            if (tid + NT * r < LDC / DW)
+#pragma unroll
+                for (int w = 0; w < DW; ++w) sD[buf][dm[r][w]] = pd[r][w];
+    };
+    // member sources of the lane's target for class list entry q; absent
+    // members read the all-zero row after the boxes
+    const int zrow = v.nboxes;
+    // (as 32-bit byte offsets from Mh: plans check that the array is below 4 GiB)
+    auto class_src = [&](int q, uint32_t (&src)[8]) {
+        const int c = sList[q];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int j = sMem[c][m];
+            const int b = j >= 0 ? vsl[j] : -1;
+            src[m] = ((uint32_t)(b >= 0 ? b : zrow) * (uint32_t)ldmh + (uint32_t)(VW * kq)) * (uint32_t)sizeof(T);
+        }
+    };
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
+    vec_t pb[2][8]; // vector j of a class lives in pb[j % 2]
+    const auto Mg = gptr((const char *)Mh);
+    // (the empty asm keeps each 32-bit offset in its register at the load, so
+    // the address stays base + offset instead of a 64-bit pointer per member
+    // hoisted out of the class loop)
+    auto load_b = [&](int slot, int j, const uint32_t (&src)[8]) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            uint32_t o = src[m];
+            asm volatile("" : "+v"(o));
+            pb[slot][m] = *(gp<const vec_t>)(Mg + (uint64_t)o + 16 * (4 * j));
+        }
+    };
+    uint32_t srcc[8], srcn[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) srcc[m] = srcn[m] = (uint32_t)zrow * (uint32_t)ldmh * (uint32_t)sizeof(T);
+    // one class: KS k-steps; Z (zero-axis mask) decides at compile time which
+    // row-tile / k-step products exist
+    auto run_class = [&](auto zc, const T *D) {
+        constexpr int Z = decltype(zc)::value;
+        const int *Ho = sHo[kq];
+#pragma unroll
+        for (int ks = 0; ks < VW * KSVW; ++ks) {
+            if (ks < KS) {
+                const int ha = Ho[ks];
+                T ac[MTW];
+#pragma unroll
+                for (int mt = 0; mt < MTW; ++mt) {
+                    if (!((S.rc[mt] ^ S.kc[ks]) & Z)) ac[mt] = D[hb[mt] + ha];
+                }
+                T h[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) h[m] = pb[(ks / VW) % 2][m][ks % VW];
+                wht8(h);
+#pragma unroll
+                for (int mt = 0; mt < MTW; ++mt) {
+                    if (!((S.rc[mt] ^ S.kc[ks]) & Z))
+                        acc[mt] = Mfma<T>::run(ac[mt], h[S.rc[mt] ^ S.kc[ks]], acc[mt]);
+                }
+            }
+            if (ks % VW == VW - 1) { // vector j used up: refill its registers with vector j + 2
+                const int j = ks / VW, jn = j + 2;
+                if (jn < KSV) load_b(j % 2, jn, srcc);
+                else if (jn >= KSVW && jn - KSVW < KSV) load_b(j % 2, jn - KSVW, srcn);
+            }
+        }
+    };
+    if (nvalid > 0) {
+        load_d(sList[0]);
+        store_d(0);
+        class_src(0, srcc);
+        load_b(0, 0, srcc);
+        if (KSV > 1) load_b(1, 1, srcc);
+        __syncthreads();
+    }
+    // the classes of one zero mask follow each other: one loop per mask
+    int q = 0;
+    auto run_mask = [&](auto zc) {
+        const int qend = sZend[decltype(zc)::value];
+        for (; q < qend; ++q) {
+            const int cur = q & 1;
+            const bool more = q + 1 < nvalid;
+            if (more) {
+                load_d(sList[q + 1]);
+                class_src(q + 1, srcn);
+            }
+            run_class(zc, sD[cur]);
+            if constexpr (sizeof(T) == 4) {
+#pragma unroll
+                for (int mt = 0; mt < MTW; ++mt) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc64[mt][r] += (double)acc[mt][r];
+                    acc[mt] = acc_t{0, 0, 0, 0};
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) srcc[m] = srcn[m];
+            if (more) store_d(cur ^ 1);
+            __syncthreads();
+        }
+    };
+    run_mask(std::integral_constant<int, 0>{});
+    run_mask(std::integral_constant<int, 1>{});
+    run_mask(std::integral_constant<int, 2>{});
+    run_mask(std::integral_constant<int, 3>{});
+    run_mask(std::integral_constant<int, 4>{});
+    run_mask(std::integral_constant<int, 5>{});
+    run_mask(std::integral_constant<int, 6>{}); // at most two zero axes
+    if (tgt < 0) return;
+    double *Lh = v.Lh + (int64_t)tgt * v.ldh;
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int b = gptr(tb.srow)[16 * mt + Mfma<T>::row(lane, r)];
+            if (b >= 0) Lh[b] = sizeof(T) == 4 ? acc64[mt][r] : (double)acc[mt][r];
+        }
+    }
+}
+
 #define M2L_CASE(PP)                                                               \
     case PP:                                                                       \
         if (f32) k_m2l<PP, float><<<nb, 256, 0, s>>>(V, B);                        \
@@ -332,14 +604,25 @@ __global__ __launch_bounds__(256 * m2l_row_split(P)) void k_m2l(const PlanView *
     case PP: k_m2l<PP, double><<<nb, 256 * m2l_row_split(PP), 0, s>>>(V, B); break;
 
 // FP32 M2L exists for p <= 8 only (the mixed path keeps M2L in FP64 above)
+#define M2L_SYM(PP)                                                                \
+    case PP:                                                                       \
+        if (f32) k_m2l_sym<PP, float><<<nb, 256, 0, s>>>(V, B);                    \
+        else k_m2l_sym<PP, double><<<nb, 256, 0, s>>>(V, B);                       \
+        break;
+#define M2L_SYM64(PP)                                                              \
+    case PP: k_m2l_sym<PP, double><<<nb, 256, 0, s>>>(V, B); break;
+
+// FP32 M2L exists for p <= 8 only (the mixed path keeps M2L in FP64 above);
+// orders 6..11 run on sign classes (m2l_sym)
 void launch_m2l(int p, int f32, const PlanView *V, const Bases &B, hipStream_t s)
 {
     unsigned nb = (unsigned)B.b[B.n];
     if (!nb) return;
+    static_assert(m2l_sym(6) && m2l_sym(11) && !m2l_sym(5) && !m2l_sym(12), "dispatch below");
     switch (p) {
-        M2L_CASE(0) M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5) M2L_CASE(6)
-        M2L_CASE(7) M2L_CASE(8) M2L_CASE64(9) M2L_CASE64(10) M2L_CASE64(11) M2L_CASE64(12)
-        M2L_CASE64(13) M2L_CASE64(14) M2L_CASE64(15)
+        M2L_CASE(0) M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5)
+        M2L_SYM(6) M2L_SYM(7) M2L_SYM(8) M2L_SYM64(9) M2L_SYM64(10) M2L_SYM64(11)
+        M2L_CASE64(12) M2L_CASE64(13) M2L_CASE64(14) M2L_CASE64(15)
     default: k_m2l<16, double><<<nb, 256 * m2l_row_split(16), 0, s>>>(V, B);
     }
 }

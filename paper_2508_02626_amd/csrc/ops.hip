@@ -137,14 +137,19 @@ __global__ __launch_bounds__(256) void k_fold(const PlanView *V, Bases B)
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     int box = (blockIdx.x - B.b[k]) * 4 + (threadIdx.x >> 6);
-    if (box >= v.nboxes) return;
+    if (box > v.nboxes) return;
     const OrderTables &t = *v.tab;
     const double *M = v.M + (int64_t)box * v.ldm;
-    for (int c = threadIdx.x & 63; c < v.ldh; c += 64) {
+    // row nboxes is the zero row (the operand of absent M2L sources)
+    auto fold = [&](int h) {
         double s = 0.0;
-        for (int e = t.fold_off[c]; e < t.fold_off[c + 1]; ++e) s += t.fold_c[e] * M[t.fold_idx[e]];
-        v.Mh[(int64_t)box * v.ldh + c] = s;
-        if (v.mixed_m2l) v.Mhf[(int64_t)box * v.ldh + c] = (float)s;
+        if (h >= 0 && box < v.nboxes)
+            for (int e = t.fold_off[h]; e < t.fold_off[h + 1]; ++e) s += t.fold_c[e] * M[t.fold_idx[e]];
+        return s;
+    };
+    for (int c = threadIdx.x & 63; c < v.ldmh; c += 64) { // c: folded position
+        v.Mh[(int64_t)box * v.ldmh + c] = fold(t.mpos[c]);
+        if (v.mixed_m2l) v.Mhf[(int64_t)box * v.ldmh + c] = (float)fold(t.mposf[c]);
     }
 }
 

@@ -165,6 +165,7 @@ struct Built {
     std::vector<double> D, S, G, P2M, P2L, fold_c, unfold_c, inv_fact, inv_w;
     std::vector<float> Df;
     std::vector<int> offs, hoff, fold_off, fold_idx, unfold_off, unfold_idx, exps, dmap;
+    std::vector<int> mpos, mposf, srow, scol, srep, smem;
     int ldd = 0, ldc = 0;
 };
 
@@ -234,6 +235,69 @@ void build_tables(int p, Built &B)
                     int s = vslot_of(o, kx, ky, kz);
                     if (s >= 0) B.offs[o * kVSlots + s] = (kx + 3) * 49 + (ky + 3) * 7 + (kz + 3);
                 }
+
+    // sign classes: parity-sorted rows (padded to 16) and columns (padded to 4)
+    B.srow.clear();
+    B.scol.clear();
+    for (int c = 0; c < 8; ++c) {
+        for (int h = 0; h < nh; ++h)
+            if ((hx[h] & 1) == ((c >> 2) & 1) && (hy[h] & 1) == ((c >> 1) & 1) && hz[h] == (c & 1)) {
+                B.srow.push_back(h);
+                B.scol.push_back(h);
+            }
+        B.srow.resize(pad16((int)B.srow.size()), -1);
+        B.scol.resize(pad4((int)B.scol.size()), -1);
+    }
+    if ((int)B.srow.size() != 16 * sym_row_tiles(p) || (int)B.scol.size() != 4 * sym_ksteps(p))
+        throw std::logic_error("sign-class layout");
+    // folded multipoles: parity-sorted in load order for sign-class orders,
+    // else harmonic order
+    B.mpos.assign(folded_ld(p), -1);
+    B.mposf.assign(folded_ld(p), -1);
+    if (m2l_sym(p)) {
+        for (int ks = 0; ks < sym_ksteps(p); ++ks)
+            for (int g = 0; g < 4; ++g) {
+                B.mpos[sym_pos(ks, g, 2)] = B.scol[4 * ks + g];
+                B.mposf[sym_pos(ks, g, 4)] = B.scol[4 * ks + g];
+            }
+    } else {
+        for (int c = 0; c < nh; ++c) B.mpos[c] = B.mposf[c] = c;
+    }
+    // the classes of each octant: per axis, |k| in {1, 2} gives a pair of
+    // members (+, -), 0 and 3 a single one (the octant admits only one of +-3)
+    // (listed by zero-axis mask, so that a block runs the classes of one mask
+    // one after the other)
+    B.srep.assign(8 * kSymClasses, 0);
+    B.smem.assign(8 * kSymClasses * 8, -1);
+    for (int o = 0; o < 8; ++o) {
+        int c = 0;
+        for (int zsel = 0; zsel < 8; ++zsel)
+            for (int ax = 0; ax <= 3; ++ax)
+                for (int ay = 0; ay <= 3; ++ay)
+                    for (int az = 0; az <= 3; ++az) {
+                        if (ax <= 1 && ay <= 1 && az <= 1) continue;
+                        const int a[3] = {ax, ay, az};
+                        int rep[3], zero = 0, pair = 0;
+                        for (int d = 0; d < 3; ++d) {
+                            const int hi = (o >> (2 - d)) & 1; // octant bit: range [-3, 2] or [-2, 3]
+                            rep[d] = a[d] == 3 ? (hi ? 3 : -3) : a[d];
+                            if (a[d] == 0) zero |= 4 >> d;
+                            if (a[d] == 1 || a[d] == 2) pair |= 4 >> d;
+                        }
+                        if (zero != zsel) continue;
+                        B.srep[o * kSymClasses + c] = ((rep[0] + 3) * 49 + (rep[1] + 3) * 7 + (rep[2] + 3)) | (zero << 16);
+                        for (int m = 0; m < 8; ++m) {
+                            if (m & ~pair) continue;
+                            int k[3];
+                            for (int d = 0; d < 3; ++d) k[d] = (m & (4 >> d)) ? -rep[d] : rep[d];
+                            const int slot = vslot_of(o, k[0], k[1], k[2]);
+                            if (slot < 0) throw std::logic_error("sign class member outside the V slots");
+                            B.smem[(o * kSymClasses + c) * 8 + m] = slot;
+                        }
+                        ++c;
+                    }
+        if (c != kSymClasses) throw std::logic_error("sign class count");
+    }
 
     // P2M: moments -> Mhat, table[g][a] = w_|a| C[a][g]
     std::vector<ld> C = p2m_polys(m);
@@ -371,7 +435,7 @@ const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::s
     Entry e;
     OrderTables &t = e.host;
     t.p = p; t.nc = ncoef(p); t.nh = nharm(p); t.ldm = pad16(t.nc); t.ldh = pad16(t.nh);
-    t.ldd = B.ldd; t.ldc = B.ldc; t.d3 = dlayout_s1(p);
+    t.ldd = B.ldd; t.ldc = B.ldc; t.d3 = dlayout_s1(p); t.ldmh = folded_ld(p);
     if (upload(B.D, &t.D, err) || upload(B.Df, &t.Df, err) || upload(B.dmap, &t.dmap, err) ||
         upload(B.offs, &t.offs, err) ||
         upload(B.hoff, &t.hoff, err) || upload(B.S, &t.S, err) || upload(B.G, &t.G, err) ||
@@ -379,7 +443,9 @@ const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::s
         upload(B.fold_idx, &t.fold_idx, err) || upload(B.fold_c, &t.fold_c, err) ||
         upload(B.unfold_off, &t.unfold_off, err) || upload(B.unfold_idx, &t.unfold_idx, err) ||
         upload(B.unfold_c, &t.unfold_c, err) || upload(B.inv_fact, &t.inv_fact, err) ||
-        upload(B.inv_w, &t.inv_w, err) || upload(B.exps, &t.exps, err))
+        upload(B.inv_w, &t.inv_w, err) || upload(B.exps, &t.exps, err) || upload(B.mpos, &t.mpos, err) || upload(B.mposf, &t.mposf, err) ||
+        upload(B.srow, &t.srow, err) || upload(B.scol, &t.scol, err) || upload(B.srep, &t.srep, err) ||
+        upload(B.smem, &t.smem, err))
         return nullptr;
     void *d = nullptr;
     if (hipMalloc(&d, sizeof(OrderTables)) != hipSuccess ||
