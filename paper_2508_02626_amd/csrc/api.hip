@@ -734,10 +734,10 @@ StagePlan stage_blocks(const fmm_plan_s *P)
     StagePlan sp;
     sp.permute = (int)ceil_div(P->n, 256);
     sp.p2m = P->nleaves;
-    sp.fold = (int)ceil_div(P->nboxes + 1, 4); // and the zero row
+    sp.fold = (int)ceil_div(P->nboxes + 1, kRemapBoxes); // and the zero row
     sp.m2l = P->nslots / kM2LSlots;
     sp.p2l = P->nxtgt;
-    sp.unfold = (int)ceil_div(P->nboxes, 4);
+    sp.unfold = (int)ceil_div(P->nboxes, kRemapBoxes);
     sp.far = P->nleaves;
     const int split = p2p_split(P->nleaves);
     sp.p2p[0] = (int)ceil_div(split, 4);
@@ -868,7 +868,9 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
                        sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldm / 16); }), l, s);
     T.end();
     T.begin(3);
-    launch_fold(V, make([](const fmm_plan_s *p) { return stage_blocks(p).fold; }, all), s);
+    for (auto &r : runs)
+        launch_fold(P[r.first]->p, V + r.first,
+                    sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).fold; }), s);
     T.end();
     HIPCHK(hipStreamWaitEvent(s, F->ev_join, 0)); // first part of P2P done
     T.begin(4);
@@ -889,7 +891,9 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
             return (int)ceil_div(p->nxtgt, 16) * (p->ldh / 16); }), s);
     T.end();
     T.begin(6);
-    launch_unfold(V, make([](const fmm_plan_s *p) { return stage_blocks(p).unfold; }, all), s);
+    for (auto &r : runs)
+        launch_unfold(P[r.first]->p, V + r.first,
+                      sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).unfold; }), s);
     T.end();
     T.begin(7);
     for (auto &r : runs)

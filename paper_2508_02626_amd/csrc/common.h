@@ -25,8 +25,8 @@ constexpr int kMaxDepth = 21;
 constexpr int kVSlots = 189;   // M2L sources per box, one slot per offset (Sec. 3.4)
 constexpr int kMaxBatch = 256; // plans per batched launch
 
-__host__ __device__ inline int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
-__host__ __device__ inline int nharm(int p) { return (p + 1) * (p + 1); }
+__host__ __device__ constexpr int ncoef(int p) { return (p + 1) * (p + 2) * (p + 3) / 6; }
+__host__ __device__ constexpr int nharm(int p) { return (p + 1) * (p + 1); }
 __host__ __device__ inline int below(int n) { return n * (n + 1) * (n + 2) / 6; }
 // position of d1^i d2^j d3^k in the DA order of Table 1
 __host__ __device__ inline int mono_index(int i, int j, int k)
@@ -41,8 +41,23 @@ __host__ __device__ inline int harm_index(int i, int j, int kz)
     int n = i + j + kz;
     return n * n + (kz == 0 ? (n - i) : (n + 1) + (n - 1 - i));
 }
-inline int pad16(int n) { return (n + 15) & ~15; }
-inline int pad4(int n) { return (n + 3) & ~3; }
+__host__ __device__ constexpr int pad16(int n) { return (n + 15) & ~15; }
+__host__ __device__ constexpr int pad4(int n) { return (n + 3) & ~3; }
+// terms of the fold (and of the unfold): harmonic (I, J, kz) collects the full
+// components (I - 2a, J - 2(m - a), kz + 2m)
+__host__ __device__ constexpr int fold_terms(int p)
+{
+    int t = 0;
+    for (int n = 0; n <= p; ++n)
+        for (int kz = 0; kz <= 1 && kz <= n; ++kz)
+            for (int i = n - kz; i >= 0; --i) {
+                const int j = n - kz - i;
+                for (int m = 0; kz + 2 * m <= p; ++m)
+                    for (int a = 0; a <= m; ++a)
+                        if (i - 2 * a >= 0 && j - 2 * (m - a) >= 0) ++t;
+            }
+    return t;
+}
 // Additive layout of one offset's derivative table: addr(i,j,k) = k*s2 + i*s1 + j
 // for x, y exponents up to 2p and z exponent up to 2 (any s1 > 2p and
 // s2 > 2p (s1 + 1) keep it one-to-one).  The strides are chosen per order to

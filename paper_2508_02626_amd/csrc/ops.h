@@ -7,10 +7,10 @@ namespace fmm {
 void launch_permute_q(const PlanView *V, const Bases &B, hipStream_t s);   // 256 particles/block
 void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block
 void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 leaves x 16 rows/block
-void launch_fold(const PlanView *V, const Bases &B, hipStream_t s);        // 4 boxes/block
+void launch_fold(int p, const PlanView *V, const Bases &B, hipStream_t s); // kRemapBoxes boxes/block
 void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block
 void launch_l2l(const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block
-void launch_unfold(const PlanView *V, const Bases &B, hipStream_t s);      // 4 boxes/block
+void launch_unfold(int p, const PlanView *V, const Bases &B, hipStream_t s); // kRemapBoxes boxes/block
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 X target/block
 void launch_p2l_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 X targets x 16 rows/block
 void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block
@@ -21,4 +21,5 @@ void launch_p2p(int mixed, int part, const PlanView *V, const Bases &B, hipStrea
 void launch_zero(double *p, int64_t n, hipStream_t s);
 void launch_m2l(int p, int f32, const PlanView *V, const Bases &B, hipStream_t s); // 64 slots/block
 constexpr int kM2LSlots = 64;
+constexpr int kRemapBoxes = 16; // boxes per block of the fold and unfold
 } // namespace fmm

@@ -132,24 +132,44 @@ __global__ __launch_bounds__(64) void k_p2m_transform(const PlanView *V, Bases B
 }
 
 // ---------------- fold Mhat onto the harmonic components used by M2L ----------------
+// A block folds 16 boxes (4 per wavefront): the term tables sit in LDS, each
+// box's row of Mhat is staged in LDS by one coalesced load, and every lane
+// gathers its outputs from there.  Row nboxes is the zero row (the operand
+// of absent M2L sources).
+template <int P>
 __global__ __launch_bounds__(256) void k_fold(const PlanView *V, Bases B)
 {
-    int k = find_plan(B, blockIdx.x);
+    constexpr int NH = nharm(P), NT = fold_terms(P), LDM = pad16(ncoef(P)), LDMH = folded_ld(P);
+    __shared__ int sOff[NH + 1], sIdx[NT], sPos[LDMH], sPosf[LDMH];
+    __shared__ double sC[NT];
+    __shared__ double sRow[4][LDM];
+    const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
-    int box = (blockIdx.x - B.b[k]) * 4 + (threadIdx.x >> 6);
-    if (box > v.nboxes) return;
     const OrderTables &t = *v.tab;
-    const double *M = v.M + (int64_t)box * v.ldm;
-    // row nboxes is the zero row (the operand of absent M2L sources)
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int e = tid; e < NT; e += 256) { sIdx[e] = gptr(t.fold_idx)[e]; sC[e] = gptr(t.fold_c)[e]; }
+    for (int e = tid; e <= NH; e += 256) sOff[e] = gptr(t.fold_off)[e];
+    for (int e = tid; e < LDMH; e += 256) { sPos[e] = gptr(t.mpos)[e]; sPosf[e] = gptr(t.mposf)[e]; }
+    __syncthreads();
+    const bool mixed = v.mixed_m2l;
     auto fold = [&](int h) {
         double s = 0.0;
-        if (h >= 0 && box < v.nboxes)
-            for (int e = t.fold_off[h]; e < t.fold_off[h + 1]; ++e) s += t.fold_c[e] * M[t.fold_idx[e]];
+        if (h >= 0)
+            for (int e = sOff[h]; e < sOff[h + 1]; ++e) s += sC[e] * sRow[w][sIdx[e]];
         return s;
     };
-    for (int c = threadIdx.x & 63; c < v.ldmh; c += 64) { // c: folded position
-        v.Mh[(int64_t)box * v.ldmh + c] = fold(t.mpos[c]);
-        if (v.mixed_m2l) v.Mhf[(int64_t)box * v.ldmh + c] = (float)fold(t.mposf[c]);
+    const int first = (blockIdx.x - B.b[k]) * kRemapBoxes + 4 * w;
+    for (int i = 0; i < 4; ++i) {
+        const int box = first + i;
+        if (box > v.nboxes) break;
+        const auto M = gptr(v.M + (int64_t)box * LDM);
+        for (int a = lane; a < LDM; a += 64) sRow[w][a] = box < v.nboxes ? M[a] : 0.0;
+        wave_sync();
+        for (int c = lane; c < LDMH; c += 64) {
+            gptr(v.Mh)[(int64_t)box * LDMH + c] = fold(sPos[c]);
+            if (mixed) gptr(v.Mhf)[(int64_t)box * LDMH + c] = (float)fold(sPosf[c]);
+        }
+        wave_sync();
     }
 }
 
@@ -227,22 +247,44 @@ __global__ __launch_bounds__(512) void k_translate(const PlanView *V, Bases B, i
 }
 
 // ---------------- unfold the M2L result to full local expansions ----------------
+// Same layout as the fold: 16 boxes per block, tables and the box's Lhat row
+// in LDS.
+template <int P>
 __global__ __launch_bounds__(256) void k_unfold(const PlanView *V, Bases B)
 {
-    int k = find_plan(B, blockIdx.x);
+    constexpr int NC = ncoef(P), NT = fold_terms(P), LDM = pad16(NC), LDH = pad16(nharm(P));
+    __shared__ int sOff[NC + 1], sIdx[NT];
+    __shared__ double sC[NT];
+    __shared__ double sRow[4][LDH];
+    const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
-    int box = (blockIdx.x - B.b[k]) * 4 + (threadIdx.x >> 6);
-    if (box >= v.nboxes) return;
     const OrderTables &t = *v.tab;
-    const double *Lh = v.Lh + (int64_t)box * v.ldh;
-    // rows of Lh exist only for boxes that received M2L or P2L contributions
-    bool on = v.level[box] >= 2 &&
-              (v.V_off[box + 1] > v.V_off[box] || v.X_off[box + 1] > v.X_off[box]);
-    for (int b = threadIdx.x & 63; b < v.ldm; b += 64) {
-        double s = 0.0;
-        if (on && b < v.nc)
-            for (int e = t.unfold_off[b]; e < t.unfold_off[b + 1]; ++e) s += t.unfold_c[e] * Lh[t.unfold_idx[e]];
-        v.L[(int64_t)box * v.ldm + b] = s;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (int e = tid; e < NT; e += 256) { sIdx[e] = gptr(t.unfold_idx)[e]; sC[e] = gptr(t.unfold_c)[e]; }
+    for (int e = tid; e <= NC; e += 256) sOff[e] = gptr(t.unfold_off)[e];
+    __syncthreads();
+    const int first = (blockIdx.x - B.b[k]) * kRemapBoxes + 4 * w;
+    for (int i = 0; i < 4; ++i) {
+        const int box = first + i;
+        if (box >= v.nboxes) break;
+        // rows of Lh exist only for boxes that received M2L or P2L contributions
+        const bool on = v.level[box] >= 2 &&
+                        (v.V_off[box + 1] > v.V_off[box] || v.X_off[box + 1] > v.X_off[box]);
+        double *L = v.L + (int64_t)box * LDM;
+        if (!on) {
+            for (int b = lane; b < LDM; b += 64) gptr(L)[b] = 0.0;
+            continue;
+        }
+        const auto Lh = gptr(v.Lh + (int64_t)box * LDH);
+        for (int a = lane; a < LDH; a += 64) sRow[w][a] = Lh[a];
+        wave_sync();
+        for (int b = lane; b < LDM; b += 64) {
+            double s = 0.0;
+            if (b < NC)
+                for (int e = sOff[b]; e < sOff[b + 1]; ++e) s += sC[e] * sRow[w][sIdx[e]];
+            gptr(L)[b] = s;
+        }
+        wave_sync();
     }
 }
 
@@ -674,9 +716,9 @@ void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (nblk(B)) k_p2m_transform<<<nblk(B), 64, 0, s>>>(V, B);
 }
-void launch_fold(const PlanView *V, const Bases &B, hipStream_t s)
+void launch_fold(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {
-    if (nblk(B)) k_fold<<<nblk(B), 256, 0, s>>>(V, B);
+    if (nblk(B)) DISPATCH_P(p, k_fold, <<<nblk(B), 256, 0, s>>>(V, B));
 }
 void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s)
 {
@@ -685,10 +727,9 @@ void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s)
 void launch_l2l(const PlanView *V, const Bases &B, int level, hipStream_t s)
 {
     if (nblk(B)) k_translate<0><<<nblk(B), 512, 0, s>>>(V, B, level);
-}
-void launch_unfold(const PlanView *V, const Bases &B, hipStream_t s)
+}void launch_unfold(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {
-    if (nblk(B)) k_unfold<<<nblk(B), 256, 0, s>>>(V, B);
+    if (nblk(B)) DISPATCH_P(p, k_unfold, <<<nblk(B), 256, 0, s>>>(V, B));
 }
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {

@@ -382,6 +382,7 @@ void build_tables(int p, Built &B)
             }
     }
     B.fold_off[ldh] = (int)B.fold_idx.size();
+    if ((int)B.fold_idx.size() != fold_terms(p)) throw std::logic_error("fold term count");
     // unfold: full b = (i,j,k) <- harmonic (i+2a, j+2(m-a), k mod 2), m = k/2
     B.unfold_off.assign(nc + 1, 0);
     for (int be = 0; be < nc; ++be) {
@@ -393,6 +394,7 @@ void build_tables(int p, Built &B)
         }
     }
     B.unfold_off[nc] = (int)B.unfold_idx.size();
+    if ((int)B.unfold_idx.size() != fold_terms(p)) throw std::logic_error("unfold term count");
 }
 
 struct Entry {
