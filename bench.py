@@ -10,9 +10,12 @@ by fmm_evaluate (P2M, M2M, M2L, P2L, L2L, L2P/M2P, P2P, output).  The step is
 timed for the plain FP64 path (reported as `value`) and for the mixed path
 (FP32 P2P with FP64 accumulation, FP32-MFMA M2L), reported beside it.
 
-The roofline entry is for the dominant kernel, M2L: its algorithmic work is
-2 (p+1)^4 flops per V-list pair (the harmonic contraction), measured with HIP
-events on the evaluation stream over the timed steps.  The CPU baseline times
+The roofline entry is for the dominant kernel, M2L on sign classes: its
+algorithmic work is, per target and per sign class of its V list with a
+member, the contraction over parity-compatible (row, column) classes plus the
+butterflies that combine the members (m2l_work); time from HIP events on the
+evaluation stream over the timed steps.  The dense harmonic count, 2 (p+1)^4
+flops per V-list pair, is reported beside it.  The CPU baseline times
 the plain oracle on the same workload once (a few seconds on the host cores).
 
 Other workloads (--workload): plummer4m (4e6 Plummer points, adaptive s=64,
@@ -38,12 +41,14 @@ METRIC = "particles/s at 1e-7 rel. err (plain FP64 vs mixed); p50/p99 solve late
 N_DEFAULT, DEPTH, ORDER, SEED = 1_000_000, 5, 8, 1
 FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS = 78.6, 157.3
 
-# HBM bytes per launch of k_m2l<8,double> on this workload, from rocprofv3
+# HBM bytes per launch of k_m2l_sym<8,double> on this workload, from rocprofv3
 # FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration (read x2.0,
 # write x1.0; profiles/uniform1m_hbm_traffic.txt).  Valid only for the kernel
-# sources it was measured on: a different fingerprint reports null.
+# sources it was measured on (kernel, shared header, tile order): a different
+# fingerprint reports null.
 M2L_TRAFFIC = {"fingerprint": "398da7ea6d3c6576", "bytes": (3643.99 + 25.16) * 1e6}
-M2L_SOURCES = ("paper_2508_02626_amd/csrc/m2l.hip", "paper_2508_02626_amd/csrc/common.h")
+M2L_SOURCES = ("paper_2508_02626_amd/csrc/m2l.hip", "paper_2508_02626_amd/csrc/common.h",
+               "paper_2508_02626_amd/csrc/tree_kernels.hip")
 
 
 def m2l_traffic():
@@ -90,10 +95,60 @@ def run_mode(x, q, precision, steps, warmup, n):
     eval_s = (time.perf_counter() - t0) / steps
     stages = pl.read_timing()
     sizes = pl.sizes()
-    sizes["p2p_pairs"] = p2p_pairs(pl.export_tree())
+    tree = pl.export_tree()
+    sizes["p2p_pairs"] = p2p_pairs(tree)
+    m2l_flops = m2l_work(tree, ORDER)[0]
     pl.close()
-    return dict(step_s=step_s, eval_s=eval_s, stages=stages, sizes=sizes,
+    return dict(step_s=step_s, eval_s=eval_s, stages=stages, sizes=sizes, m2l_flops=m2l_flops,
                 phi=phi.cpu().numpy(), fld=fld.cpu().numpy())
+
+
+def sym_class_counts(p):
+    """Harmonic components (i, j, kz), kz in {0, 1}, |.| <= p, per parity class
+    c = (i % 2) << 2 | (j % 2) << 1 | kz."""
+    n = [0] * 8
+    for d in range(p + 1):
+        for kz in (0, 1):
+            for i in range(d - kz + 1) if d - kz >= 0 else []:
+                j = d - kz - i
+                n[(i & 1) << 2 | (j & 1) << 1 | kz] += 1
+    return n
+
+
+def m2l_work(t, p):
+    """Algorithmic flops of one M2L launch on sign classes.  For every target
+    and every sign class (|k_x|, |k_y|, |k_z|) of its V list that has a
+    member: 2 sum n_pi n_tau over row / column parity classes compatible on
+    the zero axes of the class (the contraction with the representative's
+    derivative table), plus the butterflies combining the members
+    (|P| 2^|P| additions per column, P the axes with a +- pair).  Also returns
+    the V pairs, for the dense harmonic count 2 (p+1)^4 per pair."""
+    vo, vs = t["V_off"].astype(np.int64), t["V_src"].astype(np.int64)
+    nv = len(vs)
+    if nv == 0:
+        return 0.0, 0
+    tg = np.repeat(np.arange(len(vo) - 1), np.diff(vo))
+    lev, code = t["level"].astype(np.int64), t["morton"].astype(np.uint64)
+
+    def coords(b):
+        c = np.zeros((len(b), 3), np.int64)
+        cb, lb = code[b], lev[b]
+        for bit in range(int(lev.max())):
+            on = bit < lb
+            for d in range(3):
+                c[:, d] |= np.where(on, ((cb >> np.uint64(3 * bit + 2 - d)) & np.uint64(1)).astype(np.int64), 0) << bit
+        return c
+
+    k = np.abs(coords(tg) - coords(vs))
+    cls = np.unique(tg * 64 + k[:, 0] * 16 + k[:, 1] * 4 + k[:, 2]) % 64
+    a = np.stack([cls // 16, (cls // 4) % 4, cls % 4], 1)
+    zero = ((a == 0) * np.array([4, 2, 1])).sum(1)
+    pair = ((a == 1) | (a == 2)).sum(1)
+    n = sym_class_counts(p)
+    nh = (p + 1) ** 2
+    macs = {z: sum(n[x] * n[y] for x in range(8) for y in range(8) if not ((x ^ y) & z)) for z in range(8)}
+    flops = sum(2.0 * macs[int(z)] for z in zero) + float((pair * (2 ** pair) * nh).sum())
+    return flops, nv
 
 
 def p2p_pairs(t):
@@ -192,7 +247,9 @@ def bench_plummer(args):
         eval_s = (time.perf_counter() - t0) / args.steps
         st, sizes = pl.read_timing(), pl.sizes()
         if mode == "fp64":
-            sizes["p2p_pairs"] = p2p_pairs(pl.export_tree())
+            tree = pl.export_tree()
+            sizes["p2p_pairs"] = p2p_pairs(tree)
+            sizes["m2l_flops"] = m2l_work(tree, p)[0]
         pl.close()
         ph, fh = phi.cpu().numpy(), fld.cpu().numpy()
         sp, sf, nt = sampled_sigma(xh, qh, ph, fh, count=1000)
@@ -219,7 +276,8 @@ def bench_plummer(args):
         hi[mode] = {"value": n / step_s, "ms_per_step": 1e3 * step_s, "sigma_phi_vs_direct": sp,
                     "sigma_field_vs_direct": sf}
     f, m = res["fp64"], res["mixed"]
-    flops = 2.0 * (p + 1) ** 4 * f["sizes"]["V"]
+    flops = f["sizes"]["m2l_flops"]
+    dense = 2.0 * (p + 1) ** 4 * f["sizes"]["V"]
     m2l_ms = f["stages"]["m2l"]
     out = base_record(args)
     out.update({
@@ -231,10 +289,13 @@ def bench_plummer(args):
                      "targets_sampled": 1000},
         "eval_only": {"value": n / f["eval_s"], "ms": 1e3 * f["eval_s"]},
         "stage_ms": f["stages"],
-        "roofline": {"kernel": "k_m2l<10,double>", "bound": "mfma", "achieved": flops / (m2l_ms * 1e-3) / 1e12,
+        "roofline": {"kernel": "k_m2l_sym<10,double>", "bound": "mfma", "achieved": flops / (m2l_ms * 1e-3) / 1e12,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": flops / (m2l_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
-                     "flops_per_launch": flops, "ms_per_launch": m2l_ms},
+                     "flops_per_launch": flops, "ms_per_launch": m2l_ms,
+                     "work": "sign-class contraction (unpadded) + member butterflies",
+                     "dense_harmonic_flops_per_launch": dense,
+                     "dense_equivalent_tflops": dense / (m2l_ms * 1e-3) / 1e12},
         "p2p": {"kernel": "k_p2p<0>", "pairs_per_launch": f["sizes"]["p2p_pairs"],
                 "pairs_per_s": f["sizes"]["p2p_pairs"] / (1e-3 * f["stages"]["p2p"]),
                 "achieved": P2P_FLOPS_PER_PAIR * f["sizes"]["p2p_pairs"] / (1e-3 * f["stages"]["p2p"]) / 1e12,
@@ -496,7 +557,8 @@ def main():
     f = res["fp64"]
     nv = f["sizes"]["V"]
     m2l_ms = f["stages"]["m2l"][0] / max(f["stages"]["m2l"][1], 1)
-    flops = 2.0 * (ORDER + 1) ** 4 * nv
+    flops = f["m2l_flops"]
+    dense = 2.0 * (ORDER + 1) ** 4 * nv
     achieved = flops / (m2l_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -518,10 +580,13 @@ def main():
                      "targets_sampled": f["sigma_targets"]},
         "eval_only": {"value": n / f["eval_s"], "ms": 1e3 * f["eval_s"]},
         "stage_ms": stage_avg(f["stages"]),
-        "roofline": {"kernel": "k_m2l<8,double>", "bound": "mfma", "achieved": achieved,
+        "roofline": {"kernel": "k_m2l_sym<8,double>", "bound": "mfma", "achieved": achieved,
                      "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                      "traffic": m2l_traffic(), "traffic_unit": "bytes per launch",
-                     "flops_per_launch": flops, "ms_per_launch": m2l_ms},
+                     "flops_per_launch": flops, "ms_per_launch": m2l_ms,
+                     "work": "sign-class contraction (unpadded) + member butterflies",
+                     "dense_harmonic_flops_per_launch": dense,
+                     "dense_equivalent_tflops": dense / (m2l_ms * 1e-3) / 1e12},
         "p2p": p2p_roofline(f),
     }
     if "mixed" in res:
@@ -534,6 +599,7 @@ def main():
                         "sigma_phi_vs_direct": m["sigma_phi"], "sigma_field_vs_direct": m["sigma_field"],
                         "dtype": "f64 with f32 P2P terms and f32 MFMA M2L",
                         "stage_ms": stage_avg(m["stages"]),
+                        "m2l_kernel": "k_m2l_sym<8,float>", "m2l_ms": mm,
                         "m2l_tflops": flops / (mm * 1e-3) / 1e12, "m2l_peak_fp32": FP32_PEAK_TFLOPS,
                         "p2p_pairs_per_s": m["sizes"]["p2p_pairs"] / (1e-3 * stage_avg(m["stages"])["p2p"])}
     if not args.no_cpu_baseline:

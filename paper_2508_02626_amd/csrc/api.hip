@@ -546,7 +546,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         while ((1LL << bits) < nb) ++bits;
         radix_sort_pairs(wk, P->src[3], wk2, wv2, (int)mw, bits, wscr, s);
     }
-    int *octoff = P->temp<int>(32);
+    int *octoff = P->temp<int>(128);
     uint64_t *okey = P->temp<uint64_t>(nt + 1), *otk = P->temp<uint64_t>(nt + 1);
     int32_t *oval = P->temp<int32_t>(nt + 1), *otv = P->temp<int32_t>(nt + 1);
     int32_t *oscr = P->temp<int32_t>(sort_scratch_bytes(nt + 1) / 4 + 1);

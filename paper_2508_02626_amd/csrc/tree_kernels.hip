@@ -710,7 +710,11 @@ void compact(const int64_t *flag, const int64_t *pos, int nboxes, int32_t *out, 
 // box actually has depend only on its octant and on its distance (0, 1, 2 or
 // more cells) to each face of the root, so there the targets are also grouped
 // by these distances (Morton order inside a group): the blocks near the faces
-// then skip the offsets none of their targets has.
+// then skip the offsets none of their targets has.  The tiles are then laid
+// out region by region: the x-th eighth of every octant's tiles (a spatial
+// region, as the tiles follow Morton order) forms the x-th eighth of the
+// sequence, which the M2L launch hands to XCD x, so each XCD's L2 holds the
+// multipoles of one region instead of those of the whole domain.
 constexpr int kCatBits = 12;
 
 __global__ __launch_bounds__(256) void k_oct_keys(const BoxArrays bx, const int32_t *tg, int nt, int uniform,
@@ -752,10 +756,19 @@ __global__ void k_oct_offsets(const uint64_t *key, int nt, int *octoff)
         for (int k = 0; k < 8; ++k) {
             octoff[k] = s;              // padded start
             octoff[9 + k] = st[k];      // unpadded start
+            octoff[96 + k] = (st[k + 1] - st[k] + 63) / 64; // tiles of the octant
             s += (st[k + 1] - st[k] + 63) & ~63;
         }
         octoff[8] = s;
         octoff[17] = nt;
+        // first tile of (region x, octant k) in the region-major sequence
+        int t = 0;
+        for (int x = 0; x < 8; ++x)
+            for (int k = 0; k < 8; ++k) {
+                const int T = octoff[96 + k];
+                octoff[32 + 8 * x + k] = t;
+                t += (x + 1) * T / 8 - x * T / 8;
+            }
     }
 }
 
@@ -764,8 +777,11 @@ __global__ __launch_bounds__(256) void k_oct_place(const uint64_t *key, const in
 {
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= nt) return;
-    int o = (int)(key[i] >> kCatBits);
-    slots[octoff[o] + (i - octoff[9 + o])] = val[i];
+    const int o = (int)(key[i] >> kCatBits), j = i - octoff[9 + o], t = j >> 6, T = octoff[96 + o];
+    int x = 0;
+    while (x < 7 && t >= (x + 1) * T / 8) ++x;
+    const int tile = octoff[32 + 8 * x + o] + (t - x * T / 8);
+    slots[(int64_t)tile * 64 + (j & 63)] = val[i];
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
