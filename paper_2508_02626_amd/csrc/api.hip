@@ -428,6 +428,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
          .add<int32_t>(kMaxDepth + 2).add<PlanView>(1)
          .add<double>((size_t)nb * P->ldm).add<double>((size_t)nb * P->ldm)
          .add<double>((size_t)(nb + 1) * P->ldmh).add<double>((size_t)nb * P->ldh);
+        if (m2l_sym(P->p)) o.add<double>((size_t)nb * P->ldh);
         if (P->mixed_m2l) o.add<float>((size_t)(nb + 1) * P->ldmh);
         if (!P->reserve(true, o.total)) return fail(FMM_ENOMEM, "device allocation failed (boxes)");
         Sizer t;
@@ -457,6 +458,8 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     // folded multipoles: one row per box and an all-zero row after them
     double *Mh = P->own<double>((size_t)(nb + 1) * P->ldmh), *Lh = P->own<double>((size_t)nb * P->ldh);
     float *Mhf = P->mixed_m2l ? P->own<float>((size_t)(nb + 1) * P->ldmh) : nullptr;
+    double *Lh2 = m2l_sym(P->p) ? P->own<double>((size_t)nb * P->ldh) : nullptr;
+    if (m2l_sym(P->p)) NOMEM(Lh2);
     NOMEM(vslot); NOMEM(leaves); NOMEM(nonleaf); NOMEM(xtgt); NOMEM(lnl_off); NOMEM(P->view_dev);
     NOMEM(M); NOMEM(L); NOMEM(Mh); NOMEM(Lh);
     if (P->mixed_m2l) NOMEM(Mhf);
@@ -567,7 +570,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     v.U_src = P->src[0]; v.W_src = P->src[2]; v.X_src = P->src[3];
     v.m2l_tgt = slots; v.vslot = vslot; v.leaves = leaves; v.xtgt = xtgt;
     v.lvl_nonleaf = nonleaf; v.lvl_nonleaf_off = lnl_off; v.tab = P->tab;
-    v.qs = qs; v.M = M; v.Mh = Mh; v.Lh = Lh; v.L = L; v.Mhf = Mhf; v.phi_near = pf; v.fld_near = ff;
+    v.qs = qs; v.M = M; v.Mh = Mh; v.Lh = Lh; v.Lh2 = Lh2; v.L = L; v.Mhf = Mhf; v.phi_near = pf; v.fld_near = ff;
     HIPCHK(hipMemcpyAsync(P->view_dev, &v, sizeof(PlanView), hipMemcpyHostToDevice, s));
     HIPCHK(hipGetLastError());
     P->release_temps();
@@ -735,7 +738,7 @@ StagePlan stage_blocks(const fmm_plan_s *P)
     sp.permute = (int)ceil_div(P->n, 256);
     sp.p2m = P->nleaves;
     sp.fold = (int)ceil_div(P->nboxes + 1, kRemapBoxes); // and the zero row
-    sp.m2l = P->nslots / kM2LSlots;
+    sp.m2l = P->nslots / kM2LSlots * (m2l_sym(P->p) ? 2 : 1); // sign classes: two blocks per tile
     sp.p2l = P->nxtgt;
     sp.unfold = (int)ceil_div(P->nboxes, kRemapBoxes);
     sp.far = P->nleaves;
@@ -996,7 +999,7 @@ extern "C" int fmm_plan_estimate(int64_t n, int32_t order, int32_t leaf_size, co
         boxes = 1 + 8.0 * 2.0 * n / (leaf_size + 1);
     }
     double ldm = pad16(ncoef(order)), ldh = pad16(nharm(order)), ldmh = folded_ld(order);
-    double per_box = 8 * (2 * ldm + ldh + ldmh) + 4 * ldmh + 4 * 200 + 64; // expansions, slots, lists
+    double per_box = 8 * (2 * ldm + (m2l_sym(order) ? 2 : 1) * ldh + ldmh) + 4 * ldmh + 4 * 200 + 64; // expansions, slots, lists
     double per_particle = 8 * 3 + 4 + 8 * 5 + 8 * 2;
     double total = boxes * per_box + n * per_particle + 8 * 27 * boxes;
     *bytes = (size_t)(total * 1.25);

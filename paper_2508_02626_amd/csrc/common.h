@@ -245,6 +245,7 @@ struct PlanView {
     // evaluation buffers
     double *qs;                         // sorted charges
     double *M, *Mh, *Lh, *L;            // [boxes][ldm] / [boxes][ldmh] / [boxes][ldh]
+    double *Lh2;                        // sign-class orders: second half of the M2L classes
     float *Mhf;                         // FP32 folded multipoles (mixed M2L)
     double *phi_near, *fld_near;        // near-field (P2P) part, sorted order
     // caller's arrays for this evaluation

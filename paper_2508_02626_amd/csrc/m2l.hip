@@ -340,8 +340,9 @@ __global__ __launch_bounds__(256 * m2l_row_split(P)) void k_m2l(const PlanView *
 // k has a zero component, D_g(k) vanishes for odd g on that axis, and the
 // row-tile / k-step pairs of opposite parity on it are skipped.  Each k-step
 // loads the members' operands (one component per lane and member, 8 loads,
-// always issued so that the waits count them) W steps ahead, across class
-// boundaries.
+// always issued so that the waits count them) two vectors ahead, across
+// class boundaries.  Two blocks share a tile, each running half of its
+// classes; the second writes its partial sums to Lh2, which the unfold adds.
 template <int P> struct SymShape {
     static constexpr int RT = sym_row_tiles(P), KS = sym_ksteps(P);
     int rc[RT], kc[KS]; // parity class of each row tile and k-step
@@ -398,7 +399,9 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
 
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
-    const int tile = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]);
+    // two blocks per tile, each taking half of the tile's classes (twice as
+    // many, shorter blocks: less idle time at the end of the launch)
+    const int rb = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]), tile = rb >> 1, half = rb & 1;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
     const int tgt = v.m2l_tgt[tile * kM2LSlots + wave * 16 + col];
     if (!__syncthreads_or(tgt >= 0)) return;
@@ -447,6 +450,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
     }
     __syncthreads();
     const int nvalid = sN;
+    const int qa = half ? (nvalid + 1) / 2 : 0, qb = half ? nvalid : (nvalid + 1) / 2; // this block's classes
     const int64_t ldmh = v.ldmh;
     const T *Dt = Mfma<T>::D(tb);
     const T *Mh = Mfma<T>::M(v);
@@ -542,21 +546,21 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
             }
         }
     };
-    if (nvalid > 0) {
-        load_d(sList[0]);
+    if (qb > qa) {
+        load_d(sList[qa]);
         store_d(0);
-        class_src(0, srcc);
+        class_src(qa, srcc);
         load_b(0, 0, srcc);
         if (KSV > 1) load_b(1, 1, srcc);
         __syncthreads();
     }
     // the classes of one zero mask follow each other: one loop per mask
-    int q = 0;
+    int q = qa;
     auto run_mask = [&](auto zc) {
-        const int qend = sZend[decltype(zc)::value];
+        const int qend = min(sZend[decltype(zc)::value], qb);
         for (; q < qend; ++q) {
-            const int cur = q & 1;
-            const bool more = q + 1 < nvalid;
+            const int cur = (q - qa) & 1;
+            const bool more = q + 1 < qb;
             if (more) {
                 load_d(sList[q + 1]);
                 class_src(q + 1, srcn);
@@ -584,7 +588,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
     run_mask(std::integral_constant<int, 5>{});
     run_mask(std::integral_constant<int, 6>{}); // at most two zero axes
     if (tgt < 0) return;
-    double *Lh = v.Lh + (int64_t)tgt * v.ldh;
+    double *Lh = (half ? v.Lh2 : v.Lh) + (int64_t)tgt * v.ldh;
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll

@@ -276,7 +276,12 @@ __global__ __launch_bounds__(256) void k_unfold(const PlanView *V, Bases B)
             continue;
         }
         const auto Lh = gptr(v.Lh + (int64_t)box * LDH);
-        for (int a = lane; a < LDH; a += 64) sRow[w][a] = Lh[a];
+        if (m2l_sym(P) && v.V_off[box + 1] > v.V_off[box]) { // M2L split over two halves of its classes
+            const auto Lh2 = gptr(v.Lh2 + (int64_t)box * LDH);
+            for (int a = lane; a < LDH; a += 64) sRow[w][a] = Lh[a] + Lh2[a];
+        } else {
+            for (int a = lane; a < LDH; a += 64) sRow[w][a] = Lh[a];
+        }
         wave_sync();
         for (int b = lane; b < LDM; b += 64) {
             double s = 0.0;
