@@ -46,7 +46,7 @@ FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS = 78.6, 157.3
 # write x1.0; profiles/uniform1m_hbm_traffic.txt).  Valid only for the kernel
 # sources it was measured on (kernel, shared header, tile order): a different
 # fingerprint reports null.
-M2L_TRAFFIC = {"fingerprint": "398da7ea6d3c6576", "bytes": (3643.99 + 25.16) * 1e6}
+M2L_TRAFFIC = {"fingerprint": "74481c87e4fb51e5", "bytes": (1177.68 + 66.04) * 1e6}
 M2L_SOURCES = ("paper_2508_02626_amd/csrc/m2l.hip", "paper_2508_02626_amd/csrc/common.h",
                "paper_2508_02626_amd/csrc/tree_kernels.hip")
 
@@ -494,9 +494,10 @@ def bench_sweep(args):
             ms.append(1e3 * timed(x, q, p, best[near][p]))
             del x, q
         ln, lt = np.log(scan), np.log(ms)
-        big = np.array(scan) >= 100_000
+        big, huge = np.array(scan) >= 100_000, np.array(scan) >= 1_000_000
         linear[p] = {"n": scan, "ms": ms, "slope": float(np.polyfit(ln, lt, 1)[0]),
-                     "slope_n_ge_1e5": float(np.polyfit(ln[big], lt[big], 1)[0])}
+                     "slope_n_ge_1e5": float(np.polyfit(ln[big], lt[big], 1)[0]),
+                     "slope_n_ge_1e6": float(np.polyfit(ln[huge], lt[huge], 1)[0])}
         log("bench sweep: p=%d slope %.3f (N>=1e5: %.3f)" % (p, linear[p]["slope"], linear[p]["slope_n_ge_1e5"]))
     n_top, p_top = sizes_n[-1], orders[-1]
     t_top = table[n_top][p_top][best[n_top][p_top]]
