@@ -105,16 +105,26 @@ __host__ __device__ constexpr int sym_row_tiles(int p)
     for (int c = 0; c < 8; ++c) n += (sym_class_count(p, c) + 15) / 16;
     return n;
 }
+// columns of a parity class are padded to a multiple of sym_colpad: 4 (one
+// k-step) up to p = 11; 8 from p = 12, where the kernel walks each class's
+// k-steps in a loop of 16-byte operand vectors (two k-steps) that must not
+// straddle classes
+__host__ __device__ constexpr int sym_colpad(int p) { return p >= 12 ? 8 : 4; }
+__host__ __device__ constexpr int sym_class_ksteps(int p, int c)
+{
+    return (sym_class_count(p, c) + sym_colpad(p) - 1) / sym_colpad(p) * (sym_colpad(p) / 4);
+}
 __host__ __device__ constexpr int sym_ksteps(int p)
 {
     int n = 0;
-    for (int c = 0; c < 8; ++c) n += (sym_class_count(p, c) + 3) / 4;
+    for (int c = 0; c < 8; ++c) n += sym_class_ksteps(p, c);
     return n;
 }
-// orders whose M2L runs on sign classes (fewer matrix-core products from p = 6
-// on; above p = 11 the accumulators of all row tiles no longer fit one
-// wavefront's registers and the slot-by-slot kernel is used)
-__host__ __device__ constexpr bool m2l_sym(int p) { return p >= 6 && p <= 11; }
+// orders whose M2L runs on sign classes (fewer matrix-core products from p = 6 on)
+__host__ __device__ constexpr bool m2l_sym(int p) { return p >= 6; }
+// launches the row tiles of an order >= 12 sign-class M2L are split over (at
+// most 9 row tiles of accumulators per wavefront)
+__host__ __device__ constexpr int sym_row_parts(int p) { return p >= 12 ? (sym_row_tiles(p) + 8) / 9 : 1; }
 // Folded multipoles of sign-class orders are stored so that a lane's
 // operands of vw consecutive k-steps are adjacent (one 16-byte load): sorted
 // column 4 ks + g (k-step ks, lane group g) sits at 4 vw (ks / vw) + vw g +
@@ -213,6 +223,7 @@ struct OrderTables {
     const int *scol;    // [4 k-steps] harmonic index of each sorted column (-1 padding)
     const int *srep;    // [8][56]
     const int *smem;    // [8][56][8]
+    const int *sslot;   // [8][189] class of each V slot
     const double *inv_fact;     // [nc] 1/b!
     const double *inv_w;        // [p+1] 1/w_n = (-1)^n (2n-1)!!
     const int *exps;            // [nc] packed exponents i | j<<8 | k<<16

@@ -346,14 +346,17 @@ __global__ __launch_bounds__(256 * m2l_row_split(P)) void k_m2l(const PlanView *
 template <int P> struct SymShape {
     static constexpr int RT = sym_row_tiles(P), KS = sym_ksteps(P);
     int rc[RT], kc[KS]; // parity class of each row tile and k-step
-    constexpr SymShape() : rc(), kc()
+    int kb[9];          // first k-step of each column class
+    constexpr SymShape() : rc(), kc(), kb()
     {
         int r = 0, k = 0;
         for (int c = 0; c < 8; ++c) {
             const int n = sym_class_count(P, c);
             for (int t = 0; t < (n + 15) / 16; ++t) rc[r++] = c;
-            for (int t = 0; t < (n + 3) / 4; ++t) kc[k++] = c;
+            kb[c] = k;
+            for (int t = 0; t < sym_class_ksteps(P, c); ++t) kc[k++] = c;
         }
+        kb[8] = k;
     }
 };
 
@@ -599,13 +602,240 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
     }
 }
 
+// ---------------- sign-class M2L for orders >= 12 ----------------
+// The same decomposition as k_m2l_sym (classes in zero-mask order, two blocks
+// per tile over halves of the classes, transform of the members, one MFMA per
+// row tile and k-step with a compile-time transform output), organised so
+// that the code stays small at high order: the row tiles are split over
+// sym_row_parts launches (at most 9 tiles of accumulators per wavefront), and
+// within a class the eight column classes are unrolled while each one's
+// k-steps run in a loop over 16-byte operand vectors (two k-steps; columns are
+// padded to 8 per class so that no vector straddles two classes).  Operands
+// move one vector ahead through a current / next register pair, the next
+// class's first vector loaded during the last one.  The targets' slot rows
+// are read from memory (the classes a block uses come from a 64-bit mask
+// built by all threads), which leaves LDS to the derivative tables.
+template <int P, int RH>
+__global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
+{
+    typedef double T;
+    static constexpr SymShape<P> S{};
+    constexpr int RT = SymShape<P>::RT, KS = SymShape<P>::KS;
+    constexpr int NRP = sym_row_parts(P), MTP = (RT + NRP - 1) / NRP, R0 = RH * MTP;
+    constexpr int MTW = RT - R0 < MTP ? RT - R0 : MTP; // row tiles [R0, R0 + MTW)
+    static_assert(RH < NRP && MTW >= 1 && MTW <= 9, "row part");
+    static_assert(KS % 2 == 0 && 8 * (KS / 2) <= folded_ld(P), "two-k-step vectors inside the folded row");
+    constexpr int KSV = KS / 2; // operand vectors per class
+    constexpr int NT = 256;
+    constexpr int LDD = dlayout_ldd(P), LDC = dlayout_ldc(P);
+    constexpr int DW = 2;
+    static_assert(LDC % DW == 0, "compact rows must be whole vectors");
+    constexpr int DV = (LDC / DW + NT - 1) / NT;
+    typedef typename Mfma<T>::acc_t acc_t;
+    typedef T vec_t __attribute__((ext_vector_type(2)));
+    __shared__ T sD[2][LDD];
+    __shared__ int sHo[4][KS];
+    __shared__ int sTg[64];
+    __shared__ int sList[kSymClasses];
+    __shared__ int sRep[kSymClasses];
+    __shared__ int sMem[kSymClasses][8];
+    __shared__ int sZend[8];
+    __shared__ unsigned long long sUsed;
+    __shared__ int sN, soct;
+
+    const int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int rb = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]), tile = rb >> 1, half = rb & 1;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
+    const int tgt = v.m2l_tgt[tile * kM2LSlots + wave * 16 + col];
+    if (!__syncthreads_or(tgt >= 0)) return;
+    if (tgt >= 0) soct = (int)(v.morton[tgt] & 7);
+    if (tid < 64) sTg[tid] = v.m2l_tgt[tile * kM2LSlots + tid];
+    if (tid == 0) sUsed = 0;
+    const OrderTables &tb = *v.tab;
+    for (int e = tid; e < 4 * KS; e += NT) {
+        const int g = e / KS, ks = e - g * KS, a = gptr(tb.scol)[4 * ks + g];
+        sHo[g][ks] = a >= 0 ? gptr(tb.hoff)[a] : 0;
+    }
+    int hb[MTW];
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) {
+        const int b = gptr(tb.srow)[16 * (R0 + mt) + col];
+        hb[mt] = b >= 0 ? gptr(tb.hoff)[b] : 0;
+    }
+    __syncthreads();
+    const auto vs = gptr(v.vslot);
+    {
+        for (int e = tid; e < kSymClasses * 8; e += NT)
+            sMem[e >> 3][e & 7] = gptr(tb.smem)[soct * kSymClasses * 8 + e];
+        if (tid < kSymClasses) sRep[tid] = gptr(tb.srep)[soct * kSymClasses + tid];
+        // classes used by the block: four threads scan each target's slots
+        const int g = sTg[tid >> 2];
+        unsigned long long used = 0;
+        if (g >= 0)
+            for (int j = tid & 3; j < kVSlots; j += 4)
+                if (vs[(int64_t)g * kVSlots + j] >= 0) used |= 1ull << gptr(tb.sslot)[soct * kVSlots + j];
+        if (used) atomicOr(&sUsed, used);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int n = 0;
+        const unsigned long long used = sUsed;
+        for (int c = 0; c < kSymClasses; ++c) {
+            if ((used >> c) & 1) sList[n++] = c;
+            sZend[sRep[c] >> 16] = n;
+        }
+        sN = n;
+    }
+    __syncthreads();
+    const int nvalid = sN;
+    const int qa = half ? (nvalid + 1) / 2 : 0, qb = half ? nvalid : (nvalid + 1) / 2;
+    const int64_t ldmh = v.ldmh;
+    const T *Dt = tb.D;
+    const T *Mh = v.Mh;
+
+    acc_t acc[MTW];
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) acc[mt] = acc_t{0, 0, 0, 0};
+
+    typedef T dvec_t __attribute__((ext_vector_type(2)));
+    dvec_t pd[DV];
+    int dm[DV][DW];
+#pragma unroll
+    for (int r = 0; r < DV; ++r)
+#pragma unroll
+        for (int w = 0; w < DW; ++w) {
+            const int e = (tid + NT * r) * DW + w;
+            dm[r][w] = e < LDC ? gptr(tb.dmap)[e] : LDD - 1;
+        }
+    auto load_d = [&](int c) {
+        const dvec_t *Dk = (const dvec_t *)(Dt + (int64_t)(sRep[c] & 0xffff) * LDC);
+#pragma unroll
+        for (int r = 0; r < DV; ++r) {
+            const int e = tid + NT * r;
+            pd[r] = e < LDC / DW ? gload(Dk + e) : dvec_t{};
+        }
+    };
+    auto store_d = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < DV; ++r)
+            if (tid + NT * r < LDC / DW)
+#pragma unroll
+                for (int w = 0; w < DW; ++w) sD[buf][dm[r][w]] = pd[r][w];
+    };
+    // member operand rows as 32-bit byte offsets (plans check the 4 GiB bound);
+    // absent members read the zero row after the boxes
+    const uint32_t zoff = (uint32_t)v.nboxes * (uint32_t)ldmh * 8u;
+    const uint32_t vrow = (uint32_t)(tgt >= 0 ? tgt : 0) * (uint32_t)kVSlots;
+    auto class_src = [&](int q, uint32_t (&src)[8]) {
+        const int c = sList[q];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const int j = sMem[c][m];
+            const int b = j >= 0 && tgt >= 0 ? vs[vrow + (uint32_t)j] : -1;
+            src[m] = (b >= 0 ? (uint32_t)b * (uint32_t)ldmh * 8u : zoff) + 16u * (uint32_t)kq;
+        }
+    };
+    const auto Mg = gptr((const char *)Mh);
+    auto load_v = [&](vec_t (&dst)[8], int j, const uint32_t (&src)[8]) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            uint32_t o = src[m];
+            asm volatile("" : "+v"(o));
+            dst[m] = *(gp<const vec_t>)(Mg + (uint64_t)o + 64 * j);
+        }
+    };
+    uint32_t srcc[8], srcn[8];
+    vec_t cur[8], nxt[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) srcc[m] = srcn[m] = zoff;
+    if (qb > qa) {
+        load_d(sList[qa]);
+        store_d(0);
+        class_src(qa, srcc);
+        load_v(cur, 0, srcc);
+        __syncthreads();
+    }
+    // one class: column classes unrolled, their vectors in a loop
+    auto run_class = [&](auto zc, const T *D) {
+        constexpr int Z = decltype(zc)::value;
+        const int *Ho = sHo[kq];
+        auto column_class = [&](auto tc) {
+            constexpr int TAU = decltype(tc)::value;
+#pragma unroll 1
+            for (int j = S.kb[TAU] / 2; j < S.kb[TAU + 1] / 2; ++j) {
+                if (j + 1 < KSV) load_v(nxt, j + 1, srcc);
+                else load_v(nxt, 0, srcn);
+#pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    const int ha = Ho[2 * j + w];
+                    T ac[MTW];
+#pragma unroll
+                    for (int mt = 0; mt < MTW; ++mt)
+                        if (!((S.rc[R0 + mt] ^ TAU) & Z)) ac[mt] = D[hb[mt] + ha];
+                    T h[8];
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) h[m] = cur[m][w];
+                    wht8(h);
+#pragma unroll
+                    for (int mt = 0; mt < MTW; ++mt)
+                        if (!((S.rc[R0 + mt] ^ TAU) & Z))
+                            acc[mt] = Mfma<T>::run(ac[mt], h[S.rc[R0 + mt] ^ TAU], acc[mt]);
+                }
+#pragma unroll
+                for (int m = 0; m < 8; ++m) cur[m] = nxt[m];
+            }
+        };
+        column_class(std::integral_constant<int, 0>{});
+        column_class(std::integral_constant<int, 1>{});
+        column_class(std::integral_constant<int, 2>{});
+        column_class(std::integral_constant<int, 3>{});
+        column_class(std::integral_constant<int, 4>{});
+        column_class(std::integral_constant<int, 5>{});
+        column_class(std::integral_constant<int, 6>{});
+        column_class(std::integral_constant<int, 7>{});
+    };
+    int q = qa;
+    auto run_mask = [&](auto zc) {
+        const int qend = min(sZend[decltype(zc)::value], qb);
+        for (; q < qend; ++q) {
+            const int curb = (q - qa) & 1;
+            const bool more = q + 1 < qb;
+            if (more) {
+                load_d(sList[q + 1]);
+                class_src(q + 1, srcn);
+            }
+            run_class(zc, sD[curb]);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) srcc[m] = srcn[m];
+            if (more) store_d(curb ^ 1);
+            __syncthreads();
+        }
+    };
+    run_mask(std::integral_constant<int, 0>{});
+    run_mask(std::integral_constant<int, 1>{});
+    run_mask(std::integral_constant<int, 2>{});
+    run_mask(std::integral_constant<int, 3>{});
+    run_mask(std::integral_constant<int, 4>{});
+    run_mask(std::integral_constant<int, 5>{});
+    run_mask(std::integral_constant<int, 6>{});
+    if (tgt < 0) return;
+    double *Lh = (half ? v.Lh2 : v.Lh) + (int64_t)tgt * v.ldh;
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int b = gptr(tb.srow)[16 * (R0 + mt) + Mfma<T>::row(lane, r)];
+            if (b >= 0) Lh[b] = acc[mt][r];
+        }
+    }
+}
+
 #define M2L_CASE(PP)                                                               \
     case PP:                                                                       \
         if (f32) k_m2l<PP, float><<<nb, 256, 0, s>>>(V, B);                        \
         else k_m2l<PP, double><<<nb, 256, 0, s>>>(V, B);                           \
         break;
-#define M2L_CASE64(PP)                                                             \
-    case PP: k_m2l<PP, double><<<nb, 256 * m2l_row_split(PP), 0, s>>>(V, B); break;
 
 // FP32 M2L exists for p <= 8 only (the mixed path keeps M2L in FP64 above)
 #define M2L_SYM(PP)                                                                \
@@ -616,18 +846,28 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
 #define M2L_SYM64(PP)                                                              \
     case PP: k_m2l_sym<PP, double><<<nb, 256, 0, s>>>(V, B); break;
 
+template <int P> void launch_symh(unsigned nb, const PlanView *V, const Bases &B, hipStream_t s)
+{
+    static_assert(sym_row_parts(P) <= 3, "row parts");
+    k_m2l_symh<P, 0><<<nb, 256, 0, s>>>(V, B);
+    if constexpr (sym_row_parts(P) > 1) k_m2l_symh<P, 1><<<nb, 256, 0, s>>>(V, B);
+    if constexpr (sym_row_parts(P) > 2) k_m2l_symh<P, 2><<<nb, 256, 0, s>>>(V, B);
+}
+#define M2L_SYMH(PP) \
+    case PP: launch_symh<PP>(nb, V, B, s); break;
+
 // FP32 M2L exists for p <= 8 only (the mixed path keeps M2L in FP64 above);
-// orders 6..11 run on sign classes (m2l_sym)
+// orders from 6 on run on sign classes (m2l_sym), from 12 on in k_m2l_symh
 void launch_m2l(int p, int f32, const PlanView *V, const Bases &B, hipStream_t s)
 {
     unsigned nb = (unsigned)B.b[B.n];
     if (!nb) return;
-    static_assert(m2l_sym(6) && m2l_sym(11) && !m2l_sym(5) && !m2l_sym(12), "dispatch below");
+    static_assert(m2l_sym(6) && !m2l_sym(5), "dispatch below");
     switch (p) {
         M2L_CASE(0) M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5)
         M2L_SYM(6) M2L_SYM(7) M2L_SYM(8) M2L_SYM64(9) M2L_SYM64(10) M2L_SYM64(11)
-        M2L_CASE64(12) M2L_CASE64(13) M2L_CASE64(14) M2L_CASE64(15)
-    default: k_m2l<16, double><<<nb, 256 * m2l_row_split(16), 0, s>>>(V, B);
+        M2L_SYMH(12) M2L_SYMH(13) M2L_SYMH(14) M2L_SYMH(15)
+    default: launch_symh<16>(nb, V, B, s);
     }
 }
 

@@ -165,7 +165,7 @@ struct Built {
     std::vector<double> D, S, G, P2M, P2L, fold_c, unfold_c, inv_fact, inv_w;
     std::vector<float> Df;
     std::vector<int> offs, hoff, fold_off, fold_idx, unfold_off, unfold_idx, exps, dmap;
-    std::vector<int> mpos, mposf, srow, scol, srep, smem;
+    std::vector<int> mpos, mposf, srow, scol, srep, smem, sslot;
     int ldd = 0, ldc = 0;
 };
 
@@ -246,7 +246,8 @@ void build_tables(int p, Built &B)
                 B.scol.push_back(h);
             }
         B.srow.resize(pad16((int)B.srow.size()), -1);
-        B.scol.resize(pad4((int)B.scol.size()), -1);
+        const int cp = sym_colpad(p);
+        B.scol.resize(((int)B.scol.size() + cp - 1) / cp * cp, -1);
     }
     if ((int)B.srow.size() != 16 * sym_row_tiles(p) || (int)B.scol.size() != 4 * sym_ksteps(p))
         throw std::logic_error("sign-class layout");
@@ -297,6 +298,16 @@ void build_tables(int p, Built &B)
                         ++c;
                     }
         if (c != kSymClasses) throw std::logic_error("sign class count");
+    }
+    B.sslot.assign(8 * kVSlots, -1);
+    for (int o = 0; o < 8; ++o) {
+        for (int c = 0; c < kSymClasses; ++c)
+            for (int m = 0; m < 8; ++m) {
+                const int j = B.smem[(o * kSymClasses + c) * 8 + m];
+                if (j >= 0) B.sslot[o * kVSlots + j] = c;
+            }
+        for (int j = 0; j < kVSlots; ++j)
+            if (B.sslot[o * kVSlots + j] < 0) throw std::logic_error("V slot without a sign class");
     }
 
     // P2M: moments -> Mhat, table[g][a] = w_|a| C[a][g]
@@ -447,7 +458,7 @@ const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::s
         upload(B.unfold_c, &t.unfold_c, err) || upload(B.inv_fact, &t.inv_fact, err) ||
         upload(B.inv_w, &t.inv_w, err) || upload(B.exps, &t.exps, err) || upload(B.mpos, &t.mpos, err) || upload(B.mposf, &t.mposf, err) ||
         upload(B.srow, &t.srow, err) || upload(B.scol, &t.scol, err) || upload(B.srep, &t.srep, err) ||
-        upload(B.smem, &t.smem, err))
+        upload(B.smem, &t.smem, err) || upload(B.sslot, &t.sslot, err))
         return nullptr;
     void *d = nullptr;
     if (hipMalloc(&d, sizeof(OrderTables)) != hipSuccess ||
