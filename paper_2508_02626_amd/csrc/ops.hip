@@ -42,12 +42,15 @@ __global__ __launch_bounds__(256) void k_permute_q(const PlanView *V, Bases B)
 }
 
 // ---------------- P2M ----------------
+constexpr int kPwChunk = 16; // particles per LDS chunk of P2M / P2L
 template <int P>
 __global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
 {
     constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
     constexpr int R = (NC + 63) / 64;
-    __shared__ double pw[3][P + 1][65];
+    // particles are taken kPwChunk at a time: their powers in LDS stay small
+    // enough for many wavefronts per CU
+    __shared__ double pw[3][P + 1][kPwChunk + 1];
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int box = v.leaves[blockIdx.x - B.b[k]];
@@ -65,23 +68,24 @@ __global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
         acc[r] = 0.0;
     }
     const int f = v.first[box], cnt = v.count[box];
-    for (int s = 0; s < cnt; s += 64) {
+    for (int s = 0; s < cnt; s += kPwChunk) {
         int i = f + s + lane;
         double u0 = 0, u1 = 0, u2 = 0, q = 0;
-        if (s + lane < cnt) {
+        if (lane < kPwChunk && s + lane < cnt) {
             u0 = (v.xs[i] - cen[0]) * ih;
             u1 = (v.ys[i] - cen[1]) * ih;
             u2 = (v.zs[i] - cen[2]) * ih;
             q = v.qs[i];
         }
         double a = q, b = 1.0, c = 1.0;
+        if (lane < kPwChunk)
 #pragma unroll
-        for (int e = 0; e <= P; ++e) {
-            pw[0][e][lane] = a; pw[1][e][lane] = b; pw[2][e][lane] = c;
-            a *= u0; b *= u1; c *= u2;
-        }
+            for (int e = 0; e <= P; ++e) {
+                pw[0][e][lane] = a; pw[1][e][lane] = b; pw[2][e][lane] = c;
+                a *= u0; b *= u1; c *= u2;
+            }
         __syncthreads();
-        int m = cnt - s < 64 ? cnt - s : 64;
+        int m = cnt - s < kPwChunk ? cnt - s : kPwChunk;
         for (int t = 0; t < m; ++t)
 #pragma unroll
             for (int r = 0; r < R; ++r) acc[r] += pw[0][ex[r]][t] * pw[1][ey[r]][t] * pw[2][ez[r]][t];
@@ -305,8 +309,8 @@ __global__ __launch_bounds__(64) void k_p2l(const PlanView *V, Bases B)
 {
     constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
     constexpr int R = (NC + 63) / 64;
-    __shared__ double pw[3][P + 1][65];
-    __shared__ double sr[P + 1][65];
+    __shared__ double pw[3][P + 1][kPwChunk + 1];
+    __shared__ double sr[P + 1][kPwChunk + 1];
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int box = v.xtgt[blockIdx.x - B.b[k]];
@@ -327,22 +331,23 @@ __global__ __launch_bounds__(64) void k_p2l(const PlanView *V, Bases B)
     for (int64_t e = v.X_off[box]; e < v.X_off[box + 1]; ++e) {
         const int src = v.X_src[e];
         const int f = v.first[src], cnt = v.count[src];
-        for (int s = 0; s < cnt; s += 64) {
+        for (int s = 0; s < cnt; s += kPwChunk) {
             double x = 1.0, y = 0.0, z = 0.0, q = 0.0;
-            if (s + lane < cnt) {
+            if (lane < kPwChunk && s + lane < cnt) {
                 const int i = f + s + lane;
                 x = (cen[0] - v.xs[i]) * ih; y = (cen[1] - v.ys[i]) * ih; z = (cen[2] - v.zs[i]) * ih;
                 q = v.qs[i];
             }
             const double ir2 = 1.0 / (x * x + y * y + z * z);
             double a = 1.0, b = 1.0, c = 1.0, w = q * sqrt(ir2);
+            if (lane < kPwChunk)
 #pragma unroll
-            for (int t = 0; t <= P; ++t) {
-                pw[0][t][lane] = a; pw[1][t][lane] = b; pw[2][t][lane] = c; sr[t][lane] = w;
-                a *= x; b *= y; c *= z; w *= ir2;
-            }
+                for (int t = 0; t <= P; ++t) {
+                    pw[0][t][lane] = a; pw[1][t][lane] = b; pw[2][t][lane] = c; sr[t][lane] = w;
+                    a *= x; b *= y; c *= z; w *= ir2;
+                }
             __syncthreads();
-            const int m = cnt - s < 64 ? cnt - s : 64;
+            const int m = cnt - s < kPwChunk ? cnt - s : kPwChunk;
             for (int t = 0; t < m; ++t)
 #pragma unroll
                 for (int r = 0; r < R; ++r)
