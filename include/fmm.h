@@ -122,7 +122,8 @@ int fmm_plan_batch(int32_t count, const double *const *xyz_dev, const int64_t *n
  * Asynchronous on `stream`: P2P runs on a stream of the plan's own, in two
  * parts forked from `stream` (after the charges are sorted, after M2L) and
  * joined back (before M2L, before the output), so that it overlaps the
- * upward and downward passes.  Deterministic: the
+ * upward and downward passes; M2P (W lists) follows the second part there.
+ * Deterministic: the
  * same plan and charges give bitwise identical results on every call.
  */
 int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_dev, double *field_dev,
@@ -189,9 +190,9 @@ int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, double *M_ho
  * fmm_plan_read_timing waits for the recorded events, adds their durations
  * (milliseconds) per stage into ms[0..15] and the number of timed evaluations
  * into calls[0..15], and clears the records.  Stages: 0 permute charges,
- * 1 P2M, 2 M2M, 3 fold, 4 M2L, 5 P2L, 6 unfold, 7 L2L, 8 L2P+M2P+output,
- * 9 and 10 the two parts of P2P (on the plan's side stream, concurrent with
- * stages 1-3 and 5-7 respectively).
+ * 1 P2M, 2 M2M, 3 fold, 4 M2L, 5 P2L, 6 unfold, 7 L2L, 8 L2P+output,
+ * 9 and 10 the two parts of P2P and 11 M2P (on the plan's side stream,
+ * concurrent with stages 1-3 and 5-7 respectively).
  */
 int fmm_plan_set_timing(fmm_plan_t plan, int on);
 int fmm_plan_read_timing(fmm_plan_t plan, double ms[16], int64_t calls[16]);

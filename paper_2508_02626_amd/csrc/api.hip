@@ -884,6 +884,19 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     HIPCHK(hipEventRecord(F->ev_fork, s)); // second part of P2P next to the downward pass
     HIPCHK(hipStreamWaitEvent(F->side, F->ev_fork, 0));
     p2p_part(1);
+    // M2P (W lists) adds into the near-field sums after P2P, next to the
+    // downward pass; plans without W lists skip it
+    {
+        T2.begin(11);
+        for (auto &r : runs) {
+            int w = 0;
+            for (int i = r.first; i < r.second; ++i) w += P[i]->nlist[2] > 0;
+            if (w)
+                launch_m2p(P[r.first]->p, V + r.first,
+                           sub(r.first, r.second, [](const fmm_plan_s *p) { return p->nlist[2] > 0 ? p->nleaves : 0; }), F->side);
+        }
+        T2.end();
+    }
     HIPCHK(hipEventRecord(F->ev_join, F->side));
     T.begin(5);
     for (auto &r : runs)
@@ -904,7 +917,7 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
             launch_l2l(V + r.first,
                        sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldm / 16); }), l, s);
     T.end();
-    // far field (L2P + M2P) plus the near field, written in the caller's order
+    // far field (L2P) plus the near field (P2P, M2P), written in the caller's order
     HIPCHK(hipStreamWaitEvent(s, F->ev_join, 0));
     T.begin(8);
     for (auto &r : runs)

@@ -445,7 +445,7 @@ template <int P>
 __global__ __launch_bounds__(64) void k_far(const PlanView *V, Bases B)
 {
     constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
-    __shared__ double cl[NC], cm[NC];
+    __shared__ double cl[NC];
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int box = v.leaves[blockIdx.x - B.b[k]];
@@ -458,7 +458,6 @@ __global__ __launch_bounds__(64) void k_far(const PlanView *V, Bases B)
         for (int a = lane; a < NC; a += 64) cl[a] = v.L[(int64_t)box * v.ldm + a] * t.inv_fact[a];
     __syncthreads();
     const int f = v.first[box], cnt = v.count[box];
-    const int64_t w0 = v.W_off[box], w1 = v.W_off[box + 1];
     for (int s = 0; s < cnt; s += 64) {
         int i = f + s + lane;
         bool act = s + lane < cnt;
@@ -471,6 +470,44 @@ __global__ __launch_bounds__(64) void k_far(const PlanView *V, Bases B)
             double ih2 = ih * ih;
             gx = fx * ih2; gy = fy * ih2; gz = fz * ih2;
         }
+        if (act) { // far part plus the near part (P2P, M2P), in the caller's order
+            const int o = v.perm[i];
+            v.phi_out[o] = phi + v.phi_near[i];
+            if (v.fld_out) {
+                v.fld_out[3 * o] = -gx + v.fld_near[3 * i];
+                v.fld_out[3 * o + 1] = -gy + v.fld_near[3 * i + 1];
+                v.fld_out[3 * o + 2] = -gz + v.fld_near[3 * i + 2];
+            }
+        }
+    }
+}
+
+// ---------------- M2P (W list) ----------------
+// phi_i += |d| sum_a M_a d^a, d = (x_i - c_C)/|x_i - c_C|^2 (Eq. P2M_phi at a
+// target, the M2P of Sec. 3.2), and its gradient, for every box C of the
+// leaf's W list, added to the near-field sums.  It needs only multipoles and
+// the near field, so it runs after the second P2P part on the side stream,
+// next to the downward pass.  One wavefront per leaf.
+template <int P>
+__global__ __launch_bounds__(64) void k_m2p(const PlanView *V, Bases B)
+{
+    constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
+    __shared__ double cm[NC];
+    int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int box = v.leaves[blockIdx.x - B.b[k]];
+    const int64_t w0 = v.W_off[box], w1 = v.W_off[box + 1];
+    if (w0 == w1) return;
+    const int lane = threadIdx.x;
+    const OrderTables &t = *v.tab;
+    double cen[3], h;
+    box_geom(v, box, cen, h);
+    const int f = v.first[box], cnt = v.count[box];
+    for (int s = 0; s < cnt; s += 64) {
+        int i = f + s + lane;
+        bool act = s + lane < cnt;
+        double x = act ? v.xs[i] : cen[0], y = act ? v.ys[i] : cen[1], z = act ? v.zs[i] : cen[2];
+        double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
         for (int64_t e = w0; e < w1; ++e) {
             int src = v.W_src[e];
             double sc[3], hs;
@@ -491,14 +528,11 @@ __global__ __launch_bounds__(64) void k_far(const PlanView *V, Bases B)
             gy += sr * (-y1 * s2 * f0 + hs * s2 * fy - 2.0 * hs * s2 * s2 * y1 * yf);
             gz += sr * (-y2 * s2 * f0 + hs * s2 * fz - 2.0 * hs * s2 * s2 * y2 * yf);
         }
-        if (act) { // far part plus the near part P2P left, in the caller's order
-            const int o = v.perm[i];
-            v.phi_out[o] = phi + v.phi_near[i];
-            if (v.fld_out) {
-                v.fld_out[3 * o] = -gx + v.fld_near[3 * i];
-                v.fld_out[3 * o + 1] = -gy + v.fld_near[3 * i + 1];
-                v.fld_out[3 * o + 2] = -gz + v.fld_near[3 * i + 2];
-            }
+        if (act) { // E = -grad phi
+            v.phi_near[i] += phi;
+            v.fld_near[3 * i] -= gx;
+            v.fld_near[3 * i + 1] -= gy;
+            v.fld_near[3 * i + 2] -= gz;
         }
     }
 }
@@ -748,6 +782,10 @@ void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s)
 void launch_p2l_transform(const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (nblk(B)) k_p2l_transform<<<nblk(B), 64, 0, s>>>(V, B);
+}
+void launch_m2p(int p, const PlanView *V, const Bases &B, hipStream_t s)
+{
+    if (nblk(B)) DISPATCH_P(p, k_m2p, <<<nblk(B), 64, 0, s>>>(V, B));
 }
 void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {

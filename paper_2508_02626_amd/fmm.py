@@ -20,7 +20,7 @@ SYMBOLS = ["fmm_default_options", "fmm_plan", "fmm_evaluate", "fmm_evaluate_batc
            "fmm_plan_footprint", "fmm_plan_estimate", "fmm_plan_sizes", "fmm_plan_export_tree",
            "fmm_plan_export_expansions", "fmm_plan_set_timing", "fmm_plan_read_timing",
            "fmm_plan_destroy", "fmm_last_error", "fmm_plan_batch"]
-STAGES = ["permute", "p2m", "m2m", "fold", "m2l", "p2l", "unfold", "l2l", "l2p_m2p", "p2p", "p2p_part2"]
+STAGES = ["permute", "p2m", "m2m", "fold", "m2l", "p2l", "unfold", "l2l", "l2p", "p2p", "p2p_part2", "m2p"]
 
 
 class FmmError(RuntimeError):
