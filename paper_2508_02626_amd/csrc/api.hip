@@ -905,17 +905,20 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     for (auto &r : runs)
         launch_p2l_transform(V + r.first, sub(r.first, r.second, [](const fmm_plan_s *p) {
             return (int)ceil_div(p->nxtgt, 16) * (p->ldh / 16); }), s);
+    // complete Lh rows (zero where nothing arrived, second half of the sign classes)
+    launch_lh_init(V, make([](const fmm_plan_s *p) { return (int)ceil_div(p->nboxes, 4); }, all), s);
+    T.end();
+    // L2L on the harmonic components, then full local expansions at the leaves
+    T.begin(7);
+    for (auto &r : runs)
+        for (int l = 2; l < maxdepth; ++l)
+            launch_l2lh(V + r.first,
+                        sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldh / 16); }), l, s);
     T.end();
     T.begin(6);
     for (auto &r : runs)
         launch_unfold(P[r.first]->p, V + r.first,
-                      sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).unfold; }), s);
-    T.end();
-    T.begin(7);
-    for (auto &r : runs)
-        for (int l = 2; l < maxdepth; ++l)
-            launch_l2l(V + r.first,
-                       sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldm / 16); }), l, s);
+                      sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).unfold; }), 1, s);
     T.end();
     // far field (L2P) plus the near field (P2P, M2P), written in the caller's order
     HIPCHK(hipStreamWaitEvent(s, F->ev_join, 0));
@@ -1128,6 +1131,13 @@ extern "C" int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, d
         }
     }
     if (L_host) {
+        // the evaluation unfolds leaves only: complete the full expansions of every box
+        Bases B{};
+        B.n = 1;
+        B.b[0] = 0;
+        B.b[1] = stage_blocks(P).unfold;
+        launch_unfold(P->p, P->view_dev, B, 0, stream);
+        HIPCHK(hipStreamSynchronize(stream));
         HIPCHK(hipMemcpy(buf.data(), P->view.L, 8ull * nb * ldm, hipMemcpyDeviceToHost));
         for (int b = 0; b < nb; ++b) {
             double h = P->root[3] / std::ldexp(1.0, lev[b]);

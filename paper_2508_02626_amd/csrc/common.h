@@ -211,6 +211,7 @@ struct OrderTables {
     const int *hoff;    // [ldh] additive D address of each harmonic index (-1 padding)
     const double *S;    // [8][nc][nc] M2M, S[o][a][b] = d Mhat'_b / d Mhat_a
     const double *G;    // [8][nc][nc] L2L, G[o][g][b] = d Lhat'_b / d Lhat_g
+    const double *GH;   // [8][nh][nh] L2L on the harmonic components, GH[o][a][c] = d Lh'_c / d Lh_a
     const double *P2M;  // [nc][nc] moments -> Mhat, P2M[g][a] = d Mhat_a / d Q_g
     const double *P2L;  // [nc][ldh] inverse moments -> harmonic Lhat
     const int *fold_off; const int *fold_idx; const double *fold_c;     // Mhat -> folded

@@ -9,8 +9,9 @@ void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 
 void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 leaves x 16 rows/block
 void launch_fold(int p, const PlanView *V, const Bases &B, hipStream_t s); // kRemapBoxes boxes/block
 void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block
-void launch_l2l(const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block
-void launch_unfold(int p, const PlanView *V, const Bases &B, hipStream_t s); // kRemapBoxes boxes/block
+void launch_l2lh(const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block (harmonic rows)
+void launch_lh_init(const PlanView *V, const Bases &B, hipStream_t s);        // 4 boxes/block
+void launch_unfold(int p, const PlanView *V, const Bases &B, int leaves_only, hipStream_t s); // kRemapBoxes boxes/block
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 X target/block
 void launch_p2l_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 X targets x 16 rows/block
 void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block (L2P + output)

@@ -177,7 +177,8 @@ __global__ __launch_bounds__(256) void k_fold(const PlanView *V, Bases B)
     }
 }
 
-// ---------------- M2M / L2L on the matrix cores ----------------
+// ---------------- M2M on the matrix cores ----------------
+// (instantiated for M2M; the L2L runs on the harmonic components, k_l2lh)
 // A block computes a 16 x 16 tile: 16 output coefficients (rows) of 16
 // parents (columns) of one level, as sum over octants of T_o^t * X_o with the
 // 16x16x4 FP64 MFMA, one wavefront per octant (M2M sums the eight partial
@@ -250,11 +251,72 @@ __global__ __launch_bounds__(512) void k_translate(const PlanView *V, Bases B, i
     }
 }
 
+// ---------------- L2L on the harmonic components ----------------
+// Lh(child) += GH_o^t Lh(parent): a block computes 16 rows of 16 parents of
+// one level, one wavefront per child octant (16x16x4 FP64 MFMA), and adds the
+// product of octant o to the octant-o children.
+__global__ __launch_bounds__(512) void k_l2lh(const PlanView *V, Bases B, int level)
+{
+    typedef double double4_t __attribute__((ext_vector_type(4)));
+    const int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int item = blockIdx.x - B.b[k];
+    const int nh = v.nh, ldh = v.ldh, MT = ldh / 16, g = item / MT, mt = item - g * MT;
+    const int o = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, col = lane & 15, kq = lane >> 4;
+    const int lb = v.lvl_nonleaf_off[level], le = v.lvl_nonleaf_off[level + 1];
+    const int pidx = lb + g * kPG + col;
+    const int parent = pidx < le ? v.lvl_nonleaf[pidx] : -1;
+    int ch = -1; // child of this lane's parent in octant o
+    if (parent >= 0) {
+        const int cb = v.child_begin[parent], ncd = v.nchild[parent];
+        for (int i = 0; i < ncd; ++i)
+            if ((int)(v.morton[cb + i] & 7) == o) ch = cb + i;
+    }
+    if (!__any(ch >= 0)) return;
+    const auto T = gptr(v.tab->GH + (int64_t)o * nh * nh);
+    const int bA = mt * 16 + col;
+    const auto X = gptr(v.Lh + (int64_t)(parent >= 0 ? parent : 0) * ldh);
+    double4_t acc = {0, 0, 0, 0};
+#pragma unroll 8
+    for (int kk = 0; kk < nh; kk += 4) {
+        const int a = kk + kq;
+        const double av = (bA < nh && a < nh) ? T[(int64_t)a * nh + bA] : 0.0;
+        const double bv = (parent >= 0 && a < nh) ? X[a] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    if (ch < 0) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int b = mt * 16 + 4 * r + kq; // f64 layout: lane l reg r -> row 4r + l/16
+        if (b < nh) gptr(v.Lh)[(int64_t)ch * ldh + b] += acc[r];
+    }
+}
+
+// Before the L2L: Lh rows of boxes (level >= 2) without M2L or P2L
+// contributions are set to zero, and for sign-class orders the second half of
+// the M2L classes (Lh2) is added.
+__global__ __launch_bounds__(256) void k_lh_init(const PlanView *V, Bases B)
+{
+    const int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int box = (blockIdx.x - B.b[k]) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (box >= v.nboxes || v.level[box] < 2) return;
+    const bool has_v = v.V_off[box + 1] > v.V_off[box], has_x = v.X_off[box + 1] > v.X_off[box];
+    const auto Lh = gptr(v.Lh + (int64_t)box * v.ldh);
+    if (!has_v && !has_x) {
+        for (int a = lane; a < v.ldh; a += 64) Lh[a] = 0.0;
+    } else if (has_v && v.Lh2) {
+        const auto Lh2 = gptr(v.Lh2 + (int64_t)box * v.ldh);
+        for (int a = lane; a < v.ldh; a += 64) Lh[a] = Lh[a] + Lh2[a];
+    }
+}
+
 // ---------------- unfold the M2L result to full local expansions ----------------
 // Same layout as the fold: 16 boxes per block, tables and the box's Lhat row
 // in LDS.
 template <int P>
-__global__ __launch_bounds__(256) void k_unfold(const PlanView *V, Bases B)
+__global__ __launch_bounds__(256) void k_unfold(const PlanView *V, Bases B, int leaves_only)
 {
     constexpr int NC = ncoef(P), NT = fold_terms(P), LDM = pad16(NC), LDH = pad16(nharm(P));
     __shared__ int sOff[NC + 1], sIdx[NT];
@@ -271,21 +333,15 @@ __global__ __launch_bounds__(256) void k_unfold(const PlanView *V, Bases B)
     for (int i = 0; i < 4; ++i) {
         const int box = first + i;
         if (box >= v.nboxes) break;
-        // rows of Lh exist only for boxes that received M2L or P2L contributions
-        const bool on = v.level[box] >= 2 &&
-                        (v.V_off[box + 1] > v.V_off[box] || v.X_off[box + 1] > v.X_off[box]);
+        if (leaves_only && v.nchild[box] > 0) continue;
+        // local expansions exist from level 2 on (Lh complete after the L2L)
         double *L = v.L + (int64_t)box * LDM;
-        if (!on) {
+        if (v.level[box] < 2) {
             for (int b = lane; b < LDM; b += 64) gptr(L)[b] = 0.0;
             continue;
         }
         const auto Lh = gptr(v.Lh + (int64_t)box * LDH);
-        if (m2l_sym(P) && v.V_off[box + 1] > v.V_off[box]) { // M2L split over two halves of its classes
-            const auto Lh2 = gptr(v.Lh2 + (int64_t)box * LDH);
-            for (int a = lane; a < LDH; a += 64) sRow[w][a] = Lh[a] + Lh2[a];
-        } else {
-            for (int a = lane; a < LDH; a += 64) sRow[w][a] = Lh[a];
-        }
+        for (int a = lane; a < LDH; a += 64) sRow[w][a] = Lh[a];
         wave_sync();
         for (int b = lane; b < LDM; b += 64) {
             double s = 0.0;
@@ -768,12 +824,17 @@ void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s)
 {
     if (nblk(B)) k_translate<1><<<nblk(B), 512, 0, s>>>(V, B, level);
 }
-void launch_l2l(const PlanView *V, const Bases &B, int level, hipStream_t s)
+void launch_unfold(int p, const PlanView *V, const Bases &B, int leaves_only, hipStream_t s)
 {
-    if (nblk(B)) k_translate<0><<<nblk(B), 512, 0, s>>>(V, B, level);
-}void launch_unfold(int p, const PlanView *V, const Bases &B, hipStream_t s)
+    if (nblk(B)) DISPATCH_P(p, k_unfold, <<<nblk(B), 256, 0, s>>>(V, B, leaves_only));
+}
+void launch_lh_init(const PlanView *V, const Bases &B, hipStream_t s)
 {
-    if (nblk(B)) DISPATCH_P(p, k_unfold, <<<nblk(B), 256, 0, s>>>(V, B));
+    if (nblk(B)) k_lh_init<<<nblk(B), 256, 0, s>>>(V, B);
+}
+void launch_l2lh(const PlanView *V, const Bases &B, int level, hipStream_t s)
+{
+    if (nblk(B)) k_l2lh<<<nblk(B), 512, 0, s>>>(V, B, level);
 }
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {

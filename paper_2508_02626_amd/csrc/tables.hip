@@ -162,7 +162,7 @@ std::vector<ld> harmonic_projection(const Mono &m, const std::vector<ld> &v, int
 }
 
 struct Built {
-    std::vector<double> D, S, G, P2M, P2L, fold_c, unfold_c, inv_fact, inv_w;
+    std::vector<double> D, S, G, GH, P2M, P2L, fold_c, unfold_c, inv_fact, inv_w;
     std::vector<float> Df;
     std::vector<int> offs, hoff, fold_off, fold_idx, unfold_off, unfold_idx, exps, dmap;
     std::vector<int> mpos, mposf, srow, scol, srep, smem, sslot;
@@ -406,6 +406,19 @@ void build_tables(int p, Built &B)
     }
     B.unfold_off[nc] = (int)B.unfold_idx.size();
     if ((int)B.unfold_idx.size() != fold_terms(p)) throw std::logic_error("unfold term count");
+    // L2L on the harmonic components: a local expansion is harmonic, so the
+    // full Lhat is the unfold of its (p+1)^2 components and the child's
+    // components follow from the parent's ones:
+    // GH[o][a][c] = sum_g unfold(g <- a) G[o][g][full index of c]
+    B.GH.assign((size_t)8 * nh * nh, 0.0);
+    for (int o = 0; o < 8; ++o)
+        for (int g = 0; g < nc; ++g)
+            for (int e = B.unfold_off[g]; e < B.unfold_off[g + 1]; ++e) {
+                const int a = B.unfold_idx[e];
+                const double w = B.unfold_c[e];
+                for (int c = 0; c < nh; ++c)
+                    B.GH[((size_t)o * nh + a) * nh + c] += w * B.G[((size_t)o * nc + g) * nc + mono_index(hx[c], hy[c], hz[c])];
+            }
 }
 
 struct Entry {
@@ -451,7 +464,7 @@ const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::s
     t.ldd = B.ldd; t.ldc = B.ldc; t.d3 = dlayout_s1(p); t.ldmh = folded_ld(p);
     if (upload(B.D, &t.D, err) || upload(B.Df, &t.Df, err) || upload(B.dmap, &t.dmap, err) ||
         upload(B.offs, &t.offs, err) ||
-        upload(B.hoff, &t.hoff, err) || upload(B.S, &t.S, err) || upload(B.G, &t.G, err) ||
+        upload(B.hoff, &t.hoff, err) || upload(B.S, &t.S, err) || upload(B.G, &t.G, err) || upload(B.GH, &t.GH, err) ||
         upload(B.P2M, &t.P2M, err) || upload(B.P2L, &t.P2L, err) || upload(B.fold_off, &t.fold_off, err) ||
         upload(B.fold_idx, &t.fold_idx, err) || upload(B.fold_c, &t.fold_c, err) ||
         upload(B.unfold_off, &t.unfold_off, err) || upload(B.unfold_idx, &t.unfold_idx, err) ||
