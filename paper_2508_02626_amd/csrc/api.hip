@@ -255,6 +255,7 @@ struct fmm_plan_s {
     }
     PlanSizes sizes{};         // host copy of the device size record
     int32_t *lvl_dev = nullptr; // first box of every level (device)
+    int32_t *wsrc = nullptr;    // W-list source flags (plans with W lists)
 
     static size_t rounded(size_t bytes) { return ((bytes ? bytes : 8) + 255) & ~(size_t)255; }
     // returns the chunk and, in *got, its size
@@ -548,6 +549,11 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         int bits = 1;
         while ((1LL << bits) < nb) ++bits;
         radix_sort_pairs(wk, P->src[3], wk2, wv2, (int)mw, bits, wscr, s);
+        // M2P sources: their full multipoles are rebuilt from the folded ones
+        P->wsrc = P->own<int32_t>(nb);
+        NOMEM(P->wsrc);
+        fill_i32(P->wsrc, nb, 0, s);
+        mark(P->src[2], mw, P->wsrc, s);
     }
     int *octoff = P->temp<int>(128);
     uint64_t *okey = P->temp<uint64_t>(nt + 1), *otk = P->temp<uint64_t>(nt + 1);
@@ -567,7 +573,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     v.nchild = bx.nchild; v.first = bx.first; v.count = bx.count; v.morton = bx.morton;
     v.perm = P->perm; v.xs = xs; v.ys = ys; v.zs = zs;
     v.U_off = P->off[0]; v.V_off = P->off[1]; v.W_off = P->off[2]; v.X_off = P->off[3];
-    v.U_src = P->src[0]; v.W_src = P->src[2]; v.X_src = P->src[3];
+    v.U_src = P->src[0]; v.W_src = P->src[2]; v.X_src = P->src[3]; v.wsrc = P->wsrc;
     v.m2l_tgt = slots; v.vslot = vslot; v.leaves = leaves; v.xtgt = xtgt;
     v.lvl_nonleaf = nonleaf; v.lvl_nonleaf_off = lnl_off; v.tab = P->tab;
     v.qs = qs; v.M = M; v.Mh = Mh; v.Lh = Lh; v.Lh2 = Lh2; v.L = L; v.Mhf = Mhf; v.phi_near = pf; v.fld_near = ff;
@@ -861,19 +867,29 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     T.end();
     int maxdepth = 0;
     for (int i = 0; i < count; ++i) maxdepth = std::max(maxdepth, P[i]->depth);
+    // fold the leaves' multipoles; the parents' folded multipoles follow from
+    // the M2M on the folded components
+    T.begin(3);
+    for (auto &r : runs)
+        launch_fold(P[r.first]->p, V + r.first,
+                    sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).fold; }), s);
+    T.end();
     T.begin(2);
     // Multipoles of levels 0 and 1 are never read by M2L (V lists start at
     // level 2) nor by M2P (W lists hold boxes of level >= 2), so the upward
     // pass stops at level 2; fmm_plan_export_expansions completes it on demand.
     for (auto &r : runs)
         for (int l = maxdepth - 1; l >= 2; --l)
-            launch_m2m(V + r.first,
-                       sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldm / 16); }), l, s);
-    T.end();
-    T.begin(3);
-    for (auto &r : runs)
-        launch_fold(P[r.first]->p, V + r.first,
-                    sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).fold; }), s);
+            launch_m2mh(V + r.first,
+                        sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldmh / 16); }), l, s);
+    // parents' FP32 operands (mixed M2L) and full multipoles (M2P sources)
+    for (auto &r : runs) {
+        int mixed = 0, wl = 0;
+        for (int i = r.first; i < r.second; ++i) { mixed |= P[i]->mixed_m2l; wl |= P[i]->nlist[2] > 0; }
+        if (mixed || wl)
+            launch_parent_mh(V + r.first,
+                             sub(r.first, r.second, [](const fmm_plan_s *p) { return (int)ceil_div(p->nboxes, 4); }), wl, s);
+    }
     T.end();
     HIPCHK(hipStreamWaitEvent(s, F->ev_join, 0)); // first part of P2P done
     T.begin(4);
@@ -1114,11 +1130,12 @@ extern "C" int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, d
     }
     std::vector<double> buf((size_t)nb * ldm);
     if (M_host) {
-        // finish the upward pass into levels 1 and 0 (not needed by the evaluation)
+        // full multipoles of every parent (the evaluation keeps the parents'
+        // ones folded and stops at level 2): the full M2M from the leaves up
         Bases B{};
         B.n = 1;
         B.b[0] = 0;
-        for (int l = std::min(1, P->depth - 1); l >= 0; --l) {
+        for (int l = P->depth - 1; l >= 0; --l) {
             B.b[1] = nonleaf_groups(P, l) * (P->ldm / 16);
             launch_m2m(P->view_dev, B, l, stream);
         }

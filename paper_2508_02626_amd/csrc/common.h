@@ -212,6 +212,9 @@ struct OrderTables {
     const double *S;    // [8][nc][nc] M2M, S[o][a][b] = d Mhat'_b / d Mhat_a
     const double *G;    // [8][nc][nc] L2L, G[o][g][b] = d Lhat'_b / d Lhat_g
     const double *GH;   // [8][nh][nh] L2L on the harmonic components, GH[o][a][c] = d Lh'_c / d Lh_a
+    const double *TM;   // [8][ldmh][ldmh] M2M on the folded positions, TM[o][a][c] = d Mh'_c / d Mh_a
+    const double *HR;   // [nh][nc] full harmonic Mhat from the folded (harmonic-order) components, HR[c][b]
+    const int *hpos;    // [nh] folded position of each harmonic component
     const double *P2M;  // [nc][nc] moments -> Mhat, P2M[g][a] = d Mhat_a / d Q_g
     const double *P2L;  // [nc][ldh] inverse moments -> harmonic Lhat
     const int *fold_off; const int *fold_idx; const double *fold_c;     // Mhat -> folded
@@ -247,6 +250,7 @@ struct PlanView {
     const int32_t *leaf_of;             // sorted position -> leaf box
     const int64_t *U_off, *V_off, *W_off, *X_off;
     const int32_t *U_src, *W_src, *X_src;
+    const int32_t *wsrc;                // [boxes] 1 for boxes in some W list (M2P sources), or null
     const int32_t *m2l_tgt;             // M2L targets, octant-grouped, groups padded to 64
     const int32_t *vslot;               // [boxes][189] M2L source per offset slot, or -1
     const int32_t *leaves;              // leaf boxes

@@ -136,7 +136,8 @@ __global__ __launch_bounds__(64) void k_p2m_transform(const PlanView *V, Bases B
 }
 
 // ---------------- fold Mhat onto the harmonic components used by M2L ----------------
-// A block folds 16 boxes (4 per wavefront): the term tables sit in LDS, each
+// The leaves' multipoles are folded here, the parents' ones come from the
+// folded M2M.  A block folds 16 boxes (4 per wavefront): the term tables sit in LDS, each
 // box's row of Mhat is staged in LDS by one coalesced load, and every lane
 // gathers its outputs from there.  Row nboxes is the zero row (the operand
 // of absent M2L sources).
@@ -166,6 +167,7 @@ __global__ __launch_bounds__(256) void k_fold(const PlanView *V, Bases B)
     for (int i = 0; i < 4; ++i) {
         const int box = first + i;
         if (box > v.nboxes) break;
+        if (box < v.nboxes && v.nchild[box] > 0) continue; // parents: folded M2M
         const auto M = gptr(v.M + (int64_t)box * LDM);
         for (int a = lane; a < LDM; a += 64) sRow[w][a] = box < v.nboxes ? M[a] : 0.0;
         wave_sync();
@@ -248,6 +250,81 @@ __global__ __launch_bounds__(512) void k_translate(const PlanView *V, Bases B, i
     for (int r = 0; r < 4; ++r) {
         const int b = mt * 16 + 4 * r + kq;
         v.M[(int64_t)parent * ldm + b] = sum[r]; // rows >= nc are zero
+    }
+}
+
+// ---------------- M2M on the folded components ----------------
+// The far field of a multipole, hence its translation truncated at degree p,
+// depends only on its folded vector: Mh(parent) = sum_o TM_o^t Mh(child_o),
+// TM_o a (folded positions)^2 matrix.  A block computes 16 folded positions of
+// 16 parents of one level, one wavefront per child octant (16x16x4 FP64 MFMA),
+// the eight partial tiles summed in octant order.
+__global__ __launch_bounds__(512) void k_m2mh(const PlanView *V, Bases B, int level)
+{
+    typedef double double4_t __attribute__((ext_vector_type(4)));
+    __shared__ double4_t red[8][64];
+    const int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int item = blockIdx.x - B.b[k];
+    const int ld = v.ldmh, MT = ld / 16, g = item / MT, mt = item - g * MT;
+    const int o = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, col = lane & 15, kq = lane >> 4;
+    const int lb = v.lvl_nonleaf_off[level], le = v.lvl_nonleaf_off[level + 1];
+    const int pidx = lb + g * kPG + col;
+    const int parent = pidx < le ? v.lvl_nonleaf[pidx] : -1;
+    int ch = -1; // child of this lane's parent in octant o
+    if (parent >= 0) {
+        const int cb = v.child_begin[parent], ncd = v.nchild[parent];
+        for (int i = 0; i < ncd; ++i)
+            if ((int)(v.morton[cb + i] & 7) == o) ch = cb + i;
+    }
+    double4_t acc = {0, 0, 0, 0};
+    if (__any(ch >= 0)) {
+        const auto T = gptr(v.tab->TM + (int64_t)o * ld * ld);
+        const auto X = gptr(v.Mh + (int64_t)(ch >= 0 ? ch : 0) * ld);
+        const int bA = mt * 16 + col;
+#pragma unroll 8
+        for (int kk = 0; kk < ld; kk += 4) {
+            const int a = kk + kq;
+            const double av = T[(int64_t)a * ld + bA];
+            const double bv = ch >= 0 ? X[a] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+        }
+    }
+    red[o][lane] = acc;
+    __syncthreads();
+    if (o != 0 || parent < 0) return;
+    double4_t sum = red[0][lane];
+#pragma unroll
+    for (int w = 1; w < 8; ++w) sum += red[w][lane]; // fixed order
+#pragma unroll
+    for (int r = 0; r < 4; ++r) // f64 layout: lane l reg r -> row 4r + l/16
+        gptr(v.Mh)[(int64_t)parent * ld + mt * 16 + 4 * r + kq] = sum[r];
+}
+
+// Parents' FP32 operand copy (mixed M2L) and, for plans with W lists, their
+// full multipoles for M2P, from the folded ones: one wavefront per non-leaf
+// box of level >= 2.
+__global__ __launch_bounds__(256) void k_parent_mh(const PlanView *V, Bases B, int full)
+{
+    const int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int box = (blockIdx.x - B.b[k]) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (box >= v.nboxes || v.nchild[box] == 0 || v.level[box] < 2) return;
+    const OrderTables &t = *v.tab;
+    const auto Mh = gptr(v.Mh + (int64_t)box * v.ldmh);
+    if (v.mixed_m2l)
+        for (int c = lane; c < v.ldmh; c += 64) {
+            const int h = t.mposf[c];
+            gptr(v.Mhf)[(int64_t)box * v.ldmh + c] = h >= 0 ? (float)Mh[t.hpos[h]] : 0.f;
+        }
+    if (!full || !v.wsrc || !v.wsrc[box]) return; // only M2P sources need it
+    const auto HR = gptr(t.HR);
+    for (int b = lane; b < v.ldm; b += 64) {
+        double s = 0.0;
+        if (b < v.nc)
+            for (int c = 0; c < v.nh; ++c) s += HR[(int64_t)c * v.nc + b] * Mh[t.hpos[c]];
+        gptr(v.M)[(int64_t)box * v.ldm + b] = s;
     }
 }
 
@@ -827,6 +904,14 @@ void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s)
 void launch_unfold(int p, const PlanView *V, const Bases &B, int leaves_only, hipStream_t s)
 {
     if (nblk(B)) DISPATCH_P(p, k_unfold, <<<nblk(B), 256, 0, s>>>(V, B, leaves_only));
+}
+void launch_m2mh(const PlanView *V, const Bases &B, int level, hipStream_t s)
+{
+    if (nblk(B)) k_m2mh<<<nblk(B), 512, 0, s>>>(V, B, level);
+}
+void launch_parent_mh(const PlanView *V, const Bases &B, int full, hipStream_t s)
+{
+    if (nblk(B)) k_parent_mh<<<nblk(B), 256, 0, s>>>(V, B, full);
 }
 void launch_lh_init(const PlanView *V, const Bases &B, hipStream_t s)
 {

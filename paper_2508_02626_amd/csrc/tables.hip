@@ -26,6 +26,7 @@
 
 #include <stdexcept>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -162,10 +163,10 @@ std::vector<ld> harmonic_projection(const Mono &m, const std::vector<ld> &v, int
 }
 
 struct Built {
-    std::vector<double> D, S, G, GH, P2M, P2L, fold_c, unfold_c, inv_fact, inv_w;
+    std::vector<double> D, S, G, GH, TM, HR, P2M, P2L, fold_c, unfold_c, inv_fact, inv_w;
     std::vector<float> Df;
     std::vector<int> offs, hoff, fold_off, fold_idx, unfold_off, unfold_idx, exps, dmap;
-    std::vector<int> mpos, mposf, srow, scol, srep, smem, sslot;
+    std::vector<int> mpos, mposf, hpos, srow, scol, srep, smem, sslot;
     int ldd = 0, ldc = 0;
 };
 
@@ -419,6 +420,84 @@ void build_tables(int p, Built &B)
                 for (int c = 0; c < nh; ++c)
                     B.GH[((size_t)o * nh + a) * nh + c] += w * B.G[((size_t)o * nc + g) * nc + mono_index(hx[c], hy[c], hz[c])];
             }
+    // M2M on the folded components: the far field of a multipole, hence its
+    // translation truncated at degree p, depends only on the folded vector, so
+    // TMh[o][a][c] = sum over the fold terms (j, w) of c of w S[o][full a][j],
+    // a taken as the full component with the same exponents; stored on the
+    // folded positions (mpos) of the M2L operand layout
+    const int ldmh = (int)B.mpos.size();
+    std::vector<ld> TMh((size_t)8 * nh * nh, 0.0L);
+    for (int o = 0; o < 8; ++o)
+        for (int c = 0; c < nh; ++c)
+            for (int e = B.fold_off[c]; e < B.fold_off[c + 1]; ++e) {
+                const int j = B.fold_idx[e];
+                const ld w = B.fold_c[e];
+                for (int a = 0; a < nh; ++a)
+                    TMh[((size_t)o * nh + a) * nh + c] +=
+                        w * (ld)B.S[((size_t)o * nc + mono_index(hx[a], hy[a], hz[a])) * nc + j];
+            }
+    B.TM.assign((size_t)8 * ldmh * ldmh, 0.0);
+    for (int o = 0; o < 8; ++o)
+        for (int pa = 0; pa < ldmh; ++pa)
+            for (int pb = 0; pb < ldmh; ++pb) {
+                const int a = B.mpos[pa], c = B.mpos[pb];
+                if (a >= 0 && c >= 0) B.TM[((size_t)o * ldmh + pa) * ldmh + pb] = (double)TMh[((size_t)o * nh + a) * nh + c];
+            }
+    B.hpos.assign(nh, -1);
+    for (int pa = 0; pa < ldmh; ++pa)
+        if (B.mpos[pa] >= 0) B.hpos[B.mpos[pa]] = pa;
+    // full harmonic Mhat from the folded components (for M2P sources that are
+    // not leaves): per degree n, the projections of the monomials with z
+    // exponent <= 1 span the harmonic polynomials; with F the fold,
+    // HR_n = Bn (F Bn)^-1, stored transposed ([nh][nc])
+    B.HR.assign((size_t)nc * nh, 0.0);
+    for (int n = 0; n <= p; ++n) {
+        std::vector<int> hc; // harmonic components of degree n
+        for (int c = 0; c < nh; ++c)
+            if (hx[c] + hy[c] + hz[c] == n) hc.push_back(c);
+        const int k = (int)hc.size();
+        std::vector<ld> A((size_t)k * k, 0.0L); // A[r][s] = (F Bn)[hc r][hc s]
+        for (int r = 0; r < k; ++r)
+            for (int e = B.fold_off[hc[r]]; e < B.fold_off[hc[r] + 1]; ++e)
+                for (int t = 0; t < k; ++t) {
+                    const int g = mono_index(hx[hc[t]], hy[hc[t]], hz[hc[t]]);
+                    A[(size_t)r * k + t] += (ld)B.fold_c[e] * Pi[(size_t)g * nc + B.fold_idx[e]];
+                }
+        // invert A (Gauss-Jordan with partial pivoting, long double)
+        std::vector<ld> Ai((size_t)k * k, 0.0L);
+        for (int r = 0; r < k; ++r) Ai[(size_t)r * k + r] = 1.0L;
+        for (int col = 0; col < k; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < k; ++r)
+                if (std::fabs(A[(size_t)r * k + col]) > std::fabs(A[(size_t)piv * k + col])) piv = r;
+            if (A[(size_t)piv * k + col] == 0.0L) throw std::logic_error("harmonic reconstruction: singular");
+            for (int t = 0; t < k; ++t) {
+                std::swap(A[(size_t)col * k + t], A[(size_t)piv * k + t]);
+                std::swap(Ai[(size_t)col * k + t], Ai[(size_t)piv * k + t]);
+            }
+            const ld d = A[(size_t)col * k + col];
+            for (int t = 0; t < k; ++t) { A[(size_t)col * k + t] /= d; Ai[(size_t)col * k + t] /= d; }
+            for (int r = 0; r < k; ++r)
+                if (r != col) {
+                    const ld f = A[(size_t)r * k + col];
+                    if (f == 0.0L) continue;
+                    for (int t = 0; t < k; ++t) {
+                        A[(size_t)r * k + t] -= f * A[(size_t)col * k + t];
+                        Ai[(size_t)r * k + t] -= f * Ai[(size_t)col * k + t];
+                    }
+                }
+        }
+        // HR[be][hc s] = sum_t Bn[be][t] Ai[t][s], Bn[be][t] = Pi[mono(hc t)][be]
+        for (int be = 0; be < nc; ++be) {
+            if (m.deg(be) != n) continue;
+            for (int sI = 0; sI < k; ++sI) {
+                ld acc = 0.0L;
+                for (int t = 0; t < k; ++t)
+                    acc += Pi[(size_t)mono_index(hx[hc[t]], hy[hc[t]], hz[hc[t]]) * nc + be] * Ai[(size_t)t * k + sI];
+                B.HR[(size_t)hc[sI] * nc + be] = (double)acc;
+            }
+        }
+    }
 }
 
 struct Entry {
@@ -464,7 +543,8 @@ const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::s
     t.ldd = B.ldd; t.ldc = B.ldc; t.d3 = dlayout_s1(p); t.ldmh = folded_ld(p);
     if (upload(B.D, &t.D, err) || upload(B.Df, &t.Df, err) || upload(B.dmap, &t.dmap, err) ||
         upload(B.offs, &t.offs, err) ||
-        upload(B.hoff, &t.hoff, err) || upload(B.S, &t.S, err) || upload(B.G, &t.G, err) || upload(B.GH, &t.GH, err) ||
+        upload(B.hoff, &t.hoff, err) || upload(B.S, &t.S, err) || upload(B.G, &t.G, err) || upload(B.GH, &t.GH, err) || upload(B.TM, &t.TM, err) ||
+        upload(B.HR, &t.HR, err) || upload(B.hpos, &t.hpos, err) ||
         upload(B.P2M, &t.P2M, err) || upload(B.P2L, &t.P2L, err) || upload(B.fold_off, &t.fold_off, err) ||
         upload(B.fold_idx, &t.fold_idx, err) || upload(B.fold_c, &t.fold_c, err) ||
         upload(B.unfold_off, &t.unfold_off, err) || upload(B.unfold_idx, &t.unfold_idx, err) ||
@@ -496,6 +576,8 @@ int host_order_tables(int p, int which, std::vector<double> &out)
     case 1: out = B.S; return ncoef(p);
     case 2: out = B.G; return ncoef(p);
     case 3: out = B.P2M; return ncoef(p);
+    case 4: out = B.TM; return (int)B.mpos.size();
+    case 5: out = B.HR; return nharm(p);
     default: return -1;
     }
 }

@@ -42,6 +42,7 @@ void flags(const BoxArrays &bx, int nboxes, const int64_t *xcnt, const int64_t *
            int64_t *fnon, int64_t *fx, int64_t *fv, hipStream_t s);
 void compact(const int64_t *flag, const int64_t *pos, int nboxes, int32_t *out, hipStream_t s);
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+void mark(const int32_t *idx, int64_t n, int32_t *flag, hipStream_t s); // flag[idx[i]] = 1
 void m2l_tiles(const BoxArrays &bx, const int32_t *tg, int nt, int uniform, uint64_t *key, int32_t *val,
                uint64_t *tk, int32_t *tv, int32_t *sort_scratch, int *octoff, int32_t *slots,
                int64_t slot_cap, hipStream_t s);

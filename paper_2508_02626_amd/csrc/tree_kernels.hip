@@ -795,6 +795,17 @@ void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
     if (n > 0) k_fill_i32<<<ceil_div(n, 256), 256, 0, s>>>(p, n, v);
 }
 
+__global__ void k_mark(const int32_t *idx, int64_t n, int32_t *flag)
+{
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) flag[idx[i]] = 1;
+}
+
+void mark(const int32_t *idx, int64_t n, int32_t *flag, hipStream_t s)
+{
+    if (n > 0) k_mark<<<ceil_div(n, 256), 256, 0, s>>>(idx, n, flag);
+}
+
 void m2l_tiles(const BoxArrays &bx, const int32_t *tg, int nt, int uniform, uint64_t *key, int32_t *val,
                uint64_t *tk, int32_t *tv, int32_t *sort_scratch, int *octoff, int32_t *slots,
                int64_t slot_cap, hipStream_t s)
