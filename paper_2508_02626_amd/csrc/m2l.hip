@@ -74,14 +74,12 @@ template <typename T> __device__ inline T gload(const T *p)
     return *(const __attribute__((address_space(1))) T *)p;
 }
 
-// From p = 12 on two wavefronts share each group of 16 targets, each taking
-// half of the row tiles (registers would not hold all of them).
-__host__ __device__ constexpr int m2l_row_split(int p) { return p >= 12 ? 2 : 1; }
-
+// (orders 0-5; orders from 6 on run on sign classes)
 template <int P, typename T>
-__global__ __launch_bounds__(256 * m2l_row_split(P)) void k_m2l(const PlanView *V, Bases B)
+__global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
 {
-    constexpr int RS = m2l_row_split(P);
+    static_assert(P <= 5, "slot-by-slot M2L serves orders 0-5");
+    constexpr int RS = 1; // row tiles per wavefront group: all of them
     constexpr int NT = 256 * RS; // threads per block
     constexpr int NH = (P + 1) * (P + 1);
     constexpr int MF = NH / 16, XR0 = NH - 16 * MF;
@@ -182,10 +180,10 @@ __global__ __launch_bounds__(256 * m2l_row_split(P)) void k_m2l(const PlanView *
     // components 4 VW t + VW kq (+0 .. VW-1).  FP64 keeps a window of NW
     // vectors in flight: vector t of the current slot lives in pb[t % NW], and
     // once it is used, vector t + NW is loaded into the same register (taken
-    // from the next slot when t + NW runs past the end of this one).  Up to
-    // p = 12 the window is the whole slot.
+    // from the next slot when t + NW runs past the end of this one).  At these
+    // orders the window is the whole slot.
     constexpr bool DB = sizeof(T) == 4;
-    constexpr int NW = (DB || P <= 12 || NV <= 8) ? NV : 8;
+    constexpr int NW = NV;
     vec_t pb[NW];
     dvec_t pd[DV];
     int dm[DV][DW]; // LDS address of each compact table entry this thread moves
