@@ -678,9 +678,10 @@ __global__ __launch_bounds__(64) void k_m2p(const PlanView *V, Bases B)
 // TPG = ceil(c/2) for the c targets of the pass), and the 64 / TPG lane groups
 // split every source chunk into contiguous ranges, so that each source read
 // from LDS serves two pairs and few lanes idle.  The group partial sums are
-// combined in a fixed order at the end.  Source chunks (<= 64 particles of one
-// U-list box) are staged in LDS as 32-byte records; the next chunk is loaded
-// into registers while the current one is summed.  FP64: plain sums.  Mixed:
+// combined in a fixed order at the end.  Source chunks (up to 64 particles, 32
+// in the mixed path, taken from consecutive U-list boxes) are staged in LDS as
+// 32-byte records; the next chunk is loaded into registers while the current
+// one is summed.  FP64: plain sums.  Mixed:
 // pair offsets are formed in FP64 and rounded to FP32, the pair terms are FP32
 // (hardware rsq), each lane sums a chunk in FP32 and the chunk partials are
 // accumulated in FP64.
@@ -799,39 +800,40 @@ __global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B, int par
         }
         ta.phi = ta.ex = ta.ey = ta.ez = 0.0;
         tb.phi = tb.ex = tb.ey = tb.ez = 0.0;
-        // walk (U entry, 64-particle chunk) pairs with one chunk prefetched
+        // the U list's particles as one stream, in chunks of up to CH (a chunk
+        // spans several source boxes), the next chunk prefetched into registers
+        constexpr int CH = MIXED ? 32 : 64; // mixed: FP32 partial sums stay short
         int64_t e = u0;
         int s = 0, sf = 0, sc = 0;
         if (e < u1) { int src = usrc[e]; sf = first[src]; sc = count[src]; }
         SrcRec nx{0, 0, 0, 0};
-        auto fetch = [&](int base, int m) {
-            if (lane < m) {
-                const int j = base + lane;
-                nx.x = xs[j]; nx.y = ys[j]; nx.z = zs[j]; nx.q = qs[j];
+        auto fill = [&]() { // next chunk into nx; returns its size
+            int m = 0;
+            while (m < CH && e < u1) {
+                const int take = sc - s < CH - m ? sc - s : CH - m;
+                if (lane >= m && lane < m + take) {
+                    const int j = sf + s + (lane - m);
+                    nx.x = xs[j]; nx.y = ys[j]; nx.z = zs[j]; nx.q = qs[j];
+                }
+                m += take;
+                s += take;
+                if (s >= sc) {
+                    s = 0;
+                    if (++e < u1) { int src = usrc[e]; sf = first[src]; sc = count[src]; }
+                }
             }
+            return m;
         };
-        // advance to the first non-empty chunk
-        while (e < u1 && sc == 0) {
-            if (++e < u1) { int src = usrc[e]; sf = first[src]; sc = count[src]; }
-        }
-        if (e < u1) fetch(sf, sc < 64 ? sc : 64);
-        while (e < u1) {
-            const int m = sc - s < 64 ? sc - s : 64;
+        int m = fill();
+        while (m > 0) {
             wave_sync();
             S[lane] = nx;
             wave_sync();
-            // next chunk
-            s += 64;
-            if (s >= sc) {
-                s = 0;
-                do {
-                    if (++e < u1) { int src = usrc[e]; sf = first[src]; sc = count[src]; }
-                } while (e < u1 && sc == 0);
-            }
-            if (e < u1) fetch(sf + s, sc - s < 64 ? sc - s : 64);
+            const int mn = fill(); // in flight during this chunk's pairs
             const int per = (m + G - 1) / G;
             const int lo = inG ? grp * per : m, hi = lo + per < m ? lo + per : m;
             p2p_range<MIXED>(S, lo, hi, ta, tb);
+            m = mn;
         }
         // combine the lane groups in a fixed order
         wave_sync();
