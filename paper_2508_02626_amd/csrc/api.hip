@@ -206,7 +206,7 @@ struct fmm_plan_s {
     double root[4] = {0, 0, 0, 1};
     int p = 0, nc = 0, nh = 0, ldm = 0, ldh = 0, ldmh = 0, D = 0, depth = 0, leaf_size = 0;
     int uniform = 0, precision = 0, mixed_m2l = 0;
-    int n = 0, nboxes = 0, nleaves = 0, nxtgt = 0, nslots = 0;
+    int n = 0, nboxes = 0, nleaves = 0, nxtgt = 0, nslots = 0, m2l_parts = 1;
     int64_t nlist[4] = {0, 0, 0, 0};
     std::vector<int> lvl_begin;       // boxes per level (host)
     std::vector<int> lvl_nonleaf_off; // non-leaf boxes per level (host)
@@ -416,6 +416,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         P->nboxes = (int)tot;
     }
     const int nb = P->nboxes;
+    P->m2l_parts = sym_m2l_parts(P->p);
     // the sign-class M2L addresses the folded multipoles with 32-bit byte offsets
     if (m2l_sym(P->p) && (unsigned long long)(nb + 1) * (unsigned long long)P->ldmh * 8ULL >= (1ULL << 32))
         return fail(FMM_EUNSUPPORTED, "too many boxes for this order (folded multipoles reach 4 GiB)");
@@ -429,7 +430,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
          .add<int32_t>(kMaxDepth + 2).add<PlanView>(1)
          .add<double>((size_t)nb * P->ldm).add<double>((size_t)nb * P->ldm)
          .add<double>((size_t)(nb + 1) * P->ldmh).add<double>((size_t)nb * P->ldh);
-        if (m2l_sym(P->p)) o.add<double>((size_t)nb * P->ldh);
+        if (P->m2l_parts > 1) o.add<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh);
         if (P->mixed_m2l) o.add<float>((size_t)(nb + 1) * P->ldmh);
         if (!P->reserve(true, o.total)) return fail(FMM_ENOMEM, "device allocation failed (boxes)");
         Sizer t;
@@ -459,8 +460,9 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     // folded multipoles: one row per box and an all-zero row after them
     double *Mh = P->own<double>((size_t)(nb + 1) * P->ldmh), *Lh = P->own<double>((size_t)nb * P->ldh);
     float *Mhf = P->mixed_m2l ? P->own<float>((size_t)(nb + 1) * P->ldmh) : nullptr;
-    double *Lh2 = m2l_sym(P->p) ? P->own<double>((size_t)nb * P->ldh) : nullptr;
-    if (m2l_sym(P->p)) NOMEM(Lh2);
+    // partial sums of the M2L class parts after the first
+    double *Lh2 = P->m2l_parts > 1 ? P->own<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh) : nullptr;
+    if (P->m2l_parts > 1) NOMEM(Lh2);
     NOMEM(vslot); NOMEM(leaves); NOMEM(nonleaf); NOMEM(xtgt); NOMEM(lnl_off); NOMEM(P->view_dev);
     NOMEM(M); NOMEM(L); NOMEM(Mh); NOMEM(Lh);
     if (P->mixed_m2l) NOMEM(Mhf);
@@ -576,7 +578,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     v.U_src = P->src[0]; v.W_src = P->src[2]; v.X_src = P->src[3]; v.wsrc = P->wsrc;
     v.m2l_tgt = slots; v.vslot = vslot; v.leaves = leaves; v.xtgt = xtgt;
     v.lvl_nonleaf = nonleaf; v.lvl_nonleaf_off = lnl_off; v.tab = P->tab;
-    v.qs = qs; v.M = M; v.Mh = Mh; v.Lh = Lh; v.Lh2 = Lh2; v.L = L; v.Mhf = Mhf; v.phi_near = pf; v.fld_near = ff;
+    v.qs = qs; v.M = M; v.Mh = Mh; v.Lh = Lh; v.Lh2 = Lh2; v.m2l_parts = P->m2l_parts; v.L = L; v.Mhf = Mhf; v.phi_near = pf; v.fld_near = ff;
     HIPCHK(hipMemcpyAsync(P->view_dev, &v, sizeof(PlanView), hipMemcpyHostToDevice, s));
     HIPCHK(hipGetLastError());
     P->release_temps();
@@ -744,7 +746,7 @@ StagePlan stage_blocks(const fmm_plan_s *P)
     sp.permute = (int)ceil_div(P->n, 256);
     sp.p2m = P->nleaves;
     sp.fold = (int)ceil_div(P->nboxes + 1, kRemapBoxes); // and the zero row
-    sp.m2l = P->nslots / kM2LSlots * (m2l_sym(P->p) ? 2 : 1); // sign classes: two blocks per tile
+    sp.m2l = P->nslots / kM2LSlots * P->m2l_parts; // sign classes: m2l_parts blocks per tile
     sp.p2l = P->nxtgt;
     sp.unfold = (int)ceil_div(P->nboxes, kRemapBoxes);
     sp.far = P->nleaves;
@@ -1031,7 +1033,8 @@ extern "C" int fmm_plan_estimate(int64_t n, int32_t order, int32_t leaf_size, co
         boxes = 1 + 8.0 * 2.0 * n / (leaf_size + 1);
     }
     double ldm = pad16(ncoef(order)), ldh = pad16(nharm(order)), ldmh = folded_ld(order);
-    double per_box = 8 * (2 * ldm + (m2l_sym(order) ? 2 : 1) * ldh + ldmh) + 4 * ldmh + 4 * 200 + 64; // expansions, slots, lists
+    const int parts = sym_m2l_parts(order);
+    double per_box = 8 * (2 * ldm + parts * ldh + ldmh) + 4 * ldmh + 4 * 200 + 64; // expansions, slots, lists
     double per_particle = 8 * 3 + 4 + 8 * 5 + 8 * 2;
     double total = boxes * per_box + n * per_particle + 8 * 27 * boxes;
     *bytes = (size_t)(total * 1.25);

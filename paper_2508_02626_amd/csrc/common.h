@@ -122,6 +122,13 @@ __host__ __device__ constexpr int sym_ksteps(int p)
 }
 // orders whose M2L runs on sign classes (fewer matrix-core products from p = 6 on)
 __host__ __device__ constexpr bool m2l_sym(int p) { return p >= 6; }
+// blocks per M2L tile of 64 targets at sign-class orders: the tile's classes
+// are split into this many parts of about equal matrix-core work, each block
+// writing its own partial sums.  Two: more, shorter blocks did not shorten the
+// launch's tail as much as their per-block set-up (the targets' slot rows)
+// cost (uniform 10^6 points, p = 8: 1.03 ms with two, 1.17 with four, 1.29
+// with eight).
+__host__ __device__ constexpr int sym_m2l_parts(int p) { return m2l_sym(p) ? 2 : 1; }
 // launches the row tiles of an order >= 12 sign-class M2L are split over (at
 // most 9 row tiles of accumulators per wavefront)
 __host__ __device__ constexpr int sym_row_parts(int p) { return p >= 12 ? (sym_row_tiles(p) + 8) / 9 : 1; }
@@ -261,7 +268,9 @@ struct PlanView {
     // evaluation buffers
     double *qs;                         // sorted charges
     double *M, *Mh, *Lh, *L;            // [boxes][ldm] / [boxes][ldmh] / [boxes][ldh]
-    double *Lh2;                        // sign-class orders: second half of the M2L classes
+    double *Lh2;                        // sign-class orders: [m2l_parts - 1][boxes][ldh] partial
+                                        // sums of the M2L class parts after the first
+    int m2l_parts;                      // blocks per M2L tile (1 below the sign-class orders)
     float *Mhf;                         // FP32 folded multipoles (mixed M2L)
     double *phi_near, *fld_near;        // near-field (P2P) part, sorted order
     // caller's arrays for this evaluation

@@ -336,11 +336,16 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
 // parity of a + b is the same for a whole 16-row tile and k-step: each MFMA
 // takes its B operand from one transform output fixed at compile time.  Where
 // k has a zero component, D_g(k) vanishes for odd g on that axis, and the
-// row-tile / k-step pairs of opposite parity on it are skipped.  Each k-step
-// loads the members' operands (one component per lane and member, 8 loads,
-// always issued so that the waits count them) two vectors ahead, across
-// class boundaries.  Two blocks share a tile, each running half of its
-// classes; the second writes its partial sums to Lh2, which the unfold adds.
+// row-tile / k-step pairs of opposite parity on it are skipped, and so are
+// the members that would negate it (they do not exist) with their loads and
+// butterflies.  Each k-step loads the members' operands (one component per
+// lane and member; a member missing on a nonzero axis reads the zero row, so
+// that the loads of one zero mask are fixed at compile time and the waits
+// count them) two vectors ahead, across class boundaries (all eight members
+// for the next class, whose mask is not known there).  m2l_parts blocks share
+// a tile, each running a contiguous part of its classes of about equal
+// matrix-core work; part i > 0 writes its partial sums to slice i - 1 of Lh2,
+// which the L2L initialisation adds in part order.
 template <int P> struct SymShape {
     static constexpr int RT = sym_row_tiles(P), KS = sym_ksteps(P);
     int rc[RT], kc[KS]; // parity class of each row tile and k-step
@@ -365,6 +370,44 @@ template <typename T> __device__ inline void wht8(T (&h)[8])
 #pragma unroll
         for (int i = 0; i < 8; ++i)
             if (!(i & bit)) {
+                const T u = h[i], w = h[i | bit];
+                h[i] = u + w;
+                h[i | bit] = u - w;
+            }
+}
+
+// Class range [qa, qb) of part `part` of a tile whose classes list[0..n) are
+// split into `parts` contiguous ranges of about equal matrix-core work (a
+// class with z zero axes runs 1 / 2^z of the row-tile / k-step products): a
+// class belongs to the part that holds the midpoint of its weight.
+__device__ inline void sym_part_range(const int *list, const int *rep, int n, int parts, int part, int &qa,
+                                      int &qb)
+{
+    int W = 0;
+    for (int q = 0; q < n; ++q) W += 4 >> __popc(rep[list[q]] >> 16);
+    int lo = 0, hi = 0, cw = 0;
+    for (int q = 0; q < n; ++q) {
+        const int w = 4 >> __popc(rep[list[q]] >> 16);
+        const int pt = min(parts - 1, (2 * cw + w) * parts / (2 * W));
+        lo += pt < part;
+        hi += pt <= part;
+        cw += w;
+    }
+    qa = lo;
+    qb = hi;
+}
+
+// The transform of a class with zero axes Z: members that negate a zero axis
+// do not exist, and only outputs r with r & Z == 0 are used, so the butterflies
+// run over the other axes on the entries with no bit of Z (h[m], m & Z != 0,
+// is neither read nor written).
+template <int Z, typename T> __device__ inline void wht8z(T (&h)[8])
+{
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!(bit & Z) && !(i & bit) && !(i & Z)) {
                 const T u = h[i], w = h[i | bit];
                 h[i] = u + w;
                 h[i | bit] = u - w;
@@ -396,13 +439,14 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
     __shared__ int sMem[kSymClasses][8];    // member slots
     __shared__ int sZend[8];                // end of each zero mask's classes in sList
     __shared__ int sSrc[64][kVSlots];
-    __shared__ int sN, soct;
+    __shared__ int sQa, sQb, soct;
 
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
-    // two blocks per tile, each taking half of the tile's classes (twice as
-    // many, shorter blocks: less idle time at the end of the launch)
-    const int rb = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]), tile = rb >> 1, half = rb & 1;
+    // m2l_parts blocks per tile, each taking a part of the tile's classes
+    // (more, shorter blocks: less idle time at the end of the launch)
+    const int parts = v.m2l_parts;
+    const int rb = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]), tile = rb / parts, part = rb - tile * parts;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
     const int tgt = v.m2l_tgt[tile * kM2LSlots + wave * 16 + col];
     if (!__syncthreads_or(tgt >= 0)) return;
@@ -447,11 +491,13 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
             if (sList[c]) sList[n++] = c;
             sZend[sRep[c] >> 16] = n;
         }
-        sN = n;
+        int qa, qb;
+        sym_part_range(sList, sRep, n, parts, part, qa, qb);
+        sQa = qa;
+        sQb = qb;
     }
     __syncthreads();
-    const int nvalid = sN;
-    const int qa = half ? (nvalid + 1) / 2 : 0, qb = half ? nvalid : (nvalid + 1) / 2; // this block's classes
+    const int qa = sQa, qb = sQb; // this block's classes
     const int64_t ldmh = v.ldmh;
     const T *Dt = Mfma<T>::D(tb);
     const T *Mh = Mfma<T>::M(v);
@@ -505,9 +551,13 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
     // (the empty asm keeps each 32-bit offset in its register at the load, so
     // the address stays base + offset instead of a 64-bit pointer per member
     // hoisted out of the class loop)
-    auto load_b = [&](int slot, int j, const uint32_t (&src)[8]) {
+    // (zc: the class's zero axes, whose negating members are absent and not
+    // loaded; 0 for loads of a class whose mask is not known here)
+    auto load_b = [&](int slot, int j, const uint32_t (&src)[8], auto zc) {
+        constexpr int Z = decltype(zc)::value;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
+            if (m & Z) continue;
             uint32_t o = src[m];
             asm volatile("" : "+v"(o));
             pb[slot][m] = *(gp<const vec_t>)(Mg + (uint64_t)o + 16 * (4 * j));
@@ -532,8 +582,8 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
                 }
                 T h[8];
 #pragma unroll
-                for (int m = 0; m < 8; ++m) h[m] = pb[(ks / VW) % 2][m][ks % VW];
-                wht8(h);
+                for (int m = 0; m < 8; ++m) h[m] = (m & Z) ? T(0) : pb[(ks / VW) % 2][m][ks % VW];
+                wht8z<Z>(h);
 #pragma unroll
                 for (int mt = 0; mt < MTW; ++mt) {
                     if (!((S.rc[mt] ^ S.kc[ks]) & Z))
@@ -542,8 +592,8 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
             }
             if (ks % VW == VW - 1) { // vector j used up: refill its registers with vector j + 2
                 const int j = ks / VW, jn = j + 2;
-                if (jn < KSV) load_b(j % 2, jn, srcc);
-                else if (jn >= KSVW && jn - KSVW < KSV) load_b(j % 2, jn - KSVW, srcn);
+                if (jn < KSV) load_b(j % 2, jn, srcc, zc);
+                else if (jn >= KSVW && jn - KSVW < KSV) load_b(j % 2, jn - KSVW, srcn, std::integral_constant<int, 0>{});
             }
         }
     };
@@ -551,8 +601,8 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
         load_d(sList[qa]);
         store_d(0);
         class_src(qa, srcc);
-        load_b(0, 0, srcc);
-        if (KSV > 1) load_b(1, 1, srcc);
+        load_b(0, 0, srcc, std::integral_constant<int, 0>{});
+        if (KSV > 1) load_b(1, 1, srcc, std::integral_constant<int, 0>{});
         __syncthreads();
     }
     // the classes of one zero mask follow each other: one loop per mask
@@ -589,7 +639,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
     run_mask(std::integral_constant<int, 5>{});
     run_mask(std::integral_constant<int, 6>{}); // at most two zero axes
     if (tgt < 0) return;
-    double *Lh = (half ? v.Lh2 : v.Lh) + (int64_t)tgt * v.ldh;
+    double *Lh = (part ? v.Lh2 + (int64_t)(part - 1) * v.nboxes * v.ldh : v.Lh) + (int64_t)tgt * v.ldh;
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
@@ -601,8 +651,8 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
 }
 
 // ---------------- sign-class M2L for orders >= 12 ----------------
-// The same decomposition as k_m2l_sym (classes in zero-mask order, two blocks
-// per tile over halves of the classes, transform of the members, one MFMA per
+// The same decomposition as k_m2l_sym (classes in zero-mask order, m2l_parts
+// blocks per tile over parts of the classes, transform of the members, one MFMA per
 // row tile and k-step with a compile-time transform output), organised so
 // that the code stays small at high order: the row tiles are split over
 // sym_row_parts launches (at most 9 tiles of accumulators per wavefront), and
@@ -639,11 +689,12 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     __shared__ int sMem[kSymClasses][8];
     __shared__ int sZend[8];
     __shared__ unsigned long long sUsed;
-    __shared__ int sN, soct;
+    __shared__ int sQa, sQb, soct;
 
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
-    const int rb = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]), tile = rb >> 1, half = rb & 1;
+    const int parts = v.m2l_parts;
+    const int rb = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]), tile = rb / parts, part = rb - tile * parts;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
     const int tgt = v.m2l_tgt[tile * kM2LSlots + wave * 16 + col];
     if (!__syncthreads_or(tgt >= 0)) return;
@@ -683,11 +734,13 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
             if ((used >> c) & 1) sList[n++] = c;
             sZend[sRep[c] >> 16] = n;
         }
-        sN = n;
+        int qa, qb;
+        sym_part_range(sList, sRep, n, parts, part, qa, qb);
+        sQa = qa;
+        sQb = qb;
     }
     __syncthreads();
-    const int nvalid = sN;
-    const int qa = half ? (nvalid + 1) / 2 : 0, qb = half ? nvalid : (nvalid + 1) / 2;
+    const int qa = sQa, qb = sQb;
     const int64_t ldmh = v.ldmh;
     const T *Dt = tb.D;
     const T *Mh = v.Mh;
@@ -818,7 +871,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     run_mask(std::integral_constant<int, 5>{});
     run_mask(std::integral_constant<int, 6>{});
     if (tgt < 0) return;
-    double *Lh = (half ? v.Lh2 : v.Lh) + (int64_t)tgt * v.ldh;
+    double *Lh = (part ? v.Lh2 + (int64_t)(part - 1) * v.nboxes * v.ldh : v.Lh) + (int64_t)tgt * v.ldh;
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll

@@ -371,8 +371,8 @@ __global__ __launch_bounds__(512) void k_l2lh(const PlanView *V, Bases B, int le
 }
 
 // Before the L2L: Lh rows of boxes (level >= 2) without M2L or P2L
-// contributions are set to zero, and for sign-class orders the second half of
-// the M2L classes (Lh2) is added.
+// contributions are set to zero, and for sign-class orders the partial sums of
+// the other M2L class parts (Lh2 slices) are added in part order.
 __global__ __launch_bounds__(256) void k_lh_init(const PlanView *V, Bases B)
 {
     const int k = find_plan(B, blockIdx.x);
@@ -383,9 +383,14 @@ __global__ __launch_bounds__(256) void k_lh_init(const PlanView *V, Bases B)
     const auto Lh = gptr(v.Lh + (int64_t)box * v.ldh);
     if (!has_v && !has_x) {
         for (int a = lane; a < v.ldh; a += 64) Lh[a] = 0.0;
-    } else if (has_v && v.Lh2) {
+    } else if (has_v && v.m2l_parts > 1) {
+        const int64_t slice = (int64_t)v.nboxes * v.ldh;
         const auto Lh2 = gptr(v.Lh2 + (int64_t)box * v.ldh);
-        for (int a = lane; a < v.ldh; a += 64) Lh[a] = Lh[a] + Lh2[a];
+        for (int a = lane; a < v.ldh; a += 64) {
+            double s = Lh[a];
+            for (int i = 0; i < v.m2l_parts - 1; ++i) s += Lh2[i * slice + a];
+            Lh[a] = s;
+        }
     }
 }
 
