@@ -376,25 +376,32 @@ template <typename T> __device__ inline void wht8(T (&h)[8])
             }
 }
 
-// Class range [qa, qb) of part `part` of a tile whose classes list[0..n) are
-// split into `parts` contiguous ranges of about equal matrix-core work (a
-// class with z zero axes runs 1 / 2^z of the row-tile / k-step products): a
-// class belongs to the part that holds the midpoint of its weight.
-__device__ inline void sym_part_range(const int *list, const int *rep, int n, int parts, int part, int &qa,
-                                      int &qb)
+// Run by one whole wavefront: from the mask of classes used by a tile's
+// targets, list them in class order (sList), note where each zero mask's
+// classes end in the list (sZend; the table orders classes by zero mask) and
+// pick the range [sQa, sQb) of part `part` when the list is split into
+// `parts` contiguous ranges of about equal matrix-core work (a class with z
+// zero axes runs 1 / 2^z of the row-tile / k-step products): a class belongs
+// to the part that holds the midpoint of its weight.  Lane c handles class c.
+__device__ inline void sym_select_classes(unsigned long long used, const int *rep, int parts, int part, int lane,
+                                          int *list, int *zend, int *qa, int *qb)
 {
-    int W = 0;
-    for (int q = 0; q < n; ++q) W += 4 >> __popc(rep[list[q]] >> 16);
-    int lo = 0, hi = 0, cw = 0;
-    for (int q = 0; q < n; ++q) {
-        const int w = 4 >> __popc(rep[list[q]] >> 16);
-        const int pt = min(parts - 1, (2 * cw + w) * parts / (2 * W));
-        lo += pt < part;
-        hi += pt <= part;
-        cw += w;
+    const int c = lane;
+    const bool u = c < kSymClasses && ((used >> c) & 1);
+    const int z = c < kSymClasses ? rep[c] >> 16 : 0, zn = c + 1 < kSymClasses ? rep[c + 1] >> 16 : 8;
+    const unsigned long long below = lanes_below(c);
+    if (u) list[__popcll(used & below)] = c;
+    if (c < kSymClasses && zn != z) zend[z] = __popcll(used & (below | (1ull << c)));
+    const int pz = __popc(z), w = 4 >> pz;
+    const unsigned long long b0 = __ballot(u && pz == 0), b1 = __ballot(u && pz == 1), b2 = __ballot(u && pz == 2);
+    const int W = 4 * __popcll(b0) + 2 * __popcll(b1) + __popcll(b2);
+    const int cw = 4 * __popcll(b0 & below) + 2 * __popcll(b1 & below) + __popcll(b2 & below);
+    const int pt = W > 0 ? min(parts - 1, (2 * cw + w) * parts / (2 * W)) : 0;
+    const unsigned long long lo = __ballot(u && pt < part), hi = __ballot(u && pt <= part);
+    if (lane == 0) {
+        *qa = __popcll(lo);
+        *qb = __popcll(hi);
     }
-    qa = lo;
-    qb = hi;
 }
 
 // The transform of a class with zero axes Z: members that negate a zero axis
@@ -439,6 +446,8 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
     __shared__ int sMem[kSymClasses][8];    // member slots
     __shared__ int sZend[8];                // end of each zero mask's classes in sList
     __shared__ int sSrc[64][kVSlots];
+    __shared__ int sSl[kVSlots];            // class of each V slot
+    __shared__ unsigned long long sUsed;
     __shared__ int sQa, sQb, soct;
 
     const int k = find_plan(B, blockIdx.x);
@@ -452,6 +461,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
     if (!__syncthreads_or(tgt >= 0)) return;
     if (tgt >= 0) soct = (int)(v.morton[tgt] & 7);
     if (tid < 64) sTg[tid] = v.m2l_tgt[tile * kM2LSlots + tid];
+    if (tid == 0) sUsed = 0;
     const OrderTables &tb = *v.tab;
     for (int e = tid; e < 4 * KS; e += NT) {
         const int g = e / KS, ks = e - g * KS, a = gptr(tb.scol)[4 * ks + g];
@@ -473,29 +483,18 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
         for (int e = tid; e < kSymClasses * 8; e += NT)
             sMem[e >> 3][e & 7] = gptr(tb.smem)[soct * kSymClasses * 8 + e];
         if (tid < kSymClasses) sRep[tid] = gptr(tb.srep)[soct * kSymClasses + tid];
+        if (tid < kVSlots) sSl[tid] = gptr(tb.sslot)[soct * kVSlots + tid];
     }
     __syncthreads();
-    if (tid < kSymClasses) {
-        int any = 0;
-        for (int m = 0; m < 8; ++m) {
-            const int j = sMem[tid][m];
-            if (j >= 0)
-                for (int t = 0; t < 64; ++t) any |= sSrc[t][j] >= 0;
-        }
-        sList[tid] = any;
+    { // classes used by the block: four threads scan each target's slots
+        const int *row = sSrc[tid >> 2];
+        unsigned long long used = 0;
+        for (int j = tid & 3; j < kVSlots; j += 4)
+            if (row[j] >= 0) used |= 1ull << sSl[j];
+        if (used) atomicOr(&sUsed, used);
     }
     __syncthreads();
-    if (tid == 0) { // compact; the table lists classes by zero mask, keep where each mask ends
-        int n = 0;
-        for (int c = 0; c < kSymClasses; ++c) {
-            if (sList[c]) sList[n++] = c;
-            sZend[sRep[c] >> 16] = n;
-        }
-        int qa, qb;
-        sym_part_range(sList, sRep, n, parts, part, qa, qb);
-        sQa = qa;
-        sQb = qb;
-    }
+    if (tid < 64) sym_select_classes(sUsed, sRep, parts, part, lane, sList, sZend, &sQa, &sQb);
     __syncthreads();
     const int qa = sQa, qb = sQb; // this block's classes
     const int64_t ldmh = v.ldmh;
@@ -727,18 +726,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
         if (used) atomicOr(&sUsed, used);
     }
     __syncthreads();
-    if (tid == 0) {
-        int n = 0;
-        const unsigned long long used = sUsed;
-        for (int c = 0; c < kSymClasses; ++c) {
-            if ((used >> c) & 1) sList[n++] = c;
-            sZend[sRep[c] >> 16] = n;
-        }
-        int qa, qb;
-        sym_part_range(sList, sRep, n, parts, part, qa, qb);
-        sQa = qa;
-        sQb = qb;
-    }
+    if (tid < 64) sym_select_classes(sUsed, sRep, parts, part, lane, sList, sZend, &sQa, &sQb);
     __syncthreads();
     const int qa = sQa, qb = sQb;
     const int64_t ldmh = v.ldmh;
