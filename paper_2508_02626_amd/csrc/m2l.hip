@@ -421,6 +421,72 @@ template <int Z, typename T> __device__ inline void wht8z(T (&h)[8])
             }
 }
 
+// Block set-up shared by the sign-class kernels.  The loads are issued in
+// batches (row and column indices, then their D addresses and the octant), so
+// that the set-up costs a few memory round trips rather than one per entry.
+// Returns the thread's target (-1 for an empty slot), or kNoTargets when the
+// tile has none (the whole block then returns).  Fills hb (D address of the
+// lane's row in each of the MTW row tiles from R0 on), sTg, sHo (D address of each
+// column), soct and clears sUsed.
+constexpr int kNoTargets = -2;
+template <int MTW, int KS, int R0 = 0>
+__device__ inline int sym_setup_tile(const PlanView &v, const OrderTables &tb, int tile, int tid, int col, int (&hb)[MTW],
+                                     int *sTg, int (*sHo)[KS], int *soct, unsigned long long *sUsed)
+{
+    constexpr int NT = 256, NHO = (4 * KS + NT - 1) / NT;
+    const auto t_hoff = gptr(tb.hoff), t_srow = gptr(tb.srow), t_scol = gptr(tb.scol);
+    const auto mtg = gptr(v.m2l_tgt) + (int64_t)tile * kM2LSlots;
+    const int wave = tid >> 6;
+    const int tgt = mtg[wave * 16 + col], tg64 = mtg[tid & 63];
+    int rowi[MTW], coli[NHO];
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) rowi[mt] = t_srow[16 * (R0 + mt) + col];
+#pragma unroll
+    for (int i = 0; i < NHO; ++i) {
+        const int e = tid + NT * i < 4 * KS ? tid + NT * i : 0, g = e / KS, ks = e - g * KS;
+        coli[i] = t_scol[4 * ks + g];
+    }
+    if (!__syncthreads_or(tgt >= 0)) return kNoTargets;
+    const int oct = (int)(gptr(v.morton)[max(tgt, 0)] & 7);
+    int hov[NHO];
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) hb[mt] = t_hoff[max(rowi[mt], 0)];
+#pragma unroll
+    for (int i = 0; i < NHO; ++i) hov[i] = t_hoff[max(coli[i], 0)];
+    if (tid < 64) sTg[tid] = tg64;
+    if (tid == 0) *sUsed = 0;
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) hb[mt] = rowi[mt] >= 0 ? hb[mt] : 0;
+#pragma unroll
+    for (int i = 0; i < NHO; ++i) {
+        const int e = tid + NT * i, g = e / KS, ks = e - g * KS;
+        if (e < 4 * KS) sHo[g][ks] = coli[i] >= 0 ? hov[i] : 0;
+    }
+    if (tgt >= 0) *soct = oct;
+    __syncthreads();
+    return tgt;
+}
+
+// The octant's class table: members, representative | zero mask, and the
+// class of each V slot.
+__device__ inline void sym_stage_classes(const OrderTables &tb, int oct, int tid, int (*sMem)[8], int *sRep, int *sSl)
+{
+    constexpr int NT = 256, NM = (kSymClasses * 8 + NT - 1) / NT;
+    const auto t_smem = gptr(tb.smem) + oct * kSymClasses * 8;
+    int mv[NM];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) mv[i] = t_smem[tid + NT * i < kSymClasses * 8 ? tid + NT * i : 0];
+    const int rv = gptr(tb.srep)[oct * kSymClasses + (tid < kSymClasses ? tid : 0)];
+    const int sv = gptr(tb.sslot)[oct * kVSlots + (tid < kVSlots ? tid : 0)];
+#pragma unroll
+    for (int i = 0; i < NM; ++i) {
+        const int e = tid + NT * i;
+        if (e < kSymClasses * 8) sMem[e >> 3][e & 7] = mv[i];
+    }
+    if (tid < kSymClasses) sRep[tid] = rv;
+    if (tid < kVSlots) sSl[tid] = sv;
+}
+
 template <int P, typename T>
 __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
 {
@@ -457,33 +523,26 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
     const int parts = v.m2l_parts;
     const int rb = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]), tile = rb / parts, part = rb - tile * parts;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
-    const int tgt = v.m2l_tgt[tile * kM2LSlots + wave * 16 + col];
-    if (!__syncthreads_or(tgt >= 0)) return;
-    if (tgt >= 0) soct = (int)(v.morton[tgt] & 7);
-    if (tid < 64) sTg[tid] = v.m2l_tgt[tile * kM2LSlots + tid];
-    if (tid == 0) sUsed = 0;
     const OrderTables &tb = *v.tab;
-    for (int e = tid; e < 4 * KS; e += NT) {
-        const int g = e / KS, ks = e - g * KS, a = gptr(tb.scol)[4 * ks + g];
-        sHo[g][ks] = a >= 0 ? gptr(tb.hoff)[a] : 0;
-    }
     int hb[MTW];
-#pragma unroll
-    for (int mt = 0; mt < MTW; ++mt) {
-        const int b = gptr(tb.srow)[16 * mt + col];
-        hb[mt] = b >= 0 ? gptr(tb.hoff)[b] : 0;
-    }
-    __syncthreads();
+    const int tgt = sym_setup_tile<MTW, KS>(v, tb, tile, tid, col, hb, sTg, sHo, &soct, &sUsed);
+    if (tgt == kNoTargets) return;
     {
+        // the targets' slot rows: every load issued before the first is used
         const auto vs = gptr(v.vslot);
-        for (int e = tid; e < 64 * kVSlots; e += NT) {
-            const int t = e / kVSlots, j = e - t * kVSlots, g = sTg[t];
-            sSrc[t][j] = g >= 0 ? vs[(int64_t)g * kVSlots + j] : -1;
+        constexpr int NE = 64 * kVSlots, PER = (NE + NT - 1) / NT;
+        int val[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + NT * i < NE ? tid + NT * i : NE - 1, t = e / kVSlots, j = e - t * kVSlots;
+            val[i] = vs[(int64_t)max(sTg[t], 0) * kVSlots + j];
         }
-        for (int e = tid; e < kSymClasses * 8; e += NT)
-            sMem[e >> 3][e & 7] = gptr(tb.smem)[soct * kSymClasses * 8 + e];
-        if (tid < kSymClasses) sRep[tid] = gptr(tb.srep)[soct * kSymClasses + tid];
-        if (tid < kVSlots) sSl[tid] = gptr(tb.sslot)[soct * kVSlots + tid];
+        sym_stage_classes(tb, soct, tid, sMem, sRep, sSl);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + NT * i, t = e / kVSlots, j = e - t * kVSlots;
+            if (e < NE) sSrc[t][j] = sTg[t] >= 0 ? val[i] : -1;
+        }
     }
     __syncthreads();
     { // classes used by the block: four threads scan each target's slots
@@ -687,6 +746,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     __shared__ int sRep[kSymClasses];
     __shared__ int sMem[kSymClasses][8];
     __shared__ int sZend[8];
+    __shared__ int sSl[kVSlots];
     __shared__ unsigned long long sUsed;
     __shared__ int sQa, sQb, soct;
 
@@ -695,34 +755,30 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     const int parts = v.m2l_parts;
     const int rb = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]), tile = rb / parts, part = rb - tile * parts;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
-    const int tgt = v.m2l_tgt[tile * kM2LSlots + wave * 16 + col];
-    if (!__syncthreads_or(tgt >= 0)) return;
-    if (tgt >= 0) soct = (int)(v.morton[tgt] & 7);
-    if (tid < 64) sTg[tid] = v.m2l_tgt[tile * kM2LSlots + tid];
-    if (tid == 0) sUsed = 0;
     const OrderTables &tb = *v.tab;
-    for (int e = tid; e < 4 * KS; e += NT) {
-        const int g = e / KS, ks = e - g * KS, a = gptr(tb.scol)[4 * ks + g];
-        sHo[g][ks] = a >= 0 ? gptr(tb.hoff)[a] : 0;
-    }
     int hb[MTW];
-#pragma unroll
-    for (int mt = 0; mt < MTW; ++mt) {
-        const int b = gptr(tb.srow)[16 * (R0 + mt) + col];
-        hb[mt] = b >= 0 ? gptr(tb.hoff)[b] : 0;
-    }
-    __syncthreads();
+    const int tgt = sym_setup_tile<MTW, KS, R0>(v, tb, tile, tid, col, hb, sTg, sHo, &soct, &sUsed);
+    if (tgt == kNoTargets) return;
     const auto vs = gptr(v.vslot);
     {
-        for (int e = tid; e < kSymClasses * 8; e += NT)
-            sMem[e >> 3][e & 7] = gptr(tb.smem)[soct * kSymClasses * 8 + e];
-        if (tid < kSymClasses) sRep[tid] = gptr(tb.srep)[soct * kSymClasses + tid];
         // classes used by the block: four threads scan each target's slots
+        // (all loads issued before the first is used)
+        constexpr int PER = (kVSlots + 3) / 4;
         const int g = sTg[tid >> 2];
+        int sv[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int j = (tid & 3) + 4 * i < kVSlots ? (tid & 3) + 4 * i : kVSlots - 1;
+            sv[i] = vs[(int64_t)max(g, 0) * kVSlots + j];
+        }
+        sym_stage_classes(tb, soct, tid, sMem, sRep, sSl);
+        __syncthreads();
         unsigned long long used = 0;
-        if (g >= 0)
-            for (int j = tid & 3; j < kVSlots; j += 4)
-                if (vs[(int64_t)g * kVSlots + j] >= 0) used |= 1ull << gptr(tb.sslot)[soct * kVSlots + j];
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int j = (tid & 3) + 4 * i;
+            if (g >= 0 && j < kVSlots && sv[i] >= 0) used |= 1ull << sSl[j];
+        }
         if (used) atomicOr(&sUsed, used);
     }
     __syncthreads();
