@@ -86,8 +86,11 @@ void fmm_default_options(fmm_options_t *opt);
  *   alloc      allocator, or NULL for hipMallocAsync on `stream`
  *   stream     HIP stream for all device work
  *   out        receives the plan handle on success (untouched on failure)
- * Synchronises `stream` to learn tree and list sizes; returns FMM_EINVAL for
- * invalid arguments or non-finite coordinates, FMM_EUNSUPPORTED when the
+ * Waits once for `stream` to learn tree and list sizes (the points have been
+ * read by then); the last build steps are still enqueued on `stream` when the
+ * call returns: later work on `stream` follows them, and evaluations and
+ * exports on other streams wait for them (an event of the plan).  Returns
+ * FMM_EINVAL for invalid arguments or non-finite coordinates, FMM_EUNSUPPORTED when the
  * tree has so many boxes that its folded multipoles (order >= 6: boxes + 1
  * rows of 16 ceil(k / 4) doubles, k the M2L k-steps, 24 at order 8) reach
  * 4 GiB.

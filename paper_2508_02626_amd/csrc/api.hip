@@ -213,6 +213,9 @@ struct fmm_plan_s {
     const OrderTables *tab = nullptr;
     PlanView view{};
     PlanView *view_dev = nullptr;
+    // recorded on the build stream after the last build step: work on other
+    // streams (evaluations, exports) waits for it
+    hipEvent_t built = nullptr;
     BoxArrays bx{};
     int64_t *off[4] = {nullptr, nullptr, nullptr, nullptr};
     int32_t *src[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -582,7 +585,10 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     HIPCHK(hipMemcpyAsync(P->view_dev, &v, sizeof(PlanView), hipMemcpyHostToDevice, s));
     HIPCHK(hipGetLastError());
     P->release_temps();
-    HIPCHK(hipStreamSynchronize(s));
+    // no wait for the rest of the build: later work on this stream follows it,
+    // work on other streams waits for this event
+    HIPCHK(hipEventCreateWithFlags(&P->built, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(P->built, s));
     return 0;
 }
 
@@ -712,7 +718,15 @@ extern "C" int fmm_plan_batch(int32_t count, const double *const *xyz_dev, const
                 while (i < cur && !first_bad.compare_exchange_weak(cur, i)) {}
                 break;
             }
-            out[i]->stream = stream; // built and synchronised: later frees are ordered on the caller's stream
+            // complete before it changes streams: later frees are ordered on the caller's stream
+            if (ws != stream && hipStreamSynchronize(ws) != hipSuccess) {
+                rcs[i] = FMM_EDEVICE;
+                msgs[i] = "stream synchronisation failed";
+                int cur = first_bad.load();
+                while (i < cur && !first_bad.compare_exchange_weak(cur, i)) {}
+                break;
+            }
+            out[i]->stream = stream;
         }
         if (ws != stream) side_release(dev, ws, e1, e2);
     };
@@ -724,6 +738,7 @@ extern "C" int fmm_plan_batch(int32_t count, const double *const *xyz_dev, const
         for (auto &t : pool) t.join();
     }
     (void)hipEventDestroy(ready);
+    if (nthr == 1) HIPCHK(hipStreamSynchronize(stream)); // every plan complete on return
     int bad = first_bad.load();
     if (bad < count) {
         for (int i = 0; i < count; ++i)
@@ -957,6 +972,7 @@ extern "C" int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_de
     g_err.clear();
     if (!plan || !q_dev || !phi_dev) return fail(FMM_EINVAL, "null pointer argument");
     fmm_plan_s *P = plan;
+    if (stream != P->stream) HIPCHK(hipStreamWaitEvent(stream, P->built, 0));
     PlanView v = P->view;
     v.q_in = q_dev;
     v.phi_out = phi_dev;
@@ -979,6 +995,8 @@ extern "C" int fmm_evaluate_batch(fmm_plan_t const *plans, const double *const *
     if (count == 0) return FMM_OK;
     for (int i = 0; i < count; ++i)
         if (!plans[i] || !q_dev[i] || !phi_dev[i]) return fail(FMM_EINVAL, "null entry in batch");
+    for (int i = 0; i < count; ++i)
+        if (stream != plans[i]->stream) HIPCHK(hipStreamWaitEvent(stream, plans[i]->built, 0));
     // order the plans by (order, mixed M2L) so that equal orders are contiguous
     std::vector<int> idx(count);
     for (int i = 0; i < count; ++i) idx[i] = i;
@@ -1060,6 +1078,7 @@ extern "C" int fmm_plan_export_tree(fmm_plan_t plan, hipStream_t stream, double 
 {
     if (!plan) return fail(FMM_EINVAL, "null plan");
     fmm_plan_s *P = plan;
+    HIPCHK(hipEventSynchronize(P->built));
     HIPCHK(hipStreamSynchronize(stream));
     const int nb = P->nboxes, n = P->n;
     if (!P->src[1]) { // the V list proper is built on first request (evaluation reads the slot rows)
@@ -1108,6 +1127,7 @@ extern "C" int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, d
 {
     if (!plan) return fail(FMM_EINVAL, "null plan");
     fmm_plan_s *P = plan;
+    HIPCHK(hipEventSynchronize(P->built));
     HIPCHK(hipStreamSynchronize(stream));
     const int nb = P->nboxes, nc = P->nc, ldm = P->ldm;
     std::vector<int32_t> lev(nb);
@@ -1208,6 +1228,7 @@ extern "C" int fmm_plan_destroy(fmm_plan_t plan)
     plan->uses.clear();
     plan->release_all();
     plan->release_side();
+    if (plan->built) (void)hipEventDestroy(plan->built);
     if (dev != plan->device) (void)hipSetDevice(dev);
     delete plan;
     return FMM_OK;
