@@ -123,12 +123,17 @@ __host__ __device__ constexpr int sym_ksteps(int p)
 // orders whose M2L runs on sign classes (fewer matrix-core products from p = 6 on)
 __host__ __device__ constexpr bool m2l_sym(int p) { return p >= 6; }
 // blocks per M2L tile of 64 targets at sign-class orders: the tile's classes
-// are split into this many parts of about equal matrix-core work, each block
+// are split into this many contiguous parts by matrix-core work, each block
 // writing its own partial sums.  Two: more, shorter blocks did not shorten the
-// launch's tail as much as their per-block set-up (the targets' slot rows)
-// cost (uniform 10^6 points, p = 8: 1.03 ms with two, 1.17 with four, 1.29
-// with eight).
+// launch's tail as much as their per-block set-up cost (uniform 10^6 points,
+// p = 8, equal parts: 0.97 ms with two, 0.96 with three, 1.07 with four; on a
+// Plummer tree three were slower than two).
 __host__ __device__ constexpr int sym_m2l_parts(int p) { return m2l_sym(p) ? 2 : 1; }
+// share (percent) of a tile's matrix-core work in its first part; the launch
+// runs the first parts before the others (longest first), so that its end is
+// made of the shorter blocks (uniform 10^6 points, p = 8, FP64: about 6%
+// faster at 68-74 than at 50-56, slower again from 78)
+constexpr int kSymFirstPart = 72;
 // launches the row tiles of an order >= 12 sign-class M2L are split over (at
 // most 9 row tiles of accumulators per wavefront)
 __host__ __device__ constexpr int sym_row_parts(int p) { return p >= 12 ? (sym_row_tiles(p) + 8) / 9 : 1; }

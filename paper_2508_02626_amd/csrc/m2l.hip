@@ -380,9 +380,11 @@ template <typename T> __device__ inline void wht8(T (&h)[8])
 // targets, list them in class order (sList), note where each zero mask's
 // classes end in the list (sZend; the table orders classes by zero mask) and
 // pick the range [sQa, sQb) of part `part` when the list is split into
-// `parts` contiguous ranges of about equal matrix-core work (a class with z
-// zero axes runs 1 / 2^z of the row-tile / k-step products): a class belongs
-// to the part that holds the midpoint of its weight.  Lane c handles class c.
+// `parts` contiguous ranges of matrix-core work (a class with z zero axes
+// runs 1 / 2^z of the row-tile / k-step products), the first holding
+// kSymFirstPart % of it and the others equal shares of the rest: a class
+// belongs to the part that holds the midpoint of its weight.  Lane c handles
+// class c.
 __device__ inline void sym_select_classes(unsigned long long used, const int *rep, int parts, int part, int lane,
                                           int *list, int *zend, int *qa, int *qb)
 {
@@ -396,7 +398,11 @@ __device__ inline void sym_select_classes(unsigned long long used, const int *re
     const unsigned long long b0 = __ballot(u && pz == 0), b1 = __ballot(u && pz == 1), b2 = __ballot(u && pz == 2);
     const int W = 4 * __popcll(b0) + 2 * __popcll(b1) + __popcll(b2);
     const int cw = 4 * __popcll(b0 & below) + 2 * __popcll(b1 & below) + __popcll(b2 & below);
-    const int pt = W > 0 ? min(parts - 1, (2 * cw + w) * parts / (2 * W)) : 0;
+    // part 0 ends at kSymFirstPart % of the weight, the others share the rest
+    int pt = 0;
+    for (int q = 0; q + 1 < parts; ++q)
+        pt += (int64_t)(2 * cw + w) * 100 * (parts - 1) >=
+              (int64_t)2 * W * (kSymFirstPart * (parts - 1) + q * (100 - kSymFirstPart));
     const unsigned long long lo = __ballot(u && pt < part), hi = __ballot(u && pt <= part);
     if (lane == 0) {
         *qa = __popcll(lo);
@@ -429,6 +435,25 @@ template <int Z, typename T> __device__ inline void wht8z(T (&h)[8])
 // lane's row in each of the MTW row tiles from R0 on), sTg, sHo (D address of each
 // column), soct and clears sUsed.
 constexpr int kNoTargets = -2;
+
+// Tile and part of block i of n = tiles x parts: each XCD gets a contiguous
+// range of (tile, part) items (as xcd_remap) and runs the range's first parts
+// (the longest) before its other parts, so that the end of the launch is made
+// of the shorter blocks.
+__device__ inline void sym_block(int i, int n, int parts, int &tile, int &part)
+{
+    const int x = i % kXCDs, y = i / kXCDs, q = n / kXCDs, r = n % kXCDs;
+    const int b0 = x * q + (x < r ? x : r), cnt = q + (x < r ? 1 : 0);
+    int yy = y, rb = b0;
+    for (int p = 0; p < parts; ++p) {
+        const int fp = b0 + ((p - b0 % parts) + parts) % parts;
+        const int np = fp < b0 + cnt ? (b0 + cnt - 1 - fp) / parts + 1 : 0;
+        if (yy < np) { rb = fp + parts * yy; break; }
+        yy -= np;
+    }
+    tile = rb / parts;
+    part = rb - tile * parts;
+}
 template <int MTW, int KS, int R0 = 0>
 __device__ inline int sym_setup_tile(const PlanView &v, const OrderTables &tb, int tile, int tid, int col, int (&hb)[MTW],
                                      int *sTg, int (*sHo)[KS], int *soct, unsigned long long *sUsed)
@@ -521,7 +546,8 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
     // m2l_parts blocks per tile, each taking a part of the tile's classes
     // (more, shorter blocks: less idle time at the end of the launch)
     const int parts = v.m2l_parts;
-    const int rb = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]), tile = rb / parts, part = rb - tile * parts;
+    int tile, part;
+    sym_block(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k], parts, tile, part);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
     const OrderTables &tb = *v.tab;
     int hb[MTW];
@@ -753,7 +779,8 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int parts = v.m2l_parts;
-    const int rb = xcd_remap(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k]), tile = rb / parts, part = rb - tile * parts;
+    int tile, part;
+    sym_block(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k], parts, tile, part);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
     const OrderTables &tb = *v.tab;
     int hb[MTW];
