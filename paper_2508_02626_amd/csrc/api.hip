@@ -897,7 +897,7 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     // pass stops at level 2; fmm_plan_export_expansions completes it on demand.
     for (auto &r : runs)
         for (int l = maxdepth - 1; l >= 2; --l)
-            launch_m2mh(V + r.first,
+            launch_m2mh(P[r.first]->p, V + r.first,
                         sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldmh / 16); }), l, s);
     // parents' FP32 operands (mixed M2L) and full multipoles (M2P sources)
     for (auto &r : runs) {
@@ -945,7 +945,7 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     T.begin(7);
     for (auto &r : runs)
         for (int l = 2; l < maxdepth; ++l)
-            launch_l2lh(V + r.first,
+            launch_l2lh(P[r.first]->p, V + r.first,
                         sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldh / 16); }), l, s);
     T.end();
     T.begin(6);

@@ -253,44 +253,77 @@ __global__ __launch_bounds__(512) void k_translate(const PlanView *V, Bases B, i
     }
 }
 
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// Child of `parent` in octant o, or -1: the children are consecutive and their
+// Morton codes are loaded together (a non-leaf has at least one child).
+__device__ inline int child_in_octant(const PlanView &v, int parent, int o)
+{
+    if (parent < 0) return -1;
+    const int cb = gptr(v.child_begin)[parent], ncd = gptr(v.nchild)[parent];
+    uint64_t mk[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) mk[i] = gptr(v.morton)[cb + (i < ncd ? i : ncd - 1)];
+    int ch = -1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (i < ncd && (int)(mk[i] & 7) == o) ch = cb + i;
+    return ch;
+}
+
+// acc += A^t x for one 16-row tile: A [K][lda] in memory (rows a, column
+// bA), x the lane's source vector; k-steps of four in batches of 16 whose
+// loads are all issued before the first product.  Entries a >= K and
+// lanes without a source (xok false) contribute zero.
+template <int K>
+__device__ inline void mfma_rows(const double *A, int lda, int bA, bool aok, const double *x, bool xok, int kq,
+                                 double4_t &acc)
+{
+    constexpr int KS = (K + 3) / 4, CHK = 16;
+#pragma unroll
+    for (int s0 = 0; s0 < KS; s0 += CHK) {
+        double av[CHK], bv[CHK];
+#pragma unroll
+        for (int t = 0; t < CHK; ++t) {
+            if (s0 + t >= KS) break;
+            const int a = 4 * (s0 + t) + kq, ac = a < K ? a : K - 1;
+            const double ta = gptr(A)[(int64_t)ac * lda + bA], tx = gptr(x)[ac];
+            av[t] = aok && a < K ? ta : 0.0;
+            bv[t] = xok && a < K ? tx : 0.0;
+        }
+#pragma unroll
+        for (int t = 0; t < CHK; ++t) {
+            if (s0 + t >= KS) break;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
+        }
+    }
+}
+
 // ---------------- M2M on the folded components ----------------
 // The far field of a multipole, hence its translation truncated at degree p,
 // depends only on its folded vector: Mh(parent) = sum_o TM_o^t Mh(child_o),
 // TM_o a (folded positions)^2 matrix.  A block computes 16 folded positions of
 // 16 parents of one level, one wavefront per child octant (16x16x4 FP64 MFMA),
 // the eight partial tiles summed in octant order.
+template <int P>
 __global__ __launch_bounds__(512) void k_m2mh(const PlanView *V, Bases B, int level)
 {
-    typedef double double4_t __attribute__((ext_vector_type(4)));
     __shared__ double4_t red[8][64];
+    constexpr int LD = folded_ld(P), MT = LD / 16;
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int item = blockIdx.x - B.b[k];
-    const int ld = v.ldmh, MT = ld / 16, g = item / MT, mt = item - g * MT;
+    const int ld = LD, g = item / MT, mt = item - g * MT;
     const int o = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63, col = lane & 15, kq = lane >> 4;
     const int lb = v.lvl_nonleaf_off[level], le = v.lvl_nonleaf_off[level + 1];
     const int pidx = lb + g * kPG + col;
     const int parent = pidx < le ? v.lvl_nonleaf[pidx] : -1;
-    int ch = -1; // child of this lane's parent in octant o
-    if (parent >= 0) {
-        const int cb = v.child_begin[parent], ncd = v.nchild[parent];
-        for (int i = 0; i < ncd; ++i)
-            if ((int)(v.morton[cb + i] & 7) == o) ch = cb + i;
-    }
+    const int ch = child_in_octant(v, parent, o); // child of this lane's parent in octant o
     double4_t acc = {0, 0, 0, 0};
-    if (__any(ch >= 0)) {
-        const auto T = gptr(v.tab->TM + (int64_t)o * ld * ld);
-        const auto X = gptr(v.Mh + (int64_t)(ch >= 0 ? ch : 0) * ld);
-        const int bA = mt * 16 + col;
-#pragma unroll 8
-        for (int kk = 0; kk < ld; kk += 4) {
-            const int a = kk + kq;
-            const double av = T[(int64_t)a * ld + bA];
-            const double bv = ch >= 0 ? X[a] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-        }
-    }
+    if (__any(ch >= 0))
+        mfma_rows<LD>(v.tab->TM + (int64_t)o * ld * ld, ld, mt * 16 + col, true,
+                      v.Mh + (int64_t)(ch >= 0 ? ch : 0) * ld, ch >= 0, kq, acc);
     red[o][lane] = acc;
     __syncthreads();
     if (o != 0 || parent < 0) return;
@@ -332,36 +365,25 @@ __global__ __launch_bounds__(256) void k_parent_mh(const PlanView *V, Bases B, i
 // Lh(child) += GH_o^t Lh(parent): a block computes 16 rows of 16 parents of
 // one level, one wavefront per child octant (16x16x4 FP64 MFMA), and adds the
 // product of octant o to the octant-o children.
+template <int P>
 __global__ __launch_bounds__(512) void k_l2lh(const PlanView *V, Bases B, int level)
 {
-    typedef double double4_t __attribute__((ext_vector_type(4)));
+    constexpr int NH = nharm(P), LDH = pad16(NH), MT = LDH / 16;
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int item = blockIdx.x - B.b[k];
-    const int nh = v.nh, ldh = v.ldh, MT = ldh / 16, g = item / MT, mt = item - g * MT;
+    const int nh = NH, ldh = LDH, g = item / MT, mt = item - g * MT;
     const int o = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63, col = lane & 15, kq = lane >> 4;
     const int lb = v.lvl_nonleaf_off[level], le = v.lvl_nonleaf_off[level + 1];
     const int pidx = lb + g * kPG + col;
     const int parent = pidx < le ? v.lvl_nonleaf[pidx] : -1;
-    int ch = -1; // child of this lane's parent in octant o
-    if (parent >= 0) {
-        const int cb = v.child_begin[parent], ncd = v.nchild[parent];
-        for (int i = 0; i < ncd; ++i)
-            if ((int)(v.morton[cb + i] & 7) == o) ch = cb + i;
-    }
+    const int ch = child_in_octant(v, parent, o); // child of this lane's parent in octant o
     if (!__any(ch >= 0)) return;
-    const auto T = gptr(v.tab->GH + (int64_t)o * nh * nh);
     const int bA = mt * 16 + col;
-    const auto X = gptr(v.Lh + (int64_t)(parent >= 0 ? parent : 0) * ldh);
     double4_t acc = {0, 0, 0, 0};
-#pragma unroll 8
-    for (int kk = 0; kk < nh; kk += 4) {
-        const int a = kk + kq;
-        const double av = (bA < nh && a < nh) ? T[(int64_t)a * nh + bA] : 0.0;
-        const double bv = (parent >= 0 && a < nh) ? X[a] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
+    mfma_rows<NH>(v.tab->GH + (int64_t)o * nh * nh, nh, bA < nh ? bA : nh - 1, bA < nh,
+                  v.Lh + (int64_t)(parent >= 0 ? parent : 0) * ldh, parent >= 0, kq, acc);
     if (ch < 0) return;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -912,9 +934,9 @@ void launch_unfold(int p, const PlanView *V, const Bases &B, int leaves_only, hi
 {
     if (nblk(B)) DISPATCH_P(p, k_unfold, <<<nblk(B), 256, 0, s>>>(V, B, leaves_only));
 }
-void launch_m2mh(const PlanView *V, const Bases &B, int level, hipStream_t s)
+void launch_m2mh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s)
 {
-    if (nblk(B)) k_m2mh<<<nblk(B), 512, 0, s>>>(V, B, level);
+    if (nblk(B)) DISPATCH_P(p, k_m2mh, <<<nblk(B), 512, 0, s>>>(V, B, level));
 }
 void launch_parent_mh(const PlanView *V, const Bases &B, int full, hipStream_t s)
 {
@@ -924,9 +946,9 @@ void launch_lh_init(const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (nblk(B)) k_lh_init<<<nblk(B), 256, 0, s>>>(V, B);
 }
-void launch_l2lh(const PlanView *V, const Bases &B, int level, hipStream_t s)
+void launch_l2lh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s)
 {
-    if (nblk(B)) k_l2lh<<<nblk(B), 512, 0, s>>>(V, B, level);
+    if (nblk(B)) DISPATCH_P(p, k_l2lh, <<<nblk(B), 512, 0, s>>>(V, B, level));
 }
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {
