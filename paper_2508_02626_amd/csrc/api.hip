@@ -764,7 +764,7 @@ StagePlan stage_blocks(const fmm_plan_s *P)
     sp.m2l = P->nslots / kM2LSlots * P->m2l_parts; // sign classes: m2l_parts blocks per tile
     sp.p2l = P->nxtgt;
     sp.unfold = (int)ceil_div(P->nboxes, kRemapBoxes);
-    sp.far = P->nleaves;
+    sp.far = (int)ceil_div(P->nleaves, 2); // two leaves per block
     const int split = p2p_split(P->nleaves);
     sp.p2p[0] = (int)ceil_div(split, 4);
     sp.p2p[1] = (int)ceil_div(P->nleaves - split, 4);
@@ -938,7 +938,7 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     for (auto &r : runs)
         launch_p2l_transform(V + r.first, sub(r.first, r.second, [](const fmm_plan_s *p) {
             return (int)ceil_div(p->nxtgt, 16) * (p->ldh / 16); }), s);
-    // complete Lh rows (zero where nothing arrived, second half of the sign classes)
+    // complete Lh rows (zero where nothing arrived, plus the second part of the sign classes)
     launch_lh_init(V, make([](const fmm_plan_s *p) { return (int)ceil_div(p->nboxes, 4); }, all), s);
     T.end();
     // L2L on the harmonic components, then full local expansions at the leaves

@@ -16,7 +16,7 @@ void launch_parent_mh(const PlanView *V, const Bases &B, int full, hipStream_t s
 void launch_unfold(int p, const PlanView *V, const Bases &B, int leaves_only, hipStream_t s); // kRemapBoxes boxes/block
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 X target/block
 void launch_p2l_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 X targets x 16 rows/block
-void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block (L2P + output)
+void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 2 leaves/block (L2P + output)
 void launch_m2p(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block (W lists)
 // P2P runs in two parts (leaves [0, split) and [split, nleaves)), each
 // overlapping a latency-bound phase of the far field

@@ -601,31 +601,38 @@ __device__ inline void eval_poly(const double *c, double x, double y, double z, 
     }
 }
 
+// Two leaves per wavefront, one per 32-lane half (leaves hold a few tens of
+// particles: one leaf per wavefront left most lanes idle), each half with its
+// leaf's coefficients in LDS.
 template <int P>
 __global__ __launch_bounds__(64) void k_far(const PlanView *V, Bases B)
 {
     constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
-    __shared__ double cl[NC];
+    __shared__ double cl[2][NC];
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
-    const int box = v.leaves[blockIdx.x - B.b[k]];
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x, half = lane >> 5, hl = lane & 31;
+    const int l0 = 2 * (blockIdx.x - B.b[k]);
+    const int li = l0 + half;
+    const bool valid = li < v.nleaves;
+    const int box = v.leaves[valid ? li : l0];
     const OrderTables &t = *v.tab;
     double cen[3], h;
     box_geom(v, box, cen, h);
-    const bool loc = v.level[box] >= 2;
+    const bool loc = valid && v.level[box] >= 2;
     if (loc)
-        for (int a = lane; a < NC; a += 64) cl[a] = v.L[(int64_t)box * v.ldm + a] * t.inv_fact[a];
+        for (int a = hl; a < NC; a += 32) cl[half][a] = v.L[(int64_t)box * v.ldm + a] * t.inv_fact[a];
     __syncthreads();
-    const int f = v.first[box], cnt = v.count[box];
-    for (int s = 0; s < cnt; s += 64) {
-        int i = f + s + lane;
-        bool act = s + lane < cnt;
+    const int f = v.first[box], cnt = valid ? v.count[box] : 0;
+    const int cmax = max(cnt, __shfl_xor(cnt, 32)); // both halves run the longer leaf's chunks
+    for (int s = 0; s < cmax; s += 32) {
+        int i = f + s + hl;
+        bool act = s + hl < cnt;
         double x = act ? v.xs[i] : cen[0], y = act ? v.ys[i] : cen[1], z = act ? v.zs[i] : cen[2];
         double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
         if (loc) {
             double ih = 1.0 / h, f0, fx, fy, fz;
-            eval_poly<P>(cl, (x - cen[0]) * ih, (y - cen[1]) * ih, (z - cen[2]) * ih, f0, fx, fy, fz);
+            eval_poly<P>(cl[half], (x - cen[0]) * ih, (y - cen[1]) * ih, (z - cen[2]) * ih, f0, fx, fy, fz);
             phi = f0 * ih;
             double ih2 = ih * ih;
             gx = fx * ih2; gy = fy * ih2; gz = fz * ih2;
