@@ -343,9 +343,10 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
 // that the loads of one zero mask are fixed at compile time and the waits
 // count them) two vectors ahead, across class boundaries (all eight members
 // for the next class, whose mask is not known there).  m2l_parts blocks share
-// a tile, each running a contiguous part of its classes of about equal
-// matrix-core work; part i > 0 writes its partial sums to slice i - 1 of Lh2,
-// which the L2L initialisation adds in part order.
+// a tile, each running a contiguous part of its classes (the first with
+// kSymFirstPart % of the matrix-core work, dispatched before the others); part
+// i > 0 writes its partial sums to slice i - 1 of Lh2, which the L2L
+// initialisation adds in part order.
 template <int P> struct SymShape {
     static constexpr int RT = sym_row_tiles(P), KS = sym_ksteps(P);
     int rc[RT], kc[KS]; // parity class of each row tile and k-step

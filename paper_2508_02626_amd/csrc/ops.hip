@@ -6,8 +6,11 @@
 //        u = (x - c)/h; one wavefront per leaf, one lane per moment, so the
 //        per-box reduction is an in-lane sequential sum (deterministic); the
 //        fixed matrix P is then applied to 16 leaves at a time on MFMA.
-//   M2M  (Sec. 2.2) parent Mhat = sum over children of S_octant * child Mhat.
-//   L2L  (Sec. 2.5) child Lhat += G_octant * parent Lhat.
+//   M2M  (Sec. 2.2) parent Mhat = sum over children of S_octant * child Mhat,
+//        applied during evaluation to the folded components (TM_octant) and
+//        in full only to complete the expansions for export.
+//   L2L  (Sec. 2.5) child Lhat += G_octant * parent Lhat, applied to the
+//        harmonic components (GH_octant) before the leaves are unfolded.
 //   L2P / M2P (Sec. 3.2) share one evaluation routine (nested Horner with the
 //        gradient); M2P evaluates phi = |d| phi_M(d), d = y/|y|^2 (Eq. P2M_phi).
 //   P2L  (Sec. 2.4) Lhat_b += q d^b(1/|x|) at x = (c - x_i)/h, through inverse
@@ -16,6 +19,8 @@
 #include "ops.h"
 
 namespace fmm {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline void box_geom(const PlanView &v, int b, double cen[3], double &h)
 {
@@ -104,7 +109,6 @@ __global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
 // moments is visited.
 __global__ __launch_bounds__(64) void k_p2m_transform(const PlanView *V, Bases B)
 {
-    typedef double double4_t __attribute__((ext_vector_type(4)));
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int item = blockIdx.x - B.b[k];
@@ -194,7 +198,6 @@ constexpr int kPG = 16;
 template <int UP>
 __global__ __launch_bounds__(512) void k_translate(const PlanView *V, Bases B, int level)
 {
-    typedef double double4_t __attribute__((ext_vector_type(4)));
     __shared__ double4_t red[8][64]; // M2M: per-octant partial tiles
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
@@ -252,8 +255,6 @@ __global__ __launch_bounds__(512) void k_translate(const PlanView *V, Bases B, i
         v.M[(int64_t)parent * ldm + b] = sum[r]; // rows >= nc are zero
     }
 }
-
-typedef double double4_t __attribute__((ext_vector_type(4)));
 
 // Child of `parent` in octant o, or -1: the children are consecutive and their
 // Morton codes are loaded together (a non-leaf has at least one child).
@@ -530,7 +531,6 @@ __device__ inline int harm_degree(int c)
 
 __global__ __launch_bounds__(64) void k_p2l_transform(const PlanView *V, Bases B)
 {
-    typedef double double4_t __attribute__((ext_vector_type(4)));
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int item = blockIdx.x - B.b[k];
