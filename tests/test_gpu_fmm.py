@@ -221,6 +221,34 @@ def test_plan_batch_equals_single_plans():
     assert all(np.isfinite(o[0].cpu().numpy()).all() for o in outs)
 
 
+def test_plan_then_evaluate_on_another_stream():
+    """fmm_plan returns with its last build steps still enqueued on its stream;
+    an evaluation or export issued at once on another stream waits for them
+    and matches, bit for bit, the same work done on the build stream."""
+    import torch
+    from paper_2508_02626_amd import fmm
+    x, q = inputs.plummer(200_000, 5)
+    xd, qd = to_dev(x), to_dev(q)
+    side = torch.cuda.Stream()
+    for prec in ("fp64", "mixed"):
+        ref = fmm.Plan(xd, 8, leaf_size=64, precision=prec)
+        a, fa = ref.evaluate(qd)
+        tref = ref.export_tree()
+        ref.close()
+        pl = fmm.Plan(xd, 8, leaf_size=64, precision=prec)  # built on the current stream
+        with torch.cuda.stream(side):
+            b, fb = pl.evaluate(qd, stream=side)  # no synchronisation in between
+        side.synchronize()
+        assert np.array_equal(a.cpu().numpy(), b.cpu().numpy()), prec
+        assert np.array_equal(fa.cpu().numpy(), fb.cpu().numpy()), prec
+        pl.close()
+        pl = fmm.Plan(xd, 8, leaf_size=64, precision=prec)
+        g = pl.export_tree(stream=side)
+        for k in ("perm", "first", "count", "U_src", "V_src", "W_src", "X_src"):
+            assert np.array_equal(g[k], tref[k]), (prec, k)
+        pl.close()
+
+
 def test_full_size_uniform_sampled_against_direct():
     """1e6 points, depth 5, p = 8 (the benchmark workload), in the launch
     configuration the benchmark times: sampled targets against the direct sum,
