@@ -480,7 +480,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     } else {
         uniform_boxes(keys, n, P->D, nb, bx, lvl_dev, s);
     }
-    TreeArgs ta{bx, lvl_dev, P->D, nb};
+    TreeArgs ta{bx, lvl_dev, P->D, nb, P->uniform};
     int32_t *coll = P->temp<int32_t>(27ull * nb);
     int64_t *cnt[4], *flg[4], *pos[4];
     for (int w = 0; w < 4; ++w) { cnt[w] = P->temp<int64_t>(nb + 1); NOMEM(cnt[w]); }
@@ -1082,7 +1082,7 @@ extern "C" int fmm_plan_export_tree(fmm_plan_t plan, hipStream_t stream, double 
     HIPCHK(hipStreamSynchronize(stream));
     const int nb = P->nboxes, n = P->n;
     if (!P->src[1]) { // the V list proper is built on first request (evaluation reads the slot rows)
-        TreeArgs ta{P->bx, P->lvl_dev, P->D, nb};
+        TreeArgs ta{P->bx, P->lvl_dev, P->D, nb, P->uniform};
         int32_t *coll = nullptr;
         HIPCHK(hipMalloc((void **)&coll, sizeof(int32_t) * 27 * (size_t)nb));
         int32_t *v1 = P->own<int32_t>(P->nlist[1] ? P->nlist[1] : 1);

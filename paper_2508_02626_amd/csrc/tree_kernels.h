@@ -16,6 +16,7 @@ struct TreeArgs {
     BoxArrays bx;
     const int32_t *lvl_begin; // device [kMaxDepth + 2]
     int D, nboxes;
+    int uniform; // every level full: no coarser adjacent leaves, no W lists
 };
 
 void plan_init(const double *given_root, double *root_dev, int *bad, hipStream_t s);

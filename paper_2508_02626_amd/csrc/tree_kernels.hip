@@ -344,11 +344,15 @@ struct TreeView {
     BoxArrays bx;
     const int32_t *lvl_begin; // [kMaxDepth + 2]
     int D, nboxes;
+    int uniform; // every level full: all leaves on the last level
 };
 
 __device__ inline int find_box(const TreeView &t, int l, uint64_t code)
 {
     int lo = t.lvl_begin[l], hi = t.lvl_begin[l + 1];
+    // a level that holds all 8^l cells (every level of a uniform tree) is
+    // sorted by code with no gaps: the box is the level's start plus the code
+    if (l <= 10 && hi - lo == (1 << (3 * l))) return lo + (int)code;
     while (lo < hi) {
         int mid = (lo + hi) >> 1;
         if (t.bx.morton[mid] < code) lo = mid + 1; else hi = mid;
@@ -419,19 +423,39 @@ __global__ __launch_bounds__(256) void k_vlist(TreeView t, const int32_t *coll, 
         deinterleave(t.bx.morton[b], l, cb);
         const int oct = (int)(t.bx.morton[b] & 7);
         const int pb = t.bx.parent[b];
-        for (int base = 0; base < 27 * 8; base += 64) {
-            const int j = base + lane, i = j >> 3, k = j & 7;
+        // the four rounds' loads are issued together, one dependent level at
+        // a time (colleague, its children, their codes)
+        constexpr int R = (27 * 8 + 63) / 64;
+        int cc[R], ch[R], nc[R];
+        uint64_t md[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = (64 * r + lane) >> 3;
+            cc[r] = coll[27 * pb + (i < 27 ? i : 26)];
+            if (i >= 27) cc[r] = -1;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int c = cc[r] >= 0 ? cc[r] : 0;
+            nc[r] = t.bx.nchild[c];
+            ch[r] = t.bx.child_begin[c];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int k = (64 * r + lane) & 7;
+            ch[r] = (cc[r] >= 0 && k < nc[r]) ? ch[r] + k : -1;
+            md[r] = t.bx.morton[ch[r] >= 0 ? ch[r] : 0];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
             bool sel = false;
-            int d = -1, dx = 0, dy = 0, dz = 0;
-            if (i < 27) {
-                int c = coll[27 * pb + i];
-                if (c >= 0 && k < t.bx.nchild[c]) {
-                    d = t.bx.child_begin[c] + k;
-                    int cd[3];
-                    deinterleave(t.bx.morton[d], l, cd);
-                    dx = cd[0] - cb[0]; dy = cd[1] - cb[1]; dz = cd[2] - cb[2];
-                    sel = dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1;
-                }
+            const int d = ch[r];
+            int dx = 0, dy = 0, dz = 0;
+            if (d >= 0) {
+                int cd[3];
+                deinterleave(md[r], l, cd);
+                dx = cd[0] - cb[0]; dy = cd[1] - cb[1]; dz = cd[2] - cb[2];
+                sel = dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1;
             }
             const uint64_t m = __ballot(sel);
             if (sel && which) src[o + n + __popcll(m & lanes_below(lane))] = d;
@@ -602,7 +626,7 @@ __global__ __launch_bounds__(256) void k_uwlist(TreeView t, const int32_t *coll,
             wave_sync();
         }
     }
-    if (ok) {
+    if (ok && !t.uniform) { // (a uniform tree has all its leaves on one level)
         for (int a = t.bx.parent[b]; a >= 0; a = t.bx.parent[a]) {
             const int c = lane < 27 ? coll[27 * a + lane] : -1;
             const bool hit = c >= 0 && c != a && t.bx.nchild[c] == 0 && touches(cell_of(t, c), cb);
@@ -632,21 +656,21 @@ __global__ __launch_bounds__(256) void k_uwlist(TreeView t, const int32_t *coll,
 
 void colleagues(const TreeArgs &a, int32_t *coll, int64_t *zero, hipStream_t s)
 {
-    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes};
+    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
     k_colleagues<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, zero);
 }
 
 void vlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *cnt, const int64_t *off,
            int32_t *src, int32_t *vslot, hipStream_t s)
 {
-    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes};
+    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
     k_vlist<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, which, cnt, off, src, vslot);
 }
 
 void uwlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *ucnt, const int64_t *uoff,
             int32_t *usrc, int64_t *wcnt, const int64_t *woff, int32_t *wsrc, int64_t *xcnt, hipStream_t s)
 {
-    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes};
+    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
     k_uwlist<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, which, ucnt, uoff, usrc, wcnt, woff, wsrc, xcnt);
 }
 
