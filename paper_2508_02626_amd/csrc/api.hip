@@ -489,9 +489,13 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     int32_t *mtg = P->temp<int32_t>(nb);
     PlanSizes *sizes_dev = P->temp<PlanSizes>(1);
     NOMEM(coll); NOMEM(mscr); NOMEM(mtg); NOMEM(sizes_dev);
-    fill_i32(vslot, (int64_t)nb * kVSlots, -1, s);
-    colleagues(ta, coll, cnt[3], s);                        // also clears the X counts
-    vlist(ta, coll, 0, cnt[1], nullptr, nullptr, vslot, s); // V counts and M2L slot rows
+    colleagues(ta, coll, cnt[3], s); // also clears the X counts
+    if (P->uniform) {
+        vslot_uniform(ta, cnt[1], vslot, s); // V counts and whole M2L slot rows
+    } else {
+        fill_i32(vslot, (int64_t)nb * kVSlots, -1, s);
+        vlist(ta, coll, 0, cnt[1], nullptr, nullptr, vslot, s); // V counts and M2L slot rows
+    }
     uwlist(ta, coll, 0, cnt[0], nullptr, nullptr, cnt[2], nullptr, nullptr, cnt[3], s);
     flags(bx, nb, cnt[3], cnt[1], flg[0], flg[1], flg[2], flg[3], s);
     {

@@ -20,6 +20,8 @@ struct TreeArgs {
 };
 
 void plan_init(const double *given_root, double *root_dev, int *bad, hipStream_t s);
+// uniform trees: V counts and complete M2L slot rows (no fill needed)
+void vslot_uniform(const TreeArgs &a, int64_t *cnt, int32_t *vslot, hipStream_t s);
 void bbox(const double *xyz, int n, double *part, double *root, hipStream_t s);
 void morton_keys(const double *xyz, int n, const double *root_dev, int D, uint64_t *keys,
                  int32_t *idx, int *bad, hipStream_t s);

@@ -469,6 +469,42 @@ __global__ __launch_bounds__(256) void k_vlist(TreeView t, const int32_t *coll, 
     if (!which && lane == 0) cnt[b] = n;
 }
 
+// Uniform trees: V counts and M2L slot rows without the colleague walk.  In a
+// full level the V source at slot offset k (target - source) is the box of
+// cell (target cell - k) whenever that cell lies in the grid; every row is
+// written whole (-1 where there is no source, all of it below level 2).
+__global__ __launch_bounds__(256) void k_vslot_uniform(TreeView t, int64_t *cnt, int32_t *vslot)
+{
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= t.nboxes) return;
+    const int l = t.bx.level[b];
+    int32_t *row = vslot + (int64_t)b * kVSlots;
+    int n = 0;
+    if (l < 2) {
+        for (int j = lane; j < kVSlots; j += 64) row[j] = -1;
+    } else {
+        const int side = 1 << l, base = t.lvl_begin[l];
+        const uint64_t code = t.bx.morton[b];
+        int cb[3];
+        deinterleave(code, l, cb);
+        const int oct = (int)(code & 7);
+        const int s[3] = {((oct >> 2) & 1) ? -2 : -3, ((oct >> 1) & 1) ? -2 : -3, (oct & 1) ? -2 : -3};
+        for (int j = lane; j < 216; j += 64) { // the 6 x 6 x 6 block of offsets, near cube excluded
+            const int k[3] = {j / 36 + s[0], (j / 6) % 6 + s[1], j % 6 + s[2]};
+            const int sl = vslot_of(oct, k[0], k[1], k[2]);
+            if (sl < 0) continue;
+            int c[3] = {cb[0] - k[0], cb[1] - k[1], cb[2] - k[2]};
+            const bool in = c[0] >= 0 && c[1] >= 0 && c[2] >= 0 && c[0] < side && c[1] < side && c[2] < side;
+            row[sl] = in ? base + (int)interleave(c, l) : -1;
+            n += in;
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) n += __shfl_xor(n, o);
+    }
+    if (lane == 0) cnt[b] = n;
+}
+
 // U (P2P) and W (M2P) for leaves.  U(b): the leaves adjacent to b (b
 // included); W(b): boxes not adjacent to b whose parent is adjacent to b and
 // that descend from a colleague of b.  A wavefront walks the adjacent
@@ -665,6 +701,12 @@ void vlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *cnt, cons
 {
     TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
     k_vlist<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, which, cnt, off, src, vslot);
+}
+
+void vslot_uniform(const TreeArgs &a, int64_t *cnt, int32_t *vslot, hipStream_t s)
+{
+    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
+    k_vslot_uniform<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, cnt, vslot);
 }
 
 void uwlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *ucnt, const int64_t *uoff,
