@@ -489,14 +489,15 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     int32_t *mtg = P->temp<int32_t>(nb);
     PlanSizes *sizes_dev = P->temp<PlanSizes>(1);
     NOMEM(coll); NOMEM(mscr); NOMEM(mtg); NOMEM(sizes_dev);
-    colleagues(ta, coll, cnt[3], s); // also clears the X counts
-    if (P->uniform) {
+    if (P->uniform) { // lists straight from the cell coordinates
+        ulist_uniform(ta, 0, cnt[0], cnt[2], cnt[3], nullptr, nullptr, s); // U counts, empty W and X
         vslot_uniform(ta, cnt[1], vslot, s); // V counts and whole M2L slot rows
     } else {
+        colleagues(ta, coll, cnt[3], s); // also clears the X counts
         fill_i32(vslot, (int64_t)nb * kVSlots, -1, s);
         vlist(ta, coll, 0, cnt[1], nullptr, nullptr, vslot, s); // V counts and M2L slot rows
+        uwlist(ta, coll, 0, cnt[0], nullptr, nullptr, cnt[2], nullptr, nullptr, cnt[3], s);
     }
-    uwlist(ta, coll, 0, cnt[0], nullptr, nullptr, cnt[2], nullptr, nullptr, cnt[3], s);
     flags(bx, nb, cnt[3], cnt[1], flg[0], flg[1], flg[2], flg[3], s);
     {
         const int64_t *in[8] = {cnt[0], cnt[1], cnt[2], cnt[3], flg[0], flg[1], flg[2], flg[3]};
@@ -549,7 +550,8 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     }
     int32_t *slots = P->own<int32_t>(slot_cap);
     NOMEM(slots);
-    uwlist(ta, coll, 1, nullptr, P->off[0], P->src[0], nullptr, P->off[2], P->src[2], nullptr, s);
+    if (P->uniform) ulist_uniform(ta, 1, nullptr, nullptr, nullptr, P->off[0], P->src[0], s);
+    else uwlist(ta, coll, 1, nullptr, P->off[0], P->src[0], nullptr, P->off[2], P->src[2], nullptr, s);
     if (mw > 0) { // X = transpose of W
         uint64_t *wk = P->temp<uint64_t>(mw), *wk2 = P->temp<uint64_t>(mw);
         int32_t *wv2 = P->temp<int32_t>(mw), *wscr = P->temp<int32_t>(sort_scratch_bytes((int)mw) / 4 + 1);

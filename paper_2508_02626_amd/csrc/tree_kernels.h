@@ -20,6 +20,9 @@ struct TreeArgs {
 };
 
 void plan_init(const double *given_root, double *root_dev, int *bad, hipStream_t s);
+// uniform trees: U counts (W and X set empty) or U contents, without colleagues
+void ulist_uniform(const TreeArgs &a, int which, int64_t *ucnt, int64_t *wcnt, int64_t *xcnt, const int64_t *uoff,
+                   int32_t *usrc, hipStream_t s);
 // uniform trees: V counts and complete M2L slot rows (no fill needed)
 void vslot_uniform(const TreeArgs &a, int64_t *cnt, int32_t *vslot, hipStream_t s);
 void bbox(const double *xyz, int n, double *part, double *root, hipStream_t s);

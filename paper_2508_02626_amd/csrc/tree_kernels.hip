@@ -505,6 +505,49 @@ __global__ __launch_bounds__(256) void k_vslot_uniform(TreeView t, int64_t *cnt,
     if (lane == 0) cnt[b] = n;
 }
 
+// Uniform trees: U lists without the colleague walk.  A leaf's U list is the
+// leaves of its 3 x 3 x 3 cell neighbourhood (itself included), in box order;
+// W and X lists are empty.  Counts: one thread per box; fill: one wavefront
+// per leaf, the neighbours ranked by box index.
+__global__ __launch_bounds__(256) void k_ucount_uniform(TreeView t, int64_t *ucnt, int64_t *wcnt, int64_t *xcnt)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= t.nboxes) return;
+    const int l = t.bx.level[b];
+    int n = 0;
+    if (l == t.D) {
+        const int side = 1 << l;
+        int c[3];
+        deinterleave(t.bx.morton[b], l, c);
+        n = 1;
+        for (int k = 0; k < 3; ++k) n *= (c[k] + 1 < side - 1 ? c[k] + 1 : side - 1) - (c[k] > 0 ? c[k] - 1 : 0) + 1;
+    }
+    ucnt[b] = n;
+    wcnt[b] = 0;
+    xcnt[b] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_ufill_uniform(TreeView t, const int64_t *uoff, int32_t *usrc)
+{
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= t.nboxes) return;
+    const int l = t.bx.level[b];
+    if (l != t.D) return;
+    const int side = 1 << l, base = t.lvl_begin[l];
+    int c[3];
+    deinterleave(t.bx.morton[b], l, c);
+    int f = INT_MAX;
+    if (lane < 27) {
+        int nb[3] = {c[0] + lane / 9 - 1, c[1] + (lane / 3) % 3 - 1, c[2] + lane % 3 - 1};
+        if (nb[0] >= 0 && nb[1] >= 0 && nb[2] >= 0 && nb[0] < side && nb[1] < side && nb[2] < side)
+            f = base + (int)interleave(nb, l);
+    }
+    int rank = 0;
+    for (int k = 0; k < 27; ++k) rank += __shfl(f, k) < f;
+    if (f != INT_MAX) usrc[uoff[b] + rank] = f;
+}
+
 // U (P2P) and W (M2P) for leaves.  U(b): the leaves adjacent to b (b
 // included); W(b): boxes not adjacent to b whose parent is adjacent to b and
 // that descend from a colleague of b.  A wavefront walks the adjacent
@@ -701,6 +744,14 @@ void vlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *cnt, cons
 {
     TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
     k_vlist<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, which, cnt, off, src, vslot);
+}
+
+void ulist_uniform(const TreeArgs &a, int which, int64_t *ucnt, int64_t *wcnt, int64_t *xcnt, const int64_t *uoff,
+                   int32_t *usrc, hipStream_t s)
+{
+    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
+    if (!which) k_ucount_uniform<<<ceil_div(a.nboxes, 256), 256, 0, s>>>(t, ucnt, wcnt, xcnt);
+    else k_ufill_uniform<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, uoff, usrc);
 }
 
 void vslot_uniform(const TreeArgs &a, int64_t *cnt, int32_t *vslot, hipStream_t s)
