@@ -166,25 +166,40 @@ template <typename T> using gp = __attribute__((address_space(1))) T *;
 template <typename T> __device__ inline gp<const T> gptr(const T *p) { return (gp<const T>)p; }
 template <typename T> __device__ inline gp<T> gptr(T *p) { return (gp<T>)p; }
 
-// Morton codes: bit b of the x, y, z cell index sits at code bits 3b+2, 3b+1, 3b.
+// Morton codes: bit b of the x, y, z cell index sits at code bits 3b+2, 3b+1, 3b
+// (levels up to 21).  The bits are spread and gathered with the usual shift-
+// and-mask steps (5 each); only the low l bits of a cell index take part.
+__host__ __device__ inline uint64_t spread3(uint64_t v) // bit b -> bit 3b
+{
+    v &= 0x1fffffull;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+__host__ __device__ inline uint32_t gather3(uint64_t v) // bit 3b -> bit b
+{
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return (uint32_t)v;
+}
 __host__ __device__ inline void deinterleave(uint64_t code, int l, int c[3])
 {
-    c[0] = c[1] = c[2] = 0;
-    for (int b = 0; b < l; ++b) {
-        c[0] |= (int)((code >> (3 * b + 2)) & 1) << b;
-        c[1] |= (int)((code >> (3 * b + 1)) & 1) << b;
-        c[2] |= (int)((code >> (3 * b)) & 1) << b;
-    }
+    const uint32_t m = (1u << l) - 1;
+    c[0] = (int)(gather3(code >> 2) & m);
+    c[1] = (int)(gather3(code >> 1) & m);
+    c[2] = (int)(gather3(code) & m);
 }
 __host__ __device__ inline uint64_t interleave(const int c[3], int l)
 {
-    uint64_t k = 0;
-    for (int b = 0; b < l; ++b) {
-        k |= (uint64_t)((c[0] >> b) & 1) << (3 * b + 2);
-        k |= (uint64_t)((c[1] >> b) & 1) << (3 * b + 1);
-        k |= (uint64_t)((c[2] >> b) & 1) << (3 * b);
-    }
-    return k;
+    const uint32_t m = (1u << l) - 1;
+    return spread3((uint32_t)c[0] & m) << 2 | spread3((uint32_t)c[1] & m) << 1 | spread3((uint32_t)c[2] & m);
 }
 
 // V-list slots.  A box whose octant within its parent is o (bits ox, oy, oz)
