@@ -440,7 +440,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         if (adaptive)
             t.add<uint64_t>(nb).add<int32_t>(nb).add<uint64_t>(nb).add<int32_t>(nb).add<int32_t>(nb).add<int32_t>(nb)
              .add<uint64_t>(nb).add<int32_t>(sort_scratch_bytes(nb) / 4 + 1);
-        t.add<int32_t>(27ull * nb);
+        t.add<int32_t>(27ull * nb).add<int32_t>(nb);
         for (int w = 0; w < 8; ++w) t.add<int64_t>(nb + 1);
         for (int w = 0; w < 4; ++w) t.add<int64_t>(nb + 1);
         t.add<int64_t>(scan_multi_scratch_bytes(nb, 8) / 8 + 1).add<int32_t>(nb).add<PlanSizes>(1);
@@ -480,7 +480,8 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     } else {
         uniform_boxes(keys, n, P->D, nb, bx, lvl_dev, s);
     }
-    TreeArgs ta{bx, lvl_dev, P->D, nb, P->uniform};
+    int32_t *leafcol = P->uniform ? nullptr : P->temp<int32_t>(nb);
+    TreeArgs ta{bx, lvl_dev, P->D, nb, P->uniform, leafcol};
     int32_t *coll = P->temp<int32_t>(27ull * nb);
     int64_t *cnt[4], *flg[4], *pos[4];
     for (int w = 0; w < 4; ++w) { cnt[w] = P->temp<int64_t>(nb + 1); NOMEM(cnt[w]); }
@@ -493,7 +494,8 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         ulist_uniform(ta, 0, cnt[0], cnt[2], cnt[3], nullptr, nullptr, s); // U counts, empty W and X
         vslot_uniform(ta, cnt[1], vslot, s); // V counts and whole M2L slot rows
     } else {
-        colleagues(ta, coll, cnt[3], s); // also clears the X counts
+        NOMEM(leafcol);
+        colleagues(ta, coll, cnt[3], leafcol, s); // also clears the X counts
         fill_i32(vslot, (int64_t)nb * kVSlots, -1, s);
         vlist(ta, coll, 0, cnt[1], nullptr, nullptr, vslot, s); // V counts and M2L slot rows
         uwlist(ta, coll, 0, cnt[0], nullptr, nullptr, cnt[2], nullptr, nullptr, cnt[3], s);
@@ -1093,7 +1095,7 @@ extern "C" int fmm_plan_export_tree(fmm_plan_t plan, hipStream_t stream, double 
         HIPCHK(hipMalloc((void **)&coll, sizeof(int32_t) * 27 * (size_t)nb));
         int32_t *v1 = P->own<int32_t>(P->nlist[1] ? P->nlist[1] : 1);
         if (!v1) { (void)hipFree(coll); return fail(FMM_ENOMEM, "device allocation failed (V list)"); }
-        colleagues(ta, coll, nullptr, P->stream);
+        colleagues(ta, coll, nullptr, nullptr, P->stream);
         vlist(ta, coll, 1, nullptr, P->off[1], v1, nullptr, P->stream);
         hipError_t e1 = hipStreamSynchronize(P->stream);
         (void)hipFree(coll);

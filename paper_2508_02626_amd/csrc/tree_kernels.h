@@ -17,6 +17,7 @@ struct TreeArgs {
     const int32_t *lvl_begin; // device [kMaxDepth + 2]
     int D, nboxes;
     int uniform; // every level full: no coarser adjacent leaves, no W lists
+    const int32_t *leafcol; // per box: a colleague (other than itself) is a leaf; NULL = unknown
 };
 
 void plan_init(const double *given_root, double *root_dev, int *bad, hipStream_t s);
@@ -38,7 +39,7 @@ void adaptive_boxes(const uint64_t *keys, int n, int D, int leaf_size, const int
                     uint64_t *elevel, int32_t *eidx, uint64_t *tk, int32_t *tv, int32_t *efirst,
                     int32_t *ecount, uint64_t *emorton, int32_t *sort_scratch, BoxArrays bx,
                     int32_t *lvl_begin, hipStream_t s);
-void colleagues(const TreeArgs &a, int32_t *coll, int64_t *zero, hipStream_t s);
+void colleagues(const TreeArgs &a, int32_t *coll, int64_t *zero, int32_t *leafcol, hipStream_t s);
 void vlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *cnt, const int64_t *off,
            int32_t *src, int32_t *vslot, hipStream_t s);
 void uwlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *ucnt, const int64_t *uoff,

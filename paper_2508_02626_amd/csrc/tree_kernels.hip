@@ -345,6 +345,7 @@ struct TreeView {
     const int32_t *lvl_begin; // [kMaxDepth + 2]
     int D, nboxes;
     int uniform; // every level full: all leaves on the last level
+    const int32_t *leafcol; // per box: a colleague (other than itself) is a leaf, or NULL
 };
 
 __device__ inline int find_box(const TreeView &t, int l, uint64_t code)
@@ -378,7 +379,7 @@ __device__ inline bool adjacent(const TreeView &t, int a, int b)
 
 // Colleagues: the up to 27 same-level boxes adjacent to b (b included),
 // ascending, padded with -1.  Lane j < 27 looks up neighbour cell j.
-__global__ __launch_bounds__(256) void k_colleagues(TreeView t, int32_t *coll, int64_t *zero)
+__global__ __launch_bounds__(256) void k_colleagues(TreeView t, int32_t *coll, int64_t *zero, int32_t *leafcol)
 {
     const int lane = threadIdx.x & 63;
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -400,6 +401,11 @@ __global__ __launch_bounds__(256) void k_colleagues(TreeView t, int32_t *coll, i
     const int found = __popcll(__ballot(f != INT_MAX));
     if (f != INT_MAX) coll[27 * b + rank] = f;    // ranks fill [0, found)
     if (lane >= found && lane < 27) coll[27 * b + lane] = -1;
+    if (leafcol) { // does the U/W walk of a descendant leaf need this box's colleagues?
+        const bool lf = f != INT_MAX && f != b && t.bx.nchild[f] == 0;
+        const uint64_t m = __ballot(lf);
+        if (lane == 0) leafcol[b] = m != 0;
+    }
 }
 
 // which: 0 count, 1 fill.  V for boxes of level >= 2: children of the
@@ -707,6 +713,7 @@ __global__ __launch_bounds__(256) void k_uwlist(TreeView t, const int32_t *coll,
     }
     if (ok && !t.uniform) { // (a uniform tree has all its leaves on one level)
         for (int a = t.bx.parent[b]; a >= 0; a = t.bx.parent[a]) {
+            if (t.leafcol && !t.leafcol[a]) continue; // no leaf among a's colleagues
             const int c = lane < 27 ? coll[27 * a + lane] : -1;
             const bool hit = c >= 0 && c != a && t.bx.nchild[c] == 0 && touches(cell_of(t, c), cb);
             const uint64_t m = __ballot(hit);
@@ -733,37 +740,37 @@ __global__ __launch_bounds__(256) void k_uwlist(TreeView t, const int32_t *coll,
     write_ranked(bw, nw, wsrc + woff[b], lane);
 }
 
-void colleagues(const TreeArgs &a, int32_t *coll, int64_t *zero, hipStream_t s)
+void colleagues(const TreeArgs &a, int32_t *coll, int64_t *zero, int32_t *leafcol, hipStream_t s)
 {
-    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
-    k_colleagues<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, zero);
+    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform, a.leafcol};
+    k_colleagues<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, zero, leafcol);
 }
 
 void vlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *cnt, const int64_t *off,
            int32_t *src, int32_t *vslot, hipStream_t s)
 {
-    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
+    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform, a.leafcol};
     k_vlist<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, which, cnt, off, src, vslot);
 }
 
 void ulist_uniform(const TreeArgs &a, int which, int64_t *ucnt, int64_t *wcnt, int64_t *xcnt, const int64_t *uoff,
                    int32_t *usrc, hipStream_t s)
 {
-    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
+    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform, a.leafcol};
     if (!which) k_ucount_uniform<<<ceil_div(a.nboxes, 256), 256, 0, s>>>(t, ucnt, wcnt, xcnt);
     else k_ufill_uniform<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, uoff, usrc);
 }
 
 void vslot_uniform(const TreeArgs &a, int64_t *cnt, int32_t *vslot, hipStream_t s)
 {
-    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
+    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform, a.leafcol};
     k_vslot_uniform<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, cnt, vslot);
 }
 
 void uwlist(const TreeArgs &a, const int32_t *coll, int which, int64_t *ucnt, const int64_t *uoff,
             int32_t *usrc, int64_t *wcnt, const int64_t *woff, int32_t *wsrc, int64_t *xcnt, hipStream_t s)
 {
-    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform};
+    TreeView t{a.bx, a.lvl_begin, a.D, a.nboxes, a.uniform, a.leafcol};
     k_uwlist<<<ceil_div(a.nboxes, 4), 256, 0, s>>>(t, coll, which, ucnt, uoff, usrc, wcnt, woff, wsrc, xcnt);
 }
 
