@@ -46,9 +46,9 @@ FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS = 78.6, 157.3
 # write x1.0; profiles/uniform1m_hbm_traffic.txt).  Valid only for the kernel
 # sources it was measured on (kernel, shared header, tile order): a different
 # fingerprint reports null.
-M2L_TRAFFIC = {"fingerprint": "c810e8b87df51e74", "bytes": (1342.94 + 83.36) * 1e6}
+M2L_TRAFFIC = {"fingerprint": "2e96bb397b2bc4cb", "bytes": (1342.94 + 83.36) * 1e6}
 M2L_SOURCES = ("paper_2508_02626_amd/csrc/m2l.hip", "paper_2508_02626_amd/csrc/common.h",
-               "paper_2508_02626_amd/csrc/tree_kernels.hip")
+               "paper_2508_02626_amd/csrc/m2l_tiles.hip")
 
 
 def m2l_traffic():
