@@ -36,6 +36,15 @@ def test_config1_potentials_match_oracle(p):
     _check_fp64(x, q, p, CFG1)
 
 
+@pytest.mark.parametrize("depth,n,p", [(0, 60, 4), (1, 400, 6), (2, 3000, 8), (4, 200, 8)])
+def test_shallow_and_sparse_uniform_trees_match_oracle(depth, n, p):
+    """Uniform trees without M2L targets (depth 0 and 1), with only level-2
+    targets, and a sparse one whose leaves are mostly empty."""
+    x, q = inputs.uniform(n, 20 + depth)
+    say("uniform depth", depth, "n", n, "p", p)
+    _check_fp64(x, q, p, dict(uniform_depth=depth, root=[0, 0, 0, 1]))
+
+
 @pytest.mark.parametrize("p", [13, 14, 15, 16])
 def test_high_orders_match_oracle(p):
     """Orders above 12 (M2L with the row tiles split over two wavefronts and a

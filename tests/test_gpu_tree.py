@@ -14,6 +14,10 @@ def _cases():
     c.append(("config1_uniform_d3", lambda: inputs.uniform(2000, 0), dict(uniform_depth=3, root=[0, 0, 0, 1])))
     c.append(("uniform_d5_1e5", lambda: inputs.uniform(100_000, 1), dict(uniform_depth=5, root=[0, 0, 0, 1])))
     c.append(("uniform_d4_bbox", lambda: inputs.uniform(30_000, 4), dict(uniform_depth=4)))
+    # shallow and sparse uniform trees: no level >= 2 (no V lists), and many empty leaves
+    c.append(("uniform_d0", lambda: inputs.uniform(50, 11), dict(uniform_depth=0, root=[0, 0, 0, 1])))
+    c.append(("uniform_d1", lambda: inputs.uniform(300, 12), dict(uniform_depth=1, root=[0, 0, 0, 1])))
+    c.append(("uniform_d4_sparse", lambda: inputs.uniform(40, 13), dict(uniform_depth=4, root=[0, 0, 0, 1])))
     c.append(("plummer_5e4_s64", lambda: inputs.plummer(50_000, 2), dict(leaf_size=64)))
     c.append(("plummer_2e4_s16", lambda: inputs.plummer(20_000, 5), dict(leaf_size=16)))
     c.append(("clusters_3e4_s32", lambda: inputs.clusters(30_000, 6), dict(leaf_size=32)))
