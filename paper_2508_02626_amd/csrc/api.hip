@@ -670,6 +670,7 @@ extern "C" int fmm_plan(const double *xyz_dev, int64_t n, int32_t order, int32_t
         (void)hipStreamSynchronize(stream);
         P->release_all();
         (void)hipStreamSynchronize(stream);
+        if (P->built) (void)hipEventDestroy(P->built);
         delete P;
         g_err = msg;
         return rc;
