@@ -782,15 +782,7 @@ __device__ inline void p2p_range(const SrcRec *S, int lo, int hi, Tgt &a, Tgt &b
             t.phi += qr;
             t.ex += qr3 * dx; t.ey += qr3 * dy; t.ez += qr3 * dz;
         };
-        int jj = lo;
-        for (; jj + 2 <= hi; jj += 2) {
-            const SrcRec s0 = S[jj], s1 = S[jj + 1];
-            term(s0, a);
-            term(s0, b);
-            term(s1, a);
-            term(s1, b);
-        }
-        if (jj < hi) {
+        for (int jj = lo; jj < hi; ++jj) {
             const SrcRec s0 = S[jj];
             term(s0, a);
             term(s0, b);
@@ -798,8 +790,11 @@ __device__ inline void p2p_range(const SrcRec *S, int lo, int hi, Tgt &a, Tgt &b
     }
 }
 
+// five waves per SIMD (at most 102 VGPRs): the kernel waits on its source
+// loads more than on arithmetic, and the few values this spills are read
+// once per target pass, outside the pair loop
 template <int MIXED>
-__global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B, int part)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_p2p(const PlanView *V, Bases B, int part)
 {
     __shared__ SrcRec sS[4][64];
     __shared__ double sR[4][8][64]; // group partials for the final combination
@@ -837,9 +832,27 @@ __global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B, int par
         // the U list's particles as one stream, in chunks of up to CH (a chunk
         // spans several source boxes), the next chunk prefetched into registers
         constexpr int CH = MIXED ? 32 : 64; // mixed: FP32 partial sums stay short
+        // the U list's boxes are read 64 at a time, lane l holding the first
+        // particle and the count of entry ub + l, so that walking the list
+        // costs one round of dependent loads per 64 boxes, not one per box
+        int64_t ub = u0;
+        int bfirst = 0, bcount = 0;
+        auto load_boxes = [&]() {
+            const int64_t ee = ub + lane;
+            bfirst = 0;
+            bcount = 0;
+            if (ee < u1) { const int src = usrc[ee]; bfirst = first[src]; bcount = count[src]; }
+        };
         int64_t e = u0;
         int s = 0, sf = 0, sc = 0;
-        if (e < u1) { int src = usrc[e]; sf = first[src]; sc = count[src]; }
+        auto box_at = [&]() { // sf, sc of entry e (u0 <= e < u1, e - ub <= 64)
+            if (e - ub >= 64) { ub += 64; load_boxes(); }
+            const int l = (int)(e - ub);
+            sf = __builtin_amdgcn_readlane(bfirst, l);
+            sc = __builtin_amdgcn_readlane(bcount, l);
+        };
+        load_boxes();
+        if (e < u1) box_at();
         SrcRec nx{0, 0, 0, 0};
         auto fill = [&]() { // next chunk into nx; returns its size
             int m = 0;
@@ -853,7 +866,7 @@ __global__ __launch_bounds__(256) void k_p2p(const PlanView *V, Bases B, int par
                 s += take;
                 if (s >= sc) {
                     s = 0;
-                    if (++e < u1) { int src = usrc[e]; sf = first[src]; sc = count[src]; }
+                    if (++e < u1) box_at();
                 }
             }
             return m;
