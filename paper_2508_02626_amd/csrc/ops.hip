@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_permute_q(const PlanView *V, Bases B)
 }
 
 // ---------------- P2M ----------------
-constexpr int kPwChunk = 16; // particles per LDS chunk of P2M / P2L
+constexpr int kPwChunk = 16; // particles per LDS chunk of P2M
 template <int P>
 __global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
 {
@@ -462,16 +462,27 @@ __global__ __launch_bounds__(256) void k_unfold(const PlanView *V, Bases B, int 
 // Lhat_b(B) += sum_i q_i d^b(1/|x|) at x_i' = (c_B - x_i)/h_B (Sec. 2.4 in
 // scaled units).  With d^b(1/|x|) = (-1)^n (2n-1)!! pi(x^b)/|x|^(2n+1), the
 // harmonic components are a fixed map (table P2L) of the inverse moments
-// W_g = sum_i q_i x'^g / |x'|^(2|g|+1).  One wavefront per target box
-// accumulates W over the particles of its X list, one lane per moment (as in
-// P2M); k_p2l_transform then applies the map on MFMA for 16 boxes at a time.
+// W_g = sum_i q_i x'^g / |x'|^(2|g|+1) = sum_i w_i u_i^g, with u = x'/|x'|^2
+// and w = q/|x'| (the Kelvin inversion of the particle about the centre).
+// One wavefront per target box accumulates W over the particles of its X
+// list.  Lane l owns the columns (b, c) = (g_y, g_z) numbered l, l + 64, ...
+// (by degree b + c) and sums every g_x = a of them: per particle a lane forms
+// one product u_y^b u_z^c from the powers staged in LDS and adds it times
+// w u_x^a, formed in registers, to its P + 1 - (b + c) sums.
+// k_p2l_transform then applies the map on MFMA for 16 boxes at a time.
+__host__ __device__ constexpr int col_degree(int j) // degree b + c of column j
+{
+    int s = 0;
+    while ((s + 1) * (s + 2) / 2 <= j) ++s;
+    return s;
+}
 template <int P>
 __global__ __launch_bounds__(64) void k_p2l(const PlanView *V, Bases B)
 {
-    constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
-    constexpr int R = (NC + 63) / 64;
-    __shared__ double pw[3][P + 1][kPwChunk + 1];
-    __shared__ double sr[P + 1][kPwChunk + 1];
+    constexpr int NCOL = (P + 1) * (P + 2) / 2, RC = (NCOL + 63) / 64;
+    constexpr int CH = 32; // particles per LDS chunk
+    __shared__ double py[P + 1][CH + 1], pz[P + 1][CH + 1];
+    __shared__ double2 xw[CH]; // (u_x, w)
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int box = v.xtgt[blockIdx.x - B.b[k]];
@@ -479,47 +490,67 @@ __global__ __launch_bounds__(64) void k_p2l(const PlanView *V, Bases B)
     double cen[3], h;
     box_geom(v, box, cen, h);
     const double ih = 1.0 / h;
-    int ex[R], ey[R], ez[R], en[R];
-    double acc[R];
+    int cb[RC], cc[RC];
+    double acc[RC][P + 1];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        int g = lane + 64 * r;
-        int e = g < NC ? v.tab->exps[g] : 0;
-        ex[r] = e & 255; ey[r] = (e >> 8) & 255; ez[r] = (e >> 16) & 255;
-        en[r] = ex[r] + ey[r] + ez[r];
-        acc[r] = 0.0;
+    for (int r = 0; r < RC; ++r) {
+        const int j = lane + 64 * r, d = j < NCOL ? col_degree(j) : 0;
+        cc[r] = j < NCOL ? j - d * (d + 1) / 2 : 0;
+        cb[r] = d - cc[r];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[r][a] = 0.0;
     }
-    for (int64_t e = v.X_off[box]; e < v.X_off[box + 1]; ++e) {
-        const int src = v.X_src[e];
-        const int f = v.first[src], cnt = v.count[src];
-        for (int s = 0; s < cnt; s += kPwChunk) {
-            double x = 1.0, y = 0.0, z = 0.0, q = 0.0;
-            if (lane < kPwChunk && s + lane < cnt) {
-                const int i = f + s + lane;
-                x = (cen[0] - v.xs[i]) * ih; y = (cen[1] - v.ys[i]) * ih; z = (cen[2] - v.zs[i]) * ih;
-                q = v.qs[i];
-            }
-            const double ir2 = 1.0 / (x * x + y * y + z * z);
-            double a = 1.0, b = 1.0, c = 1.0, w = q * sqrt(ir2);
-            if (lane < kPwChunk)
+    // the X list's source leaves, 64 at a time, lane l holding entry xb + l
+    const int64_t x0 = v.X_off[box], x1 = v.X_off[box + 1];
+    for (int64_t xb = x0; xb < x1; xb += 64) {
+        int lf = 0, lc = 0;
+        if (xb + lane < x1) { const int src = v.X_src[xb + lane]; lf = v.first[src]; lc = v.count[src]; }
+        const int ne = x1 - xb < 64 ? (int)(x1 - xb) : 64;
+        for (int e = 0; e < ne; ++e) {
+            const int f = __builtin_amdgcn_readlane(lf, e), cnt = __builtin_amdgcn_readlane(lc, e);
+            for (int s0 = 0; s0 < cnt; s0 += CH) {
+                const int m = cnt - s0 < CH ? cnt - s0 : CH;
+                __syncthreads(); // the previous chunk is consumed
+                if (lane < m) {
+                    const int i = f + s0 + lane;
+                    const double x = (cen[0] - v.xs[i]) * ih, y = (cen[1] - v.ys[i]) * ih, z = (cen[2] - v.zs[i]) * ih;
+                    const double ir2 = 1.0 / (x * x + y * y + z * z);
+                    const double uy = y * ir2, uz = z * ir2;
+                    double a = 1.0, c = 1.0;
 #pragma unroll
-                for (int t = 0; t <= P; ++t) {
-                    pw[0][t][lane] = a; pw[1][t][lane] = b; pw[2][t][lane] = c; sr[t][lane] = w;
-                    a *= x; b *= y; c *= z; w *= ir2;
+                    for (int t = 0; t <= P; ++t) {
+                        py[t][lane] = a; pz[t][lane] = c;
+                        a *= uy; c *= uz;
+                    }
+                    xw[lane] = make_double2(x * ir2, v.qs[i] * sqrt(ir2));
                 }
-            __syncthreads();
-            const int m = cnt - s < kPwChunk ? cnt - s : kPwChunk;
-            for (int t = 0; t < m; ++t)
+                __syncthreads();
+                for (int t = 0; t < m; ++t) {
+                    const double2 u = xw[t];
+                    double xp[P + 1];
+                    xp[0] = u.y;
 #pragma unroll
-                for (int r = 0; r < R; ++r)
-                    acc[r] += pw[0][ex[r]][t] * pw[1][ey[r]][t] * pw[2][ez[r]][t] * sr[en[r]][t];
-            __syncthreads();
+                    for (int a = 1; a <= P; ++a) xp[a] = xp[a - 1] * u.x;
+#pragma unroll
+                    for (int r = 0; r < RC; ++r) {
+                        const double yz = py[cb[r]][t] * pz[cc[r]][t];
+                        // columns of slot r have degree >= col_degree(64 r)
+#pragma unroll
+                        for (int a = 0; a <= P - col_degree(64 * r); ++a) acc[r][a] = fma(xp[a], yz, acc[r][a]);
+                    }
+                }
+            }
         }
     }
     double *W = v.L + (int64_t)box * v.ldm; // free until the unfold stage
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (lane + 64 * r < NC) W[lane + 64 * r] = acc[r];
+    for (int r = 0; r < RC; ++r) {
+        const int j = lane + 64 * r;
+        if (j >= NCOL) continue;
+#pragma unroll
+        for (int a = 0; a <= P; ++a)
+            if (a <= P - cb[r] - cc[r]) W[mono_index(a, cb[r], cc[r])] = acc[r][a];
+    }
 }
 
 __device__ inline int harm_degree(int c)
