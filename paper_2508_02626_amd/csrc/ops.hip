@@ -701,21 +701,53 @@ __global__ __launch_bounds__(64) void k_m2p(const PlanView *V, Bases B)
     double cen[3], h;
     box_geom(v, box, cen, h);
     const int f = v.first[box], cnt = v.count[box];
+    // the coefficients of the next W box are loaded into registers (a slice
+    // per lane) while the current box is evaluated
+    constexpr int R = (NC + 63) / 64;
+    double wsc[R], nxt[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int a = lane + 64 * r, ea = a < NC ? t.exps[a] : 0;
+        wsc[r] = a < NC ? t.inv_w[(ea & 255) + ((ea >> 8) & 255) + ((ea >> 16) & 255)] : 0.0;
+    }
+    // W entries are read 64 at a time, lane l holding entry wb + l
+    int64_t wb = w0;
+    int wl = 0;
+    auto load_entries = [&]() { wl = wb + lane < w1 ? v.W_src[wb + lane] : 0; };
+    int nlev = 0;
+    uint64_t nmor = 0;
+    auto fetch = [&](int64_t e) { // raw coefficients and cell of entry e
+        if (e - wb >= 64) { wb += 64; load_entries(); }
+        const int src = __builtin_amdgcn_readlane(wl, (int)(e - wb));
+        const double *Ms = v.M + (int64_t)src * v.ldm;
+#pragma unroll
+        for (int r = 0; r < R; ++r) nxt[r] = lane + 64 * r < NC ? Ms[lane + 64 * r] : 0.0;
+        nlev = v.level[src];
+        nmor = v.morton[src];
+    };
     for (int s = 0; s < cnt; s += 64) {
         int i = f + s + lane;
         bool act = s + lane < cnt;
         double x = act ? v.xs[i] : cen[0], y = act ? v.ys[i] : cen[1], z = act ? v.zs[i] : cen[2];
         double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        wb = w0;
+        load_entries();
+        fetch(w0);
         for (int64_t e = w0; e < w1; ++e) {
-            int src = v.W_src[e];
-            double sc[3], hs;
+            __syncthreads(); // the previous box's coefficients are consumed
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (lane + 64 * r < NC) cm[lane + 64 * r] = nxt[r] * wsc[r];
+            const int lev = nlev;
+            const uint64_t mor = nmor;
             __syncthreads();
-            box_geom(v, src, sc, hs);
-            for (int a = lane; a < NC; a += 64) {
-                int ea = t.exps[a];
-                cm[a] = v.M[(int64_t)src * v.ldm + a] * t.inv_w[(ea & 255) + ((ea >> 8) & 255) + ((ea >> 16) & 255)];
-            }
-            __syncthreads();
+            if (e + 1 < w1) fetch(e + 1);
+            double sc[3];
+            int cc[3];
+            deinterleave(mor, lev, cc);
+            const double hs = v.W / (double)(1ll << lev);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) sc[d] = v.lo[d] + ((double)cc[d] + 0.5) * hs;
             double y0 = x - sc[0], y1 = y - sc[1], y2 = z - sc[2];
             double s2 = 1.0 / (y0 * y0 + y1 * y1 + y2 * y2), sr = sqrt(s2);
             double f0, fx, fy, fz;
