@@ -106,6 +106,10 @@ def test_degenerate_inputs():
 @pytest.mark.parametrize("name,gen,p,kw", [
     ("config1_p6", lambda: inputs.uniform(2000, 0), 6, CFG1),
     ("plummer_5000_s32_p5", lambda: inputs.plummer(5000, 2), 5, dict(leaf_size=32)),
+    # X and W lists at orders where a P2L lane owns two (p = 11) and three
+    # (p = 16) columns (g_y, g_z)
+    ("clusters_60_s6_p11", lambda: inputs.clusters(60, 5), 11, dict(leaf_size=6)),
+    ("clusters_60_s6_p16", lambda: inputs.clusters(60, 5), 16, dict(leaf_size=6)),
 ])
 def test_expansions_match_oracle(name, gen, p, kw):
     """Coefficient-by-coefficient parity of M (Eq. P2M) and L (Eq. P2L form)."""
