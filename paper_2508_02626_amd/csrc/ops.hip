@@ -46,16 +46,98 @@ __global__ __launch_bounds__(256) void k_permute_q(const PlanView *V, Bases B)
     if (i < v.n) v.qs[i] = v.q_in[v.perm[i]];
 }
 
+// ---------------- moments by columns (P2M, P2L) ----------------
+// Both P2M and P2L sum moments W_g = sum_t w_t u_t^g over all monomials g of
+// degree <= P of a set of particles (P2M: u = (x - c)/h, w = q; P2L: the
+// inverted u = x'/|x'|^2, w = q/|x'|).  Lane l owns the columns (b, c) =
+// (g_y, g_z) numbered l, l + 64, ... by degree b + c and sums every a = g_x of
+// them: per particle a lane forms one product u_y^b u_z^c from the powers
+// staged in LDS and adds it times w u_x^a, formed in registers, to its
+// P + 1 - (b + c) sums (p = 10: 12 mults, 12 FMAs and 5 LDS reads, where a lane
+// per moment reads three staged powers for each of its moments).
+__host__ __device__ constexpr int col_degree(int j) // degree b + c of column j
+{
+    int s = 0;
+    while ((s + 1) * (s + 2) / 2 <= j) ++s;
+    return s;
+}
+template <int P>
+struct Cols {
+    static constexpr int NCOL = (P + 1) * (P + 2) / 2, RC = (NCOL + 63) / 64;
+    static constexpr int CH = 32; // particles per LDS chunk
+    typedef double Pow[P + 1][CH + 1];
+};
+template <int P>
+__device__ inline void col_setup(int lane, int (&cb)[Cols<P>::RC], int (&cc)[Cols<P>::RC],
+                                 double (&acc)[Cols<P>::RC][P + 1])
+{
+#pragma unroll
+    for (int r = 0; r < Cols<P>::RC; ++r) {
+        const int j = lane + 64 * r, d = j < Cols<P>::NCOL ? col_degree(j) : 0;
+        cc[r] = j < Cols<P>::NCOL ? j - d * (d + 1) / 2 : 0;
+        cb[r] = d - cc[r];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) acc[r][a] = 0.0;
+    }
+}
+// stage particle `slot` of a chunk: powers of u_y, u_z and the pair (u_x, w)
+template <int P>
+__device__ inline void col_stage(typename Cols<P>::Pow &py, typename Cols<P>::Pow &pz, double2 *xw, int slot,
+                                 double ux, double uy, double uz, double w)
+{
+    double a = 1.0, c = 1.0;
+#pragma unroll
+    for (int t = 0; t <= P; ++t) {
+        py[t][slot] = a; pz[t][slot] = c;
+        a *= uy; c *= uz;
+    }
+    xw[slot] = make_double2(ux, w);
+}
+// add the m staged particles to the lane's column sums
+template <int P>
+__device__ inline void col_add(const typename Cols<P>::Pow &py, const typename Cols<P>::Pow &pz, const double2 *xw,
+                               int m, const int (&cb)[Cols<P>::RC], const int (&cc)[Cols<P>::RC],
+                               double (&acc)[Cols<P>::RC][P + 1])
+{
+#pragma unroll 1
+    for (int t = 0; t < m; ++t) {
+        const double2 u = xw[t];
+        double xp[P + 1];
+        xp[0] = u.y;
+#pragma unroll
+        for (int a = 1; a <= P; ++a) xp[a] = xp[a - 1] * u.x;
+#pragma unroll
+        for (int r = 0; r < Cols<P>::RC; ++r) {
+            const double yz = py[cb[r]][t] * pz[cc[r]][t];
+            // columns of slot r have degree >= col_degree(64 r)
+#pragma unroll
+            for (int a = 0; a <= P - col_degree(64 * r); ++a) acc[r][a] = fma(xp[a], yz, acc[r][a]);
+        }
+    }
+}
+// W[mono_index(a, b, c)] for every monomial of degree <= P
+template <int P>
+__device__ inline void col_store(double *W, int lane, const int (&cb)[Cols<P>::RC], const int (&cc)[Cols<P>::RC],
+                                 const double (&acc)[Cols<P>::RC][P + 1])
+{
+#pragma unroll
+    for (int r = 0; r < Cols<P>::RC; ++r) {
+        if (lane + 64 * r >= Cols<P>::NCOL) continue;
+#pragma unroll
+        for (int a = 0; a <= P; ++a)
+            if (a <= P - cb[r] - cc[r]) W[mono_index(a, cb[r], cc[r])] = acc[r][a];
+    }
+}
+
 // ---------------- P2M ----------------
-constexpr int kPwChunk = 16; // particles per LDS chunk of P2M
+// Raw moments Q_g = sum_i q_i ((x_i - c)/h)^g of a leaf (Eq. P2M in scaled
+// units), one wavefront per leaf, by columns.
 template <int P>
 __global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
 {
-    constexpr int NC = (P + 1) * (P + 2) * (P + 3) / 6;
-    constexpr int R = (NC + 63) / 64;
-    // particles are taken kPwChunk at a time: their powers in LDS stay small
-    // enough for many wavefronts per CU
-    __shared__ double pw[3][P + 1][kPwChunk + 1];
+    using C = Cols<P>;
+    __shared__ typename C::Pow py, pz;
+    __shared__ double2 xw[C::CH];
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int box = v.leaves[blockIdx.x - B.b[k]];
@@ -63,45 +145,24 @@ __global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
     double cen[3], h;
     box_geom(v, box, cen, h);
     const double ih = 1.0 / h;
-    int ex[R], ey[R], ez[R];
-    double acc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        int g = lane + 64 * r;
-        int e = g < NC ? v.tab->exps[g] : 0;
-        ex[r] = e & 255; ey[r] = (e >> 8) & 255; ez[r] = (e >> 16) & 255;
-        acc[r] = 0.0;
-    }
+    int cb[C::RC], cc[C::RC];
+    double acc[C::RC][P + 1];
+    col_setup<P>(lane, cb, cc, acc);
     const int f = v.first[box], cnt = v.count[box];
-    for (int s = 0; s < cnt; s += kPwChunk) {
-        int i = f + s + lane;
-        double u0 = 0, u1 = 0, u2 = 0, q = 0;
-        if (lane < kPwChunk && s + lane < cnt) {
-            u0 = (v.xs[i] - cen[0]) * ih;
-            u1 = (v.ys[i] - cen[1]) * ih;
-            u2 = (v.zs[i] - cen[2]) * ih;
-            q = v.qs[i];
+    for (int s0 = 0; s0 < cnt; s0 += C::CH) {
+        const int m = cnt - s0 < C::CH ? cnt - s0 : C::CH;
+        __syncthreads(); // the previous chunk is consumed
+        if (lane < m) {
+            const int i = f + s0 + lane;
+            col_stage<P>(py, pz, xw, lane, (v.xs[i] - cen[0]) * ih, (v.ys[i] - cen[1]) * ih,
+                         (v.zs[i] - cen[2]) * ih, v.qs[i]);
         }
-        double a = q, b = 1.0, c = 1.0;
-        if (lane < kPwChunk)
-#pragma unroll
-            for (int e = 0; e <= P; ++e) {
-                pw[0][e][lane] = a; pw[1][e][lane] = b; pw[2][e][lane] = c;
-                a *= u0; b *= u1; c *= u2;
-            }
         __syncthreads();
-        int m = cnt - s < kPwChunk ? cnt - s : kPwChunk;
-        for (int t = 0; t < m; ++t)
-#pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] += pw[0][ex[r]][t] * pw[1][ey[r]][t] * pw[2][ez[r]][t];
-        __syncthreads();
+        col_add<P>(py, pz, xw, m, cb, cc, acc);
     }
     // raw moments go to the (not yet used) local-expansion row of the leaf;
     // k_p2m_transform turns them into Mhat
-    double *Qg = v.L + (int64_t)box * v.ldm;
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (lane + 64 * r < NC) Qg[lane + 64 * r] = acc[r];
+    col_store<P>(v.L + (int64_t)box * v.ldm, lane, cb, cc, acc);
 }
 
 // Mhat = P2M^t Q for 16 leaves x 16 coefficients per wavefront (FP64 MFMA);
@@ -464,25 +525,15 @@ __global__ __launch_bounds__(256) void k_unfold(const PlanView *V, Bases B, int 
 // harmonic components are a fixed map (table P2L) of the inverse moments
 // W_g = sum_i q_i x'^g / |x'|^(2|g|+1) = sum_i w_i u_i^g, with u = x'/|x'|^2
 // and w = q/|x'| (the Kelvin inversion of the particle about the centre).
-// One wavefront per target box accumulates W over the particles of its X
-// list.  Lane l owns the columns (b, c) = (g_y, g_z) numbered l, l + 64, ...
-// (by degree b + c) and sums every g_x = a of them: per particle a lane forms
-// one product u_y^b u_z^c from the powers staged in LDS and adds it times
-// w u_x^a, formed in registers, to its P + 1 - (b + c) sums.
-// k_p2l_transform then applies the map on MFMA for 16 boxes at a time.
-__host__ __device__ constexpr int col_degree(int j) // degree b + c of column j
-{
-    int s = 0;
-    while ((s + 1) * (s + 2) / 2 <= j) ++s;
-    return s;
-}
+// One wavefront per target box accumulates W by columns over the particles of
+// its X list; k_p2l_transform then applies the map on MFMA for 16 boxes at a
+// time.
 template <int P>
 __global__ __launch_bounds__(64) void k_p2l(const PlanView *V, Bases B)
 {
-    constexpr int NCOL = (P + 1) * (P + 2) / 2, RC = (NCOL + 63) / 64;
-    constexpr int CH = 32; // particles per LDS chunk
-    __shared__ double py[P + 1][CH + 1], pz[P + 1][CH + 1];
-    __shared__ double2 xw[CH]; // (u_x, w)
+    using C = Cols<P>;
+    __shared__ typename C::Pow py, pz;
+    __shared__ double2 xw[C::CH];
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int box = v.xtgt[blockIdx.x - B.b[k]];
@@ -490,16 +541,9 @@ __global__ __launch_bounds__(64) void k_p2l(const PlanView *V, Bases B)
     double cen[3], h;
     box_geom(v, box, cen, h);
     const double ih = 1.0 / h;
-    int cb[RC], cc[RC];
-    double acc[RC][P + 1];
-#pragma unroll
-    for (int r = 0; r < RC; ++r) {
-        const int j = lane + 64 * r, d = j < NCOL ? col_degree(j) : 0;
-        cc[r] = j < NCOL ? j - d * (d + 1) / 2 : 0;
-        cb[r] = d - cc[r];
-#pragma unroll
-        for (int a = 0; a <= P; ++a) acc[r][a] = 0.0;
-    }
+    int cb[C::RC], cc[C::RC];
+    double acc[C::RC][P + 1];
+    col_setup<P>(lane, cb, cc, acc);
     // the X list's source leaves, 64 at a time, lane l holding entry xb + l
     const int64_t x0 = v.X_off[box], x1 = v.X_off[box + 1];
     for (int64_t xb = x0; xb < x1; xb += 64) {
@@ -508,49 +552,21 @@ __global__ __launch_bounds__(64) void k_p2l(const PlanView *V, Bases B)
         const int ne = x1 - xb < 64 ? (int)(x1 - xb) : 64;
         for (int e = 0; e < ne; ++e) {
             const int f = __builtin_amdgcn_readlane(lf, e), cnt = __builtin_amdgcn_readlane(lc, e);
-            for (int s0 = 0; s0 < cnt; s0 += CH) {
-                const int m = cnt - s0 < CH ? cnt - s0 : CH;
+            for (int s0 = 0; s0 < cnt; s0 += C::CH) {
+                const int m = cnt - s0 < C::CH ? cnt - s0 : C::CH;
                 __syncthreads(); // the previous chunk is consumed
                 if (lane < m) {
                     const int i = f + s0 + lane;
                     const double x = (cen[0] - v.xs[i]) * ih, y = (cen[1] - v.ys[i]) * ih, z = (cen[2] - v.zs[i]) * ih;
                     const double ir2 = 1.0 / (x * x + y * y + z * z);
-                    const double uy = y * ir2, uz = z * ir2;
-                    double a = 1.0, c = 1.0;
-#pragma unroll
-                    for (int t = 0; t <= P; ++t) {
-                        py[t][lane] = a; pz[t][lane] = c;
-                        a *= uy; c *= uz;
-                    }
-                    xw[lane] = make_double2(x * ir2, v.qs[i] * sqrt(ir2));
+                    col_stage<P>(py, pz, xw, lane, x * ir2, y * ir2, z * ir2, v.qs[i] * sqrt(ir2));
                 }
                 __syncthreads();
-                for (int t = 0; t < m; ++t) {
-                    const double2 u = xw[t];
-                    double xp[P + 1];
-                    xp[0] = u.y;
-#pragma unroll
-                    for (int a = 1; a <= P; ++a) xp[a] = xp[a - 1] * u.x;
-#pragma unroll
-                    for (int r = 0; r < RC; ++r) {
-                        const double yz = py[cb[r]][t] * pz[cc[r]][t];
-                        // columns of slot r have degree >= col_degree(64 r)
-#pragma unroll
-                        for (int a = 0; a <= P - col_degree(64 * r); ++a) acc[r][a] = fma(xp[a], yz, acc[r][a]);
-                    }
-                }
+                col_add<P>(py, pz, xw, m, cb, cc, acc);
             }
         }
     }
-    double *W = v.L + (int64_t)box * v.ldm; // free until the unfold stage
-#pragma unroll
-    for (int r = 0; r < RC; ++r) {
-        const int j = lane + 64 * r;
-        if (j >= NCOL) continue;
-#pragma unroll
-        for (int a = 0; a <= P; ++a)
-            if (a <= P - cb[r] - cc[r]) W[mono_index(a, cb[r], cc[r])] = acc[r][a];
-    }
+    col_store<P>(v.L + (int64_t)box * v.ldm, lane, cb, cc, acc); // L is free until the unfold stage
 }
 
 __device__ inline int harm_degree(int c)
