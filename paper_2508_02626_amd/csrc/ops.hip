@@ -913,7 +913,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         constexpr int CH = MIXED ? 32 : 64; // mixed: FP32 partial sums stay short
         // the U list's boxes are read 64 at a time, lane l holding the first
         // particle and the count of entry ub + l, so that walking the list
-        // costs one round of dependent loads per 64 boxes, not one per box
+        // waits on one chain of dependent loads per 64 boxes, not one per box
         int64_t ub = u0;
         int bfirst = 0, bcount = 0;
         auto load_boxes = [&]() {
