@@ -56,7 +56,6 @@ void da_monomials(const da_ctx *outer, const da_ctx *inner, const double *const 
                   double *cols);
 void da_compose(const da_ctx *outer, const double *f,
                 const da_ctx *inner, const double *const args[3], double *out);
-double da_eval(const da_ctx *c, const double *a, const double y[3]);
 
 /* Taylor coefficients of 1/|x0 + d| about x0 (Table 1): built with the DA
  * algebra exactly as Sec. 3 describes (v, then square root, then inverse). */

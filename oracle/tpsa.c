@@ -188,19 +188,6 @@ void da_compose(const da_ctx *outer, const double *f, const da_ctx *inner,
     free(t); free(cols);
 }
 
-/* Value of the polynomial at a point: sum_J a_J y^J (Eq. poly). */
-double da_eval(const da_ctx *c, const double *a, const double y[3])
-{
-    double s = 0.0;
-    for (int id = 0; id < c->n; ++id) {
-        double m = 1.0;
-        for (int v = 0; v < 3; ++v)
-            for (int k = 0; k < c->e[id][v]; ++k) m *= y[v];
-        s += a[id] * m;
-    }
-    return s;
-}
-
 /* Table 1: f = 1/|x0 + d|.  Following Sec. 3, first v = sum_k (x0_k + d_k)^2,
  * then the square root, then the inverse. */
 int oracle_da_inv_r(int p, const double x0[3], double *out)
