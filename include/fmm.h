@@ -48,7 +48,15 @@ enum {
     FMM_EUNSUPPORTED = -4   /* valid but not supported by this build          */
 };
 
-enum { FMM_FP64 = 0, FMM_MIXED = 1 };
+/* Precision of the evaluation (fmm_options_t.precision): a set of parts run
+ * in FP32; everything not named stays FP64.  FMM_MIXED is both. */
+enum {
+    FMM_FP64 = 0,
+    FMM_P2P_F32 = 1,   /* P2P pair terms in FP32, compensated (Kahan) FP32 sum
+                          per target and source range, FP64 combination       */
+    FMM_M2L_F32 = 2,   /* M2L contraction on FP32 MFMA (orders <= 8)          */
+    FMM_MIXED = 3
+};
 
 typedef struct fmm_plan_s *fmm_plan_t;
 
@@ -65,9 +73,8 @@ typedef struct {
                               -1: adaptive octree, a box with more than
                               leaf_size particles is subdivided (Sec. 3.5)    */
     int32_t max_depth;     /* adaptive depth cap, 1..21 (default 21)          */
-    int32_t precision;     /* FMM_FP64, or FMM_MIXED: FP32 P2P with a
-                              compensated sum and, for order <= 8, FP32 MFMA
-                              M2L; everything else stays FP64                 */
+    int32_t precision;     /* FMM_FP64, or a combination of FMM_P2P_F32 and
+                              FMM_M2L_F32 (FMM_MIXED: both)                   */
     int32_t want_field;    /* nonzero: fmm_evaluate may be given a field array */
     const double *root;    /* host {lo_x, lo_y, lo_z, W} of the root cube, or
                               NULL for the bounding cube of the points        */
@@ -143,8 +150,16 @@ int fmm_evaluate_batch(fmm_plan_t const *plans, const double *const *q_dev,
                        double *const *phi_dev, double *const *field_dev, int32_t count,
                        hipStream_t stream);
 
-/* Device bytes held by the plan (its workspace), for admission control. */
+/* Device bytes held by the plan (its workspace, as allocated: a chunk reused
+ * from the library's cache counts with its full size), for admission control. */
 int fmm_plan_footprint(fmm_plan_t plan, size_t *bytes);
+
+/* Device bytes the library keeps on `device` outside any plan: chunks of
+ * destroyed plans cached for reuse by later plans (at most 8 GiB per device;
+ * returned to the device when an allocation fails).  Plans built without a
+ * caller allocator also draw on HIP's default memory pool, which is set to
+ * keep freed memory for reuse. */
+int fmm_cached_bytes(int device, size_t *bytes);
 
 /* Predicted device bytes of a plan before building it (upper bound used for
  * admission: tree, lists and expansions for n points at this order). */
@@ -182,7 +197,11 @@ int fmm_plan_export_tree(fmm_plan_t plan, hipStream_t stream, double *root_host,
  * paper's DA convention: M holds the Taylor coefficients of phi_M in
  * d = r/r^2 about the box centre (Eq. P2M), L those of phi_L in d' = r - c
  * (Eq. P2L); monomials ordered by degree, then descending exponents of d1, d2
- * (Table 1).  Either pointer may be NULL.  Synchronous.
+ * (Table 1).  Either pointer may be NULL.  Synchronous.  Leaves' M are the
+ * P2M results; parents' M are rebuilt from the folded (harmonic) multipoles
+ * the evaluation's M2M produced (levels 0 and 1, which the evaluation does
+ * not need, are completed by the same M2M first); L of boxes at level >= 2
+ * are unfolded from the harmonic local expansions after the L2L (zero above).
  */
 int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, double *M_host,
                                double *L_host);
@@ -199,6 +218,35 @@ int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, double *M_ho
  */
 int fmm_plan_set_timing(fmm_plan_t plan, int on);
 int fmm_plan_read_timing(fmm_plan_t plan, double ms[16], int64_t calls[16]);
+
+/*
+ * fmm_order_table - copy one of the per-order constant tables, built on the
+ * host from closed forms in long double exactly as the device tables are
+ * (for tests of the closed forms; no device is touched).  Scaled units:
+ * Mhat_a = w_|a| M_a / h^|a| with w_n = (-1)^n / (2n-1)!!, Lhat_b = b! L_b
+ * h^(|b|+1), h the box width; monomials in the DA order of Table 1
+ * (n_p = (p+1)(p+2)(p+3)/6 of them).
+ *   which 0  derivative tables: [343][ld], offset k = (kx, ky, kz) in
+ *            {-3..3}^3 at row (kx+3)*49 + (ky+3)*7 + (kz+3) (rows of the 27
+ *            near offsets are zero); entry e of a row runs over z = 0..2,
+ *            then i = 0.., then j = 0.. with i + j + z <= 2p, holding
+ *            d^(i,j,z) (1/|x|) at x = k (Eq. m2l's derivatives of 1/r)
+ *         1  M2M (Sec. 2.2): [8][n_p][n_p], S[o][a][b] = d Mhat'_b / d Mhat_a
+ *            from the child of octant o (bits x, y, z: child centre above
+ *            the parent's) to its parent, on harmonic multipoles
+ *         2  L2L (Sec. 2.5): [8][n_p][n_p], G[o][g][b] = d Lhat'_b / d Lhat_g
+ *            from a parent to its child of octant o
+ *         3  P2M (Sec. 2.1, 3.1): [n_p][n_p], Mhat_a = sum_g P[g][a] Q_g with
+ *            the raw moments Q_g = sum q u^g, u = (x - c)/h
+ *         4  harmonic reconstruction: [(p+1)^2][n_p], the full harmonic Mhat
+ *            from its components with z exponent <= 1 (harmonic order:
+ *            degree n holds (i, n-i, 0) for i = n..0, then (i, n-1-i, 1))
+ *   out_host   host buffer of `capacity` doubles, or NULL to query the size
+ *   count      receives the number of doubles; ld the row length
+ * Returns FMM_EINVAL for a bad order, table or a buffer too small.
+ */
+int fmm_order_table(int32_t order, int32_t which, double *out_host, int64_t capacity, int64_t *count,
+                    int32_t *ld);
 
 /* Release the plan.  Stream-ordered on the plan's build stream: memory is
  * returned after work already enqueued there, and the latest evaluation on

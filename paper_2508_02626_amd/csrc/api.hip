@@ -17,6 +17,7 @@
 #include "sort.h"
 #include "tables.h"
 #include "tree_kernels.h"
+#include "batch.h"
 
 using namespace fmm;
 
@@ -295,7 +296,7 @@ struct fmm_plan_s {
         size_t got = 0;
         void *p = raw_alloc(bytes, &got);
         if (!p) return false;
-        if (owned) { bufs.push_back({p, got}); footprint += bytes; own_chunk = {(char *)p, bytes, 0}; }
+        if (owned) { bufs.push_back({p, got}); footprint += got; own_chunk = {(char *)p, bytes, 0}; }
         else { temps.push_back({p, got}); temp_chunk = {(char *)p, bytes, 0}; }
         return true;
     }
@@ -305,7 +306,7 @@ struct fmm_plan_s {
         void *p = carve(own_chunk, b);
         if (p) return (T *)p;
         p = raw_alloc(b, &got);
-        if (p) { bufs.push_back({p, got}); footprint += rounded(b); }
+        if (p) { bufs.push_back({p, got}); footprint += got; }
         return (T *)p;
     }
     template <typename T> T *temp(size_t count)
@@ -606,7 +607,7 @@ int check_options(const fmm_options_t &o, int order, int leaf_size)
         return fail(FMM_EINVAL, "uniform_depth must be -1 or 0..8");
     if (o.uniform_depth < 0 && (o.max_depth < 1 || o.max_depth > kMaxDepth))
         return fail(FMM_EINVAL, "max_depth must be 1..21");
-    if (o.precision != FMM_FP64 && o.precision != FMM_MIXED) return fail(FMM_EINVAL, "bad precision");
+    if (o.precision & ~FMM_MIXED) return fail(FMM_EINVAL, "bad precision");
     if (o.uniform_depth < 0 && leaf_size < 1) return fail(FMM_EINVAL, "leaf_size must be >= 1");
     if (order < 0 || order > kMaxOrder) return fail(FMM_EINVAL, "order must be 0..16");
     if (o.root) {
@@ -659,7 +660,7 @@ extern "C" int fmm_plan(const double *xyz_dev, int64_t n, int32_t order, int32_t
     P->D = P->uniform ? o.uniform_depth : o.max_depth;
     P->leaf_size = leaf_size;
     P->precision = o.precision;
-    P->mixed_m2l = (o.precision == FMM_MIXED && order <= 8) ? 1 : 0;
+    P->mixed_m2l = ((o.precision & FMM_M2L_F32) && order <= 8) ? 1 : 0;
     P->n = (int)n;
     P->tab = tab;
     if (o.root) for (int k = 0; k < 4; ++k) P->root[k] = o.root[k];
@@ -822,19 +823,19 @@ struct StageTimer {
 // kernels; everything else is one launch per stage for all plans.
 int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t s)
 {
+    // (no heap allocation here: the batched entry point without allocation
+    // runs this too)
     StageTimer T(count == 1 ? P[0] : nullptr, s);
-    auto make = [&](auto fn, const std::vector<int> &sel) {
-        Bases B{};
-        B.n = (int)sel.size();
-        B.b[0] = 0;
-        for (size_t i = 0; i < sel.size(); ++i) B.b[i + 1] = B.b[i] + fn(P[sel[i]]);
-        return B;
-    };
     // all plans are addressed by their index in V; a launch over a subset uses
     // a view array offset, so subsets must be contiguous runs of equal order
-    std::vector<int> all(count);
-    for (int i = 0; i < count; ++i) all[i] = i;
-    Bases Bp = make([](const fmm_plan_s *p) { return stage_blocks(p).permute; }, all);
+    auto sub = [&](int a, int b, auto fn) {
+        Bases B{};
+        B.n = b - a;
+        B.b[0] = 0;
+        for (int i = 0; i < b - a; ++i) B.b[i + 1] = B.b[i] + fn(P[a + i]);
+        return B;
+    };
+    Bases Bp = sub(0, count, [](const fmm_plan_s *p) { return stage_blocks(p).permute; });
     T.begin(0);
     launch_permute_q(V, Bp, s);
     T.end();
@@ -849,9 +850,9 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
         T2.begin(9 + part);
         for (int mixed = 0; mixed <= 1; ++mixed) { // FP64 and mixed plans in separate launches
             for (int i = 0; i < count;) {
-                if ((P[i]->precision == FMM_MIXED) != (mixed == 1)) { ++i; continue; }
+                if (((P[i]->precision & FMM_P2P_F32) != 0) != (mixed == 1)) { ++i; continue; }
                 int j = i;
-                while (j < count && (P[j]->precision == FMM_MIXED) == (mixed == 1)) ++j;
+                while (j < count && ((P[j]->precision & FMM_P2P_F32) != 0) == (mixed == 1)) ++j;
                 Bases Bq{};
                 Bq.n = j - i;
                 Bq.b[0] = 0;
@@ -867,22 +868,20 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     p2p_part(0);
     HIPCHK(hipEventRecord(F->ev_join, F->side));
     // runs of equal order (callers sort batches by order)
-    std::vector<std::pair<int, int>> runs;
+    struct Run { int first, second; };
+    Run runs_buf[kMaxBatch];
+    int nruns = 0;
     for (int i = 0; i < count;) {
         int j = i;
         while (j < count && P[j]->p == P[i]->p && P[j]->mixed_m2l == P[i]->mixed_m2l) ++j;
-        runs.push_back({i, j});
+        runs_buf[nruns++] = {i, j};
         i = j;
     }
-    auto sub = [&](int a, int b, auto fn) {
-        std::vector<int> idx;
-        for (int i = a; i < b; ++i) idx.push_back(i);
-        Bases B{};
-        B.n = b - a;
-        B.b[0] = 0;
-        for (int i = 0; i < b - a; ++i) B.b[i + 1] = B.b[i] + fn(P[a + i]);
-        return B;
-    };
+    struct Runs {
+        const Run *b, *e;
+        const Run *begin() const { return b; }
+        const Run *end() const { return e; }
+    } runs{runs_buf, runs_buf + nruns};
     T.begin(1);
     for (auto &r : runs)
         launch_p2m(P[r.first]->p, V + r.first,
@@ -948,7 +947,7 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
         launch_p2l_transform(V + r.first, sub(r.first, r.second, [](const fmm_plan_s *p) {
             return (int)ceil_div(p->nxtgt, 16) * (p->ldh / 16); }), s);
     // complete Lh rows (zero where nothing arrived, plus the second part of the sign classes)
-    launch_lh_init(V, make([](const fmm_plan_s *p) { return (int)ceil_div(p->nboxes, 4); }, all), s);
+    launch_lh_init(V, sub(0, count, [](const fmm_plan_s *p) { return (int)ceil_div(p->nboxes, 4); }), s);
     T.end();
     // L2L on the harmonic components, then full local expansions at the leaves
     T.begin(7);
@@ -994,54 +993,95 @@ extern "C" int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_de
     return FMM_OK;
 }
 
+namespace fmm {
+
+int set_error(int code, const std::string &msg) { return fail(code, msg); }
+
+// Checks a batch, makes `stream` wait for the plans' builds and fills idx[]
+// with the plans ordered by (order, FP32 M2L, position), so that equal orders
+// are contiguous.  No heap allocation.
+int batch_prepare(fmm_plan_t const *plans, const double *const *q_dev, double *const *phi_dev, int32_t count,
+                  hipStream_t stream, int *idx)
+{
+    if (count < 0 || (count > 0 && (!plans || !q_dev || !phi_dev)))
+        return fail(FMM_EINVAL, "bad batch arguments");
+    for (int i = 0; i < count; ++i)
+        if (!plans[i] || !q_dev[i] || !phi_dev[i]) return fail(FMM_EINVAL, "null entry in batch");
+    for (int i = 0; i < count; ++i)
+        if (stream != plans[i]->stream) HIPCHK(hipStreamWaitEvent(stream, plans[i]->built, 0));
+    for (int i = 0; i < count; ++i) idx[i] = i;
+    std::sort(idx, idx + count, [&](int a, int b) {
+        if (plans[a]->p != plans[b]->p) return plans[a]->p < plans[b]->p;
+        if (plans[a]->mixed_m2l != plans[b]->mixed_m2l) return plans[a]->mixed_m2l < plans[b]->mixed_m2l;
+        return a < b;
+    });
+    return 0;
+}
+
+// Runs the plans idx[c0..c1) (c1 - c0 <= kMaxBatch) with their views staged in
+// the device array Vd.  No heap allocation (the views are built on the stack
+// and copied on `stream`).
+int batch_chunk(fmm_plan_t const *plans, const int *idx, int c0, int c1, const double *const *q_dev,
+                double *const *phi_dev, double *const *field_dev, hipStream_t stream, PlanView *Vd)
+{
+    fmm_plan_s *P[kMaxBatch];
+    PlanView views[kMaxBatch];
+    const int m = c1 - c0;
+    for (int t = 0; t < m; ++t) {
+        const int i = idx[c0 + t];
+        P[t] = plans[i];
+        views[t] = plans[i]->view;
+        views[t].q_in = q_dev[i];
+        views[t].phi_out = phi_dev[i];
+        views[t].fld_out = field_dev ? field_dev[i] : nullptr;
+    }
+    HIPCHK(hipMemcpyAsync(Vd, views, sizeof(PlanView) * m, hipMemcpyHostToDevice, stream));
+    return run_pipeline(P, m, Vd, stream);
+}
+
+int batch_note_use(fmm_plan_t const *plans, int32_t count, hipStream_t stream)
+{
+    for (int i = 0; i < count; ++i)
+        if (plans[i]->note_use(stream)) return fail(FMM_EDEVICE, "event record failed");
+    return FMM_OK;
+}
+
+int plan_device(fmm_plan_t plan) { return plan->device; }
+
+} // namespace fmm
+
 extern "C" int fmm_evaluate_batch(fmm_plan_t const *plans, const double *const *q_dev,
                                   double *const *phi_dev, double *const *field_dev, int32_t count,
                                   hipStream_t stream)
 {
     g_err.clear();
-    if (count < 0 || (count > 0 && (!plans || !q_dev || !phi_dev)))
-        return fail(FMM_EINVAL, "bad batch arguments");
     if (count == 0) return FMM_OK;
-    for (int i = 0; i < count; ++i)
-        if (!plans[i] || !q_dev[i] || !phi_dev[i]) return fail(FMM_EINVAL, "null entry in batch");
-    for (int i = 0; i < count; ++i)
-        if (stream != plans[i]->stream) HIPCHK(hipStreamWaitEvent(stream, plans[i]->built, 0));
-    // order the plans by (order, mixed M2L) so that equal orders are contiguous
-    std::vector<int> idx(count);
-    for (int i = 0; i < count; ++i) idx[i] = i;
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-        if (plans[a]->p != plans[b]->p) return plans[a]->p < plans[b]->p;
-        return plans[a]->mixed_m2l < plans[b]->mixed_m2l;
-    });
+    std::vector<int> idx(count > 0 ? count : 0);
+    if (int rc = batch_prepare(plans, q_dev, phi_dev, count, stream, idx.data())) return rc;
     for (int c0 = 0; c0 < count; c0 += kMaxBatch) {
-        int c1 = std::min(count, c0 + kMaxBatch);
-        std::vector<fmm_plan_s *> P;
-        std::vector<PlanView> views;
-        for (int t = c0; t < c1; ++t) {
-            int i = idx[t];
-            P.push_back(plans[i]);
-            PlanView v = plans[i]->view;
-            v.q_in = q_dev[i];
-            v.phi_out = phi_dev[i];
-            v.fld_out = field_dev ? field_dev[i] : nullptr;
-            views.push_back(v);
-        }
+        const int c1 = std::min(count, c0 + kMaxBatch);
         PlanView *Vd = nullptr;
-        HIPCHK(hipMallocAsync((void **)&Vd, sizeof(PlanView) * views.size(), stream));
-        HIPCHK(hipMemcpyAsync(Vd, views.data(), sizeof(PlanView) * views.size(), hipMemcpyHostToDevice, stream));
-        int rc = run_pipeline(P.data(), (int)P.size(), Vd, stream);
+        HIPCHK(hipMallocAsync((void **)&Vd, sizeof(PlanView) * (c1 - c0), stream));
+        int rc = batch_chunk(plans, idx.data(), c0, c1, q_dev, phi_dev, field_dev, stream, Vd);
         (void)hipFreeAsync(Vd, stream);
         if (rc) return rc;
     }
-    for (int i = 0; i < count; ++i)
-        if (plans[i]->note_use(stream)) return fail(FMM_EDEVICE, "event record failed");
-    return FMM_OK;
+    return batch_note_use(plans, count, stream);
 }
 
 extern "C" int fmm_plan_footprint(fmm_plan_t plan, size_t *bytes)
 {
     if (!plan || !bytes) return fail(FMM_EINVAL, "null pointer argument");
     *bytes = plan->footprint;
+    return FMM_OK;
+}
+
+extern "C" int fmm_cached_bytes(int device, size_t *bytes)
+{
+    if (!bytes) return fail(FMM_EINVAL, "null pointer argument");
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    auto it = g_cache_total.find(device);
+    *bytes = it == g_cache_total.end() ? 0 : it->second;
     return FMM_OK;
 }
 
@@ -1162,15 +1202,22 @@ extern "C" int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, d
     }
     std::vector<double> buf((size_t)nb * ldm);
     if (M_host) {
-        // full multipoles of every parent (the evaluation keeps the parents'
-        // ones folded and stops at level 2): the full M2M from the leaves up
+        // The evaluation keeps the parents' multipoles folded (written by the
+        // folded M2M) and stops at level 2.  Levels 1 and 0 are completed with
+        // the same folded M2M, then every parent's full multipole is rebuilt
+        // from its folded one by the per-degree harmonic reconstruction, which
+        // is exact for harmonic expansions: the exported parents are the
+        // evaluation's own M2M results, not a separate computation.
         Bases B{};
         B.n = 1;
         B.b[0] = 0;
-        for (int l = P->depth - 1; l >= 0; --l) {
-            B.b[1] = nonleaf_groups(P, l) * (P->ldm / 16);
-            launch_m2m(P->view_dev, B, l, stream);
+        for (int l = std::min(P->depth - 1, 1); l >= 0; --l) {
+            B.b[1] = nonleaf_groups(P, l) * (P->ldmh / 16);
+            launch_m2mh(P->p, P->view_dev, B, l, stream);
         }
+        B.b[1] = (int)ceil_div(P->nboxes, 4);
+        launch_parent_mh(P->view_dev, B, 2, stream);
+        HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(stream));
         HIPCHK(hipMemcpy(buf.data(), P->view.M, 8ull * nb * ldm, hipMemcpyDeviceToHost));
         for (int b = 0; b < nb; ++b) {

@@ -236,8 +236,6 @@ struct OrderTables {
     const int *dmap;    // [ldc] additive-layout address of each compact entry
     const int *offs;    // [8][189] packed offsets (kx+3)*49 + (ky+3)*7 + (kz+3)
     const int *hoff;    // [ldh] additive D address of each harmonic index (-1 padding)
-    const double *S;    // [8][nc][nc] M2M, S[o][a][b] = d Mhat'_b / d Mhat_a
-    const double *G;    // [8][nc][nc] L2L, G[o][g][b] = d Lhat'_b / d Lhat_g
     const double *GH;   // [8][nh][nh] L2L on the harmonic components, GH[o][a][c] = d Lh'_c / d Lh_a
     const double *TM;   // [8][ldmh][ldmh] M2M on the folded positions, TM[o][a][c] = d Mh'_c / d Mh_a
     const double *HR;   // [nh][nc] full harmonic Mhat from the folded (harmonic-order) components, HR[c][b]
@@ -272,9 +270,6 @@ struct PlanView {
     const uint64_t *morton;
     const int32_t *perm;                // sorted position -> original index
     const double *xs, *ys, *zs;         // sorted positions (SoA)
-    const float *ux, *uy, *uz;          // mixed: leaf-local offsets, hi parts
-    const float *vx, *vy, *vz;          // mixed: leaf-local offsets, lo parts
-    const int32_t *leaf_of;             // sorted position -> leaf box
     const int64_t *U_off, *V_off, *W_off, *X_off;
     const int32_t *U_src, *W_src, *X_src;
     const int32_t *wsrc;                // [boxes] 1 for boxes in some W list (M2P sources), or null

@@ -8,7 +8,6 @@ void launch_permute_q(const PlanView *V, const Bases &B, hipStream_t s);   // 25
 void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block
 void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 leaves x 16 rows/block
 void launch_fold(int p, const PlanView *V, const Bases &B, hipStream_t s); // kRemapBoxes boxes/block
-void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block
 void launch_l2lh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block (harmonic rows)
 void launch_lh_init(const PlanView *V, const Bases &B, hipStream_t s);        // 4 boxes/block
 void launch_m2mh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 folded rows/block

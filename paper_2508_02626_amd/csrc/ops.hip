@@ -244,78 +244,7 @@ __global__ __launch_bounds__(256) void k_fold(const PlanView *V, Bases B)
     }
 }
 
-// ---------------- M2M on the matrix cores ----------------
-// (instantiated for M2M; the L2L runs on the harmonic components, k_l2lh)
-// A block computes a 16 x 16 tile: 16 output coefficients (rows) of 16
-// parents (columns) of one level, as sum over octants of T_o^t * X_o with the
-// 16x16x4 FP64 MFMA, one wavefront per octant (M2M sums the eight partial
-// tiles in octant order).  M2M: X_o holds the octant-o children's Mhat and the
-// tile is written to the parents.  L2L: X holds the parents' Lhat, and the
-// product of octant o is added to the octant-o children.  S is zero unless
-// |a| <= |b| and G unless g >= b, so only the contributing degree range of
-// the inner index is visited.
-constexpr int kPG = 16;
-
-template <int UP>
-__global__ __launch_bounds__(512) void k_translate(const PlanView *V, Bases B, int level)
-{
-    __shared__ double4_t red[8][64]; // M2M: per-octant partial tiles
-    const int k = find_plan(B, blockIdx.x);
-    const PlanView &v = V[k];
-    const int item = blockIdx.x - B.b[k];
-    const int MT = v.ldm / 16, g = item / MT, mt = item - g * MT;
-    const int o = threadIdx.x >> 6; // one wavefront per child octant
-    const int lane = threadIdx.x & 63, col = lane & 15, kq = lane >> 4;
-    const int lb = v.lvl_nonleaf_off[level], le = v.lvl_nonleaf_off[level + 1];
-    const int pidx = lb + g * kPG + col;
-    const int parent = pidx < le ? v.lvl_nonleaf[pidx] : -1;
-    const int nc = v.nc, ldm = v.ldm;
-    const int bA = mt * 16 + col; // row of the A operand held by this lane
-    const double *Mat = UP ? v.tab->S : v.tab->G;
-    const int dlo = degree_of(mt * 16 < nc ? mt * 16 : nc - 1);
-    const int dhi = degree_of(mt * 16 + 15 < nc ? mt * 16 + 15 : nc - 1);
-    // inner index range [k0, k1) that can contribute to this row tile
-    const int k0 = UP ? 0 : (below(dlo) & ~3);
-    const int k1 = UP ? below(dhi + 1) : nc;
-    int ch = -1; // child of this lane's parent in octant o
-    if (parent >= 0) {
-        const int cb = v.child_begin[parent], ncd = v.nchild[parent];
-        for (int i = 0; i < ncd; ++i)
-            if ((int)(v.morton[cb + i] & 7) == o) ch = cb + i;
-    }
-    double4_t acc = {0, 0, 0, 0};
-    if (__any(ch >= 0)) {
-        const double *T = Mat + (int64_t)o * nc * nc;
-        const double *X = UP ? (ch >= 0 ? v.M + (int64_t)ch * ldm : nullptr)
-                             : (parent >= 0 ? v.L + (int64_t)parent * ldm : nullptr);
-#pragma unroll 8
-        for (int kk = k0; kk < k1; kk += 4) {
-            const int a = kk + kq;
-            const double av = (bA < nc && a < nc) ? T[(int64_t)a * nc + bA] : 0.0;
-            const double bv = (X && a < nc) ? X[a] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-        }
-        if (!UP && ch >= 0) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int b = mt * 16 + 4 * r + kq; // f64 layout: lane l reg r -> row 4r + l/16
-                if (b < nc) v.L[(int64_t)ch * ldm + b] += acc[r];
-            }
-        }
-    }
-    if (!UP) return;
-    red[o][lane] = acc;
-    __syncthreads();
-    if (o != 0 || parent < 0) return;
-    double4_t sum = red[0][lane];
-#pragma unroll
-    for (int w = 1; w < 8; ++w) sum += red[w][lane]; // fixed order
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int b = mt * 16 + 4 * r + kq;
-        v.M[(int64_t)parent * ldm + b] = sum[r]; // rows >= nc are zero
-    }
-}
+constexpr int kPG = 16; // parents per translation block
 
 // Child of `parent` in octant o, or -1: the children are consecutive and their
 // Morton codes are loaded together (a non-leaf has at least one child).
@@ -399,21 +328,23 @@ __global__ __launch_bounds__(512) void k_m2mh(const PlanView *V, Bases B, int le
 
 // Parents' FP32 operand copy (mixed M2L) and, for plans with W lists, their
 // full multipoles for M2P, from the folded ones: one wavefront per non-leaf
-// box of level >= 2.
+// box of level >= 2 (full = 0: FP32 copy only, 1: also the full multipoles
+// of M2P sources).  full = 2 (export): the full multipoles of every non-leaf
+// box, of any level, and nothing else.
 __global__ __launch_bounds__(256) void k_parent_mh(const PlanView *V, Bases B, int full)
 {
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int box = (blockIdx.x - B.b[k]) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (box >= v.nboxes || v.nchild[box] == 0 || v.level[box] < 2) return;
+    if (box >= v.nboxes || v.nchild[box] == 0 || (full != 2 && v.level[box] < 2)) return;
     const OrderTables &t = *v.tab;
     const auto Mh = gptr(v.Mh + (int64_t)box * v.ldmh);
-    if (v.mixed_m2l)
+    if (v.mixed_m2l && full != 2)
         for (int c = lane; c < v.ldmh; c += 64) {
             const int h = t.mposf[c];
             gptr(v.Mhf)[(int64_t)box * v.ldmh + c] = h >= 0 ? (float)Mh[t.hpos[h]] : 0.f;
         }
-    if (!full || !v.wsrc || !v.wsrc[box]) return; // only M2P sources need it
+    if (!full || (full == 1 && (!v.wsrc || !v.wsrc[box]))) return; // only M2P sources need it
     const auto HR = gptr(t.HR);
     for (int b = lane; b < v.ldm; b += 64) {
         double s = 0.0;
@@ -688,9 +619,9 @@ __global__ __launch_bounds__(64) void k_far(const PlanView *V, Bases B)
             const int o = v.perm[i];
             v.phi_out[o] = phi + v.phi_near[i];
             if (v.fld_out) {
-                v.fld_out[3 * o] = -gx + v.fld_near[3 * i];
-                v.fld_out[3 * o + 1] = -gy + v.fld_near[3 * i + 1];
-                v.fld_out[3 * o + 2] = -gz + v.fld_near[3 * i + 2];
+                v.fld_out[3 * (int64_t)o] = -gx + v.fld_near[3 * (int64_t)i];
+                v.fld_out[3 * (int64_t)o + 1] = -gy + v.fld_near[3 * (int64_t)i + 1];
+                v.fld_out[3 * (int64_t)o + 2] = -gz + v.fld_near[3 * (int64_t)i + 2];
             }
         }
     }
@@ -776,9 +707,9 @@ __global__ __launch_bounds__(64) void k_m2p(const PlanView *V, Bases B)
         }
         if (act) { // E = -grad phi
             v.phi_near[i] += phi;
-            v.fld_near[3 * i] -= gx;
-            v.fld_near[3 * i + 1] -= gy;
-            v.fld_near[3 * i + 2] -= gz;
+            v.fld_near[3 * (int64_t)i] -= gx;
+            v.fld_near[3 * (int64_t)i + 1] -= gy;
+            v.fld_near[3 * (int64_t)i + 2] -= gz;
         }
     }
 }
@@ -791,13 +722,14 @@ __global__ __launch_bounds__(64) void k_m2p(const PlanView *V, Bases B)
 // TPG = ceil(c/2) for the c targets of the pass), and the 64 / TPG lane groups
 // split every source chunk into contiguous ranges, so that each source read
 // from LDS serves two pairs and few lanes idle.  The group partial sums are
-// combined in a fixed order at the end.  Source chunks (up to 64 particles, 32
-// in the mixed path, taken from consecutive U-list boxes) are staged in LDS as
-// 32-byte records; the next chunk is loaded into registers while the current
-// one is summed.  FP64: plain sums.  Mixed:
-// pair offsets are formed in FP64 and rounded to FP32, the pair terms are FP32
-// (hardware rsq), each lane sums a chunk in FP32 and the chunk partials are
-// accumulated in FP64.
+// combined in a fixed order at the end.  Source chunks (up to 64 particles,
+// taken from consecutive U-list boxes) are staged in LDS as 32-byte records;
+// the next chunk is loaded into registers while the current one is summed.
+// FP64: plain sums.  FP32 (mixed precision): pair offsets are formed in FP64
+// and rounded to FP32, the pair terms are FP32 (hardware rsq), and each
+// lane's sums over all its sources are compensated FP32 sums (Kahan: the
+// rounding error of every addition is carried in a second FP32 register and
+// subtracted at the end), taken to FP64 for the combination of the groups.
 struct SrcRec {
     double x, y, z, q;
 };
@@ -806,7 +738,17 @@ struct Tgt {
     double x, y, z;
     int i;
     double phi, ex, ey, ez;
+    float s[4], c[4]; // FP32 path: compensated sums (phi, ex, ey, ez) and their errors
 };
+
+// s + t with the rounding error kept in c (the true sum is s - c)
+__device__ inline void kahan_add(float &s, float &c, float t)
+{
+    const float y = t - c;
+    const float u = s + y;
+    c = (u - s) - y;
+    s = u;
+}
 
 // 1/sqrt(x) for finite x > 0: the hardware estimate (relative error about
 // 2^-24) refined by one third-order Householder step,
@@ -825,32 +767,23 @@ template <int MIXED>
 __device__ inline void p2p_range(const SrcRec *S, int lo, int hi, Tgt &a, Tgt &b)
 {
     if (MIXED) {
-        float pa = 0.f, ax = 0.f, ay = 0.f, az = 0.f, pb = 0.f, bx = 0.f, by = 0.f, bz = 0.f;
-        auto term = [](const SrcRec &s, const Tgt &t, float &p, float &fx, float &fy, float &fz) {
+        auto term = [](const SrcRec &s, Tgt &t) {
             const float dx = (float)(t.x - s.x), dy = (float)(t.y - s.y), dz = (float)(t.z - s.z);
             const float r2 = dx * dx + dy * dy + dz * dz;
             float ri = __builtin_amdgcn_rsqf(r2);
             ri = r2 > 0.f ? ri : 0.f;
             const float qr = (float)s.q * ri;
             const float qr3 = qr * ri * ri;
-            p += qr;
-            fx += qr3 * dx; fy += qr3 * dy; fz += qr3 * dz;
+            kahan_add(t.s[0], t.c[0], qr);
+            kahan_add(t.s[1], t.c[1], qr3 * dx);
+            kahan_add(t.s[2], t.c[2], qr3 * dy);
+            kahan_add(t.s[3], t.c[3], qr3 * dz);
         };
-        int jj = lo;
-        for (; jj + 2 <= hi; jj += 2) {
-            const SrcRec s0 = S[jj], s1 = S[jj + 1];
-            term(s0, a, pa, ax, ay, az);
-            term(s0, b, pb, bx, by, bz);
-            term(s1, a, pa, ax, ay, az);
-            term(s1, b, pb, bx, by, bz);
-        }
-        if (jj < hi) {
+        for (int jj = lo; jj < hi; ++jj) {
             const SrcRec s0 = S[jj];
-            term(s0, a, pa, ax, ay, az);
-            term(s0, b, pb, bx, by, bz);
+            term(s0, a);
+            term(s0, b);
         }
-        a.phi += (double)pa; a.ex += (double)ax; a.ey += (double)ay; a.ez += (double)az;
-        b.phi += (double)pb; b.ex += (double)bx; b.ey += (double)by; b.ez += (double)bz;
     } else {
         auto term = [](const SrcRec &s, Tgt &t) {
             const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
@@ -908,9 +841,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         }
         ta.phi = ta.ex = ta.ey = ta.ez = 0.0;
         tb.phi = tb.ex = tb.ey = tb.ez = 0.0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) ta.s[r] = ta.c[r] = tb.s[r] = tb.c[r] = 0.f;
         // the U list's particles as one stream, in chunks of up to CH (a chunk
         // spans several source boxes), the next chunk prefetched into registers
-        constexpr int CH = MIXED ? 32 : 64; // mixed: FP32 partial sums stay short
+        constexpr int CH = 64;
         // the U list's boxes are read 64 at a time, lane l holding the first
         // particle and the count of entry ub + l, so that walking the list
         // waits on one chain of dependent loads per 64 boxes, not one per box
@@ -961,6 +896,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             p2p_range<MIXED>(S, lo, hi, ta, tb);
             m = mn;
         }
+        if (MIXED) { // compensated FP32 sums -> FP64
+            ta.phi = (double)ta.s[0] - (double)ta.c[0]; ta.ex = (double)ta.s[1] - (double)ta.c[1];
+            ta.ey = (double)ta.s[2] - (double)ta.c[2]; ta.ez = (double)ta.s[3] - (double)ta.c[3];
+            tb.phi = (double)tb.s[0] - (double)tb.c[0]; tb.ex = (double)tb.s[1] - (double)tb.c[1];
+            tb.ey = (double)tb.s[2] - (double)tb.c[2]; tb.ez = (double)tb.s[3] - (double)tb.c[3];
+        }
         // combine the lane groups in a fixed order
         wave_sync();
         R[0][lane] = ta.phi; R[1][lane] = ta.ex; R[2][lane] = ta.ey; R[3][lane] = ta.ez;
@@ -979,9 +920,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
                 if (t >= c) continue;
                 const int i = f + ts + t;
                 v.phi_near[i] = acc[4 * h];
-                v.fld_near[3 * i] = acc[4 * h + 1];
-                v.fld_near[3 * i + 1] = acc[4 * h + 2];
-                v.fld_near[3 * i + 2] = acc[4 * h + 3];
+                v.fld_near[3 * (int64_t)i] = acc[4 * h + 1];
+                v.fld_near[3 * (int64_t)i + 1] = acc[4 * h + 2];
+                v.fld_near[3 * (int64_t)i + 2] = acc[4 * h + 3];
             }
         }
     }
@@ -1024,10 +965,6 @@ void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s)
 void launch_fold(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (nblk(B)) DISPATCH_P(p, k_fold, <<<nblk(B), 256, 0, s>>>(V, B));
-}
-void launch_m2m(const PlanView *V, const Bases &B, int level, hipStream_t s)
-{
-    if (nblk(B)) k_translate<1><<<nblk(B), 512, 0, s>>>(V, B, level);
 }
 void launch_unfold(int p, const PlanView *V, const Bases &B, int leaves_only, hipStream_t s)
 {

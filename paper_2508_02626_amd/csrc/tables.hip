@@ -23,6 +23,7 @@
 //              pi_n(P) = sum_k (-1)^k (2n-2k-1)!! / ((2n-1)!! (2k)!!) r^(2k) Lap^k P.
 //  L2L     Taylor shift of a polynomial (map M3 of Sec. 2.5).
 #include "tables.h"
+#include "fmm.h"
 
 #include <stdexcept>
 
@@ -543,7 +544,7 @@ const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::s
     t.ldd = B.ldd; t.ldc = B.ldc; t.d3 = dlayout_s1(p); t.ldmh = folded_ld(p);
     if (upload(B.D, &t.D, err) || upload(B.Df, &t.Df, err) || upload(B.dmap, &t.dmap, err) ||
         upload(B.offs, &t.offs, err) ||
-        upload(B.hoff, &t.hoff, err) || upload(B.S, &t.S, err) || upload(B.G, &t.G, err) || upload(B.GH, &t.GH, err) || upload(B.TM, &t.TM, err) ||
+        upload(B.hoff, &t.hoff, err) || upload(B.GH, &t.GH, err) || upload(B.TM, &t.TM, err) ||
         upload(B.HR, &t.HR, err) || upload(B.hpos, &t.hpos, err) ||
         upload(B.P2M, &t.P2M, err) || upload(B.P2L, &t.P2L, err) || upload(B.fold_off, &t.fold_off, err) ||
         upload(B.fold_idx, &t.fold_idx, err) || upload(B.fold_c, &t.fold_c, err) ||
@@ -576,10 +577,27 @@ int host_order_tables(int p, int which, std::vector<double> &out)
     case 1: out = B.S; return ncoef(p);
     case 2: out = B.G; return ncoef(p);
     case 3: out = B.P2M; return ncoef(p);
-    case 4: out = B.TM; return (int)B.mpos.size();
-    case 5: out = B.HR; return nharm(p);
+    case 4: out = B.HR; return ncoef(p);
     default: return -1;
     }
 }
 
 } // namespace fmm
+
+extern "C" int fmm_order_table(int32_t order, int32_t which, double *out_host, int64_t capacity,
+                               int64_t *count, int32_t *ld)
+{
+    if (order < 0 || order > fmm::kMaxOrder || which < 0 || which > 4 || !count || !ld) return FMM_EINVAL;
+    std::vector<double> t;
+    try {
+        *ld = fmm::host_order_tables(order, which, t);
+    } catch (...) {
+        return FMM_EUNSUPPORTED;
+    }
+    *count = (int64_t)t.size();
+    if (out_host) {
+        if (capacity < (int64_t)t.size()) return FMM_EINVAL;
+        std::memcpy(out_host, t.data(), sizeof(double) * t.size());
+    }
+    return FMM_OK;
+}

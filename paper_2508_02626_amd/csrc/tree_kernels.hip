@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_bbox_partial(const double *xyz, int n, 
     double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256)
         for (int k = 0; k < 3; ++k) {
-            double v = xyz[3 * i + k];
+            double v = xyz[3 * (int64_t)i + k];
             mn[k] = fmin(mn[k], v);
             mx[k] = fmax(mx[k], v);
         }
@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_keys(const double *xyz, int n, const do
     int g[3];
     bool finite = true;
     for (int k = 0; k < 3; ++k) {
-        double x = xyz[3 * i + k];
+        double x = xyz[3 * (int64_t)i + k];
         finite = finite && isfinite(x);
         double t = __dsub_rn(x, lo[k]);
         double f = floor(__dmul_rn(t, scale));
@@ -126,9 +126,9 @@ __global__ __launch_bounds__(256) void k_gather_sorted(const double *xyz, const 
     int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     int j = perm[i];
-    xs[i] = xyz[3 * j];
-    ys[i] = xyz[3 * j + 1];
-    zs[i] = xyz[3 * j + 2];
+    xs[i] = xyz[3 * (int64_t)j];
+    ys[i] = xyz[3 * (int64_t)j + 1];
+    zs[i] = xyz[3 * (int64_t)j + 2];
 }
 
 void gather_sorted(const double *xyz, const int32_t *perm, int n, double *xs, double *ys,

@@ -14,12 +14,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfmm_mi355x.so")
 
 FMM_OK, FMM_EINVAL, FMM_ENOMEM, FMM_EDEVICE, FMM_EUNSUPPORTED = 0, -1, -2, -3, -4
-FMM_FP64, FMM_MIXED = 0, 1
+FMM_FP64, FMM_P2P_F32, FMM_M2L_F32, FMM_MIXED = 0, 1, 2, 3
+PRECISIONS = {"fp64": FMM_FP64, "p2p32": FMM_P2P_F32, "m2l32": FMM_M2L_F32, "mixed": FMM_MIXED}
 
 SYMBOLS = ["fmm_default_options", "fmm_plan", "fmm_evaluate", "fmm_evaluate_batch",
            "fmm_plan_footprint", "fmm_plan_estimate", "fmm_plan_sizes", "fmm_plan_export_tree",
            "fmm_plan_export_expansions", "fmm_plan_set_timing", "fmm_plan_read_timing",
-           "fmm_plan_destroy", "fmm_last_error", "fmm_plan_batch"]
+           "fmm_plan_destroy", "fmm_last_error", "fmm_plan_batch", "fmm_cached_bytes",
+           "fmm_order_table"]
 STAGES = ["permute", "p2m", "m2m", "fold", "m2l", "p2l", "unfold", "l2l", "l2p", "p2p", "p2p_part2", "m2p"]
 
 
@@ -65,6 +67,8 @@ def lib():
         L.fmm_plan_destroy.argtypes = [vp]
         L.fmm_plan_batch.argtypes = [i32, P(vp), P(i64), P(i32), P(i32), P(Options), P(Allocator), vp, i32,
                                      P(vp)]
+        L.fmm_cached_bytes.argtypes = [ctypes.c_int, P(ctypes.c_size_t)]
+        L.fmm_order_table.argtypes = [i32, i32, vp, i64, P(i64), P(i32)]
         L.fmm_last_error.restype = ctypes.c_char_p
         L.fmm_last_error.argtypes = []
         _lib = L
@@ -91,7 +95,7 @@ def _options(uniform_depth, max_depth, precision, want_field, root):
     lib().fmm_default_options(ctypes.byref(o))
     o.uniform_depth = uniform_depth
     o.max_depth = max_depth
-    o.precision = {"fp64": FMM_FP64, "mixed": FMM_MIXED}[precision] if isinstance(precision, str) else precision
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
     o.want_field = 1 if want_field else 0
     keep = None
     if root is not None:
@@ -104,7 +108,9 @@ class Plan:
     """Octree, interaction lists and workspace for one point set (fmm_plan)."""
 
     def __init__(self, xyz, order, leaf_size=64, uniform_depth=-1, max_depth=21,
-                 precision="fp64", want_field=True, root=None, stream=None):
+                 precision="fp64", want_field=True, root=None, stream=None, allocator=None):
+        """allocator: an Allocator (C function pointers) for the plan's device
+        memory, or None for the library's own stream-ordered allocation."""
         import torch
         if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda):
             raise FmmError(FMM_EINVAL, "xyz must be a CUDA/HIP tensor")
@@ -116,7 +122,8 @@ class Plan:
         self.device = xyz.device
         o, keep = _options(uniform_depth, max_depth, precision, want_field, root)
         h = ctypes.c_void_p()
-        _check(lib().fmm_plan(_ptr(xyz), self.n, self.order, int(leaf_size), ctypes.byref(o), None,
+        _check(lib().fmm_plan(_ptr(xyz), self.n, self.order, int(leaf_size), ctypes.byref(o),
+                              ctypes.byref(allocator) if allocator is not None else None,
                               _stream(stream), ctypes.byref(h)))
         self._h = h
         del keep
@@ -254,6 +261,24 @@ def evaluate_batch(plans, qs, want_field=True, stream=None):
         hv[i] = p.handle.value
     _check(lib().fmm_evaluate_batch(hv, qv, pv, fv if want_field else None, n, _stream(stream)))
     return outs
+
+
+def order_table(order, which):
+    """fmm_order_table: one per-order constant table (host copy) as a 2-D array
+    of rows of its leading dimension."""
+    cnt, ld = ctypes.c_int64(), ctypes.c_int32()
+    _check(lib().fmm_order_table(int(order), int(which), None, 0, ctypes.byref(cnt), ctypes.byref(ld)))
+    out = np.zeros(cnt.value)
+    _check(lib().fmm_order_table(int(order), int(which), ctypes.c_void_p(out.ctypes.data), cnt.value,
+                                 ctypes.byref(cnt), ctypes.byref(ld)))
+    return out.reshape(-1, ld.value)
+
+
+def cached_bytes(device=0):
+    """Device bytes the library caches outside any plan (fmm_cached_bytes)."""
+    b = ctypes.c_size_t()
+    _check(lib().fmm_cached_bytes(int(device), ctypes.byref(b)))
+    return int(b.value)
 
 
 def estimate(n, order, leaf_size=64, uniform_depth=-1, max_depth=21, precision="fp64"):

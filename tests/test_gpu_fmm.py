@@ -158,8 +158,8 @@ def test_deterministic_repeat():
 
 @pytest.mark.parametrize("p", [4, 6, 8])
 def test_mixed_precision_error_is_bounded(p):
-    """Mixed path (FP32 P2P terms with FP64 accumulation, FP32-MFMA M2L for
-    p <= 8): stated error against the FP64 oracle FMM."""
+    """Mixed path (FP32 P2P terms with compensated FP32 sums, FP32-MFMA M2L
+    for p <= 8): stated error against the FP64 oracle FMM."""
     x, q = inputs.uniform(2000, 0)
     pl, phi, fld = gpu_solve(x, q, p, precision="mixed", **CFG1)
     t = oracle_tree(x, **CFG1)
