@@ -1,29 +1,38 @@
 #!/usr/bin/env python3
-"""Throughput of the DA-FMM hot path on one MI355X.
+"""Throughput of the DA-FMM hot path on one MI355X, at 1e-7 relative error.
 
-Workload: N = 1,000,000 points uniform in [0,1)^3 (seed 1), charges U(-1,1),
-uniform octree of depth 5 on the root cube [0,1]^3, truncation order p = 8,
-potentials and fields.  One step is one pass of the whole path over this input
-with the positions and charges already in HBM: fmm_plan (root, Morton keys,
-radix sort, boxes, U/V/W/X lists, sorted particles, M2L slot tables) followed
-by fmm_evaluate (P2M, M2M, M2L, P2L, L2L, L2P/M2P, P2P, output).  The step is
-timed for the plain FP64 path (reported as `value`) and for the mixed path
-(FP32 P2P with FP64 accumulation, FP32-MFMA M2L), reported beside it.
+Default workload (plummer4m): N = 4,000,000 points from a Plummer sphere
+(scale radius 0.05, truncated at r = 1, seed 2), charges U(-1,1), adaptive
+octree with at most 64 points per leaf, potentials and fields.  The order p is
+the lowest from 12 up whose relative L2 error of the potential against the
+FP64 direct sum, on 4096 seeded sample targets, is at most 1e-7 (the paper's
+error measure sigma of Sec. 3.5); it is 14 on this input.  One step is one pass
+of the whole path over the input with positions and charges already in HBM:
+fmm_plan (root, Morton keys, radix sort, boxes, U/V/W/X lists, sorted
+particles, M2L tiles) followed by fmm_evaluate (P2M, M2M, M2L, P2L, L2L,
+L2P/M2P, P2P, output).  `value` is the plain FP64 path; the mixed path
+(FP32 P2P terms with compensated sums, FP32 M2L where the precision rule
+allows it) is timed beside it with its own sigma.
 
-The roofline entry is for the dominant kernel, M2L on sign classes: its
-algorithmic work is, per target and per sign class of its V list with a
-member, the contraction over parity-compatible (row, column) classes plus the
-butterflies that combine the members (m2l_work); time from HIP events on the
-evaluation stream over the timed steps.  The dense harmonic count, 2 (p+1)^4
-flops per V-list pair, is reported beside it.  The CPU baseline times
-the plain oracle on the same workload once (a few seconds on the host cores).
+The roofline entry is for the dominant kernel, the sign-class M2L: its
+algorithmic work per launch is, for every target and every sign class of its
+V list with a member, the contraction over parity-compatible (row, column)
+classes of harmonic components plus the butterflies that combine the members
+(m2l_work); the time is the M2L stage from HIP events on the evaluation
+stream, averaged over the timed evaluations.  The dense counts (2 (p+1)^4 per
+V pair on harmonic components, 2 n_p^2 on the full DA vectors) are reported
+beside it.  The CPU baseline is the oracle's direct sum on the 4096 sample
+targets (the exact reference at any accuracy), timed on the host cores.
 
-Other workloads (--workload): plummer4m (4e6 Plummer points, adaptive s=64,
-p=10), batch256 (256 independent problems, one fmm_evaluate_batch), serve
-(Poisson request stream through the continuous-batching server, p50/p99),
-sweep (leaf size x order x N on Gaussian points, and the scaling with N).
-Each prints one JSON line of the same form.
+The same line carries a short served run (continuous batching, Poisson
+arrivals at half the saturated rate) with p50/p99 latency and the achieved
+sigma per requested-accuracy bucket, and the uniform 1e6-point workload at
+p = 8 (uniform1m).
 
+Other workloads (--workload): uniform1m alone, batch256 (256 independent
+problems, one fmm_evaluate_batch), serve (the served stream at four arrival
+rates), sweep (leaf size x order x N on Gaussian points), calib (a plain
+256 MiB device copy, for the HBM byte-counter calibration).
 Prints one JSON line.
 """
 import argparse
@@ -38,71 +47,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particles/s at 1e-7 rel. err (plain FP64 vs mixed); p50/p99 solve latency"
-N_DEFAULT, DEPTH, ORDER, SEED = 1_000_000, 5, 8, 1
 FP64_PEAK_TFLOPS, FP32_PEAK_TFLOPS = 78.6, 157.3
+TARGET_SIGMA = 1e-7
 
-# HBM bytes per launch of k_m2l_sym<8,double> on this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration (read x2.0,
-# write x1.0; profiles/uniform1m_hbm_traffic.txt).  Valid only for the kernel
-# sources it was measured on (kernel, shared header, tile order): a different
-# fingerprint reports null.
-M2L_TRAFFIC = {"fingerprint": "2e96bb397b2bc4cb", "bytes": (1342.94 + 83.36) * 1e6}
+# HBM bytes per launch of the dominant M2L kernel, from rocprofv3 FETCH_SIZE
+# and WRITE_SIZE scaled by a plain-copy calibration (read x2.0, write x1.0;
+# profiles/).  Each figure is valid only for the kernel sources it was
+# measured on (kernel, shared header, tile order): a different fingerprint
+# reports null.
+M2L_TRAFFIC = {
+    "uniform1m": {"fingerprint": "2e96bb397b2bc4cb", "bytes": (1342.94 + 83.36) * 1e6},
+}
 M2L_SOURCES = ("paper_2508_02626_amd/csrc/m2l.hip", "paper_2508_02626_amd/csrc/common.h",
                "paper_2508_02626_amd/csrc/m2l_tiles.hip")
 
 
-def m2l_traffic():
+def m2l_fingerprint():
     import hashlib
     h = hashlib.sha256()
     for f in M2L_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return M2L_TRAFFIC["bytes"] if h.hexdigest()[:16] == M2L_TRAFFIC["fingerprint"] else None
+    return h.hexdigest()[:16]
+
+
+def m2l_traffic(workload):
+    e = M2L_TRAFFIC.get(workload)
+    return e["bytes"] if e and e["fingerprint"] == m2l_fingerprint() else None
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_mode(x, q, precision, steps, warmup, n):
-    import torch
-    from paper_2508_02626_amd import fmm
-    phi = torch.empty(n, dtype=torch.float64, device=x.device)
-    fld = torch.empty(n, 3, dtype=torch.float64, device=x.device)
-
-    def step():
-        pl = fmm.Plan(x, ORDER, uniform_depth=DEPTH, root=[0, 0, 0, 1], precision=precision)
-        pl.evaluate(q, phi, fld)
-        return pl
-
-    for _ in range(warmup):
-        step().close()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step().close()
-    torch.cuda.synchronize()
-    step_s = (time.perf_counter() - t0) / steps
-    # stage breakdown and evaluate-only rate on one plan, HIP events per stage
-    pl = fmm.Plan(x, ORDER, uniform_depth=DEPTH, root=[0, 0, 0, 1], precision=precision)
-    pl.evaluate(q, phi, fld)
-    torch.cuda.synchronize()
-    pl.set_timing(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        pl.evaluate(q, phi, fld)
-    torch.cuda.synchronize()
-    eval_s = (time.perf_counter() - t0) / steps
-    stages = pl.read_timing()
-    sizes = pl.sizes()
-    tree = pl.export_tree()
-    sizes["p2p_pairs"] = p2p_pairs(tree)
-    m2l_flops = m2l_work(tree, ORDER)[0]
-    pl.close()
-    return dict(step_s=step_s, eval_s=eval_s, stages=stages, sizes=sizes, m2l_flops=m2l_flops,
-                phi=phi.cpu().numpy(), fld=fld.cpu().numpy())
-
-
+# ---------------------------------------------------------------- work counts
 def sym_class_counts(p):
     """Harmonic components (i, j, kz), kz in {0, 1}, |.| <= p, per parity class
     c = (i % 2) << 2 | (j % 2) << 1 | kz."""
@@ -116,13 +94,13 @@ def sym_class_counts(p):
 
 
 def m2l_work(t, p):
-    """Algorithmic flops of one M2L launch on sign classes.  For every target
-    and every sign class (|k_x|, |k_y|, |k_z|) of its V list that has a
+    """Algorithmic flops of one M2L evaluation on sign classes.  For every
+    target and every sign class (|k_x|, |k_y|, |k_z|) of its V list that has a
     member: 2 sum n_pi n_tau over row / column parity classes compatible on
     the zero axes of the class (the contraction with the representative's
     derivative table), plus the butterflies combining the members
     (|P| 2^|P| additions per column, P the axes with a +- pair).  Also returns
-    the V pairs, for the dense harmonic count 2 (p+1)^4 per pair."""
+    the number of V pairs, for the dense counts."""
     vo, vs = t["V_off"].astype(np.int64), t["V_src"].astype(np.int64)
     nv = len(vs)
     if nv == 0:
@@ -161,49 +139,11 @@ def p2p_pairs(t):
     return int((cnt * per_box).sum())
 
 
-def cpu_baseline(xh, qh):
-    """The oracle DA-FMM on the whole workload (same points, tree and order)."""
-    import oracle
-    t0 = time.perf_counter()
-    tree = oracle.Tree(xh, root=[0, 0, 0, 1], uniform_depth=DEPTH)
-    tree.fmm(ORDER, qh)
-    dt = time.perf_counter() - t0
-    return {"value": len(qh) / dt, "unit": "particles/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "seconds": dt,
-            "sample": "oracle DA-FMM (TPSA operators, memoised translations) on the whole workload: "
-                      "%d points, uniform depth %d on [0,1]^3, p=%d, potential+field" % (len(qh), DEPTH, ORDER)}
-
-
-def sampled_sigma(xh, qh, phi, fld, count=2000, seed=7):
-    import oracle
-    rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(len(qh), size=min(count, len(qh)), replace=False))
-    dp, df = oracle.direct(xh, qh, idx)
-    s_phi = float(np.linalg.norm(phi[idx] - dp) / np.linalg.norm(dp))
-    s_fld = float(np.linalg.norm(fld[idx] - df) / np.linalg.norm(df))
-    return s_phi, s_fld, len(idx)
-
-
 # Algorithmic FP64 operations of one P2P pair (potential and field):
 # 3 differences, r^2 (3 mul + 2 add), 1/r (counted as 2: square root and
 # division), q/r, q/r^3 (3 mul), 4 accumulations (1 add + 3 fused
 # multiply-adds counted as 2) = 20.
 P2P_FLOPS_PER_PAIR = 20
-
-
-def p2p_roofline(r):
-    ms = stage_avg(r["stages"])["p2p"]
-    pairs = r["sizes"]["p2p_pairs"]
-    achieved = P2P_FLOPS_PER_PAIR * pairs / (ms * 1e-3) / 1e12
-    return {"kernel": "k_p2p<0>", "bound": "alu", "pairs_per_launch": pairs, "ms_per_launch": ms,
-            "pairs_per_s": pairs / (ms * 1e-3), "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s (FP64 vector)", "frac": achieved / FP64_PEAK_TFLOPS}
-
-
-def base_record(args):
-    return {"metric": METRIC, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "data": "synthetic"}
 
 
 def stage_avg(stages):
@@ -213,103 +153,313 @@ def stage_avg(stages):
     return out
 
 
-def bench_plummer(args):
-    """4e6 Plummer points (a=0.05, r<=1, seed 2), adaptive s=64, p=10."""
+# ---------------------------------------------------------------- measurement
+def timed_steps(make_plan, q, phi, fld, steps, warmup):
+    """Mean seconds of one step (fmm_plan + fmm_evaluate) over `steps` after
+    `warmup` untimed ones; the plan is destroyed at the end of every step."""
     import torch
+    for _ in range(warmup):
+        pl = make_plan()
+        pl.evaluate(q, phi, fld)
+        pl.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pl = make_plan()
+        pl.evaluate(q, phi, fld)
+        pl.close()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def timed_evaluations(pl, q, phi, fld, steps):
+    """Mean seconds of one fmm_evaluate on a built plan, with HIP-event stage
+    times (ms per evaluation)."""
+    import torch
+    pl.evaluate(q, phi, fld)
+    torch.cuda.synchronize()
+    pl.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pl.evaluate(q, phi, fld)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = pl.read_timing()
+    pl.set_timing(False)
+    return dt, stage_avg(st)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def sample_targets(n, count, seed=7):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, size=min(count, n), replace=False))
+
+
+def m2l_roofline(tree, p, m2l_ms, kernel, workload, peak):
+    flops, nv = m2l_work(tree, p)
+    nc = (p + 1) * (p + 2) * (p + 3) // 6
+    achieved = flops / (m2l_ms * 1e-3) / 1e12
+    dense_h = 2.0 * (p + 1) ** 4 * nv
+    dense_full = 2.0 * nc * nc * nv
+    return {"kernel": kernel, "bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": m2l_traffic(workload), "traffic_unit": "HBM bytes per launch",
+            "flops_per_launch": flops, "ms_per_launch": m2l_ms, "v_pairs": nv,
+            "work": "sign-class contraction on harmonic components (unpadded) + member butterflies",
+            "dense_harmonic_flops_per_launch": dense_h,
+            "dense_harmonic_equivalent_tflops": dense_h / (m2l_ms * 1e-3) / 1e12,
+            "dense_full_flops_per_launch": dense_full,
+            "dense_full_equivalent_tflops": dense_full / (m2l_ms * 1e-3) / 1e12}
+
+
+def p2p_roofline(tree, p2p_ms, kernel):
+    pairs = p2p_pairs(tree)
+    achieved = P2P_FLOPS_PER_PAIR * pairs / (p2p_ms * 1e-3) / 1e12
+    return {"kernel": kernel, "bound": "alu", "pairs_per_launch": pairs, "ms_per_launch": p2p_ms,
+            "pairs_per_s": pairs / (p2p_ms * 1e-3), "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s (FP64 vector)", "frac": achieved / FP64_PEAK_TFLOPS}
+
+
+def base_record(args):
+    return {"metric": METRIC, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "data": "synthetic"}
+
+
+# ---------------------------------------------------------------- plummer4m
+def bench_plummer(args):
+    """The metric's workload: 4e6 Plummer points, adaptive s = 64, at the
+    lowest order that reaches sigma <= 1e-7, FP64 and mixed."""
+    import torch
+    import oracle
     from paper_2508_02626_amd import fmm, inputs
-    n = args.n if args.n != N_DEFAULT else 4_000_000
+    n = args.n or 4_000_000
     xh, qh = inputs.plummer(n, 2)
     x = torch.tensor(xh, device="cuda:0")
     q = torch.tensor(qh, device="cuda:0")
-    p = 10
+    phi = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    fld = torch.empty(n, 3, dtype=torch.float64, device="cuda:0")
+    idx = sample_targets(n, args.sigma_targets)
+    log("bench plummer4m: direct sum on %d sample targets (host)" % len(idx))
+    t0 = time.perf_counter()
+    dphi, dfld = oracle.direct(xh, qh, idx)
+    t_direct = time.perf_counter() - t0
+    log("bench plummer4m: direct sum %.1f s on %d threads" % (t_direct, oracle.num_threads()))
+
+    def sigma_of(ph, fl):
+        return rel(ph[idx], dphi), rel(fl[idx], dfld)
+
+    # order: the lowest from 12 up that reaches the target
+    scan = {}
+    orders = [args.order] if args.order else list(range(12, 17))
+    for p in orders:
+        pl = fmm.Plan(x, p, leaf_size=64)
+        pl.evaluate(q, phi, fld)
+        pl.close()
+        scan[p] = sigma_of(phi.cpu().numpy(), fld.cpu().numpy())
+        log("bench plummer4m: p=%d sigma phi %.3e field %.3e" % (p, *scan[p]))
+        if scan[p][0] <= TARGET_SIGMA:
+            break
+    p = max(scan) if args.order else next((o for o in sorted(scan) if scan[o][0] <= TARGET_SIGMA), max(scan))
     res = {}
-    for mode in ("fp64", "mixed"):
-        def step():
-            pl = fmm.Plan(x, p, leaf_size=64, precision=mode)
-            pl.evaluate(q)
-            return pl
-        for _ in range(args.warmup):
-            step().close()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            step().close()
-        torch.cuda.synchronize()
-        step_s = (time.perf_counter() - t0) / args.steps
-        pl = fmm.Plan(x, p, leaf_size=64, precision=mode)
-        phi, fld = pl.evaluate(q)
-        torch.cuda.synchronize()
-        pl.set_timing(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            pl.evaluate(q, phi, fld)
-        torch.cuda.synchronize()
-        eval_s = (time.perf_counter() - t0) / args.steps
-        st, sizes = pl.read_timing(), pl.sizes()
+    for mode in (["fp64"] if args.no_mixed else ["fp64", "mixed"]):
+        mk = lambda: fmm.Plan(x, p, leaf_size=64, precision=mode)
+        step_s = timed_steps(mk, q, phi, fld, args.steps, args.warmup)
+        pl = mk()
+        eval_s, stages = timed_evaluations(pl, q, phi, fld, args.steps)
+        r = dict(step_s=step_s, eval_s=eval_s, stages=stages, sizes=pl.sizes())
         if mode == "fp64":
-            tree = pl.export_tree()
-            sizes["p2p_pairs"] = p2p_pairs(tree)
-            sizes["m2l_flops"] = m2l_work(tree, p)[0]
+            r["tree"] = pl.export_tree()
         pl.close()
-        ph, fh = phi.cpu().numpy(), fld.cpu().numpy()
-        sp, sf, nt = sampled_sigma(xh, qh, ph, fh, count=1000)
-        log("bench plummer: %s step %.2f ms eval %.2f ms sigma %.3e" % (mode, 1e3 * step_s, 1e3 * eval_s, sp))
-        res[mode] = dict(step_s=step_s, eval_s=eval_s, stages=stage_avg(st), sizes=sizes, sigma=sp, sigma_f=sf,
-                         phi=ph, fld=fh)
-    # the same problem at the order that reaches a relative error of 1e-7
-    hi = {}
-    ph = 14
-    for mode in ("fp64", "mixed"):
-        pl = fmm.Plan(x, ph, leaf_size=64, precision=mode)
-        phi, fld = pl.evaluate(q)
-        pl.close()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(max(1, args.steps // 2)):
-            pl = fmm.Plan(x, ph, leaf_size=64, precision=mode)
-            pl.evaluate(q, phi, fld)
-            pl.close()
-        torch.cuda.synchronize()
-        step_s = (time.perf_counter() - t0) / max(1, args.steps // 2)
-        sp, sf, nt = sampled_sigma(xh, qh, phi.cpu().numpy(), fld.cpu().numpy(), count=1000)
-        log("bench plummer: p=%d %s step %.2f ms sigma %.3e" % (ph, mode, 1e3 * step_s, sp))
-        hi[mode] = {"value": n / step_s, "ms_per_step": 1e3 * step_s, "sigma_phi_vs_direct": sp,
-                    "sigma_field_vs_direct": sf}
-    f, m = res["fp64"], res["mixed"]
-    flops = f["sizes"]["m2l_flops"]
-    dense = 2.0 * (p + 1) ** 4 * f["sizes"]["V"]
-    m2l_ms = f["stages"]["m2l"]
+        r["phi"], r["fld"] = phi.cpu().numpy(), fld.cpu().numpy()
+        r["sigma"], r["sigma_f"] = sigma_of(r["phi"], r["fld"])
+        log("bench plummer4m: p=%d %s step %.2f ms eval %.2f ms sigma %.3e" %
+            (p, mode, 1e3 * step_s, 1e3 * eval_s, r["sigma"]))
+        res[mode] = r
+    f = res["fp64"]
+    kern = "k_m2l_symh<%d,*>" % p if p >= 12 else "k_m2l_sym<%d,double>" % p
     out = base_record(args)
     out.update({
         "value": n / f["step_s"], "ms_per_step": 1e3 * f["step_s"], "dtype": "f64",
-        "config": {"workload": "Plummer sphere: N=%d, scale 0.05, truncated at r=1 (seed 2), q~U(-1,1), "
-                               "adaptive octree s=64, p=10, potential+field" % n, "n": n, "order": p,
-                   "tree": "adaptive s=64", "step": "fmm_plan + fmm_evaluate", "sizes": f["sizes"]},
+        "config": {"workload": "Plummer sphere: N=%d, scale radius 0.05, truncated at r=1 (seed 2), q~U(-1,1), "
+                               "adaptive octree s=64, order p=%d (lowest order from 12 with sampled sigma <= 1e-7), "
+                               "potential+field" % (n, p),
+                   "n": n, "order": p, "leaf_size": 64, "step": "fmm_plan + fmm_evaluate", "sizes": f["sizes"]},
         "accuracy": {"sigma_phi_vs_direct": f["sigma"], "sigma_field_vs_direct": f["sigma_f"],
-                     "targets_sampled": 1000},
+                     "targets_sampled": len(idx), "target": TARGET_SIGMA, "meets_target": f["sigma"] <= TARGET_SIGMA,
+                     "sigma_phi_by_order": {str(o): s[0] for o, s in scan.items()}},
         "eval_only": {"value": n / f["eval_s"], "ms": 1e3 * f["eval_s"]},
         "stage_ms": f["stages"],
-        "roofline": {"kernel": "k_m2l_sym<10,double>", "bound": "mfma", "achieved": flops / (m2l_ms * 1e-3) / 1e12,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": flops / (m2l_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "traffic": None,
-                     "flops_per_launch": flops, "ms_per_launch": m2l_ms,
-                     "work": "sign-class contraction (unpadded) + member butterflies",
-                     "dense_harmonic_flops_per_launch": dense,
-                     "dense_equivalent_tflops": dense / (m2l_ms * 1e-3) / 1e12},
-        "p2p": {"kernel": "k_p2p<0>", "pairs_per_launch": f["sizes"]["p2p_pairs"],
-                "pairs_per_s": f["sizes"]["p2p_pairs"] / (1e-3 * f["stages"]["p2p"]),
-                "achieved": P2P_FLOPS_PER_PAIR * f["sizes"]["p2p_pairs"] / (1e-3 * f["stages"]["p2p"]) / 1e12,
-                "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s (FP64 vector)"},
-        "mixed": {"value": n / m["step_s"], "ms_per_step": 1e3 * m["step_s"], "eval_ms": 1e3 * m["eval_s"],
-                  "sigma_phi_vs_direct": m["sigma"], "sigma_field_vs_direct": m["sigma_f"],
-                  "rel_l2_vs_fp64_path_phi": float(np.linalg.norm(m["phi"] - f["phi"]) / np.linalg.norm(f["phi"])),
-                  "rel_l2_vs_fp64_path_field": float(np.linalg.norm(m["fld"] - f["fld"]) / np.linalg.norm(f["fld"])),
-                  "dtype": "f64 with f32 P2P terms (M2L stays FP64 at p=10)", "stage_ms": m["stages"]},
-        "order_for_1e-7": {"order": ph, "fp64": hi["fp64"], "mixed": hi["mixed"]},
+        "roofline": m2l_roofline(f["tree"], p, f["stages"]["m2l"], kern, "plummer4m", FP64_PEAK_TFLOPS),
+        "p2p": p2p_roofline(f["tree"], f["stages"]["p2p"], "k_p2p<0>"),
     })
+    if "mixed" in res:
+        m = res["mixed"]
+        out["mixed"] = {"value": n / m["step_s"], "ms_per_step": 1e3 * m["step_s"],
+                        "speedup_vs_fp64": f["step_s"] / m["step_s"],
+                        "eval_only_value": n / m["eval_s"], "eval_ms": 1e3 * m["eval_s"],
+                        "sigma_phi_vs_direct": m["sigma"], "sigma_field_vs_direct": m["sigma_f"],
+                        "meets_target": m["sigma"] <= TARGET_SIGMA,
+                        "rel_l2_vs_fp64_path_phi": rel(m["phi"], f["phi"]),
+                        "rel_l2_vs_fp64_path_field": rel(m["fld"], f["fld"]),
+                        "dtype": "f64 with f32 P2P terms (compensated sums) and the FP32 M2L of this order's rule",
+                        "stage_ms": m["stages"]}
+    cores = oracle.num_threads()
+    out["cpu_baseline"] = {"value": len(idx) / t_direct, "unit": "particles/s", "cores": cores, "kind": "oracle",
+                           "seconds": t_direct,
+                           "sample": "oracle direct O(N^2) sum (FP64, exact at any accuracy) for %d seeded sample "
+                                     "targets against all %d sources of this workload" % (len(idx), n)}
     return out
 
 
+# ---------------------------------------------------------------- uniform1m
+def bench_uniform(args, with_cpu=True):
+    """1e6 uniform points in [0,1)^3 (seed 1), uniform depth 5 on [0,1]^3,
+    p = 8, FP64 and mixed."""
+    import torch
+    import oracle
+    from paper_2508_02626_amd import fmm, inputs
+    n, depth, p = 1_000_000, 5, 8
+    xh, qh = inputs.uniform(n, 1)
+    x = torch.tensor(xh, device="cuda:0")
+    q = torch.tensor(qh, device="cuda:0")
+    phi = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    fld = torch.empty(n, 3, dtype=torch.float64, device="cuda:0")
+    idx = sample_targets(n, 2000)
+    dphi, dfld = oracle.direct(xh, qh, idx)
+    res = {}
+    for mode in (["fp64"] if args.no_mixed else ["fp64", "p2p32", "m2l32", "mixed"]):
+        mk = lambda: fmm.Plan(x, p, uniform_depth=depth, root=[0, 0, 0, 1], precision=mode)
+        step_s = timed_steps(mk, q, phi, fld, args.steps, args.warmup)
+        pl = mk()
+        eval_s, stages = timed_evaluations(pl, q, phi, fld, args.steps)
+        r = dict(step_s=step_s, eval_s=eval_s, stages=stages)
+        if mode == "fp64":
+            r["tree"] = pl.export_tree()
+        pl.close()
+        r["phi"], r["fld"] = phi.cpu().numpy(), fld.cpu().numpy()
+        r["sigma"], r["sigma_f"] = rel(r["phi"][idx], dphi), rel(r["fld"][idx], dfld)
+        log("bench uniform1m: %s step %.3f ms eval %.3f ms sigma %.3e" % (mode, 1e3 * step_s, 1e3 * eval_s, r["sigma"]))
+        res[mode] = r
+    f = res["fp64"]
+    out = {"value": n / f["step_s"], "ms_per_step": 1e3 * f["step_s"], "dtype": "f64",
+           "config": {"workload": "uniform cube: N=%d uniform in [0,1)^3 (seed 1), q~U(-1,1), uniform octree depth 5 "
+                                  "on [0,1]^3, order p=8, potential+field" % n, "n": n, "order": p},
+           "accuracy": {"sigma_phi_vs_direct": f["sigma"], "sigma_field_vs_direct": f["sigma_f"],
+                        "targets_sampled": len(idx)},
+           "eval_only": {"value": n / f["eval_s"], "ms": 1e3 * f["eval_s"]},
+           "stage_ms": f["stages"],
+           "roofline": m2l_roofline(f["tree"], p, f["stages"]["m2l"], "k_m2l_sym<8,double>", "uniform1m",
+                                    FP64_PEAK_TFLOPS),
+           "p2p": p2p_roofline(f["tree"], f["stages"]["p2p"], "k_p2p<0>")}
+    for mode in ("p2p32", "m2l32", "mixed"):
+        if mode not in res:
+            continue
+        m = res[mode]
+        e = {"value": n / m["step_s"], "ms_per_step": 1e3 * m["step_s"], "eval_ms": 1e3 * m["eval_s"],
+             "sigma_phi_vs_direct": m["sigma"], "sigma_field_vs_direct": m["sigma_f"],
+             "rel_l2_vs_fp64_path_phi": rel(m["phi"], f["phi"]),
+             "rel_l2_vs_fp64_path_field": rel(m["fld"], f["fld"]), "stage_ms": m["stages"]}
+        if mode in ("m2l32", "mixed"):
+            mm = m["stages"]["m2l"]
+            e["m2l_kernel"], e["m2l_ms"] = "k_m2l_sym<8,float>", mm
+            e["m2l_roofline"] = m2l_roofline(f["tree"], p, mm, "k_m2l_sym<8,float>", "-", FP32_PEAK_TFLOPS)
+        if mode in ("p2p32", "mixed"):
+            e["p2p"] = p2p_roofline(f["tree"], m["stages"]["p2p"], "k_p2p<1>")
+        out[mode if mode == "mixed" else "only_" + mode] = e
+    if with_cpu:
+        t0 = time.perf_counter()
+        tree = oracle.Tree(xh, root=[0, 0, 0, 1], uniform_depth=depth)
+        tree.fmm(p, qh)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n / dt, "unit": "particles/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "seconds": dt,
+                               "sample": "oracle DA-FMM (TPSA operators, memoised translations) on the whole "
+                                         "workload: %d points, uniform depth 5, p=8, potential+field" % n}
+    return out
+
+
+# ---------------------------------------------------------------- served
+def served_run(nreq, fracs, sigma_per_bucket=6, sigma_targets=256):
+    """Poisson stream through the continuous-batching server: N log-uniform in
+    [1e3, 1e6], uniform or Plummer, rel. error in {1e-4, 1e-7, 1e-9} -> p in
+    {4, 8, 12}.  Saturated throughput first, then the given arrival rates
+    (fractions of it), p50/p99 latency per rate, and the achieved sigma of the
+    first `sigma_per_bucket` requests of every accuracy bucket (sampled direct
+    sum)."""
+    import oracle
+    from paper_2508_02626_amd import inputs, serve
+    warm = max(nreq // 10, 5)
+    reqs = [inputs.served_request(i) for i in range(nreq + warm)]
+    ntot = sum(len(q) for _, q, _ in reqs[warm:])
+    srv = serve.Server(hbm_budget_bytes=64 << 30, slots=4)
+    futs = [srv.submit(x, q, e) for x, q, e in reqs[:warm]]
+    [f.result() for f in futs]
+    t0 = time.perf_counter()
+    futs = [srv.submit(x, q, e) for x, q, e in reqs[warm:]]
+    sat = [f.result() for f in futs]
+    sat_s = time.perf_counter() - t0
+    rate_sat = nreq / sat_s
+    log("bench serve: saturated %.1f req/s, %.3e particles/s" % (rate_sat, ntot / sat_s))
+    rates = {}
+    for frac in fracs:
+        lam = frac * rate_sat
+        arr = inputs.poisson_arrivals(nreq, lam, seed=5)
+        futs = []
+        t0 = time.perf_counter()
+        for (x, q, e), ta in zip(reqs[warm:], arr):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            futs.append(srv.submit(x, q, e))
+        lat = [f.result()[2] for f in futs]
+        span = time.perf_counter() - t0
+        st = serve.latency_stats(lat)
+        st.update({"arrival_rate_req_s": lam, "throughput_particles_s": ntot / span})
+        rates["%.2f" % frac] = st
+        log("bench serve: rate %.2f x sat: p50 %.1f ms p99 %.1f ms" % (frac, st["p50_ms"], st["p99_ms"]))
+    srv.close()
+    # achieved accuracy per bucket, from the saturated run's results
+    buckets = {}
+    for (x, q, e), (phi, fld, _) in zip(reqs[warm:], sat):
+        b = buckets.setdefault(e, {"num": 0.0, "den": 0.0, "num_f": 0.0, "den_f": 0.0, "requests": 0})
+        if b["requests"] >= sigma_per_bucket:
+            continue
+        idx = sample_targets(len(q), sigma_targets, seed=11)
+        dp, df = oracle.direct(x, q, idx)
+        b["num"] += float(np.sum((phi[idx] - dp) ** 2)); b["den"] += float(np.sum(dp ** 2))
+        b["num_f"] += float(np.sum((fld[idx] - df) ** 2)); b["den_f"] += float(np.sum(df ** 2))
+        b["requests"] += 1
+    acc = {}
+    for e, b in sorted(buckets.items(), reverse=True):
+        acc["%g" % e] = {"order": serve.order_for(e), "precision": serve.precision_for(e),
+                         "sigma_phi_vs_direct": float(np.sqrt(b["num"] / b["den"])),
+                         "sigma_field_vs_direct": float(np.sqrt(b["num_f"] / b["den_f"])),
+                         "meets_request": bool(np.sqrt(b["num"] / b["den"]) <= e),
+                         "requests_sampled": b["requests"], "targets_per_request": sigma_targets}
+    return {"saturated": dict(serve.latency_stats([s[2] for s in sat]), requests_per_s=rate_sat,
+                              throughput_particles_s=ntot / sat_s),
+            "latency_by_load": rates, "accuracy_by_bucket": acc, "requests": nreq, "particles": ntot,
+            "config": "served Poisson stream: %d requests (+%d warm-up, seeds 10000+i), N log-uniform in "
+                      "[1e3,1e6], uniform or Plummer, rel. error {1e-4,1e-7,1e-9} -> p {4,8,12} (mixed precision "
+                      "only for 1e-4), adaptive s=64, 4 slots, 64 GiB admission budget" % (nreq, warm)}
+
+
+def bench_serve(args):
+    s = served_run(args.requests, (0.25, 0.5, 0.75, 0.9))
+    out = base_record(args)
+    out.update({"value": s["saturated"]["throughput_particles_s"],
+                "ms_per_step": 1e3 / s["saturated"]["requests_per_s"],
+                "dtype": "f64 (1e-7, 1e-9 buckets) / mixed (1e-4 bucket)",
+                "config": {"workload": s["config"], "requests": s["requests"]},
+                "saturated": s["saturated"], "latency_by_load": s["latency_by_load"],
+                "accuracy_by_bucket": s["accuracy_by_bucket"], "roofline": None})
+    return out
+
+
+# ---------------------------------------------------------------- batch256
 def bench_batch(args):
     """256 problems (N log-uniform in [1e3, 2e5], half uniform, half 8-cluster
     mixtures, p in {4,6,8}), adaptive s=64, mixed precision: plans + one
@@ -345,7 +495,6 @@ def bench_batch(args):
                 pl.close()
         torch.cuda.synchronize()
         times[batched] = (time.perf_counter() - t0) / args.steps
-    # evaluate-only, plans built once
     ps = plans()
     torch.cuda.synchronize()
     ev = {}
@@ -380,57 +529,7 @@ def bench_batch(args):
     return out
 
 
-def bench_serve(args):
-    """Poisson stream through the continuous-batching server: N log-uniform in
-    [1e3, 1e6], uniform or Plummer, rel. error in {1e-4, 1e-7, 1e-9} -> p in
-    {4, 8, 12}; saturated throughput first, then arrival rates 0.25/0.5/0.75/0.9
-    of it; p50/p99 latency per rate."""
-    import torch
-    from paper_2508_02626_amd import inputs, serve
-    nreq, warm = args.requests, max(args.requests // 10, 5)
-    reqs = [inputs.served_request(i) for i in range(nreq + warm)]
-    ntot = sum(len(q) for _, q, _ in reqs[warm:])
-    srv = serve.Server(hbm_budget_bytes=64 << 30, slots=4)
-    # saturated: everything submitted at once
-    futs = [srv.submit(x, q, e) for x, q, e in reqs[:warm]]
-    [f.result() for f in futs]
-    t0 = time.perf_counter()
-    futs = [srv.submit(x, q, e) for x, q, e in reqs[warm:]]
-    lat_sat = [f.result()[2] for f in futs]
-    sat_s = time.perf_counter() - t0
-    rate_sat = nreq / sat_s
-    log("bench serve: saturated %.1f req/s, %.3e particles/s" % (rate_sat, ntot / sat_s))
-    rates = {}
-    for frac in (0.25, 0.5, 0.75, 0.9):
-        lam = frac * rate_sat
-        arr = inputs.poisson_arrivals(nreq, lam, seed=5)
-        futs = []
-        t0 = time.perf_counter()
-        for (x, q, e), ta in zip(reqs[warm:], arr):
-            dt = ta - (time.perf_counter() - t0)
-            if dt > 0:
-                time.sleep(dt)
-            futs.append(srv.submit(x, q, e))
-        lat = [f.result()[2] for f in futs]
-        span = time.perf_counter() - t0
-        st = serve.latency_stats(lat)
-        st.update({"arrival_rate_req_s": lam, "throughput_particles_s": ntot / span})
-        rates["%.2f" % frac] = st
-        log("bench serve: rate %.2f x sat: p50 %.1f ms p99 %.1f ms" % (frac, st["p50_ms"], st["p99_ms"]))
-    srv.close()
-    out = base_record(args)
-    out.update({
-        "value": ntot / sat_s, "ms_per_step": 1e3 * sat_s / nreq, "dtype": "f64 (p=12) / mixed (p<=8)",
-        "config": {"workload": "served Poisson stream: %d requests (+%d warm-up), N log-uniform in [1e3,1e6], "
-                               "uniform or Plummer, rel. error {1e-4,1e-7,1e-9} -> p {4,8,12}, adaptive s=64, "
-                               "4 slots, 64 GiB admission budget" % (nreq, warm), "requests": nreq},
-        "saturated": dict(serve.latency_stats(lat_sat), requests_per_s=rate_sat),
-        "latency_by_load": rates,
-        "roofline": None,
-    })
-    return out
-
-
+# ---------------------------------------------------------------- sweep
 def bench_sweep(args):
     """Leaf-size and order sweep and the scaling with N, on the distribution
     of the paper's sweeps (3-D Gaussian, unit standard deviation, adaptive
@@ -439,6 +538,7 @@ def bench_sweep(args):
     behind the paper's optimal-s table); then the step time over N at
     p in {2, 6, 10} with that leaf size, and the slope of its log-log fit."""
     import torch
+    import oracle
     from paper_2508_02626_amd import fmm, inputs
     sizes_n = [100_000, 1_000_000, 10_000_000]
     orders = [2, 4, 6, 8, 10]
@@ -470,18 +570,18 @@ def bench_sweep(args):
             best[n][p] = min(row, key=row.get)
             log("bench sweep: N=%d p=%d best s=%d (%.2f ms)" % (n, p, best[n][p], row[best[n][p]]))
         del x, q
-    # accuracy of each order against the direct sum at N = 1e6, best leaf size
     xh, qh = inputs.gaussian(1_000_000, 3)
     x = torch.tensor(xh, device="cuda:0")
     q = torch.tensor(qh, device="cuda:0")
+    idx = sample_targets(len(qh), 500)
+    dp, _ = oracle.direct(xh, qh, idx)
     sigma = {}
     for p in orders:
         pl = fmm.Plan(x, p, leaf_size=best[1_000_000][p], precision="fp64")
         phi, fld = pl.evaluate(q)
         pl.close()
-        sigma[p] = sampled_sigma(xh, qh, phi.cpu().numpy(), fld.cpu().numpy(), count=500)[0]
+        sigma[p] = rel(phi.cpu().numpy()[idx], dp)
     del x, q
-    # scaling with N at the best leaf size of the nearest swept N
     scan = [10_000, 30_000, 100_000, 300_000, 1_000_000, 3_000_000, 10_000_000]
     linear = {}
     for p in (2, 6, 10):
@@ -518,93 +618,64 @@ def bench_sweep(args):
     return out
 
 
+def bench_calib(args):
+    """A plain device-to-device copy of 256 MiB, twice: the reference for the
+    HBM byte counters (FETCH_SIZE, WRITE_SIZE) of rocprofv3."""
+    import torch
+    nbytes = 256 << 20
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"workload": "calib", "bytes_copied_per_launch": nbytes, "launches": 2}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=N_DEFAULT)
-    ap.add_argument("--workload", default="uniform1m", choices=["uniform1m", "plummer4m", "batch256", "serve", "sweep"])
+    ap.add_argument("--n", type=int, default=0, help="points of the plummer4m workload (default 4e6)")
+    ap.add_argument("--order", type=int, default=0, help="plummer4m: fixed order instead of the scan")
+    ap.add_argument("--sigma-targets", type=int, default=4096)
+    ap.add_argument("--workload", default="plummer4m",
+                    choices=["plummer4m", "uniform1m", "batch256", "serve", "sweep", "calib"])
     ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--serve-requests", type=int, default=120, help="requests of the served run in the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-uniform", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs a solve on a single GPU "
               "and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
-    from paper_2508_02626_amd import inputs
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    if args.workload != "uniform1m":
-        fn = {"plummer4m": bench_plummer, "batch256": bench_batch, "serve": bench_serve,
-              "sweep": bench_sweep}[args.workload]
-        print(json.dumps(fn(args)), flush=True)
-        return
-    n = args.n
-    xh, qh = inputs.uniform(n, SEED)
-    x = torch.tensor(xh, device="cuda:0")
-    q = torch.tensor(qh, device="cuda:0")
-    log("bench: n=%d depth=%d p=%d steps=%d warmup=%d" % (n, DEPTH, ORDER, args.steps, args.warmup))
-    res = {}
-    for mode in (["fp64"] if args.no_mixed else ["fp64", "mixed"]):
-        r = run_mode(x, q, mode, args.steps, args.warmup, n)
-        r["sigma_phi"], r["sigma_field"], r["sigma_targets"] = sampled_sigma(xh, qh, r["phi"], r["fld"])
-        log("bench: %s step %.3f ms eval %.3f ms sigma %.3e" % (mode, 1e3 * r["step_s"], 1e3 * r["eval_s"],
-                                                                r["sigma_phi"]))
-        res[mode] = r
-    f = res["fp64"]
-    nv = f["sizes"]["V"]
-    m2l_ms = f["stages"]["m2l"][0] / max(f["stages"]["m2l"][1], 1)
-    flops = f["m2l_flops"]
-    dense = 2.0 * (ORDER + 1) ** 4 * nv
-    achieved = flops / (m2l_ms * 1e-3) / 1e12
-    out = {
-        "metric": METRIC,
-        "value": n / f["step_s"],
-        "unit": "particles/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * f["step_s"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "uniform cube: N=%d uniform in [0,1)^3 (seed %d), q~U(-1,1), uniform octree "
-                               "depth 5 on [0,1]^3, order p=8, potential+field" % (n, SEED),
-                   "n": n, "order": ORDER, "tree": "uniform depth 5", "step": "fmm_plan + fmm_evaluate"},
-        "accuracy": {"sigma_phi_vs_direct": f["sigma_phi"], "sigma_field_vs_direct": f["sigma_field"],
-                     "targets_sampled": f["sigma_targets"]},
-        "eval_only": {"value": n / f["eval_s"], "ms": 1e3 * f["eval_s"]},
-        "stage_ms": stage_avg(f["stages"]),
-        "roofline": {"kernel": "k_m2l_sym<8,double>", "bound": "mfma", "achieved": achieved,
-                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
-                     "traffic": m2l_traffic(), "traffic_unit": "bytes per launch",
-                     "flops_per_launch": flops, "ms_per_launch": m2l_ms,
-                     "work": "sign-class contraction (unpadded) + member butterflies",
-                     "dense_harmonic_flops_per_launch": dense,
-                     "dense_equivalent_tflops": dense / (m2l_ms * 1e-3) / 1e12},
-        "p2p": p2p_roofline(f),
-    }
-    if "mixed" in res:
-        m = res["mixed"]
-        mm = m["stages"]["m2l"][0] / max(m["stages"]["m2l"][1], 1)
-        out["mixed"] = {"rel_l2_vs_fp64_path_phi": float(np.linalg.norm(m["phi"] - f["phi"]) / np.linalg.norm(f["phi"])),
-                        "rel_l2_vs_fp64_path_field": float(np.linalg.norm(m["fld"] - f["fld"]) / np.linalg.norm(f["fld"])),
-                        "value": n / m["step_s"], "ms_per_step": 1e3 * m["step_s"],
-                        "eval_only_value": n / m["eval_s"], "eval_ms": 1e3 * m["eval_s"],
-                        "sigma_phi_vs_direct": m["sigma_phi"], "sigma_field_vs_direct": m["sigma_field"],
-                        "dtype": "f64 with f32 P2P terms and f32 MFMA M2L",
-                        "stage_ms": stage_avg(m["stages"]),
-                        "m2l_kernel": "k_m2l_sym<8,float>", "m2l_ms": mm,
-                        "m2l_tflops": flops / (mm * 1e-3) / 1e12, "m2l_peak_fp32": FP32_PEAK_TFLOPS,
-                        "p2p_pairs_per_s": m["sizes"]["p2p_pairs"] / (1e-3 * stage_avg(m["stages"])["p2p"])}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(xh, qh)
+    if args.workload == "plummer4m":
+        out = bench_plummer(args)
+        if args.no_cpu_baseline:
+            out.pop("cpu_baseline", None)
+        if not args.no_serve:
+            s = served_run(args.serve_requests, (0.5,))
+            out["served"] = {"p50_ms": s["latency_by_load"]["0.50"]["p50_ms"],
+                             "p99_ms": s["latency_by_load"]["0.50"]["p99_ms"],
+                             "arrival_rate_req_s": s["latency_by_load"]["0.50"]["arrival_rate_req_s"],
+                             "throughput_particles_s": s["latency_by_load"]["0.50"]["throughput_particles_s"],
+                             "saturated": s["saturated"], "accuracy_by_bucket": s["accuracy_by_bucket"],
+                             "config": s["config"] + "; arrivals at 0.5 x the saturated rate"}
+        if not args.no_uniform:
+            out["uniform1m"] = bench_uniform(args, with_cpu=not args.no_cpu_baseline)
+    elif args.workload == "uniform1m":
+        out = base_record(args)
+        out.update(bench_uniform(args, with_cpu=not args.no_cpu_baseline))
+    else:
+        out = {"batch256": bench_batch, "serve": bench_serve, "sweep": bench_sweep,
+               "calib": bench_calib}[args.workload](args)
     print(json.dumps(out), flush=True)
 
 

@@ -41,3 +41,10 @@ def test_admission_is_thread_safe():
     for t in ts:
         t.join()
     assert a.in_flight == 0 and len(ok) == 8000
+
+
+def test_precision_policy():
+    from paper_2508_02626_amd.serve import precision_for
+    # the mixed path only where its own error is far below the request
+    assert precision_for(1e-4) == "mixed"
+    assert precision_for(1e-7) == "fp64" and precision_for(1e-9) == "fp64"
