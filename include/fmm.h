@@ -212,7 +212,8 @@ int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, double *M_ho
  * fmm_plan_read_timing waits for the recorded events, adds their durations
  * (milliseconds) per stage into ms[0..15] and the number of timed evaluations
  * into calls[0..15], and clears the records.  Stages: 0 permute charges,
- * 1 P2M, 2 M2M, 3 fold, 4 M2L, 5 P2L, 6 unfold, 7 L2L, 8 L2P+output,
+ * 1 P2M raw moments, 2 M2M, 3 folded multipoles of the leaves (and full
+ * ones of M2P sources), 4 M2L, 5 P2L, 6 unfold, 7 L2L, 8 L2P+output,
  * 9 and 10 the two parts of P2P and 11 M2P (on the plan's side stream,
  * concurrent with stages 1-3 and 5-7 respectively).
  */

@@ -590,6 +590,10 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     v.U_src = P->src[0]; v.W_src = P->src[2]; v.X_src = P->src[3]; v.wsrc = P->wsrc;
     v.m2l_tgt = slots; v.vslot = vslot; v.leaves = leaves; v.xtgt = xtgt;
     v.lvl_nonleaf = nonleaf; v.lvl_nonleaf_off = lnl_off; v.tab = P->tab;
+    // row `nb` of the folded multipoles is the all-zero operand of absent M2L
+    // sources; it is never written by an evaluation
+    launch_zero(Mh + (size_t)nb * P->ldmh, P->ldmh, s);
+    if (Mhf) launch_zero_f32(Mhf + (size_t)nb * P->ldmh, P->ldmh, s);
     v.qs = qs; v.M = M; v.Mh = Mh; v.Lh = Lh; v.Lh2 = Lh2; v.m2l_parts = P->m2l_parts; v.L = L; v.Mhf = Mhf; v.phi_near = pf; v.fld_near = ff;
     HIPCHK(hipMemcpyAsync(P->view_dev, &v, sizeof(PlanView), hipMemcpyHostToDevice, s));
     HIPCHK(hipGetLastError());
@@ -660,7 +664,7 @@ extern "C" int fmm_plan(const double *xyz_dev, int64_t n, int32_t order, int32_t
     P->D = P->uniform ? o.uniform_depth : o.max_depth;
     P->leaf_size = leaf_size;
     P->precision = o.precision;
-    P->mixed_m2l = ((o.precision & FMM_M2L_F32) && order <= 8) ? 1 : 0;
+    P->mixed_m2l = ((o.precision & FMM_M2L_F32) && (order <= 8 || order >= 12)) ? 1 : 0;
     P->n = (int)n;
     P->tab = tab;
     if (o.root) for (int k = 0; k < 4; ++k) P->root[k] = o.root[k];
@@ -770,7 +774,7 @@ StagePlan stage_blocks(const fmm_plan_s *P)
     StagePlan sp;
     sp.permute = (int)ceil_div(P->n, 256);
     sp.p2m = P->nleaves;
-    sp.fold = (int)ceil_div(P->nboxes + 1, kRemapBoxes); // and the zero row
+    sp.fold = (int)ceil_div(P->nleaves, 16) * (P->ldh / 16);
     sp.m2l = P->nslots / kM2LSlots * P->m2l_parts; // sign classes: m2l_parts blocks per tile
     sp.p2l = P->nxtgt;
     sp.unfold = (int)ceil_div(P->nboxes, kRemapBoxes);
@@ -882,23 +886,21 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
         const Run *begin() const { return b; }
         const Run *end() const { return e; }
     } runs{runs_buf, runs_buf + nruns};
+    // raw moments of the leaves, then their folded multipoles (P2M and fold
+    // in one map); the parents' folded multipoles follow from the M2M on the
+    // folded components.  Full multipoles only for leaves M2P reads.
     T.begin(1);
     for (auto &r : runs)
         launch_p2m(P[r.first]->p, V + r.first,
                    sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).p2m; }), s);
-    for (auto &r : runs)
-        launch_p2m_transform(V + r.first, sub(r.first, r.second, [](const fmm_plan_s *p) {
-            return (int)ceil_div(p->nleaves, 16) * (p->ldm / 16); }), s);
+    T.end();
+    T.begin(3);
+    launch_p2m_fold(V, sub(0, count, [](const fmm_plan_s *p) { return stage_blocks(p).fold; }), s);
+    launch_p2m_transform(V, sub(0, count, [](const fmm_plan_s *p) {
+        return p->nlist[2] > 0 ? (int)ceil_div(p->nleaves, 16) * (p->ldm / 16) : 0; }), s);
     T.end();
     int maxdepth = 0;
     for (int i = 0; i < count; ++i) maxdepth = std::max(maxdepth, P[i]->depth);
-    // fold the leaves' multipoles; the parents' folded multipoles follow from
-    // the M2M on the folded components
-    T.begin(3);
-    for (auto &r : runs)
-        launch_fold(P[r.first]->p, V + r.first,
-                    sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).fold; }), s);
-    T.end();
     T.begin(2);
     // Multipoles of levels 0 and 1 are never read by M2L (V lists start at
     // level 2) nor by M2P (W lists hold boxes of level >= 2), so the upward
@@ -1202,12 +1204,13 @@ extern "C" int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, d
     }
     std::vector<double> buf((size_t)nb * ldm);
     if (M_host) {
-        // The evaluation keeps the parents' multipoles folded (written by the
-        // folded M2M) and stops at level 2.  Levels 1 and 0 are completed with
-        // the same folded M2M, then every parent's full multipole is rebuilt
-        // from its folded one by the per-degree harmonic reconstruction, which
-        // is exact for harmonic expansions: the exported parents are the
-        // evaluation's own M2M results, not a separate computation.
+        // The evaluation keeps the multipoles folded (leaves: written by the
+        // folded P2M, parents: by the folded M2M) and stops at level 2.
+        // Levels 1 and 0 are completed with the same folded M2M, then every
+        // box's full multipole is rebuilt from its folded one by the
+        // per-degree harmonic reconstruction, which is exact for harmonic
+        // expansions: the exported multipoles are the evaluation's own P2M and
+        // M2M results, not a separate computation.
         Bases B{};
         B.n = 1;
         B.b[0] = 0;
@@ -1216,7 +1219,7 @@ extern "C" int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, d
             launch_m2mh(P->p, P->view_dev, B, l, stream);
         }
         B.b[1] = (int)ceil_div(P->nboxes, 4);
-        launch_parent_mh(P->view_dev, B, 2, stream);
+        launch_parent_mh(P->view_dev, B, 2, stream); // leaves too: from the folded P2M
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(stream));
         HIPCHK(hipMemcpy(buf.data(), P->view.M, 8ull * nb * ldm, hipMemcpyDeviceToHost));

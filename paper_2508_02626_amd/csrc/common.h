@@ -137,10 +137,35 @@ constexpr int kSymFirstPart = 72;
 // launches the row tiles of an order >= 12 sign-class M2L are split over (at
 // most 9 row tiles of accumulators per wavefront)
 __host__ __device__ constexpr int sym_row_parts(int p) { return p >= 12 ? (sym_row_tiles(p) + 8) / 9 : 1; }
+// Order of the row tiles: by parity class, then tile within the class, up to
+// p = 11; from p = 12 by tile within the class first (the first 16 rows of
+// every class, then the next 16, ...), so that each of the sym_row_parts
+// launches holds rows of similar degree (rows of a class are in increasing
+// degree) and the first one the lowest degrees.  Class and tile-in-class of
+// row tile r:
+__host__ __device__ constexpr int sym_tile_class(int p, int r, bool want_class)
+{
+    if (p < 12) {
+        for (int c = 0; c < 8; ++c) {
+            const int n = (sym_class_count(p, c) + 15) / 16;
+            if (r < n) return want_class ? c : r;
+            r -= n;
+        }
+        return -1;
+    }
+    for (int t = 0; t < 8; ++t)
+        for (int c = 0; c < 8; ++c)
+            if (16 * t < sym_class_count(p, c)) {
+                if (r == 0) return want_class ? c : t;
+                --r;
+            }
+    return -1;
+}
 // Folded multipoles of sign-class orders are stored so that a lane's
 // operands of vw consecutive k-steps are adjacent (one 16-byte load): sorted
 // column 4 ks + g (k-step ks, lane group g) sits at 4 vw (ks / vw) + vw g +
-// ks % vw, vw = 2 for FP64 and 4 for FP32.
+// ks % vw, vw = 2 for FP64 and 4 for FP32 (2 for both from p = 12, where
+// the operands move two k-steps at a time in either precision).
 __host__ __device__ constexpr int sym_pos(int ks, int g, int vw) { return 4 * vw * (ks / vw) + vw * g + ks % vw; }
 // row stride of the folded multipoles (both precisions' layouts fit)
 __host__ __device__ constexpr int folded_ld(int p)
@@ -240,6 +265,8 @@ struct OrderTables {
     const double *TM;   // [8][ldmh][ldmh] M2M on the folded positions, TM[o][a][c] = d Mh'_c / d Mh_a
     const double *HR;   // [nh][nc] full harmonic Mhat from the folded (harmonic-order) components, HR[c][b]
     const int *hpos;    // [nh] folded position of each harmonic component
+    const int *hposf;   // [nh] same in the FP32 copy
+    const double *FP2M; // [nc][ldh] raw moments -> folded components in harmonic order (P2M, then fold)
     const double *P2M;  // [nc][nc] moments -> Mhat, P2M[g][a] = d Mhat_a / d Q_g
     const double *P2L;  // [nc][ldh] inverse moments -> harmonic Lhat
     const int *fold_off; const int *fold_idx; const double *fold_c;     // Mhat -> folded

@@ -353,10 +353,9 @@ template <int P> struct SymShape {
     int kb[9];          // first k-step of each column class
     constexpr SymShape() : rc(), kc(), kb()
     {
-        int r = 0, k = 0;
+        for (int r = 0; r < RT; ++r) rc[r] = sym_tile_class(P, r, true);
+        int k = 0;
         for (int c = 0; c < 8; ++c) {
-            const int n = sym_class_count(P, c);
-            for (int t = 0; t < (n + 15) / 16; ++t) rc[r++] = c;
             kb[c] = k;
             for (int t = 0; t < sym_class_ksteps(P, c); ++t) kc[k++] = c;
         }
@@ -748,10 +747,12 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
 // class's first vector loaded during the last one.  The targets' slot rows
 // are read from memory (the classes a block uses come from a 64-bit mask
 // built by all threads), which leaves LDS to the derivative tables.
-template <int P, int RH>
+// T = float (mixed precision, launches RH >= 1: the higher-degree row tiles):
+// FP32 tables and operands on FP32 MFMA, each class's products summed in FP32
+// and added to FP64 accumulators after the class.
+template <int P, int RH, typename T>
 __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
 {
-    typedef double T;
     static constexpr SymShape<P> S{};
     constexpr int RT = SymShape<P>::RT, KS = SymShape<P>::KS;
     constexpr int NRP = sym_row_parts(P), MTP = (RT + NRP - 1) / NRP, R0 = RH * MTP;
@@ -761,9 +762,11 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     constexpr int KSV = KS / 2; // operand vectors per class
     constexpr int NT = 256;
     constexpr int LDD = dlayout_ldd(P), LDC = dlayout_ldc(P);
-    constexpr int DW = 2;
+    constexpr int DW = 16 / (int)sizeof(T); // compact tables move in 16-byte vectors
     static_assert(LDC % DW == 0, "compact rows must be whole vectors");
     constexpr int DV = (LDC / DW + NT - 1) / NT;
+    constexpr bool F32 = sizeof(T) == 4;
+    constexpr uint32_t VB = 2 * sizeof(T); // bytes of one lane's two-k-step operand vector
     typedef typename Mfma<T>::acc_t acc_t;
     typedef T vec_t __attribute__((ext_vector_type(2)));
     __shared__ T sD[2][LDD];
@@ -814,14 +817,17 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     __syncthreads();
     const int qa = sQa, qb = sQb;
     const int64_t ldmh = v.ldmh;
-    const T *Dt = tb.D;
-    const T *Mh = v.Mh;
+    const T *Dt = Mfma<T>::D(tb);
+    const T *Mh = Mfma<T>::M(v);
 
     acc_t acc[MTW];
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) acc[mt] = acc_t{0, 0, 0, 0};
+    double4_t acc64[F32 ? MTW : 1]; // FP32: per-class sums added here
+#pragma unroll
+    for (int mt = 0; mt < (F32 ? MTW : 1); ++mt) acc64[mt] = double4_t{0, 0, 0, 0};
 
-    typedef T dvec_t __attribute__((ext_vector_type(2)));
+    typedef T dvec_t __attribute__((ext_vector_type(DW)));
     dvec_t pd[DV];
     int dm[DV][DW];
 #pragma unroll
@@ -848,7 +854,8 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     };
     // member operand rows as 32-bit byte offsets (plans check the 4 GiB bound);
     // absent members read the zero row after the boxes
-    const uint32_t zoff = (uint32_t)v.nboxes * (uint32_t)ldmh * 8u;
+    constexpr uint32_t ES = sizeof(T);
+    const uint32_t zoff = (uint32_t)v.nboxes * (uint32_t)ldmh * ES;
     const uint32_t vrow = (uint32_t)(tgt >= 0 ? tgt : 0) * (uint32_t)kVSlots;
     auto class_src = [&](int q, uint32_t (&src)[8]) {
         const int c = sList[q];
@@ -856,7 +863,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
         for (int m = 0; m < 8; ++m) {
             const int j = sMem[c][m];
             const int b = j >= 0 && tgt >= 0 ? vs[vrow + (uint32_t)j] : -1;
-            src[m] = (b >= 0 ? (uint32_t)b * (uint32_t)ldmh * 8u : zoff) + 16u * (uint32_t)kq;
+            src[m] = (b >= 0 ? (uint32_t)b * (uint32_t)ldmh * ES : zoff) + VB * (uint32_t)kq;
         }
     };
     const auto Mg = gptr((const char *)Mh);
@@ -865,7 +872,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
         for (int m = 0; m < 8; ++m) {
             uint32_t o = src[m];
             asm volatile("" : "+v"(o));
-            dst[m] = *(gp<const vec_t>)(Mg + (uint64_t)o + 64 * j);
+            dst[m] = *(gp<const vec_t>)(Mg + (uint64_t)o + 4 * VB * j);
         }
     };
     uint32_t srcc[8], srcn[8];
@@ -929,6 +936,14 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
                 class_src(q + 1, srcn);
             }
             run_class(zc, sD[curb]);
+            if constexpr (F32) {
+#pragma unroll
+                for (int mt = 0; mt < MTW; ++mt) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc64[mt][r] += (double)acc[mt][r];
+                    acc[mt] = acc_t{0, 0, 0, 0};
+                }
+            }
 #pragma unroll
             for (int m = 0; m < 8; ++m) srcc[m] = srcn[m];
             if (more) store_d(curb ^ 1);
@@ -949,7 +964,11 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int b = gptr(tb.srow)[16 * (R0 + mt) + Mfma<T>::row(lane, r)];
-            if (b >= 0) Lh[b] = acc[mt][r];
+            if constexpr (F32) {
+                if (b >= 0) Lh[b] = acc64[mt][r];
+            } else {
+                if (b >= 0) Lh[b] = acc[mt][r];
+            }
         }
     }
 }
@@ -960,7 +979,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
         else k_m2l<PP, double><<<nb, 256, 0, s>>>(V, B);                           \
         break;
 
-// FP32 M2L exists for p <= 8 only (the mixed path keeps M2L in FP64 above)
+// FP32 sign-class M2L with all rows in FP32: orders 6-8 (9-11 stay FP64)
 #define M2L_SYM(PP)                                                                \
     case PP:                                                                       \
         if (f32) k_m2l_sym<PP, float><<<nb, 256, 0, s>>>(V, B);                    \
@@ -969,18 +988,30 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
 #define M2L_SYM64(PP)                                                              \
     case PP: k_m2l_sym<PP, double><<<nb, 256, 0, s>>>(V, B); break;
 
-template <int P> void launch_symh(unsigned nb, const PlanView *V, const Bases &B, hipStream_t s)
+// Orders >= 12: one launch per row part.  With f32 the first part (the
+// lowest degrees of every parity class) stays FP64 and the others run on
+// FP32 MFMA: a local coefficient of degree n carries about rho^n of the far
+// field, rho < 1 the expansion's convergence ratio, so the FP32 rounding of
+// the high-degree rows is scaled down by it.
+template <int P> void launch_symh(unsigned nb, const PlanView *V, const Bases &B, int f32, hipStream_t s)
 {
     static_assert(sym_row_parts(P) <= 3, "row parts");
-    k_m2l_symh<P, 0><<<nb, 256, 0, s>>>(V, B);
-    if constexpr (sym_row_parts(P) > 1) k_m2l_symh<P, 1><<<nb, 256, 0, s>>>(V, B);
-    if constexpr (sym_row_parts(P) > 2) k_m2l_symh<P, 2><<<nb, 256, 0, s>>>(V, B);
+    k_m2l_symh<P, 0, double><<<nb, 256, 0, s>>>(V, B);
+    if constexpr (sym_row_parts(P) > 1) {
+        if (f32) k_m2l_symh<P, 1, float><<<nb, 256, 0, s>>>(V, B);
+        else k_m2l_symh<P, 1, double><<<nb, 256, 0, s>>>(V, B);
+    }
+    if constexpr (sym_row_parts(P) > 2) {
+        if (f32) k_m2l_symh<P, 2, float><<<nb, 256, 0, s>>>(V, B);
+        else k_m2l_symh<P, 2, double><<<nb, 256, 0, s>>>(V, B);
+    }
 }
 #define M2L_SYMH(PP) \
-    case PP: launch_symh<PP>(nb, V, B, s); break;
+    case PP: launch_symh<PP>(nb, V, B, f32, s); break;
 
-// FP32 M2L exists for p <= 8 only (the mixed path keeps M2L in FP64 above);
-// orders from 6 on run on sign classes (m2l_sym), from 12 on in k_m2l_symh
+// FP32 M2L: all of it up to p = 8, the row parts after the first from
+// p = 12 (orders 9-11 keep M2L in FP64); orders from 6 on run on sign
+// classes (m2l_sym), from 12 on in k_m2l_symh
 void launch_m2l(int p, int f32, const PlanView *V, const Bases &B, hipStream_t s)
 {
     unsigned nb = (unsigned)B.b[B.n];
@@ -990,7 +1021,7 @@ void launch_m2l(int p, int f32, const PlanView *V, const Bases &B, hipStream_t s
         M2L_CASE(0) M2L_CASE(1) M2L_CASE(2) M2L_CASE(3) M2L_CASE(4) M2L_CASE(5)
         M2L_SYM(6) M2L_SYM(7) M2L_SYM(8) M2L_SYM64(9) M2L_SYM64(10) M2L_SYM64(11)
         M2L_SYMH(12) M2L_SYMH(13) M2L_SYMH(14) M2L_SYMH(15)
-    default: launch_symh<16>(nb, V, B, s);
+    default: launch_symh<16>(nb, V, B, f32, s);
     }
 }
 

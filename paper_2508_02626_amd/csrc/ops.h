@@ -6,8 +6,8 @@
 namespace fmm {
 void launch_permute_q(const PlanView *V, const Bases &B, hipStream_t s);   // 256 particles/block
 void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block
-void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 leaves x 16 rows/block
-void launch_fold(int p, const PlanView *V, const Bases &B, hipStream_t s); // kRemapBoxes boxes/block
+void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 leaves x 16 rows/block (M2P sources)
+void launch_p2m_fold(const PlanView *V, const Bases &B, hipStream_t s); // 16 leaves x 16 harmonic rows/block
 void launch_l2lh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block (harmonic rows)
 void launch_lh_init(const PlanView *V, const Bases &B, hipStream_t s);        // 4 boxes/block
 void launch_m2mh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 folded rows/block
@@ -22,7 +22,8 @@ void launch_m2p(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 
 __host__ __device__ inline int p2p_split(int nleaves) { return (int)((int64_t)nleaves * 5 / 8) & ~3; }
 void launch_p2p(int mixed, int part, const PlanView *V, const Bases &B, hipStream_t s); // 4 leaves/block
 void launch_zero(double *p, int64_t n, hipStream_t s);
+void launch_zero_f32(float *p, int64_t n, hipStream_t s);
 void launch_m2l(int p, int f32, const PlanView *V, const Bases &B, hipStream_t s); // 64 slots/block
 constexpr int kM2LSlots = 64;
-constexpr int kRemapBoxes = 16; // boxes per block of the fold and unfold
+constexpr int kRemapBoxes = 16; // boxes per block of the unfold
 } // namespace fmm

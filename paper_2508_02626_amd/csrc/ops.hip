@@ -165,9 +165,60 @@ __global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
     col_store<P>(v.L + (int64_t)box * v.ldm, lane, cb, cc, acc);
 }
 
-// Mhat = P2M^t Q for 16 leaves x 16 coefficients per wavefront (FP64 MFMA);
-// the matrix is block diagonal by degree, so only the tile's degree range of
-// moments is visited.
+// Folded multipoles of the leaves straight from their raw moments:
+// Mh = FP2M^t Q (P2M followed by the fold, one matrix) for 16 leaves x 16
+// harmonic components per wavefront (FP64 MFMA), stored at the components'
+// folded positions (and in the FP32 copy for the FP32 M2L).  Both maps keep
+// the degree, so a tile of components visits only its degrees' moments.  The
+// first tile's wavefront also writes the padding positions of the rows
+// (zero: the M2L reads them as operands of padded columns).
+__global__ __launch_bounds__(64) void k_p2m_fold(const PlanView *V, Bases B)
+{
+    const int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int item = blockIdx.x - B.b[k];
+    const int MT = v.ldh / 16, g = item / MT, mt = item - g * MT;
+    const int lane = threadIdx.x, col = lane & 15, kq = lane >> 4;
+    const int li = g * 16 + col;
+    const int leaf = li < v.nleaves ? v.leaves[li] : -1;
+    const int nh = v.nh, ldh = v.ldh, ldm = v.ldm, ldmh = v.ldmh;
+    const OrderTables &t = *v.tab;
+    const int bA = mt * 16 + col;
+    auto hdeg = [](int c) { int n = 0; while ((n + 1) * (n + 1) <= c) ++n; return n; };
+    const int dlo = hdeg(mt * 16 < nh ? mt * 16 : nh - 1);
+    const int dhi = hdeg(mt * 16 + 15 < nh ? mt * 16 + 15 : nh - 1);
+    const int k0 = below(dlo) & ~3, k1 = below(dhi + 1);
+    const auto T = gptr(t.FP2M);
+    const auto Q = gptr(v.L + (int64_t)(leaf >= 0 ? leaf : 0) * ldm);
+    double4_t acc = {0, 0, 0, 0};
+#pragma unroll 4
+    for (int kk = k0; kk < k1; kk += 4) {
+        const int a = kk + kq;
+        const double av = (bA < nh && a < v.nc) ? T[(int64_t)a * ldh + bA] : 0.0;
+        const double bv = (leaf >= 0 && a < v.nc) ? Q[a] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    if (leaf < 0) return;
+    const auto Mh = gptr(v.Mh + (int64_t)leaf * ldmh);
+    const bool f32 = v.mixed_m2l;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { // f64 layout: lane l reg r -> row 4r + l/16
+        const int c = mt * 16 + 4 * r + kq;
+        if (c < nh) {
+            Mh[t.hpos[c]] = acc[r];
+            if (f32) gptr(v.Mhf)[(int64_t)leaf * ldmh + t.hposf[c]] = (float)acc[r];
+        }
+    }
+    if (mt == 0)
+        for (int pos = kq; pos < ldmh; pos += 4) {
+            if (t.mpos[pos] < 0) Mh[pos] = 0.0;
+            if (f32 && t.mposf[pos] < 0) gptr(v.Mhf)[(int64_t)leaf * ldmh + pos] = 0.f;
+        }
+}
+
+// Full Mhat = P2M^t Q for 16 leaves x 16 coefficients per wavefront (FP64
+// MFMA), for the leaves M2P reads (sources of W lists); the matrix is block
+// diagonal by degree, so only the tile's degree range of moments is visited.
 __global__ __launch_bounds__(64) void k_p2m_transform(const PlanView *V, Bases B)
 {
     const int k = find_plan(B, blockIdx.x);
@@ -177,6 +228,7 @@ __global__ __launch_bounds__(64) void k_p2m_transform(const PlanView *V, Bases B
     const int lane = threadIdx.x, col = lane & 15, kq = lane >> 4;
     const int li = g * 16 + col;
     const int leaf = li < v.nleaves ? v.leaves[li] : -1;
+    if (!__any(leaf >= 0 && v.wsrc && v.wsrc[leaf])) return; // no M2P source among the 16
     const int nc = v.nc, ldm = v.ldm;
     const int bA = mt * 16 + col;
     const double *T = v.tab->P2M;
@@ -197,50 +249,6 @@ __global__ __launch_bounds__(64) void k_p2m_transform(const PlanView *V, Bases B
     for (int r = 0; r < 4; ++r) {
         const int b = mt * 16 + 4 * r + kq;
         v.M[(int64_t)leaf * ldm + b] = b < nc ? acc[r] : 0.0;
-    }
-}
-
-// ---------------- fold Mhat onto the harmonic components used by M2L ----------------
-// The leaves' multipoles are folded here, the parents' ones come from the
-// folded M2M.  A block folds 16 boxes (4 per wavefront): the term tables sit in LDS, each
-// box's row of Mhat is staged in LDS by one coalesced load, and every lane
-// gathers its outputs from there.  Row nboxes is the zero row (the operand
-// of absent M2L sources).
-template <int P>
-__global__ __launch_bounds__(256) void k_fold(const PlanView *V, Bases B)
-{
-    constexpr int NH = nharm(P), NT = fold_terms(P), LDM = pad16(ncoef(P)), LDMH = folded_ld(P);
-    __shared__ int sOff[NH + 1], sIdx[NT], sPos[LDMH], sPosf[LDMH];
-    __shared__ double sC[NT];
-    __shared__ double sRow[4][LDM];
-    const int k = find_plan(B, blockIdx.x);
-    const PlanView &v = V[k];
-    const OrderTables &t = *v.tab;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    for (int e = tid; e < NT; e += 256) { sIdx[e] = gptr(t.fold_idx)[e]; sC[e] = gptr(t.fold_c)[e]; }
-    for (int e = tid; e <= NH; e += 256) sOff[e] = gptr(t.fold_off)[e];
-    for (int e = tid; e < LDMH; e += 256) { sPos[e] = gptr(t.mpos)[e]; sPosf[e] = gptr(t.mposf)[e]; }
-    __syncthreads();
-    const bool mixed = v.mixed_m2l;
-    auto fold = [&](int h) {
-        double s = 0.0;
-        if (h >= 0)
-            for (int e = sOff[h]; e < sOff[h + 1]; ++e) s += sC[e] * sRow[w][sIdx[e]];
-        return s;
-    };
-    const int first = (blockIdx.x - B.b[k]) * kRemapBoxes + 4 * w;
-    for (int i = 0; i < 4; ++i) {
-        const int box = first + i;
-        if (box > v.nboxes) break;
-        if (box < v.nboxes && v.nchild[box] > 0) continue; // parents: folded M2M
-        const auto M = gptr(v.M + (int64_t)box * LDM);
-        for (int a = lane; a < LDM; a += 64) sRow[w][a] = box < v.nboxes ? M[a] : 0.0;
-        wave_sync();
-        for (int c = lane; c < LDMH; c += 64) {
-            gptr(v.Mh)[(int64_t)box * LDMH + c] = fold(sPos[c]);
-            if (mixed) gptr(v.Mhf)[(int64_t)box * LDMH + c] = (float)fold(sPosf[c]);
-        }
-        wave_sync();
     }
 }
 
@@ -329,14 +337,14 @@ __global__ __launch_bounds__(512) void k_m2mh(const PlanView *V, Bases B, int le
 // Parents' FP32 operand copy (mixed M2L) and, for plans with W lists, their
 // full multipoles for M2P, from the folded ones: one wavefront per non-leaf
 // box of level >= 2 (full = 0: FP32 copy only, 1: also the full multipoles
-// of M2P sources).  full = 2 (export): the full multipoles of every non-leaf
-// box, of any level, and nothing else.
+// of M2P sources).  full = 2 (export): the full multipoles of every box, leaf
+// or not, of any level, and nothing else.
 __global__ __launch_bounds__(256) void k_parent_mh(const PlanView *V, Bases B, int full)
 {
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
     const int box = (blockIdx.x - B.b[k]) * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (box >= v.nboxes || v.nchild[box] == 0 || (full != 2 && v.level[box] < 2)) return;
+    if (box >= v.nboxes || (full != 2 && (v.nchild[box] == 0 || v.level[box] < 2))) return;
     const OrderTables &t = *v.tab;
     const auto Mh = gptr(v.Mh + (int64_t)box * v.ldmh);
     if (v.mixed_m2l && full != 2)
@@ -928,10 +936,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     }
 }
 
-__global__ void k_zero(double *p, int64_t n)
+template <typename T> __global__ void k_zero(T *p, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < n) p[i] = 0.0;
+    if (i < n) p[i] = T(0);
 }
 
 // ---------------- launchers ----------------
@@ -962,9 +970,9 @@ void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (nblk(B)) k_p2m_transform<<<nblk(B), 64, 0, s>>>(V, B);
 }
-void launch_fold(int p, const PlanView *V, const Bases &B, hipStream_t s)
+void launch_p2m_fold(const PlanView *V, const Bases &B, hipStream_t s)
 {
-    if (nblk(B)) DISPATCH_P(p, k_fold, <<<nblk(B), 256, 0, s>>>(V, B));
+    if (nblk(B)) k_p2m_fold<<<nblk(B), 64, 0, s>>>(V, B);
 }
 void launch_unfold(int p, const PlanView *V, const Bases &B, int leaves_only, hipStream_t s)
 {
@@ -1010,7 +1018,11 @@ void launch_p2p(int mixed, int part, const PlanView *V, const Bases &B, hipStrea
 }
 void launch_zero(double *p, int64_t n, hipStream_t s)
 {
-    if (n > 0) k_zero<<<ceil_div(n, 256), 256, 0, s>>>(p, n);
+    if (n > 0) k_zero<double><<<ceil_div(n, 256), 256, 0, s>>>(p, n);
+}
+void launch_zero_f32(float *p, int64_t n, hipStream_t s)
+{
+    if (n > 0) k_zero<float><<<ceil_div(n, 256), 256, 0, s>>>(p, n);
 }
 
 } // namespace fmm

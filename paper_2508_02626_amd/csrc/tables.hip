@@ -164,10 +164,10 @@ std::vector<ld> harmonic_projection(const Mono &m, const std::vector<ld> &v, int
 }
 
 struct Built {
-    std::vector<double> D, S, G, GH, TM, HR, P2M, P2L, fold_c, unfold_c, inv_fact, inv_w;
+    std::vector<double> D, S, G, GH, TM, HR, P2M, FP2M, P2L, fold_c, unfold_c, inv_fact, inv_w;
     std::vector<float> Df;
     std::vector<int> offs, hoff, fold_off, fold_idx, unfold_off, unfold_idx, exps, dmap;
-    std::vector<int> mpos, mposf, hpos, srow, scol, srep, smem, sslot;
+    std::vector<int> mpos, mposf, hpos, hposf, srow, scol, srep, smem, sslot;
     int ldd = 0, ldc = 0;
 };
 
@@ -238,18 +238,24 @@ void build_tables(int p, Built &B)
                     if (s >= 0) B.offs[o * kVSlots + s] = (kx + 3) * 49 + (ky + 3) * 7 + (kz + 3);
                 }
 
-    // sign classes: parity-sorted rows (padded to 16) and columns (padded to 4)
+    // sign classes: parity-sorted rows (16-row tiles in the order of
+    // sym_tile_class) and columns (padded to sym_colpad per class)
     B.srow.clear();
     B.scol.clear();
+    std::vector<int> cls[8];
     for (int c = 0; c < 8; ++c) {
         for (int h = 0; h < nh; ++h)
             if ((hx[h] & 1) == ((c >> 2) & 1) && (hy[h] & 1) == ((c >> 1) & 1) && hz[h] == (c & 1)) {
-                B.srow.push_back(h);
+                cls[c].push_back(h);
                 B.scol.push_back(h);
             }
-        B.srow.resize(pad16((int)B.srow.size()), -1);
         const int cp = sym_colpad(p);
         B.scol.resize(((int)B.scol.size() + cp - 1) / cp * cp, -1);
+    }
+    for (int r = 0; r < sym_row_tiles(p); ++r) {
+        const int c = sym_tile_class(p, r, true), t = sym_tile_class(p, r, false);
+        for (int i = 0; i < 16; ++i)
+            B.srow.push_back(16 * t + i < (int)cls[c].size() ? cls[c][16 * t + i] : -1);
     }
     if ((int)B.srow.size() != 16 * sym_row_tiles(p) || (int)B.scol.size() != 4 * sym_ksteps(p))
         throw std::logic_error("sign-class layout");
@@ -261,7 +267,7 @@ void build_tables(int p, Built &B)
         for (int ks = 0; ks < sym_ksteps(p); ++ks)
             for (int g = 0; g < 4; ++g) {
                 B.mpos[sym_pos(ks, g, 2)] = B.scol[4 * ks + g];
-                B.mposf[sym_pos(ks, g, 4)] = B.scol[4 * ks + g];
+                B.mposf[sym_pos(ks, g, p >= 12 ? 2 : 4)] = B.scol[4 * ks + g];
             }
     } else {
         for (int c = 0; c < nh; ++c) B.mpos[c] = B.mposf[c] = c;
@@ -445,8 +451,24 @@ void build_tables(int p, Built &B)
                 if (a >= 0 && c >= 0) B.TM[((size_t)o * ldmh + pa) * ldmh + pb] = (double)TMh[((size_t)o * nh + a) * nh + c];
             }
     B.hpos.assign(nh, -1);
-    for (int pa = 0; pa < ldmh; ++pa)
+    B.hposf.assign(nh, -1);
+    for (int pa = 0; pa < ldmh; ++pa) {
         if (B.mpos[pa] >= 0) B.hpos[B.mpos[pa]] = pa;
+        if (B.mposf[pa] >= 0) B.hposf[B.mposf[pa]] = pa;
+    }
+    // P2M followed by the fold: raw moments -> folded components (harmonic
+    // order), FP2M[g][c] = sum over the fold terms (j, w) of c of w P2M[g][j];
+    // both keep the degree, so column c only has entries of its degree's moments
+    {
+        std::vector<ld> F((size_t)nc * ldh, 0.0L);
+        for (int c = 0; c < nh; ++c)
+            for (int e = B.fold_off[c]; e < B.fold_off[c + 1]; ++e) {
+                const int j = B.fold_idx[e], d = m.deg(j);
+                const ld wf = (ld)B.fold_c[e] * (((d & 1) ? -1.0L : 1.0L) / dfact(2 * d - 1));
+                for (int g = below(d); g < below(d + 1); ++g) F[(size_t)g * ldh + c] += wf * C[(size_t)j * nc + g];
+            }
+        B.FP2M.assign(F.begin(), F.end());
+    }
     // full harmonic Mhat from the folded components (for M2P sources that are
     // not leaves): per degree n, the projections of the monomials with z
     // exponent <= 1 span the harmonic polynomials; with F the fold,
@@ -545,7 +567,8 @@ const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::s
     if (upload(B.D, &t.D, err) || upload(B.Df, &t.Df, err) || upload(B.dmap, &t.dmap, err) ||
         upload(B.offs, &t.offs, err) ||
         upload(B.hoff, &t.hoff, err) || upload(B.GH, &t.GH, err) || upload(B.TM, &t.TM, err) ||
-        upload(B.HR, &t.HR, err) || upload(B.hpos, &t.hpos, err) ||
+        upload(B.HR, &t.HR, err) || upload(B.hpos, &t.hpos, err) || upload(B.hposf, &t.hposf, err) ||
+        upload(B.FP2M, &t.FP2M, err) ||
         upload(B.P2M, &t.P2M, err) || upload(B.P2L, &t.P2L, err) || upload(B.fold_off, &t.fold_off, err) ||
         upload(B.fold_idx, &t.fold_idx, err) || upload(B.fold_c, &t.fold_c, err) ||
         upload(B.unfold_off, &t.unfold_off, err) || upload(B.unfold_idx, &t.unfold_idx, err) ||

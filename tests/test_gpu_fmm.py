@@ -55,6 +55,20 @@ def test_high_orders_match_oracle(p):
     _check_fp64(x, q, p, dict(leaf_size=6))
 
 
+@pytest.mark.parametrize("p", [12, 13, 14, 15, 16])
+def test_high_orders_mixed_error_is_bounded(p):
+    """Mixed path above order 11 (FP32 MFMA for the M2L row parts after the
+    first, FP32 P2P terms) on the small clustered tree: stated error against
+    the FP64 oracle."""
+    x, q = inputs.clusters(60, 5)
+    pl, phi, fld = gpu_solve(x, q, p, leaf_size=6, precision="mixed")
+    pl.close()
+    ophi, ofld = oracle_tree(x, leaf_size=6).fmm(p, q)
+    e_phi, e_fld = rel_l2(phi, ophi), rel_l2(fld, ofld)
+    say("  clusters 60 mixed p=%d rel L2 vs oracle: phi %.3e field %.3e" % (p, e_phi, e_fld))
+    assert e_phi <= 1e-7 and e_fld <= 1e-6
+
+
 def test_high_order_error_against_direct():
     """At 2e5 Plummer points the error against the direct sum keeps falling up
     to p = 16 (sampled targets)."""
@@ -84,6 +98,13 @@ def test_order12_small_tree():
     ("gaussian_5000_s50_p6", lambda: inputs.gaussian(5000, 4), 6, dict(leaf_size=50)),
     ("ragged_777_s5_p4", lambda: inputs.uniform(777, 5), 4, dict(leaf_size=5)),
     ("bbox_uniform_d3_p5", lambda: inputs.plummer(3000, 6), 5, dict(uniform_depth=3)),
+    # leaf sizes and orders of the leaf-size / order sweep (3-D Gaussian, as
+    # the paper's sweeps): the smallest and largest leaf sizes, lowest and
+    # highest orders
+    ("gaussian_6000_s16_p2", lambda: inputs.gaussian(6000, 40), 2, dict(leaf_size=16)),
+    ("gaussian_6000_s32_p10", lambda: inputs.gaussian(6000, 41), 10, dict(leaf_size=32)),
+    ("gaussian_12000_s128_p8", lambda: inputs.gaussian(12000, 42), 8, dict(leaf_size=128)),
+    ("gaussian_20000_s512_p10", lambda: inputs.gaussian(20000, 43), 10, dict(leaf_size=512)),
 ])
 def test_adaptive_potentials_match_oracle(name, gen, p, kw):
     x, q = gen()

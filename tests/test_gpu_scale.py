@@ -42,16 +42,18 @@ def test_uniform1m_fp64_whole_result_matches_oracle():
     assert e_phi <= 1e-12 and e_fld <= 1e-12
 
 
-# stated bounds of each FP32 part against the FP64 oracle (relative L2)
-@pytest.mark.parametrize("prec,bound", [("p2p32", 1e-7), ("m2l32", 3e-7), ("mixed", 3e-7)])
-def test_uniform1m_mixed_parts_error_against_oracle(prec, bound):
+# stated bounds of each FP32 part against the FP64 oracle (relative L2 of the
+# potential, of the field)
+@pytest.mark.parametrize("prec,bound,bound_f", [("p2p32", 5e-8, 3e-7), ("m2l32", 3e-7, 1e-6),
+                                                ("mixed", 3e-7, 1e-6)])
+def test_uniform1m_mixed_parts_error_against_oracle(prec, bound, bound_f):
     x, q = inputs.uniform(1_000_000, 1)
     ophi, ofld = _oracle_fmm("uniform1m", x, q, 8, UNI)
     pl, phi, fld = gpu_solve(x, q, 8, precision=prec, **UNI)
     pl.close()
     e_phi, e_fld = rel_l2(phi, ophi), rel_l2(fld, ofld)
     say("  uniform1m p=8 %s rel L2 vs oracle: phi %.3e field %.3e" % (prec, e_phi, e_fld))
-    assert e_phi <= bound and e_fld <= bound
+    assert e_phi <= bound and e_fld <= bound_f
 
 
 @pytest.mark.parametrize("p", [10, 14])
@@ -78,6 +80,21 @@ def test_adaptive_plummer_matches_oracle(p):
             assert np.abs(M[:, sel] - oM[:, sel]).max() <= 1e-12 * sm, ("M", d)
             assert np.abs(L[:, sel] - oL[:, sel]).max() <= 1e-12 * sl, ("L", d)
     pl.close()
+
+
+@pytest.mark.parametrize("p", [12, 14])
+def test_adaptive_plummer_mixed_error_against_oracle(p):
+    """Mixed path at orders >= 12: FP32 P2P terms with compensated sums and
+    FP32 MFMA for the M2L row tiles after the first row part (the higher
+    degrees); stated error against the FP64 oracle."""
+    x, q = inputs.plummer(30_000, 11)
+    kw = dict(leaf_size=64)
+    res = _oracle_fmm(("plummer3e4", p), x, q, p, kw, expansions=p == 10)
+    pl, phi, fld = gpu_solve(x, q, p, precision="mixed", **kw)
+    pl.close()
+    e_phi, e_fld = rel_l2(phi, res[0]), rel_l2(fld, res[1])
+    say("  plummer 3e4 p=%d mixed rel L2 vs oracle: phi %.3e field %.3e" % (p, e_phi, e_fld))
+    assert e_phi <= 1e-7 and e_fld <= 1e-6
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
