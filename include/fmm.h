@@ -150,6 +150,29 @@ int fmm_evaluate_batch(fmm_plan_t const *plans, const double *const *q_dev,
                        double *const *phi_dev, double *const *field_dev, int32_t count,
                        hipStream_t stream);
 
+/*
+ * fmm_evaluate_batch_noalloc - fmm_evaluate_batch for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, same results (bitwise
+ * equal to fmm_evaluate_batch and to fmm_evaluate on each plan).  Where
+ * fmm_evaluate_batch allocates, on every call, device memory for the per-plan
+ * views its kernels read, this call stages them in a fixed array of the
+ * library: FMM_NOALLOC_MAX_PLANS views (a few hundred bytes each), one copy
+ * per device, held until the process ends.  It calls no hipMalloc, hipFree or
+ * other allocating routine.
+ *   count  0..FMM_NOALLOC_MAX_PLANS (FMM_EINVAL beyond)
+ * Every call on a device shares that device's array and leaves its last
+ * contents there: calls on one stream are ordered and safe, but calls that
+ * overlap on one device (different streams, or threads without ordering)
+ * race and give wrong results.  All plans must belong to the current device.
+ * The first evaluation of a plan on a stream may still create a HIP event,
+ * and a plan's first evaluation its side stream.
+ */
+#define FMM_NOALLOC_MAX_PLANS 1024
+int fmm_evaluate_batch_noalloc(fmm_plan_t const *plans, const double *const *q_dev,
+                               double *const *phi_dev, double *const *field_dev, int32_t count,
+                               hipStream_t stream);
+
 /* Device bytes held by the plan (its workspace, as allocated: a chunk reused
  * from the library's cache counts with its full size), for admission control. */
 int fmm_plan_footprint(fmm_plan_t plan, size_t *bytes);

@@ -21,7 +21,7 @@ SYMBOLS = ["fmm_default_options", "fmm_plan", "fmm_evaluate", "fmm_evaluate_batc
            "fmm_plan_footprint", "fmm_plan_estimate", "fmm_plan_sizes", "fmm_plan_export_tree",
            "fmm_plan_export_expansions", "fmm_plan_set_timing", "fmm_plan_read_timing",
            "fmm_plan_destroy", "fmm_last_error", "fmm_plan_batch", "fmm_cached_bytes",
-           "fmm_order_table"]
+           "fmm_order_table", "fmm_evaluate_batch_noalloc"]
 STAGES = ["permute", "p2m", "m2m", "fold", "m2l", "p2l", "unfold", "l2l", "l2p", "p2p", "p2p_part2", "m2p"]
 
 
@@ -57,6 +57,7 @@ def lib():
         L.fmm_plan.argtypes = [vp, i64, i32, i32, P(Options), P(Allocator), vp, P(vp)]
         L.fmm_evaluate.argtypes = [vp, vp, vp, vp, vp]
         L.fmm_evaluate_batch.argtypes = [P(vp), P(vp), P(vp), P(vp), i32, vp]
+        L.fmm_evaluate_batch_noalloc.argtypes = [P(vp), P(vp), P(vp), P(vp), i32, vp]
         L.fmm_plan_footprint.argtypes = [vp, P(ctypes.c_size_t)]
         L.fmm_plan_estimate.argtypes = [i64, i32, i32, P(Options), P(ctypes.c_size_t)]
         L.fmm_plan_sizes.argtypes = [vp, P(i64)]
@@ -239,8 +240,9 @@ def plan_batch(xyzs, orders, leaf_size=64, precision="fp64", uniform_depth=-1, m
     return [Plan._adopt(ctypes.c_void_p(hv[i]), xs[i].shape[0], orders[i], xs[i].device) for i in range(m)]
 
 
-def evaluate_batch(plans, qs, want_field=True, stream=None):
-    """One fmm_evaluate_batch call over several plans; returns [(phi, field)]."""
+def evaluate_batch(plans, qs, want_field=True, stream=None, noalloc=False):
+    """One fmm_evaluate_batch call over several plans (fmm_evaluate_batch_noalloc
+    with noalloc=True); returns [(phi, field)]."""
     import torch
     n = len(plans)
     outs = []
@@ -259,7 +261,8 @@ def evaluate_batch(plans, qs, want_field=True, stream=None):
         pv[i] = phi.data_ptr()
         fv[i] = fld.data_ptr() if fld is not None else None
         hv[i] = p.handle.value
-    _check(lib().fmm_evaluate_batch(hv, qv, pv, fv if want_field else None, n, _stream(stream)))
+    fn = lib().fmm_evaluate_batch_noalloc if noalloc else lib().fmm_evaluate_batch
+    _check(fn(hv, qv, pv, fv if want_field else None, n, _stream(stream)))
     return outs
 
 
