@@ -306,6 +306,33 @@ def bench_plummer(args):
                         "rel_l2_vs_fp64_path_field": rel(m["fld"], f["fld"]),
                         "dtype": "f64 with f32 P2P terms (compensated sums) and the FP32 M2L of this order's rule",
                         "stage_ms": m["stages"]}
+    if not args.no_rotation:
+        # the rotation-based M2L of Sec. 3.4 (vector unit) beside the sign-class
+        # contraction (matrix cores), same plan and order
+        mk = lambda: fmm.Plan(x, p, leaf_size=64, m2l="rotation")
+        rsteps = max(1, args.steps // 2)
+        step_s = timed_steps(mk, q, phi, fld, rsteps, 1)
+        pl = mk()
+        eval_s, stages = timed_evaluations(pl, q, phi, fld, rsteps)
+        pl.close()
+        rphi, rfld = phi.cpu().numpy(), fld.cpu().numpy()
+        rs, rsf = sigma_of(rphi, rfld)
+        flops, nv = m2l_work(f["tree"], p)
+        S = (p + 1) * (2 * p + 1) * (2 * p + 3) // 3
+        SA = (p + 1) * (p + 2) * (2 * p + 3) // 6
+        rot_flops = 2.0 * (2 * S + (2 * SA - (p + 1) ** 2)) * nv  # per pair: F and B per degree, A per mode
+        log("bench plummer4m: p=%d rotation M2L %.2f ms (sign-class %.2f ms), step %.2f ms" %
+            (p, stages["m2l"], f["stages"]["m2l"], 1e3 * step_s))
+        out["m2l_rotation"] = {
+            "kernel": "k_m2l_rot<%d>" % p, "ms_per_launch": stages["m2l"],
+            "sign_class_ms_per_launch": f["stages"]["m2l"],
+            "flops_per_launch": rot_flops, "achieved": rot_flops / (stages["m2l"] * 1e-3) / 1e12,
+            "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s (FP64 vector)",
+            "frac": rot_flops / (stages["m2l"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+            "value": n / step_s, "ms_per_step": 1e3 * step_s, "eval_ms": 1e3 * eval_s,
+            "sigma_phi_vs_direct": rs, "sigma_field_vs_direct": rsf,
+            "rel_l2_vs_sign_class_phi": rel(rphi, f["phi"]), "rel_l2_vs_sign_class_field": rel(rfld, f["fld"]),
+            "work": "per V pair: 2 sum_n (2n+1)^2 (rotations) + 2 sum_m (p+1-|m|)^2 (axial) flops"}
     cores = oracle.num_threads()
     out["cpu_baseline"] = {"value": len(idx) / t_direct, "unit": "particles/s", "cores": cores, "kind": "oracle",
                            "seconds": t_direct,
@@ -647,6 +674,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-uniform", action="store_true")
+    ap.add_argument("--no-rotation", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs a solve on a single GPU "

@@ -54,7 +54,10 @@ enum {
     FMM_FP64 = 0,
     FMM_P2P_F32 = 1,   /* P2P pair terms in FP32, compensated (Kahan) FP32 sum
                           per target and source range, FP64 combination       */
-    FMM_M2L_F32 = 2,   /* M2L contraction on FP32 MFMA (orders <= 8)          */
+    FMM_M2L_F32 = 2,   /* M2L contraction on FP32 MFMA: all of it at orders
+                          <= 8, the rows of higher degree (all but the first
+                          16 of each parity class) from order 12; orders 9-11
+                          keep M2L in FP64                                    */
     FMM_MIXED = 3
 };
 
@@ -78,9 +81,18 @@ typedef struct {
     int32_t want_field;    /* nonzero: fmm_evaluate may be given a field array */
     const double *root;    /* host {lo_x, lo_y, lo_z, W} of the root cube, or
                               NULL for the bounding cube of the points        */
+    int32_t m2l_method;    /* FMM_M2L_SIGN_CLASS (default): the derivative-
+                              tensor contraction on the matrix cores, shared by
+                              the offsets of a sign class; FMM_M2L_ROTATION:
+                              the axis-rotation form of Sec. 3.4 on the vector
+                              unit (rotate, one-variable axial map, rotate
+                              back; FP64 whatever the precision)              */
 } fmm_options_t;
 
-/* Default options: adaptive, max_depth 21, FP64, field on, bounding cube. */
+enum { FMM_M2L_SIGN_CLASS = 0, FMM_M2L_ROTATION = 1 };
+
+/* Default options: adaptive, max_depth 21, FP64, field on, bounding cube,
+ * sign-class M2L. */
 void fmm_default_options(fmm_options_t *opt);
 
 /*
@@ -265,6 +277,19 @@ int fmm_plan_read_timing(fmm_plan_t plan, double ms[16], int64_t calls[16]);
  *         4  harmonic reconstruction: [(p+1)^2][n_p], the full harmonic Mhat
  *            from its components with z exponent <= 1 (harmonic order:
  *            degree n holds (i, n-i, 0) for i = n..0, then (i, n-1-i, 1))
+ *         5  rotation-based M2L (Sec. 3.4), multipole side: [64][S] per class
+ *            of offsets (|k_x|, |k_y|, |k_z|) at row |k_x| 16 + |k_y| 4 + |k_z|
+ *            (rows of the near offsets zero), S = sum_n (2n+1)^2: per degree n
+ *            a (2n+1)^2 block [folded component][mode], the map from the
+ *            folded multipole to azimuthal mode coordinates about the offset
+ *            (mode index 0 for m = 0, 2m - 1 + t for m > 0, t = 0 cos, 1 sin)
+ *         6  local side: [64][S], per degree a block [mode][folded component]
+ *         7  axial map: [distinct |k|^2][sum_m (p+1-m)^2], per m = 0..p a
+ *            block [n - m][l - m] coupling mode m of multipole degree n to
+ *            local degree l (the same for cos and sin)
+ *         8  [64] the axial block of each class (-1 for near offsets)
+ *            For a sign vector s, T(s o k) = R_s T(k) R_s, R_s = +-1 by the
+ *            parities of a folded component's exponents; T(k) = B A F.
  *   out_host   host buffer of `capacity` doubles, or NULL to query the size
  *   count      receives the number of doubles; ld the row length
  * Returns FMM_EINVAL for a bad order, table or a buffer too small.

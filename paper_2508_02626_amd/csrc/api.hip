@@ -206,7 +206,8 @@ struct fmm_plan_s {
     size_t footprint = 0;
     double root[4] = {0, 0, 0, 1};
     int p = 0, nc = 0, nh = 0, ldm = 0, ldh = 0, ldmh = 0, D = 0, depth = 0, leaf_size = 0;
-    int uniform = 0, precision = 0, mixed_m2l = 0;
+    int uniform = 0, precision = 0, mixed_m2l = 0, m2l_rot = 0;
+    const RotTables *rot = nullptr; // rotation-based M2L factors (device)
     int n = 0, nboxes = 0, nleaves = 0, nxtgt = 0, nslots = 0, m2l_parts = 1;
     int64_t nlist[4] = {0, 0, 0, 0};
     std::vector<int> lvl_begin;       // boxes per level (host)
@@ -342,6 +343,7 @@ extern "C" void fmm_default_options(fmm_options_t *opt)
     opt->precision = FMM_FP64;
     opt->want_field = 1;
     opt->root = nullptr;
+    opt->m2l_method = FMM_M2L_SIGN_CLASS;
 }
 
 extern "C" const char *fmm_last_error(void) { return g_err.c_str(); }
@@ -420,7 +422,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         P->nboxes = (int)tot;
     }
     const int nb = P->nboxes;
-    P->m2l_parts = sym_m2l_parts(P->p);
+    P->m2l_parts = P->m2l_rot ? 1 : sym_m2l_parts(P->p);
     // the sign-class M2L addresses the folded multipoles with 32-bit byte offsets
     if (m2l_sym(P->p) && (unsigned long long)(nb + 1) * (unsigned long long)P->ldmh * 8ULL >= (1ULL << 32))
         return fail(FMM_EUNSUPPORTED, "too many boxes for this order (folded multipoles reach 4 GiB)");
@@ -435,7 +437,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
          .add<double>((size_t)nb * P->ldm).add<double>((size_t)nb * P->ldm)
          .add<double>((size_t)(nb + 1) * P->ldmh).add<double>((size_t)nb * P->ldh);
         if (P->m2l_parts > 1) o.add<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh);
-        if (P->mixed_m2l) o.add<float>((size_t)(nb + 1) * P->ldmh);
+        if (P->mixed_m2l && m2l_f32_operands(P->p)) o.add<float>((size_t)(nb + 1) * P->ldmh);
         if (!P->reserve(true, o.total)) return fail(FMM_ENOMEM, "device allocation failed (boxes)");
         Sizer t;
         if (adaptive)
@@ -463,13 +465,13 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     double *M = P->own<double>((size_t)nb * P->ldm), *L = P->own<double>((size_t)nb * P->ldm);
     // folded multipoles: one row per box and an all-zero row after them
     double *Mh = P->own<double>((size_t)(nb + 1) * P->ldmh), *Lh = P->own<double>((size_t)nb * P->ldh);
-    float *Mhf = P->mixed_m2l ? P->own<float>((size_t)(nb + 1) * P->ldmh) : nullptr;
+    float *Mhf = P->mixed_m2l && m2l_f32_operands(P->p) ? P->own<float>((size_t)(nb + 1) * P->ldmh) : nullptr;
     // partial sums of the M2L class parts after the first
     double *Lh2 = P->m2l_parts > 1 ? P->own<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh) : nullptr;
     if (P->m2l_parts > 1) NOMEM(Lh2);
     NOMEM(vslot); NOMEM(leaves); NOMEM(nonleaf); NOMEM(xtgt); NOMEM(lnl_off); NOMEM(P->view_dev);
     NOMEM(M); NOMEM(L); NOMEM(Mh); NOMEM(Lh);
-    if (P->mixed_m2l) NOMEM(Mhf);
+    if (P->mixed_m2l && m2l_f32_operands(P->p)) NOMEM(Mhf);
     if (adaptive) {
         uint64_t *elevel = P->temp<uint64_t>(nb), *etk = P->temp<uint64_t>(nb), *emorton = P->temp<uint64_t>(nb);
         int32_t *eidx = P->temp<int32_t>(nb), *etv = P->temp<int32_t>(nb);
@@ -589,7 +591,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     v.U_off = P->off[0]; v.V_off = P->off[1]; v.W_off = P->off[2]; v.X_off = P->off[3];
     v.U_src = P->src[0]; v.W_src = P->src[2]; v.X_src = P->src[3]; v.wsrc = P->wsrc;
     v.m2l_tgt = slots; v.vslot = vslot; v.leaves = leaves; v.xtgt = xtgt;
-    v.lvl_nonleaf = nonleaf; v.lvl_nonleaf_off = lnl_off; v.tab = P->tab;
+    v.lvl_nonleaf = nonleaf; v.lvl_nonleaf_off = lnl_off; v.tab = P->tab; v.rot = P->rot;
     // row `nb` of the folded multipoles is the all-zero operand of absent M2L
     // sources; it is never written by an evaluation
     launch_zero(Mh + (size_t)nb * P->ldmh, P->ldmh, s);
@@ -612,6 +614,8 @@ int check_options(const fmm_options_t &o, int order, int leaf_size)
     if (o.uniform_depth < 0 && (o.max_depth < 1 || o.max_depth > kMaxDepth))
         return fail(FMM_EINVAL, "max_depth must be 1..21");
     if (o.precision & ~FMM_MIXED) return fail(FMM_EINVAL, "bad precision");
+    if (o.m2l_method != FMM_M2L_SIGN_CLASS && o.m2l_method != FMM_M2L_ROTATION)
+        return fail(FMM_EINVAL, "bad m2l_method");
     if (o.uniform_depth < 0 && leaf_size < 1) return fail(FMM_EINVAL, "leaf_size must be >= 1");
     if (order < 0 || order > kMaxOrder) return fail(FMM_EINVAL, "order must be 0..16");
     if (o.root) {
@@ -664,7 +668,12 @@ extern "C" int fmm_plan(const double *xyz_dev, int64_t n, int32_t order, int32_t
     P->D = P->uniform ? o.uniform_depth : o.max_depth;
     P->leaf_size = leaf_size;
     P->precision = o.precision;
-    P->mixed_m2l = ((o.precision & FMM_M2L_F32) && (order <= 8 || order >= 12)) ? 1 : 0;
+    P->m2l_rot = o.m2l_method == FMM_M2L_ROTATION;
+    P->mixed_m2l = (!P->m2l_rot && (o.precision & FMM_M2L_F32) && (order <= 8 || order >= 12)) ? 1 : 0;
+    if (P->m2l_rot) {
+        P->rot = get_rotation_tables(order, err);
+        if (!P->rot) { delete P; return fail(FMM_EDEVICE, err); }
+    }
     P->n = (int)n;
     P->tab = tab;
     if (o.root) for (int k = 0; k < 4; ++k) P->root[k] = o.root[k];
@@ -774,8 +783,8 @@ StagePlan stage_blocks(const fmm_plan_s *P)
     StagePlan sp;
     sp.permute = (int)ceil_div(P->n, 256);
     sp.p2m = P->nleaves;
-    sp.fold = (int)ceil_div(P->nleaves, 16) * (P->ldh / 16);
-    sp.m2l = P->nslots / kM2LSlots * P->m2l_parts; // sign classes: m2l_parts blocks per tile
+    sp.fold = (int)ceil_div(P->nleaves, 64);
+    sp.m2l = P->nslots / kM2LSlots * (P->m2l_rot ? m2l_rot_blocks_per_tile(P->p) : P->m2l_parts);
     sp.p2l = P->nxtgt;
     sp.unfold = (int)ceil_div(P->nboxes, kRemapBoxes);
     sp.far = (int)ceil_div(P->nleaves, 2); // two leaves per block
@@ -877,7 +886,9 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     int nruns = 0;
     for (int i = 0; i < count;) {
         int j = i;
-        while (j < count && P[j]->p == P[i]->p && P[j]->mixed_m2l == P[i]->mixed_m2l) ++j;
+        while (j < count && P[j]->p == P[i]->p && P[j]->mixed_m2l == P[i]->mixed_m2l &&
+               P[j]->m2l_rot == P[i]->m2l_rot)
+            ++j;
         runs_buf[nruns++] = {i, j};
         i = j;
     }
@@ -895,9 +906,9 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
                    sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).p2m; }), s);
     T.end();
     T.begin(3);
-    launch_p2m_fold(V, sub(0, count, [](const fmm_plan_s *p) { return stage_blocks(p).fold; }), s);
-    launch_p2m_transform(V, sub(0, count, [](const fmm_plan_s *p) {
-        return p->nlist[2] > 0 ? (int)ceil_div(p->nleaves, 16) * (p->ldm / 16) : 0; }), s);
+    for (auto &r : runs)
+        launch_p2m_fold(P[r.first]->p, V + r.first,
+                        sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).fold; }), s);
     T.end();
     int maxdepth = 0;
     for (int i = 0; i < count; ++i) maxdepth = std::max(maxdepth, P[i]->depth);
@@ -908,11 +919,11 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     for (auto &r : runs)
         for (int l = maxdepth - 1; l >= 2; --l)
             launch_m2mh(P[r.first]->p, V + r.first,
-                        sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l) * (p->ldmh / 16); }), l, s);
+                        sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l); }), l, s);
     // parents' FP32 operands (mixed M2L) and full multipoles (M2P sources)
     for (auto &r : runs) {
         int mixed = 0, wl = 0;
-        for (int i = r.first; i < r.second; ++i) { mixed |= P[i]->mixed_m2l; wl |= P[i]->nlist[2] > 0; }
+        for (int i = r.first; i < r.second; ++i) { mixed |= P[i]->view.Mhf != nullptr; wl |= P[i]->nlist[2] > 0; }
         if (mixed || wl)
             launch_parent_mh(V + r.first,
                              sub(r.first, r.second, [](const fmm_plan_s *p) { return (int)ceil_div(p->nboxes, 4); }), wl, s);
@@ -921,8 +932,12 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     HIPCHK(hipStreamWaitEvent(s, F->ev_join, 0)); // first part of P2P done
     T.begin(4);
     for (auto &r : runs)
-        launch_m2l(P[r.first]->p, P[r.first]->mixed_m2l, V + r.first,
-                   sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).m2l; }), s);
+        if (P[r.first]->m2l_rot)
+            launch_m2l_rot(P[r.first]->p, V + r.first,
+                           sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).m2l; }), s);
+        else
+            launch_m2l(P[r.first]->p, P[r.first]->mixed_m2l, V + r.first,
+                       sub(r.first, r.second, [](const fmm_plan_s *p) { return stage_blocks(p).m2l; }), s);
     T.end();
     HIPCHK(hipEventRecord(F->ev_fork, s)); // second part of P2P next to the downward pass
     HIPCHK(hipStreamWaitEvent(F->side, F->ev_fork, 0));
@@ -1015,6 +1030,7 @@ int batch_prepare(fmm_plan_t const *plans, const double *const *q_dev, double *c
     std::sort(idx, idx + count, [&](int a, int b) {
         if (plans[a]->p != plans[b]->p) return plans[a]->p < plans[b]->p;
         if (plans[a]->mixed_m2l != plans[b]->mixed_m2l) return plans[a]->mixed_m2l < plans[b]->mixed_m2l;
+        if (plans[a]->m2l_rot != plans[b]->m2l_rot) return plans[a]->m2l_rot < plans[b]->m2l_rot;
         return a < b;
     });
     return 0;
@@ -1215,7 +1231,7 @@ extern "C" int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, d
         B.n = 1;
         B.b[0] = 0;
         for (int l = std::min(P->depth - 1, 1); l >= 0; --l) {
-            B.b[1] = nonleaf_groups(P, l) * (P->ldmh / 16);
+            B.b[1] = nonleaf_groups(P, l);
             launch_m2mh(P->p, P->view_dev, B, l, stream);
         }
         B.b[1] = (int)ceil_div(P->nboxes, 4);

@@ -134,15 +134,11 @@ __host__ __device__ constexpr int sym_m2l_parts(int p) { return m2l_sym(p) ? 2 :
 // made of the shorter blocks (uniform 10^6 points, p = 8, FP64: about 6%
 // faster at 68-74 than at 50-56, slower again from 78)
 constexpr int kSymFirstPart = 72;
-// launches the row tiles of an order >= 12 sign-class M2L are split over (at
-// most 9 row tiles of accumulators per wavefront)
-__host__ __device__ constexpr int sym_row_parts(int p) { return p >= 12 ? (sym_row_tiles(p) + 8) / 9 : 1; }
 // Order of the row tiles: by parity class, then tile within the class, up to
 // p = 11; from p = 12 by tile within the class first (the first 16 rows of
-// every class, then the next 16, ...), so that each of the sym_row_parts
-// launches holds rows of similar degree (rows of a class are in increasing
-// degree) and the first one the lowest degrees.  Class and tile-in-class of
-// row tile r:
+// every class, then the next 16, ...): rows of a class are in increasing
+// degree, so the first eight tiles hold the lowest degrees (the FP32 M2L of
+// these orders keeps them in FP64).  Class and tile-in-class of row tile r:
 __host__ __device__ constexpr int sym_tile_class(int p, int r, bool want_class)
 {
     if (p < 12) {
@@ -164,10 +160,12 @@ __host__ __device__ constexpr int sym_tile_class(int p, int r, bool want_class)
 // Folded multipoles of sign-class orders are stored so that a lane's
 // operands of vw consecutive k-steps are adjacent (one 16-byte load): sorted
 // column 4 ks + g (k-step ks, lane group g) sits at 4 vw (ks / vw) + vw g +
-// ks % vw, vw = 2 for FP64 and 4 for FP32 (2 for both from p = 12, where
-// the operands move two k-steps at a time in either precision).
+// ks % vw, vw = 2 for FP64 and 4 for FP32.
 __host__ __device__ constexpr int sym_pos(int ks, int g, int vw) { return 4 * vw * (ks / vw) + vw * g + ks % vw; }
 // row stride of the folded multipoles (both precisions' layouts fit)
+// orders whose FP32 M2L reads an FP32 copy of the folded multipoles (above
+// them the FP32 row tiles round the FP64 operands in registers)
+__host__ __device__ constexpr bool m2l_f32_operands(int p) { return p <= 8; }
 __host__ __device__ constexpr int folded_ld(int p)
 {
     return m2l_sym(p) ? 16 * ((sym_ksteps(p) + 3) / 4) : (((p + 1) * (p + 1) + 15) & ~15);
@@ -285,6 +283,15 @@ struct OrderTables {
     const int *exps;            // [nc] packed exponents i | j<<8 | k<<16
 };
 
+// Rotation-based M2L factors of one order (device pointers): per class of
+// offsets (|k_x|, |k_y|, |k_z|) the multipole map F and local map B (per
+// degree, [input][output]), the axial blocks A per distinct |k|^2 and the
+// block of each class (rotation.hip).
+struct RotTables {
+    const double *F, *B, *A;
+    const int *aidx;
+};
+
 // Everything a kernel needs to know about one plan (lives in device memory).
 struct PlanView {
     int p, nc, nh, ldm, ldh, ldmh;
@@ -307,6 +314,7 @@ struct PlanView {
     const int32_t *lvl_nonleaf;         // non-leaf boxes grouped by level
     const int32_t *lvl_nonleaf_off;     // [depth+2] ranges into lvl_nonleaf
     const OrderTables *tab;             // device copy of the order tables
+    const RotTables *rot;               // rotation-based M2L factors (device), or null
     // evaluation buffers
     double *qs;                         // sorted charges
     double *M, *Mh, *Lh, *L;            // [boxes][ldm] / [boxes][ldmh] / [boxes][ldh]

@@ -736,38 +736,41 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
 
 // ---------------- sign-class M2L for orders >= 12 ----------------
 // The same decomposition as k_m2l_sym (classes in zero-mask order, m2l_parts
-// blocks per tile over parts of the classes, transform of the members, one MFMA per
-// row tile and k-step with a compile-time transform output), organised so
-// that the code stays small at high order: the row tiles are split over
-// sym_row_parts launches (at most 9 tiles of accumulators per wavefront), and
-// within a class the eight column classes are unrolled while each one's
-// k-steps run in a loop over 16-byte operand vectors (two k-steps; columns are
-// padded to 8 per class so that no vector straddles two classes).  Operands
-// move one vector ahead through a current / next register pair, the next
-// class's first vector loaded during the last one.  The targets' slot rows
-// are read from memory (the classes a block uses come from a 64-bit mask
-// built by all threads), which leaves LDS to the derivative tables.
-// T = float (mixed precision, launches RH >= 1: the higher-degree row tiles):
-// FP32 tables and operands on FP32 MFMA, each class's products summed in FP32
-// and added to FP64 accumulators after the class.
-template <int P, int RH, typename T>
-__global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
+// blocks per tile over parts of the classes, transform of the members, one
+// MFMA per row tile and k-step with a compile-time transform output),
+// organised so that the code stays small at high order: within a class the
+// eight column classes are unrolled while each one's k-steps run in a loop
+// over 16-byte operand vectors (two k-steps; columns are padded to 8 per
+// class so that no vector straddles two classes).  Operands move one vector
+// ahead through a current / next register pair, the next class's first vector
+// loaded during the last one.  The targets' slot rows are read from memory
+// (the classes a block uses come from a 64-bit mask built by all threads),
+// which leaves LDS to the derivative tables.  All row tiles of the 16
+// targets stay in one wavefront (one wavefront per SIMD, the accumulators in
+// the accumulation registers), so that every member operand and transform
+// serves every row.  Row tiles from F32T on (the higher degrees: rows are in
+// sym_tile_class order) run on FP32 MFMA from the same FP64 operands and
+// transform outputs rounded to FP32, each class's FP32 sums added into FP64
+// after the class; a local coefficient of degree n carries about rho^n of the
+// far field (rho < 1 the convergence ratio), which scales their rounding down.
+template <int P, int F32T>
+__global__ __launch_bounds__(256, 1) void k_m2l_symh(const PlanView *V, Bases B)
 {
+    typedef double T;
     static constexpr SymShape<P> S{};
     constexpr int RT = SymShape<P>::RT, KS = SymShape<P>::KS;
-    constexpr int NRP = sym_row_parts(P), MTP = (RT + NRP - 1) / NRP, R0 = RH * MTP;
-    constexpr int MTW = RT - R0 < MTP ? RT - R0 : MTP; // row tiles [R0, R0 + MTW)
-    static_assert(RH < NRP && MTW >= 1 && MTW <= 9, "row part");
+    constexpr int MTW = RT, R0 = 0;
+    static_assert(MTW <= 24 && F32T >= 1 && F32T <= RT, "row tiles");
+    constexpr int N32 = RT - F32T; // FP32 row tiles
     static_assert(KS % 2 == 0 && 8 * (KS / 2) <= folded_ld(P), "two-k-step vectors inside the folded row");
     constexpr int KSV = KS / 2; // operand vectors per class
     constexpr int NT = 256;
     constexpr int LDD = dlayout_ldd(P), LDC = dlayout_ldc(P);
-    constexpr int DW = 16 / (int)sizeof(T); // compact tables move in 16-byte vectors
+    constexpr int DW = 2; // compact tables move in 16-byte vectors
     static_assert(LDC % DW == 0, "compact rows must be whole vectors");
     constexpr int DV = (LDC / DW + NT - 1) / NT;
-    constexpr bool F32 = sizeof(T) == 4;
-    constexpr uint32_t VB = 2 * sizeof(T); // bytes of one lane's two-k-step operand vector
     typedef typename Mfma<T>::acc_t acc_t;
+    typedef typename Mfma<float>::acc_t acc32_t;
     typedef T vec_t __attribute__((ext_vector_type(2)));
     __shared__ T sD[2][LDD];
     __shared__ int sHo[4][KS];
@@ -785,7 +788,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     const int parts = v.m2l_parts;
     int tile, part;
     sym_block(blockIdx.x - B.b[k], B.b[k + 1] - B.b[k], parts, tile, part);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
+    const int tid = threadIdx.x, lane = tid & 63, col = lane & 15, kq = lane >> 4;
     const OrderTables &tb = *v.tab;
     int hb[MTW];
     const int tgt = sym_setup_tile<MTW, KS, R0>(v, tb, tile, tid, col, hb, sTg, sHo, &soct, &sUsed);
@@ -817,15 +820,16 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     __syncthreads();
     const int qa = sQa, qb = sQb;
     const int64_t ldmh = v.ldmh;
-    const T *Dt = Mfma<T>::D(tb);
-    const T *Mh = Mfma<T>::M(v);
+    const T *Dt = tb.D;
+    const T *Mh = v.Mh;
 
-    acc_t acc[MTW];
+    acc_t acc[F32T];
 #pragma unroll
-    for (int mt = 0; mt < MTW; ++mt) acc[mt] = acc_t{0, 0, 0, 0};
-    double4_t acc64[F32 ? MTW : 1]; // FP32: per-class sums added here
+    for (int mt = 0; mt < F32T; ++mt) acc[mt] = acc_t{0, 0, 0, 0};
+    acc32_t acc32[N32 > 0 ? N32 : 1];
+    double4_t acc64[N32 > 0 ? N32 : 1]; // FP32 tiles: per-class sums added here
 #pragma unroll
-    for (int mt = 0; mt < (F32 ? MTW : 1); ++mt) acc64[mt] = double4_t{0, 0, 0, 0};
+    for (int mt = 0; mt < N32; ++mt) { acc32[mt] = acc32_t{0, 0, 0, 0}; acc64[mt] = double4_t{0, 0, 0, 0}; }
 
     typedef T dvec_t __attribute__((ext_vector_type(DW)));
     dvec_t pd[DV];
@@ -854,8 +858,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     };
     // member operand rows as 32-bit byte offsets (plans check the 4 GiB bound);
     // absent members read the zero row after the boxes
-    constexpr uint32_t ES = sizeof(T);
-    const uint32_t zoff = (uint32_t)v.nboxes * (uint32_t)ldmh * ES;
+    const uint32_t zoff = (uint32_t)v.nboxes * (uint32_t)ldmh * 8u;
     const uint32_t vrow = (uint32_t)(tgt >= 0 ? tgt : 0) * (uint32_t)kVSlots;
     auto class_src = [&](int q, uint32_t (&src)[8]) {
         const int c = sList[q];
@@ -863,7 +866,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
         for (int m = 0; m < 8; ++m) {
             const int j = sMem[c][m];
             const int b = j >= 0 && tgt >= 0 ? vs[vrow + (uint32_t)j] : -1;
-            src[m] = (b >= 0 ? (uint32_t)b * (uint32_t)ldmh * ES : zoff) + VB * (uint32_t)kq;
+            src[m] = (b >= 0 ? (uint32_t)b * (uint32_t)ldmh * 8u : zoff) + 16u * (uint32_t)kq;
         }
     };
     const auto Mg = gptr((const char *)Mh);
@@ -872,7 +875,7 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
         for (int m = 0; m < 8; ++m) {
             uint32_t o = src[m];
             asm volatile("" : "+v"(o));
-            dst[m] = *(gp<const vec_t>)(Mg + (uint64_t)o + 4 * VB * j);
+            dst[m] = *(gp<const vec_t>)(Mg + (uint64_t)o + 64 * j);
         }
     };
     uint32_t srcc[8], srcn[8];
@@ -902,15 +905,24 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
                     T ac[MTW];
 #pragma unroll
                     for (int mt = 0; mt < MTW; ++mt)
-                        if (!((S.rc[R0 + mt] ^ TAU) & Z)) ac[mt] = D[hb[mt] + ha];
+                        if (!((S.rc[mt] ^ TAU) & Z)) ac[mt] = D[hb[mt] + ha];
                     T h[8];
 #pragma unroll
                     for (int m = 0; m < 8; ++m) h[m] = cur[m][w];
                     wht8(h);
 #pragma unroll
-                    for (int mt = 0; mt < MTW; ++mt)
-                        if (!((S.rc[R0 + mt] ^ TAU) & Z))
-                            acc[mt] = Mfma<T>::run(ac[mt], h[S.rc[R0 + mt] ^ TAU], acc[mt]);
+                    for (int mt = 0; mt < F32T; ++mt)
+                        if (!((S.rc[mt] ^ TAU) & Z))
+                            acc[mt] = Mfma<T>::run(ac[mt], h[S.rc[mt] ^ TAU], acc[mt]);
+                    if constexpr (N32 > 0) {
+                        float hf[8];
+#pragma unroll
+                        for (int m = 0; m < 8; ++m) hf[m] = (float)h[m];
+#pragma unroll
+                        for (int mt = F32T; mt < MTW; ++mt)
+                            if (!((S.rc[mt] ^ TAU) & Z))
+                                acc32[mt - F32T] = Mfma<float>::run((float)ac[mt], hf[S.rc[mt] ^ TAU], acc32[mt - F32T]);
+                    }
                 }
 #pragma unroll
                 for (int m = 0; m < 8; ++m) cur[m] = nxt[m];
@@ -936,12 +948,12 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
                 class_src(q + 1, srcn);
             }
             run_class(zc, sD[curb]);
-            if constexpr (F32) {
+            if constexpr (N32 > 0) {
 #pragma unroll
-                for (int mt = 0; mt < MTW; ++mt) {
+                for (int mt = 0; mt < N32; ++mt) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) acc64[mt][r] += (double)acc[mt][r];
-                    acc[mt] = acc_t{0, 0, 0, 0};
+                    for (int r = 0; r < 4; ++r) acc64[mt][r] += (double)acc32[mt][r];
+                    acc32[mt] = acc32_t{0, 0, 0, 0};
                 }
             }
 #pragma unroll
@@ -960,15 +972,19 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
     if (tgt < 0) return;
     double *Lh = (part ? v.Lh2 + (int64_t)(part - 1) * v.nboxes * v.ldh : v.Lh) + (int64_t)tgt * v.ldh;
 #pragma unroll
-    for (int mt = 0; mt < MTW; ++mt) {
+    for (int mt = 0; mt < F32T; ++mt) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int b = gptr(tb.srow)[16 * (R0 + mt) + Mfma<T>::row(lane, r)];
-            if constexpr (F32) {
-                if (b >= 0) Lh[b] = acc64[mt][r];
-            } else {
-                if (b >= 0) Lh[b] = acc[mt][r];
-            }
+            const int b = gptr(tb.srow)[16 * mt + Mfma<T>::row(lane, r)];
+            if (b >= 0) Lh[b] = acc[mt][r];
+        }
+    }
+#pragma unroll
+    for (int mt = F32T; mt < MTW; ++mt) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int b = gptr(tb.srow)[16 * mt + Mfma<float>::row(lane, r)];
+            if (b >= 0) Lh[b] = acc64[mt - F32T][r];
         }
     }
 }
@@ -988,23 +1004,15 @@ __global__ __launch_bounds__(256, 2) void k_m2l_symh(const PlanView *V, Bases B)
 #define M2L_SYM64(PP)                                                              \
     case PP: k_m2l_sym<PP, double><<<nb, 256, 0, s>>>(V, B); break;
 
-// Orders >= 12: one launch per row part.  With f32 the first part (the
-// lowest degrees of every parity class) stays FP64 and the others run on
-// FP32 MFMA: a local coefficient of degree n carries about rho^n of the far
-// field, rho < 1 the expansion's convergence ratio, so the FP32 rounding of
-// the high-degree rows is scaled down by it.
+// Orders >= 12: one launch with every row tile; with f32 the row tiles after
+// the first eight (the first 16 rows, lowest degrees, of each parity class
+// stay FP64; rows are in sym_tile_class order) run on FP32 MFMA.
 template <int P> void launch_symh(unsigned nb, const PlanView *V, const Bases &B, int f32, hipStream_t s)
 {
-    static_assert(sym_row_parts(P) <= 3, "row parts");
-    k_m2l_symh<P, 0, double><<<nb, 256, 0, s>>>(V, B);
-    if constexpr (sym_row_parts(P) > 1) {
-        if (f32) k_m2l_symh<P, 1, float><<<nb, 256, 0, s>>>(V, B);
-        else k_m2l_symh<P, 1, double><<<nb, 256, 0, s>>>(V, B);
-    }
-    if constexpr (sym_row_parts(P) > 2) {
-        if (f32) k_m2l_symh<P, 2, float><<<nb, 256, 0, s>>>(V, B);
-        else k_m2l_symh<P, 2, double><<<nb, 256, 0, s>>>(V, B);
-    }
+    constexpr int RT = sym_row_tiles(P);
+    static_assert(RT > 8 && sym_tile_class(P, 7, false) == 0 && sym_tile_class(P, 8, false) == 1, "tile order");
+    if (f32) k_m2l_symh<P, 8><<<nb, 256, 0, s>>>(V, B);
+    else k_m2l_symh<P, RT><<<nb, 256, 0, s>>>(V, B);
 }
 #define M2L_SYMH(PP) \
     case PP: launch_symh<PP>(nb, V, B, f32, s); break;

@@ -1,16 +1,16 @@
 // Launchers of the evaluation kernels (see ops.hip and m2l.hip).  Every
 // launcher takes the device array of plan views and the block split.
 #pragma once
+#include <string>
 #include "common.h"
 
 namespace fmm {
 void launch_permute_q(const PlanView *V, const Bases &B, hipStream_t s);   // 256 particles/block
 void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 leaf/block
-void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s); // 16 leaves x 16 rows/block (M2P sources)
-void launch_p2m_fold(const PlanView *V, const Bases &B, hipStream_t s); // 16 leaves x 16 harmonic rows/block
+void launch_p2m_fold(int p, const PlanView *V, const Bases &B, hipStream_t s); // 64 leaves/block
 void launch_l2lh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block (harmonic rows)
 void launch_lh_init(const PlanView *V, const Bases &B, hipStream_t s);        // 4 boxes/block
-void launch_m2mh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 folded rows/block
+void launch_m2mh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents/block
 void launch_parent_mh(const PlanView *V, const Bases &B, int full, hipStream_t s); // 4 boxes/block
 void launch_unfold(int p, const PlanView *V, const Bases &B, int leaves_only, hipStream_t s); // kRemapBoxes boxes/block
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 X target/block
@@ -25,5 +25,10 @@ void launch_zero(double *p, int64_t n, hipStream_t s);
 void launch_zero_f32(float *p, int64_t n, hipStream_t s);
 void launch_m2l(int p, int f32, const PlanView *V, const Bases &B, hipStream_t s); // 64 slots/block
 constexpr int kM2LSlots = 64;
+// rotation-based M2L (rotation.hip): device factors of order p (built on
+// first use, kept for the process), blocks per 64-target tile, launcher
+const RotTables *get_rotation_tables(int p, std::string &err);
+int m2l_rot_blocks_per_tile(int p);
+void launch_m2l_rot(int p, const PlanView *V, const Bases &B, hipStream_t s);
 constexpr int kRemapBoxes = 16; // boxes per block of the unfold
 } // namespace fmm

@@ -161,95 +161,93 @@ __global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
         col_add<P>(py, pz, xw, m, cb, cc, acc);
     }
     // raw moments go to the (not yet used) local-expansion row of the leaf;
-    // k_p2m_transform turns them into Mhat
+    // k_p2m_fold turns them into the folded (and, for M2P sources, full) Mhat
     col_store<P>(v.L + (int64_t)box * v.ldm, lane, cb, cc, acc);
 }
 
 // Folded multipoles of the leaves straight from their raw moments:
-// Mh = FP2M^t Q (P2M followed by the fold, one matrix) for 16 leaves x 16
-// harmonic components per wavefront (FP64 MFMA), stored at the components'
-// folded positions (and in the FP32 copy for the FP32 M2L).  Both maps keep
-// the degree, so a tile of components visits only its degrees' moments.  The
-// first tile's wavefront also writes the padding positions of the rows
-// (zero: the M2L reads them as operands of padded columns).
-__global__ __launch_bounds__(64) void k_p2m_fold(const PlanView *V, Bases B)
+// Mh = FP2M^t Q (P2M followed by the fold, one matrix; both keep the degree)
+// and, for groups holding a leaf that M2P reads (a W-list source), the full
+// Mhat = P2M^t Q as well.  A wavefront takes 16 leaves and walks the degrees:
+// it loads the 16 leaves' moments of degree n once (the B operands of every
+// k-step), then runs the 16-row tiles of that degree's 2n+1 folded
+// components (and n_p-block rows of the full multipole) on FP64 MFMA.
+// Results go to the components' folded positions (and the FP32 copy for the
+// FP32 M2L); the padding positions of the rows are written as zeros (the M2L
+// reads them as operands of padded columns).
+template <int P>
+__global__ __launch_bounds__(256) void k_p2m_fold(const PlanView *V, Bases B)
 {
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
-    const int item = blockIdx.x - B.b[k];
-    const int MT = v.ldh / 16, g = item / MT, mt = item - g * MT;
-    const int lane = threadIdx.x, col = lane & 15, kq = lane >> 4;
-    const int li = g * 16 + col;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
+    const int li = (blockIdx.x - B.b[k]) * 64 + wave * 16 + col;
     const int leaf = li < v.nleaves ? v.leaves[li] : -1;
-    const int nh = v.nh, ldh = v.ldh, ldm = v.ldm, ldmh = v.ldmh;
+    if (!__any(leaf >= 0)) return;
+    const bool full = v.wsrc && __any(leaf >= 0 && v.wsrc[leaf]);
+    constexpr int NC = ncoef(P), NH = nharm(P), LDM = pad16(NC), LDH = pad16(NH);
+    const int ldmh = v.ldmh;
     const OrderTables &t = *v.tab;
-    const int bA = mt * 16 + col;
-    auto hdeg = [](int c) { int n = 0; while ((n + 1) * (n + 1) <= c) ++n; return n; };
-    const int dlo = hdeg(mt * 16 < nh ? mt * 16 : nh - 1);
-    const int dhi = hdeg(mt * 16 + 15 < nh ? mt * 16 + 15 : nh - 1);
-    const int k0 = below(dlo) & ~3, k1 = below(dhi + 1);
-    const auto T = gptr(t.FP2M);
-    const auto Q = gptr(v.L + (int64_t)(leaf >= 0 ? leaf : 0) * ldm);
-    double4_t acc = {0, 0, 0, 0};
-#pragma unroll 4
-    for (int kk = k0; kk < k1; kk += 4) {
-        const int a = kk + kq;
-        const double av = (bA < nh && a < v.nc) ? T[(int64_t)a * ldh + bA] : 0.0;
-        const double bv = (leaf >= 0 && a < v.nc) ? Q[a] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
-    if (leaf < 0) return;
-    const auto Mh = gptr(v.Mh + (int64_t)leaf * ldmh);
-    const bool f32 = v.mixed_m2l;
+    const auto Q = gptr(v.L + (int64_t)(leaf >= 0 ? leaf : 0) * LDM);
+    const auto FT = gptr(t.FP2M), PT = gptr(t.P2M);
+    const auto Mh = gptr(v.Mh + (int64_t)(leaf >= 0 ? leaf : 0) * ldmh);
+    const auto Mf = gptr(v.M + (int64_t)(leaf >= 0 ? leaf : 0) * LDM);
+    const bool f32 = v.Mhf != nullptr; // FP32 copy for the FP32 M2L
 #pragma unroll
-    for (int r = 0; r < 4; ++r) { // f64 layout: lane l reg r -> row 4r + l/16
-        const int c = mt * 16 + 4 * r + kq;
-        if (c < nh) {
-            Mh[t.hpos[c]] = acc[r];
-            if (f32) gptr(v.Mhf)[(int64_t)leaf * ldmh + t.hposf[c]] = (float)acc[r];
+    for (int n = 0; n <= P; ++n) {
+        const int g0 = below(n), mn = (n + 1) * (n + 2) / 2, KS = (mn + 3) / 4;
+        double q[(P + 1) * (P + 2) / 8 + 1];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int g = 4 * s + kq;
+            q[s] = leaf >= 0 && g < mn ? Q[g0 + g] : 0.0;
+        }
+        // folded components n^2 .. (n+1)^2 - 1
+#pragma unroll
+        for (int t0 = 0; t0 < 2 * n + 1; t0 += 16) {
+            const int c = n * n + t0 + col, cend = (n + 1) * (n + 1);
+            double4_t acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int g = 4 * s + kq;
+                const double a = c < cend && g < mn ? FT[(int64_t)(g0 + g) * LDH + c] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, q[s], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) { // f64 layout: lane l reg r -> row 4r + l/16
+                const int cr = n * n + t0 + 4 * r + kq;
+                if (leaf >= 0 && cr < cend) {
+                    Mh[t.hpos[cr]] = acc[r];
+                    if (f32) gptr(v.Mhf)[(int64_t)leaf * ldmh + t.hposf[cr]] = (float)acc[r];
+                }
+            }
+        }
+        if (!full) continue;
+        // full multipole, monomials g0 .. g0 + mn - 1
+#pragma unroll
+        for (int t0 = 0; t0 < mn; t0 += 16) {
+            const int b = g0 + t0 + col;
+            double4_t acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int g = 4 * s + kq;
+                const double a = t0 + col < mn && g < mn ? PT[(int64_t)(g0 + g) * NC + b] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, q[s], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int br = t0 + 4 * r + kq;
+                if (leaf >= 0 && br < mn) Mf[g0 + br] = acc[r];
+            }
         }
     }
-    if (mt == 0)
-        for (int pos = kq; pos < ldmh; pos += 4) {
-            if (t.mpos[pos] < 0) Mh[pos] = 0.0;
-            if (f32 && t.mposf[pos] < 0) gptr(v.Mhf)[(int64_t)leaf * ldmh + pos] = 0.f;
-        }
-}
-
-// Full Mhat = P2M^t Q for 16 leaves x 16 coefficients per wavefront (FP64
-// MFMA), for the leaves M2P reads (sources of W lists); the matrix is block
-// diagonal by degree, so only the tile's degree range of moments is visited.
-__global__ __launch_bounds__(64) void k_p2m_transform(const PlanView *V, Bases B)
-{
-    const int k = find_plan(B, blockIdx.x);
-    const PlanView &v = V[k];
-    const int item = blockIdx.x - B.b[k];
-    const int MT = v.ldm / 16, g = item / MT, mt = item - g * MT;
-    const int lane = threadIdx.x, col = lane & 15, kq = lane >> 4;
-    const int li = g * 16 + col;
-    const int leaf = li < v.nleaves ? v.leaves[li] : -1;
-    if (!__any(leaf >= 0 && v.wsrc && v.wsrc[leaf])) return; // no M2P source among the 16
-    const int nc = v.nc, ldm = v.ldm;
-    const int bA = mt * 16 + col;
-    const double *T = v.tab->P2M;
-    const int dlo = degree_of(mt * 16 < nc ? mt * 16 : nc - 1);
-    const int dhi = degree_of(mt * 16 + 15 < nc ? mt * 16 + 15 : nc - 1);
-    const int k0 = below(dlo) & ~3, k1 = below(dhi + 1);
-    const double *Q = leaf >= 0 ? v.L + (int64_t)leaf * ldm : nullptr;
-    double4_t acc = {0, 0, 0, 0};
-#pragma unroll 4
-    for (int kk = k0; kk < k1; kk += 4) {
-        const int a = kk + kq;
-        const double av = (bA < nc && a < nc) ? T[(int64_t)a * nc + bA] : 0.0;
-        const double bv = (Q && a < nc) ? Q[a] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
     if (leaf < 0) return;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int b = mt * 16 + 4 * r + kq;
-        v.M[(int64_t)leaf * ldm + b] = b < nc ? acc[r] : 0.0;
+    for (int pos = kq; pos < ldmh; pos += 4) { // padding of the folded rows
+        if (t.mpos[pos] < 0) Mh[pos] = 0.0;
+        if (f32 && t.mposf[pos] < 0) gptr(v.Mhf)[(int64_t)leaf * ldmh + pos] = 0.f;
     }
+    if (full)
+        for (int b = NC + kq; b < LDM; b += 4) Mf[b] = 0.0;
 }
 
 constexpr int kPG = 16; // parents per translation block
@@ -301,37 +299,57 @@ __device__ inline void mfma_rows(const double *A, int lda, int bA, bool aok, con
 // ---------------- M2M on the folded components ----------------
 // The far field of a multipole, hence its translation truncated at degree p,
 // depends only on its folded vector: Mh(parent) = sum_o TM_o^t Mh(child_o),
-// TM_o a (folded positions)^2 matrix.  A block computes 16 folded positions of
-// 16 parents of one level, one wavefront per child octant (16x16x4 FP64 MFMA),
-// the eight partial tiles summed in octant order.
+// TM_o a (folded positions)^2 matrix.  A block takes 16 parents of one level,
+// one wavefront per child octant (16x16x4 FP64 MFMA): the wavefront loads its
+// children's folded vectors once (the B operands of every k-step) and runs
+// every row tile of the parents' vectors; the eight octants' partial tiles
+// are summed in octant order through LDS.
 template <int P>
 __global__ __launch_bounds__(512) void k_m2mh(const PlanView *V, Bases B, int level)
 {
     __shared__ double4_t red[8][64];
-    constexpr int LD = folded_ld(P), MT = LD / 16;
+    constexpr int LD = folded_ld(P), MT = LD / 16, KS = LD / 4;
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
-    const int item = blockIdx.x - B.b[k];
-    const int ld = LD, g = item / MT, mt = item - g * MT;
+    const int g = blockIdx.x - B.b[k];
     const int o = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63, col = lane & 15, kq = lane >> 4;
     const int lb = v.lvl_nonleaf_off[level], le = v.lvl_nonleaf_off[level + 1];
     const int pidx = lb + g * kPG + col;
     const int parent = pidx < le ? v.lvl_nonleaf[pidx] : -1;
     const int ch = child_in_octant(v, parent, o); // child of this lane's parent in octant o
-    double4_t acc = {0, 0, 0, 0};
-    if (__any(ch >= 0))
-        mfma_rows<LD>(v.tab->TM + (int64_t)o * ld * ld, ld, mt * 16 + col, true,
-                      v.Mh + (int64_t)(ch >= 0 ? ch : 0) * ld, ch >= 0, kq, acc);
-    red[o][lane] = acc;
-    __syncthreads();
-    if (o != 0 || parent < 0) return;
-    double4_t sum = red[0][lane];
+    const bool any = __any(ch >= 0);
+    const auto X = gptr(v.Mh + (int64_t)(ch >= 0 ? ch : 0) * LD);
+    double b[KS];
 #pragma unroll
-    for (int w = 1; w < 8; ++w) sum += red[w][lane]; // fixed order
+    for (int st = 0; st < KS; ++st) b[st] = ch >= 0 ? X[4 * st + kq] : 0.0;
+    const auto T = gptr(v.tab->TM + (int64_t)o * LD * LD);
+    for (int mt = 0; mt < MT; ++mt) {
+        double4_t acc = {0, 0, 0, 0};
+        if (any) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) // f64 layout: lane l reg r -> row 4r + l/16
-        gptr(v.Mh)[(int64_t)parent * ld + mt * 16 + 4 * r + kq] = sum[r];
+            for (int s0 = 0; s0 < KS; s0 += 16) { // A operands in batches of 16 k-steps
+                double a[16];
+#pragma unroll
+                for (int st = 0; st < 16 && s0 + st < KS; ++st)
+                    a[st] = T[(int64_t)(4 * (s0 + st) + kq) * LD + mt * 16 + col];
+#pragma unroll
+                for (int st = 0; st < 16 && s0 + st < KS; ++st)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st], b[s0 + st], acc, 0, 0, 0);
+            }
+        }
+        red[o][lane] = acc;
+        __syncthreads();
+        if (o == 0 && parent >= 0) {
+            double4_t sum = red[0][lane];
+#pragma unroll
+            for (int w = 1; w < 8; ++w) sum += red[w][lane]; // fixed order
+#pragma unroll
+            for (int r = 0; r < 4; ++r) // f64 layout: lane l reg r -> row 4r + l/16
+                gptr(v.Mh)[(int64_t)parent * LD + mt * 16 + 4 * r + kq] = sum[r];
+        }
+        __syncthreads();
+    }
 }
 
 // Parents' FP32 operand copy (mixed M2L) and, for plans with W lists, their
@@ -347,7 +365,7 @@ __global__ __launch_bounds__(256) void k_parent_mh(const PlanView *V, Bases B, i
     if (box >= v.nboxes || (full != 2 && (v.nchild[box] == 0 || v.level[box] < 2))) return;
     const OrderTables &t = *v.tab;
     const auto Mh = gptr(v.Mh + (int64_t)box * v.ldmh);
-    if (v.mixed_m2l && full != 2)
+    if (v.Mhf && full != 2)
         for (int c = lane; c < v.ldmh; c += 64) {
             const int h = t.mposf[c];
             gptr(v.Mhf)[(int64_t)box * v.ldmh + c] = h >= 0 ? (float)Mh[t.hpos[h]] : 0.f;
@@ -966,13 +984,9 @@ void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (nblk(B)) DISPATCH_P(p, k_p2m, <<<nblk(B), 64, 0, s>>>(V, B));
 }
-void launch_p2m_transform(const PlanView *V, const Bases &B, hipStream_t s)
+void launch_p2m_fold(int p, const PlanView *V, const Bases &B, hipStream_t s)
 {
-    if (nblk(B)) k_p2m_transform<<<nblk(B), 64, 0, s>>>(V, B);
-}
-void launch_p2m_fold(const PlanView *V, const Bases &B, hipStream_t s)
-{
-    if (nblk(B)) k_p2m_fold<<<nblk(B), 64, 0, s>>>(V, B);
+    if (nblk(B)) DISPATCH_P(p, k_p2m_fold, <<<nblk(B), 256, 0, s>>>(V, B));
 }
 void launch_unfold(int p, const PlanView *V, const Bases &B, int leaves_only, hipStream_t s)
 {

@@ -60,6 +60,8 @@ ld dfact(int n) { ld r = 1; for (int i = n; i > 1; i -= 2) r *= i; return r; } /
 ld binom(int m, int a) { return fact(m) / (fact(a) * fact(m - a)); }
 ld ipow(ld x, int k) { ld r = 1; for (int i = 0; i < k; ++i) r *= x; return r; }
 
+} // namespace
+
 // Taylor coefficients a_g(x) of 1/|x| for |g| <= maxdeg and g_z <= maxz,
 // stored by mono_index (order maxdeg); entries with g_z > maxz left 0.
 void inv_r_taylor(const ld x[3], int maxdeg, int maxz, std::vector<ld> &a)
@@ -86,6 +88,8 @@ void inv_r_taylor(const ld x[3], int maxdeg, int maxz, std::vector<ld> &a)
         a[id] = -((2 * n - 1) * s1 + (n - 1) * s2) / (n * r2);
     }
 }
+
+namespace {
 
 // P2M: coefficients of the polynomials c_a(u) (degree |a|) over monomials u^g.
 // Returns C[a][g] (n x n, block diagonal by degree).
@@ -267,7 +271,7 @@ void build_tables(int p, Built &B)
         for (int ks = 0; ks < sym_ksteps(p); ++ks)
             for (int g = 0; g < 4; ++g) {
                 B.mpos[sym_pos(ks, g, 2)] = B.scol[4 * ks + g];
-                B.mposf[sym_pos(ks, g, p >= 12 ? 2 : 4)] = B.scol[4 * ks + g];
+                B.mposf[sym_pos(ks, g, 4)] = B.scol[4 * ks + g];
             }
     } else {
         for (int c = 0; c < nh; ++c) B.mpos[c] = B.mposf[c] = c;
@@ -610,10 +614,10 @@ int host_order_tables(int p, int which, std::vector<double> &out)
 extern "C" int fmm_order_table(int32_t order, int32_t which, double *out_host, int64_t capacity,
                                int64_t *count, int32_t *ld)
 {
-    if (order < 0 || order > fmm::kMaxOrder || which < 0 || which > 4 || !count || !ld) return FMM_EINVAL;
+    if (order < 0 || order > fmm::kMaxOrder || which < 0 || which > 8 || !count || !ld) return FMM_EINVAL;
     std::vector<double> t;
     try {
-        *ld = fmm::host_order_tables(order, which, t);
+        *ld = which <= 4 ? fmm::host_order_tables(order, which, t) : fmm::host_rotation_tables(order, which - 5, t);
     } catch (...) {
         return FMM_EUNSUPPORTED;
     }

@@ -34,7 +34,7 @@ class FmmError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("uniform_depth", ctypes.c_int32), ("max_depth", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("want_field", ctypes.c_int32),
-                ("root", ctypes.POINTER(ctypes.c_double))]
+                ("root", ctypes.POINTER(ctypes.c_double)), ("m2l_method", ctypes.c_int32)]
 
 
 class Allocator(ctypes.Structure):
@@ -91,9 +91,13 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _options(uniform_depth, max_depth, precision, want_field, root):
+M2L_METHODS = {"sign_class": 0, "rotation": 1}
+
+
+def _options(uniform_depth, max_depth, precision, want_field, root, m2l="sign_class"):
     o = Options()
     lib().fmm_default_options(ctypes.byref(o))
+    o.m2l_method = M2L_METHODS[m2l] if isinstance(m2l, str) else int(m2l)
     o.uniform_depth = uniform_depth
     o.max_depth = max_depth
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
@@ -109,9 +113,10 @@ class Plan:
     """Octree, interaction lists and workspace for one point set (fmm_plan)."""
 
     def __init__(self, xyz, order, leaf_size=64, uniform_depth=-1, max_depth=21,
-                 precision="fp64", want_field=True, root=None, stream=None, allocator=None):
+                 precision="fp64", want_field=True, root=None, stream=None, allocator=None, m2l="sign_class"):
         """allocator: an Allocator (C function pointers) for the plan's device
-        memory, or None for the library's own stream-ordered allocation."""
+        memory, or None for the library's own stream-ordered allocation.
+        m2l: "sign_class" (matrix cores) or "rotation" (Sec. 3.4, vector unit)."""
         import torch
         if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda):
             raise FmmError(FMM_EINVAL, "xyz must be a CUDA/HIP tensor")
@@ -121,7 +126,7 @@ class Plan:
         self.n = int(xyz.shape[0])
         self.order = int(order)
         self.device = xyz.device
-        o, keep = _options(uniform_depth, max_depth, precision, want_field, root)
+        o, keep = _options(uniform_depth, max_depth, precision, want_field, root, m2l)
         h = ctypes.c_void_p()
         _check(lib().fmm_plan(_ptr(xyz), self.n, self.order, int(leaf_size), ctypes.byref(o),
                               ctypes.byref(allocator) if allocator is not None else None,

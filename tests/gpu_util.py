@@ -25,6 +25,7 @@ def gpu_solve(x, q, p, **kw):
 
 def oracle_tree(x, **kw):
     import oracle
+    # (options of the GPU path only, such as the M2L method, do not change the tree)
     return oracle.Tree(x, root=kw.get("root"), uniform_depth=kw.get("uniform_depth", -1),
                        max_depth=kw.get("max_depth", 21), leaf_size=kw.get("leaf_size", 64))
 

@@ -323,3 +323,22 @@ def test_full_size_plummer_sampled_against_direct():
     for k in ("perm", "level", "morton", "first", "count", "V_off", "V_src", "W_src", "X_src", "U_src"):
         assert np.array_equal(g[k].astype(np.int64), o[k].astype(np.int64)), k
     pl.close()
+
+
+@pytest.mark.parametrize("name,gen,p,kw", [
+    ("config1_p6", lambda: inputs.uniform(2000, 0), 6, CFG1),
+    ("config1_p10", lambda: inputs.uniform(2000, 0), 10, CFG1),
+    ("plummer_6000_s32_p7", lambda: inputs.plummer(6000, 2), 7, dict(leaf_size=32)),
+    ("clusters_60_s6_p12", lambda: inputs.clusters(60, 5), 12, dict(leaf_size=6)),
+    ("clusters_60_s6_p14", lambda: inputs.clusters(60, 5), 14, dict(leaf_size=6)),
+    ("clusters_60_s6_p16", lambda: inputs.clusters(60, 5), 16, dict(leaf_size=6)),
+    ("uniform_600_d2_p13", lambda: inputs.uniform(600, 12), 13, dict(uniform_depth=2, root=[0, 0, 0, 1])),
+    ("gaussian_5000_s50_p15", lambda: inputs.gaussian(5000, 4), 15, dict(leaf_size=50)),
+])
+def test_rotation_m2l_matches_oracle(name, gen, p, kw):
+    """The axis-rotation M2L of Sec. 3.4 (rotate the multipole so the offset
+    lies on the axis, one-variable axial map, rotate back) gives the FP64
+    oracle's potentials and fields to 1e-12."""
+    x, q = gen()
+    say("rotation M2L", name)
+    _check_fp64(x, q, p, dict(kw, m2l="rotation"))

@@ -82,6 +82,20 @@ def test_adaptive_plummer_matches_oracle(p):
     pl.close()
 
 
+@pytest.mark.parametrize("p", [10, 14])
+def test_adaptive_plummer_rotation_m2l_matches_oracle(p):
+    """The rotation-based M2L (Sec. 3.4) on the Plummer tree with full V
+    lists: FP64 potentials and fields equal the oracle to 1e-12."""
+    x, q = inputs.plummer(30_000, 11)
+    kw = dict(leaf_size=64)
+    res = _oracle_fmm(("plummer3e4", p), x, q, p, kw, expansions=p == 10)
+    pl, phi, fld = gpu_solve(x, q, p, m2l="rotation", **kw)
+    pl.close()
+    e_phi, e_fld = rel_l2(phi, res[0]), rel_l2(fld, res[1])
+    say("  plummer 3e4 p=%d rotation M2L rel L2 vs oracle: phi %.3e field %.3e" % (p, e_phi, e_fld))
+    assert e_phi <= 1e-12 and e_fld <= 1e-12
+
+
 @pytest.mark.parametrize("p", [12, 14])
 def test_adaptive_plummer_mixed_error_against_oracle(p):
     """Mixed path at orders >= 12: FP32 P2P terms with compensated sums and

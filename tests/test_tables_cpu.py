@@ -203,8 +203,68 @@ def test_order_table_rejects_bad_arguments():
     cnt, ld = ctypes.c_int64(), ctypes.c_int32()
     L = fmm.lib()
     assert L.fmm_order_table(17, 0, None, 0, ctypes.byref(cnt), ctypes.byref(ld)) == fmm.FMM_EINVAL
-    assert L.fmm_order_table(4, 5, None, 0, ctypes.byref(cnt), ctypes.byref(ld)) == fmm.FMM_EINVAL
+    assert L.fmm_order_table(4, 9, None, 0, ctypes.byref(cnt), ctypes.byref(ld)) == fmm.FMM_EINVAL
     assert L.fmm_order_table(4, 1, None, 0, ctypes.byref(cnt), ctypes.byref(ld)) == fmm.FMM_OK
     buf = np.zeros(3)
     assert L.fmm_order_table(4, 1, ctypes.c_void_p(buf.ctypes.data), 3, ctypes.byref(cnt),
                              ctypes.byref(ld)) == fmm.FMM_EINVAL
+
+
+def folded_components(n):
+    return [(i, n - i, 0) for i in range(n, -1, -1)] + [(i, n - 1 - i, 1) for i in range(n - 1, -1, -1)]
+
+
+def mode_index(m, t):
+    return 0 if m == 0 else 2 * m - 1 + t
+
+
+@pytest.mark.parametrize("p", [3, 8, 12])
+def test_rotation_factors_reproduce_the_m2l_contraction(p):
+    """Rotation-based M2L (Sec. 3.4): for each of the 316 offsets k, the rotated
+    multipole map F, the axial map A (one block per azimuthal mode, the same
+    for cos and sin) and the local map B give back the folded M2L matrix,
+    T(k)[b][a] = d^(a+b)(1/|x|) at x = k, taken from the derivative tables:
+    T(s o k) = R_s B A F R_s with the factors stored for |k|."""
+    D = fmm.order_table(p, 0)
+    F = fmm.order_table(p, 5)
+    Bm = fmm.order_table(p, 6)
+    A = fmm.order_table(p, 7)
+    aidx = fmm.order_table(p, 8).ravel().astype(int)
+    ent = {e: i for i, e in enumerate(compact_index(p))}
+    offs = [0]
+    for n in range(p + 1):
+        offs.append(offs[-1] + (2 * n + 1) ** 2)
+    aoff = [0]
+    for m in range(p + 1):
+        aoff.append(aoff[-1] + (p + 1 - m) ** 2)
+    comps = [folded_components(n) for n in range(p + 1)]
+    worst = 0.0
+    for kx in range(-3, 4):
+        for ky in range(-3, 4):
+            for kz in range(-3, 4):
+                if max(abs(kx), abs(ky), abs(kz)) <= 1:
+                    continue
+                row = D[(kx + 3) * 49 + (ky + 3) * 7 + (kz + 3)]
+                cls = abs(kx) * 16 + abs(ky) * 4 + abs(kz)
+                sg = (1 if kx >= 0 else -1, 1 if ky >= 0 else -1, 1 if kz >= 0 else -1)
+                ar = A[aidx[cls]]
+                for n in range(p + 1):
+                    wn = 2 * n + 1
+                    Fn = F[cls, offs[n]:offs[n + 1]].reshape(wn, wn).T  # [mode][a]
+                    rn = np.array([sg[0] ** c[0] * sg[1] ** c[1] * sg[2] ** c[2] for c in comps[n]])
+                    for l in range(p + 1):
+                        wl = 2 * l + 1
+                        Bl = Bm[cls, offs[l]:offs[l + 1]].reshape(wl, wl).T  # [b][mode]
+                        rl = np.array([sg[0] ** c[0] * sg[1] ** c[1] * sg[2] ** c[2] for c in comps[l]])
+                        Aln = np.zeros((wl, wn))
+                        for m in range(min(l, n) + 1):
+                            w = p + 1 - m
+                            v = ar[aoff[m] + (n - m) * w + (l - m)]
+                            for t in range(2 if m else 1):
+                                Aln[mode_index(m, t), mode_index(m, t)] = v
+                        pred = (rl[:, None] * (Bl @ Aln @ Fn)) * rn[None, :]
+                        true = np.array([[row[ent[(b[0] + a[0], b[1] + a[1], b[2] + a[2])]] for a in comps[n]]
+                                         for b in comps[l]])
+                        err = np.abs(pred - true).max() / np.abs(true).max()
+                        worst = max(worst, err)
+    assert worst <= 1e-12, worst
