@@ -13,7 +13,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SRC = ["tpsa.c", "direct.c", "tree.c", "dafmm.c"]
+_SRC = ["tpsa.c", "direct.c", "tree.c", "dafmm.c", "soft.c"]
 
 
 def build(verbose=False):
@@ -56,6 +56,12 @@ def lib():
         L.oracle_tree_root.argtypes = [ctypes.c_void_p, dp]
         L.oracle_tree_export.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 16
         L.oracle_fmm.argtypes = [ctypes.c_void_p, i32, dp, dp, i32, dp, dp, dp, dp]
+        L.oracle_soft_taylor.argtypes = [i32, dp, d, dp]
+        L.oracle_direct_soft.argtypes = [i64, dp, dp, d, i64, P(i64), dp, dp]
+        L.oracle_soft_op.argtypes = [i32, i32, d, dp, dp, dp, dp]
+        L.oracle_soft_p2m.argtypes = [i32, i64, dp, dp, dp, dp]
+        L.oracle_soft_p2l.argtypes = [i32, d, i64, dp, dp, dp, dp]
+        L.oracle_fmm_soft.argtypes = [ctypes.c_void_p, i32, d, dp, dp, dp, dp, dp, dp]
         L.oracle_num_threads.restype = i32
         _lib = L
     return _lib
@@ -176,6 +182,62 @@ def direct(xyz, q, targets=None):
     return phi, field
 
 
+# ---- softened Coulomb kernel K(x) = 1/sqrt(|x|^2 + eps^2) (soft.c) ----
+def soft_taylor(p, x0, eps):
+    """Taylor coefficients of K(x0 + z) in z (DA order), by the DA algebra."""
+    out = np.zeros(ncoef(p))
+    x0 = _c(x0)
+    assert lib().oracle_soft_taylor(p, _p(x0), float(eps), _p(out)) == 0
+    return out
+
+
+def direct_soft(xyz, q, eps, targets=None):
+    xyz, q = _c(xyz), _c(q)
+    n = len(q)
+    if targets is None:
+        nt, tp = n, None
+    else:
+        targets = _c(targets, np.int64)
+        nt, tp = len(targets), targets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    phi = np.zeros(nt)
+    field = np.zeros((nt, 3))
+    assert lib().oracle_direct_soft(n, _p(xyz), _p(q), float(eps), nt, tp, _p(phi), _p(field)) == 0
+    return phi, field
+
+
+def _soft_op(op, p, eps, a3, b3, v):
+    a3, b3, v = _c(a3), _c(b3), _c(v)
+    out = np.zeros(ncoef(p))
+    assert lib().oracle_soft_op(op, p, float(eps), _p(a3), _p(b3), _p(v), _p(out)) == 0
+    return out
+
+
+def soft_m2m(p, child_center, parent_center, M):
+    return _soft_op(0, p, 0.0, child_center, parent_center, M)
+
+
+def soft_m2l(p, eps, src_center, tgt_center, M):
+    return _soft_op(1, p, eps, src_center, tgt_center, M)
+
+
+def soft_l2l(p, parent_center, child_center, L):
+    return _soft_op(2, p, 0.0, parent_center, child_center, L)
+
+
+def soft_p2m(p, xyz, q, center):
+    xyz, q, center = _c(xyz), _c(q), _c(center)
+    M = np.zeros(ncoef(p))
+    assert lib().oracle_soft_p2m(p, len(q), _p(xyz), _p(q), _p(center), _p(M)) == 0
+    return M
+
+
+def soft_p2l(p, eps, xyz, q, center):
+    xyz, q, center = _c(xyz), _c(q), _c(center)
+    L = np.zeros(ncoef(p))
+    assert lib().oracle_soft_p2l(p, float(eps), len(q), _p(xyz), _p(q), _p(center), _p(L)) == 0
+    return L
+
+
 class Tree:
     """Reference octree + CGR interaction lists (tree.c)."""
 
@@ -228,6 +290,24 @@ class Tree:
             L = np.zeros((self.nboxes, ncoef(p)))
         rc = lib().oracle_fmm(self._h, p, _p(self.xyz), _p(q), 1 if memo else 0, _p(phi), _p(field),
                               None if M is None else _p(M), None if L is None else _p(L))
+        assert rc == 0
+        if want_expansions:
+            return phi, field, M, L
+        return phi, field
+
+    def fmm_soft(self, p, q, eps, want_expansions=False):
+        """Softened-kernel FMM (soft.c): potentials and fields; M and L (box
+        order, physical units: moments and local Taylor coefficients)."""
+        q = _c(q)
+        n = len(q)
+        phi = np.zeros(n)
+        field = np.zeros((n, 3))
+        M = L = None
+        if want_expansions:
+            M = np.zeros((self.nboxes, ncoef(p)))
+            L = np.zeros((self.nboxes, ncoef(p)))
+        rc = lib().oracle_fmm_soft(self._h, p, float(eps), _p(self.xyz), _p(q), _p(phi), _p(field),
+                                   None if M is None else _p(M), None if L is None else _p(L))
         assert rc == 0
         if want_expansions:
             return phi, field, M, L

@@ -19,7 +19,9 @@
  *   - a reference octree and Carrier-Greengard-Rokhlin interaction lists
  *     (uniform full tree or adaptive tree with leaf size s, Sec. 1 and 3.5);
  *   - the FMM driver of Sec. 1 (upward pass, M2L/P2L, downward pass, L2P,
- *     M2P, P2P).
+ *     M2P, P2P);
+ *   - the same driver for a second non-oscillatory kernel, the softened
+ *     Coulomb potential (soft.c).
  *
  * Readings of passages that are garbled or silent are listed in the design
  * notes; the ones that change arithmetic are restated at the function.
@@ -115,6 +117,24 @@ void oracle_tree_export(const oracle_tree *t, int64_t *perm, int32_t *level,
  * (nboxes * n coefficients, box order of the tree) may be NULL. */
 int oracle_fmm(const oracle_tree *t, int p, const double *xyz, const double *q,
                int memo, double *phi, double *field, double *M, double *L);
+
+/* ---------------- the softened Coulomb kernel (soft.c) ---------------- */
+/* K(x) = 1/sqrt(|x|^2 + eps^2): the same recipe with Cartesian Taylor
+ * expansions (multipole moments, local Taylor coefficients in physical
+ * units) and the kernel's Taylor coefficients from the DA algebra. */
+int oracle_soft_taylor(int p, const double x0[3], double eps, double *out);
+int oracle_direct_soft(int64_t n, const double *xyz, const double *q, double eps, int64_t nt,
+                       const int64_t *targets, double *phi, double *field);
+/* op 0: M2M (a3 child centre, b3 parent centre); 1: M2L (a3 source centre,
+ * b3 target centre); 2: L2L (a3 parent centre, b3 child centre) */
+int oracle_soft_op(int op, int p, double eps, const double *a3, const double *b3, const double *in,
+                   double *out);
+int oracle_soft_p2m(int p, int64_t n, const double *xyz, const double *q, const double center[3],
+                    double *M);
+int oracle_soft_p2l(int p, double eps, int64_t n, const double *xyz, const double *q,
+                    const double center[3], double *L);
+int oracle_fmm_soft(const oracle_tree *t, int p, double eps, const double *xyz, const double *q,
+                    double *phi, double *field, double *M, double *L);
 
 /* thread count used by OpenMP regions */
 int oracle_num_threads(void);
