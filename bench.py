@@ -26,10 +26,11 @@ targets (the exact reference at any accuracy), timed on the host cores.
 
 The same line carries a short served run (continuous batching, Poisson
 arrivals at half the saturated rate) with p50/p99 latency and the achieved
-sigma per requested-accuracy bucket, and the uniform 1e6-point workload at
-p = 8 (uniform1m).
+sigma per requested-accuracy bucket, the uniform 1e6-point workload at
+p = 8 (uniform1m), and the same points under the second kernel, the softened
+Coulomb potential 1/sqrt(r^2 + eps^2) with eps = 1e-3 (softened1m).
 
-Other workloads (--workload): uniform1m alone, batch256 (256 independent
+Other workloads (--workload): uniform1m or softened1m alone, batch256 (256 independent
 problems, one fmm_evaluate_batch), serve (the served stream at four arrival
 rates), sweep (leaf size x order x N on Gaussian points), calib (a plain
 256 MiB device copy, for the HBM byte-counter calibration).
@@ -408,6 +409,50 @@ def bench_uniform(args, with_cpu=True):
     return out
 
 
+# ---------------------------------------------------------------- softened kernel
+def bench_softened(args):
+    """The second kernel, 1/sqrt(r^2 + eps^2): 1e6 uniform points in [0,1)^3
+    (seed 1), uniform depth 5 on [0,1]^3, p = 8, eps = 1e-3 (a tenth of the
+    mean spacing), FP64.  Its M2L is the full contraction (the kernel is not
+    harmonic): 2 n_p^2 flops per V pair."""
+    import torch
+    import oracle
+    from paper_2508_02626_amd import fmm, inputs
+    n, depth, p, eps = 1_000_000, 5, 8, 1e-3
+    xh, qh = inputs.uniform(n, 1)
+    x = torch.tensor(xh, device="cuda:0")
+    q = torch.tensor(qh, device="cuda:0")
+    phi = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    fld = torch.empty(n, 3, dtype=torch.float64, device="cuda:0")
+    idx = sample_targets(n, 2000)
+    dphi, dfld = oracle.direct_soft(xh, qh, eps, idx)
+    mk = lambda: fmm.Plan(x, p, uniform_depth=depth, root=[0, 0, 0, 1], kernel="softened", softening=eps)
+    step_s = timed_steps(mk, q, phi, fld, args.steps, args.warmup)
+    pl = mk()
+    eval_s, stages = timed_evaluations(pl, q, phi, fld, args.steps)
+    tree = pl.export_tree()
+    pl.close()
+    ph, fl = phi.cpu().numpy(), fld.cpu().numpy()
+    sig, sig_f = rel(ph[idx], dphi), rel(fl[idx], dfld)
+    log("bench softened1m: step %.3f ms eval %.3f ms sigma %.3e" % (1e3 * step_s, 1e3 * eval_s, sig))
+    nv = int(tree["V_off"][-1])
+    nc = (p + 1) * (p + 2) * (p + 3) // 6
+    flops = 2.0 * nc * nc * nv
+    m2l_ms = stages["m2l"]
+    achieved = flops / (m2l_ms * 1e-3) / 1e12
+    return {"value": n / step_s, "ms_per_step": 1e3 * step_s, "dtype": "f64",
+            "config": {"workload": "softened Coulomb kernel 1/sqrt(r^2+eps^2), eps=1e-3: N=%d uniform in [0,1)^3 "
+                                   "(seed 1), q~U(-1,1), uniform octree depth 5 on [0,1]^3, order p=8, "
+                                   "potential+field" % n, "n": n, "order": p, "softening": eps},
+            "accuracy": {"sigma_phi_vs_direct": sig, "sigma_field_vs_direct": sig_f, "targets_sampled": len(idx)},
+            "eval_only": {"value": n / eval_s, "ms": 1e3 * eval_s},
+            "stage_ms": stages,
+            "roofline": {"kernel": "k_m2l_soft<8>", "bound": "mfma", "achieved": achieved,
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                         "flops_per_launch": flops, "ms_per_launch": m2l_ms, "v_pairs": nv,
+                         "work": "full Cartesian contraction, 2 n_p^2 per V pair"}}
+
+
 # ---------------------------------------------------------------- served
 def served_run(nreq, fracs, sigma_per_bucket=6, sigma_targets=256):
     """Poisson stream through the continuous-batching server: N log-uniform in
@@ -667,7 +712,7 @@ def main():
     ap.add_argument("--order", type=int, default=0, help="plummer4m: fixed order instead of the scan")
     ap.add_argument("--sigma-targets", type=int, default=4096)
     ap.add_argument("--workload", default="plummer4m",
-                    choices=["plummer4m", "uniform1m", "batch256", "serve", "sweep", "calib"])
+                    choices=["plummer4m", "uniform1m", "softened1m", "batch256", "serve", "sweep", "calib"])
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--serve-requests", type=int, default=120, help="requests of the served run in the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -675,6 +720,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-uniform", action="store_true")
     ap.add_argument("--no-rotation", action="store_true")
+    ap.add_argument("--no-softened", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library runs a solve on a single GPU "
@@ -698,6 +744,11 @@ def main():
                              "config": s["config"] + "; arrivals at 0.5 x the saturated rate"}
         if not args.no_uniform:
             out["uniform1m"] = bench_uniform(args, with_cpu=not args.no_cpu_baseline)
+        if not args.no_softened:
+            out["softened1m"] = bench_softened(args)
+    elif args.workload == "softened1m":
+        out = base_record(args)
+        out.update(bench_softened(args))
     elif args.workload == "uniform1m":
         out = base_record(args)
         out.update(bench_uniform(args, with_cpu=not args.no_cpu_baseline))

@@ -87,12 +87,27 @@ typedef struct {
                               the axis-rotation form of Sec. 3.4 on the vector
                               unit (rotate, one-variable axial map, rotate
                               back; FP64 whatever the precision)              */
+    int32_t kernel;        /* FMM_KERNEL_COULOMB (default): phi_i = sum q_j /
+                              |x_i - x_j|.  FMM_KERNEL_SOFTENED: the softened
+                              (Plummer) kernel 1/sqrt(|x|^2 + eps^2), a second
+                              non-oscillatory kernel (the DA formulation is not
+                              tied to 1/r: closing remark of Sec. 3.4); every
+                              j != i contributes, also at distance 0 when
+                              eps > 0.  Softened plans use full Cartesian
+                              Taylor expansions (the kernel is not harmonic, so
+                              there is no fold), need a uniform tree
+                              (uniform_depth >= 0), FMM_FP64, order <= 10 and
+                              the sign-class M2L method, and are evaluated by
+                              fmm_evaluate only                               */
+    double softening;      /* eps >= 0, in the units of the coordinates
+                              (softened kernel only)                          */
 } fmm_options_t;
 
 enum { FMM_M2L_SIGN_CLASS = 0, FMM_M2L_ROTATION = 1 };
+enum { FMM_KERNEL_COULOMB = 0, FMM_KERNEL_SOFTENED = 1 };
 
 /* Default options: adaptive, max_depth 21, FP64, field on, bounding cube,
- * sign-class M2L. */
+ * sign-class M2L, Coulomb kernel. */
 void fmm_default_options(fmm_options_t *opt);
 
 /*
@@ -147,6 +162,8 @@ int fmm_plan_batch(int32_t count, const double *const *xyz_dev, const int64_t *n
  * upward and downward passes; M2P (W lists) follows the second part there.
  * Deterministic: the
  * same plan and charges give bitwise identical results on every call.
+ * Softened-kernel plans run P2P on the plan's stream in one piece next to the
+ * whole far-field pipeline (P2M, M2M, M2L, L2L on full expansions).
  */
 int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_dev, double *field_dev,
                  hipStream_t stream);
@@ -156,7 +173,8 @@ int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_dev, double *
  * of all of them into shared launches (one launch per pipeline stage instead
  * of one per stage and plan).  Arrays of length count; field[i] may be NULL.
  * Plans may differ in n, order and precision.  Each result is bitwise equal to
- * fmm_evaluate on the same plan alone.
+ * fmm_evaluate on the same plan alone.  Softened-kernel plans are refused
+ * (FMM_EINVAL): they have their own pipeline, run by fmm_evaluate.
  */
 int fmm_evaluate_batch(fmm_plan_t const *plans, const double *const *q_dev,
                        double *const *phi_dev, double *const *field_dev, int32_t count,
@@ -237,6 +255,10 @@ int fmm_plan_export_tree(fmm_plan_t plan, hipStream_t stream, double *root_host,
  * the evaluation's M2M produced (levels 0 and 1, which the evaluation does
  * not need, are completed by the same M2M first); L of boxes at level >= 2
  * are unfolded from the harmonic local expansions after the L2L (zero above).
+ * Softened-kernel plans hold Cartesian Taylor expansions instead: M the
+ * moments M_a = sum_i q_i (c - x_i)^a / a! (phi = sum_a M_a d^a K(x - c)), L
+ * the Taylor coefficients of the local expansion in x - c, in the same
+ * monomial order (levels 0 and 1 of M completed as above, L zero there).
  */
 int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, double *M_host,
                                double *L_host);

@@ -49,12 +49,15 @@ void oracle_tree_center(const oracle_tree *t, int32_t b, double c[3]);
 double oracle_tree_width(const oracle_tree *t, int l);
 void oracle_tree_coords(const oracle_tree *t, int32_t b, int64_t g[3]);
 
-static double fact(int n)
-{
-    double r = 1.0;
-    for (int i = 2; i <= n; ++i) r *= i;
-    return r;
-}
+/* n! for n <= 22 (exact in double) */
+static const double FACT[23] = {
+    1.0, 1.0, 2.0, 6.0,
+    24.0, 120.0, 720.0, 5040.0,
+    40320.0, 362880.0, 3628800.0, 39916800.0,
+    479001600.0, 6227020800.0, 87178291200.0, 1307674368000.0,
+    20922789888000.0, 355687428096000.0, 6402373705728000.0, 121645100408832000.0,
+    2432902008176640000.0, 51090942171709440000.0, 1124000727777607680000.0};
+static double fact(int n) { return FACT[n]; }
 static double mfact(const int e[3]) { return fact(e[0]) * fact(e[1]) * fact(e[2]); }
 static double binom(int n, int k) { return fact(n) / (fact(k) * fact(n - k)); }
 static double ipow(double x, int n)
@@ -120,17 +123,35 @@ static void s_m2m(const da_ctx *c, const double t[3], const double *Mc, double *
     }
 }
 
-/* T: coefficients of order 2p (context c2) */
-static void s_m2l(const da_ctx *c, const double *T, const double *M, double *L)
+/* The M2L's fixed structure: for output b and input a, the position of
+ * a + b among the order-2p coefficients and the factor (a+b)! / b!. */
+typedef struct { int *ix; double *cf; } m2l_index;
+static void m2l_index_init(const da_ctx *c, m2l_index *m)
 {
+    const size_t n = (size_t)c->n;
+    m->ix = malloc(sizeof(int) * n * n);
+    m->cf = malloc(sizeof(double) * n * n);
     for (int b = 0; b < c->n; ++b) {
         const int *eb = c->e[b];
-        double s = 0.0;
         for (int a = 0; a < c->n; ++a) {
             const int *ea = c->e[a];
             const int g[3] = {ea[0] + eb[0], ea[1] + eb[1], ea[2] + eb[2]};
-            s += M[a] * mfact(g) / mfact(eb) * T[da_index(g[0], g[1], g[2])];
+            m->ix[(size_t)b * n + a] = da_index(g[0], g[1], g[2]);
+            m->cf[(size_t)b * n + a] = mfact(g) / mfact(eb);
         }
+    }
+}
+static void m2l_index_free(m2l_index *m) { free(m->ix); free(m->cf); }
+
+/* L_b += sum_a M_a (a+b)!/b! T_(a+b); T: coefficients of order 2p */
+static void s_m2l(const da_ctx *c, const m2l_index *mi, const double *T, const double *M, double *L)
+{
+    const size_t n = (size_t)c->n;
+    for (int b = 0; b < c->n; ++b) {
+        const int *ix = mi->ix + (size_t)b * n;
+        const double *cf = mi->cf + (size_t)b * n;
+        double s = 0.0;
+        for (int a = 0; a < c->n; ++a) s += M[a] * cf[a] * T[ix[a]];
         L[b] += s;
     }
 }
@@ -224,8 +245,11 @@ int oracle_soft_op(int op, int p, double eps, const double *a3, const double *b3
         const double k[3] = {b3[0] - a3[0], b3[1] - a3[1], b3[2] - a3[2]};
         double *T = calloc((size_t)c2.n, sizeof(double));
         if (k[0] * k[0] + k[1] * k[1] + k[2] * k[2] + eps * eps > 0.0) {
+            m2l_index mi;
+            m2l_index_init(&c, &mi);
             soft_taylor_ctx(&c2, k, eps, T);
-            s_m2l(&c, T, in, out);
+            s_m2l(&c, &mi, T, in, out);
+            m2l_index_free(&mi);
         } else rc = -1;
         free(T);
     } else if (op == 2) { /* L2L: a3 parent centre, b3 child centre */
@@ -323,6 +347,8 @@ int oracle_fmm_soft(const oracle_tree *t, int p, double eps, const double *xyz, 
      * scale with the boxes), so they are kept per level and offset. */
     double *T343 = malloc(sizeof(double) * 343 * (size_t)c2.n);
     int have[343];
+    m2l_index mi;
+    m2l_index_init(&c, &mi);
     for (int l = 2; l <= depth; ++l) {
         const double h = oracle_tree_width(t, l);
         memset(have, 0, sizeof(have));
@@ -347,7 +373,7 @@ int oracle_fmm_soft(const oracle_tree *t, int p, double eps, const double *xyz, 
                 oracle_tree_coords(t, (int32_t)b, gb);
                 oracle_tree_coords(t, Vs[e], gs);
                 const int k = (int)((gb[0] - gs[0] + 3) * 49 + (gb[1] - gs[1] + 3) * 7 + (gb[2] - gs[2] + 3));
-                s_m2l(&c, T343 + (size_t)k * c2.n, M + (int64_t)Vs[e] * n, L + b * n);
+                s_m2l(&c, &mi, T343 + (size_t)k * c2.n, M + (int64_t)Vs[e] * n, L + b * n);
             }
             for (int64_t e = Xo[b]; e < Xo[b + 1]; ++e) {
                 const int32_t s = Xs[e];
@@ -370,6 +396,7 @@ int oracle_fmm_soft(const oracle_tree *t, int p, double eps, const double *xyz, 
         }
     }
     free(T343);
+    m2l_index_free(&mi);
 
     /* evaluation at the leaves: L2P + M2P (W list) + P2P (U list) */
     double *phs = calloc((size_t)(N ? N : 1), sizeof(double)), *fs = calloc(3 * (size_t)(N ? N : 1), sizeof(double));

@@ -7,7 +7,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["api.hip", "tables.hip", "sort.hip", "tree_kernels.hip", "m2l_tiles.hip", "ops.hip", "m2l.hip", "noalloc.hip", "rotation.hip"]
+SOURCES = ["api.hip", "tables.hip", "sort.hip", "tree_kernels.hip", "m2l_tiles.hip", "ops.hip", "m2l.hip", "noalloc.hip", "rotation.hip", "soft.hip"]
 LIB = os.path.join(HERE, "libfmm_mi355x.so")
 OBJDIR = os.path.join(HERE, "_build")
 

@@ -14,6 +14,7 @@
 
 #include "common.h"
 #include "ops.h"
+#include "soft.h"
 #include "sort.h"
 #include "tables.h"
 #include "tree_kernels.h"
@@ -208,6 +209,8 @@ struct fmm_plan_s {
     int p = 0, nc = 0, nh = 0, ldm = 0, ldh = 0, ldmh = 0, D = 0, depth = 0, leaf_size = 0;
     int uniform = 0, precision = 0, mixed_m2l = 0, m2l_rot = 0;
     const RotTables *rot = nullptr; // rotation-based M2L factors (device)
+    int kernel = FMM_KERNEL_COULOMB;  // softened kernel: full expansions, tables per level
+    double eps = 0.0;
     int n = 0, nboxes = 0, nleaves = 0, nxtgt = 0, nslots = 0, m2l_parts = 1;
     int64_t nlist[4] = {0, 0, 0, 0};
     std::vector<int> lvl_begin;       // boxes per level (host)
@@ -344,6 +347,8 @@ extern "C" void fmm_default_options(fmm_options_t *opt)
     opt->want_field = 1;
     opt->root = nullptr;
     opt->m2l_method = FMM_M2L_SIGN_CLASS;
+    opt->kernel = FMM_KERNEL_COULOMB;
+    opt->softening = 0.0;
 }
 
 extern "C" const char *fmm_last_error(void) { return g_err.c_str(); }
@@ -422,9 +427,12 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         P->nboxes = (int)tot;
     }
     const int nb = P->nboxes;
-    P->m2l_parts = P->m2l_rot ? 1 : sym_m2l_parts(P->p);
+    const bool soft = P->kernel == FMM_KERNEL_SOFTENED;
+    // softened kernel (uniform trees): derivative tables for levels 2..D
+    const int soft_nlev = soft ? std::max(P->D - 1, 0) : 0;
+    P->m2l_parts = (P->m2l_rot || soft) ? 1 : sym_m2l_parts(P->p);
     // the sign-class M2L addresses the folded multipoles with 32-bit byte offsets
-    if (m2l_sym(P->p) && (unsigned long long)(nb + 1) * (unsigned long long)P->ldmh * 8ULL >= (1ULL << 32))
+    if (!soft && m2l_sym(P->p) && (unsigned long long)(nb + 1) * (unsigned long long)P->ldmh * 8ULL >= (1ULL << 32))
         return fail(FMM_EUNSUPPORTED, "too many boxes for this order (folded multipoles reach 4 GiB)");
     // ---- phase B: boxes, list counts, work lists (sizes known from nb)
     {
@@ -434,10 +442,15 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         for (int w = 0; w < 4; ++w) o.add<int64_t>(nb + 1);
         o.add<int32_t>((size_t)nb * kVSlots).add<int32_t>(nb).add<int32_t>(nb).add<int32_t>(nb)
          .add<int32_t>(kMaxDepth + 2).add<PlanView>(1)
-         .add<double>((size_t)nb * P->ldm).add<double>((size_t)nb * P->ldm)
-         .add<double>((size_t)(nb + 1) * P->ldmh).add<double>((size_t)nb * P->ldh);
-        if (P->m2l_parts > 1) o.add<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh);
-        if (P->mixed_m2l && m2l_f32_operands(P->p)) o.add<float>((size_t)(nb + 1) * P->ldmh);
+         .add<double>((size_t)nb * P->ldm).add<double>((size_t)nb * P->ldm);
+        if (soft) {
+            o.add<double>((size_t)soft_nlev * 343 * soft_table_ldc(P->p)).add<int>(soft_table_ldc(P->p))
+             .add<double>(P->ldm);
+        } else {
+            o.add<double>((size_t)(nb + 1) * P->ldmh).add<double>((size_t)nb * P->ldh);
+            if (P->m2l_parts > 1) o.add<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh);
+            if (P->mixed_m2l && m2l_f32_operands(P->p)) o.add<float>((size_t)(nb + 1) * P->ldmh);
+        }
         if (!P->reserve(true, o.total)) return fail(FMM_ENOMEM, "device allocation failed (boxes)");
         Sizer t;
         if (adaptive)
@@ -464,13 +477,25 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     P->view_dev = P->own<PlanView>(1);
     double *M = P->own<double>((size_t)nb * P->ldm), *L = P->own<double>((size_t)nb * P->ldm);
     // folded multipoles: one row per box and an all-zero row after them
-    double *Mh = P->own<double>((size_t)(nb + 1) * P->ldmh), *Lh = P->own<double>((size_t)nb * P->ldh);
+    // (Coulomb kernel; the softened kernel has its tables instead)
+    double *Mh = soft ? nullptr : P->own<double>((size_t)(nb + 1) * P->ldmh);
+    double *Lh = soft ? nullptr : P->own<double>((size_t)nb * P->ldh);
     float *Mhf = P->mixed_m2l && m2l_f32_operands(P->p) ? P->own<float>((size_t)(nb + 1) * P->ldmh) : nullptr;
     // partial sums of the M2L class parts after the first
     double *Lh2 = P->m2l_parts > 1 ? P->own<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh) : nullptr;
     if (P->m2l_parts > 1) NOMEM(Lh2);
+    double *Dsoft = nullptr, *zrow = nullptr;
+    int *soft_map = nullptr;
+    if (soft) {
+        Dsoft = P->own<double>((size_t)std::max(soft_nlev, 1) * 343 * soft_table_ldc(P->p));
+        soft_map = P->own<int>(soft_table_ldc(P->p));
+        zrow = P->own<double>(P->ldm);
+        NOMEM(Dsoft); NOMEM(soft_map); NOMEM(zrow);
+    } else {
+        NOMEM(Mh); NOMEM(Lh);
+    }
     NOMEM(vslot); NOMEM(leaves); NOMEM(nonleaf); NOMEM(xtgt); NOMEM(lnl_off); NOMEM(P->view_dev);
-    NOMEM(M); NOMEM(L); NOMEM(Mh); NOMEM(Lh);
+    NOMEM(M); NOMEM(L);
     if (P->mixed_m2l && m2l_f32_operands(P->p)) NOMEM(Mhf);
     if (adaptive) {
         uint64_t *elevel = P->temp<uint64_t>(nb), *etk = P->temp<uint64_t>(nb), *emorton = P->temp<uint64_t>(nb);
@@ -594,8 +619,15 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     v.lvl_nonleaf = nonleaf; v.lvl_nonleaf_off = lnl_off; v.tab = P->tab; v.rot = P->rot;
     // row `nb` of the folded multipoles is the all-zero operand of absent M2L
     // sources; it is never written by an evaluation
-    launch_zero(Mh + (size_t)nb * P->ldmh, P->ldmh, s);
+    if (Mh) launch_zero(Mh + (size_t)nb * P->ldmh, P->ldmh, s);
     if (Mhf) launch_zero_f32(Mhf + (size_t)nb * P->ldmh, P->ldmh, s);
+    v.kernel = P->kernel;
+    v.eps2 = P->eps * P->eps;
+    v.Dsoft = Dsoft; v.soft_map = soft_map; v.zrow = zrow;
+    if (soft) {
+        launch_zero(zrow, P->ldm, s);
+        launch_soft_tables(P->p, soft_nlev, Dsoft, soft_map, P->root[3], P->eps, s);
+    }
     v.qs = qs; v.M = M; v.Mh = Mh; v.Lh = Lh; v.Lh2 = Lh2; v.m2l_parts = P->m2l_parts; v.L = L; v.Mhf = Mhf; v.phi_near = pf; v.fld_near = ff;
     HIPCHK(hipMemcpyAsync(P->view_dev, &v, sizeof(PlanView), hipMemcpyHostToDevice, s));
     HIPCHK(hipGetLastError());
@@ -616,6 +648,14 @@ int check_options(const fmm_options_t &o, int order, int leaf_size)
     if (o.precision & ~FMM_MIXED) return fail(FMM_EINVAL, "bad precision");
     if (o.m2l_method != FMM_M2L_SIGN_CLASS && o.m2l_method != FMM_M2L_ROTATION)
         return fail(FMM_EINVAL, "bad m2l_method");
+    if (o.kernel != FMM_KERNEL_COULOMB && o.kernel != FMM_KERNEL_SOFTENED) return fail(FMM_EINVAL, "bad kernel");
+    if (o.kernel == FMM_KERNEL_SOFTENED) {
+        if (!std::isfinite(o.softening) || o.softening < 0) return fail(FMM_EINVAL, "softening must be finite and >= 0");
+        if (o.uniform_depth < 0) return fail(FMM_EINVAL, "the softened kernel needs a uniform tree (uniform_depth >= 0)");
+        if (o.precision != FMM_FP64) return fail(FMM_EINVAL, "the softened kernel runs in FMM_FP64 only");
+        if (o.m2l_method != FMM_M2L_SIGN_CLASS) return fail(FMM_EINVAL, "the softened kernel has one M2L method");
+        if (order > kSoftMaxOrder) return fail(FMM_EINVAL, "the softened kernel supports orders 0..10");
+    }
     if (o.uniform_depth < 0 && leaf_size < 1) return fail(FMM_EINVAL, "leaf_size must be >= 1");
     if (order < 0 || order > kMaxOrder) return fail(FMM_EINVAL, "order must be 0..16");
     if (o.root) {
@@ -669,6 +709,8 @@ extern "C" int fmm_plan(const double *xyz_dev, int64_t n, int32_t order, int32_t
     P->leaf_size = leaf_size;
     P->precision = o.precision;
     P->m2l_rot = o.m2l_method == FMM_M2L_ROTATION;
+    P->kernel = o.kernel;
+    P->eps = o.kernel == FMM_KERNEL_SOFTENED ? o.softening : 0.0;
     P->mixed_m2l = (!P->m2l_rot && (o.precision & FMM_M2L_F32) && (order <= 8 || order >= 12)) ? 1 : 0;
     if (P->m2l_rot) {
         P->rot = get_rotation_tables(order, err);
@@ -989,6 +1031,69 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     return 0;
 }
 
+// The softened kernel's pipeline (uniform trees, one plan): P2P on the side
+// stream next to the whole far field; P2M raw moments -> moments, M2M by
+// one-axis shifts, M2L on the full components with the level's tables, L2L by
+// one-axis shifts, then L2P with the near field.
+int run_soft(fmm_plan_s *P, hipStream_t s)
+{
+    const PlanView *V = P->view_dev;
+    StageTimer T(P, s);
+    auto one = [](int nblocks) {
+        Bases B{};
+        B.n = 1;
+        B.b[0] = 0;
+        B.b[1] = nblocks;
+        return B;
+    };
+    const StagePlan sp = stage_blocks(P);
+    T.begin(0);
+    launch_permute_q(V, one(sp.permute), s);
+    T.end();
+    if (P->ensure_side()) return fail(FMM_EDEVICE, "side stream creation failed");
+    StageTimer T2(P, P->side);
+    HIPCHK(hipEventRecord(P->ev_fork, s));
+    HIPCHK(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+    T2.begin(9);
+    launch_p2p(2, 0, V, one(sp.p2p[0]), P->side);
+    launch_p2p(2, 1, V, one(sp.p2p[1]), P->side);
+    T2.end();
+    HIPCHK(hipEventRecord(P->ev_join, P->side));
+    const int depth = P->depth;
+    auto lb = [&](int l) { return P->lvl_begin[l]; };
+    T.begin(1);
+    launch_p2m(P->p, V, one(sp.p2m), s);
+    launch_soft_p2m(P->p, V, P->nleaves, P->ldm, s);
+    T.end();
+    T.begin(2);
+    for (int l = depth - 1; l >= 2; --l) launch_soft_m2m(P->p, V, lb(l), lb(l + 1) - lb(l), s);
+    T.end();
+    T.begin(4);
+    {
+        SoftGrid G{};
+        G.nlev = std::max(depth - 1, 0);
+        for (int i = 0; i < G.nlev; ++i) {
+            const int l = i + 2;
+            const long long cells = 1ll << (3 * (l - 1));
+            G.tiles[i] = (int)((cells + 63) / 64);
+            G.start[i] = G.nblocks;
+            G.lvl_first[i] = lb(l);
+            G.nblocks += 8 * G.tiles[i];
+        }
+        launch_m2l_soft(P->p, V, G, s);
+    }
+    T.end();
+    T.begin(7);
+    for (int l = 2; l < depth; ++l) launch_soft_l2l(P->p, V, lb(l + 1), lb(l + 2) - lb(l + 1), s);
+    T.end();
+    HIPCHK(hipStreamWaitEvent(s, P->ev_join, 0));
+    T.begin(8);
+    launch_far(P->p, V, one(sp.far), s);
+    T.end();
+    HIPCHK(hipGetLastError());
+    return 0;
+}
+
 } // namespace
 
 extern "C" int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_dev, double *field_dev,
@@ -1004,7 +1109,7 @@ extern "C" int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_de
     v.fld_out = field_dev;
     HIPCHK(hipMemcpyAsync(P->view_dev, &v, sizeof(PlanView), hipMemcpyHostToDevice, stream));
     fmm_plan_s *arr[1] = {P};
-    int rc = run_pipeline(arr, 1, P->view_dev, stream);
+    int rc = P->kernel == FMM_KERNEL_SOFTENED ? run_soft(P, stream) : run_pipeline(arr, 1, P->view_dev, stream);
     if (rc) return rc;
     if (P->note_use(stream)) return fail(FMM_EDEVICE, "event record failed");
     return FMM_OK;
@@ -1024,6 +1129,9 @@ int batch_prepare(fmm_plan_t const *plans, const double *const *q_dev, double *c
         return fail(FMM_EINVAL, "bad batch arguments");
     for (int i = 0; i < count; ++i)
         if (!plans[i] || !q_dev[i] || !phi_dev[i]) return fail(FMM_EINVAL, "null entry in batch");
+    for (int i = 0; i < count; ++i)
+        if (plans[i]->kernel != FMM_KERNEL_COULOMB)
+            return fail(FMM_EINVAL, "batched evaluation runs Coulomb-kernel plans only (softened plans: fmm_evaluate)");
     for (int i = 0; i < count; ++i)
         if (stream != plans[i]->stream) HIPCHK(hipStreamWaitEvent(stream, plans[i]->built, 0));
     for (int i = 0; i < count; ++i) idx[i] = i;
@@ -1122,6 +1230,8 @@ extern "C" int fmm_plan_estimate(int64_t n, int32_t order, int32_t leaf_size, co
     double per_box = 8 * (2 * ldm + parts * ldh + ldmh) + 4 * ldmh + 4 * 200 + 64; // expansions, slots, lists
     double per_particle = 8 * 3 + 4 + 8 * 5 + 8 * 2;
     double total = boxes * per_box + n * per_particle + 8 * 27 * boxes;
+    if (o.kernel == FMM_KERNEL_SOFTENED && o.uniform_depth >= 2 && order <= kSoftMaxOrder)
+        total += 8.0 * (o.uniform_depth - 1) * 343 * soft_table_ldc(order); // derivative tables per level
     *bytes = (size_t)(total * 1.25);
     return FMM_OK;
 }
@@ -1227,31 +1337,42 @@ extern "C" int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, d
         // per-degree harmonic reconstruction, which is exact for harmonic
         // expansions: the exported multipoles are the evaluation's own P2M and
         // M2M results, not a separate computation.
+        const bool soft = P->kernel == FMM_KERNEL_SOFTENED;
         Bases B{};
         B.n = 1;
         B.b[0] = 0;
         for (int l = std::min(P->depth - 1, 1); l >= 0; --l) {
+            if (soft) {
+                launch_soft_m2m(P->p, P->view_dev, P->lvl_begin[l], P->lvl_begin[l + 1] - P->lvl_begin[l], stream);
+                continue;
+            }
             B.b[1] = nonleaf_groups(P, l);
             launch_m2mh(P->p, P->view_dev, B, l, stream);
         }
-        B.b[1] = (int)ceil_div(P->nboxes, 4);
-        launch_parent_mh(P->view_dev, B, 2, stream); // leaves too: from the folded P2M
+        if (!soft) {
+            B.b[1] = (int)ceil_div(P->nboxes, 4);
+            launch_parent_mh(P->view_dev, B, 2, stream); // leaves too: from the folded P2M
+        }
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(stream));
         HIPCHK(hipMemcpy(buf.data(), P->view.M, 8ull * nb * ldm, hipMemcpyDeviceToHost));
+        // Coulomb: Mhat_a = w_|a| M_a / h^|a|; softened: moments Mhat_a = M_a / h^|a|
         for (int b = 0; b < nb; ++b) {
             double h = P->root[3] / std::ldexp(1.0, lev[b]);
             for (int a = 0; a < nc; ++a)
-                M_host[(size_t)b * nc + a] = buf[(size_t)b * ldm + a] * inv_w[deg[a]] * std::pow(h, deg[a]);
+                M_host[(size_t)b * nc + a] = buf[(size_t)b * ldm + a] * (soft ? 1.0 : inv_w[deg[a]]) * std::pow(h, deg[a]);
         }
     }
     if (L_host) {
-        // the evaluation unfolds leaves only: complete the full expansions of every box
-        Bases B{};
-        B.n = 1;
-        B.b[0] = 0;
-        B.b[1] = stage_blocks(P).unfold;
-        launch_unfold(P->p, P->view_dev, B, 0, stream);
+        // the evaluation unfolds leaves only: complete the full expansions of
+        // every box (softened kernel: L holds the full expansions already)
+        if (P->kernel == FMM_KERNEL_COULOMB) {
+            Bases B{};
+            B.n = 1;
+            B.b[0] = 0;
+            B.b[1] = stage_blocks(P).unfold;
+            launch_unfold(P->p, P->view_dev, B, 0, stream);
+        }
         HIPCHK(hipStreamSynchronize(stream));
         HIPCHK(hipMemcpy(buf.data(), P->view.L, 8ull * nb * ldm, hipMemcpyDeviceToHost));
         for (int b = 0; b < nb; ++b) {

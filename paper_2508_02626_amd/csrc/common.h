@@ -322,6 +322,13 @@ struct PlanView {
                                         // sums of the M2L class parts after the first
     int m2l_parts;                      // blocks per M2L tile (1 below the sign-class orders)
     float *Mhf;                         // FP32 folded multipoles (mixed M2L)
+    // softened kernel 1/sqrt(|x|^2 + eps^2) (kernel == 1): full Cartesian
+    // expansions in M and L, derivative tables per level
+    int kernel;
+    double eps2;                        // eps^2 (P2P)
+    const double *Dsoft;                // [depth - 1][343][soft_ldc] d^g K at the offsets of levels 2..depth
+    const int *soft_map;                // [soft_ldc] LDS address of each compact entry (dense cube)
+    const double *zrow;                 // [ldm] zeros: operand of absent M2L sources
     double *phi_near, *fld_near;        // near-field (P2P) part, sorted order
     // caller's arrays for this evaluation
     const double *q_in;

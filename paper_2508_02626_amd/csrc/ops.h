@@ -20,6 +20,7 @@ void launch_m2p(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 
 // P2P runs in two parts (leaves [0, split) and [split, nleaves)), each
 // overlapping a latency-bound phase of the far field
 __host__ __device__ inline int p2p_split(int nleaves) { return (int)((int64_t)nleaves * 5 / 8) & ~3; }
+// mixed: 0 FP64, 1 FP32 terms, 2 softened kernel (FP64)
 void launch_p2p(int mixed, int part, const PlanView *V, const Bases &B, hipStream_t s); // 4 leaves/block
 void launch_zero(double *p, int64_t n, hipStream_t s);
 void launch_zero_f32(float *p, int64_t n, hipStream_t s);

@@ -18,6 +18,8 @@
 //   P2P  (Sec. 1) pairwise sum over the U list, skipping j == i and r == 0.
 #include "ops.h"
 
+#include <type_traits>
+
 namespace fmm {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -759,6 +761,13 @@ __global__ __launch_bounds__(64) void k_m2p(const PlanView *V, Bases B)
 struct SrcRec {
     double x, y, z, q;
 };
+// softened kernel: the source's sorted index too (j == i is skipped by index,
+// since distinct coincident points interact through q / eps)
+struct SrcRecS {
+    double x, y, z, q;
+    int j;
+};
+template <int KIND> using SrcT = typename std::conditional<KIND == 2, SrcRecS, SrcRec>::type;
 
 struct Tgt {
     double x, y, z;
@@ -787,12 +796,28 @@ __device__ inline double rsqrt_refined(double x)
     return fma(y, e * fma(e, 0.375, 0.5), y);
 }
 
-// A pair contributes iff r^2 > 0: this skips j == i (same coordinates) and
-// coincident points alike.
+// KIND 0 (FP64) and 1 (FP32 terms): a pair contributes iff r^2 > 0, which
+// skips j == i (same coordinates) and coincident points alike.  KIND 2 (the
+// softened kernel, FP64): every j != i with r^2 + eps^2 > 0.
 template <int MIXED>
-__device__ inline void p2p_range(const SrcRec *S, int lo, int hi, Tgt &a, Tgt &b)
+__device__ inline void p2p_range(const SrcT<MIXED> *S, int lo, int hi, Tgt &a, Tgt &b, double eps2)
 {
-    if (MIXED) {
+    if constexpr (MIXED == 2) {
+        auto term = [eps2](const SrcRecS &s, Tgt &t) {
+            const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
+            const double r2 = dx * dx + dy * dy + dz * dz + eps2;
+            const double ri = (s.j != t.i && r2 > 0.0) ? rsqrt_refined(r2) : 0.0;
+            const double qr = s.q * ri;
+            const double qr3 = qr * ri * ri;
+            t.phi += qr;
+            t.ex += qr3 * dx; t.ey += qr3 * dy; t.ez += qr3 * dz;
+        };
+        for (int jj = lo; jj < hi; ++jj) {
+            const SrcRecS s0 = S[jj];
+            term(s0, a);
+            term(s0, b);
+        }
+    } else if constexpr (MIXED == 1) {
         auto term = [](const SrcRec &s, Tgt &t) {
             const float dx = (float)(t.x - s.x), dy = (float)(t.y - s.y), dz = (float)(t.z - s.z);
             const float r2 = dx * dx + dy * dy + dz * dz;
@@ -834,7 +859,7 @@ __device__ inline void p2p_range(const SrcRec *S, int lo, int hi, Tgt &a, Tgt &b
 template <int MIXED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_p2p(const PlanView *V, Bases B, int part)
 {
-    __shared__ SrcRec sS[4][64];
+    __shared__ SrcT<MIXED> sS[4][64];
     __shared__ double sR[4][8][64]; // group partials for the final combination
     int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
@@ -850,7 +875,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
     const int box = v.leaves[li];
     const int f = first[box], cnt = count[box];
     const int64_t u0 = v.U_off[box], u1 = v.U_off[box + 1];
-    SrcRec *S = sS[wave];
+    SrcT<MIXED> *S = sS[wave];
     double(*R)[64] = sR[wave];
     for (int ts = 0; ts < cnt; ts += 64) {
         const int c = cnt - ts < 64 ? cnt - ts : 64;
@@ -893,7 +918,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
         };
         load_boxes();
         if (e < u1) box_at();
-        SrcRec nx{0, 0, 0, 0};
+        SrcT<MIXED> nx{};
         auto fill = [&]() { // next chunk into nx; returns its size
             int m = 0;
             while (m < CH && e < u1) {
@@ -901,6 +926,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
                 if (lane >= m && lane < m + take) {
                     const int j = sf + s + (lane - m);
                     nx.x = xs[j]; nx.y = ys[j]; nx.z = zs[j]; nx.q = qs[j];
+                    if constexpr (MIXED == 2) nx.j = j;
                 }
                 m += take;
                 s += take;
@@ -919,10 +945,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) voi
             const int mn = fill(); // in flight during this chunk's pairs
             const int per = (m + G - 1) / G;
             const int lo = inG ? grp * per : m, hi = lo + per < m ? lo + per : m;
-            p2p_range<MIXED>(S, lo, hi, ta, tb);
+            p2p_range<MIXED>(S, lo, hi, ta, tb, v.eps2);
             m = mn;
         }
-        if (MIXED) { // compensated FP32 sums -> FP64
+        if (MIXED == 1) { // compensated FP32 sums -> FP64
             ta.phi = (double)ta.s[0] - (double)ta.c[0]; ta.ex = (double)ta.s[1] - (double)ta.c[1];
             ta.ey = (double)ta.s[2] - (double)ta.c[2]; ta.ez = (double)ta.s[3] - (double)ta.c[3];
             tb.phi = (double)tb.s[0] - (double)tb.c[0]; tb.ex = (double)tb.s[1] - (double)tb.c[1];
@@ -1027,7 +1053,8 @@ void launch_far(int p, const PlanView *V, const Bases &B, hipStream_t s)
 void launch_p2p(int mixed, int part, const PlanView *V, const Bases &B, hipStream_t s)
 {
     if (!nblk(B)) return;
-    if (mixed) k_p2p<1><<<nblk(B), 256, 0, s>>>(V, B, part);
+    if (mixed == 2) k_p2p<2><<<nblk(B), 256, 0, s>>>(V, B, part);
+    else if (mixed) k_p2p<1><<<nblk(B), 256, 0, s>>>(V, B, part);
     else k_p2p<0><<<nblk(B), 256, 0, s>>>(V, B, part);
 }
 void launch_zero(double *p, int64_t n, hipStream_t s)

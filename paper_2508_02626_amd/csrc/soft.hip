@@ -1,0 +1,460 @@
+// The softened Coulomb kernel K(x) = 1/sqrt(|x|^2 + eps^2): a second
+// non-oscillatory kernel through the same tree, lists and pipeline (the DA
+// formulation is not tied to 1/r; closing remark of Sec. 3.4).
+//
+// K is not harmonic, so there is no fold: the expansions are the full
+// Cartesian Taylor ones.  In scaled units (h = box width, u = (x - c)/h):
+//   Mhat_a = M_a / h^|a| = sum_i q_i (-u_i)^a / a!          (P2M: moments)
+//   Lhat_b = b! h^(|b|+1) L_b,  phi(c + h u) = (1/h) sum_b Lhat_b u^b / b!
+//   M2L  Lhat_b(B) = sum_a D_(a+b)(k) Mhat_a(C),  D_g(k) = d^g K_eta(k),
+//        eta = eps / h: unlike 1/r the kernel is not homogeneous, so the
+//        derivative tables depend on the level (one set per level)
+//   M2M  Mhat_a(P) = sum_{b <= a} 2^-|b| Mhat_b(C) (-tau)^(a-b) / (a-b)!
+//   L2L  Lhat_b(C) += 2^(-|b|-1) sum_{g >= b} Lhat_g(P) tau^(g-b) / (g-b)!
+//        tau = (c_C - c_P) / h_P = (+-1/4, +-1/4, +-1/4)
+// The shifts factor over the axes, so M2M and L2L run as three one-axis
+// shifts (O(n_p p) per box instead of n_p^2).  The tables come from the
+// Taylor recurrence of rho^(-1/2), rho = |x|^2 + eta^2:
+//   n rho a_g + (2n - 1) sum_k x_k a_(g - e_k) + (n - 1) sum_k a_(g - 2e_k) = 0,
+// a_g = d^g K / g! (degree n = |g|; eta = 0 gives the 1/r recurrence).
+#include "ops.h"
+#include "soft.h"
+
+namespace fmm {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+template <typename T> __device__ inline T gload(const T *p) { return *gptr(p); }
+
+// exponents of the monomial at DA index e of degree n (mono_index inverse)
+__device__ inline void mono_exps(int e, int n, int &i, int &j, int &k)
+{
+    int r = e - below(n), a = 0;
+    while ((a + 1) * (a + 2) / 2 <= r) ++a;
+    k = r - a * (a + 1) / 2;
+    j = a - k;
+    i = n - a;
+}
+__device__ inline double fact_d(int n)
+{
+    double r = 1.0;
+    for (int t = 2; t <= n; ++t) r *= t;
+    return r;
+}
+
+// ---------------- derivative tables, one block per (level, offset) ----------------
+template <int P>
+__global__ __launch_bounds__(256) void k_soft_tables(double *D, int *map, int ldc, double W, double eps)
+{
+    constexpr int Q = 2 * P, NQ = ncoef(Q), S = Q + 1;
+    __shared__ double a[NQ];
+    const int lev = blockIdx.x / 343 + 2, off = blockIdx.x % 343;
+    const int kx = off / 49 - 3, ky = (off / 7) % 7 - 3, kz = off % 7 - 3;
+    double *out = D + (int64_t)blockIdx.x * ldc;
+    const int tid = threadIdx.x;
+    if (blockIdx.x == 0)
+        for (int e = tid; e < ldc; e += 256) {
+            int n = 0, i = 0, j = 0, k = 0;
+            if (e < NQ) {
+                while (below(n + 1) <= e) ++n;
+                mono_exps(e, n, i, j, k);
+                map[e] = (i * S + j) * S + k;
+            } else {
+                map[e] = S * S * S; // the slot after the cube, never read
+            }
+        }
+    // only V-list offsets (some |k_i| >= 2) are ever read
+    if (max(abs(kx), max(abs(ky), abs(kz))) <= 1) {
+        for (int e = tid; e < ldc; e += 256) out[e] = 0.0;
+        return;
+    }
+    const double eta = eps * (double)(1ll << lev) / W;
+    const double x[3] = {(double)kx, (double)ky, (double)kz};
+    const double rho = x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + eta * eta;
+    if (tid == 0) a[0] = 1.0 / sqrt(rho);
+    for (int n = 1; n <= Q; ++n) {
+        __syncthreads();
+        for (int e = below(n) + tid; e < below(n + 1); e += 256) {
+            int g[3];
+            mono_exps(e, n, g[0], g[1], g[2]);
+            double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (g[d] >= 1) {
+                    int h[3] = {g[0], g[1], g[2]};
+                    h[d] -= 1;
+                    s1 += x[d] * a[mono_index(h[0], h[1], h[2])];
+                }
+                if (g[d] >= 2) {
+                    int h[3] = {g[0], g[1], g[2]};
+                    h[d] -= 2;
+                    s2 += a[mono_index(h[0], h[1], h[2])];
+                }
+            }
+            a[e] = -((2 * n - 1) * s1 + (n - 1) * s2) / (n * rho);
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < ldc; e += 256) {
+        double v = 0.0;
+        if (e < NQ) {
+            int n = 0, i, j, k;
+            while (below(n + 1) <= e) ++n;
+            mono_exps(e, n, i, j, k);
+            v = a[e] * fact_d(i) * fact_d(j) * fact_d(k); // d^g K = g! a_g
+        }
+        out[e] = v;
+    }
+}
+
+// ---------------- P2M: moments from the raw moments ----------------
+// Raw moments Q_g = sum q u^g (k_p2m, in the leaf's L row) -> Mhat_a =
+// (-1)^|a| Q_a / a! in its M row (padding columns zero).
+template <int P>
+__global__ __launch_bounds__(256) void k_soft_p2m(const PlanView *V)
+{
+    constexpr int NC = ncoef(P);
+    const PlanView &v = V[0];
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int ldm = v.ldm;
+    if (e >= (int64_t)v.nleaves * ldm) return;
+    const int li = (int)(e / ldm), a = (int)(e - (int64_t)li * ldm);
+    const int box = v.leaves[li];
+    double m = 0.0;
+    if (a < NC) {
+        int n = 0, i, j, k;
+        while (below(n + 1) <= a) ++n;
+        mono_exps(a, n, i, j, k);
+        const double q = v.L[(int64_t)box * ldm + a] * v.tab->inv_fact[a];
+        m = (n & 1) ? -q : q;
+    }
+    v.M[(int64_t)box * ldm + a] = m;
+}
+
+// one-axis shift of a vector of NC coefficients in LDS: out[g] = sum_m c[m] in[g -+ m e_d]
+// (dir = -1: lower indices, the moment shift; dir = +1: higher, the Taylor shift)
+template <int P>
+__device__ inline void axis_shift(const double *in, double *out, int d, int dir, const double *c, int lane)
+{
+    constexpr int NC = ncoef(P);
+    for (int g = lane; g < NC; g += 64) {
+        int n = 0, e[3];
+        while (below(n + 1) <= g) ++n;
+        mono_exps(g, n, e[0], e[1], e[2]);
+        double s = 0.0;
+        if (dir < 0) {
+            for (int m = 0; m <= e[d]; ++m) {
+                int h[3] = {e[0], e[1], e[2]};
+                h[d] -= m;
+                s += c[m] * in[mono_index(h[0], h[1], h[2])];
+            }
+        } else {
+            for (int m = 0; m <= P - n; ++m) {
+                int h[3] = {e[0], e[1], e[2]};
+                h[d] += m;
+                s += c[m] * in[mono_index(h[0], h[1], h[2])];
+            }
+        }
+        out[g] = s;
+    }
+}
+
+// ---------------- M2M: one block (one wavefront) per parent of `level` ----------------
+template <int P>
+__global__ __launch_bounds__(64) void k_soft_m2m(const PlanView *V, int first_box)
+{
+    constexpr int NC = ncoef(P);
+    __shared__ double s0[NC], s1[NC];
+    __shared__ double cf[3][P + 1];
+    const PlanView &v = V[0];
+    const int box = first_box + blockIdx.x, lane = threadIdx.x, ldm = v.ldm;
+    constexpr int RC = (NC + 63) / 64;
+    double acc[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) acc[r] = 0.0;
+    const int nch = v.nchild[box], c0 = v.child_begin[box];
+    for (int c = 0; c < nch; ++c) {
+        const int ch = c0 + c, o = (int)(v.morton[ch] & 7);
+        __syncthreads();
+        for (int g = lane; g < NC; g += 64) {
+            int n = 0;
+            while (below(n + 1) <= g) ++n;
+            s0[g] = v.M[(int64_t)ch * ldm + g] * ldexp(1.0, -n);
+        }
+        if (lane < 3 * (P + 1)) { // (-tau_d)^m / m!, tau_d = (2 o_d - 1) / 4
+            const int d = lane / (P + 1), m = lane - d * (P + 1);
+            const double t = -(2.0 * ((o >> (2 - d)) & 1) - 1.0) * 0.25;
+            double pw = 1.0;
+            for (int u = 0; u < m; ++u) pw *= t;
+            cf[d][m] = pw / fact_d(m);
+        }
+        __syncthreads();
+        axis_shift<P>(s0, s1, 0, -1, cf[0], lane);
+        __syncthreads();
+        axis_shift<P>(s1, s0, 1, -1, cf[1], lane);
+        __syncthreads();
+        axis_shift<P>(s0, s1, 2, -1, cf[2], lane);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RC; ++r)
+            if (lane + 64 * r < NC) acc[r] += s1[lane + 64 * r];
+    }
+    for (int g = lane; g < ldm; g += 64) {
+        const int r = g / 64;
+        double val = 0.0;
+#pragma unroll
+        for (int q = 0; q < RC; ++q)
+            if (q == r && g < NC) val = acc[q];
+        v.M[(int64_t)box * ldm + g] = val;
+    }
+}
+
+// ---------------- L2L: one block (one wavefront) per child of a box of `level` ----------------
+template <int P>
+__global__ __launch_bounds__(64) void k_soft_l2l(const PlanView *V, int first_child)
+{
+    constexpr int NC = ncoef(P);
+    __shared__ double s0[NC], s1[NC];
+    __shared__ double cf[3][P + 1];
+    const PlanView &v = V[0];
+    const int ch = first_child + blockIdx.x, lane = threadIdx.x, ldm = v.ldm;
+    const int par = v.parent[ch], o = (int)(v.morton[ch] & 7);
+    for (int g = lane; g < NC; g += 64) s0[g] = v.L[(int64_t)par * ldm + g];
+    if (lane < 3 * (P + 1)) { // tau_d^m / m!
+        const int d = lane / (P + 1), m = lane - d * (P + 1);
+        const double t = (2.0 * ((o >> (2 - d)) & 1) - 1.0) * 0.25;
+        double pw = 1.0;
+        for (int u = 0; u < m; ++u) pw *= t;
+        cf[d][m] = pw / fact_d(m);
+    }
+    __syncthreads();
+    axis_shift<P>(s0, s1, 0, 1, cf[0], lane);
+    __syncthreads();
+    axis_shift<P>(s1, s0, 1, 1, cf[1], lane);
+    __syncthreads();
+    axis_shift<P>(s0, s1, 2, 1, cf[2], lane);
+    __syncthreads();
+    for (int g = lane; g < NC; g += 64) {
+        int n = 0;
+        while (below(n + 1) <= g) ++n;
+        v.L[(int64_t)ch * ldm + g] += ldexp(s1[g], -n - 1);
+    }
+}
+
+// ---------------- M2L on the full components (FP64 MFMA) ----------------
+// Uniform trees: the boxes of level l are all 8^l cells in Morton order, so
+// a block takes 64 boxes of one level and octant (Morton index 8 (64 t + i) + o)
+// and they share the 189 offsets of that octant and the level's tables.  As in
+// the slot-by-slot Coulomb M2L, per used offset slot each wavefront runs an
+// n_p x n_p by 16 product with 16x16x4 MFMAs: A[b][a] = D(addr(b) + addr(a))
+// gathered from the slot's table in LDS (dense cube addr(i,j,k) =
+// (i S + j) S + k, S = 2p + 1, so addr(a) + addr(b) = addr(a + b)); B the 16
+// targets' source multipoles, one 16-byte vector (two k-steps) per lane, one
+// vector ahead.  Tables are double-buffered in LDS (one barrier per slot).
+template <int P> struct SoftM2L {
+    static constexpr int NP = ncoef(P), MT = (NP + 15) / 16, KS = ((NP + 3) / 4 + 1) & ~1, KSV = KS / 2;
+    // LDS table: the dense cube and one slot after it for the padding entry
+    static constexpr int S = 2 * P + 1, LDD = S * S * S + 1, LDC = (ncoef(2 * P) + 1) & ~1;
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void k_m2l_soft(const PlanView *V, SoftGrid G)
+{
+    using SH = SoftM2L<P>;
+    constexpr int NP = SH::NP, MT = SH::MT, KS = SH::KS, KSV = SH::KSV, S = SH::S, LDD = SH::LDD, LDC = SH::LDC;
+    constexpr int DV = (LDC / 2 + 255) / 256;
+    static_assert(8 * KSV <= pad16(NP), "operand vectors stay inside a padded row");
+    typedef double vec_t __attribute__((ext_vector_type(2)));
+    __shared__ double sD[2][LDD];
+    __shared__ int sHo[4][KS];
+    __shared__ int sTg[64];
+    __shared__ int sList[kVSlots];
+    __shared__ int sN;
+    const PlanView &v = V[0];
+    // block -> (level, octant, tile), each XCD taking a contiguous range
+    int item = xcd_remap(blockIdx.x, G.nblocks), li = 0;
+    while (li + 1 < G.nlev && item >= G.start[li + 1]) ++li;
+    item -= G.start[li];
+    const int lev = li + 2, per = G.tiles[li], o = item / per, t = item - o * per;
+    const int64_t cells = 1ll << (3 * (lev - 1)); // boxes of one octant at this level
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
+    const OrderTables &tb = *v.tab;
+    if (tid < 64) {
+        const int64_t m = (int64_t)t * 64 + tid;
+        sTg[tid] = m < cells ? G.lvl_first[li] + (int)(8 * m + o) : -1;
+    }
+    for (int e = tid; e < 4 * KS; e += 256) {
+        const int g = e / KS, ks = e - g * KS, a = 8 * (ks / 2) + 2 * g + (ks & 1);
+        int addr = 0;
+        if (a < NP) {
+            const int x = gptr(tb.exps)[a];
+            addr = ((x & 255) * S + ((x >> 8) & 255)) * S + (x >> 16);
+        }
+        sHo[g][ks] = addr;
+    }
+    int hb[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int b = 16 * mt + col;
+        int addr = 0;
+        if (b < NP) {
+            const int x = gptr(tb.exps)[b];
+            addr = ((x & 255) * S + ((x >> 8) & 255)) * S + (x >> 16);
+        }
+        hb[mt] = addr;
+    }
+    __syncthreads();
+    const auto vs = gptr(v.vslot);
+    if (tid < kVSlots) {
+        int any = 0;
+        for (int q = 0; q < 64; ++q) any |= sTg[q] >= 0 && vs[(int64_t)sTg[q] * kVSlots + tid] >= 0;
+        sList[tid] = any;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int n = 0;
+        for (int j = 0; j < kVSlots; ++j)
+            if (sList[j]) sList[n++] = j;
+        sN = n;
+    }
+    __syncthreads();
+    const int nslot = sN;
+    const int tgt = sTg[wave * 16 + col];
+    const double *Dl = v.Dsoft + (int64_t)li * 343 * LDC;
+    const auto offs = gptr(tb.offs) + o * kVSlots;
+    typedef double dvec_t __attribute__((ext_vector_type(2)));
+    dvec_t pd[DV];
+    int dm[DV][2];
+#pragma unroll
+    for (int r = 0; r < DV; ++r)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const int e = (tid + 256 * r) * 2 + w;
+            dm[r][w] = e < LDC ? gptr(v.soft_map)[e] : LDD - 1;
+        }
+    auto load_d = [&](int j) {
+        const dvec_t *Dk = (const dvec_t *)(Dl + (int64_t)offs[j] * LDC);
+#pragma unroll
+        for (int r = 0; r < DV; ++r) {
+            const int e = tid + 256 * r;
+            pd[r] = e < LDC / 2 ? gload(Dk + e) : dvec_t{0, 0};
+        }
+    };
+    auto store_d = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < DV; ++r)
+            if (tid + 256 * r < LDC / 2)
+#pragma unroll
+                for (int w = 0; w < 2; ++w) sD[buf][dm[r][w]] = pd[r][w];
+    };
+    const int ldm = v.ldm;
+    auto row_of = [&](int j) -> const double * {
+        const int src = tgt >= 0 ? vs[(int64_t)tgt * kVSlots + j] : -1;
+        return (src >= 0 ? v.M + (int64_t)src * ldm : v.zrow) + 2 * kq;
+    };
+    double4_t acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = double4_t{0, 0, 0, 0};
+    const double *rc = v.zrow, *rn = v.zrow;
+    vec_t cur{0, 0}, nxt{0, 0};
+    if (nslot > 0) {
+        load_d(sList[0]);
+        store_d(0);
+        rc = row_of(sList[0]);
+        cur = gload((const vec_t *)rc);
+        __syncthreads();
+    }
+    for (int q = 0; q < nslot; ++q) {
+        const int buf = q & 1;
+        const bool more = q + 1 < nslot;
+        if (more) {
+            load_d(sList[q + 1]);
+            rn = row_of(sList[q + 1]);
+        }
+        // the wavefront skips a slot none of its targets has
+        const bool has = rc != v.zrow + 2 * kq;
+        if (__ballot(has)) {
+            const double *D = sD[buf];
+#pragma unroll 1
+            for (int jv = 0; jv < KSV; ++jv) {
+                nxt = jv + 1 < KSV ? gload((const vec_t *)(rc + 8 * (jv + 1))) : gload((const vec_t *)rn);
+#pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    const int ha = sHo[kq][2 * jv + w];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[hb[mt] + ha], cur[w], acc[mt], 0, 0, 0);
+                }
+                cur = nxt;
+            }
+        } else {
+            cur = gload((const vec_t *)rn);
+        }
+        rc = rn;
+        if (more) store_d(buf ^ 1);
+        __syncthreads();
+    }
+    if (tgt < 0) return;
+    double *L = v.L + (int64_t)tgt * ldm;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int b = 16 * mt + 4 * r + kq;
+            if (b < NP) L[b] = acc[mt][r];
+        }
+}
+
+// ---------------- launchers ----------------
+#define SOFT_SWITCH(p, CALL)                                                                   \
+    switch (p) {                                                                               \
+    case 0: CALL(0); break; case 1: CALL(1); break; case 2: CALL(2); break; case 3: CALL(3); break; \
+    case 4: CALL(4); break; case 5: CALL(5); break; case 6: CALL(6); break; case 7: CALL(7); break; \
+    case 8: CALL(8); break; case 9: CALL(9); break; default: CALL(10); break;                 \
+    }
+
+int soft_table_ldc(int p) { return (ncoef(2 * p) + 1) & ~1; }
+
+void launch_soft_tables(int p, int nlev, double *D, int *map, double W, double eps, hipStream_t s)
+{
+    if (nlev <= 0) return;
+    const int ldc = soft_table_ldc(p);
+#define T_(PP) k_soft_tables<PP><<<nlev * 343, 256, 0, s>>>(D, map, ldc, W, eps)
+    SOFT_SWITCH(p, T_)
+#undef T_
+}
+
+void launch_soft_p2m(int p, const PlanView *V, int nleaves, int ldm, hipStream_t s)
+{
+    const int64_t tot = (int64_t)nleaves * ldm;
+    if (!tot) return;
+    const unsigned nb = (unsigned)((tot + 255) / 256);
+#define T_(PP) k_soft_p2m<PP><<<nb, 256, 0, s>>>(V)
+    SOFT_SWITCH(p, T_)
+#undef T_
+}
+
+void launch_soft_m2m(int p, const PlanView *V, int first_box, int nbox, hipStream_t s)
+{
+    if (nbox <= 0) return;
+#define T_(PP) k_soft_m2m<PP><<<nbox, 64, 0, s>>>(V, first_box)
+    SOFT_SWITCH(p, T_)
+#undef T_
+}
+
+void launch_soft_l2l(int p, const PlanView *V, int first_child, int nchild, hipStream_t s)
+{
+    if (nchild <= 0) return;
+#define T_(PP) k_soft_l2l<PP><<<nchild, 64, 0, s>>>(V, first_child)
+    SOFT_SWITCH(p, T_)
+#undef T_
+}
+
+void launch_m2l_soft(int p, const PlanView *V, const SoftGrid &G, hipStream_t s)
+{
+    if (G.nblocks <= 0) return;
+#define T_(PP) k_m2l_soft<PP><<<G.nblocks, 256, 0, s>>>(V, G)
+    SOFT_SWITCH(p, T_)
+#undef T_
+}
+
+} // namespace fmm

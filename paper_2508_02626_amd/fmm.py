@@ -34,7 +34,8 @@ class FmmError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("uniform_depth", ctypes.c_int32), ("max_depth", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("want_field", ctypes.c_int32),
-                ("root", ctypes.POINTER(ctypes.c_double)), ("m2l_method", ctypes.c_int32)]
+                ("root", ctypes.POINTER(ctypes.c_double)), ("m2l_method", ctypes.c_int32),
+                ("kernel", ctypes.c_int32), ("softening", ctypes.c_double)]
 
 
 class Allocator(ctypes.Structure):
@@ -92,12 +93,16 @@ def _ptr(t):
 
 
 M2L_METHODS = {"sign_class": 0, "rotation": 1}
+KERNELS = {"coulomb": 0, "softened": 1}
 
 
-def _options(uniform_depth, max_depth, precision, want_field, root, m2l="sign_class"):
+def _options(uniform_depth, max_depth, precision, want_field, root, m2l="sign_class", kernel="coulomb",
+             softening=0.0):
     o = Options()
     lib().fmm_default_options(ctypes.byref(o))
     o.m2l_method = M2L_METHODS[m2l] if isinstance(m2l, str) else int(m2l)
+    o.kernel = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    o.softening = float(softening)
     o.uniform_depth = uniform_depth
     o.max_depth = max_depth
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
@@ -113,10 +118,13 @@ class Plan:
     """Octree, interaction lists and workspace for one point set (fmm_plan)."""
 
     def __init__(self, xyz, order, leaf_size=64, uniform_depth=-1, max_depth=21,
-                 precision="fp64", want_field=True, root=None, stream=None, allocator=None, m2l="sign_class"):
+                 precision="fp64", want_field=True, root=None, stream=None, allocator=None, m2l="sign_class",
+                 kernel="coulomb", softening=0.0):
         """allocator: an Allocator (C function pointers) for the plan's device
         memory, or None for the library's own stream-ordered allocation.
-        m2l: "sign_class" (matrix cores) or "rotation" (Sec. 3.4, vector unit)."""
+        m2l: "sign_class" (matrix cores) or "rotation" (Sec. 3.4, vector unit).
+        kernel: "coulomb" (1/r) or "softened" (1/sqrt(r^2 + softening^2);
+        uniform trees, FP64, order <= 10)."""
         import torch
         if not (isinstance(xyz, torch.Tensor) and xyz.is_cuda):
             raise FmmError(FMM_EINVAL, "xyz must be a CUDA/HIP tensor")
@@ -126,7 +134,7 @@ class Plan:
         self.n = int(xyz.shape[0])
         self.order = int(order)
         self.device = xyz.device
-        o, keep = _options(uniform_depth, max_depth, precision, want_field, root, m2l)
+        o, keep = _options(uniform_depth, max_depth, precision, want_field, root, m2l, kernel, softening)
         h = ctypes.c_void_p()
         _check(lib().fmm_plan(_ptr(xyz), self.n, self.order, int(leaf_size), ctypes.byref(o),
                               ctypes.byref(allocator) if allocator is not None else None,
@@ -289,8 +297,8 @@ def cached_bytes(device=0):
     return int(b.value)
 
 
-def estimate(n, order, leaf_size=64, uniform_depth=-1, max_depth=21, precision="fp64"):
-    o, keep = _options(uniform_depth, max_depth, precision, True, None)
+def estimate(n, order, leaf_size=64, uniform_depth=-1, max_depth=21, precision="fp64", kernel="coulomb"):
+    o, keep = _options(uniform_depth, max_depth, precision, True, None, kernel=kernel)
     b = ctypes.c_size_t()
     _check(lib().fmm_plan_estimate(int(n), int(order), int(leaf_size), ctypes.byref(o), ctypes.byref(b)))
     return int(b.value)
