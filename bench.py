@@ -57,7 +57,8 @@ TARGET_SIGMA = 1e-7
 # measured on (kernel, shared header, tile order): a different fingerprint
 # reports null.
 M2L_TRAFFIC = {
-    "uniform1m": {"fingerprint": "2e96bb397b2bc4cb", "bytes": (1342.94 + 83.36) * 1e6},
+    "uniform1m": {"fingerprint": "d25bdced5b8c5724", "bytes": (1343.04 + 83.45) * 1e6},
+    "plummer4m_p14": {"fingerprint": "d25bdced5b8c5724", "bytes": (33910.82 + 1172.21) * 1e6},
 }
 M2L_SOURCES = ("paper_2508_02626_amd/csrc/m2l.hip", "paper_2508_02626_amd/csrc/common.h",
                "paper_2508_02626_amd/csrc/m2l_tiles.hip")
@@ -293,7 +294,7 @@ def bench_plummer(args):
                      "sigma_phi_by_order": {str(o): s[0] for o, s in scan.items()}},
         "eval_only": {"value": n / f["eval_s"], "ms": 1e3 * f["eval_s"]},
         "stage_ms": f["stages"],
-        "roofline": m2l_roofline(f["tree"], p, f["stages"]["m2l"], kern, "plummer4m", FP64_PEAK_TFLOPS),
+        "roofline": m2l_roofline(f["tree"], p, f["stages"]["m2l"], kern, "plummer4m_p%d" % p, FP64_PEAK_TFLOPS),
         "p2p": p2p_roofline(f["tree"], f["stages"]["p2p"], "k_p2p<0>"),
     })
     if "mixed" in res:

@@ -162,8 +162,8 @@ int fmm_plan_batch(int32_t count, const double *const *xyz_dev, const int64_t *n
  * upward and downward passes; M2P (W lists) follows the second part there.
  * Deterministic: the
  * same plan and charges give bitwise identical results on every call.
- * Softened-kernel plans run P2P on the plan's stream in one piece next to the
- * whole far-field pipeline (P2M, M2M, M2L, L2L on full expansions).
+ * Softened-kernel plans (full expansions) run P2P's parts beside the upward
+ * pass and the L2L; their M2L runs alone.
  */
 int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_dev, double *field_dev,
                  hipStream_t stream);

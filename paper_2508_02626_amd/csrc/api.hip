@@ -971,6 +971,9 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
                              sub(r.first, r.second, [](const fmm_plan_s *p) { return (int)ceil_div(p->nboxes, 4); }), wl, s);
     }
     T.end();
+    // The M2L runs alone at every order: running P2L's moments, the second
+    // P2P part and M2P beside it at p = 14 (where it keeps one wavefront per
+    // SIMD) slowed it from 26.4 to 34.6 ms, more than they take.
     HIPCHK(hipStreamWaitEvent(s, F->ev_join, 0)); // first part of P2P done
     T.begin(4);
     for (auto &r : runs)
@@ -1031,8 +1034,10 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     return 0;
 }
 
-// The softened kernel's pipeline (uniform trees, one plan): P2P on the side
-// stream next to the whole far field; P2M raw moments -> moments, M2M by
+// The softened kernel's pipeline (uniform trees, one plan).  P2P's first
+// part runs on the side stream beside P2M and M2M, the M2L alone (it holds two
+// wavefronts per SIMD and slows down by more than P2P takes when they share the
+// GPU), the second part beside the L2L.  P2M raw moments -> moments, M2M by
 // one-axis shifts, M2L on the full components with the level's tables, L2L by
 // one-axis shifts, then L2P with the near field.
 int run_soft(fmm_plan_s *P, hipStream_t s)
@@ -1052,13 +1057,16 @@ int run_soft(fmm_plan_s *P, hipStream_t s)
     T.end();
     if (P->ensure_side()) return fail(FMM_EDEVICE, "side stream creation failed");
     StageTimer T2(P, P->side);
-    HIPCHK(hipEventRecord(P->ev_fork, s));
-    HIPCHK(hipStreamWaitEvent(P->side, P->ev_fork, 0));
-    T2.begin(9);
-    launch_p2p(2, 0, V, one(sp.p2p[0]), P->side);
-    launch_p2p(2, 1, V, one(sp.p2p[1]), P->side);
-    T2.end();
-    HIPCHK(hipEventRecord(P->ev_join, P->side));
+    auto p2p_part = [&](int part) {
+        HIPCHK(hipEventRecord(P->ev_fork, s));
+        HIPCHK(hipStreamWaitEvent(P->side, P->ev_fork, 0));
+        T2.begin(9 + part);
+        launch_p2p(2, part, V, one(sp.p2p[part]), P->side);
+        T2.end();
+        HIPCHK(hipEventRecord(P->ev_join, P->side));
+        return 0;
+    };
+    if (p2p_part(0)) return FMM_EDEVICE;
     const int depth = P->depth;
     auto lb = [&](int l) { return P->lvl_begin[l]; };
     T.begin(1);
@@ -1068,6 +1076,7 @@ int run_soft(fmm_plan_s *P, hipStream_t s)
     T.begin(2);
     for (int l = depth - 1; l >= 2; --l) launch_soft_m2m(P->p, V, lb(l), lb(l + 1) - lb(l), s);
     T.end();
+    HIPCHK(hipStreamWaitEvent(s, P->ev_join, 0)); // first P2P part done
     T.begin(4);
     {
         SoftGrid G{};
@@ -1083,6 +1092,7 @@ int run_soft(fmm_plan_s *P, hipStream_t s)
         launch_m2l_soft(P->p, V, G, s);
     }
     T.end();
+    if (p2p_part(1)) return FMM_EDEVICE;
     T.begin(7);
     for (int l = 2; l < depth; ++l) launch_soft_l2l(P->p, V, lb(l + 1), lb(l + 2) - lb(l + 1), s);
     T.end();
