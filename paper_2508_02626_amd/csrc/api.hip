@@ -842,6 +842,12 @@ int nonleaf_groups(const fmm_plan_s *P, int level)
     int c = P->lvl_nonleaf_off[level + 1] - P->lvl_nonleaf_off[level];
     return (int)ceil_div(c, 16);
 }
+// blocks of the folded M2M at a level (16-parent groups x row-tile groups)
+int m2m_blocks(const fmm_plan_s *P, int level)
+{
+    const int g = nonleaf_groups(P, level);
+    return g * m2m_row_split(P->ldmh / 16, g);
+}
 
 // Brackets a stage with events when the (single) plan has timing on.
 struct StageTimer {
@@ -961,7 +967,7 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     for (auto &r : runs)
         for (int l = maxdepth - 1; l >= 2; --l)
             launch_m2mh(P[r.first]->p, V + r.first,
-                        sub(r.first, r.second, [l](const fmm_plan_s *p) { return nonleaf_groups(p, l); }), l, s);
+                        sub(r.first, r.second, [l](const fmm_plan_s *p) { return m2m_blocks(p, l); }), l, s);
     // parents' FP32 operands (mixed M2L) and full multipoles (M2P sources)
     for (auto &r : runs) {
         int mixed = 0, wl = 0;
@@ -1356,7 +1362,7 @@ extern "C" int fmm_plan_export_expansions(fmm_plan_t plan, hipStream_t stream, d
                 launch_soft_m2m(P->p, P->view_dev, P->lvl_begin[l], P->lvl_begin[l + 1] - P->lvl_begin[l], stream);
                 continue;
             }
-            B.b[1] = nonleaf_groups(P, l);
+            B.b[1] = m2m_blocks(P, l);
             launch_m2mh(P->p, P->view_dev, B, l, stream);
         }
         if (!soft) {

@@ -11,6 +11,15 @@ void launch_p2m_fold(int p, const PlanView *V, const Bases &B, hipStream_t s); /
 void launch_l2lh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block (harmonic rows)
 void launch_lh_init(const PlanView *V, const Bases &B, hipStream_t s);        // 4 boxes/block
 void launch_m2mh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents/block
+// Row-tile groups per 16-parent M2M group: levels with few parents spread the
+// mt row tiles of each group over up to mt blocks (powers of two dividing mt)
+// until the level has about 512 blocks.
+__host__ __device__ inline int m2m_row_split(int mt, int groups)
+{
+    int r = 1;
+    while (2 * r <= mt && mt % (2 * r) == 0 && groups * r < 512) r *= 2;
+    return r;
+}
 void launch_parent_mh(const PlanView *V, const Bases &B, int full, hipStream_t s); // 4 boxes/block
 void launch_unfold(int p, const PlanView *V, const Bases &B, int leaves_only, hipStream_t s); // kRemapBoxes boxes/block
 void launch_p2l(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 X target/block

@@ -304,8 +304,9 @@ __device__ inline void mfma_rows(const double *A, int lda, int bA, bool aok, con
 // TM_o a (folded positions)^2 matrix.  A block takes 16 parents of one level,
 // one wavefront per child octant (16x16x4 FP64 MFMA): the wavefront loads its
 // children's folded vectors once (the B operands of every k-step) and runs
-// every row tile of the parents' vectors; the eight octants' partial tiles
-// are summed in octant order through LDS.
+// the row tiles of the parents' vectors (all of them, or at levels with few
+// parents a share, m2m_row_split); the eight octants' partial tiles are
+// summed in octant order through LDS.
 template <int P>
 __global__ __launch_bounds__(512) void k_m2mh(const PlanView *V, Bases B, int level)
 {
@@ -313,10 +314,11 @@ __global__ __launch_bounds__(512) void k_m2mh(const PlanView *V, Bases B, int le
     constexpr int LD = folded_ld(P), MT = LD / 16, KS = LD / 4;
     const int k = find_plan(B, blockIdx.x);
     const PlanView &v = V[k];
-    const int g = blockIdx.x - B.b[k];
     const int o = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63, col = lane & 15, kq = lane >> 4;
     const int lb = v.lvl_nonleaf_off[level], le = v.lvl_nonleaf_off[level + 1];
+    const int rs = m2m_row_split(MT, (le - lb + kPG - 1) / kPG);
+    const int g = (blockIdx.x - B.b[k]) / rs, rg = (blockIdx.x - B.b[k]) - g * rs;
     const int pidx = lb + g * kPG + col;
     const int parent = pidx < le ? v.lvl_nonleaf[pidx] : -1;
     const int ch = child_in_octant(v, parent, o); // child of this lane's parent in octant o
@@ -326,7 +328,7 @@ __global__ __launch_bounds__(512) void k_m2mh(const PlanView *V, Bases B, int le
 #pragma unroll
     for (int st = 0; st < KS; ++st) b[st] = ch >= 0 ? X[4 * st + kq] : 0.0;
     const auto T = gptr(v.tab->TM + (int64_t)o * LD * LD);
-    for (int mt = 0; mt < MT; ++mt) {
+    for (int mt = rg * (MT / rs); mt < (rg + 1) * (MT / rs); ++mt) {
         double4_t acc = {0, 0, 0, 0};
         if (any) {
 #pragma unroll
@@ -572,19 +574,32 @@ __global__ __launch_bounds__(64) void k_p2l_transform(const PlanView *V, Bases B
 }
 
 // ---------------- far field at the targets: L2P + M2P ----------------
+// Position of the coefficient of x^i y^j z^k in the order the nested Horner
+// below visits them (i, then j, then k descending), so that its reads are
+// consecutive and can be merged into wide LDS reads.
 template <int P>
-__device__ inline int cmono(int i, int j, int k)
+__device__ constexpr int horner_pos(int i, int j, int k)
 {
-    int n = i + j + k, a = j + k;
-    return n * (n + 1) * (n + 2) / 6 + a * (a + 1) / 2 + k;
+    // the (P - i)(P - i + 1)(P - i + 2)/6 coefficients of larger x exponents,
+    // then the (P - i - j)(P - i - j + 1)/2 of this one with larger y exponents
+    const int a = P - i, b = P - i - j;
+    return a * (a + 1) * (a + 2) / 6 + b * (b + 1) / 2 + (b - k);
+}
+// position of DA coefficient a (exponents packed i | j << 8 | k << 16)
+template <int P>
+__device__ inline int horner_pos_of(int packed)
+{
+    return horner_pos<P>(packed & 255, (packed >> 8) & 255, (packed >> 16) & 255);
 }
 
-// f = sum_a c_a x^a y^b z^c and its gradient, nested Horner in z, y, x
+// f = sum_a c_a x^a y^b z^c and its gradient, nested Horner in z, y, x; c in
+// horner_pos order
 template <int P>
 __device__ inline void eval_poly(const double *c, double x, double y, double z, double &f,
                                  double &fx, double &fy, double &fz)
 {
     f = fx = fy = fz = 0.0;
+    int h = 0;
 #pragma unroll
     for (int i = P; i >= 0; --i) {
         double S = 0.0, Sy = 0.0, Sz = 0.0;
@@ -594,7 +609,7 @@ __device__ inline void eval_poly(const double *c, double x, double y, double z, 
 #pragma unroll
             for (int kk = P - i - j; kk >= 0; --kk) {
                 Tz = Tz * z + T;
-                T = T * z + c[cmono<P>(i, j, kk)];
+                T = T * z + c[h++];
             }
             Sy = Sy * y + S;
             S = S * y + T;
@@ -627,7 +642,8 @@ __global__ __launch_bounds__(64) void k_far(const PlanView *V, Bases B)
     box_geom(v, box, cen, h);
     const bool loc = valid && v.level[box] >= 2;
     if (loc)
-        for (int a = hl; a < NC; a += 32) cl[half][a] = v.L[(int64_t)box * v.ldm + a] * t.inv_fact[a];
+        for (int a = hl; a < NC; a += 32)
+            cl[half][horner_pos_of<P>(t.exps[a])] = v.L[(int64_t)box * v.ldm + a] * t.inv_fact[a];
     __syncthreads();
     const int f = v.first[box], cnt = valid ? v.count[box] : 0;
     const int cmax = max(cnt, __shfl_xor(cnt, 32)); // both halves run the longer leaf's chunks
@@ -680,10 +696,12 @@ __global__ __launch_bounds__(64) void k_m2p(const PlanView *V, Bases B)
     // per lane) while the current box is evaluated
     constexpr int R = (NC + 63) / 64;
     double wsc[R], nxt[R];
+    int hp[R]; // LDS position of the lane's coefficients (Horner order)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int a = lane + 64 * r, ea = a < NC ? t.exps[a] : 0;
         wsc[r] = a < NC ? t.inv_w[(ea & 255) + ((ea >> 8) & 255) + ((ea >> 16) & 255)] : 0.0;
+        hp[r] = horner_pos_of<P>(ea);
     }
     // W entries are read 64 at a time, lane l holding entry wb + l
     int64_t wb = w0;
@@ -712,7 +730,7 @@ __global__ __launch_bounds__(64) void k_m2p(const PlanView *V, Bases B)
             __syncthreads(); // the previous box's coefficients are consumed
 #pragma unroll
             for (int r = 0; r < R; ++r)
-                if (lane + 64 * r < NC) cm[lane + 64 * r] = nxt[r] * wsc[r];
+                if (lane + 64 * r < NC) cm[hp[r]] = nxt[r] * wsc[r];
             const int lev = nlev;
             const uint64_t mor = nmor;
             __syncthreads();
