@@ -27,10 +27,11 @@ targets (the exact reference at any accuracy), timed on the host cores.
 The same line carries a short served run (continuous batching, Poisson
 arrivals at half the saturated rate) with p50/p99 latency and the achieved
 sigma per requested-accuracy bucket, the uniform 1e6-point workload at
-p = 8 (uniform1m), and the same points under the second kernel, the softened
-Coulomb potential 1/sqrt(r^2 + eps^2) with eps = 1e-3 (softened1m).
+p = 8 (uniform1m), and the second kernel, the softened Coulomb potential
+1/sqrt(r^2 + eps^2), on those points (eps = 1e-3, softened1m) and on 1e6
+Plummer points with an adaptive tree (eps = 1e-4, softened_plummer1m).
 
-Other workloads (--workload): uniform1m or softened1m alone, batch256 (256 independent
+Other workloads (--workload): uniform1m, softened1m or softened_plummer1m alone, batch256 (256 independent
 problems, one fmm_evaluate_batch), serve (the served stream at four arrival
 rates), sweep (leaf size x order x N on Gaussian points), calib (a plain
 256 MiB device copy, for the HBM byte-counter calibration).
@@ -411,23 +412,27 @@ def bench_uniform(args, with_cpu=True):
 
 
 # ---------------------------------------------------------------- softened kernel
-def bench_softened(args):
-    """The second kernel, 1/sqrt(r^2 + eps^2): 1e6 uniform points in [0,1)^3
-    (seed 1), uniform depth 5 on [0,1]^3, p = 8, eps = 1e-3 (a tenth of the
-    mean spacing), FP64.  Its M2L is the full contraction (the kernel is not
-    harmonic): 2 n_p^2 flops per V pair."""
+def bench_softened(args, plummer=False):
+    """The second kernel, 1/sqrt(r^2 + eps^2), FP64: 1e6 uniform points in
+    [0,1)^3 (seed 1), uniform depth 5 on [0,1]^3, p = 8, eps = 1e-3 (a tenth of
+    the mean spacing); or (plummer) 1e6 Plummer points (scale radius 0.05,
+    seed 2), adaptive s = 64, p = 8, eps = 1e-4.  Its M2L is the full
+    contraction (the kernel is not harmonic): 2 n_p^2 flops per V pair."""
     import torch
     import oracle
     from paper_2508_02626_amd import fmm, inputs
-    n, depth, p, eps = 1_000_000, 5, 8, 1e-3
-    xh, qh = inputs.uniform(n, 1)
+    n, depth, p, eps = 1_000_000, 5, 8, (1e-4 if plummer else 1e-3)
+    xh, qh = inputs.plummer(n, 2) if plummer else inputs.uniform(n, 1)
     x = torch.tensor(xh, device="cuda:0")
     q = torch.tensor(qh, device="cuda:0")
     phi = torch.empty(n, dtype=torch.float64, device="cuda:0")
     fld = torch.empty(n, 3, dtype=torch.float64, device="cuda:0")
     idx = sample_targets(n, 2000)
     dphi, dfld = oracle.direct_soft(xh, qh, eps, idx)
-    mk = lambda: fmm.Plan(x, p, uniform_depth=depth, root=[0, 0, 0, 1], kernel="softened", softening=eps)
+    if plummer:
+        mk = lambda: fmm.Plan(x, p, leaf_size=64, kernel="softened", softening=eps)
+    else:
+        mk = lambda: fmm.Plan(x, p, uniform_depth=depth, root=[0, 0, 0, 1], kernel="softened", softening=eps)
     step_s = timed_steps(mk, q, phi, fld, args.steps, args.warmup)
     pl = mk()
     eval_s, stages = timed_evaluations(pl, q, phi, fld, args.steps)
@@ -435,16 +440,20 @@ def bench_softened(args):
     pl.close()
     ph, fl = phi.cpu().numpy(), fld.cpu().numpy()
     sig, sig_f = rel(ph[idx], dphi), rel(fl[idx], dfld)
-    log("bench softened1m: step %.3f ms eval %.3f ms sigma %.3e" % (1e3 * step_s, 1e3 * eval_s, sig))
+    log("bench softened %s: step %.3f ms eval %.3f ms sigma %.3e" % ("plummer1m" if plummer else "1m", 1e3 * step_s,
+                                                                    1e3 * eval_s, sig))
     nv = int(tree["V_off"][-1])
     nc = (p + 1) * (p + 2) * (p + 3) // 6
     flops = 2.0 * nc * nc * nv
     m2l_ms = stages["m2l"]
     achieved = flops / (m2l_ms * 1e-3) / 1e12
     return {"value": n / step_s, "ms_per_step": 1e3 * step_s, "dtype": "f64",
-            "config": {"workload": "softened Coulomb kernel 1/sqrt(r^2+eps^2), eps=1e-3: N=%d uniform in [0,1)^3 "
-                                   "(seed 1), q~U(-1,1), uniform octree depth 5 on [0,1]^3, order p=8, "
-                                   "potential+field" % n, "n": n, "order": p, "softening": eps},
+            "config": {"workload": ("softened Coulomb kernel 1/sqrt(r^2+eps^2), eps=1e-4: N=%d Plummer points (scale "
+                                    "radius 0.05, truncated at r=1, seed 2), q~U(-1,1), adaptive octree s=64, order "
+                                    "p=8, potential+field" % n) if plummer else
+                                   ("softened Coulomb kernel 1/sqrt(r^2+eps^2), eps=1e-3: N=%d uniform in [0,1)^3 "
+                                    "(seed 1), q~U(-1,1), uniform octree depth 5 on [0,1]^3, order p=8, "
+                                    "potential+field" % n), "n": n, "order": p, "softening": eps},
             "accuracy": {"sigma_phi_vs_direct": sig, "sigma_field_vs_direct": sig_f, "targets_sampled": len(idx)},
             "eval_only": {"value": n / eval_s, "ms": 1e3 * eval_s},
             "stage_ms": stages,
@@ -713,7 +722,8 @@ def main():
     ap.add_argument("--order", type=int, default=0, help="plummer4m: fixed order instead of the scan")
     ap.add_argument("--sigma-targets", type=int, default=4096)
     ap.add_argument("--workload", default="plummer4m",
-                    choices=["plummer4m", "uniform1m", "softened1m", "batch256", "serve", "sweep", "calib"])
+                    choices=["plummer4m", "uniform1m", "softened1m", "softened_plummer1m", "batch256", "serve",
+                             "sweep", "calib"])
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--serve-requests", type=int, default=120, help="requests of the served run in the default line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -747,9 +757,10 @@ def main():
             out["uniform1m"] = bench_uniform(args, with_cpu=not args.no_cpu_baseline)
         if not args.no_softened:
             out["softened1m"] = bench_softened(args)
-    elif args.workload == "softened1m":
+            out["softened_plummer1m"] = bench_softened(args, plummer=True)
+    elif args.workload in ("softened1m", "softened_plummer1m"):
         out = base_record(args)
-        out.update(bench_softened(args))
+        out.update(bench_softened(args, plummer=args.workload == "softened_plummer1m"))
     elif args.workload == "uniform1m":
         out = base_record(args)
         out.update(bench_uniform(args, with_cpu=not args.no_cpu_baseline))

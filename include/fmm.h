@@ -95,10 +95,10 @@ typedef struct {
                               j != i contributes, also at distance 0 when
                               eps > 0.  Softened plans use full Cartesian
                               Taylor expansions (the kernel is not harmonic, so
-                              there is no fold), need a uniform tree
-                              (uniform_depth >= 0), FMM_FP64, order <= 10 and
-                              the sign-class M2L method, and are evaluated by
-                              fmm_evaluate only                               */
+                              there is no fold) on uniform or adaptive trees,
+                              need FMM_FP64, order <= 10 and the sign-class
+                              M2L method, and are evaluated by fmm_evaluate
+                              only                                            */
     double softening;      /* eps >= 0, in the units of the coordinates
                               (softened kernel only)                          */
 } fmm_options_t;
@@ -163,7 +163,8 @@ int fmm_plan_batch(int32_t count, const double *const *xyz_dev, const int64_t *n
  * Deterministic: the
  * same plan and charges give bitwise identical results on every call.
  * Softened-kernel plans (full expansions) run P2P's parts beside the upward
- * pass and the L2L; their M2L runs alone.
+ * pass and the downward pass (P2L, L2L), M2P after the second part; their
+ * M2L runs alone.
  */
 int fmm_evaluate(fmm_plan_t plan, const double *q_dev, double *phi_dev, double *field_dev,
                  hipStream_t stream);

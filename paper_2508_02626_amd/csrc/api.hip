@@ -428,8 +428,6 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     }
     const int nb = P->nboxes;
     const bool soft = P->kernel == FMM_KERNEL_SOFTENED;
-    // softened kernel (uniform trees): derivative tables for levels 2..D
-    const int soft_nlev = soft ? std::max(P->D - 1, 0) : 0;
     P->m2l_parts = (P->m2l_rot || soft) ? 1 : sym_m2l_parts(P->p);
     // the sign-class M2L addresses the folded multipoles with 32-bit byte offsets
     if (!soft && m2l_sym(P->p) && (unsigned long long)(nb + 1) * (unsigned long long)P->ldmh * 8ULL >= (1ULL << 32))
@@ -444,8 +442,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
          .add<int32_t>(kMaxDepth + 2).add<PlanView>(1)
          .add<double>((size_t)nb * P->ldm).add<double>((size_t)nb * P->ldm);
         if (soft) {
-            o.add<double>((size_t)soft_nlev * 343 * soft_table_ldc(P->p)).add<int>(soft_table_ldc(P->p))
-             .add<double>(P->ldm);
+            o.add<int>(soft_table_ldc(P->p)).add<double>(P->ldm);
         } else {
             o.add<double>((size_t)(nb + 1) * P->ldmh).add<double>((size_t)nb * P->ldh);
             if (P->m2l_parts > 1) o.add<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh);
@@ -487,10 +484,9 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     double *Dsoft = nullptr, *zrow = nullptr;
     int *soft_map = nullptr;
     if (soft) {
-        Dsoft = P->own<double>((size_t)std::max(soft_nlev, 1) * 343 * soft_table_ldc(P->p));
         soft_map = P->own<int>(soft_table_ldc(P->p));
         zrow = P->own<double>(P->ldm);
-        NOMEM(Dsoft); NOMEM(soft_map); NOMEM(zrow);
+        NOMEM(soft_map); NOMEM(zrow);
     } else {
         NOMEM(Mh); NOMEM(Lh);
     }
@@ -623,11 +619,15 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     if (Mhf) launch_zero_f32(Mhf + (size_t)nb * P->ldmh, P->ldmh, s);
     v.kernel = P->kernel;
     v.eps2 = P->eps * P->eps;
-    v.Dsoft = Dsoft; v.soft_map = soft_map; v.zrow = zrow;
     if (soft) {
+        // derivative tables of the levels 2..depth that have boxes
+        const int soft_nlev = std::max(P->depth - 1, 0);
+        Dsoft = P->own<double>((size_t)std::max(soft_nlev, 1) * 343 * soft_table_ldc(P->p));
+        NOMEM(Dsoft);
         launch_zero(zrow, P->ldm, s);
         launch_soft_tables(P->p, soft_nlev, Dsoft, soft_map, P->root[3], P->eps, s);
     }
+    v.Dsoft = Dsoft; v.soft_map = soft_map; v.zrow = zrow;
     v.qs = qs; v.M = M; v.Mh = Mh; v.Lh = Lh; v.Lh2 = Lh2; v.m2l_parts = P->m2l_parts; v.L = L; v.Mhf = Mhf; v.phi_near = pf; v.fld_near = ff;
     HIPCHK(hipMemcpyAsync(P->view_dev, &v, sizeof(PlanView), hipMemcpyHostToDevice, s));
     HIPCHK(hipGetLastError());
@@ -651,7 +651,6 @@ int check_options(const fmm_options_t &o, int order, int leaf_size)
     if (o.kernel != FMM_KERNEL_COULOMB && o.kernel != FMM_KERNEL_SOFTENED) return fail(FMM_EINVAL, "bad kernel");
     if (o.kernel == FMM_KERNEL_SOFTENED) {
         if (!std::isfinite(o.softening) || o.softening < 0) return fail(FMM_EINVAL, "softening must be finite and >= 0");
-        if (o.uniform_depth < 0) return fail(FMM_EINVAL, "the softened kernel needs a uniform tree (uniform_depth >= 0)");
         if (o.precision != FMM_FP64) return fail(FMM_EINVAL, "the softened kernel runs in FMM_FP64 only");
         if (o.m2l_method != FMM_M2L_SIGN_CLASS) return fail(FMM_EINVAL, "the softened kernel has one M2L method");
         if (order > kSoftMaxOrder) return fail(FMM_EINVAL, "the softened kernel supports orders 0..10");
@@ -1040,12 +1039,12 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     return 0;
 }
 
-// The softened kernel's pipeline (uniform trees, one plan).  P2P's first
-// part runs on the side stream beside P2M and M2M, the M2L alone (it holds two
-// wavefronts per SIMD and slows down by more than P2P takes when they share the
-// GPU), the second part beside the L2L.  P2M raw moments -> moments, M2M by
-// one-axis shifts, M2L on the full components with the level's tables, L2L by
-// one-axis shifts, then L2P with the near field.
+// The softened kernel's pipeline (one plan).  P2P's first part runs on the
+// side stream beside P2M and M2M, the M2L alone (it holds two wavefronts per
+// SIMD and slows down by more than P2P takes when they share the GPU), the
+// second part and M2P (W lists) beside P2L (X lists) and the L2L.  P2M raw
+// moments -> moments, M2M by one-axis shifts, M2L on the full components with
+// the level's tables, L2L by one-axis shifts, then L2P with the near field.
 int run_soft(fmm_plan_s *P, hipStream_t s)
 {
     const PlanView *V = P->view_dev;
@@ -1069,6 +1068,11 @@ int run_soft(fmm_plan_s *P, hipStream_t s)
         T2.begin(9 + part);
         launch_p2p(2, part, V, one(sp.p2p[part]), P->side);
         T2.end();
+        if (part == 1 && P->nlist[2] > 0) { // M2P adds into the near-field sums
+            T2.begin(11);
+            launch_soft_m2p(P->p, V, P->nleaves, P->side);
+            T2.end();
+        }
         HIPCHK(hipEventRecord(P->ev_join, P->side));
         return 0;
     };
@@ -1078,6 +1082,8 @@ int run_soft(fmm_plan_s *P, hipStream_t s)
     T.begin(1);
     launch_p2m(P->p, V, one(sp.p2m), s);
     launch_soft_p2m(P->p, V, P->nleaves, P->ldm, s);
+    // M2L writes the rows of its targets, P2L and L2L add: start from zero
+    launch_zero(P->view.L, (int64_t)P->nboxes * P->ldm, s);
     T.end();
     T.begin(2);
     for (int l = depth - 1; l >= 2; --l) launch_soft_m2m(P->p, V, lb(l), lb(l + 1) - lb(l), s);
@@ -1086,19 +1092,27 @@ int run_soft(fmm_plan_s *P, hipStream_t s)
     T.begin(4);
     {
         SoftGrid G{};
-        G.nlev = std::max(depth - 1, 0);
-        for (int i = 0; i < G.nlev; ++i) {
-            const int l = i + 2;
-            const long long cells = 1ll << (3 * (l - 1));
-            G.tiles[i] = (int)((cells + 63) / 64);
-            G.start[i] = G.nblocks;
-            G.lvl_first[i] = lb(l);
-            G.nblocks += 8 * G.tiles[i];
+        if (P->uniform) {
+            G.nlev = std::max(depth - 1, 0);
+            for (int i = 0; i < G.nlev; ++i) {
+                const int l = i + 2;
+                const long long cells = 1ll << (3 * (l - 1));
+                G.tiles[i] = (int)((cells + 63) / 64);
+                G.start[i] = G.nblocks;
+                G.lvl_first[i] = lb(l);
+                G.nblocks += 8 * G.tiles[i];
+            }
+        } else {
+            G.adaptive = 1;
+            G.nblocks = P->nslots / kM2LSlots;
         }
         launch_m2l_soft(P->p, V, G, s);
     }
     T.end();
     if (p2p_part(1)) return FMM_EDEVICE;
+    T.begin(5);
+    launch_soft_p2l(P->p, V, P->nxtgt, s);
+    T.end();
     T.begin(7);
     for (int l = 2; l < depth; ++l) launch_soft_l2l(P->p, V, lb(l + 1), lb(l + 2) - lb(l + 1), s);
     T.end();
@@ -1246,8 +1260,9 @@ extern "C" int fmm_plan_estimate(int64_t n, int32_t order, int32_t leaf_size, co
     double per_box = 8 * (2 * ldm + parts * ldh + ldmh) + 4 * ldmh + 4 * 200 + 64; // expansions, slots, lists
     double per_particle = 8 * 3 + 4 + 8 * 5 + 8 * 2;
     double total = boxes * per_box + n * per_particle + 8 * 27 * boxes;
-    if (o.kernel == FMM_KERNEL_SOFTENED && o.uniform_depth >= 2 && order <= kSoftMaxOrder)
-        total += 8.0 * (o.uniform_depth - 1) * 343 * soft_table_ldc(order); // derivative tables per level
+    const int depth = o.uniform_depth >= 0 ? o.uniform_depth : o.max_depth;
+    if (o.kernel == FMM_KERNEL_SOFTENED && depth >= 2 && order <= kSoftMaxOrder)
+        total += 8.0 * (depth - 1) * 343 * soft_table_ldc(order); // derivative tables per level (at most)
     *bytes = (size_t)(total * 1.25);
     return FMM_OK;
 }

@@ -1,14 +1,14 @@
-// Softened Coulomb kernel 1/sqrt(|x|^2 + eps^2) on uniform trees (soft.hip).
+// Softened Coulomb kernel 1/sqrt(|x|^2 + eps^2) (soft.hip).
 #pragma once
 #include "common.h"
 
 namespace fmm {
-// M2L launch over the levels 2..depth of a uniform tree: level 2 + i has
-// tiles[i] tiles of 64 boxes per octant, its blocks start at start[i], its
-// first box is lvl_first[i]
+// M2L launch.  Adaptive trees: one block per M2L target tile.  Uniform trees,
+// levels 2..depth: level 2 + i has tiles[i] tiles of 64 boxes per octant, its
+// blocks start at start[i], its first box is lvl_first[i].
 constexpr int kSoftMaxLevels = 8;
 struct SoftGrid {
-    int nblocks, nlev;
+    int nblocks, nlev, adaptive;
     int start[kSoftMaxLevels], tiles[kSoftMaxLevels], lvl_first[kSoftMaxLevels];
 };
 constexpr int kSoftMaxOrder = 10; // the double-buffered dense table ((2p+1)^3 doubles) fills the LDS at p = 10
@@ -18,4 +18,6 @@ void launch_soft_p2m(int p, const PlanView *V, int nleaves, int ldm, hipStream_t
 void launch_soft_m2m(int p, const PlanView *V, int first_box, int nbox, hipStream_t s);
 void launch_soft_l2l(int p, const PlanView *V, int first_child, int nchild, hipStream_t s);
 void launch_m2l_soft(int p, const PlanView *V, const SoftGrid &G, hipStream_t s);
+void launch_soft_p2l(int p, const PlanView *V, int nxtgt, hipStream_t s);   // 1 X target/block
+void launch_soft_m2p(int p, const PlanView *V, int nleaves, hipStream_t s); // 1 leaf/block (W lists)
 } // namespace fmm

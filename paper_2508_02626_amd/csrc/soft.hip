@@ -172,6 +172,7 @@ __global__ __launch_bounds__(64) void k_soft_m2m(const PlanView *V, int first_bo
 #pragma unroll
     for (int r = 0; r < RC; ++r) acc[r] = 0.0;
     const int nch = v.nchild[box], c0 = v.child_begin[box];
+    if (nch == 0) return; // a leaf keeps its P2M multipole
     for (int c = 0; c < nch; ++c) {
         const int ch = c0 + c, o = (int)(v.morton[ch] & 7);
         __syncthreads();
@@ -241,15 +242,18 @@ __global__ __launch_bounds__(64) void k_soft_l2l(const PlanView *V, int first_ch
 }
 
 // ---------------- M2L on the full components (FP64 MFMA) ----------------
-// Uniform trees: the boxes of level l are all 8^l cells in Morton order, so
-// a block takes 64 boxes of one level and octant (Morton index 8 (64 t + i) + o)
-// and they share the 189 offsets of that octant and the level's tables.  As in
-// the slot-by-slot Coulomb M2L, per used offset slot each wavefront runs an
-// n_p x n_p by 16 product with 16x16x4 MFMAs: A[b][a] = D(addr(b) + addr(a))
-// gathered from the slot's table in LDS (dense cube addr(i,j,k) =
+// Per used offset slot each wavefront runs an n_p x n_p by 16 product with
+// 16x16x4 MFMAs, as the slot-by-slot Coulomb M2L: A[b][a] = D(addr(b) +
+// addr(a)) gathered from the slot's table in LDS (dense cube addr(i,j,k) =
 // (i S + j) S + k, S = 2p + 1, so addr(a) + addr(b) = addr(a + b)); B the 16
 // targets' source multipoles, one 16-byte vector (two k-steps) per lane, one
 // vector ahead.  Tables are double-buffered in LDS (one barrier per slot).
+// The 64 targets of a block share the 189 offsets of one octant: in a uniform
+// tree 64 boxes of one level and octant (Morton index 8 (64 t + i) + o); in an
+// adaptive tree the plan's M2L target tiles, whose targets are in level order
+// within their octant, so that only the tiles at a level boundary hold two
+// levels.  A block runs its levels one after the other with that level's
+// tables; a target's operands are zero in the other levels' products.
 template <int P> struct SoftM2L {
     static constexpr int NP = ncoef(P), MT = (NP + 15) / 16, KS = ((NP + 3) / 4 + 1) & ~1, KSV = KS / 2;
     // LDS table: the dense cube and one slot after it for the padding entry
@@ -266,21 +270,26 @@ __global__ __launch_bounds__(256) void k_m2l_soft(const PlanView *V, SoftGrid G)
     typedef double vec_t __attribute__((ext_vector_type(2)));
     __shared__ double sD[2][LDD];
     __shared__ int sHo[4][KS];
-    __shared__ int sTg[64];
+    __shared__ int sTg[64], sLv[64];
     __shared__ int sList[kVSlots];
-    __shared__ int sN;
+    __shared__ int sN, sOct, sLmin, sLmax;
     const PlanView &v = V[0];
-    // block -> (level, octant, tile), each XCD taking a contiguous range
-    int item = xcd_remap(blockIdx.x, G.nblocks), li = 0;
-    while (li + 1 < G.nlev && item >= G.start[li + 1]) ++li;
-    item -= G.start[li];
-    const int lev = li + 2, per = G.tiles[li], o = item / per, t = item - o * per;
-    const int64_t cells = 1ll << (3 * (lev - 1)); // boxes of one octant at this level
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
     const OrderTables &tb = *v.tab;
-    if (tid < 64) {
-        const int64_t m = (int64_t)t * 64 + tid;
-        sTg[tid] = m < cells ? G.lvl_first[li] + (int)(8 * m + o) : -1;
+    if (G.adaptive) {
+        const int tile = xcd_remap(blockIdx.x, G.nblocks);
+        if (tid < 64) sTg[tid] = v.m2l_tgt[(int64_t)tile * kM2LSlots + tid];
+    } else {
+        // block -> (level, octant, tile), each XCD taking a contiguous range
+        int item = xcd_remap(blockIdx.x, G.nblocks), li = 0;
+        while (li + 1 < G.nlev && item >= G.start[li + 1]) ++li;
+        item -= G.start[li];
+        const int lev = li + 2, per = G.tiles[li], o = item / per, t = item - o * per;
+        const int64_t cells = 1ll << (3 * (lev - 1)); // boxes of one octant at this level
+        if (tid < 64) {
+            const int64_t m = (int64_t)t * 64 + tid;
+            sTg[tid] = m < cells ? G.lvl_first[li] + (int)(8 * m + o) : -1;
+        }
     }
     for (int e = tid; e < 4 * KS; e += 256) {
         const int g = e / KS, ks = e - g * KS, a = 8 * (ks / 2) + 2 * g + (ks & 1);
@@ -303,24 +312,26 @@ __global__ __launch_bounds__(256) void k_m2l_soft(const PlanView *V, SoftGrid G)
         hb[mt] = addr;
     }
     __syncthreads();
+    if (tid < 64) sLv[tid] = sTg[tid] >= 0 ? v.level[sTg[tid]] : -1;
+    __syncthreads();
+    if (tid == 0) { // level range and octant of the block's targets
+        int lo = 1 << 30, hi = -1, oc = 0;
+        for (int q = 0; q < 64; ++q)
+            if (sTg[q] >= 0) {
+                lo = min(lo, sLv[q]);
+                hi = max(hi, sLv[q]);
+                oc = (int)(v.morton[sTg[q]] & 7);
+            }
+        sLmin = lo;
+        sLmax = hi;
+        sOct = oc;
+    }
+    __syncthreads();
+    const int lmin = sLmin, lmax = sLmax;
+    if (lmax < 0) return; // (block-uniform)
     const auto vs = gptr(v.vslot);
-    if (tid < kVSlots) {
-        int any = 0;
-        for (int q = 0; q < 64; ++q) any |= sTg[q] >= 0 && vs[(int64_t)sTg[q] * kVSlots + tid] >= 0;
-        sList[tid] = any;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int n = 0;
-        for (int j = 0; j < kVSlots; ++j)
-            if (sList[j]) sList[n++] = j;
-        sN = n;
-    }
-    __syncthreads();
-    const int nslot = sN;
-    const int tgt = sTg[wave * 16 + col];
-    const double *Dl = v.Dsoft + (int64_t)li * 343 * LDC;
-    const auto offs = gptr(tb.offs) + o * kVSlots;
+    const auto offs = gptr(tb.offs) + sOct * kVSlots;
+    const int tgt = sTg[wave * 16 + col], tlev = sLv[wave * 16 + col];
     typedef double dvec_t __attribute__((ext_vector_type(2)));
     dvec_t pd[DV];
     int dm[DV][2];
@@ -331,67 +342,85 @@ __global__ __launch_bounds__(256) void k_m2l_soft(const PlanView *V, SoftGrid G)
             const int e = (tid + 256 * r) * 2 + w;
             dm[r][w] = e < LDC ? gptr(v.soft_map)[e] : LDD - 1;
         }
-    auto load_d = [&](int j) {
-        const dvec_t *Dk = (const dvec_t *)(Dl + (int64_t)offs[j] * LDC);
-#pragma unroll
-        for (int r = 0; r < DV; ++r) {
-            const int e = tid + 256 * r;
-            pd[r] = e < LDC / 2 ? gload(Dk + e) : dvec_t{0, 0};
-        }
-    };
-    auto store_d = [&](int buf) {
-#pragma unroll
-        for (int r = 0; r < DV; ++r)
-            if (tid + 256 * r < LDC / 2)
-#pragma unroll
-                for (int w = 0; w < 2; ++w) sD[buf][dm[r][w]] = pd[r][w];
-    };
     const int ldm = v.ldm;
-    auto row_of = [&](int j) -> const double * {
-        const int src = tgt >= 0 ? vs[(int64_t)tgt * kVSlots + j] : -1;
-        return (src >= 0 ? v.M + (int64_t)src * ldm : v.zrow) + 2 * kq;
-    };
     double4_t acc[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) acc[mt] = double4_t{0, 0, 0, 0};
-    const double *rc = v.zrow, *rn = v.zrow;
-    vec_t cur{0, 0}, nxt{0, 0};
-    if (nslot > 0) {
-        load_d(sList[0]);
-        store_d(0);
-        rc = row_of(sList[0]);
-        cur = gload((const vec_t *)rc);
-        __syncthreads();
-    }
-    for (int q = 0; q < nslot; ++q) {
-        const int buf = q & 1;
-        const bool more = q + 1 < nslot;
-        if (more) {
-            load_d(sList[q + 1]);
-            rn = row_of(sList[q + 1]);
+    for (int L = lmin; L <= lmax; ++L) {
+        // slots used by the block's targets of level L, in increasing order
+        if (tid < kVSlots) {
+            int any = 0;
+            for (int q = 0; q < 64; ++q) any |= sLv[q] == L && vs[(int64_t)sTg[q] * kVSlots + tid] >= 0;
+            sList[tid] = any;
         }
-        // the wavefront skips a slot none of its targets has
-        const bool has = rc != v.zrow + 2 * kq;
-        if (__ballot(has)) {
-            const double *D = sD[buf];
-#pragma unroll 1
-            for (int jv = 0; jv < KSV; ++jv) {
-                nxt = jv + 1 < KSV ? gload((const vec_t *)(rc + 8 * (jv + 1))) : gload((const vec_t *)rn);
+        __syncthreads();
+        if (tid == 0) {
+            int n = 0;
+            for (int j = 0; j < kVSlots; ++j)
+                if (sList[j]) sList[n++] = j;
+            sN = n;
+        }
+        __syncthreads();
+        const int nslot = sN;
+        const double *Dl = v.Dsoft + (int64_t)(L - 2) * 343 * LDC;
+        auto load_d = [&](int j) {
+            const dvec_t *Dk = (const dvec_t *)(Dl + (int64_t)offs[j] * LDC);
 #pragma unroll
-                for (int w = 0; w < 2; ++w) {
-                    const int ha = sHo[kq][2 * jv + w];
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-                        acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[hb[mt] + ha], cur[w], acc[mt], 0, 0, 0);
-                }
-                cur = nxt;
+            for (int r = 0; r < DV; ++r) {
+                const int e = tid + 256 * r;
+                pd[r] = e < LDC / 2 ? gload(Dk + e) : dvec_t{0, 0};
             }
-        } else {
-            cur = gload((const vec_t *)rn);
+        };
+        auto store_d = [&](int buf) {
+#pragma unroll
+            for (int r = 0; r < DV; ++r)
+                if (tid + 256 * r < LDC / 2)
+#pragma unroll
+                    for (int w = 0; w < 2; ++w) sD[buf][dm[r][w]] = pd[r][w];
+        };
+        auto row_of = [&](int j) -> const double * {
+            const int src = tgt >= 0 && tlev == L ? vs[(int64_t)tgt * kVSlots + j] : -1;
+            return (src >= 0 ? v.M + (int64_t)src * ldm : v.zrow) + 2 * kq;
+        };
+        const double *rc = v.zrow, *rn = v.zrow;
+        vec_t cur{0, 0}, nxt{0, 0};
+        if (nslot > 0) {
+            load_d(sList[0]);
+            store_d(0);
+            rc = row_of(sList[0]);
+            cur = gload((const vec_t *)rc);
+            __syncthreads();
         }
-        rc = rn;
-        if (more) store_d(buf ^ 1);
-        __syncthreads();
+        for (int q = 0; q < nslot; ++q) {
+            const int buf = q & 1;
+            const bool more = q + 1 < nslot;
+            if (more) {
+                load_d(sList[q + 1]);
+                rn = row_of(sList[q + 1]);
+            }
+            // the wavefront skips a slot none of its targets has
+            const bool has = rc != v.zrow + 2 * kq;
+            if (__ballot(has)) {
+                const double *D = sD[buf];
+#pragma unroll 1
+                for (int jv = 0; jv < KSV; ++jv) {
+                    nxt = jv + 1 < KSV ? gload((const vec_t *)(rc + 8 * (jv + 1))) : gload((const vec_t *)rn);
+#pragma unroll
+                    for (int w = 0; w < 2; ++w) {
+                        const int ha = sHo[kq][2 * jv + w];
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+                            acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[hb[mt] + ha], cur[w], acc[mt], 0, 0, 0);
+                    }
+                    cur = nxt;
+                }
+            } else {
+                cur = gload((const vec_t *)rn);
+            }
+            rc = rn;
+            if (more) store_d(buf ^ 1);
+            __syncthreads();
+        }
     }
     if (tgt < 0) return;
     double *L = v.L + (int64_t)tgt * ldm;
@@ -402,6 +431,186 @@ __global__ __launch_bounds__(256) void k_m2l_soft(const PlanView *V, SoftGrid G)
             const int b = 16 * mt + 4 * r + kq;
             if (b < NP) L[b] = acc[mt][r];
         }
+}
+
+// ---------------- P2L and M2P (adaptive trees) ----------------
+__device__ inline void soft_box_geom(const PlanView &v, int b, double cen[3], double &h)
+{
+    const int l = v.level[b];
+    int c[3];
+    deinterleave(v.morton[b], l, c);
+    h = v.W / (double)(1ll << l);
+    for (int k = 0; k < 3; ++k) cen[k] = v.lo[k] + ((double)c[k] + 0.5) * h;
+}
+
+// Taylor coefficients a_g (|g| <= Q) of (|x + z|^2 + eta2)^(-1/2) in z, by the
+// recurrence of the tables, one degree shell after the other across the 64
+// lanes of the (single-wavefront) block, into a[0 .. ncoef(Q)).
+template <int Q>
+__device__ inline void taylor_shells(const double x[3], double eta2, double *a, int lane)
+{
+    const double rho = x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + eta2;
+    wave_sync(); // the previous use of a is done
+    if (lane == 0) a[0] = 1.0 / sqrt(rho);
+    for (int n = 1; n <= Q; ++n) {
+        wave_sync();
+        for (int e = below(n) + lane; e < below(n + 1); e += 64) {
+            int g[3];
+            mono_exps(e, n, g[0], g[1], g[2]);
+            double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                if (g[d] >= 1) {
+                    int h[3] = {g[0], g[1], g[2]};
+                    h[d] -= 1;
+                    s1 += x[d] * a[mono_index(h[0], h[1], h[2])];
+                }
+                if (g[d] >= 2) {
+                    int h[3] = {g[0], g[1], g[2]};
+                    h[d] -= 2;
+                    s2 += a[mono_index(h[0], h[1], h[2])];
+                }
+            }
+            a[e] = -((2 * n - 1) * s1 + (n - 1) * s2) / (n * rho);
+        }
+    }
+    wave_sync();
+}
+
+__device__ inline double wave_sum(double x)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// P2L: Lhat_b(B) += q b! a_b((c_B - x_j) / h_B; eta = eps / h_B) for every
+// particle j of the boxes of B's X list; one wavefront per X target, lanes
+// over the coefficients, particles one after the other.
+template <int P>
+__global__ __launch_bounds__(64) void k_soft_p2l(const PlanView *V)
+{
+    constexpr int NC = ncoef(P), RC = (NC + 63) / 64;
+    __shared__ double a[NC];
+    const PlanView &v = V[0];
+    const int box = v.xtgt[blockIdx.x], lane = threadIdx.x;
+    double cen[3], h;
+    soft_box_geom(v, box, cen, h);
+    const double ih = 1.0 / h, eta2 = v.eps2 * ih * ih;
+    double fb[RC], acc[RC];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+        const int c = lane + 64 * r;
+        int n = 0, i = 0, j = 0, k = 0;
+        if (c < NC) {
+            while (below(n + 1) <= c) ++n;
+            mono_exps(c, n, i, j, k);
+        }
+        fb[r] = fact_d(i) * fact_d(j) * fact_d(k);
+        acc[r] = 0.0;
+    }
+    for (int64_t e = v.X_off[box]; e < v.X_off[box + 1]; ++e) {
+        const int s = v.X_src[e], f = v.first[s], cnt = v.count[s];
+        for (int i = f; i < f + cnt; ++i) {
+            const double x[3] = {(cen[0] - v.xs[i]) * ih, (cen[1] - v.ys[i]) * ih, (cen[2] - v.zs[i]) * ih};
+            const double q = v.qs[i];
+            taylor_shells<P>(x, eta2, a, lane);
+#pragma unroll
+            for (int r = 0; r < RC; ++r)
+                if (lane + 64 * r < NC) acc[r] += q * fb[r] * a[lane + 64 * r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RC; ++r)
+        if (lane + 64 * r < NC) v.L[(int64_t)box * v.ldm + lane + 64 * r] += acc[r];
+}
+
+// M2P: phi(x) += (1/h) sum_a Mhat_a a! a_a(u), u = (x - c_C)/h_C, eta = eps/h_C,
+// and its gradient (1/h^2) sum_a Mhat_a a! (a_k + 1) a_(a+e_k)(u), for every
+// box C of the leaf's W list, added to the near-field sums (after P2P).  One
+// wavefront per leaf, lanes over the coefficients, particles one after the
+// other in chunks of 64 (their sums in LDS).
+template <int P>
+__global__ __launch_bounds__(64) void k_soft_m2p(const PlanView *V)
+{
+    constexpr int NC = ncoef(P), NQ = ncoef(P + 1), RC = (NC + 63) / 64;
+    __shared__ double a[NQ];
+    __shared__ double cm[NC];
+    __shared__ double res[4][64];
+    const PlanView &v = V[0];
+    const int box = v.leaves[blockIdx.x], lane = threadIdx.x;
+    const int64_t w0 = v.W_off[box], w1 = v.W_off[box + 1];
+    if (w0 == w1) return;
+    double fb[RC];
+    int up[RC][3]; // positions of a + e_k among the degree-(P+1) coefficients
+    int ek[RC][3];
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+        const int c = lane + 64 * r;
+        int n = 0, g[3] = {0, 0, 0};
+        if (c < NC) {
+            while (below(n + 1) <= c) ++n;
+            mono_exps(c, n, g[0], g[1], g[2]);
+        }
+        fb[r] = fact_d(g[0]) * fact_d(g[1]) * fact_d(g[2]);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            int hh[3] = {g[0], g[1], g[2]};
+            hh[d] += 1;
+            up[r][d] = mono_index(hh[0], hh[1], hh[2]);
+            ek[r][d] = g[d] + 1;
+        }
+    }
+    const int f = v.first[box], cnt = v.count[box];
+    for (int s0 = 0; s0 < cnt; s0 += 64) {
+        const int m = cnt - s0 < 64 ? cnt - s0 : 64;
+        for (int k = 0; k < 4; ++k) res[k][lane] = 0.0;
+        for (int64_t e = w0; e < w1; ++e) {
+            const int src = v.W_src[e];
+            double cs[3], hs;
+            soft_box_geom(v, src, cs, hs);
+            const double ih = 1.0 / hs, eta2 = v.eps2 * ih * ih;
+            wave_sync();
+#pragma unroll
+            for (int r = 0; r < RC; ++r)
+                if (lane + 64 * r < NC) cm[lane + 64 * r] = v.M[(int64_t)src * v.ldm + lane + 64 * r] * fb[r];
+            for (int t = 0; t < m; ++t) {
+                const int i = f + s0 + t;
+                const double u[3] = {(v.xs[i] - cs[0]) * ih, (v.ys[i] - cs[1]) * ih, (v.zs[i] - cs[2]) * ih};
+                taylor_shells<P + 1>(u, eta2, a, lane); // (also orders cm's stores before its reads)
+                double ph = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+                for (int r = 0; r < RC; ++r) {
+                    const int c = lane + 64 * r;
+                    if (c >= NC) continue;
+                    const double w = cm[c];
+                    ph += w * a[c];
+                    g0 += w * ek[r][0] * a[up[r][0]];
+                    g1 += w * ek[r][1] * a[up[r][1]];
+                    g2 += w * ek[r][2] * a[up[r][2]];
+                }
+                ph = wave_sum(ph);
+                g0 = wave_sum(g0);
+                g1 = wave_sum(g1);
+                g2 = wave_sum(g2);
+                if (lane == 0) {
+                    res[0][t] += ph * ih;
+                    res[1][t] += g0 * ih * ih;
+                    res[2][t] += g1 * ih * ih;
+                    res[3][t] += g2 * ih * ih;
+                }
+            }
+        }
+        wave_sync();
+        if (lane < m) { // E = -grad phi
+            const int i = f + s0 + lane;
+            v.phi_near[i] += res[0][lane];
+            v.fld_near[3 * (int64_t)i] -= res[1][lane];
+            v.fld_near[3 * (int64_t)i + 1] -= res[2][lane];
+            v.fld_near[3 * (int64_t)i + 2] -= res[3][lane];
+        }
+        wave_sync();
+    }
 }
 
 // ---------------- launchers ----------------
@@ -445,6 +654,22 @@ void launch_soft_l2l(int p, const PlanView *V, int first_child, int nchild, hipS
 {
     if (nchild <= 0) return;
 #define T_(PP) k_soft_l2l<PP><<<nchild, 64, 0, s>>>(V, first_child)
+    SOFT_SWITCH(p, T_)
+#undef T_
+}
+
+void launch_soft_p2l(int p, const PlanView *V, int nxtgt, hipStream_t s)
+{
+    if (nxtgt <= 0) return;
+#define T_(PP) k_soft_p2l<PP><<<nxtgt, 64, 0, s>>>(V)
+    SOFT_SWITCH(p, T_)
+#undef T_
+}
+
+void launch_soft_m2p(int p, const PlanView *V, int nleaves, hipStream_t s)
+{
+    if (nleaves <= 0) return;
+#define T_(PP) k_soft_m2p<PP><<<nleaves, 64, 0, s>>>(V)
     SOFT_SWITCH(p, T_)
 #undef T_
 }

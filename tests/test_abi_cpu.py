@@ -50,11 +50,8 @@ def test_invalid_arguments_rejected_on_host():
     o.max_depth = 22
     assert lib.fmm_plan(fake, 10, 4, 8, ctypes.byref(o), None, None, ctypes.byref(h)) == fmm.FMM_EINVAL
     o.max_depth = 21
-    # softened kernel: uniform trees, FP64, sign-class M2L, order <= 10, eps finite >= 0
+    # softened kernel: FP64, sign-class M2L, order <= 10, eps finite >= 0
     o.kernel, o.softening = 1, 0.01
-    assert lib.fmm_plan(fake, 10, 4, 8, ctypes.byref(o), None, None, ctypes.byref(h)) == fmm.FMM_EINVAL
-    assert b"uniform" in lib.fmm_last_error()
-    o.uniform_depth = 3
     for field, val in (("precision", 3), ("m2l_method", 1), ("softening", -1.0), ("softening", float("inf"))):
         keep = getattr(o, field)
         setattr(o, field, val)
@@ -64,7 +61,7 @@ def test_invalid_arguments_rejected_on_host():
     o.kernel = 2
     assert lib.fmm_plan(fake, 10, 4, 8, ctypes.byref(o), None, None, ctypes.byref(h)) == fmm.FMM_EINVAL
     assert b"kernel" in lib.fmm_last_error()
-    o.kernel, o.softening, o.uniform_depth = 0, 0.0, -1
+    o.kernel, o.softening = 0, 0.0
     bad_root = (ctypes.c_double * 4)(0, 0, 0, -1)
     o.root = ctypes.cast(bad_root, ctypes.POINTER(ctypes.c_double))
     assert lib.fmm_plan(fake, 10, 4, 8, ctypes.byref(o), None, None, ctypes.byref(h)) == fmm.FMM_EINVAL

@@ -2,8 +2,9 @@
 non-oscillatory kernel) against the oracle's softened DA-FMM.
 
 Potentials and fields equal the oracle to relative L2 1e-12 on uniform trees
-of depth 0-4, orders 0-10, eps from 0 to well above the leaf size, ragged and
-clustered point sets and coincident points; the multipole moments and local
+of depth 0-4 and on adaptive trees with W and X lists, orders 0-10, eps from 0
+to well above the leaf size, ragged and clustered point sets and coincident
+points; the multipole moments and local
 Taylor coefficients match coefficient by coefficient; eps = 0 reproduces the
 Coulomb path; at 1e6 points the potentials are checked against the softened
 direct sum on sampled targets."""
@@ -68,6 +69,67 @@ def test_softened_matches_oracle(name, gen, p, depth, eps):
     x, q = gen()
     say("softened", name)
     _check(x, q, p, depth, eps)
+
+
+def soft_kw_adaptive(s, eps):
+    return dict(leaf_size=s, kernel="softened", softening=eps)
+
+
+ADAPTIVE = [
+    ("clusters_4000_s16_p5", lambda: inputs.clusters(4000, 3), 5, 16, 0.01),
+    ("plummer_6000_s32_p7", lambda: inputs.plummer(6000, 2), 7, 32, 0.003),
+    ("plummer_6000_s32_p2_eps0", lambda: inputs.plummer(6000, 2), 2, 32, 0.0),
+    ("gaussian_5000_s50_p8", lambda: inputs.gaussian(5000, 4), 8, 50, 0.05),
+    ("clusters_3000_s8_p10", lambda: inputs.clusters(3000, 9), 10, 8, 0.002),
+    ("ragged_777_s5_p4", lambda: inputs.uniform(777, 5), 4, 5, 0.02),
+]
+
+
+@pytest.mark.parametrize("name,gen,p,leaf,eps", ADAPTIVE, ids=[c[0] for c in ADAPTIVE])
+def test_softened_adaptive_matches_oracle(name, gen, p, leaf, eps):
+    """Adaptive trees: M2L over level-ordered target tiles, P2L (X lists) and
+    M2P (W lists) from the kernel's Taylor coefficients at the particles."""
+    x, q = gen()
+    say("softened adaptive", name)
+    kw = soft_kw_adaptive(leaf, eps)
+    t = oracle_tree(x, **kw)
+    assert t.nV > 0
+    pl, phi, fld = gpu_solve(x, q, p, **kw)
+    ophi, ofld = t.fmm_soft(p, q, eps)
+    e_phi, e_fld = rel_l2(phi, ophi), rel_l2(fld, ofld)
+    say("  W %d X %d: rel L2 vs oracle phi %.3e field %.3e" % (t.nW, t.nX, e_phi, e_fld))
+    assert e_phi <= 1e-12 and e_fld <= 1e-12
+    pl.close()
+
+
+def test_softened_adaptive_has_w_and_x_lists():
+    """The adaptive cases above exercise P2L and M2P (non-empty X and W lists)."""
+    x, q = inputs.clusters(4000, 3)
+    t = oracle_tree(x, leaf_size=16)
+    assert t.nW > 0 and t.nX > 0
+
+
+def test_softened_adaptive_expansions_and_eps0():
+    """Adaptive tree: M and L coefficient by coefficient; at eps = 0 the
+    softened pipeline equals the Coulomb pipeline."""
+    x, q = inputs.plummer(8000, 21)
+    p, eps = 6, 0.004
+    kw = soft_kw_adaptive(24, eps)
+    pl, phi, fld = gpu_solve(x, q, p, **kw)
+    M, L = pl.export_expansions()
+    t = oracle_tree(x, **kw)
+    assert t.nW > 0 and t.nX > 0
+    _, _, oM, oL = t.fmm_soft(p, q, eps, want_expansions=True)
+    deg = oracle.exponents(p).sum(axis=1)
+    for d in range(p + 1):
+        sel = deg == d
+        assert np.abs(M[:, sel] - oM[:, sel]).max() <= 1e-12 * np.abs(oM[:, sel]).max(), ("M", d)
+        assert np.abs(L[:, sel] - oL[:, sel]).max() <= 1e-12 * np.abs(oL[:, sel]).max(), ("L", d)
+    pl.close()
+    _, a, fa = gpu_solve(x, q, p, **soft_kw_adaptive(24, 0.0))
+    _, b, fb = gpu_solve(x, q, p, leaf_size=24)
+    say("  adaptive eps=0 vs Coulomb path: phi %.3e field %.3e" % (rel_l2(a, b), rel_l2(fa, fb)))
+    assert rel_l2(a, b) <= 1e-12 and rel_l2(fa, fb) <= 1e-12
 
 
 @pytest.mark.parametrize("p", [3, 8])
