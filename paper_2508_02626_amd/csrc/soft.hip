@@ -443,171 +443,264 @@ __device__ inline void soft_box_geom(const PlanView &v, int b, double cen[3], do
     for (int k = 0; k < 3; ++k) cen[k] = v.lo[k] + ((double)c[k] + 0.5) * h;
 }
 
-// Taylor coefficients a_g (|g| <= Q) of (|x + z|^2 + eta2)^(-1/2) in z, by the
-// recurrence of the tables, one degree shell after the other across the 64
-// lanes of the (single-wavefront) block, into a[0 .. ncoef(Q)).
-template <int Q>
-__device__ inline void taylor_shells(const double x[3], double eta2, double *a, int lane)
+// ---- Taylor coefficients per lane ----
+// One particle per lane: a_g (|g| <= Q) of (|x + z|^2 + eta^2)^(-1/2) in z by
+// the recurrence above, unrolled at compile time so that every a_g lives in a
+// register (a shell is needed only by the next two), each handed to a
+// consumer as soon as it exists.
+namespace lane_taylor {
+constexpr int cx_ncoef(int n) { return (n + 1) * (n + 2) * (n + 3) / 6; }
+constexpr int cx_below(int n) { return n * (n + 1) * (n + 2) / 6; }
+constexpr int cx_deg(int e)
 {
-    const double rho = x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + eta2;
-    wave_sync(); // the previous use of a is done
-    if (lane == 0) a[0] = 1.0 / sqrt(rho);
-    for (int n = 1; n <= Q; ++n) {
-        wave_sync();
-        for (int e = below(n) + lane; e < below(n + 1); e += 64) {
-            int g[3];
-            mono_exps(e, n, g[0], g[1], g[2]);
-            double s1 = 0.0, s2 = 0.0;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) {
-                if (g[d] >= 1) {
-                    int h[3] = {g[0], g[1], g[2]};
-                    h[d] -= 1;
-                    s1 += x[d] * a[mono_index(h[0], h[1], h[2])];
-                }
-                if (g[d] >= 2) {
-                    int h[3] = {g[0], g[1], g[2]};
-                    h[d] -= 2;
-                    s2 += a[mono_index(h[0], h[1], h[2])];
-                }
-            }
-            a[e] = -((2 * n - 1) * s1 + (n - 1) * s2) / (n * rho);
-        }
-    }
-    wave_sync();
+    int n = 0;
+    while (cx_ncoef(n) <= e) ++n;
+    return n;
 }
+constexpr int cx_jk(int e) // j + k of the monomial at DA index e
+{
+    const int r = e - cx_below(cx_deg(e));
+    int a = 0;
+    while ((a + 1) * (a + 2) / 2 <= r) ++a;
+    return a;
+}
+constexpr int cx_k(int e) { return e - cx_below(cx_deg(e)) - cx_jk(e) * (cx_jk(e) + 1) / 2; }
+constexpr int cx_j(int e) { return cx_jk(e) - cx_k(e); }
+constexpr int cx_i(int e) { return cx_deg(e) - cx_jk(e); }
+constexpr int cx_index(int i, int j, int k) { return cx_below(i + j + k) + (j + k) * (j + k + 1) / 2 + k; }
+constexpr double cx_fact(int n) { return n <= 1 ? 1.0 : n * cx_fact(n - 1); }
+constexpr double cx_gfact(int e) { return cx_fact(cx_i(e)) * cx_fact(cx_j(e)) * cx_fact(cx_k(e)); }
 
-__device__ inline double wave_sum(double x)
+// per-shell multipliers: a_g = sum_d w_d a_(g - e_d) + z sum_d a_(g - 2e_d),
+// w_d = -(2n - 1) x_d / (n rho), z = -(n - 1) / (n rho)
+struct Shell {
+    double w0, w1, w2, z;
+};
+
+template <int E, int NQ> struct Run {
+    template <class F>
+    static __device__ __forceinline__ void go(double *a, Shell &sh, const double x[3], double ir, F &f)
+    {
+        constexpr int n = cx_deg(E), i = cx_i(E), j = cx_j(E), k = cx_k(E);
+        if constexpr (E == cx_below(n)) {
+            const double c1 = -(2.0 * n - 1.0) / n * ir;
+            sh.w0 = c1 * x[0];
+            sh.w1 = c1 * x[1];
+            sh.w2 = c1 * x[2];
+            sh.z = -(n - 1.0) / n * ir;
+        }
+        double s1 = 0.0, s2 = 0.0;
+        if constexpr (i >= 1) s1 = sh.w0 * a[cx_index(i - 1, j, k)];
+        if constexpr (j >= 1) s1 = fma(sh.w1, a[cx_index(i, j - 1, k)], s1);
+        if constexpr (k >= 1) s1 = fma(sh.w2, a[cx_index(i, j, k - 1)], s1);
+        if constexpr (i >= 2) s2 = a[cx_index(i - 2, j, k)];
+        if constexpr (j >= 2) s2 += a[cx_index(i, j - 2, k)];
+        if constexpr (k >= 2) s2 += a[cx_index(i, j, k - 2)];
+        if constexpr (n >= 2)
+            a[E] = fma(sh.z, s2, s1);
+        else
+            a[E] = s1;
+        f.template on<E>(a[E]);
+        // keep the scheduler from hoisting every consumer load to the top
+        if constexpr (E % 16 == 15) __builtin_amdgcn_sched_barrier(0);
+        Run<E + 1, NQ>::go(a, sh, x, ir, f);
+    }
+};
+template <int NQ> struct Run<NQ, NQ> {
+    template <class F> static __device__ __forceinline__ void go(double *, Shell &, const double *, double, F &) {}
+};
+
+// a_g(x) for |g| <= Q into the consumer f (f.on<E>(a_E) in DA order)
+template <int Q, class F> __device__ __forceinline__ void taylor(const double x[3], double eta2, F &f)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
-    return x;
+    constexpr int NQ = cx_ncoef(Q);
+    double a[NQ];
+    const double rho = x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + eta2;
+    const double ir = 1.0 / rho;
+    a[0] = 1.0 / sqrt(rho);
+    f.template on<0>(a[0]);
+    Shell sh;
+    Run<1, NQ>::go(a, sh, x, ir, f);
 }
+} // namespace lane_taylor
 
 // P2L: Lhat_b(B) += q b! a_b((c_B - x_j) / h_B; eta = eps / h_B) for every
-// particle j of the boxes of B's X list; one wavefront per X target, lanes
-// over the coefficients, particles one after the other.
+// particle j of the boxes of B's X list.  One wavefront per X target; the
+// source particles of the list, 64 at a time, one per lane; the sums over the
+// lanes run through an LDS transpose, 32 coefficients at a time, as the
+// coefficients are produced (lane r < 32 keeps coefficient 32 G + r of group G).
+namespace p2l_detail {
+template <int P> struct Acc {
+    static constexpr int NC = ncoef(P), NG = (NC + 31) / 32;
+    double (*T)[65];
+    double q, acc[NG];
+    int lane;
+    template <int E> __device__ __forceinline__ void on(double v)
+    {
+        T[E % 32][lane] = q * v;
+        if constexpr (E % 32 == 31 || E == NC - 1) {
+            constexpr int rows = E % 32 + 1;
+            wave_sync();
+            const int r = lane & 31, c0 = (lane >> 5) * 32;
+            double s = 0.0;
+            if (r < rows) {
+#pragma unroll 8
+                for (int c = 0; c < 32; ++c) s += T[r][c0 + c];
+            }
+            s += __shfl_xor(s, 32);
+            acc[E / 32] += s;
+            wave_sync();
+        }
+    }
+};
+} // namespace p2l_detail
+
 template <int P>
 __global__ __launch_bounds__(64) void k_soft_p2l(const PlanView *V)
 {
-    constexpr int NC = ncoef(P), RC = (NC + 63) / 64;
-    __shared__ double a[NC];
+    using A = p2l_detail::Acc<P>;
+    constexpr int NC = A::NC, NG = A::NG;
+    __shared__ double T[32][65];
+    __shared__ int pre[65], pf[64];
     const PlanView &v = V[0];
     const int box = v.xtgt[blockIdx.x], lane = threadIdx.x;
     double cen[3], h;
     soft_box_geom(v, box, cen, h);
     const double ih = 1.0 / h, eta2 = v.eps2 * ih * ih;
-    double fb[RC], acc[RC];
+    A acc;
+    acc.T = T;
+    acc.lane = lane;
 #pragma unroll
-    for (int r = 0; r < RC; ++r) {
-        const int c = lane + 64 * r;
-        int n = 0, i = 0, j = 0, k = 0;
-        if (c < NC) {
-            while (below(n + 1) <= c) ++n;
-            mono_exps(c, n, i, j, k);
+    for (int g = 0; g < NG; ++g) acc.acc[g] = 0.0;
+    const int64_t x0 = v.X_off[box], x1 = v.X_off[box + 1];
+    for (int64_t xb = x0; xb < x1; xb += 64) {
+        // the next 64 entries of the list: exclusive prefix of their counts
+        const int ne = x1 - xb < 64 ? (int)(x1 - xb) : 64;
+        int c = 0, f = 0;
+        if (lane < ne) {
+            const int src = v.X_src[xb + lane];
+            c = v.count[src];
+            f = v.first[src];
         }
-        fb[r] = fact_d(i) * fact_d(j) * fact_d(k);
-        acc[r] = 0.0;
-    }
-    for (int64_t e = v.X_off[box]; e < v.X_off[box + 1]; ++e) {
-        const int s = v.X_src[e], f = v.first[s], cnt = v.count[s];
-        for (int i = f; i < f + cnt; ++i) {
+        int incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        wave_sync();
+        pre[lane + 1] = incl;
+        pf[lane] = f;
+        if (lane == 0) pre[0] = 0;
+        wave_sync();
+        const int total = pre[ne];
+        for (int t0 = 0; t0 < total; t0 += 64) {
+            const int t = t0 + lane < total ? t0 + lane : total - 1;
+            int lo = 0, hi = ne - 1; // the entry s with pre[s] <= t < pre[s + 1]
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= t) lo = mid; else hi = mid - 1;
+            }
+            const int i = pf[lo] + (t - pre[lo]);
             const double x[3] = {(cen[0] - v.xs[i]) * ih, (cen[1] - v.ys[i]) * ih, (cen[2] - v.zs[i]) * ih};
-            const double q = v.qs[i];
-            taylor_shells<P>(x, eta2, a, lane);
+            acc.q = t0 + lane < total ? v.qs[i] : 0.0;
+            lane_taylor::taylor<P>(x, eta2, acc);
+        }
+        wave_sync(); // pre and pf are rewritten for the next piece
+    }
+    if (lane < 32) {
+        double *L = v.L + (int64_t)box * v.ldm;
 #pragma unroll
-            for (int r = 0; r < RC; ++r)
-                if (lane + 64 * r < NC) acc[r] += q * fb[r] * a[lane + 64 * r];
+        for (int g = 0; g < NG; ++g) {
+            const int e = 32 * g + lane;
+            if (e < NC) {
+                int n = 0, i, j, k;
+                while (below(n + 1) <= e) ++n;
+                mono_exps(e, n, i, j, k);
+                L[e] += acc.acc[g] * (fact_d(i) * fact_d(j) * fact_d(k));
+            }
         }
     }
-#pragma unroll
-    for (int r = 0; r < RC; ++r)
-        if (lane + 64 * r < NC) v.L[(int64_t)box * v.ldm + lane + 64 * r] += acc[r];
 }
 
 // M2P: phi(x) += (1/h) sum_a Mhat_a a! a_a(u), u = (x - c_C)/h_C, eta = eps/h_C,
-// and its gradient (1/h^2) sum_a Mhat_a a! (a_k + 1) a_(a+e_k)(u), for every
+// and its gradient (1/h^2) sum_g g! a_g(u) sum_k e_k Mhat_(g - e_k), for every
 // box C of the leaf's W list, added to the near-field sums (after P2P).  One
-// wavefront per leaf, lanes over the coefficients, particles one after the
-// other in chunks of 64 (their sums in LDS).
+// wavefront per leaf, one particle per lane (64 at a time); the moments of the
+// W box are read from LDS (the same address on every lane), the next box's
+// prefetched into registers meanwhile.
+namespace m2p_detail {
+template <int P> struct Acc {
+    const double *m; // Mhat of the W box, m[NC] = 0
+    double ph, g0, g1, g2;
+    template <int E> __device__ __forceinline__ void on(double v)
+    {
+        using namespace lane_taylor;
+        constexpr int n = cx_deg(E), i = cx_i(E), j = cx_j(E), k = cx_k(E);
+        const double b = v * cx_gfact(E);
+        if constexpr (n <= P) ph = fma(m[E], b, ph);
+        if constexpr (i >= 1) g0 = fma(m[cx_index(i - 1, j, k)], b, g0);
+        if constexpr (j >= 1) g1 = fma(m[cx_index(i, j - 1, k)], b, g1);
+        if constexpr (k >= 1) g2 = fma(m[cx_index(i, j, k - 1)], b, g2);
+    }
+};
+} // namespace m2p_detail
+
 template <int P>
 __global__ __launch_bounds__(64) void k_soft_m2p(const PlanView *V)
 {
-    constexpr int NC = ncoef(P), NQ = ncoef(P + 1), RC = (NC + 63) / 64;
-    __shared__ double a[NQ];
-    __shared__ double cm[NC];
-    __shared__ double res[4][64];
+    constexpr int NC = ncoef(P), RC = (NC + 63) / 64;
+    __shared__ double cm[2][NC];
     const PlanView &v = V[0];
     const int box = v.leaves[blockIdx.x], lane = threadIdx.x;
     const int64_t w0 = v.W_off[box], w1 = v.W_off[box + 1];
     if (w0 == w1) return;
-    double fb[RC];
-    int up[RC][3]; // positions of a + e_k among the degree-(P+1) coefficients
-    int ek[RC][3];
-#pragma unroll
-    for (int r = 0; r < RC; ++r) {
-        const int c = lane + 64 * r;
-        int n = 0, g[3] = {0, 0, 0};
-        if (c < NC) {
-            while (below(n + 1) <= c) ++n;
-            mono_exps(c, n, g[0], g[1], g[2]);
-        }
-        fb[r] = fact_d(g[0]) * fact_d(g[1]) * fact_d(g[2]);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            int hh[3] = {g[0], g[1], g[2]};
-            hh[d] += 1;
-            up[r][d] = mono_index(hh[0], hh[1], hh[2]);
-            ek[r][d] = g[d] + 1;
-        }
-    }
     const int f = v.first[box], cnt = v.count[box];
     for (int s0 = 0; s0 < cnt; s0 += 64) {
-        const int m = cnt - s0 < 64 ? cnt - s0 : 64;
-        for (int k = 0; k < 4; ++k) res[k][lane] = 0.0;
+        const bool act = s0 + lane < cnt;
+        const int i = act ? f + s0 + lane : f;
+        const double px = v.xs[i], py = v.ys[i], pz = v.zs[i];
+        double phi = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+        // W entries 64 at a time, lane l holding entry wb + l
+        int64_t wb = w0;
+        int wl = wb + lane < w1 ? v.W_src[wb + lane] : 0;
+        double nxt[RC];
+        auto fetch = [&](int64_t e) {
+            if (e - wb >= 64) {
+                wb += 64;
+                wl = wb + lane < w1 ? v.W_src[wb + lane] : 0;
+            }
+            const int src = __builtin_amdgcn_readlane(wl, (int)(e - wb));
+            const double *Ms = v.M + (int64_t)src * v.ldm;
+#pragma unroll
+            for (int r = 0; r < RC; ++r) nxt[r] = lane + 64 * r < NC ? Ms[lane + 64 * r] : 0.0;
+            return src;
+        };
+        int src = fetch(w0);
         for (int64_t e = w0; e < w1; ++e) {
-            const int src = v.W_src[e];
-            double cs[3], hs;
-            soft_box_geom(v, src, cs, hs);
-            const double ih = 1.0 / hs, eta2 = v.eps2 * ih * ih;
-            wave_sync();
+            const int buf = (int)((e - w0) & 1);
 #pragma unroll
             for (int r = 0; r < RC; ++r)
-                if (lane + 64 * r < NC) cm[lane + 64 * r] = v.M[(int64_t)src * v.ldm + lane + 64 * r] * fb[r];
-            for (int t = 0; t < m; ++t) {
-                const int i = f + s0 + t;
-                const double u[3] = {(v.xs[i] - cs[0]) * ih, (v.ys[i] - cs[1]) * ih, (v.zs[i] - cs[2]) * ih};
-                taylor_shells<P + 1>(u, eta2, a, lane); // (also orders cm's stores before its reads)
-                double ph = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
-#pragma unroll
-                for (int r = 0; r < RC; ++r) {
-                    const int c = lane + 64 * r;
-                    if (c >= NC) continue;
-                    const double w = cm[c];
-                    ph += w * a[c];
-                    g0 += w * ek[r][0] * a[up[r][0]];
-                    g1 += w * ek[r][1] * a[up[r][1]];
-                    g2 += w * ek[r][2] * a[up[r][2]];
-                }
-                ph = wave_sum(ph);
-                g0 = wave_sum(g0);
-                g1 = wave_sum(g1);
-                g2 = wave_sum(g2);
-                if (lane == 0) {
-                    res[0][t] += ph * ih;
-                    res[1][t] += g0 * ih * ih;
-                    res[2][t] += g1 * ih * ih;
-                    res[3][t] += g2 * ih * ih;
-                }
-            }
+                if (lane + 64 * r < NC) cm[buf][lane + 64 * r] = nxt[r];
+            wave_sync();
+            double cs[3], hs;
+            soft_box_geom(v, src, cs, hs);
+            if (e + 1 < w1) src = fetch(e + 1);
+            const double ih = 1.0 / hs, eta2 = v.eps2 * ih * ih;
+            const double u[3] = {(px - cs[0]) * ih, (py - cs[1]) * ih, (pz - cs[2]) * ih};
+            m2p_detail::Acc<P> acc{cm[buf], 0.0, 0.0, 0.0, 0.0};
+            lane_taylor::taylor<P + 1>(u, eta2, acc);
+            phi = fma(acc.ph, ih, phi);
+            const double ih2 = ih * ih;
+            gx = fma(acc.g0, ih2, gx);
+            gy = fma(acc.g1, ih2, gy);
+            gz = fma(acc.g2, ih2, gz);
         }
-        wave_sync();
-        if (lane < m) { // E = -grad phi
-            const int i = f + s0 + lane;
-            v.phi_near[i] += res[0][lane];
-            v.fld_near[3 * (int64_t)i] -= res[1][lane];
-            v.fld_near[3 * (int64_t)i + 1] -= res[2][lane];
-            v.fld_near[3 * (int64_t)i + 2] -= res[3][lane];
+        if (act) { // E = -grad phi
+            v.phi_near[i] += phi;
+            v.fld_near[3 * (int64_t)i] -= gx;
+            v.fld_near[3 * (int64_t)i + 1] -= gy;
+            v.fld_near[3 * (int64_t)i + 2] -= gz;
         }
         wave_sync();
     }
