@@ -432,6 +432,10 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     // the sign-class M2L addresses the folded multipoles with 32-bit byte offsets
     if (!soft && m2l_sym(P->p) && (unsigned long long)(nb + 1) * (unsigned long long)P->ldmh * 8ULL >= (1ULL << 32))
         return fail(FMM_EUNSUPPORTED, "too many boxes for this order (folded multipoles reach 4 GiB)");
+    // (and the softened kernel's class-ordered moments)
+    const int ldms = soft && P->p >= kSoftSymOrder ? soft_sym_ld(P->p) : 0;
+    if ((unsigned long long)(nb + 1) * (unsigned long long)ldms * 8ULL >= (1ULL << 32))
+        return fail(FMM_EUNSUPPORTED, "too many boxes for this order (class-ordered moments reach 4 GiB)");
     // ---- phase B: boxes, list counts, work lists (sizes known from nb)
     {
         Sizer o;
@@ -443,6 +447,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
          .add<double>((size_t)nb * P->ldm).add<double>((size_t)nb * P->ldm);
         if (soft) {
             o.add<int>(soft_table_ldc(P->p)).add<double>(P->ldm);
+            if (ldms) o.add<double>((size_t)(nb + 1) * ldms);
         } else {
             o.add<double>((size_t)(nb + 1) * P->ldmh).add<double>((size_t)nb * P->ldh);
             if (P->m2l_parts > 1) o.add<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh);
@@ -487,6 +492,10 @@ int build_plan(fmm_plan_s *P, const double *xyz)
         soft_map = P->own<int>(soft_table_ldc(P->p));
         zrow = P->own<double>(P->ldm);
         NOMEM(soft_map); NOMEM(zrow);
+        if (ldms) { // class-ordered moments of the sign-class M2L (in the folded multipoles' place)
+            Mh = P->own<double>((size_t)(nb + 1) * ldms);
+            NOMEM(Mh);
+        }
     } else {
         NOMEM(Mh); NOMEM(Lh);
     }
@@ -1106,7 +1115,7 @@ int run_soft(fmm_plan_s *P, hipStream_t s)
             G.adaptive = 1;
             G.nblocks = P->nslots / kM2LSlots;
         }
-        launch_m2l_soft(P->p, V, G, s);
+        launch_m2l_soft(P->p, V, G, P->view.Mh, P->nboxes, s);
     }
     T.end();
     if (p2p_part(1)) return FMM_EDEVICE;
@@ -1263,6 +1272,8 @@ extern "C" int fmm_plan_estimate(int64_t n, int32_t order, int32_t leaf_size, co
     const int depth = o.uniform_depth >= 0 ? o.uniform_depth : o.max_depth;
     if (o.kernel == FMM_KERNEL_SOFTENED && depth >= 2 && order <= kSoftMaxOrder)
         total += 8.0 * (depth - 1) * 343 * soft_table_ldc(order); // derivative tables per level (at most)
+    if (o.kernel == FMM_KERNEL_SOFTENED && order >= kSoftSymOrder && order <= kSoftMaxOrder)
+        total += boxes * 8.0 * (soft_sym_ld(order) - ldmh); // class-ordered moments instead of folded ones
     *bytes = (size_t)(total * 1.25);
     return FMM_OK;
 }

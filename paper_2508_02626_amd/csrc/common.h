@@ -181,6 +181,25 @@ __device__ inline void wave_sync()
 }
 __device__ inline uint64_t lanes_below(int lane) { return (1ull << lane) - 1ull; }
 
+// Walsh-Hadamard transform of the 8 members of a sign class of M2L offsets,
+// h[s] <- sum_m (-1)^|m & s| h[m] (bit 2, 1, 0 of m: the member negates x, y,
+// z).  For a class with zero axes Z: members that negate a zero axis
+// do not exist, and only outputs r with r & Z == 0 are used, so the butterflies
+// run over the other axes on the entries with no bit of Z (h[m], m & Z != 0,
+// is neither read nor written).
+template <int Z, typename T> __device__ inline void wht8z(T (&h)[8])
+{
+#pragma unroll
+    for (int bit = 1; bit < 8; bit <<= 1)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (!(bit & Z) && !(i & bit) && !(i & Z)) {
+                const T u = h[i], w = h[i | bit];
+                h[i] = u + w;
+                h[i | bit] = u - w;
+            }
+}
+
 // Global address-space views of device pointers.  Loads and stores through
 // them compile to global_* instructions, counted by the vector-memory counter
 // only; the generic (flat_*) form also counts against the LDS counter, so an

@@ -410,23 +410,6 @@ __device__ inline void sym_select_classes(unsigned long long used, const int *re
     }
 }
 
-// The transform of a class with zero axes Z: members that negate a zero axis
-// do not exist, and only outputs r with r & Z == 0 are used, so the butterflies
-// run over the other axes on the entries with no bit of Z (h[m], m & Z != 0,
-// is neither read nor written).
-template <int Z, typename T> __device__ inline void wht8z(T (&h)[8])
-{
-#pragma unroll
-    for (int bit = 1; bit < 8; bit <<= 1)
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-            if (!(bit & Z) && !(i & bit) && !(i & Z)) {
-                const T u = h[i], w = h[i | bit];
-                h[i] = u + w;
-                h[i | bit] = u - w;
-            }
-}
-
 // Block set-up shared by the sign-class kernels.  The loads are issued in
 // batches (row and column indices, then their D addresses and the octant), so
 // that the set-up costs a few memory round trips rather than one per entry.

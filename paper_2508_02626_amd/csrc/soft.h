@@ -17,7 +17,12 @@ void launch_soft_tables(int p, int nlev, double *D, int *map, double W, double e
 void launch_soft_p2m(int p, const PlanView *V, int nleaves, int ldm, hipStream_t s);
 void launch_soft_m2m(int p, const PlanView *V, int first_box, int nbox, hipStream_t s);
 void launch_soft_l2l(int p, const PlanView *V, int first_child, int nchild, hipStream_t s);
-void launch_m2l_soft(int p, const PlanView *V, const SoftGrid &G, hipStream_t s);
+// orders from kSoftSymOrder on: sign-class M2L over the moments copied into
+// the class order (Ms: (nboxes + 1) rows of soft_sym_ld(p) doubles); below it
+// one contraction per offset
+constexpr int kSoftSymOrder = 4;
+int soft_sym_ld(int p);
+void launch_m2l_soft(int p, const PlanView *V, const SoftGrid &G, double *Ms, int nboxes, hipStream_t s);
 void launch_soft_p2l(int p, const PlanView *V, int nxtgt, hipStream_t s);   // 1 X target/block
 void launch_soft_m2p(int p, const PlanView *V, int nleaves, hipStream_t s); // 1 leaf/block (W lists)
 } // namespace fmm

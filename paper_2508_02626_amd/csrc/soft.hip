@@ -241,6 +241,51 @@ __global__ __launch_bounds__(64) void k_soft_l2l(const PlanView *V, int first_ch
     }
 }
 
+// dense-cube LDS address of the monomial with packed exponents x (i | j << 8 | k << 16)
+template <int S> __device__ inline int soft_cube_addr(int x) { return ((x & 255) * S + ((x >> 8) & 255)) * S + (x >> 16); }
+
+// The 64 targets of M2L block blockIdx.x (-1 for an empty place): in a uniform
+// tree boxes 8 (64 t + i) + o of one level (block -> level, octant, tile, each
+// XCD taking a contiguous range); in an adaptive tree the plan's target tile.
+__device__ inline void soft_tile_targets(const PlanView &v, const SoftGrid &G, int tid, int *sTg)
+{
+    if (G.adaptive) {
+        const int tile = xcd_remap(blockIdx.x, G.nblocks);
+        if (tid < 64) sTg[tid] = v.m2l_tgt[(int64_t)tile * kM2LSlots + tid];
+    } else {
+        int item = xcd_remap(blockIdx.x, G.nblocks), li = 0;
+        while (li + 1 < G.nlev && item >= G.start[li + 1]) ++li;
+        item -= G.start[li];
+        const int lev = li + 2, per = G.tiles[li], o = item / per, t = item - o * per;
+        const int64_t cells = 1ll << (3 * (lev - 1)); // boxes of one octant at this level
+        if (tid < 64) {
+            const int64_t m = (int64_t)t * 64 + tid;
+            sTg[tid] = m < cells ? G.lvl_first[li] + (int)(8 * m + o) : -1;
+        }
+    }
+}
+
+// Levels of the targets (sLv, -1 for empty places) and, in info, their level
+// range and octant (info[1] < 0: no target).  sTg must be visible to the block.
+__device__ inline void soft_tile_levels(const PlanView &v, int tid, const int *sTg, int *sLv, int *info)
+{
+    if (tid < 64) sLv[tid] = sTg[tid] >= 0 ? v.level[sTg[tid]] : -1;
+    __syncthreads();
+    if (tid == 0) {
+        int lo = 1 << 30, hi = -1, oc = 0;
+        for (int q = 0; q < 64; ++q)
+            if (sTg[q] >= 0) {
+                lo = min(lo, sLv[q]);
+                hi = max(hi, sLv[q]);
+                oc = (int)(v.morton[sTg[q]] & 7);
+            }
+        info[0] = lo;
+        info[1] = hi;
+        info[2] = oc;
+    }
+    __syncthreads();
+}
+
 // ---------------- M2L on the full components (FP64 MFMA) ----------------
 // Per used offset slot each wavefront runs an n_p x n_p by 16 product with
 // 16x16x4 MFMAs, as the slot-by-slot Coulomb M2L: A[b][a] = D(addr(b) +
@@ -272,65 +317,27 @@ __global__ __launch_bounds__(256) void k_m2l_soft(const PlanView *V, SoftGrid G)
     __shared__ int sHo[4][KS];
     __shared__ int sTg[64], sLv[64];
     __shared__ int sList[kVSlots];
-    __shared__ int sN, sOct, sLmin, sLmax;
+    __shared__ int sN, sInfo[3];
     const PlanView &v = V[0];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
     const OrderTables &tb = *v.tab;
-    if (G.adaptive) {
-        const int tile = xcd_remap(blockIdx.x, G.nblocks);
-        if (tid < 64) sTg[tid] = v.m2l_tgt[(int64_t)tile * kM2LSlots + tid];
-    } else {
-        // block -> (level, octant, tile), each XCD taking a contiguous range
-        int item = xcd_remap(blockIdx.x, G.nblocks), li = 0;
-        while (li + 1 < G.nlev && item >= G.start[li + 1]) ++li;
-        item -= G.start[li];
-        const int lev = li + 2, per = G.tiles[li], o = item / per, t = item - o * per;
-        const int64_t cells = 1ll << (3 * (lev - 1)); // boxes of one octant at this level
-        if (tid < 64) {
-            const int64_t m = (int64_t)t * 64 + tid;
-            sTg[tid] = m < cells ? G.lvl_first[li] + (int)(8 * m + o) : -1;
-        }
-    }
+    soft_tile_targets(v, G, tid, sTg);
     for (int e = tid; e < 4 * KS; e += 256) {
         const int g = e / KS, ks = e - g * KS, a = 8 * (ks / 2) + 2 * g + (ks & 1);
-        int addr = 0;
-        if (a < NP) {
-            const int x = gptr(tb.exps)[a];
-            addr = ((x & 255) * S + ((x >> 8) & 255)) * S + (x >> 16);
-        }
-        sHo[g][ks] = addr;
+        sHo[g][ks] = a < NP ? soft_cube_addr<S>(gptr(tb.exps)[a]) : 0;
     }
     int hb[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int b = 16 * mt + col;
-        int addr = 0;
-        if (b < NP) {
-            const int x = gptr(tb.exps)[b];
-            addr = ((x & 255) * S + ((x >> 8) & 255)) * S + (x >> 16);
-        }
-        hb[mt] = addr;
+        hb[mt] = b < NP ? soft_cube_addr<S>(gptr(tb.exps)[b]) : 0;
     }
     __syncthreads();
-    if (tid < 64) sLv[tid] = sTg[tid] >= 0 ? v.level[sTg[tid]] : -1;
-    __syncthreads();
-    if (tid == 0) { // level range and octant of the block's targets
-        int lo = 1 << 30, hi = -1, oc = 0;
-        for (int q = 0; q < 64; ++q)
-            if (sTg[q] >= 0) {
-                lo = min(lo, sLv[q]);
-                hi = max(hi, sLv[q]);
-                oc = (int)(v.morton[sTg[q]] & 7);
-            }
-        sLmin = lo;
-        sLmax = hi;
-        sOct = oc;
-    }
-    __syncthreads();
-    const int lmin = sLmin, lmax = sLmax;
+    soft_tile_levels(v, tid, sTg, sLv, sInfo);
+    const int lmin = sInfo[0], lmax = sInfo[1], oct = sInfo[2];
     if (lmax < 0) return; // (block-uniform)
     const auto vs = gptr(v.vslot);
-    const auto offs = gptr(tb.offs) + sOct * kVSlots;
+    const auto offs = gptr(tb.offs) + oct * kVSlots;
     const int tgt = sTg[wave * 16 + col], tlev = sLv[wave * 16 + col];
     typedef double dvec_t __attribute__((ext_vector_type(2)));
     dvec_t pd[DV];
@@ -431,6 +438,322 @@ __global__ __launch_bounds__(256) void k_m2l_soft(const PlanView *V, SoftGrid G)
             const int b = 16 * mt + 4 * r + kq;
             if (b < NP) L[b] = acc[mt][r];
         }
+}
+
+// ---------------- sign-class M2L (orders >= kSoftSymOrder) ----------------
+// K_eta is even in every coordinate, so d^g K_eta(s o k) = s^g d^g K_eta(k)
+// for a vector s of signs: the offsets that differ from a representative k
+// only by signs (the members of its class) share k's table.  With rows b and
+// columns a grouped by the parities pi(g) of their exponents (3 bits: x, y, z),
+//   Lhat_b = sum_a D_(a+b)(k) H_(pi(a) ^ pi(b))[a],
+//   H_s[a] = sum_m (-1)^|m & s| Mhat_a(source of member m),
+// the Walsh-Hadamard transform over the members (m: the axes a member
+// negates): one contraction per class instead of one per member.  Where k is
+// zero on an axis the class has no member negating it and the derivatives odd
+// in it vanish (those products are skipped).  The class tables are the
+// Coulomb sign-class ones (56 classes per octant).
+//
+// Layout: each parity class is padded to whole 16-row tiles (rows) and 4-index
+// k-steps (columns); the moments are copied into that column order (k_soft_msort,
+// a row per box and an all-zero row after them), k-steps 2j, 2j + 1 of lane
+// group g at 8 j + 2 g + {0, 1}, so a lane reads two k-steps with one 16-byte load.
+template <int P> struct SoftSym {
+    static constexpr int csize(int c)
+    {
+        int n = 0;
+        for (int i = 0; i <= P; ++i)
+            for (int j = 0; i + j <= P; ++j)
+                for (int k = 0; i + j + k <= P; ++k) n += ((i & 1) << 2 | (j & 1) << 1 | (k & 1)) == c;
+        return n;
+    }
+    static constexpr int sum_tiles(int q)
+    {
+        int t = 0;
+        for (int c = 0; c < 8; ++c) t += (csize(c) + q - 1) / q;
+        return t;
+    }
+    static constexpr int NP = ncoef(P), MT = sum_tiles(16), KS = sum_tiles(4), KSV = (KS + 1) / 2, LDMS = 8 * KSV;
+    static constexpr int CMAX = csize(0); // the all-even class is the largest
+    int csz[8] = {}, rc[MT] = {}, kc[KS] = {}, rfirst[9] = {}, kfirst[9] = {};
+    constexpr SoftSym()
+    {
+        int t = 0, u = 0;
+        for (int c = 0; c < 8; ++c) {
+            csz[c] = csize(c);
+            rfirst[c] = t;
+            kfirst[c] = u;
+            for (int q = 0; q < (csz[c] + 15) / 16; ++q) rc[t++] = c;
+            for (int q = 0; q < (csz[c] + 3) / 4; ++q) kc[u++] = c;
+        }
+        rfirst[8] = t;
+        kfirst[8] = u;
+    }
+};
+int soft_sym_ld(int p)
+{
+    switch (p) {
+    case 4: return SoftSym<4>::LDMS; case 5: return SoftSym<5>::LDMS; case 6: return SoftSym<6>::LDMS;
+    case 7: return SoftSym<7>::LDMS; case 8: return SoftSym<8>::LDMS; case 9: return SoftSym<9>::LDMS;
+    case 10: return SoftSym<10>::LDMS;
+    default: return 0;
+    }
+}
+
+// pos[c][t]: DA index of the t-th monomial (in DA order) of parity class c
+template <int P, int CMAX, typename IP> __device__ inline void soft_class_positions(IP exps, int tid, int nt, int (*pos)[CMAX])
+{
+    auto cls = [](int x) { return (x & 1) << 2 | ((x >> 8) & 1) << 1 | ((x >> 16) & 1); };
+    for (int e = tid; e < ncoef(P); e += nt) {
+        const int c = cls(exps[e]);
+        int r = 0;
+        for (int f = 0; f < e; ++f) r += cls(exps[f]) == c;
+        pos[c][r] = e;
+    }
+}
+
+// the moments in the sign-class column order; row nrows - 1 is all zero
+template <int P>
+__global__ __launch_bounds__(256) void k_soft_msort(const PlanView *V, double *Ms, int nrows)
+{
+    using SS = SoftSym<P>;
+    static constexpr SS S{};
+    constexpr int LDMS = SS::LDMS;
+    __shared__ int sPos[8][SS::CMAX];
+    __shared__ int sCol[LDMS];
+    const PlanView &v = V[0];
+    const int tid = threadIdx.x;
+    soft_class_positions<P, SS::CMAX>(gptr(v.tab->exps), tid, 256, sPos);
+    __syncthreads();
+    for (int q = tid; q < LDMS; q += 256) {
+        const int ks = 2 * (q / 8) + (q & 1), g = (q & 7) >> 1;
+        int a = -1;
+        if (ks < SS::KS) {
+            const int c = S.kc[ks], t = 4 * (ks - S.kfirst[c]) + g;
+            if (t < S.csz[c]) a = sPos[c][t];
+        }
+        sCol[q] = a;
+    }
+    __syncthreads();
+    const int64_t total = (int64_t)nrows * LDMS, ldm = v.ldm;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + tid; e < total; e += (int64_t)gridDim.x * 256) {
+        const int64_t row = e / LDMS;
+        const int a = sCol[e - row * LDMS];
+        Ms[e] = row < nrows - 1 && a >= 0 ? v.M[row * ldm + a] : 0.0;
+    }
+}
+
+// One block of 4 wavefronts per target tile (as k_m2l_soft), each wavefront
+// 16 targets with all row tiles; per level the classes used by the level's
+// targets, one after the other (in zero-mask order, so Z is a compile-time
+// constant of the loop that runs them): the representative's table staged in
+// LDS as the dense cube (double-buffered), per k-step the 8 members' operands
+// (one 16-byte vector of two k-steps per member, one vector ahead), their
+// transform, then one MFMA per compatible row tile with the output of the
+// transform that the row and column parities select.
+template <int P>
+__global__ __launch_bounds__(256) void k_m2l_soft_sym(const PlanView *V, SoftGrid G)
+{
+    using SS = SoftSym<P>;
+    static constexpr SS S{};
+    constexpr int MT = SS::MT, KS = SS::KS, KSV = SS::KSV, LDMS = SS::LDMS, CMAX = SS::CMAX;
+    constexpr int SC = 2 * P + 1, LDD = SC * SC * SC + 1, LDC = (ncoef(2 * P) + 1) & ~1;
+    constexpr int DV = (LDC / 2 + 255) / 256;
+    static_assert(8 * CMAX * sizeof(int) <= LDD * sizeof(double), "class positions fit in a table buffer");
+    typedef double dvec_t __attribute__((ext_vector_type(2)));
+    __shared__ double sD[2][LDD];
+    __shared__ int sHo[4][KS];
+    __shared__ int sTg[64], sLv[64];
+    __shared__ int sRep[kSymClasses];
+    __shared__ unsigned char sMem[kSymClasses][8]; // member slots (255: none)
+    __shared__ unsigned char sSl[kVSlots];         // class of each V slot
+    __shared__ unsigned char sList[kSymClasses];
+    __shared__ int sZend[8];
+    __shared__ unsigned long long sUsed;
+    __shared__ int sN, sInfo[3];
+    int(*sPos)[CMAX] = (int(*)[CMAX]) & sD[1][0]; // (set-up and output only)
+    const PlanView &v = V[0];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
+    const OrderTables &tb = *v.tab;
+    const auto exps = gptr(tb.exps);
+    soft_tile_targets(v, G, tid, sTg);
+    soft_class_positions<P, CMAX>(exps, tid, 256, sPos);
+    __syncthreads();
+    soft_tile_levels(v, tid, sTg, sLv, sInfo);
+    const int lmin = sInfo[0], lmax = sInfo[1], oct = sInfo[2];
+    if (lmax < 0) return; // (block-uniform)
+    {
+        const auto rep = gptr(tb.srep) + oct * kSymClasses, mem = gptr(tb.smem) + oct * kSymClasses * 8;
+        const auto ssl = gptr(tb.sslot) + oct * kVSlots;
+        for (int e = tid; e < kSymClasses * 8; e += 256) {
+            const int j = mem[e];
+            sMem[e >> 3][e & 7] = (unsigned char)(j >= 0 ? j : 255);
+        }
+        if (tid < kSymClasses) sRep[tid] = rep[tid];
+        if (tid < kVSlots) sSl[tid] = (unsigned char)ssl[tid];
+        for (int e = tid; e < 4 * KS; e += 256) {
+            const int g = e / KS, ks = e - g * KS, c = S.kc[ks], t = 4 * (ks - S.kfirst[c]) + g;
+            sHo[g][ks] = t < S.csz[c] ? soft_cube_addr<SC>(exps[sPos[c][t]]) : 0;
+        }
+    }
+    int hb[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int c = S.rc[mt], t = 16 * (mt - S.rfirst[c]) + col;
+        hb[mt] = t < S.csz[c] ? soft_cube_addr<SC>(exps[sPos[c][t]]) : 0;
+    }
+    const int tgt = sTg[wave * 16 + col], tlev = sLv[wave * 16 + col];
+    const auto vs = gptr(v.vslot);
+    const uint32_t zoff = (uint32_t)v.nboxes * (uint32_t)LDMS * 8u; // the all-zero row
+    const auto Mg = gptr((const char *)v.Mh);
+    dvec_t pd[DV];
+    int dm[DV][2];
+#pragma unroll
+    for (int r = 0; r < DV; ++r)
+#pragma unroll
+        for (int w = 0; w < 2; ++w) {
+            const int e = (tid + 256 * r) * 2 + w;
+            dm[r][w] = e < LDC ? gptr(v.soft_map)[e] : LDD - 1;
+        }
+    double4_t acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = double4_t{0, 0, 0, 0};
+    __syncthreads(); // sPos is overwritten by the tables from here on
+
+    for (int L = lmin; L <= lmax; ++L) {
+        // classes used by the targets of level L
+        if (tid == 0) sUsed = 0;
+        __syncthreads();
+        {
+            unsigned long long used = 0;
+            for (int e = tid; e < 64 * kVSlots; e += 256) {
+                const int q = e / kVSlots, j = e - q * kVSlots;
+                if (sLv[q] == L && vs[(int64_t)sTg[q] * kVSlots + j] >= 0) used |= 1ull << sSl[j];
+            }
+            if (used) atomicOr(&sUsed, used);
+        }
+        __syncthreads();
+        if (tid < 64) { // the used classes in table order; where each zero mask's classes end
+            const unsigned long long used = sUsed, below = lanes_below(lane);
+            const int c = lane;
+            if (c < kSymClasses && ((used >> c) & 1)) sList[__popcll(used & below)] = (unsigned char)c;
+            const int z = c < kSymClasses ? sRep[c] >> 16 : 0, zn = c + 1 < kSymClasses ? sRep[c + 1] >> 16 : 8;
+            if (c < kSymClasses && zn != z) sZend[z] = __popcll(used & (below | (1ull << c)));
+            if (lane == 0) sN = __popcll(used);
+        }
+        __syncthreads();
+        const int nq = sN;
+        if (nq == 0) continue; // (block-uniform)
+        const double *Dl = v.Dsoft + (int64_t)(L - 2) * 343 * LDC;
+        auto load_d = [&](int c) {
+            const dvec_t *Dk = (const dvec_t *)(Dl + (int64_t)(sRep[c] & 0xffff) * LDC);
+#pragma unroll
+            for (int r = 0; r < DV; ++r) {
+                const int e = tid + 256 * r;
+                pd[r] = e < LDC / 2 ? gload(Dk + e) : dvec_t{0, 0};
+            }
+        };
+        auto store_d = [&](int buf) {
+#pragma unroll
+            for (int r = 0; r < DV; ++r)
+                if (tid + 256 * r < LDC / 2)
+#pragma unroll
+                    for (int w = 0; w < 2; ++w) sD[buf][dm[r][w]] = pd[r][w];
+        };
+        // byte offsets of the members' sorted rows (lane group kq's vector 0)
+        auto class_src = [&](int q, uint32_t (&src)[8]) {
+            const int c = sList[q];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int j = sMem[c][m];
+                const int b = j != 255 && tlev == L ? vs[(int64_t)tgt * kVSlots + j] : -1;
+                src[m] = b >= 0 ? ((uint32_t)b * (uint32_t)LDMS + 2u * (uint32_t)kq) * 8u : zoff + 16u * (uint32_t)kq;
+            }
+        };
+        dvec_t cur[8], nxt[8];
+        auto load_v = [&](dvec_t (&dst)[8], const uint32_t (&src)[8], int j, auto zc) {
+            constexpr int Z = decltype(zc)::value;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                if (m & Z) continue;
+                uint32_t o = src[m];
+                asm volatile("" : "+v"(o)); // (keeps base + 32-bit offset addressing)
+                dst[m] = *(const __attribute__((address_space(1))) dvec_t *)(Mg + (uint64_t)o + 64u * (uint32_t)j);
+            }
+        };
+        uint32_t srcc[8], srcn[8];
+        load_d(sList[0]);
+        store_d(0);
+        class_src(0, srcc);
+        load_v(cur, srcc, 0, std::integral_constant<int, 0>{});
+        __syncthreads();
+        int q = 0;
+        auto run_mask = [&](auto zc) {
+            constexpr int Z = decltype(zc)::value;
+            const int qend = sZend[Z] < nq ? sZend[Z] : nq;
+            for (; q < qend; ++q) {
+                const int buf = q & 1;
+                const bool more = q + 1 < nq;
+                if (more) {
+                    load_d(sList[q + 1]);
+                    class_src(q + 1, srcn);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) srcn[m] = zoff + 16u * (uint32_t)kq;
+                }
+                const double *D = sD[buf];
+                const int *Ho = sHo[kq];
+#pragma unroll
+                for (int jv = 0; jv < KSV; ++jv) {
+                    if (jv + 1 < KSV) load_v(nxt, srcc, jv + 1, zc);
+                    else load_v(nxt, srcn, 0, std::integral_constant<int, 0>{});
+#pragma unroll
+                    for (int w = 0; w < 2; ++w) {
+                        const int ks = 2 * jv + w;
+                        if (ks < KS) {
+                            const int ha = Ho[ks];
+                            double h[8];
+#pragma unroll
+                            for (int m = 0; m < 8; ++m) h[m] = (m & Z) ? 0.0 : cur[m][w];
+                            wht8z<Z>(h);
+#pragma unroll
+                            for (int mt = 0; mt < MT; ++mt)
+                                if (!((S.rc[mt] ^ S.kc[ks]) & Z))
+                                    acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[hb[mt] + ha], h[S.rc[mt] ^ S.kc[ks]],
+                                                                                   acc[mt], 0, 0, 0);
+                        }
+                    }
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) cur[m] = nxt[m];
+                }
+#pragma unroll
+                for (int m = 0; m < 8; ++m) srcc[m] = srcn[m];
+                if (more) store_d(buf ^ 1);
+                __syncthreads();
+            }
+        };
+        run_mask(std::integral_constant<int, 0>{});
+        run_mask(std::integral_constant<int, 1>{});
+        run_mask(std::integral_constant<int, 2>{});
+        run_mask(std::integral_constant<int, 3>{});
+        run_mask(std::integral_constant<int, 4>{});
+        run_mask(std::integral_constant<int, 5>{});
+        run_mask(std::integral_constant<int, 6>{}); // at most two zero axes
+    }
+    // outputs: row 4 r + kq of each tile, back in DA order
+    __syncthreads();
+    soft_class_positions<P, CMAX>(exps, tid, 256, sPos);
+    __syncthreads();
+    if (tgt < 0) return;
+    double *Lt = v.L + (int64_t)tgt * v.ldm;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int c = S.rc[mt];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int t = 16 * (mt - S.rfirst[c]) + 4 * r + kq;
+            if (t < S.csz[c]) Lt[sPos[c][t]] = acc[mt][r];
+        }
+    }
 }
 
 // ---------------- P2L and M2P (adaptive trees) ----------------
@@ -767,12 +1090,30 @@ void launch_soft_m2p(int p, const PlanView *V, int nleaves, hipStream_t s)
 #undef T_
 }
 
-void launch_m2l_soft(int p, const PlanView *V, const SoftGrid &G, hipStream_t s)
+void launch_m2l_soft(int p, const PlanView *V, const SoftGrid &G, double *Ms, int nboxes, hipStream_t s)
 {
     if (G.nblocks <= 0) return;
-#define T_(PP) k_m2l_soft<PP><<<G.nblocks, 256, 0, s>>>(V, G)
-    SOFT_SWITCH(p, T_)
+    if (p >= kSoftSymOrder) {
+        const int64_t tot = (int64_t)(nboxes + 1) * soft_sym_ld(p);
+        const unsigned nb = (unsigned)std::min<int64_t>((tot + 255) / 256, 4096);
+        switch (p) {
+#define T_(PP)                                                                   \
+    case PP:                                                                     \
+        k_soft_msort<PP><<<nb, 256, 0, s>>>(V, Ms, nboxes + 1);                  \
+        k_m2l_soft_sym<PP><<<G.nblocks, 256, 0, s>>>(V, G);                      \
+        break;
+            T_(4) T_(5) T_(6) T_(7) T_(8) T_(9) T_(10)
 #undef T_
+        default: break;
+        }
+        return;
+    }
+    switch (p) {
+    case 0: k_m2l_soft<0><<<G.nblocks, 256, 0, s>>>(V, G); break;
+    case 1: k_m2l_soft<1><<<G.nblocks, 256, 0, s>>>(V, G); break;
+    case 2: k_m2l_soft<2><<<G.nblocks, 256, 0, s>>>(V, G); break;
+    default: k_m2l_soft<3><<<G.nblocks, 256, 0, s>>>(V, G); break;
+    }
 }
 
 } // namespace fmm
