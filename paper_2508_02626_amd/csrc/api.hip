@@ -433,7 +433,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     if (!soft && m2l_sym(P->p) && (unsigned long long)(nb + 1) * (unsigned long long)P->ldmh * 8ULL >= (1ULL << 32))
         return fail(FMM_EUNSUPPORTED, "too many boxes for this order (folded multipoles reach 4 GiB)");
     // (and the softened kernel's class-ordered moments)
-    const int ldms = soft && P->p >= kSoftSymOrder ? soft_sym_ld(P->p) : 0;
+    const int ldms = soft && P->p >= kSoftSymOrder && P->p <= kSoftSymMaxOrder ? soft_sym_ld(P->p) : 0;
     if ((unsigned long long)(nb + 1) * (unsigned long long)ldms * 8ULL >= (1ULL << 32))
         return fail(FMM_EUNSUPPORTED, "too many boxes for this order (class-ordered moments reach 4 GiB)");
     // ---- phase B: boxes, list counts, work lists (sizes known from nb)
@@ -1272,7 +1272,7 @@ extern "C" int fmm_plan_estimate(int64_t n, int32_t order, int32_t leaf_size, co
     const int depth = o.uniform_depth >= 0 ? o.uniform_depth : o.max_depth;
     if (o.kernel == FMM_KERNEL_SOFTENED && depth >= 2 && order <= kSoftMaxOrder)
         total += 8.0 * (depth - 1) * 343 * soft_table_ldc(order); // derivative tables per level (at most)
-    if (o.kernel == FMM_KERNEL_SOFTENED && order >= kSoftSymOrder && order <= kSoftMaxOrder)
+    if (o.kernel == FMM_KERNEL_SOFTENED && order >= kSoftSymOrder && order <= kSoftSymMaxOrder)
         total += boxes * 8.0 * (soft_sym_ld(order) - ldmh); // class-ordered moments instead of folded ones
     *bytes = (size_t)(total * 1.25);
     return FMM_OK;

@@ -41,11 +41,46 @@ __device__ inline double fact_d(int n)
     return r;
 }
 
+// LDS layout of one derivative table in the M2L: entry g at addr(g) = g_x SA +
+// g_y SB + g_z, linear (so addr(a) + addr(b) = addr(a + b) and a product's
+// operand is one gather) and one-to-one on the degrees |g| <= 2p the table
+// holds; the padding entry of the compact rows goes to the slot after the
+// largest address (2p SA).  Orders 0-3: the dense cube (SB = 2p + 1,
+// SA = SB^2); orders 4-10: strides picked by a search over the sign-class tiles so
+// that the 16 rows of a tile (with one column each) and the 32 lanes of two
+// columns fall on as few common LDS banks as possible (with the cube's
+// strides, both = 1 mod 16, the bank follows |a + b| mod 16 and a tile's rows
+// share two or three banks).
+template <int P> struct SoftCube {
+    static constexpr int S = 2 * P + 1;
+    static constexpr int SA = P == 4 ? 92 : P == 5 ? 100 : P == 6 ? 190 : P == 7 ? 267 : P == 8 ? 315
+                            : P == 9 ? 395 : P == 10 ? 455 : S * S;
+    static constexpr int SB = P == 4 ? 11 : P == 5 ? 22 : P == 6 ? 23 : P == 7 ? 18 : P == 8 ? 18
+                            : P == 9 ? 26 : P == 10 ? 22 : S;
+    static constexpr int SIZE = 2 * P * SA + 1, LDD = SIZE + 1; // addresses, and the padding slot
+    __host__ __device__ static constexpr int addr(int i, int j, int k) { return i * SA + j * SB + k; }
+    __device__ static int addr(int x) { return addr(x & 255, (x >> 8) & 255, x >> 16); }
+    static constexpr bool one_to_one()
+    {
+        bool used[SIZE] = {};
+        for (int i = 0; i <= 2 * P; ++i)
+            for (int j = 0; i + j <= 2 * P; ++j)
+                for (int k = 0; i + j + k <= 2 * P; ++k) {
+                    const int a = addr(i, j, k);
+                    if (a < 0 || a >= SIZE || used[a]) return false;
+                    used[a] = true;
+                }
+        return true;
+    }
+    static_assert(P == 0 || (SB > 2 * P && SA > SB), "strides");
+    static_assert(one_to_one(), "addresses one-to-one on the table's degrees");
+};
+
 // ---------------- derivative tables, one block per (level, offset) ----------------
 template <int P>
 __global__ __launch_bounds__(256) void k_soft_tables(double *D, int *map, int ldc, double W, double eps)
 {
-    constexpr int Q = 2 * P, NQ = ncoef(Q), S = Q + 1;
+    constexpr int Q = 2 * P, NQ = ncoef(Q);
     __shared__ double a[NQ];
     const int lev = blockIdx.x / 343 + 2, off = blockIdx.x % 343;
     const int kx = off / 49 - 3, ky = (off / 7) % 7 - 3, kz = off % 7 - 3;
@@ -57,9 +92,9 @@ __global__ __launch_bounds__(256) void k_soft_tables(double *D, int *map, int ld
             if (e < NQ) {
                 while (below(n + 1) <= e) ++n;
                 mono_exps(e, n, i, j, k);
-                map[e] = (i * S + j) * S + k;
+                map[e] = SoftCube<P>::addr(i, j, k);
             } else {
-                map[e] = S * S * S; // the slot after the cube, never read
+                map[e] = SoftCube<P>::SIZE; // the padding slot, never read
             }
         }
     // only V-list offsets (some |k_i| >= 2) are ever read
@@ -241,19 +276,16 @@ __global__ __launch_bounds__(64) void k_soft_l2l(const PlanView *V, int first_ch
     }
 }
 
-// dense-cube LDS address of the monomial with packed exponents x (i | j << 8 | k << 16)
-template <int S> __device__ inline int soft_cube_addr(int x) { return ((x & 255) * S + ((x >> 8) & 255)) * S + (x >> 16); }
-
-// The 64 targets of M2L block blockIdx.x (-1 for an empty place): in a uniform
-// tree boxes 8 (64 t + i) + o of one level (block -> level, octant, tile, each
-// XCD taking a contiguous range); in an adaptive tree the plan's target tile.
-__device__ inline void soft_tile_targets(const PlanView &v, const SoftGrid &G, int tid, int *sTg)
+// The 64 targets of M2L tile `item` (-1 for an empty place): in a uniform
+// tree boxes 8 (64 t + i) + o of one level (item -> level, octant, tile); in
+// an adaptive tree the plan's target tile.  Blocks map to items through
+// xcd_remap, each XCD taking a contiguous range.
+__device__ inline void soft_tile_targets(const PlanView &v, const SoftGrid &G, int item, int tid, int *sTg)
 {
     if (G.adaptive) {
-        const int tile = xcd_remap(blockIdx.x, G.nblocks);
-        if (tid < 64) sTg[tid] = v.m2l_tgt[(int64_t)tile * kM2LSlots + tid];
+        if (tid < 64) sTg[tid] = v.m2l_tgt[(int64_t)item * kM2LSlots + tid];
     } else {
-        int item = xcd_remap(blockIdx.x, G.nblocks), li = 0;
+        int li = 0;
         while (li + 1 < G.nlev && item >= G.start[li + 1]) ++li;
         item -= G.start[li];
         const int lev = li + 2, per = G.tiles[li], o = item / per, t = item - o * per;
@@ -289,8 +321,8 @@ __device__ inline void soft_tile_levels(const PlanView &v, int tid, const int *s
 // ---------------- M2L on the full components (FP64 MFMA) ----------------
 // Per used offset slot each wavefront runs an n_p x n_p by 16 product with
 // 16x16x4 MFMAs, as the slot-by-slot Coulomb M2L: A[b][a] = D(addr(b) +
-// addr(a)) gathered from the slot's table in LDS (dense cube addr(i,j,k) =
-// (i S + j) S + k, S = 2p + 1, so addr(a) + addr(b) = addr(a + b)); B the 16
+// addr(a)) gathered from the slot's table in LDS (SoftCube: addr(a) + addr(b)
+// = addr(a + b)); B the 16
 // targets' source multipoles, one 16-byte vector (two k-steps) per lane, one
 // vector ahead.  Tables are double-buffered in LDS (one barrier per slot).
 // The 64 targets of a block share the 189 offsets of one octant: in a uniform
@@ -301,15 +333,14 @@ __device__ inline void soft_tile_levels(const PlanView &v, int tid, const int *s
 // tables; a target's operands are zero in the other levels' products.
 template <int P> struct SoftM2L {
     static constexpr int NP = ncoef(P), MT = (NP + 15) / 16, KS = ((NP + 3) / 4 + 1) & ~1, KSV = KS / 2;
-    // LDS table: the dense cube and one slot after it for the padding entry
-    static constexpr int S = 2 * P + 1, LDD = S * S * S + 1, LDC = (ncoef(2 * P) + 1) & ~1;
+    static constexpr int LDD = SoftCube<P>::LDD, LDC = (ncoef(2 * P) + 1) & ~1;
 };
 
 template <int P>
 __global__ __launch_bounds__(256) void k_m2l_soft(const PlanView *V, SoftGrid G)
 {
     using SH = SoftM2L<P>;
-    constexpr int NP = SH::NP, MT = SH::MT, KS = SH::KS, KSV = SH::KSV, S = SH::S, LDD = SH::LDD, LDC = SH::LDC;
+    constexpr int NP = SH::NP, MT = SH::MT, KS = SH::KS, KSV = SH::KSV, LDD = SH::LDD, LDC = SH::LDC;
     constexpr int DV = (LDC / 2 + 255) / 256;
     static_assert(8 * KSV <= pad16(NP), "operand vectors stay inside a padded row");
     typedef double vec_t __attribute__((ext_vector_type(2)));
@@ -321,16 +352,16 @@ __global__ __launch_bounds__(256) void k_m2l_soft(const PlanView *V, SoftGrid G)
     const PlanView &v = V[0];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
     const OrderTables &tb = *v.tab;
-    soft_tile_targets(v, G, tid, sTg);
+    soft_tile_targets(v, G, xcd_remap(blockIdx.x, G.nblocks), tid, sTg);
     for (int e = tid; e < 4 * KS; e += 256) {
         const int g = e / KS, ks = e - g * KS, a = 8 * (ks / 2) + 2 * g + (ks & 1);
-        sHo[g][ks] = a < NP ? soft_cube_addr<S>(gptr(tb.exps)[a]) : 0;
+        sHo[g][ks] = a < NP ? SoftCube<P>::addr(gptr(tb.exps)[a]) : 0;
     }
     int hb[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int b = 16 * mt + col;
-        hb[mt] = b < NP ? soft_cube_addr<S>(gptr(tb.exps)[b]) : 0;
+        hb[mt] = b < NP ? SoftCube<P>::addr(gptr(tb.exps)[b]) : 0;
     }
     __syncthreads();
     soft_tile_levels(v, tid, sTg, sLv, sInfo);
@@ -440,7 +471,7 @@ __global__ __launch_bounds__(256) void k_m2l_soft(const PlanView *V, SoftGrid G)
         }
 }
 
-// ---------------- sign-class M2L (orders >= kSoftSymOrder) ----------------
+// ---------------- sign-class M2L (orders kSoftSymOrder .. kSoftSymMaxOrder) ----------------
 // K_eta is even in every coordinate, so d^g K_eta(s o k) = s^g d^g K_eta(k)
 // for a vector s of signs: the offsets that differ from a representative k
 // only by signs (the members of its class) share k's table.  With rows b and
@@ -493,8 +524,7 @@ int soft_sym_ld(int p)
 {
     switch (p) {
     case 4: return SoftSym<4>::LDMS; case 5: return SoftSym<5>::LDMS; case 6: return SoftSym<6>::LDMS;
-    case 7: return SoftSym<7>::LDMS; case 8: return SoftSym<8>::LDMS; case 9: return SoftSym<9>::LDMS;
-    case 10: return SoftSym<10>::LDMS;
+    case 7: return SoftSym<7>::LDMS; case 8: return SoftSym<8>::LDMS;
     default: return 0;
     }
 }
@@ -542,8 +572,8 @@ __global__ __launch_bounds__(256) void k_soft_msort(const PlanView *V, double *M
     }
 }
 
-// One block of 4 wavefronts per target tile (as k_m2l_soft), each wavefront
-// 16 targets with all row tiles; per level the classes used by the level's
+// Two blocks of 4 wavefronts per target tile (each block every other class of
+// the tile's used ones), each wavefront 16 targets with all row tiles; per level the classes used by the level's
 // targets, one after the other (in zero-mask order, so Z is a compile-time
 // constant of the loop that runs them): the representative's table staged in
 // LDS as the dense cube (double-buffered), per k-step the 8 members' operands
@@ -556,7 +586,7 @@ __global__ __launch_bounds__(256) void k_m2l_soft_sym(const PlanView *V, SoftGri
     using SS = SoftSym<P>;
     static constexpr SS S{};
     constexpr int MT = SS::MT, KS = SS::KS, KSV = SS::KSV, LDMS = SS::LDMS, CMAX = SS::CMAX;
-    constexpr int SC = 2 * P + 1, LDD = SC * SC * SC + 1, LDC = (ncoef(2 * P) + 1) & ~1;
+    constexpr int LDD = SoftCube<P>::LDD, LDC = (ncoef(2 * P) + 1) & ~1;
     constexpr int DV = (LDC / 2 + 255) / 256;
     static_assert(8 * CMAX * sizeof(int) <= LDD * sizeof(double), "class positions fit in a table buffer");
     typedef double dvec_t __attribute__((ext_vector_type(2)));
@@ -575,7 +605,11 @@ __global__ __launch_bounds__(256) void k_m2l_soft_sym(const PlanView *V, SoftGri
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, col = lane & 15, kq = lane >> 4;
     const OrderTables &tb = *v.tab;
     const auto exps = gptr(tb.exps);
-    soft_tile_targets(v, G, tid, sTg);
+    // two blocks per tile (consecutive, so on one XCD), each taking every
+    // other class of the tile's used ones; both add into L, which is zero
+    // before the M2L (two terms added to zero in either order: deterministic)
+    const int item = xcd_remap(blockIdx.x, 2 * G.nblocks), part = item & 1;
+    soft_tile_targets(v, G, item >> 1, tid, sTg);
     soft_class_positions<P, CMAX>(exps, tid, 256, sPos);
     __syncthreads();
     soft_tile_levels(v, tid, sTg, sLv, sInfo);
@@ -592,14 +626,14 @@ __global__ __launch_bounds__(256) void k_m2l_soft_sym(const PlanView *V, SoftGri
         if (tid < kVSlots) sSl[tid] = (unsigned char)ssl[tid];
         for (int e = tid; e < 4 * KS; e += 256) {
             const int g = e / KS, ks = e - g * KS, c = S.kc[ks], t = 4 * (ks - S.kfirst[c]) + g;
-            sHo[g][ks] = t < S.csz[c] ? soft_cube_addr<SC>(exps[sPos[c][t]]) : 0;
+            sHo[g][ks] = t < S.csz[c] ? SoftCube<P>::addr(exps[sPos[c][t]]) : 0;
         }
     }
     int hb[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int c = S.rc[mt], t = 16 * (mt - S.rfirst[c]) + col;
-        hb[mt] = t < S.csz[c] ? soft_cube_addr<SC>(exps[sPos[c][t]]) : 0;
+        hb[mt] = t < S.csz[c] ? SoftCube<P>::addr(exps[sPos[c][t]]) : 0;
     }
     const int tgt = sTg[wave * 16 + col], tlev = sLv[wave * 16 + col];
     const auto vs = gptr(v.vslot);
@@ -632,9 +666,11 @@ __global__ __launch_bounds__(256) void k_m2l_soft_sym(const PlanView *V, SoftGri
             if (used) atomicOr(&sUsed, used);
         }
         __syncthreads();
-        if (tid < 64) { // the used classes in table order; where each zero mask's classes end
-            const unsigned long long used = sUsed, below = lanes_below(lane);
+        if (tid < 64) { // this part's classes in table order; where each zero mask's classes end
+            const unsigned long long below = lanes_below(lane);
             const int c = lane;
+            const unsigned long long used =
+                __ballot(c < kSymClasses && ((sUsed >> c) & 1) && (__popcll(sUsed & below) & 1) == part);
             if (c < kSymClasses && ((used >> c) & 1)) sList[__popcll(used & below)] = (unsigned char)c;
             const int z = c < kSymClasses ? sRep[c] >> 16 : 0, zn = c + 1 < kSymClasses ? sRep[c + 1] >> 16 : 8;
             if (c < kSymClasses && zn != z) sZend[z] = __popcll(used & (below | (1ull << c)));
@@ -700,30 +736,38 @@ __global__ __launch_bounds__(256) void k_m2l_soft_sym(const PlanView *V, SoftGri
 #pragma unroll
                     for (int m = 0; m < 8; ++m) srcn[m] = zoff + 16u * (uint32_t)kq;
                 }
-                const double *D = sD[buf];
-                const int *Ho = sHo[kq];
+                // the wavefront skips a class none of its targets has
+                bool has = false;
 #pragma unroll
-                for (int jv = 0; jv < KSV; ++jv) {
-                    if (jv + 1 < KSV) load_v(nxt, srcc, jv + 1, zc);
-                    else load_v(nxt, srcn, 0, std::integral_constant<int, 0>{});
+                for (int m = 0; m < 8; ++m) has |= srcc[m] != zoff + 16u * (uint32_t)kq;
+                if (__ballot(has)) {
+                    const double *D = sD[buf];
+                    const int *Ho = sHo[kq];
 #pragma unroll
-                    for (int w = 0; w < 2; ++w) {
-                        const int ks = 2 * jv + w;
-                        if (ks < KS) {
-                            const int ha = Ho[ks];
-                            double h[8];
+                    for (int jv = 0; jv < KSV; ++jv) {
+                        if (jv + 1 < KSV) load_v(nxt, srcc, jv + 1, zc);
+                        else load_v(nxt, srcn, 0, std::integral_constant<int, 0>{});
 #pragma unroll
-                            for (int m = 0; m < 8; ++m) h[m] = (m & Z) ? 0.0 : cur[m][w];
-                            wht8z<Z>(h);
+                        for (int w = 0; w < 2; ++w) {
+                            const int ks = 2 * jv + w;
+                            if (ks < KS) {
+                                const int ha = Ho[ks];
+                                double h[8];
 #pragma unroll
-                            for (int mt = 0; mt < MT; ++mt)
-                                if (!((S.rc[mt] ^ S.kc[ks]) & Z))
-                                    acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[hb[mt] + ha], h[S.rc[mt] ^ S.kc[ks]],
-                                                                                   acc[mt], 0, 0, 0);
+                                for (int m = 0; m < 8; ++m) h[m] = (m & Z) ? 0.0 : cur[m][w];
+                                wht8z<Z>(h);
+#pragma unroll
+                                for (int mt = 0; mt < MT; ++mt)
+                                    if (!((S.rc[mt] ^ S.kc[ks]) & Z))
+                                        acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(D[hb[mt] + ha], h[S.rc[mt] ^ S.kc[ks]],
+                                                                                       acc[mt], 0, 0, 0);
+                            }
                         }
-                    }
 #pragma unroll
-                    for (int m = 0; m < 8; ++m) cur[m] = nxt[m];
+                        for (int m = 0; m < 8; ++m) cur[m] = nxt[m];
+                    }
+                } else {
+                    load_v(cur, srcn, 0, std::integral_constant<int, 0>{});
                 }
 #pragma unroll
                 for (int m = 0; m < 8; ++m) srcc[m] = srcn[m];
@@ -751,7 +795,7 @@ __global__ __launch_bounds__(256) void k_m2l_soft_sym(const PlanView *V, SoftGri
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int t = 16 * (mt - S.rfirst[c]) + 4 * r + kq;
-            if (t < S.csz[c]) Lt[sPos[c][t]] = acc[mt][r];
+            if (t < S.csz[c]) atomicAdd(Lt + sPos[c][t], acc[mt][r]);
         }
     }
 }
@@ -960,7 +1004,8 @@ template <int P> struct Acc {
     {
         using namespace lane_taylor;
         constexpr int n = cx_deg(E), i = cx_i(E), j = cx_j(E), k = cx_k(E);
-        const double b = v * cx_gfact(E);
+        constexpr double gf = cx_gfact(E); // (a constant: no factorial at run time)
+        const double b = v * gf;
         if constexpr (n <= P) ph = fma(m[E], b, ph);
         if constexpr (i >= 1) g0 = fma(m[cx_index(i - 1, j, k)], b, g0);
         if constexpr (j >= 1) g1 = fma(m[cx_index(i, j - 1, k)], b, g1);
@@ -1093,27 +1138,24 @@ void launch_soft_m2p(int p, const PlanView *V, int nleaves, hipStream_t s)
 void launch_m2l_soft(int p, const PlanView *V, const SoftGrid &G, double *Ms, int nboxes, hipStream_t s)
 {
     if (G.nblocks <= 0) return;
-    if (p >= kSoftSymOrder) {
+    if (p >= kSoftSymOrder && p <= kSoftSymMaxOrder) {
         const int64_t tot = (int64_t)(nboxes + 1) * soft_sym_ld(p);
         const unsigned nb = (unsigned)std::min<int64_t>((tot + 255) / 256, 4096);
         switch (p) {
 #define T_(PP)                                                                   \
     case PP:                                                                     \
         k_soft_msort<PP><<<nb, 256, 0, s>>>(V, Ms, nboxes + 1);                  \
-        k_m2l_soft_sym<PP><<<G.nblocks, 256, 0, s>>>(V, G);                      \
+        k_m2l_soft_sym<PP><<<2 * G.nblocks, 256, 0, s>>>(V, G);                  \
         break;
-            T_(4) T_(5) T_(6) T_(7) T_(8) T_(9) T_(10)
+            T_(4) T_(5) T_(6) T_(7) T_(8)
 #undef T_
         default: break;
         }
         return;
     }
-    switch (p) {
-    case 0: k_m2l_soft<0><<<G.nblocks, 256, 0, s>>>(V, G); break;
-    case 1: k_m2l_soft<1><<<G.nblocks, 256, 0, s>>>(V, G); break;
-    case 2: k_m2l_soft<2><<<G.nblocks, 256, 0, s>>>(V, G); break;
-    default: k_m2l_soft<3><<<G.nblocks, 256, 0, s>>>(V, G); break;
-    }
+#define T_(PP) k_m2l_soft<PP><<<G.nblocks, 256, 0, s>>>(V, G)
+    SOFT_SWITCH(p, T_)
+#undef T_
 }
 
 } // namespace fmm
