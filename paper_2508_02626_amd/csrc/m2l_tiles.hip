@@ -17,7 +17,10 @@ namespace fmm {
 // out region by region: the x-th eighth of every octant's tiles (a spatial
 // region, as the tiles follow Morton order) forms the x-th eighth of the
 // sequence, which the M2L launch hands to XCD x, so each XCD's L2 holds the
-// multipoles of one region instead of those of the whole domain.
+// multipoles of one region instead of those of the whole domain.  Inside a
+// region the eight octants' tiles are dealt round-robin, so the blocks that
+// run at the same time hold the children of the same parents, whose V lists
+// draw on the same source boxes.
 constexpr int kCatBits = 12;
 
 __global__ __launch_bounds__(256) void k_oct_keys(const BoxArrays bx, const int32_t *tg, int nt, int uniform,
@@ -83,7 +86,15 @@ __global__ __launch_bounds__(256) void k_oct_place(const uint64_t *key, const in
     const int o = (int)(key[i] >> kCatBits), j = i - octoff[9 + o], t = j >> 6, T = octoff[96 + o];
     int x = 0;
     while (x < 7 && t >= (x + 1) * T / 8) ++x;
-    const int tile = octoff[32 + 8 * x + o] + (t - x * T / 8);
+    // within region x the octants' tiles are dealt round-robin: tile u of
+    // octant o follows tile u of octants < o and precedes tile u + 1 of all
+    const int u = t - x * T / 8;
+    int pos = 0;
+    for (int k = 0; k < 8; ++k) {
+        const int n = (x + 1) * octoff[96 + k] / 8 - x * octoff[96 + k] / 8; // tiles of octant k in region x
+        pos += min(n, u + (k < o ? 1 : 0));
+    }
+    const int tile = octoff[32 + 8 * x] + pos;
     slots[(int64_t)tile * 64 + (j & 63)] = val[i];
 }
 
