@@ -165,81 +165,95 @@ __global__ __launch_bounds__(256) void k_soft_p2m(const PlanView *V)
     v.M[(int64_t)box * ldm + a] = m;
 }
 
-// one-axis shift of a vector of NC coefficients in LDS: out[g] = sum_m c[m] in[g -+ m e_d]
-// (dir = -1: lower indices, the moment shift; dir = +1: higher, the Taylor shift)
-template <int P>
-__device__ inline void axis_shift(const double *in, double *out, int d, int dir, const double *c, int lane)
+// Exponents of the coefficients a lane handles in the one-axis shifts
+// (entries lane, lane + 64, ...): degree n, a = j + k and (i, j, k).
+template <int P> struct ShiftLane {
+    static constexpr int NC = ncoef(P), RC = (NC + 63) / 64;
+    int n[RC], a[RC], e[RC][3];
+    __device__ void init(int lane)
+    {
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            const int g = lane + 64 * r;
+            int nn = 0, i = 0, j = 0, k = 0;
+            if (g < NC) {
+                while (below(nn + 1) <= g) ++nn;
+                mono_exps(g, nn, i, j, k);
+            }
+            n[r] = nn;
+            a[r] = j + k;
+            e[r][0] = i;
+            e[r][1] = j;
+            e[r][2] = k;
+        }
+    }
+};
+
+// one-axis shift of a vector of NC coefficients in LDS: out[g] = sum_m c[m] in[g -+ m e_D]
+// (DIR = -1: lower indices, the moment shift, m <= g_D; DIR = +1: higher, the
+// Taylor shift, m <= p - |g|).  The index of g -+ m e_D in the DA order is
+// below(n') + a'(a' + 1)/2 + k' with n' = n -+ m and a', k' moved only on the
+// axes they contain.
+template <int P, int D, int DIR>
+__device__ inline void axis_shift(const double *in, double *out, const double *c, const ShiftLane<P> &sl, int lane)
 {
-    constexpr int NC = ncoef(P);
-    for (int g = lane; g < NC; g += 64) {
-        int n = 0, e[3];
-        while (below(n + 1) <= g) ++n;
-        mono_exps(g, n, e[0], e[1], e[2]);
+    constexpr int NC = ncoef(P), RC = ShiftLane<P>::RC;
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+        const int g = lane + 64 * r;
+        if (g >= NC) continue;
+        const int n = sl.n[r], a = sl.a[r], k = sl.e[r][2];
+        const int top = DIR < 0 ? sl.e[r][D] : P - n;
         double s = 0.0;
-        if (dir < 0) {
-            for (int m = 0; m <= e[d]; ++m) {
-                int h[3] = {e[0], e[1], e[2]};
-                h[d] -= m;
-                s += c[m] * in[mono_index(h[0], h[1], h[2])];
-            }
-        } else {
-            for (int m = 0; m <= P - n; ++m) {
-                int h[3] = {e[0], e[1], e[2]};
-                h[d] += m;
-                s += c[m] * in[mono_index(h[0], h[1], h[2])];
-            }
+        for (int m = 0; m <= top; ++m) {
+            const int nm = n + DIR * m, am = D == 0 ? a : a + DIR * m, km = D == 2 ? k + DIR * m : k;
+            s += c[m] * in[below(nm) + am * (am + 1) / 2 + km];
         }
         out[g] = s;
     }
 }
 
-// ---------------- M2M: one block (one wavefront) per parent of `level` ----------------
+// ---------------- M2M: one block per parent of `level`, one wavefront per child ----------------
+// Each wavefront shifts one child (its own LDS vectors, three one-axis
+// shifts); the parent's moments are the sum over the children in child order.
 template <int P>
-__global__ __launch_bounds__(64) void k_soft_m2m(const PlanView *V, int first_box)
+__global__ __launch_bounds__(512) void k_soft_m2m(const PlanView *V, int first_box)
 {
     constexpr int NC = ncoef(P);
-    __shared__ double s0[NC], s1[NC];
-    __shared__ double cf[3][P + 1];
+    __shared__ double s0[8][NC], s1[8][NC];
+    __shared__ double cf[8][3][P + 1];
     const PlanView &v = V[0];
-    const int box = first_box + blockIdx.x, lane = threadIdx.x, ldm = v.ldm;
-    constexpr int RC = (NC + 63) / 64;
-    double acc[RC];
-#pragma unroll
-    for (int r = 0; r < RC; ++r) acc[r] = 0.0;
+    const int box = first_box + blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63, ldm = v.ldm;
     const int nch = v.nchild[box], c0 = v.child_begin[box];
     if (nch == 0) return; // a leaf keeps its P2M multipole
-    for (int c = 0; c < nch; ++c) {
-        const int ch = c0 + c, o = (int)(v.morton[ch] & 7);
-        __syncthreads();
-        for (int g = lane; g < NC; g += 64) {
-            int n = 0;
-            while (below(n + 1) <= g) ++n;
-            s0[g] = v.M[(int64_t)ch * ldm + g] * ldexp(1.0, -n);
+    if (w < nch) {
+        ShiftLane<P> sl;
+        sl.init(lane);
+        const int ch = c0 + w, o = (int)(v.morton[ch] & 7);
+#pragma unroll
+        for (int r = 0; r < ShiftLane<P>::RC; ++r) {
+            const int g = lane + 64 * r;
+            if (g < NC) s0[w][g] = v.M[(int64_t)ch * ldm + g] * ldexp(1.0, -sl.n[r]);
         }
         if (lane < 3 * (P + 1)) { // (-tau_d)^m / m!, tau_d = (2 o_d - 1) / 4
             const int d = lane / (P + 1), m = lane - d * (P + 1);
             const double t = -(2.0 * ((o >> (2 - d)) & 1) - 1.0) * 0.25;
             double pw = 1.0;
             for (int u = 0; u < m; ++u) pw *= t;
-            cf[d][m] = pw / fact_d(m);
+            cf[w][d][m] = pw / fact_d(m);
         }
-        __syncthreads();
-        axis_shift<P>(s0, s1, 0, -1, cf[0], lane);
-        __syncthreads();
-        axis_shift<P>(s1, s0, 1, -1, cf[1], lane);
-        __syncthreads();
-        axis_shift<P>(s0, s1, 2, -1, cf[2], lane);
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < RC; ++r)
-            if (lane + 64 * r < NC) acc[r] += s1[lane + 64 * r];
+        wave_sync();
+        axis_shift<P, 0, -1>(s0[w], s1[w], cf[w][0], sl, lane);
+        wave_sync();
+        axis_shift<P, 1, -1>(s1[w], s0[w], cf[w][1], sl, lane);
+        wave_sync();
+        axis_shift<P, 2, -1>(s0[w], s1[w], cf[w][2], sl, lane);
     }
-    for (int g = lane; g < ldm; g += 64) {
-        const int r = g / 64;
+    __syncthreads();
+    for (int g = tid; g < ldm; g += 512) {
         double val = 0.0;
-#pragma unroll
-        for (int q = 0; q < RC; ++q)
-            if (q == r && g < NC) val = acc[q];
+        if (g < NC)
+            for (int c = 0; c < nch; ++c) val += s1[c][g];
         v.M[(int64_t)box * ldm + g] = val;
     }
 }
@@ -248,13 +262,19 @@ __global__ __launch_bounds__(64) void k_soft_m2m(const PlanView *V, int first_bo
 template <int P>
 __global__ __launch_bounds__(64) void k_soft_l2l(const PlanView *V, int first_child)
 {
-    constexpr int NC = ncoef(P);
+    constexpr int NC = ncoef(P), RC = ShiftLane<P>::RC;
     __shared__ double s0[NC], s1[NC];
     __shared__ double cf[3][P + 1];
     const PlanView &v = V[0];
     const int ch = first_child + blockIdx.x, lane = threadIdx.x, ldm = v.ldm;
     const int par = v.parent[ch], o = (int)(v.morton[ch] & 7);
-    for (int g = lane; g < NC; g += 64) s0[g] = v.L[(int64_t)par * ldm + g];
+    ShiftLane<P> sl;
+    sl.init(lane);
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+        const int g = lane + 64 * r;
+        if (g < NC) s0[g] = v.L[(int64_t)par * ldm + g];
+    }
     if (lane < 3 * (P + 1)) { // tau_d^m / m!
         const int d = lane / (P + 1), m = lane - d * (P + 1);
         const double t = (2.0 * ((o >> (2 - d)) & 1) - 1.0) * 0.25;
@@ -262,17 +282,17 @@ __global__ __launch_bounds__(64) void k_soft_l2l(const PlanView *V, int first_ch
         for (int u = 0; u < m; ++u) pw *= t;
         cf[d][m] = pw / fact_d(m);
     }
-    __syncthreads();
-    axis_shift<P>(s0, s1, 0, 1, cf[0], lane);
-    __syncthreads();
-    axis_shift<P>(s1, s0, 1, 1, cf[1], lane);
-    __syncthreads();
-    axis_shift<P>(s0, s1, 2, 1, cf[2], lane);
-    __syncthreads();
-    for (int g = lane; g < NC; g += 64) {
-        int n = 0;
-        while (below(n + 1) <= g) ++n;
-        v.L[(int64_t)ch * ldm + g] += ldexp(s1[g], -n - 1);
+    wave_sync();
+    axis_shift<P, 0, 1>(s0, s1, cf[0], sl, lane);
+    wave_sync();
+    axis_shift<P, 1, 1>(s1, s0, cf[1], sl, lane);
+    wave_sync();
+    axis_shift<P, 2, 1>(s0, s1, cf[2], sl, lane);
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < RC; ++r) {
+        const int g = lane + 64 * r;
+        if (g < NC) v.L[(int64_t)ch * ldm + g] += ldexp(s1[g], -sl.n[r] - 1);
     }
 }
 
@@ -1106,7 +1126,7 @@ void launch_soft_p2m(int p, const PlanView *V, int nleaves, int ldm, hipStream_t
 void launch_soft_m2m(int p, const PlanView *V, int first_box, int nbox, hipStream_t s)
 {
     if (nbox <= 0) return;
-#define T_(PP) k_soft_m2m<PP><<<nbox, 64, 0, s>>>(V, first_box)
+#define T_(PP) k_soft_m2m<PP><<<nbox, 512, 0, s>>>(V, first_box)
     SOFT_SWITCH(p, T_)
 #undef T_
 }
