@@ -13,7 +13,10 @@
 //   L2L  Lhat_b(C) += 2^(-|b|-1) sum_{g >= b} Lhat_g(P) tau^(g-b) / (g-b)!
 //        tau = (c_C - c_P) / h_P = (+-1/4, +-1/4, +-1/4)
 // The shifts factor over the axes, so M2M and L2L run as three one-axis
-// shifts (O(n_p p) per box instead of n_p^2).  The tables come from the
+// shifts (O(n_p p) per box instead of n_p^2).  K is even in every coordinate,
+// so the M2L shares one contraction among the offsets that differ only in
+// sign (orders 4-8).  P2L and M2P (adaptive trees) need K's Taylor
+// coefficients at particles, one particle per lane.  The tables come from the
 // Taylor recurrence of rho^(-1/2), rho = |x|^2 + eta^2:
 //   n rho a_g + (2n - 1) sum_k x_k a_(g - e_k) + (n - 1) sum_k a_(g - 2e_k) = 0,
 // a_g = d^g K / g! (degree n = |g|; eta = 0 gives the 1/r recurrence).
@@ -593,10 +596,12 @@ __global__ __launch_bounds__(256) void k_soft_msort(const PlanView *V, double *M
 }
 
 // Two blocks of 4 wavefronts per target tile (each block every other class of
-// the tile's used ones), each wavefront 16 targets with all row tiles; per level the classes used by the level's
-// targets, one after the other (in zero-mask order, so Z is a compile-time
-// constant of the loop that runs them): the representative's table staged in
-// LDS as the dense cube (double-buffered), per k-step the 8 members' operands
+// the tile's used ones), each wavefront 16 targets with all row tiles; per
+// level the classes used by the level's targets, one after the other (in
+// zero-mask order, so Z is a compile-time constant of the loop that runs
+// them; a wavefront skips a class none of its targets has): the
+// representative's table staged in
+// LDS (SoftCube layout, double-buffered), per k-step the 8 members' operands
 // (one 16-byte vector of two k-steps per member, one vector ahead), their
 // transform, then one MFMA per compatible row tile with the output of the
 // transform that the row and column parities select.
