@@ -5,7 +5,10 @@ mathematics: Table 1 at eps = 0, exact symbolic Taylor coefficients, a
 40-digit direct sum, the Coulomb oracle (an independent construction through
 Eq. P2M's inversion) at eps = 0, exactness of the moment M2M, polynomial
 invariance of L2L, geometric decay of M2L/P2L/M2P/FMM errors with the order,
-trees without far field, and finite differences for the fields."""
+trees without far field, finite differences for the fields, the reflection
+symmetry of K's derivatives and the sign-class decomposition of the M2L
+(one contraction per class of offsets, members combined by a Walsh-Hadamard
+transform) against the oracle's own M2L."""
 import os
 
 import mpmath
@@ -200,3 +203,50 @@ def test_fmm_fields_are_gradients():
         phm = tm.fmm_soft(5, qz, eps)[0][i]
         fd = -(php - phm) / (2 * hstep)
         assert abs(fd - fld[i, k]) <= 1e-6 * max(1.0, abs(fld[i, k]))
+
+
+def test_derivatives_change_sign_with_odd_exponents():
+    """K is even in every coordinate: the Taylor coefficient of exponent g at
+    the offset with some axes negated is the one at k times (-1)^(g on those
+    axes) (the reflection the GPU's sign-class M2L rests on)."""
+    p, eps = 6, 0.3
+    e = oracle.exponents(p)
+    k = np.array([2.0, -1.0, 3.0])
+    base = oracle.soft_taylor(p, k, eps)
+    for m in range(8):
+        s = np.array([-1.0 if (m >> (2 - d)) & 1 else 1.0 for d in range(3)])
+        got = oracle.soft_taylor(p, s * k, eps)
+        sign = np.prod(s[None, :] ** e, axis=1)
+        assert np.allclose(got, sign * base, rtol=1e-14, atol=1e-300)
+
+
+@pytest.mark.parametrize("rep", [(2, 1, 3), (0, 2, 1), (3, 0, 0)])
+def test_sign_class_contraction_equals_member_sum(rep):
+    """Sum over the members of a sign class (offsets s o k, s over the signs
+    of the non-zero axes) of the oracle's M2L equals one contraction with the
+    representative's matrix T(k): L_b = sum_a T(k)_ba H_(pi(a) xor pi(b))[a],
+    H_s[a] = sum_m (-1)^|m and s| M_m[a] (m: the axes member m negates, pi:
+    exponent parities) - the decomposition of the GPU's sign-class M2L, here
+    with 3, 2 and 1 non-zero axes."""
+    p, eps = 5, 0.4
+    e = oracle.exponents(p)
+    nc = len(e)
+    par = (e[:, 0] & 1) << 2 | (e[:, 1] & 1) << 1 | (e[:, 2] & 1)
+    k = np.array(rep, dtype=float)
+    zero = sum(4 >> d for d in range(3) if rep[d] == 0)
+    members = [m for m in range(8) if not (m & zero)]
+    rng = np.random.default_rng(5)
+    Ms = {m: rng.normal(size=nc) / (1.0 + e.sum(axis=1)) for m in members}
+    tgt = np.zeros(3)
+    lhs = np.zeros(nc)
+    for m in members:
+        s = np.array([-1.0 if (m >> (2 - d)) & 1 else 1.0 for d in range(3)])
+        lhs += oracle.soft_m2l(p, eps, tgt - s * k, tgt, Ms[m])
+    # the representative's matrix, column by column
+    T = np.stack([oracle.soft_m2l(p, eps, tgt - k, tgt, np.eye(nc)[a]) for a in range(nc)], axis=1)
+    H = np.zeros((8, nc))
+    for sgm in range(8):
+        for m in members:
+            H[sgm] += (-1.0) ** bin(m & sgm).count("1") * Ms[m]
+    rhs = np.array([sum(T[b, a] * H[par[a] ^ par[b], a] for a in range(nc)) for b in range(nc)])
+    assert np.max(np.abs(lhs - rhs)) <= 1e-13 * np.max(np.abs(lhs))
