@@ -375,11 +375,16 @@ __global__ __launch_bounds__(256) void k_parent_mh(const PlanView *V, Bases B, i
             gptr(v.Mhf)[(int64_t)box * v.ldmh + c] = h >= 0 ? (float)Mh[t.hpos[h]] : 0.f;
         }
     if (!full || (full == 1 && (!v.wsrc || !v.wsrc[box]))) return; // only M2P sources need it
+    // the reconstruction keeps the degree: coefficient b of degree n comes
+    // from the 2n + 1 folded components n^2 .. (n + 1)^2 - 1 alone
     const auto HR = gptr(t.HR);
     for (int b = lane; b < v.ldm; b += 64) {
         double s = 0.0;
-        if (b < v.nc)
-            for (int c = 0; c < v.nh; ++c) s += HR[(int64_t)c * v.nc + b] * Mh[t.hpos[c]];
+        if (b < v.nc) {
+            int n = 0;
+            while (below(n + 1) <= b) ++n;
+            for (int c = n * n; c < (n + 1) * (n + 1); ++c) s += HR[(int64_t)c * v.nc + b] * Mh[t.hpos[c]];
+        }
         gptr(v.M)[(int64_t)box * v.ldm + b] = s;
     }
 }
