@@ -273,14 +273,16 @@ __device__ inline int child_in_octant(const PlanView &v, int parent, int o)
 // acc += A^t x for one 16-row tile: A [K][lda] in memory (rows a, column
 // bA), x the lane's source vector; k-steps of four in batches of 16 whose
 // loads are all issued before the first product.  Entries a >= K and
-// lanes without a source (xok false) contribute zero.
+// lanes without a source (xok false) contribute zero; k-steps below s_lo
+// (whose entries of A are zero for the tile's rows) are skipped.
 template <int K>
 __device__ inline void mfma_rows(const double *A, int lda, int bA, bool aok, const double *x, bool xok, int kq,
-                                 double4_t &acc)
+                                 double4_t &acc, int s_lo = 0)
 {
     constexpr int KS = (K + 3) / 4, CHK = 16;
 #pragma unroll
     for (int s0 = 0; s0 < KS; s0 += CHK) {
+        if (s0 + CHK <= s_lo) continue; // (block-uniform)
         double av[CHK], bv[CHK];
 #pragma unroll
         for (int t = 0; t < CHK; ++t) {
@@ -293,7 +295,7 @@ __device__ inline void mfma_rows(const double *A, int lda, int bA, bool aok, con
 #pragma unroll
         for (int t = 0; t < CHK; ++t) {
             if (s0 + t >= KS) break;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
+            if (s0 + t >= s_lo) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv[t], acc, 0, 0, 0);
         }
     }
 }
@@ -409,9 +411,14 @@ __global__ __launch_bounds__(512) void k_l2lh(const PlanView *V, Bases B, int le
     const int ch = child_in_octant(v, parent, o); // child of this lane's parent in octant o
     if (!__any(ch >= 0)) return;
     const int bA = mt * 16 + col;
+    // the shift keeps or lowers the degree: rows of degree >= d (the tile's
+    // lowest) take nothing from inputs of degree < d, the first d^2 harmonic
+    // components
+    int d = 0;
+    while ((d + 1) * (d + 1) <= mt * 16) ++d;
     double4_t acc = {0, 0, 0, 0};
     mfma_rows<NH>(v.tab->GH + (int64_t)o * nh * nh, nh, bA < nh ? bA : nh - 1, bA < nh,
-                  v.Lh + (int64_t)(parent >= 0 ? parent : 0) * ldh, parent >= 0, kq, acc);
+                  v.Lh + (int64_t)(parent >= 0 ? parent : 0) * ldh, parent >= 0, kq, acc, d * d / 4);
     if (ch < 0) return;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
