@@ -284,7 +284,6 @@ struct OrderTables {
     const int *hpos;    // [nh] folded position of each harmonic component
     const int *hposf;   // [nh] same in the FP32 copy
     const double *FP2M; // [nc][ldh] raw moments -> folded components in harmonic order (P2M, then fold)
-    const double *P2M;  // [nc][nc] moments -> Mhat, P2M[g][a] = d Mhat_a / d Q_g
     const double *P2L;  // [nc][ldh] inverse moments -> harmonic Lhat
     const int *fold_off; const int *fold_idx; const double *fold_c;     // Mhat -> folded
     const int *unfold_off; const int *unfold_idx; const double *unfold_c; // Lh -> Lhat

@@ -168,12 +168,16 @@ __global__ __launch_bounds__(64) void k_p2m(const PlanView *V, Bases B)
 }
 
 // Folded multipoles of the leaves straight from their raw moments:
-// Mh = FP2M^t Q (P2M followed by the fold, one matrix; both keep the degree)
-// and, for groups holding a leaf that M2P reads (a W-list source), the full
-// Mhat = P2M^t Q as well.  A wavefront takes 16 leaves and walks the degrees:
-// it loads the 16 leaves' moments of degree n once (the B operands of every
-// k-step), then runs the 16-row tiles of that degree's 2n+1 folded
-// components (and n_p-block rows of the full multipole) on FP64 MFMA.
+// Mh = FP2M^t Q (P2M followed by the fold, one matrix; both keep the degree).
+// A wavefront takes 16 leaves and walks the degrees: it loads the 16 leaves'
+// moments of degree n once (the B operands of every k-step), then runs the
+// 16-row tiles of that degree's 2n+1 folded components on FP64 MFMA.  A
+// wavefront holding a leaf that M2P reads (a W-list source) also rebuilds the
+// full multipoles of degree n from the folded ones, Mhat_n = HR_n^t Mh_n
+// (exact: each degree part of a multipole is harmonic): the MFMA result of a
+// folded 16-row tile, register r of lane (kq, col) holding row 4r + kq of
+// leaf col, is exactly the B operand of the tile's four k-steps, so the
+// reconstruction reads it from registers.
 // Results go to the components' folded positions (and the FP32 copy for the
 // FP32 M2L); the padding positions of the rows are written as zeros (the M2L
 // reads them as operands of padded columns).
@@ -186,13 +190,14 @@ __global__ __launch_bounds__(256) void k_p2m_fold(const PlanView *V, Bases B)
     const int li = (blockIdx.x - B.b[k]) * 64 + wave * 16 + col;
     const int leaf = li < v.nleaves ? v.leaves[li] : -1;
     if (!__any(leaf >= 0)) return;
-    const bool full = v.wsrc && __any(leaf >= 0 && v.wsrc[leaf]);
     constexpr int NC = ncoef(P), NH = nharm(P), LDM = pad16(NC), LDH = pad16(NH);
     const int ldmh = v.ldmh;
     const OrderTables &t = *v.tab;
     const auto Q = gptr(v.L + (int64_t)(leaf >= 0 ? leaf : 0) * LDM);
-    const auto FT = gptr(t.FP2M), PT = gptr(t.P2M);
+    const auto FT = gptr(t.FP2M), HR = gptr(t.HR);
     const auto Mh = gptr(v.Mh + (int64_t)(leaf >= 0 ? leaf : 0) * ldmh);
+    const bool full = v.wsrc && __any(leaf >= 0 && v.wsrc[leaf]);
+    const bool mine = full && leaf >= 0 && v.wsrc[leaf];
     const auto Mf = gptr(v.M + (int64_t)(leaf >= 0 ? leaf : 0) * LDM);
     const bool f32 = v.Mhf != nullptr; // FP32 copy for the FP32 M2L
 #pragma unroll
@@ -205,6 +210,7 @@ __global__ __launch_bounds__(256) void k_p2m_fold(const PlanView *V, Bases B)
             q[s] = leaf >= 0 && g < mn ? Q[g0 + g] : 0.0;
         }
         // folded components n^2 .. (n+1)^2 - 1
+        double4_t fo[(2 * P + 16) / 16];
 #pragma unroll
         for (int t0 = 0; t0 < 2 * n + 1; t0 += 16) {
             const int c = n * n + t0 + col, cend = (n + 1) * (n + 1);
@@ -223,23 +229,24 @@ __global__ __launch_bounds__(256) void k_p2m_fold(const PlanView *V, Bases B)
                     if (f32) gptr(v.Mhf)[(int64_t)leaf * ldmh + t.hposf[cr]] = (float)acc[r];
                 }
             }
+            fo[t0 / 16] = acc; // rows >= (n+1)^2 are zero
         }
         if (!full) continue;
-        // full multipole, monomials g0 .. g0 + mn - 1
+        // full multipole of degree n, monomials g0 .. g0 + mn - 1
+        const int cend = (n + 1) * (n + 1), KF = (2 * n + 4) / 4;
 #pragma unroll
-        for (int t0 = 0; t0 < mn; t0 += 16) {
-            const int b = g0 + t0 + col;
+        for (int m0 = 0; m0 < mn; m0 += 16) {
             double4_t acc = {0, 0, 0, 0};
 #pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                const int g = 4 * s + kq;
-                const double a = t0 + col < mn && g < mn ? PT[(int64_t)(g0 + g) * NC + b] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, q[s], acc, 0, 0, 0);
+            for (int s = 0; s < KF; ++s) {
+                const int c = n * n + 4 * s + kq;
+                const double a = c < cend && m0 + col < mn ? HR[(int64_t)c * NC + g0 + m0 + col] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, fo[s / 4][s % 4], acc, 0, 0, 0);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int br = t0 + 4 * r + kq;
-                if (leaf >= 0 && br < mn) Mf[g0 + br] = acc[r];
+                const int g = m0 + 4 * r + kq;
+                if (mine && g < mn) Mf[g0 + g] = acc[r];
             }
         }
     }
@@ -248,7 +255,7 @@ __global__ __launch_bounds__(256) void k_p2m_fold(const PlanView *V, Bases B)
         if (t.mpos[pos] < 0) Mh[pos] = 0.0;
         if (f32 && t.mposf[pos] < 0) gptr(v.Mhf)[(int64_t)leaf * ldmh + pos] = 0.f;
     }
-    if (full)
+    if (mine)
         for (int b = NC + kq; b < LDM; b += 4) Mf[b] = 0.0;
 }
 
@@ -361,8 +368,9 @@ __global__ __launch_bounds__(512) void k_m2mh(const PlanView *V, Bases B, int le
 // Parents' FP32 operand copy (mixed M2L) and, for plans with W lists, their
 // full multipoles for M2P, from the folded ones: one wavefront per non-leaf
 // box of level >= 2 (full = 0: FP32 copy only, 1: also the full multipoles
-// of M2P sources).  full = 2 (export): the full multipoles of every box, leaf
-// or not, of any level, and nothing else.
+// of M2P sources; the fold writes those of the leaves).  full = 2 (export):
+// the full multipoles of every box, leaf or not, of any level, and nothing
+// else.
 __global__ __launch_bounds__(256) void k_parent_mh(const PlanView *V, Bases B, int full)
 {
     const int k = find_plan(B, blockIdx.x);

@@ -573,7 +573,7 @@ const OrderTables *get_order_tables(int p, const OrderTables **host_copy, std::s
         upload(B.hoff, &t.hoff, err) || upload(B.GH, &t.GH, err) || upload(B.TM, &t.TM, err) ||
         upload(B.HR, &t.HR, err) || upload(B.hpos, &t.hpos, err) || upload(B.hposf, &t.hposf, err) ||
         upload(B.FP2M, &t.FP2M, err) ||
-        upload(B.P2M, &t.P2M, err) || upload(B.P2L, &t.P2L, err) || upload(B.fold_off, &t.fold_off, err) ||
+        upload(B.P2L, &t.P2L, err) || upload(B.fold_off, &t.fold_off, err) ||
         upload(B.fold_idx, &t.fold_idx, err) || upload(B.fold_c, &t.fold_c, err) ||
         upload(B.unfold_off, &t.unfold_off, err) || upload(B.unfold_idx, &t.unfold_idx, err) ||
         upload(B.unfold_c, &t.unfold_c, err) || upload(B.inv_fact, &t.inv_fact, err) ||
