@@ -106,10 +106,10 @@ __host__ __device__ constexpr int sym_row_tiles(int p)
     return n;
 }
 // columns of a parity class are padded to a multiple of sym_colpad: 4 (one
-// k-step) up to p = 11; 8 from p = 12, where the kernel walks each class's
-// k-steps in a loop of 16-byte operand vectors (two k-steps) that must not
-// straddle classes
-__host__ __device__ constexpr int sym_colpad(int p) { return p >= 12 ? 8 : 4; }
+// k-step) at every order; from p = 12 the kernel's 16-byte operand vectors
+// (two k-steps) may hold the last k-step of one class and the first of the
+// next
+__host__ __device__ constexpr int sym_colpad(int) { return 4; }
 __host__ __device__ constexpr int sym_class_ksteps(int p, int c)
 {
     return (sym_class_count(p, c) + sym_colpad(p) - 1) / sym_colpad(p) * (sym_colpad(p) / 4);

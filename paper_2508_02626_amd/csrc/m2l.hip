@@ -745,8 +745,8 @@ __global__ __launch_bounds__(256, 1) void k_m2l_symh(const PlanView *V, Bases B)
     constexpr int MTW = RT, R0 = 0;
     static_assert(MTW <= 24 && F32T >= 1 && F32T <= RT, "row tiles");
     constexpr int N32 = RT - F32T; // FP32 row tiles
-    static_assert(KS % 2 == 0 && 8 * (KS / 2) <= folded_ld(P), "two-k-step vectors inside the folded row");
-    constexpr int KSV = KS / 2; // operand vectors per class
+    constexpr int KSV = (KS + 1) / 2; // operand vectors per class
+    static_assert(8 * KSV <= folded_ld(P), "two-k-step vectors inside the folded row");
     constexpr int NT = 256;
     constexpr int LDD = dlayout_ldd(P), LDC = dlayout_ldc(P);
     constexpr int DW = 2; // compact tables move in 16-byte vectors
@@ -872,43 +872,69 @@ __global__ __launch_bounds__(256, 1) void k_m2l_symh(const PlanView *V, Bases B)
         load_v(cur, 0, srcc);
         __syncthreads();
     }
-    // one class: column classes unrolled, their vectors in a loop
+    // one class: column classes unrolled, their vectors in a loop.  A column
+    // class may start on the second k-step of a vector (the previous class
+    // ran its first) and end on the first k-step of one (the next class runs
+    // its second): the vector moves on, and the one after it is requested,
+    // where its first k-step is taken.
     auto run_class = [&](auto zc, const T *D) {
         constexpr int Z = decltype(zc)::value;
         const int *Ho = sHo[kq];
         auto column_class = [&](auto tc) {
             constexpr int TAU = decltype(tc)::value;
-#pragma unroll 1
-            for (int j = S.kb[TAU] / 2; j < S.kb[TAU + 1] / 2; ++j) {
+            constexpr int K0 = S.kb[TAU], K1 = S.kb[TAU + 1];
+            auto kstep = [&](int ks, auto wc) {
+                constexpr int w = decltype(wc)::value;
+                const int ha = Ho[ks];
+                T ac[MTW];
+#pragma unroll
+                for (int mt = 0; mt < MTW; ++mt)
+                    if (!((S.rc[mt] ^ TAU) & Z)) ac[mt] = D[hb[mt] + ha];
+                T h[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) h[m] = cur[m][w];
+                wht8(h);
+#pragma unroll
+                for (int mt = 0; mt < F32T; ++mt)
+                    if (!((S.rc[mt] ^ TAU) & Z))
+                        acc[mt] = Mfma<T>::run(ac[mt], h[S.rc[mt] ^ TAU], acc[mt]);
+                if constexpr (N32 > 0) {
+                    float hf[8];
+#pragma unroll
+                    for (int m = 0; m < 8; ++m) hf[m] = (float)h[m];
+#pragma unroll
+                    for (int mt = F32T; mt < MTW; ++mt)
+                        if (!((S.rc[mt] ^ TAU) & Z))
+                            acc32[mt - F32T] = Mfma<float>::run((float)ac[mt], hf[S.rc[mt] ^ TAU], acc32[mt - F32T]);
+                }
+            };
+            auto request = [&](int j) { // the vector after vector j
                 if (j + 1 < KSV) load_v(nxt, j + 1, srcc);
                 else load_v(nxt, 0, srcn);
-#pragma unroll
-                for (int w = 0; w < 2; ++w) {
-                    const int ha = Ho[2 * j + w];
-                    T ac[MTW];
-#pragma unroll
-                    for (int mt = 0; mt < MTW; ++mt)
-                        if (!((S.rc[mt] ^ TAU) & Z)) ac[mt] = D[hb[mt] + ha];
-                    T h[8];
-#pragma unroll
-                    for (int m = 0; m < 8; ++m) h[m] = cur[m][w];
-                    wht8(h);
-#pragma unroll
-                    for (int mt = 0; mt < F32T; ++mt)
-                        if (!((S.rc[mt] ^ TAU) & Z))
-                            acc[mt] = Mfma<T>::run(ac[mt], h[S.rc[mt] ^ TAU], acc[mt]);
-                    if constexpr (N32 > 0) {
-                        float hf[8];
-#pragma unroll
-                        for (int m = 0; m < 8; ++m) hf[m] = (float)h[m];
-#pragma unroll
-                        for (int mt = F32T; mt < MTW; ++mt)
-                            if (!((S.rc[mt] ^ TAU) & Z))
-                                acc32[mt - F32T] = Mfma<float>::run((float)ac[mt], hf[S.rc[mt] ^ TAU], acc32[mt - F32T]);
-                    }
-                }
+            };
+            auto move_on = [&]() {
 #pragma unroll
                 for (int m = 0; m < 8; ++m) cur[m] = nxt[m];
+            };
+            using W0 = std::integral_constant<int, 0>;
+            using W1 = std::integral_constant<int, 1>;
+            if constexpr (K1 > K0) {
+                if constexpr (K0 % 2 == 1) { // second half of a vector the previous class began
+                    kstep(K0, W1{});
+                    move_on();
+                }
+#pragma unroll 1
+                for (int j = (K0 + 1) / 2; j < K1 / 2; ++j) {
+                    request(j);
+                    kstep(2 * j, W0{});
+                    kstep(2 * j + 1, W1{});
+                    move_on();
+                }
+                if constexpr (K1 % 2 == 1) { // first half of a vector
+                    request(K1 / 2);
+                    kstep(K1 - 1, W0{});
+                    if constexpr (K1 == KS) move_on(); // its second half is padding
+                }
             }
         };
         column_class(std::integral_constant<int, 0>{});
