@@ -450,7 +450,7 @@ int build_plan(fmm_plan_s *P, const double *xyz)
             if (ldms) o.add<double>((size_t)(nb + 1) * ldms);
         } else {
             o.add<double>((size_t)(nb + 1) * P->ldmh).add<double>((size_t)nb * P->ldh);
-            if (P->m2l_parts > 1) o.add<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh);
+            if (P->m2l_parts > 1 && !sym_parts_add(P->p)) o.add<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh);
             if (P->mixed_m2l && m2l_f32_operands(P->p)) o.add<float>((size_t)(nb + 1) * P->ldmh);
         }
         if (!P->reserve(true, o.total)) return fail(FMM_ENOMEM, "device allocation failed (boxes)");
@@ -483,9 +483,10 @@ int build_plan(fmm_plan_s *P, const double *xyz)
     double *Mh = soft ? nullptr : P->own<double>((size_t)(nb + 1) * P->ldmh);
     double *Lh = soft ? nullptr : P->own<double>((size_t)nb * P->ldh);
     float *Mhf = P->mixed_m2l && m2l_f32_operands(P->p) ? P->own<float>((size_t)(nb + 1) * P->ldmh) : nullptr;
-    // partial sums of the M2L class parts after the first
-    double *Lh2 = P->m2l_parts > 1 ? P->own<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh) : nullptr;
-    if (P->m2l_parts > 1) NOMEM(Lh2);
+    // orders >= 12: partial sums of the M2L class parts after the first
+    const bool lh2 = P->m2l_parts > 1 && !sym_parts_add(P->p);
+    double *Lh2 = lh2 ? P->own<double>((size_t)(P->m2l_parts - 1) * nb * P->ldh) : nullptr;
+    if (lh2) NOMEM(Lh2);
     double *Dsoft = nullptr, *zrow = nullptr;
     int *soft_map = nullptr;
     if (soft) {
@@ -934,6 +935,10 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     };
     HIPCHK(hipEventRecord(F->ev_fork, s));
     HIPCHK(hipStreamWaitEvent(F->side, F->ev_fork, 0));
+    // Lh rows zeroed for the M2L class parts to add into (orders 6-11; the
+    // M2L waits for the side stream's first part)
+    launch_lh_zero(V, sub(0, count, [](const fmm_plan_s *p) {
+        return p->m2l_parts > 1 && sym_parts_add(p->p) ? (int)ceil_div((int64_t)p->nboxes * p->ldh, 512) : 0; }), F->side);
     p2p_part(0);
     HIPCHK(hipEventRecord(F->ev_join, F->side));
     // runs of equal order (callers sort batches by order)
@@ -1022,8 +1027,10 @@ int run_pipeline(fmm_plan_s *const *P, int count, const PlanView *V, hipStream_t
     for (auto &r : runs)
         launch_p2l_transform(V + r.first, sub(r.first, r.second, [](const fmm_plan_s *p) {
             return (int)ceil_div(p->nxtgt, 16) * (p->ldh / 16); }), s);
-    // complete Lh rows (zero where nothing arrived, plus the second part of the sign classes)
-    launch_lh_init(V, sub(0, count, [](const fmm_plan_s *p) { return (int)ceil_div(p->nboxes, 4); }), s);
+    // complete Lh rows of plans whose M2L stores them (zero where nothing
+    // arrived, plus the second part of the sign classes from order 12)
+    launch_lh_init(V, sub(0, count, [](const fmm_plan_s *p) {
+        return p->m2l_parts > 1 && sym_parts_add(p->p) ? 0 : (int)ceil_div(p->nboxes, 4); }), s);
     T.end();
     // L2L on the harmonic components, then full local expansions at the leaves
     T.begin(7);
@@ -1265,7 +1272,7 @@ extern "C" int fmm_plan_estimate(int64_t n, int32_t order, int32_t leaf_size, co
         boxes = 1 + 8.0 * 2.0 * n / (leaf_size + 1);
     }
     double ldm = pad16(ncoef(order)), ldh = pad16(nharm(order)), ldmh = folded_ld(order);
-    const int parts = sym_m2l_parts(order);
+    const int parts = sym_parts_add(order) ? 1 : sym_m2l_parts(order);
     double per_box = 8 * (2 * ldm + parts * ldh + ldmh) + 4 * ldmh + 4 * 200 + 64; // expansions, slots, lists
     double per_particle = 8 * 3 + 4 + 8 * 5 + 8 * 2;
     double total = boxes * per_box + n * per_particle + 8 * 27 * boxes;

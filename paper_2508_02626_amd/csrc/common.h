@@ -129,6 +129,15 @@ __host__ __device__ constexpr bool m2l_sym(int p) { return p >= 6; }
 // p = 8, equal parts: 0.97 ms with two, 0.96 with three, 1.07 with four; on a
 // Plummer tree three were slower than two).
 __host__ __device__ constexpr int sym_m2l_parts(int p) { return m2l_sym(p) ? 2 : 1; }
+// Orders 6-11: the parts add their sums into Lh rows zeroed before the M2L,
+// with FP64 atomics (two addends onto zero give the same sum in either order,
+// more would not), so no pass over partial sums follows the launch (uniform
+// 10^6 points, p = 8: 2.36 against 2.56 ms per step).  From order 12 the
+// second part stores its sums to a slice of its own and the pass before the
+// L2L adds them (the atomics slowed the p = 14 launch by 3%, more than that
+// pass takes).
+__host__ __device__ constexpr bool sym_parts_add(int p) { return m2l_sym(p) && p <= 11; }
+static_assert(sym_m2l_parts(6) <= 2 && sym_m2l_parts(11) <= 2, "M2L parts add into Lh in any order");
 // share (percent) of a tile's matrix-core work in its first part; the launch
 // runs the first parts before the others (longest first), so that its end is
 // made of the shorter blocks (uniform 10^6 points, p = 8, FP64: about 6%
@@ -336,8 +345,8 @@ struct PlanView {
     // evaluation buffers
     double *qs;                         // sorted charges
     double *M, *Mh, *Lh, *L;            // [boxes][ldm] / [boxes][ldmh] / [boxes][ldh]
-    double *Lh2;                        // sign-class orders: [m2l_parts - 1][boxes][ldh] partial
-                                        // sums of the M2L class parts after the first
+    double *Lh2;                        // orders >= 12: [m2l_parts - 1][boxes][ldh] partial sums
+                                        // of the M2L class parts after the first (else null)
     int m2l_parts;                      // blocks per M2L tile (1 below the sign-class orders)
     float *Mhf;                         // FP32 folded multipoles (mixed M2L)
     // softened kernel 1/sqrt(|x|^2 + eps^2) (kernel == 1): full Cartesian

@@ -344,9 +344,13 @@ __global__ __launch_bounds__(256) void k_m2l(const PlanView *V, Bases B)
 // count them) two vectors ahead, across class boundaries (all eight members
 // for the next class, whose mask is not known there).  m2l_parts blocks share
 // a tile, each running a contiguous part of its classes (the first with
-// kSymFirstPart % of the matrix-core work, dispatched before the others); part
-// i > 0 writes its partial sums to slice i - 1 of Lh2, which the L2L
-// initialisation adds in part order.
+// kSymFirstPart % of the matrix-core work, dispatched before the others),
+// and adds its sums into the target rows of Lh, zeroed before the launch, with
+// FP64 atomics: with two parts each entry receives 0 + a + b in either order,
+// which is exact-order independent (a + b = b + a), so the result does not
+// depend on which part finishes first.  (k_m2l_symh, orders >= 12: part i > 0
+// writes its partial sums to slice i - 1 of Lh2, which the pass before the L2L
+// adds in part order.)
 template <int P> struct SymShape {
     static constexpr int RT = sym_row_tiles(P), KS = sym_ksteps(P);
     int rc[RT], kc[KS]; // parity class of each row tile and k-step
@@ -706,13 +710,14 @@ __global__ __launch_bounds__(256, 2) void k_m2l_sym(const PlanView *V, Bases B)
     run_mask(std::integral_constant<int, 5>{});
     run_mask(std::integral_constant<int, 6>{}); // at most two zero axes
     if (tgt < 0) return;
-    double *Lh = (part ? v.Lh2 + (int64_t)(part - 1) * v.nboxes * v.ldh : v.Lh) + (int64_t)tgt * v.ldh;
+    static_assert(sym_parts_add(P), "parts add into the zeroed rows");
+    double *Lh = v.Lh + (int64_t)tgt * v.ldh;
 #pragma unroll
     for (int mt = 0; mt < MTW; ++mt) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int b = gptr(tb.srow)[16 * mt + Mfma<T>::row(lane, r)];
-            if (b >= 0) Lh[b] = sizeof(T) == 4 ? acc64[mt][r] : (double)acc[mt][r];
+            if (b >= 0) atomicAdd(Lh + b, sizeof(T) == 4 ? acc64[mt][r] : (double)acc[mt][r]);
         }
     }
 }
@@ -979,6 +984,7 @@ __global__ __launch_bounds__(256, 1) void k_m2l_symh(const PlanView *V, Bases B)
     run_mask(std::integral_constant<int, 5>{});
     run_mask(std::integral_constant<int, 6>{});
     if (tgt < 0) return;
+    static_assert(!sym_parts_add(P), "parts store their sums");
     double *Lh = (part ? v.Lh2 + (int64_t)(part - 1) * v.nboxes * v.ldh : v.Lh) + (int64_t)tgt * v.ldh;
 #pragma unroll
     for (int mt = 0; mt < F32T; ++mt) {

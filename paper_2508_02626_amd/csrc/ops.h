@@ -10,6 +10,7 @@ void launch_p2m(int p, const PlanView *V, const Bases &B, hipStream_t s);  // 1 
 void launch_p2m_fold(int p, const PlanView *V, const Bases &B, hipStream_t s); // 64 leaves/block
 void launch_l2lh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents x 16 rows/block (harmonic rows)
 void launch_lh_init(const PlanView *V, const Bases &B, hipStream_t s);        // 4 boxes/block
+void launch_lh_zero(const PlanView *V, const Bases &B, hipStream_t s);        // 512 doubles/block
 void launch_m2mh(int p, const PlanView *V, const Bases &B, int level, hipStream_t s); // 16 parents/block
 // Row-tile groups per 16-parent M2M group: levels with few parents spread the
 // mt row tiles of each group over up to mt blocks (powers of two dividing mt)

@@ -435,9 +435,10 @@ __global__ __launch_bounds__(512) void k_l2lh(const PlanView *V, Bases B, int le
     }
 }
 
-// Before the L2L: Lh rows of boxes (level >= 2) without M2L or P2L
-// contributions are set to zero, and for sign-class orders the partial sums of
-// the other M2L class parts (Lh2 slices) are added in part order.
+// Before the L2L, plans whose M2L stores its rows (orders below 6 and from 12
+// on): Lh rows of boxes (level >= 2) without M2L or P2L contributions are set
+// to zero, and from order 12 the partial sums of the other M2L class parts
+// (Lh2 slices) are added in part order.
 __global__ __launch_bounds__(256) void k_lh_init(const PlanView *V, Bases B)
 {
     const int k = find_plan(B, blockIdx.x);
@@ -448,7 +449,7 @@ __global__ __launch_bounds__(256) void k_lh_init(const PlanView *V, Bases B)
     const auto Lh = gptr(v.Lh + (int64_t)box * v.ldh);
     if (!has_v && !has_x) {
         for (int a = lane; a < v.ldh; a += 64) Lh[a] = 0.0;
-    } else if (has_v && v.m2l_parts > 1) {
+    } else if (has_v && v.Lh2) {
         const int64_t slice = (int64_t)v.nboxes * v.ldh;
         const auto Lh2 = gptr(v.Lh2 + (int64_t)box * v.ldh);
         for (int a = lane; a < v.ldh; a += 64) {
@@ -457,6 +458,17 @@ __global__ __launch_bounds__(256) void k_lh_init(const PlanView *V, Bases B)
             Lh[a] = s;
         }
     }
+}
+
+// Plans whose M2L parts add into Lh (orders 6-11): every row zeroed before
+// the M2L (two doubles per thread).
+__global__ __launch_bounds__(256) void k_lh_zero(const PlanView *V, Bases B)
+{
+    const int k = find_plan(B, blockIdx.x);
+    const PlanView &v = V[k];
+    const int64_t i = 2 * ((int64_t)(blockIdx.x - B.b[k]) * 256 + threadIdx.x), n = (int64_t)v.nboxes * v.ldh;
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    if (i < n) *(d2 *)(v.Lh + i) = d2{0.0, 0.0}; // ldh is a multiple of 16
 }
 
 // ---------------- unfold the M2L result to full local expansions ----------------
@@ -1063,6 +1075,10 @@ void launch_m2mh(int p, const PlanView *V, const Bases &B, int level, hipStream_
 void launch_parent_mh(const PlanView *V, const Bases &B, int full, hipStream_t s)
 {
     if (nblk(B)) k_parent_mh<<<nblk(B), 256, 0, s>>>(V, B, full);
+}
+void launch_lh_zero(const PlanView *V, const Bases &B, hipStream_t s)
+{
+    if (nblk(B)) k_lh_zero<<<nblk(B), 256, 0, s>>>(V, B);
 }
 void launch_lh_init(const PlanView *V, const Bases &B, hipStream_t s)
 {
