@@ -286,12 +286,16 @@ def test_plan_then_evaluate_on_another_stream():
 def test_full_size_uniform_sampled_against_direct():
     """1e6 points, depth 5, p = 8 (the benchmark workload), in the launch
     configuration the benchmark times: sampled targets against the direct sum,
-    and the tree bit-exact against the oracle."""
+    the tree bit-exact against the oracle, and a second evaluation equal bit
+    for bit (the two M2L blocks of each tile add into the same rows with
+    atomics, in whichever order they finish)."""
     from paper_2508_02626_amd import fmm
     x, q = inputs.uniform(1_000_000, 1)
     kw = dict(uniform_depth=5, root=[0, 0, 0, 1])
     for prec in ("fp64", "mixed"):
         pl, phi, fld = gpu_solve(x, q, 8, precision=prec, **kw)
+        again, fagain = pl.evaluate(to_dev(q))
+        assert np.array_equal(phi, again.cpu().numpy()) and np.array_equal(fld, fagain.cpu().numpy())
         idx = np.random.default_rng(7).choice(len(q), 300, replace=False)
         d, fd = oracle.direct(x, q, idx)
         e = rel_l2(phi[idx], d)
