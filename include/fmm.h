@@ -313,6 +313,15 @@ int fmm_plan_read_timing(fmm_plan_t plan, double ms[16], int64_t calls[16]);
  *         8  [64] the axial block of each class (-1 for near offsets)
  *            For a sign vector s, T(s o k) = R_s T(k) R_s, R_s = +-1 by the
  *            parities of a folded component's exponents; T(k) = B A F.
+ *         9  layout of a folded multipole row: [1][ldmh], the component (index
+ *            in the harmonic order of table 4) kept at each position, -1 for
+ *            padding.  From order 6: the components sorted by parity class
+ *            (x, y, z exponent parities, class 4 (x mod 2) + 2 (y mod 2) + z),
+ *            each class padded to a multiple of 4 (one k-step of the
+ *            matrix-core contraction); sorted column 4 s + g (k-step s, lane
+ *            group g) sits at 8 (s / 2) + 2 g + (s mod 2), so that a lane's
+ *            operands of two k-steps are adjacent; ldmh = 16 ceil(k / 4) for k
+ *            k-steps.  Below order 6: the harmonic order, padded to 16.
  *   out_host   host buffer of `capacity` doubles, or NULL to query the size
  *   count      receives the number of doubles; ld the row length
  * Returns FMM_EINVAL for a bad order, table or a buffer too small.

@@ -605,6 +605,7 @@ int host_order_tables(int p, int which, std::vector<double> &out)
     case 2: out = B.G; return ncoef(p);
     case 3: out = B.P2M; return ncoef(p);
     case 4: out = B.HR; return ncoef(p);
+    case 9: out.assign(B.mpos.begin(), B.mpos.end()); return folded_ld(p);
     default: return -1;
     }
 }
@@ -614,10 +615,11 @@ int host_order_tables(int p, int which, std::vector<double> &out)
 extern "C" int fmm_order_table(int32_t order, int32_t which, double *out_host, int64_t capacity,
                                int64_t *count, int32_t *ld)
 {
-    if (order < 0 || order > fmm::kMaxOrder || which < 0 || which > 8 || !count || !ld) return FMM_EINVAL;
+    if (order < 0 || order > fmm::kMaxOrder || which < 0 || which > 9 || !count || !ld) return FMM_EINVAL;
     std::vector<double> t;
     try {
-        *ld = which <= 4 ? fmm::host_order_tables(order, which, t) : fmm::host_rotation_tables(order, which - 5, t);
+        *ld = which <= 4 || which == 9 ? fmm::host_order_tables(order, which, t)
+                                       : fmm::host_rotation_tables(order, which - 5, t);
     } catch (...) {
         return FMM_EUNSUPPORTED;
     }

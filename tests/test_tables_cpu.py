@@ -10,7 +10,10 @@ from closed forms) against what the paper and the oracle fix, on the CPU:
 * P2M map: raw moments times the map equal the oracle's P2M (Eq. P2M);
 * harmonic reconstruction: the full multipole is recovered exactly from its
   components with z exponent <= 1, the fold being written out here from
-  Laplace's equation (d_z^2 = -(d_x^2 + d_y^2) on 1/r).
+  Laplace's equation (d_z^2 = -(d_x^2 + d_y^2) on 1/r);
+* folded multipole layout: every component is kept exactly once, and at the
+  sign-class orders the columns read back in k-step order run through the
+  parity classes in order, each padded to whole k-steps of four.
 """
 import math
 
@@ -203,7 +206,7 @@ def test_order_table_rejects_bad_arguments():
     cnt, ld = ctypes.c_int64(), ctypes.c_int32()
     L = fmm.lib()
     assert L.fmm_order_table(17, 0, None, 0, ctypes.byref(cnt), ctypes.byref(ld)) == fmm.FMM_EINVAL
-    assert L.fmm_order_table(4, 9, None, 0, ctypes.byref(cnt), ctypes.byref(ld)) == fmm.FMM_EINVAL
+    assert L.fmm_order_table(4, 10, None, 0, ctypes.byref(cnt), ctypes.byref(ld)) == fmm.FMM_EINVAL
     assert L.fmm_order_table(4, 1, None, 0, ctypes.byref(cnt), ctypes.byref(ld)) == fmm.FMM_OK
     buf = np.zeros(3)
     assert L.fmm_order_table(4, 1, ctypes.c_void_p(buf.ctypes.data), 3, ctypes.byref(cnt),
@@ -268,3 +271,36 @@ def test_rotation_factors_reproduce_the_m2l_contraction(p):
                         err = np.abs(pred - true).max() / np.abs(true).max()
                         worst = max(worst, err)
     assert worst <= 1e-12, worst
+
+
+@pytest.mark.parametrize("p", [0, 3, 5, 6, 8, 11, 12, 13, 14, 16])
+def test_folded_layout_keeps_each_component_once_in_class_order(p):
+    """The folded-multipole row (table 9) against a layout derived here from
+    the components' exponent parities: below order 6 the harmonic order; from
+    6 on, read in k-step order (sorted column 4 s + g at 8 (s // 2) + 2 g +
+    s % 2), the classes 4 (i % 2) + 2 (j % 2) + k come in increasing order,
+    each class's components in harmonic order and padded with -1 to a
+    multiple of 4, and the row length is 16 per four k-steps."""
+    pos = fmm.order_table(p, 9)
+    assert pos.shape[0] == 1
+    pos = pos[0].astype(int)
+    comps = harmonic_components(p)
+    nh = (p + 1) ** 2
+    assert len(comps) == nh
+    kept = pos[pos >= 0]
+    assert sorted(kept.tolist()) == list(range(nh))
+    if p < 6:
+        assert pos[:nh].tolist() == list(range(nh)) and (pos[nh:] == -1).all()
+        assert len(pos) == (nh + 15) // 16 * 16
+        return
+    cls = [4 * (i % 2) + 2 * (j % 2) + k for i, j, k in comps]
+    expect = []
+    for c in range(8):
+        members = [h for h in range(nh) if cls[h] == c]
+        expect += members + [-1] * (-len(members) % 4)
+    ks = len(expect) // 4
+    assert len(pos) == 16 * ((ks + 3) // 4)
+    sorted_cols = [pos[8 * (s // 2) + 2 * g + s % 2] for s in range(ks) for g in range(4)]
+    assert sorted_cols == expect
+    used = {8 * (s // 2) + 2 * g + s % 2 for s in range(ks) for g in range(4)}
+    assert all(pos[q] == -1 for q in range(len(pos)) if q not in used)
